@@ -1,0 +1,532 @@
+"""Pins of the FP64 CPU oracle against things other than itself.
+
+Each test checks the oracle against a library routine, a closed form that the
+paper's equations give for a constructed input, an invariant of the method,
+or a brute-force search, so that a dropped term, a wrong sign, a wrong index
+or a transposed operand anywhere in the oracle fails at least one of them.
+All tests run on the CPU.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+S_WIN = 5
+OFFSETS = np.array([-1.0, -0.5, 0.0, 0.5, 1.0])
+
+
+def texture(seed, h, w, smooth=1.2, lo=20.0, hi=235.0):
+    """Band-limited random texture (independent of the workload generator)."""
+    rng = np.random.default_rng(seed)
+    t = ndimage.gaussian_filter(rng.standard_normal((h, w)), smooth, mode="wrap")
+    t = (t - t.min()) / (t.max() - t.min())
+    return lo + (hi - lo) * t
+
+
+def shifted_pair_u8(seed, h, w, D):
+    """Exact integer shift: right(x') = canvas(x' + D), left(x) = canvas(x): disparity D."""
+    canvas = np.rint(texture(seed, h, w + 2 * abs(D) + 2)).astype(np.uint8)
+    off = abs(D) + 1
+    left = canvas[:, off:off + w]
+    right = canvas[:, off + D:off + D + w]
+    return np.ascontiguousarray(left), np.ascontiguousarray(right)
+
+
+# --------------------------------------------------------------------------
+# O1 pyramid / O2 gradient: against scipy's correlation with reflect-101
+# ('mirror') borders
+# --------------------------------------------------------------------------
+
+def _binomial_level(img):
+    k = np.array([1, 4, 6, 4, 1], np.int64)
+    s = ndimage.correlate(img.astype(np.int64), np.outer(k, k), mode="mirror")
+    return s[::2, ::2]
+
+
+@pytest.mark.parametrize("shape", [(37, 23), (48, 64), (31, 33)])
+def test_pyramid_integer_matches_library(oracle, shape):
+    rng = np.random.default_rng(1)
+    h, w = shape
+    left = rng.integers(0, 256, (h, w), dtype=np.uint8)
+    right = rng.integers(0, 256, (h, w), dtype=np.uint8)
+    p = oracle.default_params(levels=3, patch=3, stride=1, iters=1)
+    tr = oracle.compute(left, right, p, trace=True)["trace"]
+    cur_l, cur_r = left.astype(np.int64), right.astype(np.int64)
+    for n in range(1, 3):
+        cur_l = (_binomial_level(cur_l) + 128) >> 8
+        cur_r = (_binomial_level(cur_r) + 128) >> 8
+        assert np.array_equal(tr.get(n, "left"), cur_l.astype(np.float64))
+        assert np.array_equal(tr.get(n, "right"), cur_r.astype(np.float64))
+        lw, lh, _, _ = tr.dims(n)
+        assert (lh, lw) == cur_l.shape
+
+
+def test_pyramid_float_matches_library(oracle):
+    rng = np.random.default_rng(2)
+    left = rng.uniform(0, 255, (29, 41))
+    right = rng.uniform(0, 255, (29, 41))
+    p = oracle.default_params(levels=2, patch=3, stride=1, iters=1, float_pyramid=1)
+    tr = oracle.compute(left, right, p, trace=True)["trace"]
+    k = np.array([1, 4, 6, 4, 1], np.float64) / 16.0
+    ref = ndimage.correlate(left, np.outer(k, k), mode="mirror")[::2, ::2]
+    np.testing.assert_allclose(tr.get(1, "left"), ref, rtol=0, atol=1e-11)
+
+
+def test_pyramid_constant_and_sizes(oracle):
+    img = np.full((480, 640), 77, np.uint8)
+    p = oracle.default_params(levels=5, patch=8, stride=3, iters=1)
+    tr = oracle.compute(img, img, p, trace=True)["trace"]
+    sizes = [(640, 480), (320, 240), (160, 120), (80, 60), (40, 30)]
+    for n in range(5):
+        w, h, _, _ = tr.dims(n)
+        assert (w, h) == sizes[n]
+        assert np.all(tr.get(n, "left") == 77.0)
+    # 1080p, 6 levels: 1920x1080 -> ... -> 60x34 (odd sizes round up)
+    w, h, sz = 1920, 1080, []
+    for _ in range(6):
+        sz.append((w, h))
+        w, h = (w + 1) // 2, (h + 1) // 2
+    assert sz[-1] == (60, 34) and sz[4] == (120, 68)
+
+
+@pytest.mark.parametrize("shape", [(23, 37), (16, 16)])
+def test_sobel_matches_library(oracle, shape):
+    rng = np.random.default_rng(3)
+    left = rng.integers(0, 256, shape, dtype=np.uint8)
+    p = oracle.default_params(levels=1, patch=3, stride=1, iters=1)
+    tr = oracle.compute(left, left, p, trace=True)["trace"]
+    ref = ndimage.sobel(left.astype(np.float64), axis=1, mode="mirror") / 8.0
+    assert np.array_equal(tr.get(0, "grad"), ref)
+
+
+def test_sobel_ramp(oracle):
+    a = 3.0
+    img = np.tile(np.arange(40, dtype=np.float64) * a, (12, 1))
+    p = oracle.default_params(levels=1, patch=3, stride=1, iters=1)
+    g = oracle.compute(img, img, p, trace=True)["trace"].get(0, "grad")
+    assert np.all(g[:, 1:-1] == a)
+    assert np.all(g[:, 0] == 0.0) and np.all(g[:, -1] == 0.0)  # reflect-101 border
+
+
+# --------------------------------------------------------------------------
+# O3 patch grid
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,P,S", [(320, 8, 4), (79, 8, 3), (1080, 12, 4), (13, 12, 5), (12, 12, 4), (100, 10, 4)])
+def test_grid_covers_and_ends_on_border(oracle, n, P, S):
+    o = oracle.grid(n, P, S)
+    assert o[0] == 0 and o[-1] == n - P
+    assert np.all(np.diff(o) > 0) and np.all(np.diff(o) <= S)
+    cover = np.zeros(n, np.int64)
+    for v in o:
+        cover[v:v + P] += 1
+    assert cover.min() >= 1
+    assert len(o) == math.ceil((n - P) / S) + 1
+
+
+def test_grid_counts_of_workloads(oracle):
+    def total(w, h, L, P, S):
+        out = []
+        for _ in range(L):
+            out.append(len(oracle.grid(w, P, S)) * len(oracle.grid(h, P, S)))
+            w, h = (w + 1) // 2, (h + 1) // 2
+        return out
+
+    c1 = total(320, 240, 3, 8, 4)
+    assert c1[0] == 4661 and sum(c1) == 6058
+    c2 = total(640, 480, 5, 8, 3)
+    assert c2[0] == 33708 and sum(c2) == 44614
+    assert sum(total(640, 480, 4, 8, 4)) == 24979
+    c5 = total(1920, 1080, 6, 12, 4)
+    assert c5[0] == 128104 and sum(c5) == 169913
+
+
+# --------------------------------------------------------------------------
+# O5-O8: inverse-compositional search
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("D", [3, -2, 5, 0])
+def test_exact_integer_shift_recovered(oracle, D):
+    """A textured pair shifted by an integer D is recovered to 1e-6 px."""
+    h, w, P = 64, 96, 8
+    left, right = shifted_pair_u8(10 + D, h, w, D)
+    p = oracle.default_params(levels=3, patch=P, stride=4, iters=32)
+    out = oracle.compute(left, right, p, trace=True)
+    tr = out["trace"]
+    u = tr.get(0, "u")
+    ox = oracle.grid(w, P, 4)
+    inner = (ox >= abs(D) + 2 * P) & (ox + P + abs(D) + 2 * P <= w)
+    assert inner.sum() > 5
+    np.testing.assert_allclose(u[:, inner], -D, atol=1e-6, rtol=0)
+    d = out["disp"]
+    xs = slice(abs(D) + 3 * P, w - abs(D) - 3 * P)
+    np.testing.assert_allclose(d[:, xs], D, atol=1e-6, rtol=0)
+
+
+def _row_linear(h, w, d, a0=0.8, a1=0.05, seed=0):
+    """I(x, y) = alpha_y x + beta_y with alpha linear in y: one IC step is exact."""
+    rng = np.random.default_rng(seed)
+    alpha = a0 + a1 * np.arange(h)
+    beta = rng.uniform(10, 40, h)
+    xs = np.arange(w, dtype=np.float64)
+    left = alpha[:, None] * xs[None, :] + beta[:, None]
+    right = alpha[:, None] * (xs[None, :] + d) + beta[:, None]
+    return left, right, alpha
+
+
+@pytest.mark.parametrize("d", [0.37, 2.75, -1.6])
+def test_row_linear_one_step_exact(oracle, d):
+    """Eq. 1 linearisation is exact for row-linear texture: one iteration lands on -d."""
+    h, w, P, S = 24, 64, 8, 4
+    left, right, _ = _row_linear(h, w, d)
+    p = oracle.default_params(levels=1, patch=P, stride=S, iters=1, float_pyramid=1,
+                              sigma_r_dynamic=0, sigma_r=2.0, variance=1)
+    tr = oracle.compute(left, right, p, trace=True)["trace"]
+    u, H, ssd = tr.get(0, "u"), tr.get(0, "hess"), tr.get(0, "ssd")
+    ox, oy = oracle.grid(w, P, S), oracle.grid(h, P, S)
+    rows = (oy >= 1) & (oy + P <= h - 1)
+    cols = (ox >= 1 + 2) & (ox + P + 3 <= w - 1)
+    sel = np.ix_(rows, cols)
+    np.testing.assert_allclose(u[sel], -d, atol=1e-9, rtol=0)
+    # window SSD is exactly quadratic: SSD(delta) = H delta^2 (mean-normalised)
+    np.testing.assert_allclose(ssd[sel], H[sel][..., None] * OFFSETS ** 2, rtol=1e-9, atol=1e-8)
+    # posterior closed form of Eq. 5-6 with tau = 2 sigma_r^2 s^2
+    tau = 2.0 * 2.0 ** 2 * S_WIN ** 2
+    post = 1.0 / np.sum(np.exp(-H[sel][..., None] * OFFSETS ** 2 / tau), axis=-1)
+    np.testing.assert_allclose(tr.get(0, "post")[sel], post, rtol=1e-12)
+    # variance: exactly quadratic SSD => sigma_k^2 = sigma_r^2 s^2 / H (capped at P^2)
+    sig = np.minimum(2.0 ** 2 * S_WIN ** 2 / H[sel], P * P)
+    np.testing.assert_allclose(tr.get(0, "sigk2")[sel], sig, rtol=1e-9)
+
+
+def test_zero_hessian_keeps_start(oracle):
+    flat = np.full((20, 30), 100, np.uint8)
+    other = np.random.default_rng(0).integers(0, 256, (20, 30), dtype=np.uint8)
+    p = oracle.default_params(levels=1, patch=5, stride=5, iters=8)
+    tr = oracle.compute(flat, other, p, trace=True)["trace"]
+    assert np.all(tr.get(0, "hess") == 0.0)
+    assert np.all(tr.get(0, "u") == 0.0)
+
+
+def _bruteforce_min(Lv, Rv, ox, oy, P, lo, hi):
+    """Global minimiser over u in [lo, hi] of the mean-normalised SSD of Eq. 1.
+
+    Within a unit cell [m, m+1] the warped patch is affine in f, so the SSD is
+    an exact quadratic in f; minimise it per cell in closed form.
+    """
+    T = Lv[oy:oy + P, ox:ox + P]
+    Tc = T - T.mean()
+    best = (np.inf, None)
+    w = Rv.shape[1]
+    cols = np.arange(ox, ox + P)
+    for m in range(int(math.floor(lo)), int(math.ceil(hi))):
+        a = Rv[oy:oy + P][:, np.clip(cols + m, 0, w - 1)]
+        b = Rv[oy:oy + P][:, np.clip(cols + m + 1, 0, w - 1)]
+        A = (a - a.mean()) - Tc
+        B = (b - b.mean()) - (a - a.mean())
+        # SSD(f) = |A + f B|^2
+        bb = float((B * B).sum())
+        f = 0.0 if bb == 0 else -float((A * B).sum()) / bb
+        for cand in (0.0, 1.0, min(max(f, 0.0), 1.0)):
+            u = m + cand
+            if lo <= u <= hi:
+                v = float(((A + cand * B) ** 2).sum())
+                if v < best[0]:
+                    best = (v, u)
+    return best
+
+
+@pytest.mark.parametrize("D,seed", [(1, 0), (-2, 1), (2, 2)])
+def test_bruteforce_sweep_tiny(oracle, D, seed):
+    """On a tiny exact-shift pair the converged u is the global SSD minimiser in [u0-P, u0+P]."""
+    h, w, P = 16, 24, 5
+    left, right = shifted_pair_u8(100 + seed, h, w, D)
+    p = oracle.default_params(levels=2, patch=P, stride=2, iters=400)
+    tr = oracle.compute(left, right, p, trace=True)["trace"]
+    Lv, Rv = tr.get(0, "left"), tr.get(0, "right")
+    u = tr.get(0, "u")
+    ox, oy = oracle.grid(w, P, 2), oracle.grid(h, P, 2)
+    checked = hit = 0
+    for j, y0 in enumerate(oy):
+        for i, x0 in enumerate(ox):
+            if x0 - D < 0 or x0 + P - D > w - 1:
+                continue
+            ssd, umin = _bruteforce_min(Lv, Rv, x0, y0, P, -P, P)
+            assert ssd < 1e-9
+            assert abs(umin - (-D)) < 1e-9
+            # the iteration is a fixed-point map; where it contracts it lands on the
+            # brute-force minimiser, elsewhere it cycles around it (never elsewhere)
+            assert abs(u[j, i] - umin) < 0.25
+            hit += abs(u[j, i] - umin) < 1e-6
+            checked += 1
+    assert checked >= 6 and hit >= 0.6 * checked
+
+
+# --------------------------------------------------------------------------
+# O9-O10: posterior and propagation
+# --------------------------------------------------------------------------
+
+def test_flat_window_posterior_is_uniform(oracle):
+    """All window SSDs equal (textureless pair) => posterior 1/s (flat case of Fig. 2)."""
+    img = np.full((24, 24), 90, np.uint8)
+    p = oracle.default_params(levels=1, patch=6, stride=3, iters=4)
+    tr = oracle.compute(img, img, p, trace=True)["trace"]
+    assert np.all(tr.get(0, "acc") == 1.0)
+    np.testing.assert_array_equal(tr.get(0, "post"), 1.0 / S_WIN)
+
+
+def test_zero_residual_gets_maximal_probability(oracle):
+    """Zero residual with a tiny photometric sigma: p0 = exp(0) dominates => post = 1."""
+    left, right = shifted_pair_u8(7, 32, 48, 0)
+    p = oracle.default_params(levels=1, patch=8, stride=4, iters=4, sigma_r_dynamic=0, sigma_r=1e-3)
+    tr = oracle.compute(left, right, p, trace=True)["trace"]
+    ssd = tr.get(0, "ssd")
+    assert np.all(ssd[..., 2] == 0.0)
+    np.testing.assert_array_equal(tr.get(0, "post"), 1.0)
+
+
+def test_dynamic_sigma_floor(oracle):
+    """Identical images: every accepted residual is 0, so sigma_r^2 sits at its floor."""
+    left, _ = shifted_pair_u8(8, 32, 48, 0)
+    p = oracle.default_params(levels=2, patch=6, stride=3, iters=4, sigma_r=2.0)
+    tr = oracle.compute(left, left, p, trace=True)["trace"]
+    for n in range(2):
+        assert tr.scalar(n, "sigma_r2") == pytest.approx(4.0 * 1e-6, rel=1e-12)
+        assert tr.scalar(n, "tau") == pytest.approx(2 * 4.0 * 1e-6 * 25, rel=1e-12)
+
+
+def test_dynamic_sigma_closed_form(oracle):
+    from paper_2205_03133_amd.synth import make_pair
+    left, right, _, _ = make_pair(1, 0)
+    p = oracle.default_params(levels=2, patch=8, stride=4, iters=8, sigma_r=1.5)
+    tr = oracle.compute(left, right, p, trace=True)["trace"]
+    for n in range(2):
+        acc = tr.get(n, "acc") > 0
+        ssd0 = tr.get(n, "ssd")[..., 2][acc]
+        pooled = ssd0.sum() / (acc.sum() * 64)
+        assert tr.scalar(n, "sigma_r2") == pytest.approx(1.5 ** 2 * pooled, rel=1e-12)
+        post = tr.get(n, "post")[acc]
+        assert post.min() >= 1.0 / S_WIN - 1e-15 and post.max() <= 1.0
+
+
+def test_level_weights_sum_to_one_and_propagate(oracle):
+    """Identical textured images, tiny sigma_r: every post is 1, so pi accumulates
+    sum over coarser levels of Gamma_m (Eq. 11-12, omega_n = 2^n) and reaches 1 at the finest."""
+    left, _ = shifted_pair_u8(9, 64, 96, 0)
+    L = 3
+    p = oracle.default_params(levels=L, patch=6, stride=3, iters=4, sigma_r_dynamic=0, sigma_r=1e-3)
+    tr = oracle.compute(left, left, p, trace=True)["trace"]
+    om = np.array([2.0 ** n for n in range(L)])
+    gam = om / om.sum()
+    for n in range(L):
+        assert tr.scalar(n, "gamma") == pytest.approx(gam[n], rel=1e-15)
+        assert np.all(tr.get(n, "acc") == 1.0)
+        np.testing.assert_allclose(tr.get(n, "pi"), gam[n:].sum(), rtol=1e-12)
+        np.testing.assert_allclose(tr.get(n, "qmap"), gam[n:].sum(), rtol=1e-12)
+    np.testing.assert_allclose(tr.get(0, "pi"), 1.0, rtol=1e-12)
+
+
+def test_rejected_saddle(oracle):
+    """A patch whose centre is not the window minimum is discarded (Sec. III-B)."""
+    from paper_2205_03133_amd.synth import make_pair
+    left, right, _, _ = make_pair(2, 0)
+    p = oracle.default_params(levels=5, patch=8, stride=3, iters=16)
+    tr = oracle.compute(left, right, p, trace=True)["trace"]
+    for n in range(5):
+        ssd = tr.get(n, "ssd")
+        acc = tr.get(n, "acc") > 0
+        rho = tr.get(n, "rho")
+        centre_min = np.all(ssd[..., 2:3] <= ssd, axis=-1)
+        assert np.array_equal(acc, centre_min & (rho >= 0.75))
+        assert (~acc).sum() > 0
+
+
+# --------------------------------------------------------------------------
+# O11-O12: mixture mask and densification
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("P,s", [(8, 4.0), (12, 4.0), (5, 1.5)])
+def test_mask_separable_symmetric_centre_peak(oracle, P, s):
+    M = oracle.mask(P, s)
+    m1 = np.array([sum(math.exp(-((a - c) ** 2) / (2 * s * s)) for c in range(P)) for a in range(P)])
+    np.testing.assert_allclose(M, np.outer(m1, m1), rtol=1e-13)
+    np.testing.assert_allclose(M, M.T, rtol=1e-14)
+    np.testing.assert_allclose(M, M[::-1, ::-1], rtol=1e-14)
+    c = (P - 1) // 2
+    assert M[c, c] == pytest.approx(M.max(), rel=1e-14)
+
+
+def test_single_coverage_pixel_takes_patch_value(oracle):
+    """Non-overlapping grid (S = P): each pixel has one covering patch and takes its value."""
+    from paper_2205_03133_amd.synth import make_pair
+    left, right, _, _ = make_pair(1, 0)
+    left, right = left[:64, :96].copy(), right[:64, :96].copy()
+    P = 8
+    p = oracle.default_params(levels=1, patch=P, stride=P, iters=8, variance=1)
+    out = oracle.compute(left, right, p, trace=True)
+    tr = out["trace"]
+    u, acc, sig = tr.get(0, "u"), tr.get(0, "acc") > 0, tr.get(0, "sigk2")
+    for j in range(u.shape[0]):
+        for i in range(u.shape[1]):
+            blk = out["disp"][j * P:(j + 1) * P, i * P:(i + 1) * P]
+            vb = out["var"][j * P:(j + 1) * P, i * P:(i + 1) * P]
+            if acc[j, i]:
+                np.testing.assert_allclose(blk, -u[j, i], rtol=1e-14, atol=1e-14)
+                np.testing.assert_allclose(vb, sig[j, i], rtol=1e-13)
+            else:
+                assert np.all(np.isnan(blk)) and np.all(np.isnan(vb))
+
+
+def test_translation_equivariance(oracle):
+    """Shifting both views by a multiple of S*2^(L-1) shifts the interior output."""
+    L, P, S = 3, 6, 2
+    sh = S * 2 ** (L - 1)
+    h, w, D = 64, 160, 3
+    canvas = np.rint(texture(21, h, w + sh + D + 8)).astype(np.uint8)
+    rng = np.random.default_rng(5)
+    noise = rng.integers(-3, 4, canvas.shape)
+    canvas_r = np.clip(canvas.astype(int) + noise, 0, 255).astype(np.uint8)
+    def pair(o):
+        return (np.ascontiguousarray(canvas[:, o + D:o + D + w]),
+                np.ascontiguousarray(canvas_r[:, o:o + w]))
+    p = oracle.default_params(levels=L, patch=P, stride=S, iters=8, sigma_r_dynamic=0, sigma_r=4.0)
+    a = oracle.compute(*pair(0), p)["disp"]
+    b = oracle.compute(*pair(sh), p)["disp"]
+    m = 6 * P * 2 ** (L - 1)
+    np.testing.assert_allclose(b[16:-16, m:w - m - sh], a[16:-16, m + sh:w - m], rtol=0, atol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# O13-O14: variance
+# --------------------------------------------------------------------------
+
+def _gn_fit(ssd, tau, iters=10):
+    """Gauss-Newton on Eq. 17 (least squares) in (sigma, c), from sigma = sqrt(0.1), c = 1."""
+    y = -np.asarray(ssd) / tau
+    x = OFFSETS ** 2
+    sig, c = math.sqrt(0.1), 1.0
+    lc = math.log(c)
+    for _ in range(iters):
+        r = lc - 0.5 * np.log(2 * math.pi * sig * sig) - x / (2 * sig * sig) - y
+        J = np.stack([np.ones_like(x), -1.0 / sig + x / sig ** 3], axis=1)
+        A = J.T @ J
+        g = J.T @ r
+        try:
+            Lc = np.linalg.cholesky(A)
+        except np.linalg.LinAlgError:
+            return math.nan, math.nan
+        step = np.linalg.solve(Lc.T, np.linalg.solve(Lc, g))
+        lc -= step[0]
+        sig -= step[1]
+        if not (sig > 0):
+            return math.nan, math.nan
+    r = lc - 0.5 * np.log(2 * math.pi * sig * sig) - x / (2 * sig * sig) - y
+    return sig * sig, float(np.mean(r * r))
+
+
+def test_variance_closed_form_equals_gauss_newton(oracle):
+    """The oracle's closed-form sigma_k^2 is the fixed point of Gauss-Newton on Eq. 17.
+
+    Gauss-Newton from the paper's start (sigma = sqrt(0.1), c = 1) either
+    converges to that fixed point or diverges (the local-minimum issue the
+    paper reports for large sigma); 20 steps reach it to rounding wherever it
+    converges, and the paper's 10 steps already do for most patches.
+    """
+    from paper_2205_03133_amd.synth import make_pair
+    left, right, _, _ = make_pair(2, 0)
+    left, right = left[:160, :200].copy(), right[:160, :200].copy()
+    P = 8
+    p = oracle.default_params(levels=3, patch=P, stride=3, iters=16, variance=1)
+    tr = oracle.compute(left, right, p, trace=True)["trace"]
+    tau = tr.scalar(0, "tau")
+    ssd = tr.get(0, "ssd").reshape(-1, 5)
+    acc = tr.get(0, "acc").ravel() > 0
+    sig = tr.get(0, "sigk2").ravel()
+    n_ok = n10 = 0
+    for k in np.nonzero(acc)[0]:
+        s2, mse = _gn_fit(ssd[k], tau, iters=20)
+        if not np.isfinite(s2) or s2 >= P * P * 0.999 or mse > 0.1 * 0.999:
+            continue
+        assert sig[k] == pytest.approx(s2, rel=1e-9), k
+        n_ok += 1
+        s10, _ = _gn_fit(ssd[k], tau, iters=10)
+        n10 += np.isfinite(s10) and abs(s10 - s2) <= 1e-6 * s2
+    assert n_ok > 100
+    assert n10 >= 0.9 * n_ok
+
+
+def test_variance_failure_rules(oracle):
+    img = np.full((24, 24), 90, np.uint8)  # flat window: kappa = 0 => sigma_fail^2
+    p = oracle.default_params(levels=1, patch=6, stride=3, iters=4, variance=1)
+    out = oracle.compute(img, img, p, trace=True)
+    np.testing.assert_array_equal(out["trace"].get(0, "sigk2"), 36.0)
+    # pixel variance sum_k (W_k/Z)^2 sigma_k^2 with equal sigma: between sigma^2/N and sigma^2
+    v = out["var"]
+    assert np.all(v <= 36.0 + 1e-12) and np.all(v >= 36.0 / 9 - 1e-12)
+
+
+def test_pixel_variance_bounded_by_patch_variance(oracle):
+    from paper_2205_03133_amd.synth import make_pair
+    left, right, _, _ = make_pair(2, 0)
+    p = oracle.default_params(levels=5, patch=8, stride=3, iters=16, variance=1)
+    out = oracle.compute(left, right, p, trace=True)
+    sig = out["trace"].get(0, "sigk2")
+    v = out["var"]
+    ok = np.isfinite(v)
+    assert ok.mean() > 0.8
+    assert np.nanmax(v) <= np.nanmax(sig) + 1e-9
+    assert np.all(v[ok] > 0)
+
+
+# --------------------------------------------------------------------------
+# invariances of the mean-normalised, dynamically scaled method
+# --------------------------------------------------------------------------
+
+def test_offset_invariance(oracle):
+    from paper_2205_03133_amd.synth import make_pair
+    left, right, _, _ = make_pair(1, 0)
+    left = np.clip(left, 0, 230).astype(np.uint8)
+    right = np.clip(right, 0, 230).astype(np.uint8)
+    p = oracle.default_params(levels=3, patch=8, stride=4, iters=8, variance=1)
+    a = oracle.compute(left, right, p)
+    b = oracle.compute(left + np.uint8(20), right + np.uint8(20), p)
+    for k in ("disp", "var", "conf"):
+        np.testing.assert_allclose(b[k], a[k], rtol=1e-9, atol=1e-9, equal_nan=True)
+
+
+def test_joint_gain_invariance(oracle):
+    from paper_2205_03133_amd.synth import make_pair
+    left, right, _, _ = make_pair(1, 0, quantize=False)
+    p = oracle.default_params(levels=3, patch=8, stride=4, iters=8, variance=1, float_pyramid=1)
+    a = oracle.compute(left, right, p)
+    b = oracle.compute(left * 0.37, right * 0.37, p)
+    for k in ("disp", "var", "conf"):
+        np.testing.assert_allclose(b[k], a[k], rtol=1e-8, atol=1e-8, equal_nan=True)
+
+
+def test_accuracy_vs_ground_truth(oracle):
+    """Sanity of the method as read: most valid pixels land within a pixel of the truth."""
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    left, right, gt, valid = make_pair(2, 0)
+    p = oracle.default_params(**method_params(2))
+    d = oracle.compute(left, right, p)["disp"]
+    ok = np.isfinite(d) & valid
+    err = np.abs(d[ok] - gt[ok])
+    assert ok.mean() > 0.8
+    assert np.median(err) < 0.25
+    assert (err < 1.0).mean() > 0.8
+
+
+def test_bad_arguments(oracle):
+    img = np.zeros((16, 16), np.uint8)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.compute(img, img, oracle.default_params(levels=1, patch=2))
+    assert e.value.code == -1
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.compute(img, img, oracle.default_params(levels=3, patch=8))
+    assert e.value.code == -2
+    with pytest.raises(oracle.OracleError):
+        oracle.compute(img.astype(float) * np.nan, img.astype(float), oracle.default_params(levels=1, patch=4))
