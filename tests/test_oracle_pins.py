@@ -202,6 +202,21 @@ def test_row_linear_one_step_exact(oracle, d):
     np.testing.assert_allclose(tr.get(0, "sigk2")[sel], sig, rtol=1e-9)
 
 
+def test_search_stays_within_patch_threshold(oracle):
+    """Unrelated views: the search never ends further than P from its start
+    (the patch searching threshold; runaway patches fall back to the start)."""
+    rng = np.random.default_rng(11)
+    left = np.rint(texture(12, 48, 64)).astype(np.uint8)
+    right = rng.integers(0, 256, (48, 64), dtype=np.uint8)
+    P = 6
+    p = oracle.default_params(levels=2, patch=P, stride=3, iters=16)
+    tr = oracle.compute(left, right, p, trace=True)["trace"]
+    for n in range(2):
+        du = np.abs(tr.get(n, "u") - tr.get(n, "uinit"))
+        assert du.max() <= P
+        assert np.any(du == 0.0) and np.any(du > 0.0)
+
+
 def test_zero_hessian_keeps_start(oracle):
     flat = np.full((20, 30), 100, np.uint8)
     other = np.random.default_rng(0).integers(0, 256, (20, 30), dtype=np.uint8)
@@ -446,15 +461,20 @@ def test_variance_closed_form_equals_gauss_newton(oracle):
     acc = tr.get(0, "acc").ravel() > 0
     sig = tr.get(0, "sigk2").ravel()
     n_ok = n10 = 0
+    n_bad = 0
     for k in np.nonzero(acc)[0]:
         s2, mse = _gn_fit(ssd[k], tau, iters=20)
+        if np.isfinite(s2) and mse > 0.1 * 1.001:
+            # a converged fit whose residual exceeds the threshold fails (Sec. III-E)
+            assert sig[k] == P * P
+            n_bad += 1
         if not np.isfinite(s2) or s2 >= P * P * 0.999 or mse > 0.1 * 0.999:
             continue
         assert sig[k] == pytest.approx(s2, rel=1e-9), k
         n_ok += 1
         s10, _ = _gn_fit(ssd[k], tau, iters=10)
         n10 += np.isfinite(s10) and abs(s10 - s2) <= 1e-6 * s2
-    assert n_ok > 100
+    assert n_ok > 100 and n_bad > 0
     assert n10 >= 0.9 * n_ok
 
 
