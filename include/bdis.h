@@ -1,0 +1,167 @@
+/*
+ * bdis.h -- C ABI of the MI355X (gfx950) BDIS dense-inverse-search stereo library.
+ *
+ * BDIS (Song, Zhu, Lin, Ghaffari, arXiv 2205.03133) estimates per-pixel
+ * disparity of a rectified stereo pair by a coarse-to-fine dense inverse
+ * search (Sec. III, Fig. 1): per pyramid level, a per-patch inverse-
+ * compositional 1-D Lucas-Kanade search (Eq. 1), a Bayesian window posterior
+ * per patch (Eq. 5-6), and probability-weighted fusion of the overlapping
+ * patches through a spatial Gaussian mixture (Eq. 9-13), with the fused map
+ * initialising the next finer level.  An optional per-pixel variance follows
+ * Eq. 15-18 (disparity form, without the depth Jacobian).
+ *
+ * Conventions shared by every entry point:
+ *  - Image and output pointers are DEVICE pointers (HBM of the current HIP
+ *    device), row-major, `pitch` in ELEMENTS, pitch >= w.  Outputs are written
+ *    with pitch w (dense H x W).
+ *  - Disparity is d = x_left - x_right: left pixel x matches right pixel x - d.
+ *  - Every output pixel is written.  Invalid pixels (no accepted patch covers
+ *    them at the finest level, or confidence below `prob_thresh`) get NaN
+ *    disparity, NaN variance and confidence 0.
+ *  - The caller owns inputs and outputs.  The library owns its workspace,
+ *    allocated in bdis_create and released in bdis_destroy.
+ *  - Compute calls are asynchronous on `stream` (a hipStream_t; NULL is the
+ *    null stream).  They never synchronise the host.
+ *  - Errors are returned as bdis_status; the library never aborts.  The text
+ *    of the last error of a context is available from bdis_last_error.
+ *  - A context is not thread-safe: calls on one context must not overlap.
+ */
+#ifndef BDIS_H
+#define BDIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bdis_ctx bdis_ctx;
+
+typedef enum {
+  BDIS_OK = 0,
+  BDIS_E_ARG = -1,      /* null pointer, parameter out of range, non-finite float input   */
+  BDIS_E_SIZE = -2,     /* a processed pyramid level is smaller than the patch            */
+  BDIS_E_CAPACITY = -3, /* request exceeds the limits given to bdis_create               */
+  BDIS_E_HIP = -4,      /* a HIP runtime call failed (text in bdis_last_error)            */
+  BDIS_E_NOMEM = -5,    /* workspace allocation failed; the context stays usable         */
+  BDIS_E_STATE = -6     /* call not valid in the current state                          */
+} bdis_status;
+
+#define BDIS_MAX_LEVELS 8
+#define BDIS_MAX_PATCH 16
+
+/* Method parameters.  Defaults (bdis_params_default) follow the parameter
+ * list of Sec. IV-A where the paper gives a value. */
+typedef struct {
+  int32_t levels;          /* L, 1..8: pyramid levels n = L-1 (coarsest) .. finest_level     */
+  int32_t finest_level;    /* f: finest processed level; 0 (full resolution) is supported   */
+  int32_t patch;           /* P, 3..16: square patch side (paper: 10)                        */
+  int32_t stride;          /* S, 1..P: patch-grid stride (paper: overlap 0.55 -> S = 4)      */
+  int32_t iters;           /* K, 1..256: fixed inverse-compositional iterations (paper: 12)  */
+  int32_t sigma_r_dynamic; /* 1: sigma_r from the spread of the level's residuals (Sec.III-B)*/
+  int32_t variance;        /* 1: per-patch (Eq. 15-17) and per-pixel (Eq. 18) variance      */
+  int32_t float_pyramid;   /* 0 for the uint8 entry points (integer-rounded pyramid)        */
+  float sigma_s;           /* spatial sigma of the mixture kernel, level px (paper: 4)       */
+  float sigma_r;           /* fixed sigma_r (dynamic == 0) or its scale alpha_r (dynamic)   */
+  float valid_ratio;       /* gamma: least in-bounds fraction of an accepted patch (0.75)    */
+  float var_fail_sigma;    /* sigma given to a failed variance fit; <= 0 means P             */
+  float var_fit_thresh;    /* largest mean squared fit residual of Eq. 17 (paper: 0.1)       */
+  float prob_thresh;       /* confidence below this is invalid; 0 disables (paper: 0.15)     */
+  float level_weight[BDIS_MAX_LEVELS]; /* omega_n: level n weighs omega_n / sum (Eq. 12: 2^n) */
+} bdis_params;
+
+/* One stereo pair of a batch (all pointers device pointers). */
+typedef struct {
+  const uint8_t* left;
+  const uint8_t* right;
+  int32_t w, h, pitch;
+  int32_t levels;          /* pyramid depth for this pair; 0 means params.levels           */
+  float* disparity;        /* H x W, required                                             */
+  float* variance;         /* H x W, or NULL                                              */
+  float* confidence;       /* H x W, or NULL                                              */
+} bdis_pair;
+
+/* Fills *p with the defaults.  BDIS_E_ARG if p is NULL. */
+bdis_status bdis_params_default(bdis_params* p);
+
+/* Checks parameters on their own (no image size).  BDIS_OK or BDIS_E_ARG. */
+bdis_status bdis_params_check(const bdis_params* p);
+
+/* Creates a context for images up to max_w x max_h and batches of up to
+ * max_batch pairs, allocating its device workspace on the current device.
+ * flags: 0 (reserved).  On failure *out is NULL.
+ * Errors: BDIS_E_ARG (null out/params, bad params, max_* < 1),
+ *         BDIS_E_SIZE (max_w x max_h too small for the levels and patch),
+ *         BDIS_E_NOMEM, BDIS_E_HIP. */
+bdis_status bdis_create(bdis_ctx** out, const bdis_params* p, int max_w, int max_h, int max_batch,
+                        unsigned flags);
+
+/* Replaces the method parameters of a context.  Parameters that size the
+ * workspace (levels, patch, stride) must stay within what bdis_create sized:
+ * otherwise BDIS_E_CAPACITY and the old parameters stay in force. */
+bdis_status bdis_set_params(bdis_ctx* ctx, const bdis_params* p);
+
+/* One rectified uint8 pair -> disparity (required), variance and confidence
+ * (nullable).  variance must be NULL unless params.variance is 1.
+ * Errors: BDIS_E_ARG, BDIS_E_SIZE (image too small for levels/patch),
+ *         BDIS_E_CAPACITY (w > max_w or h > max_h), BDIS_E_HIP. */
+bdis_status bdis_compute(bdis_ctx* ctx, const uint8_t* left, const uint8_t* right, int w, int h,
+                         int pitch, float* disparity, float* variance, float* confidence,
+                         void* stream);
+
+/* A batch of n pairs of possibly different sizes and pyramid depths, all in
+ * one call (every level of every pair in a fixed sequence of launches).
+ * pairs is a HOST array of n descriptors.  Outputs as bdis_compute.
+ * Errors: as bdis_compute, plus BDIS_E_CAPACITY if n > max_batch. */
+bdis_status bdis_compute_batch(bdis_ctx* ctx, int n, const bdis_pair* pairs, void* stream);
+
+/* Debug access to the intermediates of the last single-pair compute (the
+ * call synchronises `stream`).  `what` selects the array (BDIS_DBG_*), bytes
+ * is the capacity of host_dst; returns BDIS_E_ARG if too small. */
+enum {
+  BDIS_DBG_LEFT = 0,    /* uint8 level image, W_n x H_n                              */
+  BDIS_DBG_RIGHT = 1,   /* uint8 level image                                         */
+  BDIS_DBG_UINIT = 2,   /* float per patch: initial displacement                     */
+  BDIS_DBG_PIPAR = 3,   /* float per patch: probability propagated from the parent   */
+  BDIS_DBG_U = 4,       /* float per patch: final displacement (= -disparity)        */
+  BDIS_DBG_SSD0 = 5,    /* float per patch: window SSD at the centre                 */
+  BDIS_DBG_DSSD = 6,    /* float4 per patch: SSD(d) - SSD(0) for d = -1,-1/2,1/2,1   */
+  BDIS_DBG_RHO = 7,     /* float per patch: in-bounds ratio                          */
+  BDIS_DBG_ACC = 8,     /* int32 per patch: 1 accepted                               */
+  BDIS_DBG_HESS = 9,    /* float per patch: Hessian                                  */
+  BDIS_DBG_DENS = 10,   /* float4 per patch: (u, weight pi or 0, sigma_k^2, post)    */
+  BDIS_DBG_UBAR = 11,   /* float level map (levels above the finest)                 */
+  BDIS_DBG_QMAP = 12,   /* float level map (levels above the finest)                 */
+  BDIS_DBG_SCAL = 13    /* double[2]: sigma_r^2, tau of the level                    */
+};
+bdis_status bdis_debug_dump(bdis_ctx* ctx, int level, int what, void* host_dst, size_t bytes,
+                            void* stream);
+
+/* Per-kernel timing with HIP events recorded on the compute stream around
+ * every launch (for measurement; adds two event records per launch).
+ * kernel: 0 pyramid, 1 patch search, 2 patch probability, 3 fusion.
+ * bdis_timing_enable(ctx, 1) clears the totals and starts recording;
+ * bdis_timing_read synchronises the recorded events and returns the summed
+ * GPU time (ms) and the launch count of one kernel since enabling. */
+enum { BDIS_K_PYRAMID = 0, BDIS_K_SEARCH = 1, BDIS_K_PROB = 2, BDIS_K_FUSE = 3, BDIS_K_COUNT = 4 };
+bdis_status bdis_timing_enable(bdis_ctx* ctx, int enable);
+bdis_status bdis_timing_read(bdis_ctx* ctx, int kernel, double* total_ms, long* launches);
+
+/* Geometry of level `level` for a w x h input: level size and patch grid. */
+bdis_status bdis_level_dims(const bdis_params* p, int w, int h, int level, int* lw, int* lh,
+                            int* nx, int* ny);
+
+/* Frees the context and its workspace (synchronises the device). NULL is a no-op. */
+void bdis_destroy(bdis_ctx* ctx);
+
+/* Text of the last error on ctx (or of the last failed bdis_create if ctx is NULL). */
+const char* bdis_last_error(const bdis_ctx* ctx);
+
+/* Library version string. */
+const char* bdis_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BDIS_H */

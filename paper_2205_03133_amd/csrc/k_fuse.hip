@@ -1,0 +1,164 @@
+// Patch probability and fusion of the overlapping patches into the level maps.
+//
+// k_prob (one lane per patch): window posterior post = p0 / sum_d p_d with
+//   p_d = exp(-SSD_d / tau), tau = 2 sigma_r^2 s^2 (Eq. 5-6), in the stable
+//   form 1 / sum_d exp(-(SSD_d - SSD_0) / tau); the level's contribution
+//   Gamma_n * post plus the probability propagated from the parent level
+//   (Eq. 11-12); at the finest level the patch variance of Eq. 15-17, whose
+//   Gauss-Newton fixed point is the least-squares line of ln p on d^2:
+//   sigma_k^2 = tau / (2 kappa), kappa the slope of SSD_d on d^2.
+//
+// k_densify (one lane per level pixel, gather): over the accepted patches
+//   covering the pixel, in ascending patch index, weights W_k = M(x - o_k) pi_k
+//   with the spatial mixture mask M(a, b) = m(a) m(b),
+//   m(a) = sum_c exp(-(a - c)^2 / (2 sigma_s^2)) (Eq. 9-10, unit mixture
+//   weights); fused displacement sum W u / sum W (Eq. 13, normalised),
+//   confidence sum M pi / sum M, variance sum (W / sum W)^2 sigma_k^2 (Eq. 18,
+//   disparity form).  A gather has no atomics, so results are deterministic.
+#include "bdis_internal.h"
+
+namespace bdis {
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_prob(ProbArgs a) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.np) return;
+  const float u = a.pa.u[k];
+  if (!a.pa.acc[k]) {
+    a.pa.dens[k] = make_float4(u, -1.0f, __builtin_nanf(""), 0.0f);
+    return;
+  }
+  const double tau = a.scal[1];
+  const float4 d = a.pa.dssd[k];
+  const float inv_tau = (float)(1.0 / tau);
+  const float den = 1.0f + expf(-d.x * inv_tau) + expf(-d.y * inv_tau) + expf(-d.z * inv_tau) +
+                    expf(-d.w * inv_tau);
+  const float post = 1.0f / den;
+  float wsum = 0.0f;
+  for (int n = a.finest; n < a.levels; ++n) wsum += a.omega[n];
+  const float gamma = a.omega[a.level] / wsum;
+  const float pi = gamma * post + a.pa.pipar[k];
+  float sig = __builtin_nanf("");
+  if (a.variance && a.level == a.finest) {
+    const double sfail = a.var_fail_sigma > 0.0f ? (double)a.var_fail_sigma : (double)a.P;
+    // OLS of y_d = SSD_d - SSD_0 on x_d = d^2, x = (1, 1/4, 0, 1/4, 1), mean x = 1/2,
+    // sum (x - mean x)^2 = 7/8.
+    const double y[5] = {d.x, d.y, 0.0, d.z, d.w};
+    const double x[5] = {1.0, 0.25, 0.0, 0.25, 1.0};
+    const double ym = (y[0] + y[1] + y[2] + y[3] + y[4]) / 5.0;
+    double sxy = 0.0;
+    for (int t = 0; t < 5; ++t) sxy += (x[t] - 0.5) * y[t];
+    const double kappa = sxy / 0.875;
+    double v = sfail * sfail;
+    if (kappa > 0.0) {
+      double mse = 0.0;
+      for (int t = 0; t < 5; ++t) {
+        const double res = (y[t] - (ym + kappa * (x[t] - 0.5))) / tau;
+        mse += res * res;
+      }
+      mse /= 5.0;
+      if (mse <= (double)a.var_fit_thresh) {
+        const double s2 = tau / (2.0 * kappa);
+        v = s2 < v ? s2 : v;
+      }
+    }
+    sig = (float)v;
+  }
+  a.pa.dens[k] = make_float4(u, pi, sig, post);
+}
+
+constexpr int kDx = 64, kDy = 4;
+
+// Covering patches along one axis: indices lo..hi (origin i*S), plus the last
+// patch (origin n-P) when it covers x but lies past hi.
+BDIS_DEV void cover_range(int x, int n, int P, int S, int cnt, int& lo, int& hi, int& extra) {
+  const int t = x - P;  // origin must exceed x - P
+  lo = t >= 0 ? t / S + 1 : 0;
+  hi = min(x / S, cnt - 1);
+  extra = (x >= n - P && cnt - 1 > hi) ? cnt - 1 : -1;
+}
+
+__global__ __launch_bounds__(kDx* kDy) void k_densify(DensifyArgs a) {
+  __shared__ float s_m[kMaxPatch];
+  const int tid = threadIdx.x;
+  if (tid < a.P) {
+    const float inv = 1.0f / (2.0f * a.sigma_s * a.sigma_s);
+    float acc = 0.0f;
+    for (int c = 0; c < a.P; ++c) {
+      const float dd = (float)(tid - c);
+      acc += expf(-dd * dd * inv);
+    }
+    s_m[tid] = acc;
+  }
+  __syncthreads();
+  const int x = blockIdx.x * kDx + tid % kDx;
+  const int y = blockIdx.y * kDy + tid / kDx;
+  if (x >= a.g.w || y >= a.g.h) return;
+  const int P = a.P, S = a.S;
+  int ilo, ihi, iex, jlo, jhi, jex;
+  cover_range(x, a.g.w, P, S, a.g.nx, ilo, ihi, iex);
+  cover_range(y, a.g.h, P, S, a.g.ny, jlo, jhi, jex);
+  float z = 0.0f, zu = 0.0f, zm = 0.0f, zv = 0.0f;
+  const int jend = jex >= 0 ? jhi + 1 : jhi;
+  const int iend = iex >= 0 ? ihi + 1 : ihi;
+  for (int jj = jlo; jj <= jend; ++jj) {
+    const int j = jj <= jhi ? jj : jex;
+    const float mb = s_m[y - grid_origin(j, a.g.h, P, S)];
+    const float4* row = a.dens + (size_t)j * a.g.nx;
+    for (int ii = ilo; ii <= iend; ++ii) {
+      const int i = ii <= ihi ? ii : iex;
+      const float4 d = row[i];
+      if (d.y < 0.0f) continue;  // rejected patch
+      const float m = s_m[x - grid_origin(i, a.g.w, P, S)] * mb;
+      const float wk = m * d.y;
+      z += wk;
+      zu += wk * d.x;
+      zm += m;
+      zv += wk * wk * d.z;
+    }
+  }
+  const size_t idx = (size_t)y * a.g.w + x;
+  float ub, qv;
+  bool valid = z > 0.0f;
+  if (valid) {
+    ub = zu / z;
+    qv = z / zm;
+  } else if (a.finest) {
+    ub = __builtin_nanf("");
+    qv = 0.0f;
+  } else if (a.par_ubar) {
+    // hole above the finest level: the parent estimate
+    ub = 2.0f * bilinear(a.par_ubar, a.pw, a.ph, 0.5f * x, 0.5f * y);
+    qv = bilinear(a.par_q, a.pw, a.ph, 0.5f * x, 0.5f * y);
+  } else {
+    ub = 0.0f;
+    qv = 0.0f;
+  }
+  if (!a.finest) {
+    a.ubar[idx] = ub;
+    a.qmap[idx] = qv;
+    return;
+  }
+  if (a.prob_thresh > 0.0f && qv < a.prob_thresh) valid = false;
+  const float nan = __builtin_nanf("");
+  a.disparity[idx] = valid ? -ub : nan;
+  if (a.confidence) a.confidence[idx] = valid ? qv : 0.0f;
+  if (a.variance) a.variance[idx] = (valid && a.variance_on) ? zv / (z * z) : nan;
+}
+
+}  // namespace
+
+hipError_t launch_prob(const ProbArgs& a, hipStream_t s) {
+  if (a.np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prob, dim3((a.np + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_densify(const DensifyArgs& a, hipStream_t s) {
+  dim3 grid((a.g.w + kDx - 1) / kDx, (a.g.h + kDy - 1) / kDy);
+  hipLaunchKernelGGL(k_densify, grid, dim3(kDx * kDy), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace bdis

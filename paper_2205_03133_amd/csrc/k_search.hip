@@ -1,0 +1,340 @@
+// Per-patch inverse-compositional 1-D search, Bayesian window and acceptance
+// (Eq. 1 with the inverse roles of Sec. III-A; window of Eq. 5-6 with offsets
+// -1, -1/2, 0, +1/2, +1 of Sec. IV-A; saddle / in-bounds rejection of
+// Sec. III-B and III-F), plus the level reduction that sets sigma_r^(n)
+// (Sec. III-B).
+//
+// Mapping: one lane per patch row, an aligned group of G = 8 or 16 lanes per
+// patch (a DPP quad/half-row/row, so group reductions are 3-4 DPP adds),
+// 256/G patches of one patch row per workgroup.  The left rows around those
+// patches (for the template and its Sobel gradient) and a window of the right
+// rows around the patches' starting displacements are staged in LDS once;
+// right-image samples outside the window fall back to (clamped) global loads.
+//
+// Arithmetic.  The uint8 path keeps every image sum exact in int32:
+//   with e_i(u) = I_w,i(u) - T_i and J_i = (G_i - sum G / N) / 8 (N = P^2),
+//   sum J_i e_i = [(1-f) E(m) + f E(m+1)] / (8 N),  u = m + f, m = floor(u),
+//   E(m) = N (sum G R(m) - sum G T) - sum G (sum R(m) - sum T),
+//   H = sum J^2 = (N sum G^2 - (sum G)^2) / (64 N),
+// so the update u <- u - sum J e / H (Eq. 1, inverse compositional) needs the
+// integer correlations of two cells; they are cached per cell, so iterations
+// that stay in the same unit cell cost a few scalar flops.  The window SSD of a
+// unit cell is an exact quadratic in the fraction f:
+//   SSD = [X0 + 2 f X1 + f^2 X2] / N with integer X0, X1, X2 (see below).
+// Only the final combinations are rounded (in double).
+#include "bdis_internal.h"
+
+#include <climits>
+
+namespace bdis {
+
+namespace {
+
+// Reads N consecutive right-image samples of one row starting at column x:
+// from the LDS window when it covers them, else from global memory with the
+// column clamped to the image (identical values either way).
+template <int N>
+BDIS_DEV void fetch_row(int (&v)[N], const uint8_t* win, int xs, int rw, const uint8_t* grow,
+                        int x, int W) {
+  const int off = x - xs;
+  if (off >= 0 && off + N <= rw) {
+#pragma unroll
+    for (int n = 0; n < N; ++n) v[n] = win[off + n];
+  } else {
+#pragma unroll
+    for (int n = 0; n < N; ++n) v[n] = grow[clampi(x + n, 0, W - 1)];
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_search_u8(SearchArgs a) {
+  constexpr int G = group_lanes(P);
+  constexpr int NPB = kThreads / G;              // patches per workgroup
+  constexpr int LTW = (NPB - 1) * P + P + 2;     // left tile width bound (S <= P)
+  constexpr int MARG = P + 4;                    // window margin around the start range
+  constexpr int N = P * P;
+
+  __shared__ uint8_t s_left[(P + 2) * LTW];
+  __shared__ uint8_t s_right[P * kWinRow];
+  __shared__ int s_umin, s_umax;
+  __shared__ double s_psum[NPB];
+  __shared__ int s_pcnt[NPB];
+  __shared__ int s_last;
+
+  const int tid = threadIdx.x;
+  const int q = tid / G;  // patch slot in the workgroup
+  const int r = tid % G;  // patch row of this lane
+  const int W = a.g.w, Hh = a.g.h, S = a.S;
+  const int j = blockIdx.y;
+  const int i0 = blockIdx.x * NPB;
+  const bool live = (i0 + q) < a.g.nx;
+  const int i = live ? i0 + q : a.g.nx - 1;
+  const int ilast = min(i0 + NPB - 1, a.g.nx - 1);
+  const int ox = grid_origin(i, W, P, S);
+  const int oy = grid_origin(j, Hh, P, S);
+  const int ox0 = grid_origin(i0, W, P, S);
+  const int oxl = grid_origin(ilast, W, P, S);
+
+  // ---- start from the parent level (Fig. 1): 2 * fused map at the centre
+  float uinit_f = 0.0f, pipar = 0.0f;
+  if (a.par_ubar) {
+    const float cx = 0.5f * ((float)ox + 0.5f * (float)(P - 1));
+    const float cy = 0.5f * ((float)oy + 0.5f * (float)(P - 1));
+    uinit_f = 2.0f * bilinear(a.par_ubar, a.pw, a.ph, cx, cy);
+    pipar = bilinear(a.par_q, a.pw, a.ph, cx, cy);
+  }
+  const double uinit = (double)uinit_f;
+
+  if (tid == 0) {
+    s_umin = INT_MAX;
+    s_umax = INT_MIN;
+  }
+  // ---- left tile: image rows oy-1 .. oy+P, columns ox0-1 .. oxl+P (reflect-101)
+  const int ltw = oxl - ox0 + P + 2;
+  for (int ty = 0; ty < P + 2; ++ty) {
+    const uint8_t* src = a.L + (size_t)reflect101(oy - 1 + ty, Hh) * a.pitch;
+    for (int tx = tid; tx < ltw; tx += kThreads) s_left[ty * LTW + tx] = src[reflect101(ox0 - 1 + tx, W)];
+  }
+  __syncthreads();
+  if (r == 0 && live) {
+    const int mu = (int)floor(uinit);
+    atomicMin(&s_umin, mu);
+    atomicMax(&s_umax, mu);
+  }
+  __syncthreads();
+  // ---- right window: rows oy .. oy+P-1, columns xs .. xs+rw-1 (clamped to the image)
+  const int xs = ox0 + s_umin - MARG;
+  const int rw = min(oxl + P + s_umax + MARG + 2 - xs, kWinRow);
+  for (int ty = 0; ty < P; ++ty) {
+    const uint8_t* src = a.R + (size_t)(oy + ty) * a.pitch;
+    for (int tx = tid; tx < rw; tx += kThreads) s_right[ty * kWinRow + tx] = src[clampi(xs + tx, 0, W - 1)];
+  }
+  __syncthreads();
+
+  // ---- template row: T and Sobel-x G (integer), rows r >= P are idle lanes
+  const bool row_live = r < P;
+  const int rr = row_live ? r : P - 1;
+  int T[P], Gx[P];
+  {
+    const uint8_t* l0 = s_left + rr * LTW + (ox - ox0);
+    const uint8_t* l1 = l0 + LTW;
+    const uint8_t* l2 = l1 + LTW;
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      T[c] = l1[c + 1];
+      Gx[c] = (l0[c + 2] - l0[c]) + 2 * (l1[c + 2] - l1[c]) + (l2[c + 2] - l2[c]);
+    }
+  }
+  int sG = 0, sT = 0, sGG = 0, sGT = 0;
+#pragma unroll
+  for (int c = 0; c < P; ++c) {
+    sG += Gx[c];
+    sT += T[c];
+    sGG += Gx[c] * Gx[c];
+    sGT += Gx[c] * T[c];
+  }
+  if (!row_live) sG = sT = sGG = sGT = 0;
+  sG = group_sum<G>(sG);
+  sT = group_sum<G>(sT);
+  sGG = group_sum<G>(sGG);
+  sGT = group_sum<G>(sGT);
+  const long long Hs = (long long)N * sGG - (long long)sG * sG;  // = 64 N H, exact
+  const double H = (double)Hs / (64.0 * N);
+  const bool invert = H >= kEpsH;
+  const double step = invert ? 8.0 / (double)Hs : 0.0;
+
+  const uint8_t* win = s_right + rr * kWinRow;
+  const uint8_t* grow = a.R + (size_t)(oy + rr) * a.pitch;
+
+  // ---- K inverse-compositional iterations (Eq. 1), cached cell correlations
+  double u = uinit;
+  if (invert) {
+    int mc = INT_MIN;
+    double E0 = 0.0, E1 = 0.0;
+    for (int t = 0; t < a.K; ++t) {
+      const double fm = floor(u);
+      const int m = (int)fm;
+      const double f = u - fm;
+      if (m != mc) {
+        int Rv[P + 1];
+        fetch_row<P + 1>(Rv, win, xs, rw, grow, ox + m, W);
+        int cg0 = 0, cs0 = 0, cg1 = 0, cs1 = 0;
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+          cg0 += Gx[c] * Rv[c];
+          cs0 += Rv[c];
+          cg1 += Gx[c] * Rv[c + 1];
+          cs1 += Rv[c + 1];
+        }
+        if (!row_live) cg0 = cs0 = cg1 = cs1 = 0;
+        cg0 = group_sum<G>(cg0);
+        cs0 = group_sum<G>(cs0);
+        cg1 = group_sum<G>(cg1);
+        cs1 = group_sum<G>(cs1);
+        E0 = (double)((long long)N * (cg0 - sGT) - (long long)sG * (cs0 - sT));
+        E1 = (double)((long long)N * (cg1 - sGT) - (long long)sG * (cs1 - sT));
+        mc = m;
+      }
+      u -= ((1.0 - f) * E0 + f * E1) * step;
+    }
+  }
+  // patch searching threshold: a run-away patch falls back to its start
+  if (fabs(u - uinit) > (double)P) u = uinit;
+
+  // ---- window SSDs.  Cell q in {0,1,2} is [m-1+q, m+q]; with a_i the sample
+  // at the cell's left end minus T_i and d_i the step to its right end,
+  // e_i(f) = a_i + f d_i and SSD(f) = sum (e - mean e)^2 = [X0 + 2fX1 + f^2X2]/N,
+  // X0 = N sum a^2 - (sum a)^2, X1 = N sum ad - sum a sum d, X2 = N sum d^2 - (sum d)^2.
+  const double fm = floor(u);
+  const int m = (int)fm;
+  const double f = u - fm;
+  double X0[3], X1[3], X2[3];
+  {
+    int Rv[P + 3];
+    fetch_row<P + 3>(Rv, win, xs, rw, grow, ox + m - 1, W);
+#pragma unroll
+    for (int cq = 0; cq < 3; ++cq) {
+      int sa = 0, saa = 0, sd = 0, sdd = 0, sad = 0;
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        const int av = Rv[c + cq] - T[c];
+        const int dv = Rv[c + cq + 1] - Rv[c + cq];
+        sa += av;
+        saa += av * av;
+        sd += dv;
+        sdd += dv * dv;
+        sad += av * dv;
+      }
+      if (!row_live) sa = saa = sd = sdd = sad = 0;
+      sa = group_sum<G>(sa);
+      saa = group_sum<G>(saa);
+      sd = group_sum<G>(sd);
+      sdd = group_sum<G>(sdd);
+      sad = group_sum<G>(sad);
+      X0[cq] = (double)((long long)N * saa - (long long)sa * sa);
+      X1[cq] = (double)((long long)N * sad - (long long)sa * sd);
+      X2[cq] = (double)((long long)N * sdd - (long long)sd * sd);
+    }
+  }
+  auto ssd = [&](int cq, double fr) { return (X0[cq] + fr * (2.0 * X1[cq] + fr * X2[cq])) / (double)N; };
+  const double s0 = ssd(1, f);
+  const double sm1 = ssd(0, f);
+  const double sp1 = ssd(2, f);
+  double smh, sph;
+  if (f >= 0.5) {
+    smh = ssd(1, f - 0.5);
+    sph = ssd(2, f - 0.5);
+  } else {
+    smh = ssd(0, f + 0.5);
+    sph = ssd(1, f + 0.5);
+  }
+  int inb = 0;
+#pragma unroll
+  for (int c = 0; c < P; ++c) {
+    const double xr = (double)(ox + c) + u;
+    inb += (xr >= 0.0 && xr <= (double)(W - 1)) ? 1 : 0;
+  }
+  const double rho = (double)(inb * P) / (double)N;
+  const bool acc = s0 <= sm1 && s0 <= smh && s0 <= sph && s0 <= sp1 && rho >= (double)a.valid_ratio;
+
+  const int k = j * a.g.nx + i;
+  if (r == 0 && live) {
+    a.pa.uinit[k] = uinit_f;
+    a.pa.pipar[k] = pipar;
+    a.pa.u[k] = (float)u;
+    a.pa.ssd0[k] = (float)s0;
+    a.pa.dssd[k] = make_float4((float)(sm1 - s0), (float)(smh - s0), (float)(sph - s0), (float)(sp1 - s0));
+    a.pa.rho[k] = (float)rho;
+    a.pa.acc[k] = acc ? 1 : 0;
+    a.pa.hess[k] = (float)H;
+  }
+
+  // ---- level reduction: sum of SSD(0) and count over accepted patches
+  if (r == 0) {
+    s_psum[q] = (live && acc) ? s0 : 0.0;
+    s_pcnt[q] = (live && acc) ? 1 : 0;
+  }
+  __syncthreads();
+  const int nblocks = gridDim.x * gridDim.y;
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  if (tid == 0) {
+    double ps = 0.0;
+    int pc = 0;
+    for (int t = 0; t < NPB; ++t) {
+      ps += s_psum[t];
+      pc += s_pcnt[t];
+    }
+    a.part_sum[bid] = ps;
+    a.part_cnt[bid] = pc;
+    __threadfence();
+    const unsigned prev = atomicAdd(a.counter, 1u);
+    s_last = (prev == (unsigned)(nblocks - 1)) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  // last workgroup: fixed-order reduction of all partials (deterministic)
+  __threadfence();
+  __shared__ double s_red[kThreads];
+  __shared__ long long s_redc[kThreads];
+  double ps = 0.0;
+  long long pc = 0;
+  for (int b = tid; b < nblocks; b += kThreads) {
+    ps += __hip_atomic_load(&a.part_sum[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    pc += __hip_atomic_load(&a.part_cnt[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  s_red[tid] = ps;
+  s_redc[tid] = pc;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      s_red[tid] += s_red[tid + off];
+      s_redc[tid] += s_redc[tid + off];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double sr2;
+    const double alpha2 = (double)a.sigma_r * (double)a.sigma_r;
+    if (a.sigma_r_dynamic) {
+      const double pooled = s_redc[0] > 0 ? s_red[0] / ((double)s_redc[0] * (double)N) : 0.0;
+      sr2 = alpha2 * (pooled > kEpsSigma ? pooled : kEpsSigma);
+    } else {
+      sr2 = alpha2;
+    }
+    a.scal[0] = sr2;
+    a.scal[1] = 2.0 * sr2 * 25.0;  // tau = 2 sigma_r^2 s^2, s = 5 window samples (Eq. 6)
+    __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <int P>
+hipError_t launch_p(const SearchArgs& a, hipStream_t s) {
+  constexpr int NPB = kThreads / group_lanes(P);
+  dim3 grid((a.g.nx + NPB - 1) / NPB, a.g.ny);
+  hipLaunchKernelGGL(k_search_u8<P>, grid, dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_search_u8(int P, const SearchArgs& a, hipStream_t s) {
+  switch (P) {
+    case 3: return launch_p<3>(a, s);
+    case 4: return launch_p<4>(a, s);
+    case 5: return launch_p<5>(a, s);
+    case 6: return launch_p<6>(a, s);
+    case 7: return launch_p<7>(a, s);
+    case 8: return launch_p<8>(a, s);
+    case 9: return launch_p<9>(a, s);
+    case 10: return launch_p<10>(a, s);
+    case 11: return launch_p<11>(a, s);
+    case 12: return launch_p<12>(a, s);
+    case 13: return launch_p<13>(a, s);
+    case 14: return launch_p<14>(a, s);
+    case 15: return launch_p<15>(a, s);
+    case 16: return launch_p<16>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace bdis

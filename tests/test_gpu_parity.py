@@ -1,0 +1,264 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Integer work (pyramid, patch grid) must match bit for bit; disparity within
+1e-3 px and variance within 1e-3 relative on >= 99.9% of pixels, validity-mask
+disagreements counted as misses, max error printed.
+"""
+import numpy as np
+import pytest
+
+from _common import DISP_TOL, PASS_FRAC, VAR_RTOL, oracle_params, parity, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2205_03133_amd import bdis
+    bdis.lib()
+    return bdis
+
+
+def _run(B, left, right, p, case):
+    import torch
+    print(f"[gpu] {case}: {left.shape[1]}x{left.shape[0]} L={p.levels} P={p.patch} S={p.stride} "
+          f"K={p.iters} var={p.variance}", flush=True)
+    h, w = left.shape
+    ctx = B.Context(p, w, h)
+    out = ctx.compute(to_gpu(left), to_gpu(right))
+    torch.cuda.synchronize()
+    res = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+    return ctx, res
+
+
+def _report(name, st):
+    print(f"  {name}: frac={st['frac']:.6f} max={st['max_err']:.3g} p99.9={st['p999']:.3g} "
+          f"mask_mismatch={st['mask_mismatch']} n={st['n']}", flush=True)
+
+
+@pytest.mark.parametrize("shape,L", [((217, 333), 4), ((64, 64), 3), ((101, 37), 3)])
+def test_pyramid_bit_exact(B, oracle, shape, L):
+    rng = np.random.default_rng(sum(shape))
+    left = rng.integers(0, 256, shape, dtype=np.uint8)
+    right = rng.integers(0, 256, shape, dtype=np.uint8)
+    p = B.params(levels=L, patch=3, stride=2, iters=2)
+    ctx, _ = _run(B, left, right, p, f"pyramid {shape}")
+    tr = oracle.compute(left, right, oracle_params(oracle, p), trace=True)["trace"]
+    for n in range(1, L):
+        assert np.array_equal(ctx.debug(n, "left").astype(np.float64), tr.get(n, "left"))
+        assert np.array_equal(ctx.debug(n, "right").astype(np.float64), tr.get(n, "right"))
+    ctx.close()
+
+
+def test_level_dims_match_oracle(B, oracle):
+    p = B.params(levels=6, patch=12, stride=4, iters=2)
+    for n in range(6):
+        lw, lh, nx, ny = B.level_dims(p, 1920, 1080, n)
+        assert nx == len(oracle.grid(lw, 12, 4)) and ny == len(oracle.grid(lh, 12, 4))
+
+
+def _patch_parity(B, ctx, tr, levels):
+    for n in range(levels):
+        acc_g = ctx.debug(n, "acc") > 0
+        acc_r = tr.get(n, "acc") > 0
+        agree = (acc_g == acc_r).mean()
+        ug, ur = ctx.debug(n, "u"), tr.get(n, "u")
+        ok = np.abs(ug - ur) <= DISP_TOL
+        print(f"  level {n}: patches={acc_g.size} flag_agree={agree:.5f} "
+              f"u_within_1e-3={ok.mean():.5f} max|du|={np.abs(ug - ur).max():.3g}", flush=True)
+        assert agree >= 0.995
+        assert ok.mean() >= 0.99
+        # the in-bounds ratio is exact wherever the displacements agree
+        rg, rr = ctx.debug(n, "rho"), tr.get(n, "rho")
+        same_u = np.abs(ug - ur) < 1e-6
+        assert np.array_equal(rg[same_u].astype(np.float64), rr[same_u].astype(np.float32).astype(np.float64))
+        # Hessian (exact integer form on the GPU)
+        np.testing.assert_allclose(ctx.debug(n, "hess"), tr.get(n, "hess"), rtol=2e-7, atol=1e-6)
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_end_to_end_workloads(B, oracle, cfg):
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    left, right, gt, valid = make_pair(cfg, 0)
+    p = B.params(**method_params(cfg))
+    ctx, g = _run(B, left, right, p, f"workload c{cfg}")
+    r = oracle.compute(left, right, oracle_params(oracle, p), trace=True)
+    _patch_parity(B, ctx, r["trace"], p.levels)
+    st = parity(g["disp"], r["disp"], DISP_TOL)
+    _report("disparity", st)
+    assert st["frac"] >= PASS_FRAC
+    stc = parity(g["conf"], r["conf"], 1e-4)
+    _report("confidence", stc)
+    assert stc["frac"] >= PASS_FRAC
+    if p.variance:
+        sv = parity(g["var"], r["var"], VAR_RTOL, rel=True)
+        _report("variance", sv)
+        assert sv["frac"] >= PASS_FRAC
+    ok = np.isfinite(g["disp"]) & valid
+    print(f"  EPE vs ground truth: median={np.median(np.abs(g['disp'][ok] - gt[ok])):.4f} px "
+          f"valid={np.isfinite(g['disp']).mean():.4f}", flush=True)
+    ctx.close()
+
+
+@pytest.mark.parametrize("shape,P,S,L,K", [((131, 257), 7, 3, 3, 10), ((97, 203), 16, 5, 2, 6),
+                                            ((50, 77), 3, 1, 3, 5), ((240, 320), 12, 4, 3, 16)])
+def test_ragged_shapes(B, oracle, shape, P, S, L, K):
+    from paper_2205_03133_amd.synth import make_pair
+    left, right, _, _ = make_pair(2, 3)
+    h, w = shape
+    left, right = np.ascontiguousarray(left[:h, :w]), np.ascontiguousarray(right[:h, :w])
+    p = B.params(levels=L, patch=P, stride=S, iters=K, variance=1)
+    ctx, g = _run(B, left, right, p, f"ragged {shape} P={P}")
+    r = oracle.compute(left, right, oracle_params(oracle, p))
+    st = parity(g["disp"], r["disp"], DISP_TOL)
+    _report("disparity", st)
+    assert st["frac"] >= PASS_FRAC
+    sv = parity(g["var"], r["var"], VAR_RTOL, rel=True)
+    _report("variance", sv)
+    assert sv["frac"] >= PASS_FRAC
+    ctx.close()
+
+
+def test_exact_shift_recovered_on_gpu(B):
+    """A textured pair shifted by an integer D comes back as D to 1e-6 px (interior)."""
+    from scipy import ndimage
+    rng = np.random.default_rng(4)
+    h, w, D = 96, 160, 6
+    t = ndimage.gaussian_filter(rng.standard_normal((h, w + 2 * D + 2)), 1.2, mode="wrap")
+    canvas = np.rint(20 + 215 * (t - t.min()) / (t.max() - t.min())).astype(np.uint8)
+    off = D + 1
+    left = np.ascontiguousarray(canvas[:, off:off + w])
+    right = np.ascontiguousarray(canvas[:, off + D:off + D + w])
+    p = B.params(levels=3, patch=8, stride=4, iters=32)
+    _, g = _run(B, left, right, p, "exact shift")
+    d = g["disp"][:, D + 24:w - D - 24]
+    np.testing.assert_allclose(d, D, atol=1e-6, rtol=0)
+
+
+def test_pitched_input(B, oracle):
+    """Row pitch larger than the width (views into a wider buffer)."""
+    import torch
+    from paper_2205_03133_amd.synth import make_pair
+    left, right, _, _ = make_pair(1, 1)
+    h, w = 200, 300
+    p = B.params(levels=3, patch=8, stride=4, iters=8)
+    lt = to_gpu(left)[:h, :w]
+    rt = to_gpu(right)[:h, :w]
+    assert lt.stride(0) == 320
+    print("[gpu] pitched input 300x200 pitch 320", flush=True)
+    ctx = B.Context(p, 320, 240)
+    out = ctx.compute(lt, rt)
+    torch.cuda.synchronize()
+    r = oracle.compute(np.ascontiguousarray(left[:h, :w]), np.ascontiguousarray(right[:h, :w]),
+                       oracle_params(oracle, p))
+    st = parity(out["disp"].cpu().numpy(), r["disp"], DISP_TOL)
+    _report("disparity", st)
+    assert st["frac"] >= PASS_FRAC
+    ctx.close()
+
+
+def test_smallest_image(B, oracle):
+    """The smallest legal input: every processed level exactly fits one patch column/row span."""
+    rng = np.random.default_rng(9)
+    P, L = 5, 2
+    w = h = 2 * P - 1  # level 1 is P x P: a single patch
+    left = rng.integers(0, 256, (h, w), dtype=np.uint8)
+    right = np.roll(left, -1, axis=1)
+    p = B.params(levels=L, patch=P, stride=2, iters=8, variance=1)
+    _, g = _run(B, left, right, p, "smallest")
+    r = oracle.compute(left, right, oracle_params(oracle, p))
+    st = parity(g["disp"], r["disp"], DISP_TOL)
+    _report("disparity", st)
+    assert st["frac"] == 1.0
+
+
+def test_errors_leave_context_usable(B):
+    import torch
+    from paper_2205_03133_amd.synth import make_pair
+    left, right, _, _ = make_pair(1, 0)
+    p = B.params(levels=3, patch=8, stride=4, iters=8)
+    ctx = B.Context(p, 320, 240)
+    lt, rt = to_gpu(left), to_gpu(right)
+    big = torch.zeros((300, 400), dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.BdisError) as e:
+        ctx.compute(big, big)
+    assert e.value.code == B.E_CAPACITY
+    tiny = torch.zeros((20, 20), dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.BdisError) as e:
+        ctx.compute(tiny, tiny)
+    assert e.value.code == B.E_SIZE
+    with pytest.raises(B.BdisError) as e:
+        ctx.compute(lt, rt, variance=True)  # params.variance is 0
+    assert e.value.code == B.E_ARG
+    with pytest.raises(B.BdisError) as e:
+        ctx.set_params(B.params(levels=3, patch=8, stride=1, iters=8))  # more patches than sized
+    assert e.value.code == B.E_CAPACITY
+    out = ctx.compute(lt, rt)
+    torch.cuda.synchronize()
+    assert torch.isfinite(out["disp"]).float().mean().item() > 0.8
+    ctx.close()
+
+
+def test_repeat_calls_identical(B):
+    """Deterministic: same input, same context, bitwise-identical outputs."""
+    import torch
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    left, right, _, _ = make_pair(2, 0)
+    p = B.params(**method_params(2))
+    ctx = B.Context(p, 640, 480)
+    lt, rt = to_gpu(left), to_gpu(right)
+    print("[gpu] repeat calls c2", flush=True)
+    a = ctx.compute(lt, rt)
+    torch.cuda.synchronize()
+    a = {k: v.clone() for k, v in a.items()}
+    for _ in range(3):
+        b = ctx.compute(lt, rt)
+        torch.cuda.synchronize()
+        for k in a:
+            assert torch.equal(torch.nan_to_num(a[k], nan=-7.0), torch.nan_to_num(b[k], nan=-7.0))
+    ctx.close()
+
+
+def test_full_size_1080p(B, oracle):
+    """The 1920x1080 batch-stream workload (P=12, 6 levels, variance) on one pair, whole image."""
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    left, right, gt, valid = make_pair(5, 0)
+    p = B.params(**method_params(5))
+    ctx, g = _run(B, left, right, p, "1080p c5 pair 0")
+    r = oracle.compute(left, right, oracle_params(oracle, p))
+    st = parity(g["disp"], r["disp"], DISP_TOL)
+    _report("disparity", st)
+    assert st["frac"] >= PASS_FRAC
+    sv = parity(g["var"], r["var"], VAR_RTOL, rel=True)
+    _report("variance", sv)
+    assert sv["frac"] >= PASS_FRAC
+    ctx.close()
+
+
+def test_batch_matches_single(B):
+    """compute_batch over pairs of different sizes and depths equals per-pair compute."""
+    import torch
+    from paper_2205_03133_amd.synth import make_pair
+    p = B.params(levels=4, patch=8, stride=3, iters=16, variance=1)
+    sizes = [(320, 240, 4), (360, 288, 4), (200, 150, 3), (640, 480, 4)]
+    lefts, rights = [], []
+    for idx, (w, h, _) in enumerate(sizes):
+        l, r, _, _ = make_pair(2, idx)
+        lefts.append(to_gpu(l[:h, :w]))
+        rights.append(to_gpu(r[:h, :w]))
+    print("[gpu] batch of 4 mixed sizes", flush=True)
+    ctx = B.Context(p, 640, 480, max_batch=4)
+    outs = ctx.compute_batch(lefts, rights, levels=[s[2] for s in sizes])
+    torch.cuda.synchronize()
+    outs = [{k: v.clone() for k, v in o.items()} for o in outs]
+    for i, (w, h, L) in enumerate(sizes):
+        q = B.params(levels=L, patch=8, stride=3, iters=16, variance=1)
+        ctx1 = B.Context(q, w, h)
+        one = ctx1.compute(lefts[i], rights[i])
+        torch.cuda.synchronize()
+        for k in ("disp", "var", "conf"):
+            assert torch.equal(torch.nan_to_num(outs[i][k], nan=-7.0), torch.nan_to_num(one[k], nan=-7.0)), (i, k)
+        ctx1.close()
+    ctx.close()
