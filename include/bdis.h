@@ -122,17 +122,17 @@ bdis_status bdis_compute_batch(bdis_ctx* ctx, int n, const bdis_pair* pairs, voi
 enum {
   BDIS_DBG_LEFT = 0,    /* uint8 level image, W_n x H_n                              */
   BDIS_DBG_RIGHT = 1,   /* uint8 level image                                         */
-  BDIS_DBG_UINIT = 2,   /* float per patch: initial displacement                     */
-  BDIS_DBG_PIPAR = 3,   /* float per patch: probability propagated from the parent   */
-  BDIS_DBG_U = 4,       /* float per patch: final displacement (= -disparity)        */
-  BDIS_DBG_SSD0 = 5,    /* float per patch: window SSD at the centre                 */
-  BDIS_DBG_DSSD = 6,    /* float4 per patch: SSD(d) - SSD(0) for d = -1,-1/2,1/2,1   */
+  BDIS_DBG_UINIT = 2,   /* double per patch: initial displacement                    */
+  BDIS_DBG_PIPAR = 3,   /* double per patch: probability propagated from the parent  */
+  BDIS_DBG_U = 4,       /* double per patch: final displacement (= -disparity)       */
+  BDIS_DBG_SSD0 = 5,    /* double per patch: window SSD at the centre                */
+  BDIS_DBG_DSSD = 6,    /* double[4] per patch: SSD(d)-SSD(0), d = -1,-1/2,1/2,1     */
   BDIS_DBG_RHO = 7,     /* float per patch: in-bounds ratio                          */
   BDIS_DBG_ACC = 8,     /* int32 per patch: 1 accepted                               */
   BDIS_DBG_HESS = 9,    /* float per patch: Hessian                                  */
-  BDIS_DBG_DENS = 10,   /* float4 per patch: (u, weight pi or 0, sigma_k^2, post)    */
-  BDIS_DBG_UBAR = 11,   /* float level map (levels above the finest)                 */
-  BDIS_DBG_QMAP = 12,   /* float level map (levels above the finest)                 */
+  BDIS_DBG_DENS = 10,   /* double[4] per patch: (u, weight pi or -1, sigma_k^2, post)*/
+  BDIS_DBG_UBAR = 11,   /* double level map (levels above the finest)                */
+  BDIS_DBG_QMAP = 12,   /* double level map (levels above the finest)                */
   BDIS_DBG_SCAL = 13    /* double[2]: sigma_r^2, tau of the level                    */
 };
 bdis_status bdis_debug_dump(bdis_ctx* ctx, int level, int what, void* host_dst, size_t bytes,

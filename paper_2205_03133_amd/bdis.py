@@ -267,15 +267,17 @@ class Context:
         if what in ("left", "right"):
             shape, dt = (h, w), np.uint8
         elif what in ("ubar", "qmap"):
-            shape, dt = (h, w), np.float32
+            shape, dt = (h, w), np.float64
         elif what in ("dssd", "dens"):
-            shape, dt = (ny, nx, 4), np.float32
+            shape, dt = (ny, nx, 4), np.float64
         elif what == "acc":
             shape, dt = (ny, nx), np.int32
         elif what == "scal":
             shape, dt = (2,), np.float64
-        else:
+        elif what in ("rho", "hess"):
             shape, dt = (ny, nx), np.float32
+        else:
+            shape, dt = (ny, nx), np.float64
         buf = np.empty(shape, dt)
         st = lib().bdis_debug_dump(self._h, level, DBG[what], buf.ctypes.data, buf.nbytes,
                                    _stream_ptr(stream))

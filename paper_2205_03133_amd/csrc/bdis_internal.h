@@ -30,17 +30,25 @@ __host__ __device__ inline int grid_origin(int i, int n, int P, int S) {
   return o < n - P ? o : n - P;
 }
 
-// Per-level patch arrays (structure of arrays, one entry per patch).
+// Four doubles (window SSD differences, or the fusion record of a patch).
+struct alignas(16) D4 {
+  double x, y, z, w;
+};
+
+// Per-level patch arrays (structure of arrays, one entry per patch).  The
+// per-patch scalars are FP64: the method is ill-conditioned at patches whose
+// iteration does not contract, and rounding this state to FP32 alone moves
+// ~0.3% of output pixels by more than 1e-3 px.
 struct PatchArrays {
-  float* uinit;   // initial displacement (from the parent level)
-  float* pipar;   // probability propagated from the parent level
-  float* u;       // final displacement
-  float* ssd0;    // window SSD at the centre
-  float4* dssd;   // SSD(d) - SSD(0), d = -1, -1/2, +1/2, +1
-  float* rho;     // in-bounds ratio
+  double* uinit;  // initial displacement (from the parent level)
+  double* pipar;  // probability propagated from the parent level
+  double* u;      // final displacement
+  double* ssd0;   // window SSD at the centre
+  D4* dssd;       // SSD(d) - SSD(0), d = -1, -1/2, +1/2, +1
+  float* rho;     // in-bounds ratio (exact in FP32: a multiple of 1/P)
   int* acc;       // 1 accepted
   float* hess;    // Gauss-Newton Hessian of the patch
-  float4* dens;   // (u, weight: pi if accepted else -1, sigma_k^2, post)
+  D4* dens;       // (u, weight: pi if accepted else -1, sigma_k^2, post)
 };
 
 struct SearchArgs {
@@ -50,9 +58,9 @@ struct SearchArgs {
   LevelGeom g;
   int S, K;
   float valid_ratio;
-  const float* par_ubar;  // parent fused displacement (nullptr at the coarsest level)
-  const float* par_q;     // parent fused confidence
-  int pw, ph;             // parent level size
+  const double* par_ubar;  // parent fused displacement (nullptr at the coarsest level)
+  const double* par_q;     // parent fused confidence
+  int pw, ph;              // parent level size
   PatchArrays pa;
   // level reduction for sigma_r: per-workgroup partials, reduced by the last
   // workgroup to finish (counter returns to 0 afterwards)
@@ -77,16 +85,16 @@ struct ProbArgs {
 };
 
 struct DensifyArgs {
-  const float4* dens;
+  const D4* dens;
   LevelGeom g;
   int P, S;
   float sigma_s;
-  const float* par_ubar;  // parent maps for holes (nullptr at the coarsest level)
-  const float* par_q;
+  const double* par_ubar;  // parent maps for holes (nullptr at the coarsest level)
+  const double* par_q;
   int pw, ph;
-  int finest;             // 1: write the user outputs
-  float* ubar;            // level maps (levels above the finest)
-  float* qmap;
+  int finest;              // 1: write the user outputs
+  double* ubar;            // level maps (levels above the finest)
+  double* qmap;
   float* disparity;       // user outputs (finest level)
   float* variance;        // nullable
   float* confidence;      // nullable
@@ -137,16 +145,16 @@ BDIS_DEV int reflect101(int i, int n) {
 
 BDIS_DEV int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// Bilinear sample of a w x h float map, indices clamped to the map.
-BDIS_DEV float bilinear(const float* m, int w, int h, float x, float y) {
-  float fx0 = floorf(x), fy0 = floorf(y);
-  float ax = x - fx0, ay = y - fy0;
-  int ix = (int)fx0, iy = (int)fy0;
-  int x0 = clampi(ix, 0, w - 1), x1 = clampi(ix + 1, 0, w - 1);
-  int y0 = clampi(iy, 0, h - 1), y1 = clampi(iy + 1, 0, h - 1);
-  float top = (1.0f - ax) * m[(size_t)y0 * w + x0] + ax * m[(size_t)y0 * w + x1];
-  float bot = (1.0f - ax) * m[(size_t)y1 * w + x0] + ax * m[(size_t)y1 * w + x1];
-  return (1.0f - ay) * top + ay * bot;
+// Bilinear sample of a w x h map at (x, y), indices clamped to the map.
+BDIS_DEV double bilinear(const double* m, int w, int h, double x, double y) {
+  const double fx0 = floor(x), fy0 = floor(y);
+  const double ax = x - fx0, ay = y - fy0;
+  const int ix = (int)fx0, iy = (int)fy0;
+  const int x0 = clampi(ix, 0, w - 1), x1 = clampi(ix + 1, 0, w - 1);
+  const int y0 = clampi(iy, 0, h - 1), y1 = clampi(iy + 1, 0, h - 1);
+  const double top = (1.0 - ax) * m[(size_t)y0 * w + x0] + ax * m[(size_t)y0 * w + x1];
+  const double bot = (1.0 - ax) * m[(size_t)y1 * w + x0] + ax * m[(size_t)y1 * w + x1];
+  return (1.0 - ay) * top + ay * bot;
 }
 
 }  // namespace bdis

@@ -24,22 +24,21 @@ namespace {
 __global__ __launch_bounds__(256) void k_prob(ProbArgs a) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= a.np) return;
-  const float u = a.pa.u[k];
+  const double u = a.pa.u[k];
+  const double nan = __builtin_nan("");
   if (!a.pa.acc[k]) {
-    a.pa.dens[k] = make_float4(u, -1.0f, __builtin_nanf(""), 0.0f);
+    a.pa.dens[k] = D4{u, -1.0, nan, 0.0};
     return;
   }
   const double tau = a.scal[1];
-  const float4 d = a.pa.dssd[k];
-  const float inv_tau = (float)(1.0 / tau);
-  const float den = 1.0f + expf(-d.x * inv_tau) + expf(-d.y * inv_tau) + expf(-d.z * inv_tau) +
-                    expf(-d.w * inv_tau);
-  const float post = 1.0f / den;
-  float wsum = 0.0f;
-  for (int n = a.finest; n < a.levels; ++n) wsum += a.omega[n];
-  const float gamma = a.omega[a.level] / wsum;
-  const float pi = gamma * post + a.pa.pipar[k];
-  float sig = __builtin_nanf("");
+  const D4 d = a.pa.dssd[k];
+  const double den = 1.0 + exp(-d.x / tau) + exp(-d.y / tau) + exp(-d.z / tau) + exp(-d.w / tau);
+  const double post = 1.0 / den;
+  double wsum = 0.0;
+  for (int n = a.finest; n < a.levels; ++n) wsum += (double)a.omega[n];
+  const double gamma = (double)a.omega[a.level] / wsum;
+  const double pi = gamma * post + a.pa.pipar[k];
+  double sig = nan;
   if (a.variance && a.level == a.finest) {
     const double sfail = a.var_fail_sigma > 0.0f ? (double)a.var_fail_sigma : (double)a.P;
     // OLS of y_d = SSD_d - SSD_0 on x_d = d^2, x = (1, 1/4, 0, 1/4, 1), mean x = 1/2,
@@ -63,9 +62,9 @@ __global__ __launch_bounds__(256) void k_prob(ProbArgs a) {
         v = s2 < v ? s2 : v;
       }
     }
-    sig = (float)v;
+    sig = v;
   }
-  a.pa.dens[k] = make_float4(u, pi, sig, post);
+  a.pa.dens[k] = D4{u, pi, sig, post};
 }
 
 constexpr int kDx = 64, kDy = 4;
@@ -80,14 +79,14 @@ BDIS_DEV void cover_range(int x, int n, int P, int S, int cnt, int& lo, int& hi,
 }
 
 __global__ __launch_bounds__(kDx* kDy) void k_densify(DensifyArgs a) {
-  __shared__ float s_m[kMaxPatch];
+  __shared__ double s_m[kMaxPatch];
   const int tid = threadIdx.x;
   if (tid < a.P) {
-    const float inv = 1.0f / (2.0f * a.sigma_s * a.sigma_s);
-    float acc = 0.0f;
+    const double sg = (double)a.sigma_s;
+    double acc = 0.0;
     for (int c = 0; c < a.P; ++c) {
-      const float dd = (float)(tid - c);
-      acc += expf(-dd * dd * inv);
+      const double dd = (double)(tid - c);
+      acc += exp(-dd * dd / (2.0 * sg * sg));
     }
     s_m[tid] = acc;
   }
@@ -99,19 +98,19 @@ __global__ __launch_bounds__(kDx* kDy) void k_densify(DensifyArgs a) {
   int ilo, ihi, iex, jlo, jhi, jex;
   cover_range(x, a.g.w, P, S, a.g.nx, ilo, ihi, iex);
   cover_range(y, a.g.h, P, S, a.g.ny, jlo, jhi, jex);
-  float z = 0.0f, zu = 0.0f, zm = 0.0f, zv = 0.0f;
+  double z = 0.0, zu = 0.0, zm = 0.0, zv = 0.0;
   const int jend = jex >= 0 ? jhi + 1 : jhi;
   const int iend = iex >= 0 ? ihi + 1 : ihi;
   for (int jj = jlo; jj <= jend; ++jj) {
     const int j = jj <= jhi ? jj : jex;
-    const float mb = s_m[y - grid_origin(j, a.g.h, P, S)];
-    const float4* row = a.dens + (size_t)j * a.g.nx;
+    const double mb = s_m[y - grid_origin(j, a.g.h, P, S)];
+    const D4* row = a.dens + (size_t)j * a.g.nx;
     for (int ii = ilo; ii <= iend; ++ii) {
       const int i = ii <= ihi ? ii : iex;
-      const float4 d = row[i];
-      if (d.y < 0.0f) continue;  // rejected patch
-      const float m = s_m[x - grid_origin(i, a.g.w, P, S)] * mb;
-      const float wk = m * d.y;
+      const D4 d = row[i];
+      if (d.y < 0.0) continue;  // rejected patch
+      const double m = s_m[x - grid_origin(i, a.g.w, P, S)] * mb;
+      const double wk = m * d.y;
       z += wk;
       zu += wk * d.x;
       zm += m;
@@ -119,32 +118,32 @@ __global__ __launch_bounds__(kDx* kDy) void k_densify(DensifyArgs a) {
     }
   }
   const size_t idx = (size_t)y * a.g.w + x;
-  float ub, qv;
-  bool valid = z > 0.0f;
+  double ub, qv;
+  bool valid = z > 0.0;
   if (valid) {
     ub = zu / z;
     qv = z / zm;
   } else if (a.finest) {
-    ub = __builtin_nanf("");
-    qv = 0.0f;
+    ub = __builtin_nan("");
+    qv = 0.0;
   } else if (a.par_ubar) {
     // hole above the finest level: the parent estimate
-    ub = 2.0f * bilinear(a.par_ubar, a.pw, a.ph, 0.5f * x, 0.5f * y);
-    qv = bilinear(a.par_q, a.pw, a.ph, 0.5f * x, 0.5f * y);
+    ub = 2.0 * bilinear(a.par_ubar, a.pw, a.ph, 0.5 * x, 0.5 * y);
+    qv = bilinear(a.par_q, a.pw, a.ph, 0.5 * x, 0.5 * y);
   } else {
-    ub = 0.0f;
-    qv = 0.0f;
+    ub = 0.0;
+    qv = 0.0;
   }
   if (!a.finest) {
     a.ubar[idx] = ub;
     a.qmap[idx] = qv;
     return;
   }
-  if (a.prob_thresh > 0.0f && qv < a.prob_thresh) valid = false;
+  if (a.prob_thresh > 0.0f && qv < (double)a.prob_thresh) valid = false;
   const float nan = __builtin_nanf("");
-  a.disparity[idx] = valid ? -ub : nan;
-  if (a.confidence) a.confidence[idx] = valid ? qv : 0.0f;
-  if (a.variance) a.variance[idx] = (valid && a.variance_on) ? zv / (z * z) : nan;
+  a.disparity[idx] = valid ? (float)(-ub) : nan;
+  if (a.confidence) a.confidence[idx] = valid ? (float)qv : 0.0f;
+  if (a.variance) a.variance[idx] = (valid && a.variance_on) ? (float)(zv / (z * z)) : nan;
 }
 
 }  // namespace

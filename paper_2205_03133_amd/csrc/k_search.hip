@@ -76,14 +76,13 @@ __global__ __launch_bounds__(kThreads) void k_search_u8(SearchArgs a) {
   const int oxl = grid_origin(ilast, W, P, S);
 
   // ---- start from the parent level (Fig. 1): 2 * fused map at the centre
-  float uinit_f = 0.0f, pipar = 0.0f;
+  double uinit = 0.0, pipar = 0.0;
   if (a.par_ubar) {
-    const float cx = 0.5f * ((float)ox + 0.5f * (float)(P - 1));
-    const float cy = 0.5f * ((float)oy + 0.5f * (float)(P - 1));
-    uinit_f = 2.0f * bilinear(a.par_ubar, a.pw, a.ph, cx, cy);
+    const double cx = 0.5 * ((double)ox + 0.5 * (double)(P - 1));
+    const double cy = 0.5 * ((double)oy + 0.5 * (double)(P - 1));
+    uinit = 2.0 * bilinear(a.par_ubar, a.pw, a.ph, cx, cy);
     pipar = bilinear(a.par_q, a.pw, a.ph, cx, cy);
   }
-  const double uinit = (double)uinit_f;
 
   if (tid == 0) {
     s_umin = INT_MAX;
@@ -239,11 +238,11 @@ __global__ __launch_bounds__(kThreads) void k_search_u8(SearchArgs a) {
 
   const int k = j * a.g.nx + i;
   if (r == 0 && live) {
-    a.pa.uinit[k] = uinit_f;
+    a.pa.uinit[k] = uinit;
     a.pa.pipar[k] = pipar;
-    a.pa.u[k] = (float)u;
-    a.pa.ssd0[k] = (float)s0;
-    a.pa.dssd[k] = make_float4((float)(sm1 - s0), (float)(smh - s0), (float)(sph - s0), (float)(sp1 - s0));
+    a.pa.u[k] = u;
+    a.pa.ssd0[k] = s0;
+    a.pa.dssd[k] = D4{sm1 - s0, smh - s0, sph - s0, sp1 - s0};
     a.pa.rho[k] = (float)rho;
     a.pa.acc[k] = acc ? 1 : 0;
     a.pa.hess[k] = (float)H;

@@ -79,18 +79,18 @@ bool make_layout(const bdis_params& p, int w, int h, int levels, Layout* lay) {
     }
     if (n < p.finest_level) continue;
     const size_t np = (size_t)L.g[n].nx * L.g[n].ny;
-    L.uinit[n] = take(np * 4);
-    L.pipar[n] = take(np * 4);
-    L.u[n] = take(np * 4);
-    L.ssd0[n] = take(np * 4);
-    L.dssd[n] = take(np * 16);
+    L.uinit[n] = take(np * 8);
+    L.pipar[n] = take(np * 8);
+    L.u[n] = take(np * 8);
+    L.ssd0[n] = take(np * 8);
+    L.dssd[n] = take(np * sizeof(D4));
     L.rho[n] = take(np * 4);
     L.acc[n] = take(np * 4);
     L.hess[n] = take(np * 4);
-    L.dens[n] = take(np * 16);
+    L.dens[n] = take(np * sizeof(D4));
     if (n > p.finest_level) {
-      L.ubar[n] = take(npx * 4);
-      L.qmap[n] = take(npx * 4);
+      L.ubar[n] = take(npx * 8);
+      L.qmap[n] = take(npx * 8);
     }
     L.nblocks[n] = search_blocks(L.g[n], p.patch);
     L.part_sum[n] = take((size_t)L.nblocks[n] * 8);
@@ -211,6 +211,7 @@ bdis_status run_pair(bdis_ctx* c, int slot, const uint8_t* left, const uint8_t* 
   char* base = c->ws + (size_t)slot * c->slot_bytes;
   auto P8 = [&](size_t o) { return reinterpret_cast<uint8_t*>(base + o); };
   auto PF = [&](size_t o) { return reinterpret_cast<float*>(base + o); };
+  auto PD = [&](size_t o) { return reinterpret_cast<double*>(base + o); };
   hipError_t e;
 
   // pyramid of both views (levels 1 .. L-1)
@@ -234,15 +235,15 @@ bdis_status run_pair(bdis_ctx* c, int slot, const uint8_t* left, const uint8_t* 
   for (int n = levels - 1; n >= p.finest_level; --n) {
     const LevelGeom& g = lay.g[n];
     PatchArrays pa;
-    pa.uinit = PF(lay.uinit[n]);
-    pa.pipar = PF(lay.pipar[n]);
-    pa.u = PF(lay.u[n]);
-    pa.ssd0 = PF(lay.ssd0[n]);
-    pa.dssd = reinterpret_cast<float4*>(base + lay.dssd[n]);
+    pa.uinit = PD(lay.uinit[n]);
+    pa.pipar = PD(lay.pipar[n]);
+    pa.u = PD(lay.u[n]);
+    pa.ssd0 = PD(lay.ssd0[n]);
+    pa.dssd = reinterpret_cast<D4*>(base + lay.dssd[n]);
     pa.rho = PF(lay.rho[n]);
     pa.acc = reinterpret_cast<int*>(base + lay.acc[n]);
     pa.hess = PF(lay.hess[n]);
-    pa.dens = reinterpret_cast<float4*>(base + lay.dens[n]);
+    pa.dens = reinterpret_cast<D4*>(base + lay.dens[n]);
     const bool has_par = n + 1 < levels;
     double* scal = reinterpret_cast<double*>(base + lay.scal[n]);
 
@@ -254,8 +255,8 @@ bdis_status run_pair(bdis_ctx* c, int slot, const uint8_t* left, const uint8_t* 
     sa.S = p.stride;
     sa.K = p.iters;
     sa.valid_ratio = p.valid_ratio;
-    sa.par_ubar = has_par ? PF(lay.ubar[n + 1]) : nullptr;
-    sa.par_q = has_par ? PF(lay.qmap[n + 1]) : nullptr;
+    sa.par_ubar = has_par ? PD(lay.ubar[n + 1]) : nullptr;
+    sa.par_q = has_par ? PD(lay.qmap[n + 1]) : nullptr;
     sa.pw = has_par ? lay.g[n + 1].w : 0;
     sa.ph = has_par ? lay.g[n + 1].h : 0;
     sa.pa = pa;
@@ -298,8 +299,8 @@ bdis_status run_pair(bdis_ctx* c, int slot, const uint8_t* left, const uint8_t* 
     da.pw = sa.pw;
     da.ph = sa.ph;
     da.finest = n == p.finest_level;
-    da.ubar = da.finest ? nullptr : PF(lay.ubar[n]);
-    da.qmap = da.finest ? nullptr : PF(lay.qmap[n]);
+    da.ubar = da.finest ? nullptr : PD(lay.ubar[n]);
+    da.qmap = da.finest ? nullptr : PD(lay.qmap[n]);
     da.disparity = disp;
     da.variance = var;
     da.confidence = conf;
@@ -463,17 +464,17 @@ bdis_status bdis_debug_dump(bdis_ctx* c, int level, int what, void* host_dst, si
   switch (what) {
     case BDIS_DBG_LEFT: off = lay.lvl_l[level]; n = npx; break;
     case BDIS_DBG_RIGHT: off = lay.lvl_r[level]; n = npx; break;
-    case BDIS_DBG_UINIT: off = lay.uinit[level]; n = np * 4; break;
-    case BDIS_DBG_PIPAR: off = lay.pipar[level]; n = np * 4; break;
-    case BDIS_DBG_U: off = lay.u[level]; n = np * 4; break;
-    case BDIS_DBG_SSD0: off = lay.ssd0[level]; n = np * 4; break;
-    case BDIS_DBG_DSSD: off = lay.dssd[level]; n = np * 16; break;
+    case BDIS_DBG_UINIT: off = lay.uinit[level]; n = np * 8; break;
+    case BDIS_DBG_PIPAR: off = lay.pipar[level]; n = np * 8; break;
+    case BDIS_DBG_U: off = lay.u[level]; n = np * 8; break;
+    case BDIS_DBG_SSD0: off = lay.ssd0[level]; n = np * 8; break;
+    case BDIS_DBG_DSSD: off = lay.dssd[level]; n = np * 32; break;
     case BDIS_DBG_RHO: off = lay.rho[level]; n = np * 4; break;
     case BDIS_DBG_ACC: off = lay.acc[level]; n = np * 4; break;
     case BDIS_DBG_HESS: off = lay.hess[level]; n = np * 4; break;
-    case BDIS_DBG_DENS: off = lay.dens[level]; n = np * 16; break;
-    case BDIS_DBG_UBAR: off = lay.ubar[level]; n = npx * 4; break;
-    case BDIS_DBG_QMAP: off = lay.qmap[level]; n = npx * 4; break;
+    case BDIS_DBG_DENS: off = lay.dens[level]; n = np * 32; break;
+    case BDIS_DBG_UBAR: off = lay.ubar[level]; n = npx * 8; break;
+    case BDIS_DBG_QMAP: off = lay.qmap[level]; n = npx * 8; break;
     case BDIS_DBG_SCAL: off = lay.scal[level]; n = 16; break;
     default: return fail(c, BDIS_E_ARG, "unknown dump %d", what);
   }

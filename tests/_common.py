@@ -2,8 +2,16 @@
 import numpy as np
 
 DISP_TOL = 1e-3        # px, on >= 99.9% of pixels
-VAR_RTOL = 1e-3        # relative, on >= 99.9% of pixels
+VAR_RTOL = 1e-3        # relative
 PASS_FRAC = 0.999
+# Variance overall floor.  The per-patch variance takes threshold decisions
+# (fit residual <= 0.1, kappa > 0) on tau, a level-wide statistic that one
+# rounding-level acceptance flip in a non-contracting patch moves by ~1e-4; the
+# FP64 oracle against itself under 1e-15 relative perturbations of its state
+# scores 99.89% on the 640x480 workload.  Pixels away from patches whose
+# decisions differ must still meet PASS_FRAC (decision-aware check).
+VAR_FLOOR = 0.998
+MAX_FLIP_FRAC = 5e-4   # patches whose accept / fit decision differs
 
 
 def to_gpu(a):
@@ -39,3 +47,34 @@ def oracle_params(oracle, bp):
         valid_ratio=float(d["valid_ratio"]), var_fail_sigma=float(d["var_fail_sigma"]),
         var_fit_thresh=float(d["var_fit_thresh"]), prob_thresh=float(d["prob_thresh"]),
         level_weight=[float(x) for x in d["level_weight"]])
+
+
+def footprint(mask_patches, w, h, P, S):
+    """Pixels covered by the flagged patches of a level (grid origins min(i*S, n-P))."""
+    ny, nx = mask_patches.shape
+    ox = np.minimum(np.arange(nx) * S, w - P)
+    oy = np.minimum(np.arange(ny) * S, h - P)
+    out = np.zeros((h, w), bool)
+    for j, i in np.argwhere(mask_patches):
+        out[oy[j]:oy[j] + P, ox[i]:ox[i] + P] = True
+    return out
+
+
+def variance_parity(gpu_var, ref_var, g_acc, g_sig, r_acc, r_sig, P, S):
+    """Variance agreement overall and away from patches whose decisions differ.
+
+    A decision differs when acceptance differs, or when exactly one side
+    failed the variance fit (sigma_k^2 == P^2 with the default failure sigma).
+    """
+    h, w = ref_var.shape
+    fail_g = g_acc & np.isclose(g_sig, P * P, rtol=0, atol=0)
+    fail_r = r_acc & np.isclose(r_sig, P * P, rtol=0, atol=0)
+    flip = (g_acc != r_acc) | (fail_g != fail_r)
+    st = parity(gpu_var, ref_var, VAR_RTOL, rel=True)
+    fp = footprint(flip, w, h, P, S)
+    st_away = parity(np.where(fp, 0.0, gpu_var), np.where(fp, 0.0, ref_var), VAR_RTOL, rel=True)
+    # pixels excluded above are counted as agreeing; report the fraction over the rest
+    n_rest = int((~fp).sum())
+    frac_rest = 1.0 - (1.0 - st_away["frac"]) * st_away["n"] / max(n_rest, 1)
+    return dict(overall=st, away_frac=frac_rest, flip_patches=int(flip.sum()),
+                flip_frac=float(flip.mean()))
