@@ -1,11 +1,15 @@
 """Throughput of the BDIS hot path on one MI355X.
 
-One step = one full coarse-to-fine pass (pyramid, patch search, probability,
-fusion, variance) over one 640x480 synthetic pair (5 levels, 8x8 patches,
-stride 3, 16 iterations, variance on), inputs resident in HBM.  Prints one
-JSON line with the throughput in output Mpixel/s, the roofline of the
-dominant kernel (the patch search) measured with HIP events over the timed
-region, and the FP64 CPU oracle's throughput on the host cores as a baseline.
+Headline: one step = one full coarse-to-fine pass (pyramid, patch search,
+probability, fusion, variance) over one 640x480 synthetic pair (5 levels, 8x8
+patches, stride 3, 16 iterations, variance on), inputs resident in HBM, through
+the library's default path (the captured launch graph).  A second timed region
+of the same K steps runs with per-kernel HIP events on the compute stream and
+gives the roofline of the dominant kernel (the patch search).
+
+Also reported: the 1920x1080 batch stream (6 levels, 12x12 patches, stride 4,
+16 iterations, variance on) on one GPU's share of 64 pairs, and the FP64 CPU
+oracle on the host cores as a baseline.
 """
 import argparse
 import concurrent.futures as cf
@@ -18,19 +22,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published fp32 vector peak
-HBM_PEAK_GBS = 8000.0
 WIN = 5
 
 
-def search_flops(bdis, p, w, h):
-    """Algorithmic flops of the patch search per pass: per patch 4P^2 (template
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def search_flops(bdis, p, w, h, levels=None):
+    """Algorithmic flops of the patch search of one pass: per patch 4P^2 (template
     setup) + 5KP^2 (K warped-patch iterations) + 8sP^2 (s-sample window), FMA = 2."""
     tot = 0
-    for n in range(p.levels):
+    P2 = p.patch * p.patch
+    for n in range(levels or p.levels):
         _, _, nx, ny = bdis.level_dims(p, w, h, n)
-        P2 = p.patch * p.patch
         tot += nx * ny * (4 * P2 + 5 * p.iters * P2 + 8 * WIN * P2)
     return tot
+
+
+def roofline(flops_per_step, steps, timing, kernel_name):
+    s_ms, s_n = timing["search"]
+    achieved = flops_per_step * steps / (s_ms * 1e-3) / 1e12
+    return dict(bound="alu", achieved=round(achieved, 3), peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5), traffic=None, kernel=kernel_name,
+                avg_launch_us=round(s_ms * 1e3 / max(s_n, 1), 3), launches=s_n)
+
+
+def kernel_table(tk):
+    return {k: dict(total_ms=round(v[0], 4), launches=v[1], avg_us=round(v[0] * 1e3 / max(v[1], 1), 3))
+            for k, v in tk.items()}
 
 
 def cpu_baseline(left, right, params, budget_s=16.0):
@@ -54,7 +74,92 @@ def cpu_baseline(left, right, params, budget_s=16.0):
     h, w = left.shape
     return dict(value=round(w * h * n / dt / 1e6, 4), unit="Mpixel/s", cores=threads, kind="oracle",
                 sample=f"{n} oracle passes over the 640x480 pair ({threads} threads x {reps}), "
-                       f"{dt:.1f} s wall")
+                       f"{dt:.1f} s wall, {n * t1:.1f} s of CPU work")
+
+
+def bench_single(bdis, torch, args):
+    import numpy as np
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    dev = torch.device("cuda:0")
+    left, right, gt, valid = make_pair(2, 0)
+    h, w = left.shape
+    p = bdis.params(**method_params(2))
+    ctx = bdis.Context(p, w, h)
+    lt = torch.from_numpy(left).to(dev)
+    rt = torch.from_numpy(right).to(dev)
+    out = {k: torch.empty((h, w), dtype=torch.float32, device=dev) for k in ("disp", "var", "conf")}
+    log(f"640x480 pair, L={p.levels} P={p.patch} S={p.stride} K={p.iters}: warmup {args.warmup}")
+    for _ in range(args.warmup):
+        ctx.compute(lt, rt, out=out)
+    torch.cuda.synchronize()
+    log(f"timed region: {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.compute(lt, rt, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"per-kernel event region: {args.steps} steps")
+    ctx.timing(True)
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.compute(lt, rt, out=out)
+    torch.cuda.synchronize()
+    dt_ev = time.perf_counter() - t1
+    tk = ctx.timing_read()
+    ctx.timing(False)
+    d = out["disp"].cpu().numpy()
+    ok = np.isfinite(d) & valid
+    epe = float(np.median(np.abs(d[ok] - gt[ok])))
+    ctx.close()
+    return dict(w=w, h=h, p=p, dt=dt, dt_ev=dt_ev, tk=tk, epe=epe, left=left, right=right,
+                mp=method_params(2))
+
+
+def bench_batch(bdis, torch, args):
+    """One GPU's share (64 pairs) of the 512-pair 1920x1080 stream, one call per step."""
+    import numpy as np
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    dev = torch.device("cuda:0")
+    uniq = args.batch_unique
+    log(f"1080p batch: generating {uniq} pairs")
+    base = [make_pair(5, i) for i in range(uniq)]
+    p = bdis.params(**method_params(5))
+    n = args.batch_pairs
+    lefts = [torch.from_numpy(base[i % uniq][0]).to(dev) for i in range(n)]
+    rights = [torch.from_numpy(base[i % uniq][1]).to(dev) for i in range(n)]
+    ctx = bdis.Context(p, 1920, 1080, max_batch=n)
+    outs = [{k: torch.empty((1080, 1920), dtype=torch.float32, device=dev) for k in ("disp", "var", "conf")}
+            for _ in range(n)]
+    log(f"1080p batch of {n}: warmup (includes tuning and graph capture)")
+    for _ in range(2):
+        ctx.compute_batch(lefts, rights, outs=outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        ctx.compute_batch(lefts, rights, outs=outs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.timing(True)
+    for _ in range(max(1, args.batch_steps // 2)):
+        ctx.compute_batch(lefts, rights, outs=outs)
+    torch.cuda.synchronize()
+    tk = ctx.timing_read()
+    ctx.timing(False)
+    ok = [np.isfinite(outs[i]["disp"].cpu().numpy()) & base[i][3] for i in range(min(n, uniq))]
+    epe = float(np.median(np.concatenate(
+        [np.abs(outs[i]["disp"].cpu().numpy()[ok[i]] - base[i][2][ok[i]]) for i in range(len(ok))])))
+    ctx.close()
+    steps_ev = max(1, args.batch_steps // 2)
+    mpx = 1920 * 1080 * n * args.batch_steps / dt / 1e6
+    flops = search_flops(bdis, p, 1920, 1080) * n
+    return dict(metric="disparity Mpixel/s (1080p batch)", value=round(mpx, 2), unit="Mpixel/s",
+                pairs_per_step=n, unique_pairs=uniq, steps=args.batch_steps,
+                ms_per_step=round(dt * 1e3 / args.batch_steps, 3),
+                config=dict(workload="1920x1080 synthetic pairs (planes+bumps 0-192 px, 30% textureless, "
+                                     "dark gain U(0.2,0.5), noise 3), L=6 P=12 S=4 K=16 variance on",
+                            share="64 of the 512-pair stream"),
+                roofline=roofline(flops, steps_ev, tk, "k_search_u8<12>"), kernels=kernel_table(tk),
+                epe_median_px=round(epe, 4))
 
 
 def main():
@@ -62,78 +167,44 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--batch-pairs", type=int, default=64)
+    ap.add_argument("--batch-unique", type=int, default=4)
+    ap.add_argument("--batch-steps", type=int, default=6)
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the hot path has no multi-GPU form here "
-              "(pairs shard across GPUs with no communication; see the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU form "
+              "(pairs would shard across GPUs with no communication).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2205_03133_amd import bdis
-    from paper_2205_03133_amd.synth import make_pair, method_params
 
     bdis.lib()
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    left, right, gt, valid = make_pair(2, 0)
-    h, w = left.shape
-    mp = method_params(2)
-    p = bdis.params(**mp)
-    ctx = bdis.Context(p, w, h)
-    lt = torch.from_numpy(left).to(dev)
-    rt = torch.from_numpy(right).to(dev)
-    out = dict(disp=torch.empty((h, w), dtype=torch.float32, device=dev),
-               var=torch.empty((h, w), dtype=torch.float32, device=dev),
-               conf=torch.empty((h, w), dtype=torch.float32, device=dev))
-    print(f"[bench] 640x480 pair, L={p.levels} P={p.patch} S={p.stride} K={p.iters}, "
-          f"warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        ctx.compute(lt, rt, out=out)
-    torch.cuda.synchronize()
-
-    ctx.timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.compute(lt, rt, out=out)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    tk = ctx.timing_read()
-    ctx.timing(False)
-
-    # accuracy of this run's output vs the synthetic ground truth (context only)
-    d = out["disp"].cpu().numpy()
-    ok = np.isfinite(d) & valid
-    epe = float(np.median(np.abs(d[ok] - gt[ok])))
-
-    ms = dt * 1e3 / args.steps
-    value = w * h * args.steps / dt / 1e6
-    s_ms, s_n = tk["search"]
-    flops = search_flops(bdis, p, w, h)
-    achieved = flops * args.steps / (s_ms * 1e-3) / 1e12
-    roof = dict(bound="alu", achieved=round(achieved, 3), peak=FP32_VECTOR_PEAK_TFLOPS,
-                unit="TFLOP/s", frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5), traffic=None,
-                kernel="k_search_u8<8>", avg_launch_us=round(s_ms * 1e3 / max(s_n, 1), 3),
-                launches=s_n)
-    kernels = {k: dict(total_ms=round(v[0], 4), launches=v[1],
-                       avg_us=round(v[0] * 1e3 / max(v[1], 1), 3)) for k, v in tk.items()}
-    line = dict(metric="disparity Mpixel/s (640x480)", value=round(value, 3), unit="Mpixel/s",
-                n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=round(ms, 4),
-                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="int32+f64+f32",
+    torch.cuda.set_device(0)
+    s = bench_single(bdis, torch, args)
+    w, h, p = s["w"], s["h"], s["p"]
+    value = w * h * args.steps / s["dt"] / 1e6
+    line = dict(metric="disparity Mpixel/s (640x480)", value=round(value, 3), unit="Mpixel/s", n_gpus=1,
+                steps=args.steps, warmup=args.warmup, ms_per_step=round(s["dt"] * 1e3 / args.steps, 4),
+                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="int32+f64",
                 data="synthetic",
                 config=dict(workload="640x480 synthetic stereo pair (planes+bumps 0-64 px, 20% textureless, "
                                      "highlights, gain U(0.8,1.2), noise 2), L=5 P=8 S=3 K=16 variance on",
                             global_batch=1, pairs_per_step=1),
-                roofline=roof, kernels=kernels, epe_median_px=round(epe, 4))
+                roofline=roofline(search_flops(bdis, p, w, h), args.steps, s["tk"], "k_search_u8<8>"),
+                kernels=kernel_table(s["tk"]),
+                ms_per_step_with_kernel_events=round(s["dt_ev"] * 1e3 / args.steps, 4),
+                epe_median_px=round(s["epe"], 4))
+    if not args.no_batch:
+        line["batch_1080p"] = bench_batch(bdis, torch, args)
     if not args.no_cpu_baseline:
         from oracle import ref
-        rp = ref.default_params(**mp)
-        line["cpu_baseline"] = cpu_baseline(left, right, rp)
+        log("cpu baseline (FP64 oracle)")
+        line["cpu_baseline"] = cpu_baseline(s["left"], s["right"], ref.default_params(**s["mp"]))
     line["paper_context"] = "17 Hz (0.064 s) at 640x480 on one i5-9400 core, levels 5..1, P=10, K=12"
-    ctx.close()
     print(json.dumps(line), flush=True)
 
 

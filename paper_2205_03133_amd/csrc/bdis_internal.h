@@ -1,5 +1,12 @@
 // Internal declarations shared by the gfx950 kernels and the C-ABI runtime.
 // Nothing here is part of the public interface (include/bdis.h).
+//
+// Every kernel works on a batch: a launch covers one phase (pyramid level,
+// patch search, patch probability or fusion) of one pyramid level for every
+// pair of the batch that has that level.  Per-pair geometry and pointers live
+// in a device-resident job table (one PairLevel per pair and level); each
+// workgroup finds its pair by a binary search over the table's workgroup
+// offsets, so uneven sizes and pyramid depths share one launch.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -7,12 +14,12 @@
 
 namespace bdis {
 
-constexpr int kThreads = 256;    // threads per workgroup of the patch kernels (4 waves)
 constexpr int kWinRow = 512;     // columns of the right-image row window staged in LDS
 constexpr double kEpsH = 1e-3;   // smallest Hessian that is inverted
 constexpr double kEpsSigma = 1e-6;
 constexpr int kMaxPatch = 16;    // largest patch side
 constexpr int kMaxLevels = 8;
+constexpr int kWin = 5;          // samples of the Bayesian window
 
 // Lanes that cooperate on one patch: one lane per patch row, rounded up to a
 // power of two so that the group is a DPP quad / half-row / row.
@@ -51,71 +58,77 @@ struct PatchArrays {
   D4* dens;       // (u, weight: pi if accepted else -1, sigma_k^2, post)
 };
 
-struct SearchArgs {
-  const uint8_t* L;     // left level image
-  const uint8_t* R;     // right level image
-  int pitch;            // row pitch of both level images (elements)
-  LevelGeom g;
-  int S, K;
-  float valid_ratio;
-  const double* par_ubar;  // parent fused displacement (nullptr at the coarsest level)
-  const double* par_q;     // parent fused confidence
-  int pw, ph;              // parent level size
-  PatchArrays pa;
-  // level reduction for sigma_r: per-workgroup partials, reduced by the last
-  // workgroup to finish (counter returns to 0 afterwards)
-  double* part_sum;
-  int* part_cnt;
-  unsigned* counter;
-  double* scal;           // out: [sigma_r^2, tau]
-  int sigma_r_dynamic;
-  float sigma_r;
-};
-
-struct ProbArgs {
-  PatchArrays pa;
-  int np;                 // patches in the level
-  const double* scal;     // [sigma_r^2, tau]
-  float omega[kMaxLevels];  // level weights; Gamma_n = omega_n / sum_{m=f}^{L-1} omega_m
-  int level, finest, levels;
-  int variance;           // compute sigma_k^2 (finest level)
-  int P;
-  float var_fit_thresh;
-  float var_fail_sigma;   // <= 0 means P
-};
-
-struct DensifyArgs {
-  const D4* dens;
-  LevelGeom g;
-  int P, S;
-  float sigma_s;
-  const double* par_ubar;  // parent maps for holes (nullptr at the coarsest level)
-  const double* par_q;
-  int pw, ph;
-  int finest;              // 1: write the user outputs
-  double* ubar;            // level maps (levels above the finest)
-  double* qmap;
-  float* disparity;       // user outputs (finest level)
-  float* variance;        // nullable
-  float* confidence;      // nullable
-  int variance_on;
-  float prob_thresh;
-};
-
-struct PyrArgs {
+// One pair at one pyramid level: everything a workgroup of any phase needs.
+struct PairLevel {
+  // pyramid phase: level n from level n-1 (unused at n = 0)
   const uint8_t* srcL;
   const uint8_t* srcR;
   int spitch, sw, sh;
-  uint8_t* dstL;
+  // this level's images (level 0: the caller's inputs)
+  const uint8_t* L;
+  const uint8_t* R;
+  int pitch;
+  uint8_t* dstL;   // == L for n >= 1 (written by the pyramid phase)
   uint8_t* dstR;
-  int dw, dh;
+  LevelGeom g;
+  int levels;      // the pair's pyramid depth
+  // parent maps (nullptr at the pair's coarsest level)
+  const double* par_ubar;
+  const double* par_q;
+  int pw, ph;
+  PatchArrays pa;
+  // sigma_r reduction of this pair and level
+  double* part_sum;
+  int* part_cnt;
+  unsigned* counter;
+  double* scal;    // [sigma_r^2, tau]
+  // fusion outputs: level maps above the finest, user outputs at the finest
+  double* ubar;
+  double* qmap;
+  float* disparity;
+  float* variance;
+  float* confidence;
+  // workgroup offsets of this pair in each flattened launch
+  int pyr0, search0, prob0, fuse0;
+  int search_nbx;  // search workgroups per patch row
 };
 
-// Launchers (each returns the hipError_t of its launch).
-hipError_t launch_pyramid_u8(const PyrArgs& a, hipStream_t s);
-hipError_t launch_search_u8(int P, const SearchArgs& a, hipStream_t s);
-hipError_t launch_prob(const ProbArgs& a, hipStream_t s);
-hipError_t launch_densify(const DensifyArgs& a, hipStream_t s);
+// Parameters shared by all pairs of a launch.
+struct LevelParams {
+  int level;        // n
+  int finest;       // f
+  int P, S, K;
+  float valid_ratio;
+  int sigma_r_dynamic;
+  float sigma_r;
+  float omega[kMaxLevels];
+  int variance;
+  float var_fit_thresh;
+  float var_fail_sigma;  // <= 0 means P
+  float sigma_s;
+  float prob_thresh;
+};
+
+// Tile shapes of the flattened launches.
+constexpr int kPyrTx = 64, kPyrTy = 4;      // pyramid: 64 x 4 output pixels per workgroup
+constexpr int kProbThreads = 256;           // probability: patches per workgroup
+constexpr int kFuseTx = 64, kFuseTy = 4;    // fusion: 64 x 4 pixels per workgroup
+
+// Search workgroup sizes the tuner may pick (threads; patches = threads / G).
+constexpr int kSearchThreadOptions[3] = {64, 128, 256};
+
+__host__ __device__ inline int search_patches_per_block(int P, int threads) {
+  return threads / (P <= 8 ? 8 : 16);
+}
+
+// Launchers over a device table of `npairs` entries (each returns the launch status).
+hipError_t launch_pyramid(const PairLevel* tab, int npairs, int nblocks, hipStream_t s);
+hipError_t launch_search(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,
+                         int threads, hipStream_t s);
+hipError_t launch_prob(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,
+                       hipStream_t s);
+hipError_t launch_fuse(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,
+                       hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // device helpers
@@ -125,6 +138,25 @@ hipError_t launch_densify(const DensifyArgs& a, hipStream_t s);
 #else
 #define BDIS_DEV __device__ inline
 #endif
+
+// Index of the table entry whose [first, next first) workgroup range holds
+// workgroup `b` of a launch; Field selects the offset (0 pyramid, 1 search,
+// 2 probability, 3 fusion).  Entries are stored in increasing offset order.
+template <int Field>
+BDIS_DEV int find_pair(const PairLevel* tab, int n, int b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    int off;
+    if constexpr (Field == 0) off = tab[mid].pyr0;
+    else if constexpr (Field == 1) off = tab[mid].search0;
+    else if constexpr (Field == 2) off = tab[mid].prob0;
+    else off = tab[mid].fuse0;
+    if (off <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 // All-reduce (sum) of an int over an aligned group of G lanes (G = 8 or 16)
 // with DPP lane permutations: quad swaps, then half-row and row mirrors.

@@ -1,6 +1,6 @@
 // Patch probability and fusion of the overlapping patches into the level maps.
 //
-// k_prob (one lane per patch): window posterior post = p0 / sum_d p_d with
+// k_prob (one lane per patch; one launch covers a level of every pair): window posterior post = p0 / sum_d p_d with
 //   p_d = exp(-SSD_d / tau), tau = 2 sigma_r^2 s^2 (Eq. 5-6), in the stable
 //   form 1 / sum_d exp(-(SSD_d - SSD_0) / tau); the level's contribution
 //   Gamma_n * post plus the probability propagated from the parent level
@@ -8,7 +8,7 @@
 //   Gauss-Newton fixed point is the least-squares line of ln p on d^2:
 //   sigma_k^2 = tau / (2 kappa), kappa the slope of SSD_d on d^2.
 //
-// k_densify (one lane per level pixel, gather): over the accepted patches
+// k_fuse (one lane per level pixel, gather): over the accepted patches
 //   covering the pixel, in ascending patch index, weights W_k = M(x - o_k) pi_k
 //   with the spatial mixture mask M(a, b) = m(a) m(b),
 //   m(a) = sum_c exp(-(a - c)^2 / (2 sigma_s^2)) (Eq. 9-10, unit mixture
@@ -21,9 +21,10 @@ namespace bdis {
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_prob(ProbArgs a) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.np) return;
+__global__ __launch_bounds__(kProbThreads) void k_prob(const PairLevel* tab, int npairs, LevelParams lp) {
+  const PairLevel& a = tab[find_pair<2>(tab, npairs, (int)blockIdx.x)];
+  const int k = ((int)blockIdx.x - a.prob0) * kProbThreads + (int)threadIdx.x;
+  if (k >= a.g.nx * a.g.ny) return;
   const double u = a.pa.u[k];
   const double nan = __builtin_nan("");
   if (!a.pa.acc[k]) {
@@ -35,12 +36,12 @@ __global__ __launch_bounds__(256) void k_prob(ProbArgs a) {
   const double den = 1.0 + exp(-d.x / tau) + exp(-d.y / tau) + exp(-d.z / tau) + exp(-d.w / tau);
   const double post = 1.0 / den;
   double wsum = 0.0;
-  for (int n = a.finest; n < a.levels; ++n) wsum += (double)a.omega[n];
-  const double gamma = (double)a.omega[a.level] / wsum;
+  for (int n = lp.finest; n < a.levels; ++n) wsum += (double)lp.omega[n];
+  const double gamma = (double)lp.omega[lp.level] / wsum;
   const double pi = gamma * post + a.pa.pipar[k];
   double sig = nan;
-  if (a.variance && a.level == a.finest) {
-    const double sfail = a.var_fail_sigma > 0.0f ? (double)a.var_fail_sigma : (double)a.P;
+  if (lp.variance && lp.level == lp.finest) {
+    const double sfail = lp.var_fail_sigma > 0.0f ? (double)lp.var_fail_sigma : (double)lp.P;
     // OLS of y_d = SSD_d - SSD_0 on x_d = d^2, x = (1, 1/4, 0, 1/4, 1), mean x = 1/2,
     // sum (x - mean x)^2 = 7/8.
     const double y[5] = {d.x, d.y, 0.0, d.z, d.w};
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(256) void k_prob(ProbArgs a) {
         mse += res * res;
       }
       mse /= 5.0;
-      if (mse <= (double)a.var_fit_thresh) {
+      if (mse <= (double)lp.var_fit_thresh) {
         const double s2 = tau / (2.0 * kappa);
         v = s2 < v ? s2 : v;
       }
@@ -66,8 +67,6 @@ __global__ __launch_bounds__(256) void k_prob(ProbArgs a) {
   }
   a.pa.dens[k] = D4{u, pi, sig, post};
 }
-
-constexpr int kDx = 64, kDy = 4;
 
 // Covering patches along one axis: indices lo..hi (origin i*S), plus the last
 // patch (origin n-P) when it covers x but lies past hi.
@@ -78,23 +77,27 @@ BDIS_DEV void cover_range(int x, int n, int P, int S, int cnt, int& lo, int& hi,
   extra = (x >= n - P && cnt - 1 > hi) ? cnt - 1 : -1;
 }
 
-__global__ __launch_bounds__(kDx* kDy) void k_densify(DensifyArgs a) {
+__global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab, int npairs, LevelParams lp) {
   __shared__ double s_m[kMaxPatch];
+  const PairLevel& a = tab[find_pair<3>(tab, npairs, (int)blockIdx.x)];
   const int tid = threadIdx.x;
-  if (tid < a.P) {
-    const double sg = (double)a.sigma_s;
+  if (tid < lp.P) {
+    const double sg = (double)lp.sigma_s;
     double acc = 0.0;
-    for (int c = 0; c < a.P; ++c) {
+    for (int c = 0; c < lp.P; ++c) {
       const double dd = (double)(tid - c);
       acc += exp(-dd * dd / (2.0 * sg * sg));
     }
     s_m[tid] = acc;
   }
   __syncthreads();
-  const int x = blockIdx.x * kDx + tid % kDx;
-  const int y = blockIdx.y * kDy + tid / kDx;
+  const int tiles_x = (a.g.w + kFuseTx - 1) / kFuseTx;
+  const int t = (int)blockIdx.x - a.fuse0;
+  const int x = (t % tiles_x) * kFuseTx + tid % kFuseTx;
+  const int y = (t / tiles_x) * kFuseTy + tid / kFuseTx;
   if (x >= a.g.w || y >= a.g.h) return;
-  const int P = a.P, S = a.S;
+  const int P = lp.P, S = lp.S;
+  const bool finest = lp.level == lp.finest;
   int ilo, ihi, iex, jlo, jhi, jex;
   cover_range(x, a.g.w, P, S, a.g.nx, ilo, ihi, iex);
   cover_range(y, a.g.h, P, S, a.g.ny, jlo, jhi, jex);
@@ -104,7 +107,7 @@ __global__ __launch_bounds__(kDx* kDy) void k_densify(DensifyArgs a) {
   for (int jj = jlo; jj <= jend; ++jj) {
     const int j = jj <= jhi ? jj : jex;
     const double mb = s_m[y - grid_origin(j, a.g.h, P, S)];
-    const D4* row = a.dens + (size_t)j * a.g.nx;
+    const D4* row = a.pa.dens + (size_t)j * a.g.nx;
     for (int ii = ilo; ii <= iend; ++ii) {
       const int i = ii <= ihi ? ii : iex;
       const D4 d = row[i];
@@ -123,7 +126,7 @@ __global__ __launch_bounds__(kDx* kDy) void k_densify(DensifyArgs a) {
   if (valid) {
     ub = zu / z;
     qv = z / zm;
-  } else if (a.finest) {
+  } else if (finest) {
     ub = __builtin_nan("");
     qv = 0.0;
   } else if (a.par_ubar) {
@@ -134,29 +137,29 @@ __global__ __launch_bounds__(kDx* kDy) void k_densify(DensifyArgs a) {
     ub = 0.0;
     qv = 0.0;
   }
-  if (!a.finest) {
+  if (!finest) {
     a.ubar[idx] = ub;
     a.qmap[idx] = qv;
     return;
   }
-  if (a.prob_thresh > 0.0f && qv < (double)a.prob_thresh) valid = false;
+  if (lp.prob_thresh > 0.0f && qv < (double)lp.prob_thresh) valid = false;
   const float nan = __builtin_nanf("");
   a.disparity[idx] = valid ? (float)(-ub) : nan;
   if (a.confidence) a.confidence[idx] = valid ? (float)qv : 0.0f;
-  if (a.variance) a.variance[idx] = (valid && a.variance_on) ? (float)(zv / (z * z)) : nan;
+  if (a.variance) a.variance[idx] = (valid && lp.variance) ? (float)(zv / (z * z)) : nan;
 }
 
 }  // namespace
 
-hipError_t launch_prob(const ProbArgs& a, hipStream_t s) {
-  if (a.np <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prob, dim3((a.np + 255) / 256), dim3(256), 0, s, a);
+hipError_t launch_prob(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prob, dim3(nblocks), dim3(kProbThreads), 0, s, tab, npairs, lp);
   return hipGetLastError();
 }
 
-hipError_t launch_densify(const DensifyArgs& a, hipStream_t s) {
-  dim3 grid((a.g.w + kDx - 1) / kDx, (a.g.h + kDy - 1) / kDy);
-  hipLaunchKernelGGL(k_densify, grid, dim3(kDx * kDy), 0, s, a);
+hipError_t launch_fuse(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fuse, dim3(nblocks), dim3(kFuseTx * kFuseTy), 0, s, tab, npairs, lp);
   return hipGetLastError();
 }
 

@@ -6,7 +6,8 @@
 //
 // Mapping: one lane per patch row, an aligned group of G = 8 or 16 lanes per
 // patch (a DPP quad/half-row/row, so group reductions are 3-4 DPP adds),
-// 256/G patches of one patch row per workgroup.  The left rows around those
+// THREADS/G patches of one patch row of one pair per workgroup (THREADS is
+// picked per level by the tuner).  The left rows around those
 // patches (for the template and its Sobel gradient) and a window of the right
 // rows around the patches' starting displacements are staged in LDS once;
 // right-image samples outside the window fall back to (clamped) global loads.
@@ -46,10 +47,10 @@ BDIS_DEV void fetch_row(int (&v)[N], const uint8_t* win, int xs, int rw, const u
   }
 }
 
-template <int P>
-__global__ __launch_bounds__(kThreads) void k_search_u8(SearchArgs a) {
+template <int P, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int npairs, LevelParams lp) {
   constexpr int G = group_lanes(P);
-  constexpr int NPB = kThreads / G;              // patches per workgroup
+  constexpr int NPB = THREADS / G;               // patches per workgroup
   constexpr int LTW = (NPB - 1) * P + P + 2;     // left tile width bound (S <= P)
   constexpr int MARG = P + 4;                    // window margin around the start range
   constexpr int N = P * P;
@@ -61,12 +62,14 @@ __global__ __launch_bounds__(kThreads) void k_search_u8(SearchArgs a) {
   __shared__ int s_pcnt[NPB];
   __shared__ int s_last;
 
+  const PairLevel& a = tab[find_pair<1>(tab, npairs, (int)blockIdx.x)];
+  const int blk = (int)blockIdx.x - a.search0;   // workgroup within the pair
   const int tid = threadIdx.x;
   const int q = tid / G;  // patch slot in the workgroup
   const int r = tid % G;  // patch row of this lane
-  const int W = a.g.w, Hh = a.g.h, S = a.S;
-  const int j = blockIdx.y;
-  const int i0 = blockIdx.x * NPB;
+  const int W = a.g.w, Hh = a.g.h, S = lp.S;
+  const int j = blk / a.search_nbx;
+  const int i0 = (blk % a.search_nbx) * NPB;
   const bool live = (i0 + q) < a.g.nx;
   const int i = live ? i0 + q : a.g.nx - 1;
   const int ilast = min(i0 + NPB - 1, a.g.nx - 1);
@@ -92,7 +95,7 @@ __global__ __launch_bounds__(kThreads) void k_search_u8(SearchArgs a) {
   const int ltw = oxl - ox0 + P + 2;
   for (int ty = 0; ty < P + 2; ++ty) {
     const uint8_t* src = a.L + (size_t)reflect101(oy - 1 + ty, Hh) * a.pitch;
-    for (int tx = tid; tx < ltw; tx += kThreads) s_left[ty * LTW + tx] = src[reflect101(ox0 - 1 + tx, W)];
+    for (int tx = tid; tx < ltw; tx += THREADS) s_left[ty * LTW + tx] = src[reflect101(ox0 - 1 + tx, W)];
   }
   __syncthreads();
   if (r == 0 && live) {
@@ -106,7 +109,7 @@ __global__ __launch_bounds__(kThreads) void k_search_u8(SearchArgs a) {
   const int rw = min(oxl + P + s_umax + MARG + 2 - xs, kWinRow);
   for (int ty = 0; ty < P; ++ty) {
     const uint8_t* src = a.R + (size_t)(oy + ty) * a.pitch;
-    for (int tx = tid; tx < rw; tx += kThreads) s_right[ty * kWinRow + tx] = src[clampi(xs + tx, 0, W - 1)];
+    for (int tx = tid; tx < rw; tx += THREADS) s_right[ty * kWinRow + tx] = src[clampi(xs + tx, 0, W - 1)];
   }
   __syncthreads();
 
@@ -150,7 +153,7 @@ __global__ __launch_bounds__(kThreads) void k_search_u8(SearchArgs a) {
   if (invert) {
     int mc = INT_MIN;
     double E0 = 0.0, E1 = 0.0;
-    for (int t = 0; t < a.K; ++t) {
+    for (int t = 0; t < lp.K; ++t) {
       const double fm = floor(u);
       const int m = (int)fm;
       const double f = u - fm;
@@ -234,7 +237,7 @@ __global__ __launch_bounds__(kThreads) void k_search_u8(SearchArgs a) {
     inb += (xr >= 0.0 && xr <= (double)(W - 1)) ? 1 : 0;
   }
   const double rho = (double)(inb * P) / (double)N;
-  const bool acc = s0 <= sm1 && s0 <= smh && s0 <= sph && s0 <= sp1 && rho >= (double)a.valid_ratio;
+  const bool acc = s0 <= sm1 && s0 <= smh && s0 <= sph && s0 <= sp1 && rho >= (double)lp.valid_ratio;
 
   const int k = j * a.g.nx + i;
   if (r == 0 && live) {
@@ -254,8 +257,7 @@ __global__ __launch_bounds__(kThreads) void k_search_u8(SearchArgs a) {
     s_pcnt[q] = (live && acc) ? 1 : 0;
   }
   __syncthreads();
-  const int nblocks = gridDim.x * gridDim.y;
-  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  const int nblocks = a.search_nbx * a.g.ny;  // workgroups of this pair
   if (tid == 0) {
     double ps = 0.0;
     int pc = 0;
@@ -263,8 +265,8 @@ __global__ __launch_bounds__(kThreads) void k_search_u8(SearchArgs a) {
       ps += s_psum[t];
       pc += s_pcnt[t];
     }
-    a.part_sum[bid] = ps;
-    a.part_cnt[bid] = pc;
+    a.part_sum[blk] = ps;
+    a.part_cnt[blk] = pc;
     __threadfence();
     const unsigned prev = atomicAdd(a.counter, 1u);
     s_last = (prev == (unsigned)(nblocks - 1)) ? 1 : 0;
@@ -273,18 +275,18 @@ __global__ __launch_bounds__(kThreads) void k_search_u8(SearchArgs a) {
   if (!s_last) return;
   // last workgroup: fixed-order reduction of all partials (deterministic)
   __threadfence();
-  __shared__ double s_red[kThreads];
-  __shared__ long long s_redc[kThreads];
+  __shared__ double s_red[THREADS];
+  __shared__ long long s_redc[THREADS];
   double ps = 0.0;
   long long pc = 0;
-  for (int b = tid; b < nblocks; b += kThreads) {
+  for (int b = tid; b < nblocks; b += THREADS) {
     ps += __hip_atomic_load(&a.part_sum[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     pc += __hip_atomic_load(&a.part_cnt[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   s_red[tid] = ps;
   s_redc[tid] = pc;
   __syncthreads();
-  for (int off = kThreads / 2; off > 0; off >>= 1) {
+  for (int off = THREADS / 2; off > 0; off >>= 1) {
     if (tid < off) {
       s_red[tid] += s_red[tid + off];
       s_redc[tid] += s_redc[tid + off];
@@ -293,8 +295,8 @@ __global__ __launch_bounds__(kThreads) void k_search_u8(SearchArgs a) {
   }
   if (tid == 0) {
     double sr2;
-    const double alpha2 = (double)a.sigma_r * (double)a.sigma_r;
-    if (a.sigma_r_dynamic) {
+    const double alpha2 = (double)lp.sigma_r * (double)lp.sigma_r;
+    if (lp.sigma_r_dynamic) {
       const double pooled = s_redc[0] > 0 ? s_red[0] / ((double)s_redc[0] * (double)N) : 0.0;
       sr2 = alpha2 * (pooled > kEpsSigma ? pooled : kEpsSigma);
     } else {
@@ -307,31 +309,37 @@ __global__ __launch_bounds__(kThreads) void k_search_u8(SearchArgs a) {
 }
 
 template <int P>
-hipError_t launch_p(const SearchArgs& a, hipStream_t s) {
-  constexpr int NPB = kThreads / group_lanes(P);
-  dim3 grid((a.g.nx + NPB - 1) / NPB, a.g.ny);
-  hipLaunchKernelGGL(k_search_u8<P>, grid, dim3(kThreads), 0, s, a);
+hipError_t launch_p(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, int threads,
+                    hipStream_t s) {
+  switch (threads) {
+    case 64: hipLaunchKernelGGL((k_search_u8<P, 64>), dim3(nblocks), dim3(64), 0, s, tab, npairs, lp); break;
+    case 128: hipLaunchKernelGGL((k_search_u8<P, 128>), dim3(nblocks), dim3(128), 0, s, tab, npairs, lp); break;
+    case 256: hipLaunchKernelGGL((k_search_u8<P, 256>), dim3(nblocks), dim3(256), 0, s, tab, npairs, lp); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_search_u8(int P, const SearchArgs& a, hipStream_t s) {
-  switch (P) {
-    case 3: return launch_p<3>(a, s);
-    case 4: return launch_p<4>(a, s);
-    case 5: return launch_p<5>(a, s);
-    case 6: return launch_p<6>(a, s);
-    case 7: return launch_p<7>(a, s);
-    case 8: return launch_p<8>(a, s);
-    case 9: return launch_p<9>(a, s);
-    case 10: return launch_p<10>(a, s);
-    case 11: return launch_p<11>(a, s);
-    case 12: return launch_p<12>(a, s);
-    case 13: return launch_p<13>(a, s);
-    case 14: return launch_p<14>(a, s);
-    case 15: return launch_p<15>(a, s);
-    case 16: return launch_p<16>(a, s);
+hipError_t launch_search(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, int threads,
+                         hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  switch (lp.P) {
+    case 3: return launch_p<3>(tab, npairs, nblocks, lp, threads, s);
+    case 4: return launch_p<4>(tab, npairs, nblocks, lp, threads, s);
+    case 5: return launch_p<5>(tab, npairs, nblocks, lp, threads, s);
+    case 6: return launch_p<6>(tab, npairs, nblocks, lp, threads, s);
+    case 7: return launch_p<7>(tab, npairs, nblocks, lp, threads, s);
+    case 8: return launch_p<8>(tab, npairs, nblocks, lp, threads, s);
+    case 9: return launch_p<9>(tab, npairs, nblocks, lp, threads, s);
+    case 10: return launch_p<10>(tab, npairs, nblocks, lp, threads, s);
+    case 11: return launch_p<11>(tab, npairs, nblocks, lp, threads, s);
+    case 12: return launch_p<12>(tab, npairs, nblocks, lp, threads, s);
+    case 13: return launch_p<13>(tab, npairs, nblocks, lp, threads, s);
+    case 14: return launch_p<14>(tab, npairs, nblocks, lp, threads, s);
+    case 15: return launch_p<15>(tab, npairs, nblocks, lp, threads, s);
+    case 16: return launch_p<16>(tab, npairs, nblocks, lp, threads, s);
     default: return hipErrorInvalidValue;
   }
 }

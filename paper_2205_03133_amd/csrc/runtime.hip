@@ -1,16 +1,24 @@
 // C-ABI runtime of the BDIS library: parameter validation, the device
-// workspace, and the launch sequence of one coarse-to-fine pass (Fig. 1):
-//   pyramid of both views, then for n = L-1 .. f:
-//     patch search (+ sigma_r reduction), patch probability, fusion.
-// Every launch goes to the caller's stream; nothing here synchronises the host
-// except bdis_create, bdis_destroy and bdis_debug_dump.
+// workspace, the per-level job tables and the launch sequence of one
+// coarse-to-fine pass (Fig. 1) over a batch of pairs:
+//   pyramid levels 1 .. L-1 of both views, then for n = L-1 .. f:
+//     patch search (+ per-pair sigma_r reduction), patch probability, fusion,
+// each phase one launch covering every pair that has level n.  The sequence
+// is captured once per batch shape into a hipGraph and replayed; the job
+// table (pointers) lives in device memory and is re-uploaded only when it
+// changes.  Nothing here synchronises the host except bdis_create,
+// bdis_destroy, bdis_debug_dump, the first call of a new batch shape (tuning)
+// and bdis_timing_read.
 #include <bdis.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -27,7 +35,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   int levels = 0;
   LevelGeom g[kMaxLevels]{};
-  int nblocks[kMaxLevels]{};
+  int max_search_blocks[kMaxLevels]{};
   size_t lvl_l[kMaxLevels]{}, lvl_r[kMaxLevels]{};
   size_t uinit[kMaxLevels]{}, pipar[kMaxLevels]{}, u[kMaxLevels]{}, ssd0[kMaxLevels]{},
       dssd[kMaxLevels]{}, rho[kMaxLevels]{}, acc[kMaxLevels]{}, hess[kMaxLevels]{},
@@ -37,9 +45,9 @@ struct Layout {
   size_t total = 0;
 };
 
-int search_blocks(const LevelGeom& g, int P) {
-  const int npb = kThreads / group_lanes(P);
-  return (g.nx + npb - 1) / npb * g.ny;
+int search_nbx(const LevelGeom& g, int P, int threads) {
+  const int npb = search_patches_per_block(P, threads);
+  return (g.nx + npb - 1) / npb;
 }
 
 // Level sizes W_n = ceil(W_{n-1} / 2); the patch grid exists on processed levels.
@@ -92,9 +100,10 @@ bool make_layout(const bdis_params& p, int w, int h, int levels, Layout* lay) {
       L.ubar[n] = take(npx * 8);
       L.qmap[n] = take(npx * 8);
     }
-    L.nblocks[n] = search_blocks(L.g[n], p.patch);
-    L.part_sum[n] = take((size_t)L.nblocks[n] * 8);
-    L.part_cnt[n] = take((size_t)L.nblocks[n] * 4);
+    // partials sized for the smallest workgroup the tuner may choose
+    L.max_search_blocks[n] = search_nbx(L.g[n], p.patch, kSearchThreadOptions[0]) * L.g[n].ny;
+    L.part_sum[n] = take((size_t)L.max_search_blocks[n] * 8);
+    L.part_cnt[n] = take((size_t)L.max_search_blocks[n] * 4);
     L.counter[n] = take(64);
     L.scal[n] = take(64);
   }
@@ -105,15 +114,43 @@ bool make_layout(const bdis_params& p, int w, int h, int levels, Layout* lay) {
 
 bool finite_f(float v) { return std::isfinite(v); }
 
-}  // namespace
+// One pair of a call, as validated.
+struct PairSpec {
+  const uint8_t* left;
+  const uint8_t* right;
+  int w, h, pitch, levels;
+  float* disp;
+  float* var;
+  float* conf;
+};
+
+// Launch plan of one call: level-major job table and workgroup counts.
+struct Plan {
+  int max_levels = 0;
+  int finest = 0;
+  int tab_first[kMaxLevels]{};   // first table entry of level n
+  int tab_count[kMaxLevels]{};   // entries (pairs having level n)
+  int pyr_blocks[kMaxLevels]{}, search_blocks[kMaxLevels]{}, prob_blocks[kMaxLevels]{},
+      fuse_blocks[kMaxLevels]{};
+  int threads[kMaxLevels]{};     // search workgroup size per level
+  std::vector<PairLevel> tab;
+};
 
 // HIP events recorded around each launch while timing is enabled.
 struct Timing {
   bool on = false;
-  std::vector<hipEvent_t> pool;                 // reused events
-  size_t used = 0;                              // events handed out since enable
-  std::vector<std::pair<int, size_t>> marks;    // (kernel, index of start event)
+  std::vector<hipEvent_t> pool;               // reused events
+  size_t used = 0;                            // events handed out since enable
+  std::vector<std::pair<int, size_t>> marks;  // (kernel, index of start event)
 };
+
+// A captured launch sequence for one batch shape.
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
 
 struct bdis_ctx {
   bdis_params p{};
@@ -122,6 +159,17 @@ struct bdis_ctx {
   size_t slot_bytes = 0;
   char* ws = nullptr;
   int device = 0;
+  // device job table + pinned staging, uploaded only when its contents change
+  PairLevel* tab_dev = nullptr;
+  PairLevel* tab_host = nullptr;
+  size_t tab_cap = 0;             // entries
+  std::vector<PairLevel> tab_last;
+  hipEvent_t tab_evt = nullptr;   // completion of the last upload
+  bool tab_evt_live = false;
+  hipStream_t capture_stream = nullptr;
+  std::map<std::string, GraphEntry> graphs;
+  std::map<std::string, int> tuned;  // level shape key -> search workgroup threads
+  int use_graph = 1;
   // geometry of the last single-pair compute (slot 0), for debug dumps
   int last_w = 0, last_h = 0;
   bool have_last = false;
@@ -172,6 +220,8 @@ bdis_status hip_fail(bdis_ctx* c, hipError_t e, const char* what) {
   return fail(c, BDIS_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// ---- timing ---------------------------------------------------------------
+
 hipEvent_t next_event(bdis_ctx* c) {
   if (c->tm.used == c->tm.pool.size()) {
     hipEvent_t e;
@@ -181,7 +231,6 @@ hipEvent_t next_event(bdis_ctx* c) {
   return c->tm.pool[c->tm.used++];
 }
 
-// Records a start event for `kernel` (no-op unless timing is on); returns the mark index.
 long timing_start(bdis_ctx* c, int kernel, hipStream_t st) {
   if (!c->tm.on) return -1;
   const size_t idx = c->tm.used;
@@ -198,120 +247,352 @@ void timing_stop(bdis_ctx* c, long mark, hipStream_t st) {
   (void)hipEventRecord(c->tm.pool[(size_t)mark + 1], st);
 }
 
-// Launch sequence of one pair in slot `slot`.  Inputs were validated.
-bdis_status run_pair(bdis_ctx* c, int slot, const uint8_t* left, const uint8_t* right, int w, int h,
-                     int pitch, int levels, float* disp, float* var, float* conf, hipStream_t st) {
-  const bdis_params& p = c->p;
-  Layout lay;
-  if (!make_layout(p, w, h, levels, &lay))
-    return fail(c, BDIS_E_SIZE, "a level of %dx%d with %d levels is smaller than patch %d", w, h, levels, p.patch);
-  if (lay.total > c->slot_bytes)
-    return fail(c, BDIS_E_CAPACITY, "pair %dx%d (%d levels) needs %zu workspace bytes > %zu", w, h, levels,
-                lay.total, c->slot_bytes);
-  char* base = c->ws + (size_t)slot * c->slot_bytes;
-  auto P8 = [&](size_t o) { return reinterpret_cast<uint8_t*>(base + o); };
-  auto PF = [&](size_t o) { return reinterpret_cast<float*>(base + o); };
-  auto PD = [&](size_t o) { return reinterpret_cast<double*>(base + o); };
-  hipError_t e;
+// ---- planning ---------------------------------------------------------------
 
-  // pyramid of both views (levels 1 .. L-1)
-  for (int n = 1; n < levels; ++n) {
-    PyrArgs a;
-    a.srcL = n == 1 ? left : P8(lay.lvl_l[n - 1]);
-    a.srcR = n == 1 ? right : P8(lay.lvl_r[n - 1]);
-    a.spitch = n == 1 ? pitch : lay.g[n - 1].w;
-    a.sw = lay.g[n - 1].w;
-    a.sh = lay.g[n - 1].h;
-    a.dstL = P8(lay.lvl_l[n]);
-    a.dstR = P8(lay.lvl_r[n]);
-    a.dw = lay.g[n].w;
-    a.dh = lay.g[n].h;
+LevelParams level_params(const bdis_params& p, int n) {
+  LevelParams lp;
+  lp.level = n;
+  lp.finest = p.finest_level;
+  lp.P = p.patch;
+  lp.S = p.stride;
+  lp.K = p.iters;
+  lp.valid_ratio = p.valid_ratio;
+  lp.sigma_r_dynamic = p.sigma_r_dynamic;
+  lp.sigma_r = p.sigma_r;
+  for (int k = 0; k < kMaxLevels; ++k) lp.omega[k] = p.level_weight[k];
+  lp.variance = p.variance;
+  lp.var_fit_thresh = p.var_fit_thresh;
+  lp.var_fail_sigma = p.var_fail_sigma;
+  lp.sigma_s = p.sigma_s;
+  lp.prob_thresh = p.prob_thresh;
+  return lp;
+}
+
+// Tuning key of a level: the search workload shape across the batch.
+std::string level_key(const bdis_params& p, const Plan& pl, int n) {
+  long np = 0;
+  int maxw = 0;
+  for (int e = 0; e < pl.tab_count[n]; ++e) {
+    const PairLevel& q = pl.tab[pl.tab_first[n] + e];
+    np += (long)q.g.nx * q.g.ny;
+    maxw = std::max(maxw, q.g.w);
+  }
+  char buf[160];
+  snprintf(buf, sizeof buf, "P%d S%d K%d n%d pairs%d patches%ld w%d", p.patch, p.stride, p.iters, n,
+           pl.tab_count[n], np, maxw);
+  return buf;
+}
+
+// Default search workgroup size: the largest option that still gives every
+// compute unit (256 on MI355X) two workgroups; else the smallest option.
+int default_threads(const Plan& pl, int n, int P) {
+  for (int o = 2; o >= 0; --o) {
+    const int t = kSearchThreadOptions[o];
+    long blocks = 0;
+    for (int e = 0; e < pl.tab_count[n]; ++e) {
+      const PairLevel& q = pl.tab[pl.tab_first[n] + e];
+      blocks += (long)search_nbx(q.g, P, t) * q.g.ny;
+    }
+    if (blocks >= 512) return t;
+  }
+  return kSearchThreadOptions[0];
+}
+
+// Assigns workgroup offsets for the given per-level search workgroup sizes.
+void assign_offsets(const bdis_params& p, Plan& pl) {
+  for (int n = 0; n < pl.max_levels; ++n) {
+    int pyr = 0, se = 0, pr = 0, fu = 0;
+    const bool patches = n >= p.finest_level;
+    for (int e = 0; e < pl.tab_count[n]; ++e) {
+      PairLevel& q = pl.tab[pl.tab_first[n] + e];
+      q.pyr0 = pyr;
+      pyr += n >= 1 ? ((q.g.w + kPyrTx - 1) / kPyrTx) * ((q.g.h + kPyrTy - 1) / kPyrTy) : 0;
+      q.search_nbx = patches ? search_nbx(q.g, p.patch, pl.threads[n]) : 0;
+      q.search0 = se;
+      se += patches ? q.search_nbx * q.g.ny : 0;
+      q.prob0 = pr;
+      pr += patches ? (q.g.nx * q.g.ny + kProbThreads - 1) / kProbThreads : 0;
+      q.fuse0 = fu;
+      fu += patches ? ((q.g.w + kFuseTx - 1) / kFuseTx) * ((q.g.h + kFuseTy - 1) / kFuseTy) : 0;
+    }
+    pl.pyr_blocks[n] = pyr;
+    pl.search_blocks[n] = se;
+    pl.prob_blocks[n] = pr;
+    pl.fuse_blocks[n] = fu;
+  }
+}
+
+bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* out) {
+  const bdis_params& p = c->p;
+  Plan pl;
+  pl.finest = p.finest_level;
+  std::vector<Layout> lays(pairs.size());
+  for (size_t i = 0; i < pairs.size(); ++i) {
+    const PairSpec& q = pairs[i];
+    if (!make_layout(p, q.w, q.h, q.levels, &lays[i]))
+      return fail(c, BDIS_E_SIZE, "pair %zu: a level of %dx%d with %d levels is smaller than patch %d", i, q.w,
+                  q.h, q.levels, p.patch);
+    if (lays[i].total > c->slot_bytes)
+      return fail(c, BDIS_E_CAPACITY, "pair %zu (%dx%d, %d levels) needs %zu workspace bytes > %zu", i, q.w, q.h,
+                  q.levels, lays[i].total, c->slot_bytes);
+    pl.max_levels = std::max(pl.max_levels, q.levels);
+  }
+  for (int n = 0; n < pl.max_levels; ++n) {
+    pl.tab_first[n] = (int)pl.tab.size();
+    for (size_t i = 0; i < pairs.size(); ++i) {
+      const PairSpec& q = pairs[i];
+      if (q.levels <= n) continue;
+      const Layout& lay = lays[i];
+      char* base = c->ws + i * c->slot_bytes;
+      auto B8 = [&](size_t o) { return reinterpret_cast<uint8_t*>(base + o); };
+      auto BD = [&](size_t o) { return reinterpret_cast<double*>(base + o); };
+      PairLevel e;
+      std::memset(&e, 0, sizeof e);
+      e.g = lay.g[n];
+      e.levels = q.levels;
+      if (n >= 1) {
+        e.srcL = n == 1 ? q.left : B8(lay.lvl_l[n - 1]);
+        e.srcR = n == 1 ? q.right : B8(lay.lvl_r[n - 1]);
+        e.spitch = n == 1 ? q.pitch : lay.g[n - 1].w;
+        e.sw = lay.g[n - 1].w;
+        e.sh = lay.g[n - 1].h;
+        e.dstL = B8(lay.lvl_l[n]);
+        e.dstR = B8(lay.lvl_r[n]);
+      }
+      e.L = n == 0 ? q.left : B8(lay.lvl_l[n]);
+      e.R = n == 0 ? q.right : B8(lay.lvl_r[n]);
+      e.pitch = n == 0 ? q.pitch : lay.g[n].w;
+      if (n >= p.finest_level) {
+        const bool has_par = n + 1 < q.levels;
+        e.par_ubar = has_par ? BD(lay.ubar[n + 1]) : nullptr;
+        e.par_q = has_par ? BD(lay.qmap[n + 1]) : nullptr;
+        e.pw = has_par ? lay.g[n + 1].w : 0;
+        e.ph = has_par ? lay.g[n + 1].h : 0;
+        e.pa.uinit = BD(lay.uinit[n]);
+        e.pa.pipar = BD(lay.pipar[n]);
+        e.pa.u = BD(lay.u[n]);
+        e.pa.ssd0 = BD(lay.ssd0[n]);
+        e.pa.dssd = reinterpret_cast<D4*>(base + lay.dssd[n]);
+        e.pa.rho = reinterpret_cast<float*>(base + lay.rho[n]);
+        e.pa.acc = reinterpret_cast<int*>(base + lay.acc[n]);
+        e.pa.hess = reinterpret_cast<float*>(base + lay.hess[n]);
+        e.pa.dens = reinterpret_cast<D4*>(base + lay.dens[n]);
+        e.part_sum = BD(lay.part_sum[n]);
+        e.part_cnt = reinterpret_cast<int*>(base + lay.part_cnt[n]);
+        e.counter = reinterpret_cast<unsigned*>(base + lay.counter[n]);
+        e.scal = BD(lay.scal[n]);
+        if (n > p.finest_level) {
+          e.ubar = BD(lay.ubar[n]);
+          e.qmap = BD(lay.qmap[n]);
+        } else {
+          e.disparity = q.disp;
+          e.variance = q.var;
+          e.confidence = q.conf;
+        }
+      }
+      pl.tab.push_back(e);
+    }
+    pl.tab_count[n] = (int)pl.tab.size() - pl.tab_first[n];
+  }
+  for (int n = 0; n < pl.max_levels; ++n) {
+    if (n < p.finest_level || pl.tab_count[n] == 0) {
+      pl.threads[n] = kSearchThreadOptions[2];
+      continue;
+    }
+    auto it = c->tuned.find(level_key(p, pl, n));
+    pl.threads[n] = it != c->tuned.end() ? it->second : default_threads(pl, n, p.patch);
+  }
+  assign_offsets(p, pl);
+  *out = std::move(pl);
+  return BDIS_OK;
+}
+
+// Uploads the job table when it differs from the one on the device.
+bdis_status upload_table(bdis_ctx* c, const Plan& pl, hipStream_t st) {
+  const size_t n = pl.tab.size();
+  if (n == c->tab_last.size() && std::memcmp(pl.tab.data(), c->tab_last.data(), n * sizeof(PairLevel)) == 0)
+    return BDIS_OK;
+  hipError_t e;
+  if (n > c->tab_cap) {
+    // the old table may still be read by queued work: drain before freeing it
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(c, e, "table resize");
+    if (c->tab_dev) (void)hipFree(c->tab_dev);
+    if (c->tab_host) (void)hipHostFree(c->tab_host);
+    c->tab_dev = nullptr;
+    c->tab_host = nullptr;
+    c->tab_cap = 0;
+    c->tab_last.clear();
+    c->tab_evt_live = false;
+    for (auto& kv : c->graphs) {  // graphs hold the old table address
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+      if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    c->graphs.clear();
+    if ((e = hipMalloc(reinterpret_cast<void**>(&c->tab_dev), n * sizeof(PairLevel))) != hipSuccess)
+      return fail(c, BDIS_E_NOMEM, "job table: %s", hipGetErrorString(e));
+    if ((e = hipHostMalloc(reinterpret_cast<void**>(&c->tab_host), n * sizeof(PairLevel))) != hipSuccess)
+      return fail(c, BDIS_E_NOMEM, "job table staging: %s", hipGetErrorString(e));
+    c->tab_cap = n;
+  }
+  // the staging buffer may still feed the previous (async) upload
+  if (c->tab_evt_live && (e = hipEventSynchronize(c->tab_evt)) != hipSuccess) return hip_fail(c, e, "table event");
+  std::memcpy(c->tab_host, pl.tab.data(), n * sizeof(PairLevel));
+  if ((e = hipMemcpyAsync(c->tab_dev, c->tab_host, n * sizeof(PairLevel), hipMemcpyHostToDevice, st)) != hipSuccess)
+    return hip_fail(c, e, "job table upload");
+  if ((e = hipEventRecord(c->tab_evt, st)) != hipSuccess) return hip_fail(c, e, "table event");
+  c->tab_evt_live = true;
+  c->tab_last = pl.tab;
+  return BDIS_OK;
+}
+
+// The launch sequence of a plan (eager; optionally timed per kernel).
+bdis_status launch_all(bdis_ctx* c, const Plan& pl, hipStream_t st) {
+  const bdis_params& p = c->p;
+  hipError_t e;
+  for (int n = 1; n < pl.max_levels; ++n) {
     const long tmk = timing_start(c, BDIS_K_PYRAMID, st);
-    e = launch_pyramid_u8(a, st);
+    e = launch_pyramid(c->tab_dev + pl.tab_first[n], pl.tab_count[n], pl.pyr_blocks[n], st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "pyramid launch");
   }
-
-  for (int n = levels - 1; n >= p.finest_level; --n) {
-    const LevelGeom& g = lay.g[n];
-    PatchArrays pa;
-    pa.uinit = PD(lay.uinit[n]);
-    pa.pipar = PD(lay.pipar[n]);
-    pa.u = PD(lay.u[n]);
-    pa.ssd0 = PD(lay.ssd0[n]);
-    pa.dssd = reinterpret_cast<D4*>(base + lay.dssd[n]);
-    pa.rho = PF(lay.rho[n]);
-    pa.acc = reinterpret_cast<int*>(base + lay.acc[n]);
-    pa.hess = PF(lay.hess[n]);
-    pa.dens = reinterpret_cast<D4*>(base + lay.dens[n]);
-    const bool has_par = n + 1 < levels;
-    double* scal = reinterpret_cast<double*>(base + lay.scal[n]);
-
-    SearchArgs sa;
-    sa.L = n == 0 ? left : P8(lay.lvl_l[n]);
-    sa.R = n == 0 ? right : P8(lay.lvl_r[n]);
-    sa.pitch = n == 0 ? pitch : g.w;
-    sa.g = g;
-    sa.S = p.stride;
-    sa.K = p.iters;
-    sa.valid_ratio = p.valid_ratio;
-    sa.par_ubar = has_par ? PD(lay.ubar[n + 1]) : nullptr;
-    sa.par_q = has_par ? PD(lay.qmap[n + 1]) : nullptr;
-    sa.pw = has_par ? lay.g[n + 1].w : 0;
-    sa.ph = has_par ? lay.g[n + 1].h : 0;
-    sa.pa = pa;
-    sa.part_sum = reinterpret_cast<double*>(base + lay.part_sum[n]);
-    sa.part_cnt = reinterpret_cast<int*>(base + lay.part_cnt[n]);
-    sa.counter = reinterpret_cast<unsigned*>(base + lay.counter[n]);
-    sa.scal = scal;
-    sa.sigma_r_dynamic = p.sigma_r_dynamic;
-    sa.sigma_r = p.sigma_r;
+  for (int n = pl.max_levels - 1; n >= p.finest_level; --n) {
+    const PairLevel* tab = c->tab_dev + pl.tab_first[n];
+    const int cnt = pl.tab_count[n];
+    const LevelParams lp = level_params(p, n);
     long tmk = timing_start(c, BDIS_K_SEARCH, st);
-    e = launch_search_u8(p.patch, sa, st);
+    e = launch_search(tab, cnt, pl.search_blocks[n], lp, pl.threads[n], st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "search launch");
-
-    ProbArgs pr;
-    pr.pa = pa;
-    pr.np = g.nx * g.ny;
-    pr.scal = scal;
-    for (int k = 0; k < kMaxLevels; ++k) pr.omega[k] = p.level_weight[k];
-    pr.level = n;
-    pr.finest = p.finest_level;
-    pr.levels = levels;
-    pr.variance = p.variance;
-    pr.P = p.patch;
-    pr.var_fit_thresh = p.var_fit_thresh;
-    pr.var_fail_sigma = p.var_fail_sigma;
     tmk = timing_start(c, BDIS_K_PROB, st);
-    e = launch_prob(pr, st);
+    e = launch_prob(tab, cnt, pl.prob_blocks[n], lp, st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "probability launch");
-
-    DensifyArgs da;
-    da.dens = pa.dens;
-    da.g = g;
-    da.P = p.patch;
-    da.S = p.stride;
-    da.sigma_s = p.sigma_s;
-    da.par_ubar = sa.par_ubar;
-    da.par_q = sa.par_q;
-    da.pw = sa.pw;
-    da.ph = sa.ph;
-    da.finest = n == p.finest_level;
-    da.ubar = da.finest ? nullptr : PD(lay.ubar[n]);
-    da.qmap = da.finest ? nullptr : PD(lay.qmap[n]);
-    da.disparity = disp;
-    da.variance = var;
-    da.confidence = conf;
-    da.variance_on = p.variance;
-    da.prob_thresh = p.prob_thresh;
     tmk = timing_start(c, BDIS_K_FUSE, st);
-    e = launch_densify(da, st);
+    e = launch_fuse(tab, cnt, pl.fuse_blocks[n], lp, st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "fusion launch");
   }
   return BDIS_OK;
+}
+
+// Graph key: everything that shapes the launch sequence (not the pointers).
+std::string graph_key(const bdis_params& p, const Plan& pl) {
+  std::string k(reinterpret_cast<const char*>(&p), sizeof p);
+  auto add = [&](const void* ptr, size_t n) { k.append(reinterpret_cast<const char*>(ptr), n); };
+  add(pl.tab_first, sizeof pl.tab_first);
+  add(pl.tab_count, sizeof pl.tab_count);
+  add(pl.pyr_blocks, sizeof pl.pyr_blocks);
+  add(pl.search_blocks, sizeof pl.search_blocks);
+  add(pl.prob_blocks, sizeof pl.prob_blocks);
+  add(pl.fuse_blocks, sizeof pl.fuse_blocks);
+  add(pl.threads, sizeof pl.threads);
+  add(&pl.max_levels, sizeof pl.max_levels);
+  return k;
+}
+
+bdis_status run_graph(bdis_ctx* c, const Plan& pl, hipStream_t st) {
+  const std::string key = graph_key(c->p, pl);
+  auto it = c->graphs.find(key);
+  hipError_t e;
+  if (it == c->graphs.end()) {
+    GraphEntry ge;
+    if ((e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hip_fail(c, e, "graph capture begin");
+    bdis_status s2 = launch_all(c, pl, c->capture_stream);
+    e = hipStreamEndCapture(c->capture_stream, &ge.graph);
+    if (s2 != BDIS_OK) {
+      if (ge.graph) (void)hipGraphDestroy(ge.graph);
+      return s2;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "graph capture end");
+    if ((e = hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0)) != hipSuccess) {
+      (void)hipGraphDestroy(ge.graph);
+      return hip_fail(c, e, "graph instantiate");
+    }
+    it = c->graphs.emplace(key, ge).first;
+  }
+  if ((e = hipGraphLaunch(it->second.exec, st)) != hipSuccess) return hip_fail(c, e, "graph launch");
+  return BDIS_OK;
+}
+
+// Picks the search workgroup size of every level of a new batch shape by
+// timing each option over full passes (the search is idempotent: it rewrites
+// its outputs and its reduction counter returns to 0).
+bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
+  const bdis_params& p = c->p;
+  bool need = false;
+  for (int n = p.finest_level; n < pl.max_levels; ++n)
+    if (pl.tab_count[n] && !c->tuned.count(level_key(p, pl, n))) need = true;
+  if (!need) return BDIS_OK;
+  const char* env = std::getenv("BDIS_TUNE");
+  const bool enabled = !(env && std::strcmp(env, "0") == 0);
+  float best_ms[kMaxLevels];
+  int best_t[kMaxLevels];
+  for (int n = 0; n < kMaxLevels; ++n) {
+    best_ms[n] = 1e30f;
+    best_t[n] = pl.threads[n];
+  }
+  if (enabled) {
+    std::vector<hipEvent_t> ev(2 * kMaxLevels, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto& x : ev)
+      if (e == hipSuccess) e = hipEventCreate(&x);
+    for (int o = 0; o < 3 && e == hipSuccess; ++o) {
+      Plan trial = pl;
+      for (int n = 0; n < trial.max_levels; ++n) trial.threads[n] = kSearchThreadOptions[o];
+      assign_offsets(p, trial);
+      bdis_status s2 = upload_table(c, trial, st);
+      if (s2 != BDIS_OK) {
+        for (auto& x : ev)
+          if (x) (void)hipEventDestroy(x);
+        return s2;
+      }
+      for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+        // a full pass with each level's search launch bracketed by events
+        for (int n = 1; n < trial.max_levels && e == hipSuccess; ++n)
+          e = launch_pyramid(c->tab_dev + trial.tab_first[n], trial.tab_count[n], trial.pyr_blocks[n], st);
+        for (int n = trial.max_levels - 1; n >= p.finest_level && e == hipSuccess; --n) {
+          const PairLevel* tab = c->tab_dev + trial.tab_first[n];
+          const LevelParams lp = level_params(p, n);
+          (void)hipEventRecord(ev[2 * n], st);
+          e = launch_search(tab, trial.tab_count[n], trial.search_blocks[n], lp, trial.threads[n], st);
+          (void)hipEventRecord(ev[2 * n + 1], st);
+          if (e == hipSuccess) e = launch_prob(tab, trial.tab_count[n], trial.prob_blocks[n], lp, st);
+          if (e == hipSuccess) e = launch_fuse(tab, trial.tab_count[n], trial.fuse_blocks[n], lp, st);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess || rep == 0) continue;  // the first pass warms caches and code
+        for (int n = p.finest_level; n < trial.max_levels; ++n) {
+          if (!trial.tab_count[n]) continue;
+          float ms = 0.0f;
+          if (hipEventElapsedTime(&ms, ev[2 * n], ev[2 * n + 1]) == hipSuccess && ms < best_ms[n]) {
+            best_ms[n] = ms;
+            best_t[n] = trial.threads[n];
+          }
+        }
+      }
+    }
+    for (auto& x : ev)
+      if (x) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return hip_fail(c, e, "tuning");
+  }
+  for (int n = p.finest_level; n < pl.max_levels; ++n) {
+    if (!pl.tab_count[n]) continue;
+    c->tuned[level_key(p, pl, n)] = best_t[n];
+    pl.threads[n] = best_t[n];
+  }
+  assign_offsets(p, pl);
+  return BDIS_OK;
+}
+
+bdis_status run_pairs(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipStream_t st) {
+  Plan pl;
+  bdis_status s = build_plan(c, pairs, &pl);
+  if (s != BDIS_OK) return s;
+  if ((s = tune(c, pl, st)) != BDIS_OK) return s;
+  if ((s = upload_table(c, pl, st)) != BDIS_OK) return s;
+  if (c->tm.on || !c->use_graph) return launch_all(c, pl, st);
+  return run_graph(c, pl, st);
 }
 
 }  // namespace
@@ -367,6 +648,8 @@ bdis_status bdis_create(bdis_ctx** out, const bdis_params* p, int max_w, int max
   c->max_h = max_h;
   c->max_batch = max_batch;
   c->slot_bytes = lay.total;
+  const char* g = std::getenv("BDIS_GRAPH");
+  c->use_graph = !(g && std::strcmp(g, "0") == 0);
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) {
     delete c;
@@ -376,13 +659,17 @@ bdis_status bdis_create(bdis_ctx** out, const bdis_params* p, int max_w, int max
   if (e != hipSuccess) {
     delete c;
     (void)hipGetLastError();
-    return fail(nullptr, BDIS_E_NOMEM, "hipMalloc of %zu bytes: %s", c->slot_bytes * (size_t)max_batch,
+    return fail(nullptr, BDIS_E_NOMEM, "hipMalloc of %zu bytes: %s", lay.total * (size_t)max_batch,
                 hipGetErrorString(e));
   }
   // zero the workspace once: the reduction counters must start at 0
   e = hipMemset(c->ws, 0, c->slot_bytes * (size_t)max_batch);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->tab_evt, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    if (c->tab_evt) (void)hipEventDestroy(c->tab_evt);
     (void)hipFree(c->ws);
     delete c;
     return fail(nullptr, BDIS_E_HIP, "workspace init: %s", hipGetErrorString(e));
@@ -413,8 +700,8 @@ bdis_status bdis_compute(bdis_ctx* c, const uint8_t* left, const uint8_t* right,
   if (w > c->max_w || h > c->max_h)
     return fail(c, BDIS_E_CAPACITY, "image %dx%d exceeds the context's %dx%d", w, h, c->max_w, c->max_h);
   c->have_last = false;
-  bdis_status st = run_pair(c, 0, left, right, w, h, pitch, c->p.levels, disp, var, conf,
-                            reinterpret_cast<hipStream_t>(stream));
+  std::vector<PairSpec> v{PairSpec{left, right, w, h, pitch, c->p.levels, disp, var, conf}};
+  bdis_status st = run_pairs(c, v, reinterpret_cast<hipStream_t>(stream));
   if (st == BDIS_OK) {
     c->last_w = w;
     c->last_h = h;
@@ -427,28 +714,23 @@ bdis_status bdis_compute_batch(bdis_ctx* c, int n, const bdis_pair* pairs, void*
   if (!c) return BDIS_E_ARG;
   if (n < 0 || (n > 0 && !pairs)) return fail(c, BDIS_E_ARG, "bad batch");
   if (n > c->max_batch) return fail(c, BDIS_E_CAPACITY, "batch of %d exceeds max_batch %d", n, c->max_batch);
-  // validate everything before launching anything
+  std::vector<PairSpec> v;
+  v.reserve((size_t)n);
   for (int i = 0; i < n; ++i) {
     const bdis_pair& q = pairs[i];
     if (!q.left || !q.right || !q.disparity) return fail(c, BDIS_E_ARG, "pair %d: null pointer", i);
     if (q.w < 1 || q.h < 1 || q.pitch < q.w) return fail(c, BDIS_E_ARG, "pair %d: bad size", i);
-    if (q.variance && !c->p.variance) return fail(c, BDIS_E_ARG, "pair %d: variance output without params.variance", i);
+    if (q.variance && !c->p.variance)
+      return fail(c, BDIS_E_ARG, "pair %d: variance output without params.variance", i);
+    if (q.levels < 0) return fail(c, BDIS_E_ARG, "pair %d: negative levels", i);
     const int lv = q.levels > 0 ? q.levels : c->p.levels;
     if (lv > c->p.levels) return fail(c, BDIS_E_CAPACITY, "pair %d: %d levels > %d", i, lv, c->p.levels);
     if (q.w > c->max_w || q.h > c->max_h) return fail(c, BDIS_E_CAPACITY, "pair %d: %dx%d too large", i, q.w, q.h);
-    Layout lay;
-    if (!make_layout(c->p, q.w, q.h, lv, &lay)) return fail(c, BDIS_E_SIZE, "pair %d: level smaller than patch", i);
-    if (lay.total > c->slot_bytes) return fail(c, BDIS_E_CAPACITY, "pair %d: workspace", i);
+    v.push_back(PairSpec{q.left, q.right, q.w, q.h, q.pitch, lv, q.disparity, q.variance, q.confidence});
   }
   c->have_last = false;
-  for (int i = 0; i < n; ++i) {
-    const bdis_pair& q = pairs[i];
-    const int lv = q.levels > 0 ? q.levels : c->p.levels;
-    bdis_status st = run_pair(c, i, q.left, q.right, q.w, q.h, q.pitch, lv, q.disparity, q.variance,
-                              q.confidence, reinterpret_cast<hipStream_t>(stream));
-    if (st != BDIS_OK) return st;
-  }
-  return BDIS_OK;
+  if (n == 0) return BDIS_OK;
+  return run_pairs(c, v, reinterpret_cast<hipStream_t>(stream));
 }
 
 bdis_status bdis_debug_dump(bdis_ctx* c, int level, int what, void* host_dst, size_t bytes, void* stream) {
@@ -513,8 +795,7 @@ bdis_status bdis_timing_enable(bdis_ctx* c, int enable) {
 }
 
 bdis_status bdis_timing_read(bdis_ctx* c, int kernel, double* total_ms, long* launches) {
-  if (!c || kernel < 0 || kernel >= BDIS_K_COUNT || !total_ms || !launches)
-    return BDIS_E_ARG;
+  if (!c || kernel < 0 || kernel >= BDIS_K_COUNT || !total_ms || !launches) return BDIS_E_ARG;
   double tot = 0.0;
   long n = 0;
   for (const auto& m : c->tm.marks) {
@@ -534,13 +815,21 @@ bdis_status bdis_timing_read(bdis_ctx* c, int kernel, double* total_ms, long* la
 void bdis_destroy(bdis_ctx* c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
+  for (auto& kv : c->graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+  }
   for (hipEvent_t e : c->tm.pool) (void)hipEventDestroy(e);
+  if (c->tab_evt) (void)hipEventDestroy(c->tab_evt);
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+  if (c->tab_dev) (void)hipFree(c->tab_dev);
+  if (c->tab_host) (void)hipHostFree(c->tab_host);
   if (c->ws) (void)hipFree(c->ws);
   delete c;
 }
 
 const char* bdis_last_error(const bdis_ctx* c) { return c ? c->err : g_create_err; }
 
-const char* bdis_version(void) { return "bdis-gfx950 0.1"; }
+const char* bdis_version(void) { return "bdis-gfx950 0.2"; }
 
 }  // extern "C"

@@ -134,7 +134,12 @@ def _textureless(rng, canvas, area):
     if area <= 0:
         return canvas
     h, w = canvas.shape
-    field = ndimage.gaussian_filter(rng.standard_normal((h, w)), sigma=max(h, w) / 12.0, mode="wrap")
+    # white noise low-passed by a periodic Gaussian of sigma max(h, w)/12 px (in the Fourier domain)
+    sig = max(h, w) / 12.0
+    ky = np.fft.fftfreq(h)[:, None]
+    kx = np.fft.rfftfreq(w)[None, :]
+    lp = np.exp(-2.0 * (np.pi * sig) ** 2 * (kx * kx + ky * ky))
+    field = np.fft.irfft2(np.fft.rfft2(rng.standard_normal((h, w))) * lp, s=(h, w))
     mask = field > np.quantile(field, 1.0 - area)
     blurred = ndimage.gaussian_filter(canvas, sigma=16.0, mode="reflect")
     return np.where(mask, blurred, canvas)
@@ -172,13 +177,14 @@ def _field(rng, wl):
 
 
 def _warp_rows(src, pos):
-    """Linear interpolation of each row of ``src`` at fractional columns ``pos``."""
+    """Linear interpolation of each row of ``src`` at fractional columns ``pos``
+    (positions outside the row take the end values)."""
     h, wc = src.shape
-    out = np.empty(pos.shape)
-    xs = np.arange(wc, dtype=np.float64)
-    for y in range(h):
-        out[y] = np.interp(pos[y], xs, src[y])
-    return out
+    p = np.clip(pos, 0.0, wc - 1.0)
+    i0 = np.minimum(np.floor(p).astype(np.int64), wc - 2)
+    f = p - i0
+    rows = np.arange(h)[:, None]
+    return src[rows, i0] * (1.0 - f) + src[rows, i0 + 1] * f
 
 
 def _ground_truth(d_right):

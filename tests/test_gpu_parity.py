@@ -268,3 +268,30 @@ def test_batch_matches_single(B):
             assert torch.equal(torch.nan_to_num(outs[i][k], nan=-7.0), torch.nan_to_num(one[k], nan=-7.0)), (i, k)
         ctx1.close()
     ctx.close()
+
+
+def test_graph_replays_match_eager(B, monkeypatch):
+    """Replays of the captured launch sequence equal an eager context's result, call after call."""
+    import torch
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    left, right, _, _ = make_pair(2, 1)
+    p = B.params(**method_params(2))
+    lt, rt = to_gpu(left), to_gpu(right)
+    monkeypatch.setenv("BDIS_GRAPH", "0")
+    eager = B.Context(p, 640, 480)
+    monkeypatch.delenv("BDIS_GRAPH")
+    graph = B.Context(p, 640, 480)
+    print("[gpu] graph replays vs eager, c2 pair 1", flush=True)
+    ref = eager.compute(lt, rt)
+    torch.cuda.synchronize()
+    ref = {k: v.clone() for k, v in ref.items()}
+    for rep in range(4):
+        out = graph.compute(lt, rt)
+        torch.cuda.synchronize()
+        for k in ref:
+            assert torch.equal(torch.nan_to_num(out[k], nan=-7.0), torch.nan_to_num(ref[k], nan=-7.0)), (rep, k)
+        # eager work of the program between replays
+        eager.compute(rt, lt)
+        torch.cuda.synchronize()
+    eager.close()
+    graph.close()
