@@ -67,8 +67,8 @@ struct PairLevel {
   // this level's images (level 0: the caller's inputs)
   const uint8_t* L;
   const uint8_t* R;
-  int pitch;
-  uint8_t* dstL;   // == L for n >= 1 (written by the pyramid phase)
+  int pitch;       // row pitch of L and R (level images in the workspace: 64-byte rows)
+  uint8_t* dstL;   // == L for n >= 1 (written by the pyramid phase, row pitch `pitch`)
   uint8_t* dstR;
   LevelGeom g;
   int levels;      // the pair's pyramid depth
@@ -115,7 +115,8 @@ constexpr int kProbThreads = 256;           // probability: patches per workgrou
 constexpr int kFuseTx = 64, kFuseTy = 4;    // fusion: 64 x 4 pixels per workgroup
 
 // Search workgroup sizes the tuner may pick (threads; patches = threads / G).
-constexpr int kSearchThreadOptions[3] = {64, 128, 256};
+constexpr int kNumSearchOptions = 5;
+constexpr int kSearchThreadOptions[kNumSearchOptions] = {64, 128, 256, 512, 1024};
 
 __host__ __device__ inline int search_patches_per_block(int P, int threads) {
   return threads / (P <= 8 ? 8 : 16);
@@ -169,6 +170,27 @@ BDIS_DEV int group_sum(int v) {
   return v;
 }
 
+// Global-address-space view of a pointer taken from the job table, so loads
+// and stores compile to global_* rather than flat_* instructions (flat
+// accesses also count against the LDS wait counter).
+template <typename T>
+BDIS_DEV __attribute__((address_space(1))) T* gbl(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
+// Global loads / stores of a D4 record.
+BDIS_DEV D4 ld4(const D4* p) {
+  const auto q = gbl(reinterpret_cast<const double*>(p));
+  return D4{q[0], q[1], q[2], q[3]};
+}
+BDIS_DEV void st4(D4* p, const D4& v) {
+  auto q = gbl(reinterpret_cast<double*>(p));
+  q[0] = v.x;
+  q[1] = v.y;
+  q[2] = v.z;
+  q[3] = v.w;
+}
+
 // Reflect-101 index for |overshoot| < n (the only case the kernels produce).
 BDIS_DEV int reflect101(int i, int n) {
   i = i < 0 ? -i : i;
@@ -184,8 +206,9 @@ BDIS_DEV double bilinear(const double* m, int w, int h, double x, double y) {
   const int ix = (int)fx0, iy = (int)fy0;
   const int x0 = clampi(ix, 0, w - 1), x1 = clampi(ix + 1, 0, w - 1);
   const int y0 = clampi(iy, 0, h - 1), y1 = clampi(iy + 1, 0, h - 1);
-  const double top = (1.0 - ax) * m[(size_t)y0 * w + x0] + ax * m[(size_t)y0 * w + x1];
-  const double bot = (1.0 - ax) * m[(size_t)y1 * w + x0] + ax * m[(size_t)y1 * w + x1];
+  const auto g = gbl(m);
+  const double top = (1.0 - ax) * g[(size_t)y0 * w + x0] + ax * g[(size_t)y0 * w + x1];
+  const double bot = (1.0 - ax) * g[(size_t)y1 * w + x0] + ax * g[(size_t)y1 * w + x1];
   return (1.0 - ay) * top + ay * bot;
 }
 

@@ -25,20 +25,20 @@ __global__ __launch_bounds__(kProbThreads) void k_prob(const PairLevel* tab, int
   const PairLevel& a = tab[find_pair<2>(tab, npairs, (int)blockIdx.x)];
   const int k = ((int)blockIdx.x - a.prob0) * kProbThreads + (int)threadIdx.x;
   if (k >= a.g.nx * a.g.ny) return;
-  const double u = a.pa.u[k];
+  const double u = gbl(a.pa.u)[k];
   const double nan = __builtin_nan("");
-  if (!a.pa.acc[k]) {
-    a.pa.dens[k] = D4{u, -1.0, nan, 0.0};
+  if (!gbl(a.pa.acc)[k]) {
+    st4(a.pa.dens + k, D4{u, -1.0, nan, 0.0});
     return;
   }
-  const double tau = a.scal[1];
-  const D4 d = a.pa.dssd[k];
+  const double tau = gbl(a.scal)[1];
+  const D4 d = ld4(a.pa.dssd + k);
   const double den = 1.0 + exp(-d.x / tau) + exp(-d.y / tau) + exp(-d.z / tau) + exp(-d.w / tau);
   const double post = 1.0 / den;
   double wsum = 0.0;
   for (int n = lp.finest; n < a.levels; ++n) wsum += (double)lp.omega[n];
   const double gamma = (double)lp.omega[lp.level] / wsum;
-  const double pi = gamma * post + a.pa.pipar[k];
+  const double pi = gamma * post + gbl(a.pa.pipar)[k];
   double sig = nan;
   if (lp.variance && lp.level == lp.finest) {
     const double sfail = lp.var_fail_sigma > 0.0f ? (double)lp.var_fail_sigma : (double)lp.P;
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kProbThreads) void k_prob(const PairLevel* tab, int
     }
     sig = v;
   }
-  a.pa.dens[k] = D4{u, pi, sig, post};
+  st4(a.pa.dens + k, D4{u, pi, sig, post});
 }
 
 // Covering patches along one axis: indices lo..hi (origin i*S), plus the last
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
     const D4* row = a.pa.dens + (size_t)j * a.g.nx;
     for (int ii = ilo; ii <= iend; ++ii) {
       const int i = ii <= ihi ? ii : iex;
-      const D4 d = row[i];
+      const D4 d = ld4(row + i);
       if (d.y < 0.0) continue;  // rejected patch
       const double m = s_m[x - grid_origin(i, a.g.w, P, S)] * mb;
       const double wk = m * d.y;
@@ -138,15 +138,15 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
     qv = 0.0;
   }
   if (!finest) {
-    a.ubar[idx] = ub;
-    a.qmap[idx] = qv;
+    gbl(a.ubar)[idx] = ub;
+    gbl(a.qmap)[idx] = qv;
     return;
   }
   if (lp.prob_thresh > 0.0f && qv < (double)lp.prob_thresh) valid = false;
   const float nan = __builtin_nanf("");
-  a.disparity[idx] = valid ? (float)(-ub) : nan;
-  if (a.confidence) a.confidence[idx] = valid ? (float)qv : 0.0f;
-  if (a.variance) a.variance[idx] = (valid && lp.variance) ? (float)(zv / (z * z)) : nan;
+  gbl(a.disparity)[idx] = valid ? (float)(-ub) : nan;
+  if (a.confidence) gbl(a.confidence)[idx] = valid ? (float)qv : 0.0f;
+  if (a.variance) gbl(a.variance)[idx] = (valid && lp.variance) ? (float)(zv / (z * z)) : nan;
 }
 
 }  // namespace

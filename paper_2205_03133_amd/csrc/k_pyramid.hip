@@ -34,8 +34,8 @@ __global__ __launch_bounds__(kPyrTx* kPyrTy) void k_pyr_u8(const PairLevel* tab,
     int sy = 2 * y0 - 2 + r;
     // rows beyond sh + 1 feed only idle output rows: keep them in range
     sy = sy > a.sh + 1 ? a.sh - 1 : reflect101(sy, a.sh);
-    const uint8_t* rl = a.srcL + (size_t)sy * a.spitch;
-    const uint8_t* rr = a.srcR + (size_t)sy * a.spitch;
+    const auto rl = gbl(a.srcL + (size_t)sy * a.spitch);
+    const auto rr = gbl(a.srcR + (size_t)sy * a.spitch);
     hL[r][tx] = rl[cx[0]] + 4 * rl[cx[1]] + 6 * rl[cx[2]] + 4 * rl[cx[3]] + rl[cx[4]];
     hR[r][tx] = rr[cx[0]] + 4 * rr[cx[1]] + 6 * rr[cx[2]] + 4 * rr[cx[3]] + rr[cx[4]];
   }
@@ -45,8 +45,8 @@ __global__ __launch_bounds__(kPyrTx* kPyrTy) void k_pyr_u8(const PairLevel* tab,
   const int q = 2 * ty;  // local row of source row 2*y-2
   const int sl = hL[q][tx] + 4 * hL[q + 1][tx] + 6 * hL[q + 2][tx] + 4 * hL[q + 3][tx] + hL[q + 4][tx];
   const int sr = hR[q][tx] + 4 * hR[q + 1][tx] + 6 * hR[q + 2][tx] + 4 * hR[q + 3][tx] + hR[q + 4][tx];
-  a.dstL[(size_t)y * dw + x] = (uint8_t)((sl + 128) >> 8);
-  a.dstR[(size_t)y * dw + x] = (uint8_t)((sr + 128) >> 8);
+  gbl(a.dstL)[(size_t)y * a.pitch + x] = (uint8_t)((sl + 128) >> 8);
+  gbl(a.dstR)[(size_t)y * a.pitch + x] = (uint8_t)((sr + 128) >> 8);
 }
 
 }  // namespace

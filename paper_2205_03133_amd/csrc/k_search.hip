@@ -42,8 +42,35 @@ BDIS_DEV void fetch_row(int (&v)[N], const uint8_t* win, int xs, int rw, const u
 #pragma unroll
     for (int n = 0; n < N; ++n) v[n] = win[off + n];
   } else {
+    const auto g = gbl(grow);
 #pragma unroll
-    for (int n = 0; n < N; ++n) v[n] = grow[clampi(x + n, 0, W - 1)];
+    for (int n = 0; n < N; ++n) v[n] = g[clampi(x + n, 0, W - 1)];
+  }
+}
+
+// Copies columns [x0, x0 + 4 nd) of image row `rp` (width W) into LDS as nd
+// dwords; x0 is a multiple of 4.  Columns outside the row are mapped by
+// reflect-101 (REFLECT) or clamping, and then clamped, so every access stays
+// in the row.  Interior dwords of a 4-aligned row are single global loads.
+template <bool REFLECT>
+BDIS_DEV void stage_row(uint32_t* dst, const uint8_t* rp, int W, int x0, int nd, int lane, bool aligned) {
+  const auto g = gbl(rp);
+  for (int k = lane; k < nd; k += 64) {
+    const int c = x0 + 4 * k;
+    uint32_t v;
+    if (aligned && c >= 0 && c + 3 < W) {
+      v = *reinterpret_cast<const __attribute__((address_space(1))) uint32_t*>(g + c);
+    } else {
+      v = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        int x = c + b;
+        x = REFLECT ? reflect101(x, W) : x;
+        x = clampi(x, 0, W - 1);
+        v |= (uint32_t)g[x] << (8 * b);
+      }
+    }
+    dst[k] = v;
   }
 }
 
@@ -51,16 +78,20 @@ template <int P, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int npairs, LevelParams lp) {
   constexpr int G = group_lanes(P);
   constexpr int NPB = THREADS / G;               // patches per workgroup
-  constexpr int LTW = (NPB - 1) * P + P + 2;     // left tile width bound (S <= P)
+  constexpr int LTW = ((NPB - 1) * P + P + 2 + 3 + 3) / 4 * 4;  // left tile row bytes (S <= P, 4-aligned start)
+  constexpr int RWB = kWinRow;                   // right window row bytes
   constexpr int MARG = P + 4;                    // window margin around the start range
   constexpr int N = P * P;
+  constexpr int NWAVES = THREADS / 64;
 
-  __shared__ uint8_t s_left[(P + 2) * LTW];
-  __shared__ uint8_t s_right[P * kWinRow];
+  __shared__ uint32_t s_left32[(P + 2) * LTW / 4];
+  __shared__ uint32_t s_right32[P * RWB / 4];
   __shared__ int s_umin, s_umax;
   __shared__ double s_psum[NPB];
   __shared__ int s_pcnt[NPB];
   __shared__ int s_last;
+  const uint8_t* s_left = reinterpret_cast<const uint8_t*>(s_left32);
+  const uint8_t* s_right = reinterpret_cast<const uint8_t*>(s_right32);
 
   const PairLevel& a = tab[find_pair<1>(tab, npairs, (int)blockIdx.x)];
   const int blk = (int)blockIdx.x - a.search0;   // workgroup within the pair
@@ -91,11 +122,14 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
     s_umin = INT_MAX;
     s_umax = INT_MIN;
   }
-  // ---- left tile: image rows oy-1 .. oy+P, columns ox0-1 .. oxl+P (reflect-101)
-  const int ltw = oxl - ox0 + P + 2;
-  for (int ty = 0; ty < P + 2; ++ty) {
-    const uint8_t* src = a.L + (size_t)reflect101(oy - 1 + ty, Hh) * a.pitch;
-    for (int tx = tid; tx < ltw; tx += THREADS) s_left[ty * LTW + tx] = src[reflect101(ox0 - 1 + tx, W)];
+  const int wave = tid / 64, lane = tid % 64;
+  // ---- left tile: image rows oy-1 .. oy+P, columns xa .. oxl+P (reflect-101),
+  // xa = (ox0 - 1) rounded down to a multiple of 4
+  const int xa = (ox0 - 1) & ~3;
+  const int ndl = (oxl + P + 1 - xa + 3) / 4;
+  for (int ty = wave; ty < P + 2; ty += NWAVES) {
+    const uint8_t* rp = a.L + (size_t)reflect101(oy - 1 + ty, Hh) * a.pitch;
+    stage_row<true>(s_left32 + ty * (LTW / 4), rp, W, xa, ndl, lane, ((uintptr_t)rp & 3) == 0);
   }
   __syncthreads();
   if (r == 0 && live) {
@@ -104,12 +138,14 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
     atomicMax(&s_umax, mu);
   }
   __syncthreads();
-  // ---- right window: rows oy .. oy+P-1, columns xs .. xs+rw-1 (clamped to the image)
-  const int xs = ox0 + s_umin - MARG;
-  const int rw = min(oxl + P + s_umax + MARG + 2 - xs, kWinRow);
-  for (int ty = 0; ty < P; ++ty) {
-    const uint8_t* src = a.R + (size_t)(oy + ty) * a.pitch;
-    for (int tx = tid; tx < rw; tx += THREADS) s_right[ty * kWinRow + tx] = src[clampi(xs + tx, 0, W - 1)];
+  // ---- right window: rows oy .. oy+P-1, columns xs .. xs+rw-1 (clamped to the
+  // image), xs a multiple of 4
+  const int xs = (ox0 + s_umin - MARG) & ~3;
+  const int ndr = min((oxl + P + s_umax + MARG + 2 - xs + 3) / 4, RWB / 4);
+  const int rw = 4 * ndr;
+  for (int ty = wave; ty < P; ty += NWAVES) {
+    const uint8_t* rp = a.R + (size_t)(oy + ty) * a.pitch;
+    stage_row<false>(s_right32 + ty * (RWB / 4), rp, W, xs, ndr, lane, ((uintptr_t)rp & 3) == 0);
   }
   __syncthreads();
 
@@ -118,7 +154,7 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
   const int rr = row_live ? r : P - 1;
   int T[P], Gx[P];
   {
-    const uint8_t* l0 = s_left + rr * LTW + (ox - ox0);
+    const uint8_t* l0 = s_left + rr * LTW + (ox - 1 - xa);
     const uint8_t* l1 = l0 + LTW;
     const uint8_t* l2 = l1 + LTW;
 #pragma unroll
@@ -145,7 +181,7 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
   const bool invert = H >= kEpsH;
   const double step = invert ? 8.0 / (double)Hs : 0.0;
 
-  const uint8_t* win = s_right + rr * kWinRow;
+  const uint8_t* win = s_right + rr * RWB;
   const uint8_t* grow = a.R + (size_t)(oy + rr) * a.pitch;
 
   // ---- K inverse-compositional iterations (Eq. 1), cached cell correlations
@@ -241,14 +277,14 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
 
   const int k = j * a.g.nx + i;
   if (r == 0 && live) {
-    a.pa.uinit[k] = uinit;
-    a.pa.pipar[k] = pipar;
-    a.pa.u[k] = u;
-    a.pa.ssd0[k] = s0;
-    a.pa.dssd[k] = D4{sm1 - s0, smh - s0, sph - s0, sp1 - s0};
-    a.pa.rho[k] = (float)rho;
-    a.pa.acc[k] = acc ? 1 : 0;
-    a.pa.hess[k] = (float)H;
+    gbl(a.pa.uinit)[k] = uinit;
+    gbl(a.pa.pipar)[k] = pipar;
+    gbl(a.pa.u)[k] = u;
+    gbl(a.pa.ssd0)[k] = s0;
+    st4(a.pa.dssd + k, D4{sm1 - s0, smh - s0, sph - s0, sp1 - s0});
+    gbl(a.pa.rho)[k] = (float)rho;
+    gbl(a.pa.acc)[k] = acc ? 1 : 0;
+    gbl(a.pa.hess)[k] = (float)H;
   }
 
   // ---- level reduction: sum of SSD(0) and count over accepted patches
@@ -265,8 +301,8 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
       ps += s_psum[t];
       pc += s_pcnt[t];
     }
-    a.part_sum[blk] = ps;
-    a.part_cnt[blk] = pc;
+    gbl(a.part_sum)[blk] = ps;
+    gbl(a.part_cnt)[blk] = pc;
     __threadfence();
     const unsigned prev = atomicAdd(a.counter, 1u);
     s_last = (prev == (unsigned)(nblocks - 1)) ? 1 : 0;
@@ -275,18 +311,21 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
   if (!s_last) return;
   // last workgroup: fixed-order reduction of all partials (deterministic)
   __threadfence();
-  __shared__ double s_red[THREADS];
-  __shared__ long long s_redc[THREADS];
-  double ps = 0.0;
-  long long pc = 0;
-  for (int b = tid; b < nblocks; b += THREADS) {
-    ps += __hip_atomic_load(&a.part_sum[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    pc += __hip_atomic_load(&a.part_cnt[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  constexpr int RED = THREADS < 256 ? THREADS : 256;
+  __shared__ double s_red[RED];
+  __shared__ long long s_redc[RED];
+  if (tid < RED) {
+    double ps = 0.0;
+    long long pc = 0;
+    for (int b = tid; b < nblocks; b += RED) {
+      ps += __hip_atomic_load(&a.part_sum[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      pc += __hip_atomic_load(&a.part_cnt[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_red[tid] = ps;
+    s_redc[tid] = pc;
   }
-  s_red[tid] = ps;
-  s_redc[tid] = pc;
   __syncthreads();
-  for (int off = THREADS / 2; off > 0; off >>= 1) {
+  for (int off = RED / 2; off > 0; off >>= 1) {
     if (tid < off) {
       s_red[tid] += s_red[tid + off];
       s_redc[tid] += s_redc[tid + off];
@@ -315,6 +354,8 @@ hipError_t launch_p(const PairLevel* tab, int npairs, int nblocks, const LevelPa
     case 64: hipLaunchKernelGGL((k_search_u8<P, 64>), dim3(nblocks), dim3(64), 0, s, tab, npairs, lp); break;
     case 128: hipLaunchKernelGGL((k_search_u8<P, 128>), dim3(nblocks), dim3(128), 0, s, tab, npairs, lp); break;
     case 256: hipLaunchKernelGGL((k_search_u8<P, 256>), dim3(nblocks), dim3(256), 0, s, tab, npairs, lp); break;
+    case 512: hipLaunchKernelGGL((k_search_u8<P, 512>), dim3(nblocks), dim3(512), 0, s, tab, npairs, lp); break;
+    case 1024: hipLaunchKernelGGL((k_search_u8<P, 1024>), dim3(nblocks), dim3(1024), 0, s, tab, npairs, lp); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

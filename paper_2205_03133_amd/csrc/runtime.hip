@@ -35,6 +35,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   int levels = 0;
   LevelGeom g[kMaxLevels]{};
+  int lpitch[kMaxLevels]{};      // row pitch of the level images (64-byte rows)
   int max_search_blocks[kMaxLevels]{};
   size_t lvl_l[kMaxLevels]{}, lvl_r[kMaxLevels]{};
   size_t uinit[kMaxLevels]{}, pipar[kMaxLevels]{}, u[kMaxLevels]{}, ssd0[kMaxLevels]{},
@@ -81,9 +82,10 @@ bool make_layout(const bdis_params& p, int w, int h, int levels, Layout* lay) {
   };
   for (int n = 0; n < levels; ++n) {
     const size_t npx = (size_t)L.g[n].w * L.g[n].h;
+    L.lpitch[n] = (L.g[n].w + 63) / 64 * 64;
     if (n >= 1) {
-      L.lvl_l[n] = take(npx);
-      L.lvl_r[n] = take(npx);
+      L.lvl_l[n] = take((size_t)L.lpitch[n] * L.g[n].h);
+      L.lvl_r[n] = take((size_t)L.lpitch[n] * L.g[n].h);
     }
     if (n < p.finest_level) continue;
     const size_t np = (size_t)L.g[n].nx * L.g[n].ny;
@@ -286,7 +288,7 @@ std::string level_key(const bdis_params& p, const Plan& pl, int n) {
 // Default search workgroup size: the largest option that still gives every
 // compute unit (256 on MI355X) two workgroups; else the smallest option.
 int default_threads(const Plan& pl, int n, int P) {
-  for (int o = 2; o >= 0; --o) {
+  for (int o = 2; o >= 0; --o) {  // 256, 128, 64
     const int t = kSearchThreadOptions[o];
     long blocks = 0;
     for (int e = 0; e < pl.tab_count[n]; ++e) {
@@ -353,7 +355,7 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
       if (n >= 1) {
         e.srcL = n == 1 ? q.left : B8(lay.lvl_l[n - 1]);
         e.srcR = n == 1 ? q.right : B8(lay.lvl_r[n - 1]);
-        e.spitch = n == 1 ? q.pitch : lay.g[n - 1].w;
+        e.spitch = n == 1 ? q.pitch : lay.lpitch[n - 1];
         e.sw = lay.g[n - 1].w;
         e.sh = lay.g[n - 1].h;
         e.dstL = B8(lay.lvl_l[n]);
@@ -361,7 +363,7 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
       }
       e.L = n == 0 ? q.left : B8(lay.lvl_l[n]);
       e.R = n == 0 ? q.right : B8(lay.lvl_r[n]);
-      e.pitch = n == 0 ? q.pitch : lay.g[n].w;
+      e.pitch = n == 0 ? q.pitch : lay.lpitch[n];
       if (n >= p.finest_level) {
         const bool has_par = n + 1 < q.levels;
         e.par_ubar = has_par ? BD(lay.ubar[n + 1]) : nullptr;
@@ -396,7 +398,7 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
   }
   for (int n = 0; n < pl.max_levels; ++n) {
     if (n < p.finest_level || pl.tab_count[n] == 0) {
-      pl.threads[n] = kSearchThreadOptions[2];
+      pl.threads[n] = 256;
       continue;
     }
     auto it = c->tuned.find(level_key(p, pl, n));
@@ -537,7 +539,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
     hipError_t e = hipSuccess;
     for (auto& x : ev)
       if (e == hipSuccess) e = hipEventCreate(&x);
-    for (int o = 0; o < 3 && e == hipSuccess; ++o) {
+    for (int o = 0; o < kNumSearchOptions && e == hipSuccess; ++o) {
       Plan trial = pl;
       for (int n = 0; n < trial.max_levels; ++n) trial.threads[n] = kSearchThreadOptions[o];
       assign_offsets(p, trial);
@@ -768,7 +770,12 @@ bdis_status bdis_debug_dump(bdis_ctx* c, int level, int what, void* host_dst, si
     return fail(c, BDIS_E_ARG, "the finest level writes the outputs, not level maps");
   if (bytes < n) return fail(c, BDIS_E_ARG, "buffer of %zu bytes < %zu", bytes, n);
   hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
-  if (e == hipSuccess) e = hipMemcpy(host_dst, c->ws + off, n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) {
+    if (what == BDIS_DBG_LEFT || what == BDIS_DBG_RIGHT)  // padded rows -> dense W x H
+      e = hipMemcpy2D(host_dst, g.w, c->ws + off, lay.lpitch[level], g.w, g.h, hipMemcpyDeviceToHost);
+    else
+      e = hipMemcpy(host_dst, c->ws + off, n, hipMemcpyDeviceToHost);
+  }
   if (e != hipSuccess) return hip_fail(c, e, "debug dump");
   return BDIS_OK;
 }
