@@ -140,11 +140,12 @@ bdis_status bdis_debug_dump(bdis_ctx* ctx, int level, int what, void* host_dst, 
 
 /* Per-kernel timing with HIP events recorded on the compute stream around
  * every launch (for measurement; adds two event records per launch).
- * kernel: 0 pyramid, 1 patch search, 2 patch probability, 3 fusion.
+ * kernel: 0 pyramid, 1 patch search, 2 patch probability, 3 fusion,
+ * 4 the per-pair sigma_r reduction.
  * bdis_timing_enable(ctx, 1) clears the totals and starts recording;
  * bdis_timing_read synchronises the recorded events and returns the summed
  * GPU time (ms) and the launch count of one kernel since enabling. */
-enum { BDIS_K_PYRAMID = 0, BDIS_K_SEARCH = 1, BDIS_K_PROB = 2, BDIS_K_FUSE = 3, BDIS_K_COUNT = 4 };
+enum { BDIS_K_PYRAMID = 0, BDIS_K_SEARCH = 1, BDIS_K_PROB = 2, BDIS_K_FUSE = 3, BDIS_K_REDUCE = 4, BDIS_K_COUNT = 5 };
 bdis_status bdis_timing_enable(bdis_ctx* ctx, int enable);
 bdis_status bdis_timing_read(bdis_ctx* ctx, int kernel, double* total_ms, long* launches);
 

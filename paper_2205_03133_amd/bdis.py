@@ -241,7 +241,7 @@ class Context:
             raise self._err(st)
         return results
 
-    KERNELS = ("pyramid", "search", "prob", "fuse")
+    KERNELS = ("pyramid", "search", "prob", "fuse", "reduce")
 
     def timing(self, enable):
         """Start (clearing totals) or stop per-kernel HIP-event timing."""

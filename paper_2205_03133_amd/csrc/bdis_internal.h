@@ -77,10 +77,9 @@ struct PairLevel {
   const double* par_q;
   int pw, ph;
   PatchArrays pa;
-  // sigma_r reduction of this pair and level
+  // sigma_r reduction of this pair and level: per-workgroup partials
   double* part_sum;
   int* part_cnt;
-  unsigned* counter;
   double* scal;    // [sigma_r^2, tau]
   // fusion outputs: level maps above the finest, user outputs at the finest
   double* ubar;
@@ -126,6 +125,7 @@ __host__ __device__ inline int search_patches_per_block(int P, int threads) {
 hipError_t launch_pyramid(const PairLevel* tab, int npairs, int nblocks, hipStream_t s);
 hipError_t launch_search(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,
                          int threads, hipStream_t s);
+hipError_t launch_reduce(const PairLevel* tab, int npairs, const LevelParams& lp, hipStream_t s);
 hipError_t launch_prob(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,
                        hipStream_t s);
 hipError_t launch_fuse(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,

@@ -1,8 +1,8 @@
 // Per-patch inverse-compositional 1-D search, Bayesian window and acceptance
 // (Eq. 1 with the inverse roles of Sec. III-A; window of Eq. 5-6 with offsets
 // -1, -1/2, 0, +1/2, +1 of Sec. IV-A; saddle / in-bounds rejection of
-// Sec. III-B and III-F), plus the level reduction that sets sigma_r^(n)
-// (Sec. III-B).
+// Sec. III-B and III-F), plus the per-pair reduction that sets sigma_r^(n)
+// (Sec. III-B): workgroups write partial sums, k_reduce adds them in order.
 //
 // Mapping: one lane per patch row, an aligned group of G = 8 or 16 lanes per
 // patch (a DPP quad/half-row/row, so group reductions are 3-4 DPP adds),
@@ -89,7 +89,6 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
   __shared__ int s_umin, s_umax;
   __shared__ double s_psum[NPB];
   __shared__ int s_pcnt[NPB];
-  __shared__ int s_last;
   const uint8_t* s_left = reinterpret_cast<const uint8_t*>(s_left32);
   const uint8_t* s_right = reinterpret_cast<const uint8_t*>(s_right32);
 
@@ -287,13 +286,13 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
     gbl(a.pa.hess)[k] = (float)H;
   }
 
-  // ---- level reduction: sum of SSD(0) and count over accepted patches
+  // ---- per-workgroup partial of the level reduction: sum of SSD(0) and count
+  // over accepted patches (summed per pair, in workgroup order, by k_reduce)
   if (r == 0) {
     s_psum[q] = (live && acc) ? s0 : 0.0;
     s_pcnt[q] = (live && acc) ? 1 : 0;
   }
   __syncthreads();
-  const int nblocks = a.search_nbx * a.g.ny;  // workgroups of this pair
   if (tid == 0) {
     double ps = 0.0;
     int pc = 0;
@@ -303,29 +302,29 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
     }
     gbl(a.part_sum)[blk] = ps;
     gbl(a.part_cnt)[blk] = pc;
-    __threadfence();
-    const unsigned prev = atomicAdd(a.counter, 1u);
-    s_last = (prev == (unsigned)(nblocks - 1)) ? 1 : 0;
   }
-  __syncthreads();
-  if (!s_last) return;
-  // last workgroup: fixed-order reduction of all partials (deterministic)
-  __threadfence();
-  constexpr int RED = THREADS < 256 ? THREADS : 256;
-  __shared__ double s_red[RED];
-  __shared__ long long s_redc[RED];
-  if (tid < RED) {
-    double ps = 0.0;
-    long long pc = 0;
-    for (int b = tid; b < nblocks; b += RED) {
-      ps += __hip_atomic_load(&a.part_sum[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      pc += __hip_atomic_load(&a.part_cnt[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    s_red[tid] = ps;
-    s_redc[tid] = pc;
+}
+
+// sigma_r^(n) of each pair (one workgroup per pair), read from Sec. III-B as
+// the pooled per-pixel variance of the mean-normalised residual over the
+// accepted patches of the level, scaled by alpha_r^2 and floored; or the fixed
+// sigma_r.  tau = 2 sigma_r^2 s^2 (Eq. 6).  Fixed-order FP64 sums.
+__global__ __launch_bounds__(256) void k_reduce(const PairLevel* tab, LevelParams lp) {
+  __shared__ double s_red[256];
+  __shared__ long long s_redc[256];
+  const PairLevel& a = tab[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int nblocks = a.search_nbx * a.g.ny;
+  double ps = 0.0;
+  long long pc = 0;
+  for (int b = tid; b < nblocks; b += 256) {
+    ps += gbl(a.part_sum)[b];
+    pc += gbl(a.part_cnt)[b];
   }
+  s_red[tid] = ps;
+  s_redc[tid] = pc;
   __syncthreads();
-  for (int off = RED / 2; off > 0; off >>= 1) {
+  for (int off = 128; off > 0; off >>= 1) {
     if (tid < off) {
       s_red[tid] += s_red[tid + off];
       s_redc[tid] += s_redc[tid + off];
@@ -336,14 +335,13 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
     double sr2;
     const double alpha2 = (double)lp.sigma_r * (double)lp.sigma_r;
     if (lp.sigma_r_dynamic) {
-      const double pooled = s_redc[0] > 0 ? s_red[0] / ((double)s_redc[0] * (double)N) : 0.0;
+      const double pooled = s_redc[0] > 0 ? s_red[0] / ((double)s_redc[0] * (double)(lp.P * lp.P)) : 0.0;
       sr2 = alpha2 * (pooled > kEpsSigma ? pooled : kEpsSigma);
     } else {
       sr2 = alpha2;
     }
-    a.scal[0] = sr2;
-    a.scal[1] = 2.0 * sr2 * 25.0;  // tau = 2 sigma_r^2 s^2, s = 5 window samples (Eq. 6)
-    __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    gbl(a.scal)[0] = sr2;
+    gbl(a.scal)[1] = 2.0 * sr2 * (double)(kWin * kWin);
   }
 }
 
@@ -362,6 +360,12 @@ hipError_t launch_p(const PairLevel* tab, int npairs, int nblocks, const LevelPa
 }
 
 }  // namespace
+
+hipError_t launch_reduce(const PairLevel* tab, int npairs, const LevelParams& lp, hipStream_t s) {
+  if (npairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce, dim3(npairs), dim3(256), 0, s, tab, lp);
+  return hipGetLastError();
+}
 
 hipError_t launch_search(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, int threads,
                          hipStream_t s) {

@@ -42,7 +42,7 @@ struct Layout {
       dssd[kMaxLevels]{}, rho[kMaxLevels]{}, acc[kMaxLevels]{}, hess[kMaxLevels]{},
       dens[kMaxLevels]{};
   size_t ubar[kMaxLevels]{}, qmap[kMaxLevels]{};
-  size_t part_sum[kMaxLevels]{}, part_cnt[kMaxLevels]{}, counter[kMaxLevels]{}, scal[kMaxLevels]{};
+  size_t part_sum[kMaxLevels]{}, part_cnt[kMaxLevels]{}, scal[kMaxLevels]{};
   size_t total = 0;
 };
 
@@ -106,7 +106,6 @@ bool make_layout(const bdis_params& p, int w, int h, int levels, Layout* lay) {
     L.max_search_blocks[n] = search_nbx(L.g[n], p.patch, kSearchThreadOptions[0]) * L.g[n].ny;
     L.part_sum[n] = take((size_t)L.max_search_blocks[n] * 8);
     L.part_cnt[n] = take((size_t)L.max_search_blocks[n] * 4);
-    L.counter[n] = take(64);
     L.scal[n] = take(64);
   }
   L.total = off;
@@ -381,7 +380,6 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
         e.pa.dens = reinterpret_cast<D4*>(base + lay.dens[n]);
         e.part_sum = BD(lay.part_sum[n]);
         e.part_cnt = reinterpret_cast<int*>(base + lay.part_cnt[n]);
-        e.counter = reinterpret_cast<unsigned*>(base + lay.counter[n]);
         e.scal = BD(lay.scal[n]);
         if (n > p.finest_level) {
           e.ubar = BD(lay.ubar[n]);
@@ -465,6 +463,10 @@ bdis_status launch_all(bdis_ctx* c, const Plan& pl, hipStream_t st) {
     e = launch_search(tab, cnt, pl.search_blocks[n], lp, pl.threads[n], st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "search launch");
+    tmk = timing_start(c, BDIS_K_REDUCE, st);
+    e = launch_reduce(tab, cnt, lp, st);
+    timing_stop(c, tmk, st);
+    if (e != hipSuccess) return hip_fail(c, e, "reduction launch");
     tmk = timing_start(c, BDIS_K_PROB, st);
     e = launch_prob(tab, cnt, pl.prob_blocks[n], lp, st);
     timing_stop(c, tmk, st);
@@ -518,8 +520,8 @@ bdis_status run_graph(bdis_ctx* c, const Plan& pl, hipStream_t st) {
 }
 
 // Picks the search workgroup size of every level of a new batch shape by
-// timing each option over full passes (the search is idempotent: it rewrites
-// its outputs and its reduction counter returns to 0).
+// timing each option over full passes (every phase rewrites its outputs, so
+// trial passes leave nothing behind).
 bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
   const bdis_params& p = c->p;
   bool need = false;
@@ -559,6 +561,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
           (void)hipEventRecord(ev[2 * n], st);
           e = launch_search(tab, trial.tab_count[n], trial.search_blocks[n], lp, trial.threads[n], st);
           (void)hipEventRecord(ev[2 * n + 1], st);
+          if (e == hipSuccess) e = launch_reduce(tab, trial.tab_count[n], lp, st);
           if (e == hipSuccess) e = launch_prob(tab, trial.tab_count[n], trial.prob_blocks[n], lp, st);
           if (e == hipSuccess) e = launch_fuse(tab, trial.tab_count[n], trial.fuse_blocks[n], lp, st);
         }
@@ -664,7 +667,7 @@ bdis_status bdis_create(bdis_ctx** out, const bdis_params* p, int max_w, int max
     return fail(nullptr, BDIS_E_NOMEM, "hipMalloc of %zu bytes: %s", lay.total * (size_t)max_batch,
                 hipGetErrorString(e));
   }
-  // zero the workspace once: the reduction counters must start at 0
+  // zero the workspace once (every array is rewritten before it is read)
   e = hipMemset(c->ws, 0, c->slot_bytes * (size_t)max_batch);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->tab_evt, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
