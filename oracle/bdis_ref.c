@@ -34,6 +34,7 @@ typedef struct {
   /* maps */
   double *ubar, *qmap, *valid;
   double sigma_r2, tau, nacc, gamma;
+  uint64_t dhash; /* hash of every discrete decision taken on this level */
 } ref_level;
 
 struct bdis_ref_trace {
@@ -46,6 +47,16 @@ struct bdis_ref_trace {
 /* ------------------------------------------------------------------------- */
 
 static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* FNV-1a over the discrete decisions (unit cells, resets, acceptances, holes,
+ * variance-fit outcomes); two runs with equal hashes took the same branches,
+ * so a finite difference between them measures a derivative. */
+static void mix(uint64_t* h, long long v) {
+  for (int b = 0; b < 8; ++b) {
+    *h ^= (uint64_t)((v >> (8 * b)) & 0xff);
+    *h *= 1099511628211ULL;
+  }
+}
 
 /* Reflect-101 border: -1 -> 1, -2 -> 2, n -> n-2, n+1 -> n-3. */
 static int reflect101(int i, int n) {
@@ -166,7 +177,7 @@ static double patch_ssd(const double* L, const double* R, int w, int ox, int oy,
 /*  - Accepted iff the centre has the smallest SSD (saddle / unconverged     */
 /*    rejection, Sec. III-B and III-F) and the in-bounds fraction >= gamma.  */
 /* ------------------------------------------------------------------------- */
-static void search_patch(const ref_level* lv, const bdis_ref_params* p, int k, int ox, int oy) {
+static void search_patch(ref_level* lv, const bdis_ref_params* p, int k, int ox, int oy) {
   const int P = p->patch, w = lv->w, n = P * P;
   const double* L = lv->left;
   const double* R = lv->right;
@@ -194,11 +205,15 @@ static void search_patch(const ref_level* lv, const bdis_ref_params* p, int k, i
           double Iw = warp_sample(R + (size_t)(oy + r) * w, w, ox + c, u);
           bsum += J * (Iw - L[idx]);
         }
+      mix(&lv->dhash, (long long)floor(u));
       u = u - bsum / H;
     }
   }
-  if (fabs(u - u0) > (double)P) u = u0;
+  const int reset = fabs(u - u0) > (double)P;
+  mix(&lv->dhash, reset);
+  if (reset) u = u0;
   lv->u[k] = u;
+  for (int d = 0; d < NWIN; ++d) mix(&lv->dhash, (long long)floor(u + kWinOffset[d]));
 
   for (int d = 0; d < NWIN; ++d) lv->ssd[(size_t)k * NWIN + d] = patch_ssd(L, R, w, ox, oy, P, u + kWinOffset[d]);
 
@@ -215,6 +230,8 @@ static void search_patch(const ref_level* lv, const bdis_ref_params* p, int k, i
   for (int d = 0; d < NWIN; ++d)
     if (d != 2 && s[2] > s[d]) centre_min = 0;
   lv->acc[k] = (centre_min && lv->rho[k] >= p->valid_ratio) ? 1.0 : 0.0;
+  mix(&lv->dhash, inb);
+  mix(&lv->dhash, (long long)lv->acc[k]);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -297,6 +314,7 @@ static int alloc_level(ref_level* lv, int w, int h, int P, int S) {
   size_t npx = (size_t)w * h;
   lv->w = w;
   lv->h = h;
+  lv->dhash = 1469598103934665603ULL;
   lv->nx = grid_count(w, P, S);
   lv->ny = grid_count(h, P, S);
   size_t np = (size_t)lv->nx * lv->ny;
@@ -452,6 +470,7 @@ static int run(const bdis_ref_params* p, const double* left0, const double* righ
       lv->post[k] = 1.0 / den;
       lv->pi[k] = gamma * lv->post[k] + lv->pipar[k];
       lv->sigk2[k] = (n == f && p->variance) ? patch_variance(s, tau, p->var_fit_thresh, sfail2) : NAN;
+      mix(&lv->dhash, lv->sigk2[k] == sfail2);
     }
 
     /* O12 / O14: fusion of the covering patches (Eq. 9, 10, 13, 18). */
@@ -477,6 +496,7 @@ static int run(const bdis_ref_params* p, const double* left0, const double* righ
           }
         }
         size_t idx = (size_t)y * lv->w + x;
+        mix(&lv->dhash, z > 0.0);
         if (z > 0.0) {
           lv->ubar[idx] = zu / z;
           lv->qmap[idx] = zq / zm;
@@ -639,6 +659,11 @@ long bdis_ref_trace_get(const bdis_ref_trace* t, int level, int what, double* ds
   if (n < cnt) return BDIS_REF_E_ARG;
   memcpy(dst, src, sizeof(double) * (size_t)cnt);
   return cnt;
+}
+
+uint64_t bdis_ref_trace_hash(const bdis_ref_trace* t, int level) {
+  if (!t || level < 0 || level >= t->levels) return 0;
+  return t->lv[level].dhash;
 }
 
 double bdis_ref_trace_scalar(const bdis_ref_trace* t, int level, int what) {

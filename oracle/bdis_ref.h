@@ -78,6 +78,9 @@ int bdis_ref_trace_dims(const bdis_ref_trace* t, int level, int* w, int* h, int*
 /* Copies `what` of `level` into dst (capacity n doubles); returns the count or < 0. */
 long bdis_ref_trace_get(const bdis_ref_trace* t, int level, int what, double* dst, long n);
 double bdis_ref_trace_scalar(const bdis_ref_trace* t, int level, int what);
+/* Hash of every discrete decision of a level (cells, resets, acceptances,
+ * variance-fit outcomes, holes): equal hashes mean equal branches. */
+uint64_t bdis_ref_trace_hash(const bdis_ref_trace* t, int level);
 void bdis_ref_trace_free(bdis_ref_trace* t);
 
 /* Patch-grid origins along an axis of length n; returns the count or < 0. */

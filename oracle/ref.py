@@ -91,6 +91,8 @@ def lib():
         L.bdis_ref_trace_scalar.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
         L.bdis_ref_trace_scalar.restype = ctypes.c_double
         L.bdis_ref_trace_free.argtypes = [ctypes.c_void_p]
+        L.bdis_ref_trace_hash.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.bdis_ref_trace_hash.restype = ctypes.c_uint64
         L.bdis_ref_grid.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_int), ctypes.c_int]
         L.bdis_ref_mask.argtypes = [ctypes.c_int, ctypes.c_double, dp]
@@ -139,6 +141,10 @@ class Trace:
 
     def scalar(self, level, what):
         return lib().bdis_ref_trace_scalar(self._h, level, SCALAR[what])
+
+    def decision_hash(self):
+        """Hashes of the discrete decisions of every level (tuple)."""
+        return tuple(int(lib().bdis_ref_trace_hash(self._h, n)) for n in range(self.levels))
 
 
 def compute(left, right, params, trace=False):
