@@ -61,7 +61,7 @@ typedef struct {
   int32_t iters;           /* K, 1..256: fixed inverse-compositional iterations (paper: 12)  */
   int32_t sigma_r_dynamic; /* 1: sigma_r from the spread of the level's residuals (Sec.III-B)*/
   int32_t variance;        /* 1: per-patch (Eq. 15-17) and per-pixel (Eq. 18) variance      */
-  int32_t float_pyramid;   /* 0 for the uint8 entry points (integer-rounded pyramid)        */
+  int32_t float_pyramid;   /* 0: uint8 entry points (integer pyramid); 1: float entry points */
   float sigma_s;           /* spatial sigma of the mixture kernel, level px (paper: 4)       */
   float sigma_r;           /* fixed sigma_r (dynamic == 0) or its scale alpha_r (dynamic)   */
   float valid_ratio;       /* gamma: least in-bounds fraction of an accepted patch (0.75)    */
@@ -90,7 +90,8 @@ bdis_status bdis_params_check(const bdis_params* p);
 
 /* Creates a context for images up to max_w x max_h and batches of up to
  * max_batch pairs, allocating its device workspace on the current device.
- * flags: 0 (reserved).  On failure *out is NULL.
+ * flags: 0, or BDIS_TRAIN for the differentiable float path (below).  On
+ * failure *out is NULL.
  * Errors: BDIS_E_ARG (null out/params, bad params, max_* < 1),
  *         BDIS_E_SIZE (max_w x max_h too small for the levels and patch),
  *         BDIS_E_NOMEM, BDIS_E_HIP. */
@@ -115,6 +116,54 @@ bdis_status bdis_compute(bdis_ctx* ctx, const uint8_t* left, const uint8_t* righ
  * pairs is a HOST array of n descriptors.  Outputs as bdis_compute.
  * Errors: as bdis_compute, plus BDIS_E_CAPACITY if n > max_batch. */
 bdis_status bdis_compute_batch(bdis_ctx* ctx, int n, const bdis_pair* pairs, void* stream);
+
+/* ---- differentiable (float) path --------------------------------------- */
+
+/* bdis_create flag: size the workspace for the float path and keep the state
+ * its backward pass needs (iterates of every patch, fusion sums, adjoints). */
+#define BDIS_TRAIN 1u
+
+/* One float pair of a batch (device pointers, pitch in elements). */
+typedef struct {
+  const float* left;
+  const float* right;
+  int32_t w, h, pitch;
+  int32_t levels;          /* 0 means params.levels                                       */
+  float* disparity;
+  float* variance;         /* or NULL */
+  float* confidence;       /* or NULL */
+} bdis_pair_f32;
+
+/* Output gradients in, image gradients out, for one pair (device pointers,
+ * dense W x H; grad_variance / grad_left / grad_right may be NULL). */
+typedef struct {
+  const float* grad_disparity;
+  const float* grad_variance;
+  float* grad_left;
+  float* grad_right;
+} bdis_pair_grad;
+
+/* Float images -> outputs, as bdis_compute, through the same method with an
+ * FP64 pyramid without rounding (params.float_pyramid must be 1; the context
+ * must have been created with BDIS_TRAIN).  The state of the call is kept for
+ * bdis_backward.  Errors: as bdis_compute, plus BDIS_E_STATE. */
+bdis_status bdis_compute_f32(bdis_ctx* ctx, const float* left, const float* right, int w, int h, int pitch,
+                             float* disparity, float* variance, float* confidence, void* stream);
+bdis_status bdis_compute_f32_batch(bdis_ctx* ctx, int n, const bdis_pair_f32* pairs, void* stream);
+
+/* Reverse mode through the last float-path call (the fixed-K unrolled search
+ * and the Bayesian fusion of every level, then the pyramid): given
+ * dL/d disparity (and dL/d variance), writes dL/d left and dL/d right (float,
+ * dense W x H) and, if grad_hyper is not NULL, the DEVICE array of 2 + L
+ * doubles [dL/d sigma_s, dL/d sigma_r (alpha_r when dynamic), dL/d omega_0 ..
+ * dL/d omega_{L-1}], summed over the pairs of the call.  Discrete decisions
+ * (unit cells, resets, acceptance, holes, variance-fit outcomes) carry no
+ * gradient.  Errors: BDIS_E_STATE without a preceding float-path call,
+ * BDIS_E_ARG for a batch size that differs from it. */
+bdis_status bdis_backward(bdis_ctx* ctx, const float* grad_disparity, const float* grad_variance,
+                          float* grad_left, float* grad_right, double* grad_hyper, void* stream);
+bdis_status bdis_backward_batch(bdis_ctx* ctx, int n, const bdis_pair_grad* grads, double* grad_hyper,
+                                void* stream);
 
 /* Debug access to the intermediates of the last single-pair compute (the
  * call synchronises `stream`).  `what` selects the array (BDIS_DBG_*), bytes
@@ -141,11 +190,19 @@ bdis_status bdis_debug_dump(bdis_ctx* ctx, int level, int what, void* host_dst, 
 /* Per-kernel timing with HIP events recorded on the compute stream around
  * every launch (for measurement; adds two event records per launch).
  * kernel: 0 pyramid, 1 patch search, 2 patch probability, 3 fusion,
- * 4 the per-pair sigma_r reduction.
+ * 4 the per-pair sigma_r reduction, 5 the backward pass (all its launches).
  * bdis_timing_enable(ctx, 1) clears the totals and starts recording;
  * bdis_timing_read synchronises the recorded events and returns the summed
  * GPU time (ms) and the launch count of one kernel since enabling. */
-enum { BDIS_K_PYRAMID = 0, BDIS_K_SEARCH = 1, BDIS_K_PROB = 2, BDIS_K_FUSE = 3, BDIS_K_REDUCE = 4, BDIS_K_COUNT = 5 };
+enum {
+  BDIS_K_PYRAMID = 0,
+  BDIS_K_SEARCH = 1,
+  BDIS_K_PROB = 2,
+  BDIS_K_FUSE = 3,
+  BDIS_K_REDUCE = 4,
+  BDIS_K_BACKWARD = 5,
+  BDIS_K_COUNT = 6
+};
 bdis_status bdis_timing_enable(bdis_ctx* ctx, int enable);
 bdis_status bdis_timing_read(bdis_ctx* ctx, int kernel, double* total_ms, long* launches);
 

@@ -46,6 +46,21 @@ class Pair(ctypes.Structure):
                 ("confidence", ctypes.c_void_p)]
 
 
+class PairF32(ctypes.Structure):
+    _fields_ = [("left", ctypes.c_void_p), ("right", ctypes.c_void_p), ("w", ctypes.c_int32),
+                ("h", ctypes.c_int32), ("pitch", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("disparity", ctypes.c_void_p), ("variance", ctypes.c_void_p),
+                ("confidence", ctypes.c_void_p)]
+
+
+class PairGrad(ctypes.Structure):
+    _fields_ = [("grad_disparity", ctypes.c_void_p), ("grad_variance", ctypes.c_void_p),
+                ("grad_left", ctypes.c_void_p), ("grad_right", ctypes.c_void_p)]
+
+
+TRAIN = 1
+
+
 class BdisError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
@@ -77,11 +92,16 @@ def lib():
         L.bdis_last_error.argtypes = [vp]
         L.bdis_last_error.restype = ctypes.c_char_p
         L.bdis_version.restype = ctypes.c_char_p
+        L.bdis_compute_f32.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp, vp]
+        L.bdis_compute_f32_batch.argtypes = [vp, i32, ctypes.POINTER(PairF32), vp]
+        L.bdis_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.bdis_backward_batch.argtypes = [vp, i32, ctypes.POINTER(PairGrad), vp, vp]
         L.bdis_timing_enable.argtypes = [vp, i32]
         L.bdis_timing_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long)]
         for name in ("bdis_params_default", "bdis_params_check", "bdis_create", "bdis_set_params",
                      "bdis_compute", "bdis_compute_batch", "bdis_debug_dump", "bdis_level_dims",
-                     "bdis_timing_enable", "bdis_timing_read"):
+                     "bdis_timing_enable", "bdis_timing_read", "bdis_compute_f32", "bdis_compute_f32_batch",
+                     "bdis_backward", "bdis_backward_batch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -140,10 +160,12 @@ def _image_arg(t, name):
 class Context:
     """Owns a ``bdis_ctx`` (device workspace sized for max_w x max_h x max_batch)."""
 
-    def __init__(self, p, max_w, max_h, max_batch=1):
+    def __init__(self, p, max_w, max_h, max_batch=1, train=False):
         self._h = ctypes.c_void_p()
         self.params = p
-        st = lib().bdis_create(ctypes.byref(self._h), ctypes.byref(p), max_w, max_h, max_batch, 0)
+        self.train = train
+        st = lib().bdis_create(ctypes.byref(self._h), ctypes.byref(p), max_w, max_h, max_batch,
+                               TRAIN if train else 0)
         if st:
             raise BdisError(st, lib().bdis_last_error(None).decode())
         self.max_w, self.max_h, self.max_batch = max_w, max_h, max_batch
@@ -241,7 +263,7 @@ class Context:
             raise self._err(st)
         return results
 
-    KERNELS = ("pyramid", "search", "prob", "fuse", "reduce")
+    KERNELS = ("pyramid", "search", "prob", "fuse", "reduce", "backward")
 
     def timing(self, enable):
         """Start (clearing totals) or stop per-kernel HIP-event timing."""
@@ -259,6 +281,56 @@ class Context:
                 raise self._err(st)
             out[name] = (ms.value, n.value)
         return out
+
+    def compute_f32(self, lefts, rights, *, variance=None, confidence=True, stream=None):
+        """Float path on a batch: lefts/rights are (B, H, W) or (H, W) float32 CUDA tensors
+        (contiguous rows).  Returns dict(disp, var, conf) shaped like the input."""
+        import torch
+        single = lefts.dim() == 2
+        L = lefts[None] if single else lefts
+        R = rights[None] if single else rights
+        if L.dtype != torch.float32 or R.dtype != torch.float32 or not L.is_cuda or L.shape != R.shape:
+            raise TypeError("float path needs equal float32 CUDA tensors")
+        if L.stride(-1) != 1 or R.stride(-1) != 1 or L.stride(-2) != R.stride(-2):
+            raise ValueError("rows must be contiguous with equal pitch")
+        if variance is None:
+            variance = bool(self.params.variance)
+        B, h, w = L.shape
+        disp = torch.empty((B, h, w), dtype=torch.float32, device=L.device)
+        var = torch.empty((B, h, w), dtype=torch.float32, device=L.device) if variance else None
+        conf = torch.empty((B, h, w), dtype=torch.float32, device=L.device) if confidence else None
+        arr = (PairF32 * B)()
+        for b in range(B):
+            arr[b] = PairF32(L[b].data_ptr(), R[b].data_ptr(), w, h, L.stride(-2), 0, disp[b].data_ptr(),
+                             var[b].data_ptr() if var is not None else None,
+                             conf[b].data_ptr() if conf is not None else None)
+        st = lib().bdis_compute_f32_batch(self._h, B, arr, _stream_ptr(stream))
+        if st:
+            raise self._err(st)
+        self._last_f32 = (B, h, w, L.device)
+        if single:
+            return dict(disp=disp[0], var=var[0] if var is not None else None,
+                        conf=conf[0] if conf is not None else None)
+        return dict(disp=disp, var=var, conf=conf)
+
+    def backward(self, grad_disp, grad_var=None, stream=None):
+        """Reverse mode through the last compute_f32: returns (grad_left, grad_right, grad_hyper)
+        with grad_hyper = [sigma_s, sigma_r (alpha_r when dynamic), omega_0 .. omega_{L-1}]."""
+        import torch
+        B, h, w, dev = self._last_f32
+        gd = grad_disp.reshape(B, h, w).to(torch.float32).contiguous()
+        gv = grad_var.reshape(B, h, w).to(torch.float32).contiguous() if grad_var is not None else None
+        gl = torch.empty((B, h, w), dtype=torch.float32, device=dev)
+        gr = torch.empty((B, h, w), dtype=torch.float32, device=dev)
+        gh = torch.zeros(2 + self.params.levels, dtype=torch.float64, device=dev)
+        arr = (PairGrad * B)()
+        for b in range(B):
+            arr[b] = PairGrad(gd[b].data_ptr(), gv[b].data_ptr() if gv is not None else None,
+                              gl[b].data_ptr(), gr[b].data_ptr())
+        st = lib().bdis_backward_batch(self._h, B, arr, gh.data_ptr(), _stream_ptr(stream))
+        if st:
+            raise self._err(st)
+        return gl, gr, gh
 
     def debug(self, level, what, stream=None):
         """Intermediate array of the last single-pair compute, copied to the host."""
@@ -298,3 +370,60 @@ def compute(left, right, p, **kw):
         import torch
         torch.cuda.current_stream().synchronize()
         return res
+
+
+def _set_hyper(ctx, sigma_s, sigma_r, omega):
+    p = ctx.params
+    q = params(**{k: v for k, v in p.as_dict().items()})
+    q.sigma_s = float(sigma_s)
+    q.sigma_r = float(sigma_r)
+    lw = list(q.level_weight)
+    for n, v in enumerate(omega):
+        lw[n] = float(v)
+    q.level_weight = (ctypes.c_float * 8)(*lw)
+    ctx.set_params(q)
+
+
+def _autograd_function():
+    import torch
+
+    class BDISFunction(torch.autograd.Function):
+        """Disparity (and variance) of float stereo pairs on the GPU with a hand-written
+        backward: gradients with respect to both images and the hyperparameters
+        sigma_s, sigma_r (alpha_r in the dynamic mode) and the level weights omega."""
+
+        @staticmethod
+        def forward(fctx, left, right, sigma_s, sigma_r, omega, bctx):
+            _set_hyper(bctx, sigma_s.item(), sigma_r.item(), omega.detach().cpu().tolist())
+            out = bctx.compute_f32(left.detach().contiguous(), right.detach().contiguous())
+            fctx.bctx = bctx
+            fctx.shapes = (left.shape, omega.shape, sigma_s.dtype, omega.dtype)
+            var = out["var"] if out["var"] is not None else torch.zeros_like(out["disp"])
+            fctx.has_var = out["var"] is not None
+            return out["disp"], var
+
+        @staticmethod
+        def backward(fctx, g_disp, g_var):
+            import torch
+            g_disp = torch.nan_to_num(g_disp) if g_disp is not None else None
+            g_var = torch.nan_to_num(g_var) if (g_var is not None and fctx.has_var) else None
+            if g_disp is None:
+                g_disp = torch.zeros(fctx.shapes[0], dtype=torch.float32, device=g_var.device)
+            gl, gr, gh = fctx.bctx.backward(g_disp, g_var)
+            shape, oshape, sdt, odt = fctx.shapes
+            L = oshape[0]
+            return (gl.reshape(shape), gr.reshape(shape), gh[0].to(sdt), gh[1].to(sdt), gh[2:2 + L].to(odt),
+                    None)
+
+    return BDISFunction
+
+
+_BDISFunction = None
+
+
+def bdis_function():
+    """The torch.autograd.Function of the differentiable path (created on first use)."""
+    global _BDISFunction
+    if _BDISFunction is None:
+        _BDISFunction = _autograd_function()
+    return _BDISFunction

@@ -80,7 +80,7 @@ struct PairLevel {
   // sigma_r reduction of this pair and level: per-workgroup partials
   double* part_sum;
   int* part_cnt;
-  double* scal;    // [sigma_r^2, tau]
+  double* scal;    // [sigma_r^2, tau, pooled residual, accepted count, d loss / d tau, SSD(0) adjoint share]
   // fusion outputs: level maps above the finest, user outputs at the finest
   double* ubar;
   double* qmap;
@@ -90,6 +90,45 @@ struct PairLevel {
   // workgroup offsets of this pair in each flattened launch
   int pyr0, search0, prob0, fuse0;
   int search_nbx;  // search workgroups per patch row
+
+  // ---- float (differentiable) path: FP64 level images, pitch in elements
+  const float* src32L;   // level 0 only: the caller's float images
+  const float* src32R;
+  int src32pitch;
+  const double* srcdL;   // level n-1 (n >= 1)
+  const double* srcdR;
+  int srcdpitch;
+  double* Ld;            // this level
+  double* Rd;
+  int dpitch;
+  // state kept for the backward pass (training contexts)
+  double* uhist;         // per patch: u_0 .. u_K of the iterations (K + 1 values)
+  int* reset;            // per patch: 1 if the search threshold reset u to u_0
+  double* zmap;          // per pixel: sum W (0 marks a hole)
+  double* smmap;         // per pixel: sum M over accepted covering patches
+  double* vmap;          // per pixel (finest level): variance
+  double* ubar_keep;     // finest level: fused displacement and confidence
+  double* qmap_keep;
+  // adjoints (training contexts)
+  double* Lbar;          // d loss / d level image
+  double* Rbar;
+  double* srcLbar;       // d loss / d level n-1 images (n >= 1)
+  double* srcRbar;
+  double* Gbar;          // d loss / d template gradient (Sobel / 8) image
+  double* ubar_adj;      // d loss / d fused maps of this level
+  double* qmap_adj;
+  double* par_ubar_adj;  // d loss / d parent maps (nullptr at the coarsest level)
+  double* par_qmap_adj;
+  double* vmap_adj;      // finest level: d loss / d variance
+  double* pu_adj;        // per patch: d loss / d u, d pi, d sigma_k^2
+  double* ppi_adj;
+  double* psig_adj;
+  double* pssd_adj;      // per patch: d loss / d SSD(d), 5 values
+  const float* grad_disp;  // finest level: caller's d loss / d disparity, variance
+  const float* grad_var;
+  float* grad_left;        // level 0: caller's image gradients (dense W x H)
+  float* grad_right;
+  double* hyper_adj;       // [sigma_s, sigma_r or alpha_r, omega_0 .. omega_7] (atomically summed)
 };
 
 // Parameters shared by all pairs of a launch.
@@ -113,6 +152,10 @@ constexpr int kPyrTx = 64, kPyrTy = 4;      // pyramid: 64 x 4 output pixels per
 constexpr int kProbThreads = 256;           // probability: patches per workgroup
 constexpr int kFuseTx = 64, kFuseTy = 4;    // fusion: 64 x 4 pixels per workgroup
 
+// Workgroups of the float-path search (fixed size) and of per-pixel adjoint launches.
+constexpr int kSearchF64Threads = 256;
+constexpr int kPixThreads = 256;
+
 // Search workgroup sizes the tuner may pick (threads; patches = threads / G).
 constexpr int kNumSearchOptions = 5;
 constexpr int kSearchThreadOptions[kNumSearchOptions] = {64, 128, 256, 512, 1024};
@@ -130,6 +173,15 @@ hipError_t launch_prob(const PairLevel* tab, int npairs, int nblocks, const Leve
                        hipStream_t s);
 hipError_t launch_fuse(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,
                        hipStream_t s);
+
+// Float (differentiable) path: FP64 pyramid and search, and the adjoint kernels.
+hipError_t launch_pyramid_f64(const PairLevel* tab, int npairs, int nblocks, int level, hipStream_t s);
+hipError_t launch_search_f64(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,
+                             hipStream_t s);
+hipError_t launch_backward_level(const PairLevel* tab, int npairs, const int* blocks, const LevelParams& lp,
+                                 hipStream_t s);
+hipError_t launch_pyramid_adj(const PairLevel* tab, int npairs, int nblocks, hipStream_t s);
+hipError_t launch_grad_out(const PairLevel* tab, int npairs, int nblocks, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // device helpers
@@ -190,6 +242,26 @@ BDIS_DEV void st4(D4* p, const D4& v) {
   q[2] = v.z;
   q[3] = v.w;
 }
+
+// All-reduce (sum) of a double over an aligned group of G lanes (two 32-bit DPP moves per step).
+template <int Ctrl>
+BDIS_DEV double dpp_move_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), Ctrl, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), Ctrl, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int G>
+BDIS_DEV double group_sum_d(double v) {
+  v += dpp_move_d<0xB1>(v);
+  v += dpp_move_d<0x4E>(v);
+  v += dpp_move_d<0x141>(v);
+  if constexpr (G == 16) v += dpp_move_d<0x140>(v);
+  return v;
+}
+
+// Hardware FP64 atomic add on global memory (accumulation of adjoints).
+BDIS_DEV void atomic_add_d(double* p, double v) { unsafeAtomicAdd(p, v); }
 
 // Reflect-101 index for |overshoot| < n (the only case the kernels produce).
 BDIS_DEV int reflect101(int i, int n) {

@@ -1,0 +1,524 @@
+// Adjoint (reverse-mode) kernels of the float path: the backward pass of the
+// fixed-K unrolled inverse-compositional search and of the Bayesian fusion,
+// level by level from the finest to the coarsest, then the transposed
+// pyramid.  Discrete decisions (unit cells, the search-threshold reset,
+// acceptance, holes, variance-fit outcomes) are piecewise constant and carry
+// no gradient.  All sums are FP64; scatters into images and parent maps use
+// hardware FP64 atomics, so gradients are reproducible to rounding only.
+//
+// Forward relations reversed here (per level n, patch k, pixel x):
+//   fusion   W_k = M(x - o_k) pi_k, Z = sum W, SM = sum M,
+//            Ubar = sum W u / Z, Q = Z / SM, V = sum W^2 sigma_k^2 / Z^2   (Eq. 9-13, 18)
+//   holes    Ubar = 2 B(Ubar^(n+1))(x/2), Q = B(Q^(n+1))(x/2)
+//   patch    pi = Gamma_n post + B(Q^(n+1))(c/2), post = 1 / sum_d exp(-(SSD_d - SSD_0) / tau)
+//            (Eq. 5-6, 11-12); sigma_k^2 = tau / (2 kappa) (Eq. 15-17)
+//   level    tau = 2 sigma_r^2 s^2, sigma_r^2 = alpha^2 pooled SSD_0 / (N_acc P^2)
+//   search   u_0 = 2 B(Ubar^(n+1))(c/2), u_{t+1} = u_t - sum J (I_w(u_t) - T) / H,
+//            J = g - mean g, H = sum J^2, g = Sobel_x(L) / 8, T = L on the patch
+//   window   SSD_d = sum (e - mean e)^2, e = I_w(u + d) - T
+//   pyramid  L_n = B5 * L_{n-1} (even samples, reflect-101)
+#include "bdis_internal.h"
+
+namespace bdis {
+
+namespace {
+
+constexpr double kXd[4] = {1.0, 0.25, 0.25, 1.0};  // d^2 of the offsets -1, -1/2, +1/2, +1
+
+// Scatter v * bilinear weights of (x, y) onto a w x h map (indices clamped).
+BDIS_DEV void bilinear_adj(double* m, int w, int h, double x, double y, double v) {
+  const double fx0 = floor(x), fy0 = floor(y);
+  const double ax = x - fx0, ay = y - fy0;
+  const int ix = (int)fx0, iy = (int)fy0;
+  const int x0 = clampi(ix, 0, w - 1), x1 = clampi(ix + 1, 0, w - 1);
+  const int y0 = clampi(iy, 0, h - 1), y1 = clampi(iy + 1, 0, h - 1);
+  atomic_add_d(m + (size_t)y0 * w + x0, v * (1.0 - ax) * (1.0 - ay));
+  atomic_add_d(m + (size_t)y0 * w + x1, v * ax * (1.0 - ay));
+  atomic_add_d(m + (size_t)y1 * w + x0, v * (1.0 - ax) * ay);
+  atomic_add_d(m + (size_t)y1 * w + x1, v * ax * ay);
+}
+
+// Block-wide sum of a double (256 threads) into *dst with one atomic.
+BDIS_DEV void block_atomic_sum(double v, double* dst, double* s_buf) {
+  const int tid = threadIdx.x;
+  s_buf[tid] = v;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (tid < off) s_buf[tid] += s_buf[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0 && s_buf[0] != 0.0) atomic_add_d(dst, s_buf[0]);
+  __syncthreads();
+}
+
+// Per pair: clear this level's d loss / d tau accumulator.
+__global__ void k_adj_init(const PairLevel* tab, int npairs) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= npairs) return;
+  gbl(tab[e].scal)[4] = 0.0;
+  gbl(tab[e].scal)[5] = 0.0;
+  gbl(tab[e].scal)[6] = 0.0;
+}
+
+// Finest level, per pixel: d loss / d Ubar = -d loss / d disparity on output
+// pixels (d = -Ubar), d loss / d variance likewise; 0 elsewhere.
+__global__ __launch_bounds__(kPixThreads) void k_seed(const PairLevel* tab, int npairs, LevelParams lp) {
+  const PairLevel& a = tab[find_pair<0>(tab, npairs, (int)blockIdx.x)];
+  const int idx = ((int)blockIdx.x - a.pyr0) * kPixThreads + (int)threadIdx.x;
+  if (idx >= a.g.w * a.g.h) return;
+  const double z = gbl(a.zmap)[idx];
+  bool ok = z > 0.0;
+  if (ok && lp.prob_thresh > 0.0f && gbl(a.qmap_keep)[idx] < (double)lp.prob_thresh) ok = false;
+  gbl(a.ubar_adj)[idx] = (ok && a.grad_disp) ? -(double)gbl(a.grad_disp)[idx] : 0.0;
+  gbl(a.qmap_adj)[idx] = 0.0;
+  if (a.vmap_adj) gbl(a.vmap_adj)[idx] = (ok && a.grad_var && lp.variance) ? (double)gbl(a.grad_var)[idx] : 0.0;
+}
+
+// Per patch (one lane): gather the fusion adjoint over the patch's pixels.
+__global__ __launch_bounds__(kPixThreads) void k_fuse_adj(const PairLevel* tab, int npairs, LevelParams lp) {
+  __shared__ double s_m1[kMaxPatch], s_dm1[kMaxPatch];
+  __shared__ double s_buf[kPixThreads];
+  const PairLevel& a = tab[find_pair<2>(tab, npairs, (int)blockIdx.x)];
+  const int tid = threadIdx.x;
+  const int P = lp.P, S = lp.S;
+  if (tid < P) {
+    // m1(t) = sum_c exp(-(t - c)^2 / (2 s^2)) and its derivative in s
+    const double sg = (double)lp.sigma_s;
+    double m = 0.0, dm = 0.0;
+    for (int c = 0; c < P; ++c) {
+      const double d2 = (double)((tid - c) * (tid - c));
+      const double e = exp(-d2 / (2.0 * sg * sg));
+      m += e;
+      dm += e * d2 / (sg * sg * sg);
+    }
+    s_m1[tid] = m;
+    s_dm1[tid] = dm;
+  }
+  __syncthreads();
+  const int k = ((int)blockIdx.x - a.prob0) * kPixThreads + tid;
+  double ss_adj = 0.0;
+  const bool finest = lp.level == lp.finest;
+  if (k < a.g.nx * a.g.ny) {
+    const D4 d = ld4(a.pa.dens + k);
+    if (d.y >= 0.0) {
+      const int i = k % a.g.nx, j = k / a.g.nx;
+      const int ox = grid_origin(i, a.g.w, P, S), oy = grid_origin(j, a.g.h, P, S);
+      const auto ub = gbl(finest ? a.ubar_keep : a.ubar);
+      const auto qm = gbl(finest ? a.qmap_keep : a.qmap);
+      const auto zm = gbl(a.zmap);
+      const auto sm = gbl(a.smmap);
+      const auto gu = gbl(a.ubar_adj);
+      const auto gq = gbl(a.qmap_adj);
+      const bool vt = finest && lp.variance && a.vmap_adj != nullptr;
+      const double u = d.x, pi = d.y, s2 = vt ? d.z : 0.0;
+      double u_adj = 0.0, pi_adj = 0.0, sig_adj = 0.0;
+      for (int b = 0; b < P; ++b) {
+        const size_t row = (size_t)(oy + b) * a.g.w + ox;
+        for (int c = 0; c < P; ++c) {
+          const size_t idx = row + c;
+          const double Z = zm[idx];
+          if (!(Z > 0.0)) continue;
+          const double m = s_m1[b] * s_m1[c];
+          const double W = m * pi;
+          const double SM = sm[idx], U = ub[idx], Qx = qm[idx];
+          const double gU = gu[idx], gQ = gq[idx];
+          double mbar = gU * pi * (u - U) / Z + gQ * (pi - Qx) / SM;
+          u_adj += gU * W / Z;
+          pi_adj += gU * m * (u - U) / Z + gQ * m / SM;
+          if (vt) {
+            const double gV = gbl(a.vmap_adj)[idx], V = gbl(a.vmap)[idx];
+            const double t = 2.0 * W * s2 / (Z * Z) - 2.0 * V / Z;
+            pi_adj += gV * m * t;
+            sig_adj += gV * W * W / (Z * Z);
+            mbar += gV * pi * t;
+          }
+          ss_adj += mbar * (s_dm1[b] * s_m1[c] + s_m1[b] * s_dm1[c]);
+        }
+      }
+      gbl(a.pu_adj)[k] = u_adj;
+      gbl(a.ppi_adj)[k] = pi_adj;
+      gbl(a.psig_adj)[k] = sig_adj;
+    }
+  }
+  block_atomic_sum(ss_adj, a.hyper_adj + 0, s_buf);
+}
+
+// Per pixel above the finest level: holes took the parent estimate.
+__global__ __launch_bounds__(kPixThreads) void k_hole_adj(const PairLevel* tab, int npairs) {
+  const PairLevel& a = tab[find_pair<0>(tab, npairs, (int)blockIdx.x)];
+  const int idx = ((int)blockIdx.x - a.pyr0) * kPixThreads + (int)threadIdx.x;
+  if (idx >= a.g.w * a.g.h || !a.par_ubar_adj) return;
+  if (gbl(a.zmap)[idx] > 0.0) return;
+  const int y = idx / a.g.w, x = idx - y * a.g.w;
+  const double gU = gbl(a.ubar_adj)[idx], gQ = gbl(a.qmap_adj)[idx];
+  if (gU != 0.0) bilinear_adj(a.par_ubar_adj, a.pw, a.ph, 0.5 * x, 0.5 * y, 2.0 * gU);
+  if (gQ != 0.0) bilinear_adj(a.par_qmap_adj, a.pw, a.ph, 0.5 * x, 0.5 * y, gQ);
+}
+
+// Per patch: posterior, propagation and patch-variance adjoints -> window SSDs,
+// tau, level weights and the parent confidence.
+__global__ __launch_bounds__(kPixThreads) void k_prob_adj(const PairLevel* tab, int npairs, LevelParams lp) {
+  __shared__ double s_buf[kPixThreads];
+  const PairLevel& a = tab[find_pair<2>(tab, npairs, (int)blockIdx.x)];
+  const int tid = threadIdx.x;
+  const int P = lp.P, S = lp.S;
+  const int k = ((int)blockIdx.x - a.prob0) * kPixThreads + tid;
+  double wsum = 0.0;
+  for (int n = lp.finest; n < a.levels; ++n) wsum += (double)lp.omega[n];
+  const double gamma = (double)lp.omega[lp.level] / wsum;
+  double gam_adj = 0.0, tau_adj = 0.0;
+  if (k < a.g.nx * a.g.ny && gbl(a.pa.acc)[k]) {
+    const double pi_adj = gbl(a.ppi_adj)[k];
+    const bool vt = lp.variance && lp.level == lp.finest;
+    const double sig_adj = vt ? gbl(a.psig_adj)[k] : 0.0;
+    const D4 dd = ld4(a.pa.dssd + k);
+    const double dl[4] = {dd.x, dd.y, dd.z, dd.w};
+    const double tau = gbl(a.scal)[1];
+    double e[4], se = 1.0;
+    for (int t = 0; t < 4; ++t) {
+      e[t] = exp(-dl[t] / tau);
+      se += e[t];
+    }
+    const double post = 1.0 / se;
+    const double post_adj = gamma * pi_adj;
+    gam_adj = pi_adj * post;
+    double dl_adj[4];
+    double sedl = 0.0;
+    for (int t = 0; t < 4; ++t) {
+      dl_adj[t] = post_adj * post * post * e[t] / tau;
+      sedl += e[t] * dl[t];
+    }
+    tau_adj = -post_adj * post * post * sedl / (tau * tau);
+    if (vt && sig_adj != 0.0) {
+      // the fit passed and was not capped iff sigma_k^2 = tau / (2 kappa) < sigma_fail^2
+      const double sfail = lp.var_fail_sigma > 0.0f ? (double)lp.var_fail_sigma : (double)P;
+      const double y[5] = {dl[0], dl[1], 0.0, dl[2], dl[3]};
+      const double x[5] = {1.0, 0.25, 0.0, 0.25, 1.0};
+      const double ym = (y[0] + y[1] + y[2] + y[3] + y[4]) / 5.0;
+      double sxy = 0.0;
+      for (int t = 0; t < 5; ++t) sxy += (x[t] - 0.5) * y[t];
+      const double kappa = sxy / 0.875;
+      bool pass = kappa > 0.0;
+      if (pass) {
+        double mse = 0.0;
+        for (int t = 0; t < 5; ++t) {
+          const double res = (y[t] - (ym + kappa * (x[t] - 0.5))) / tau;
+          mse += res * res;
+        }
+        pass = mse / 5.0 <= (double)lp.var_fit_thresh && tau / (2.0 * kappa) < sfail * sfail;
+      }
+      if (pass) {
+        tau_adj += sig_adj / (2.0 * kappa);
+        const double kappa_adj = -sig_adj * tau / (2.0 * kappa * kappa);
+        for (int t = 0; t < 4; ++t) dl_adj[t] += kappa_adj * (kXd[t] - 0.5) / 0.875;
+      }
+    }
+    auto sa = gbl(a.pssd_adj) + (size_t)k * kWin;
+    sa[0] = dl_adj[0];
+    sa[1] = dl_adj[1];
+    sa[2] = -(dl_adj[0] + dl_adj[1] + dl_adj[2] + dl_adj[3]);
+    sa[3] = dl_adj[2];
+    sa[4] = dl_adj[3];
+    if (a.par_qmap_adj && pi_adj != 0.0) {
+      const int i = k % a.g.nx, j = k / a.g.nx;
+      const double cx = 0.5 * ((double)grid_origin(i, a.g.w, P, S) + 0.5 * (double)(P - 1));
+      const double cy = 0.5 * ((double)grid_origin(j, a.g.h, P, S) + 0.5 * (double)(P - 1));
+      bilinear_adj(a.par_qmap_adj, a.pw, a.ph, cx, cy, pi_adj);
+    }
+  } else if (k < a.g.nx * a.g.ny) {
+    auto sa = gbl(a.pssd_adj) + (size_t)k * kWin;
+    for (int t = 0; t < kWin; ++t) sa[t] = 0.0;
+  }
+  block_atomic_sum(tau_adj, a.scal + 4, s_buf);
+  // d Gamma_n / d omega_m = (delta_nm - Gamma_n) / sum omega
+  block_atomic_sum(gam_adj, a.scal + 6, s_buf);
+}
+
+// Per pair: tau -> sigma_r (or alpha_r) and, in the dynamic mode, the share of
+// d loss / d tau that every accepted SSD(0) of the level receives; level weights.
+__global__ void k_tau_adj(const PairLevel* tab, int npairs, LevelParams lp) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= npairs) return;
+  const PairLevel& a = tab[e];
+  auto sc = gbl(a.scal);
+  const double tau_adj = sc[4];
+  const double al = (double)lp.sigma_r;
+  const double w2 = 2.0 * kWin * kWin;  // tau = w2 * sigma_r^2
+  double shr = 0.0;
+  if (lp.sigma_r_dynamic) {
+    const double pooled = sc[2], nacc = sc[3];
+    if (pooled > kEpsSigma) {
+      atomic_add_d(a.hyper_adj + 1, tau_adj * w2 * 2.0 * al * pooled);
+      shr = tau_adj * w2 * al * al / (nacc * (double)(lp.P * lp.P));
+    } else {
+      atomic_add_d(a.hyper_adj + 1, tau_adj * w2 * 2.0 * al * kEpsSigma);
+    }
+  } else {
+    atomic_add_d(a.hyper_adj + 1, tau_adj * w2 * 2.0 * al);
+  }
+  sc[5] = shr;
+  // level weights: Gamma_n = omega_n / sum_{m=f}^{L-1} omega_m
+  const double gam_adj = sc[6];
+  double wsum = 0.0;
+  for (int n = lp.finest; n < a.levels; ++n) wsum += (double)lp.omega[n];
+  const double gamma = (double)lp.omega[lp.level] / wsum;
+  for (int m = lp.finest; m < a.levels; ++m)
+    atomic_add_d(a.hyper_adj + 2 + m, gam_adj * ((m == lp.level ? 1.0 : 0.0) - gamma) / wsum);
+  sc[6] = 0.0;
+}
+
+// Per patch (lane per patch row): window and search adjoints, recomputing the
+// warps from the saved iterates; scatters into the level images, the template
+// gradient image and the parent displacement map.
+template <int P>
+__global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLevel* tab, int npairs, LevelParams lp) {
+  constexpr int G = group_lanes(P);
+  constexpr int NPB = kSearchF64Threads / G;
+  constexpr int N = P * P;
+  const PairLevel& a = tab[find_pair<1>(tab, npairs, (int)blockIdx.x)];
+  const int blk = (int)blockIdx.x - a.search0;
+  const int tid = threadIdx.x;
+  const int q = tid / G, r = tid % G;
+  const int W = a.g.w, Hh = a.g.h, S = lp.S;
+  const int j = blk / a.search_nbx;
+  const int i0 = (blk % a.search_nbx) * NPB;
+  const bool live = (i0 + q) < a.g.nx;
+  const int i = live ? i0 + q : a.g.nx - 1;
+  const int k = j * a.g.nx + i;
+  // whole groups skip rejected or idle patches (uniform within the group)
+  if (!live || !gbl(a.pa.acc)[k]) return;
+  const int ox = grid_origin(i, W, P, S), oy = grid_origin(j, Hh, P, S);
+  const bool row_live = r < P;
+  const int rr = row_live ? r : P - 1;
+  const auto Lg = gbl(a.Ld);
+  const auto Rg = gbl(a.Rd);
+  const int dp = a.dpitch;
+  const int yr = oy + rr;
+  const size_t r0 = (size_t)reflect101(yr - 1, Hh) * dp, r1 = (size_t)yr * dp,
+               r2 = (size_t)reflect101(yr + 1, Hh) * dp;
+  double T[P], J[P];
+  double sg = 0.0;
+#pragma unroll
+  for (int c = 0; c < P; ++c) {
+    const int x = ox + c, xm = reflect101(x - 1, W), xp = reflect101(x + 1, W);
+    T[c] = Lg[r1 + x];
+    J[c] = ((Lg[r0 + xp] - Lg[r0 + xm]) + 2.0 * (Lg[r1 + xp] - Lg[r1 + xm]) + (Lg[r2 + xp] - Lg[r2 + xm])) / 8.0;
+    sg += J[c];
+  }
+  const double gbar = group_sum_d<G>(row_live ? sg : 0.0) / (double)N;
+  double hrow = 0.0;
+#pragma unroll
+  for (int c = 0; c < P; ++c) {
+    J[c] -= gbar;
+    hrow += J[c] * J[c];
+  }
+  const double H = group_sum_d<G>(row_live ? hrow : 0.0);
+
+  double Tb[P], Jb[P];
+#pragma unroll
+  for (int c = 0; c < P; ++c) Tb[c] = Jb[c] = 0.0;
+  const auto Rrow = Rg + (size_t)(oy + rr) * dp;
+  double* Rbar_row = a.Rbar + (size_t)(oy + rr) * dp;
+
+  // ---- window: SSD_d = sum (e - mean e)^2 at u + d
+  const double u = gbl(a.pa.u)[k];
+  double ub = gbl(a.pu_adj)[k];
+  const auto sa = gbl(a.pssd_adj) + (size_t)k * kWin;
+  for (int t = 0; t < kWin; ++t) {
+    double sbar = sa[t];
+    if (t == 2) sbar += gbl(a.scal)[5];  // share of d loss / d tau through sigma_r
+    if (sbar == 0.0) continue;
+    const double v = u + 0.5 * (double)(t - 2);  // offsets -1, -1/2, 0, 1/2, 1
+    const double fm = floor(v);
+    const int m = (int)fm;
+    const double f = v - fm;
+    double ev[P], se = 0.0;
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      const double ra = Rrow[clampi(ox + c + m, 0, W - 1)], rb = Rrow[clampi(ox + c + m + 1, 0, W - 1)];
+      ev[c] = (1.0 - f) * ra + f * rb - T[c];
+      se += ev[c];
+    }
+    const double emean = group_sum_d<G>(row_live ? se : 0.0) / (double)N;
+    double urow = 0.0;
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      const int xa = clampi(ox + c + m, 0, W - 1), xb = clampi(ox + c + m + 1, 0, W - 1);
+      const double g2 = 2.0 * (ev[c] - emean) * sbar;
+      urow += g2 * (Rrow[xb] - Rrow[xa]);
+      Tb[c] -= g2;
+      if (row_live) {
+        atomic_add_d(Rbar_row + xa, g2 * (1.0 - f));
+        atomic_add_d(Rbar_row + xb, g2 * f);
+      }
+    }
+    ub += group_sum_d<G>(row_live ? urow : 0.0);
+  }
+
+  // ---- reset, then the K iterations in reverse
+  double u0_adj = ub;
+  const bool reset = gbl(a.reset)[k] != 0;
+  if (!reset && H >= kEpsH) {
+    const auto uh = gbl(a.uhist) + (size_t)k * (lp.K + 1);
+    for (int t = lp.K - 1; t >= 0; --t) {
+      const double ut = uh[t];
+      const double fm = floor(ut);
+      const int m = (int)fm;
+      const double f = ut - fm;
+      double iw[P], br = 0.0, bpr = 0.0;
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        const double ra = Rrow[clampi(ox + c + m, 0, W - 1)], rb = Rrow[clampi(ox + c + m + 1, 0, W - 1)];
+        iw[c] = (1.0 - f) * ra + f * rb;
+        br += J[c] * (iw[c] - T[c]);
+        bpr += J[c] * (rb - ra);
+      }
+      const double b = group_sum_d<G>(row_live ? br : 0.0);
+      const double bp = group_sum_d<G>(row_live ? bpr : 0.0);
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        Jb[c] += ub * (-(iw[c] - T[c]) / H + 2.0 * b * J[c] / (H * H));
+        Tb[c] += ub * J[c] / H;
+        if (row_live) {
+          atomic_add_d(Rbar_row + clampi(ox + c + m, 0, W - 1), -ub * J[c] * (1.0 - f) / H);
+          atomic_add_d(Rbar_row + clampi(ox + c + m + 1, 0, W - 1), -ub * J[c] * f / H);
+        }
+      }
+      ub = ub * (1.0 - bp / H);
+    }
+    u0_adj = ub;
+  }
+
+  // ---- J = g - mean g, T and g live on the left level image
+  double jb = 0.0;
+#pragma unroll
+  for (int c = 0; c < P; ++c) jb += Jb[c];
+  const double jmean = group_sum_d<G>(row_live ? jb : 0.0) / (double)N;
+  if (row_live) {
+    double* Lrow = a.Lbar + (size_t)(oy + rr) * dp + ox;
+    double* Grow = a.Gbar + (size_t)(oy + rr) * dp + ox;
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      if (Tb[c] != 0.0) atomic_add_d(Lrow + c, Tb[c]);
+      const double gb = Jb[c] - jmean;
+      if (gb != 0.0) atomic_add_d(Grow + c, gb);
+    }
+  }
+  // ---- u_0 = 2 B(Ubar^(n+1))(c/2)
+  if (r == 0 && a.par_ubar_adj && u0_adj != 0.0) {
+    const double cx = 0.5 * ((double)ox + 0.5 * (double)(P - 1));
+    const double cy = 0.5 * ((double)oy + 0.5 * (double)(P - 1));
+    bilinear_adj(a.par_ubar_adj, a.pw, a.ph, cx, cy, 2.0 * u0_adj);
+  }
+}
+
+// Per pixel: template gradient g = Sobel_x(L) / 8 (reflect-101) -> level image.
+__global__ __launch_bounds__(kPixThreads) void k_sobel_adj(const PairLevel* tab, int npairs) {
+  const PairLevel& a = tab[find_pair<0>(tab, npairs, (int)blockIdx.x)];
+  const int idx = ((int)blockIdx.x - a.pyr0) * kPixThreads + (int)threadIdx.x;
+  const int w = a.g.w, h = a.g.h;
+  if (idx >= w * h) return;
+  const int y = idx / w, x = idx - y * w;
+  const double v = gbl(a.Gbar)[(size_t)y * a.dpitch + x] / 8.0;
+  if (v == 0.0) return;
+  const int xm = reflect101(x - 1, w), xp = reflect101(x + 1, w);
+  const int ys[3] = {reflect101(y - 1, h), y, reflect101(y + 1, h)};
+  const double wy[3] = {1.0, 2.0, 1.0};
+  for (int t = 0; t < 3; ++t) {
+    double* row = a.Lbar + (size_t)ys[t] * a.dpitch;
+    atomic_add_d(row + xp, wy[t] * v);
+    atomic_add_d(row + xm, -wy[t] * v);
+  }
+}
+
+// Per pixel of level n >= 1: the transposed binomial pyramid step into level n-1.
+__global__ __launch_bounds__(kPixThreads) void k_pyr_adj(const PairLevel* tab, int npairs) {
+  const PairLevel& a = tab[find_pair<0>(tab, npairs, (int)blockIdx.x)];
+  const int idx = ((int)blockIdx.x - a.pyr0) * kPixThreads + (int)threadIdx.x;
+  const int w = a.g.w, h = a.g.h;
+  if (idx >= w * h) return;
+  const int y = idx / w, x = idx - y * w;
+  const double vl = gbl(a.Lbar)[(size_t)y * a.dpitch + x] / 256.0;
+  const double vr = gbl(a.Rbar)[(size_t)y * a.dpitch + x] / 256.0;
+  if (vl == 0.0 && vr == 0.0) return;
+  const int kb[5] = {1, 4, 6, 4, 1};
+  for (int b = 0; b < 5; ++b) {
+    const size_t row = (size_t)reflect101(2 * y + b - 2, a.sh) * a.srcdpitch;
+    for (int c = 0; c < 5; ++c) {
+      const int xx = reflect101(2 * x + c - 2, a.sw);
+      const double wgt = (double)(kb[c] * kb[b]);
+      if (vl != 0.0) atomic_add_d(a.srcLbar + row + xx, wgt * vl);
+      if (vr != 0.0) atomic_add_d(a.srcRbar + row + xx, wgt * vr);
+    }
+  }
+}
+
+// Level 0, per pixel: image gradients out (float32, dense W x H).
+__global__ __launch_bounds__(kPixThreads) void k_grad_out(const PairLevel* tab, int npairs) {
+  const PairLevel& a = tab[find_pair<0>(tab, npairs, (int)blockIdx.x)];
+  const int idx = ((int)blockIdx.x - a.pyr0) * kPixThreads + (int)threadIdx.x;
+  const int w = a.g.w, h = a.g.h;
+  if (idx >= w * h) return;
+  const int y = idx / w, x = idx - y * w;
+  if (a.grad_left) gbl(a.grad_left)[idx] = (float)gbl(a.Lbar)[(size_t)y * a.dpitch + x];
+  if (a.grad_right) gbl(a.grad_right)[idx] = (float)gbl(a.Rbar)[(size_t)y * a.dpitch + x];
+}
+
+template <int P>
+hipError_t launch_sadj(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
+  hipLaunchKernelGGL(k_search_adj<P>, dim3(nblocks), dim3(kSearchF64Threads), 0, s, tab, npairs, lp);
+  return hipGetLastError();
+}
+
+hipError_t launch_search_adj(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
+  switch (lp.P) {
+    case 3: return launch_sadj<3>(tab, npairs, nblocks, lp, s);
+    case 4: return launch_sadj<4>(tab, npairs, nblocks, lp, s);
+    case 5: return launch_sadj<5>(tab, npairs, nblocks, lp, s);
+    case 6: return launch_sadj<6>(tab, npairs, nblocks, lp, s);
+    case 7: return launch_sadj<7>(tab, npairs, nblocks, lp, s);
+    case 8: return launch_sadj<8>(tab, npairs, nblocks, lp, s);
+    case 9: return launch_sadj<9>(tab, npairs, nblocks, lp, s);
+    case 10: return launch_sadj<10>(tab, npairs, nblocks, lp, s);
+    case 11: return launch_sadj<11>(tab, npairs, nblocks, lp, s);
+    case 12: return launch_sadj<12>(tab, npairs, nblocks, lp, s);
+    case 13: return launch_sadj<13>(tab, npairs, nblocks, lp, s);
+    case 14: return launch_sadj<14>(tab, npairs, nblocks, lp, s);
+    case 15: return launch_sadj<15>(tab, npairs, nblocks, lp, s);
+    case 16: return launch_sadj<16>(tab, npairs, nblocks, lp, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+// blocks: [per-pixel workgroups, search workgroups, per-patch workgroups]
+hipError_t launch_backward_level(const PairLevel* tab, int npairs, const int* blocks, const LevelParams& lp,
+                                 hipStream_t s) {
+  const dim3 pix(kPixThreads);
+  hipLaunchKernelGGL(k_adj_init, dim3((npairs + 63) / 64), dim3(64), 0, s, tab, npairs);
+  if (lp.level == lp.finest) hipLaunchKernelGGL(k_seed, dim3(blocks[0]), pix, 0, s, tab, npairs, lp);
+  hipLaunchKernelGGL(k_fuse_adj, dim3(blocks[2]), pix, 0, s, tab, npairs, lp);
+  if (lp.level > lp.finest) hipLaunchKernelGGL(k_hole_adj, dim3(blocks[0]), pix, 0, s, tab, npairs);
+  hipLaunchKernelGGL(k_prob_adj, dim3(blocks[2]), pix, 0, s, tab, npairs, lp);
+  hipLaunchKernelGGL(k_tau_adj, dim3((npairs + 63) / 64), dim3(64), 0, s, tab, npairs, lp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = launch_search_adj(tab, npairs, blocks[1], lp, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sobel_adj, dim3(blocks[0]), pix, 0, s, tab, npairs);
+  return hipGetLastError();
+}
+
+hipError_t launch_pyramid_adj(const PairLevel* tab, int npairs, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pyr_adj, dim3(nblocks), dim3(kPixThreads), 0, s, tab, npairs);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_out(const PairLevel* tab, int npairs, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_grad_out, dim3(nblocks), dim3(kPixThreads), 0, s, tab, npairs);
+  return hipGetLastError();
+}
+
+}  // namespace bdis

@@ -137,6 +137,15 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
     ub = 0.0;
     qv = 0.0;
   }
+  if (a.zmap) {  // training contexts keep the fusion sums for the backward pass
+    gbl(a.zmap)[idx] = valid ? z : 0.0;
+    gbl(a.smmap)[idx] = zm;
+    if (finest) {
+      gbl(a.ubar_keep)[idx] = ub;
+      gbl(a.qmap_keep)[idx] = qv;
+      if (a.vmap) gbl(a.vmap)[idx] = (valid && lp.variance) ? zv / (z * z) : 0.0;
+    }
+  }
   if (!finest) {
     gbl(a.ubar)[idx] = ub;
     gbl(a.qmap)[idx] = qv;

@@ -342,6 +342,8 @@ __global__ __launch_bounds__(256) void k_reduce(const PairLevel* tab, LevelParam
     }
     gbl(a.scal)[0] = sr2;
     gbl(a.scal)[1] = 2.0 * sr2 * (double)(kWin * kWin);
+    gbl(a.scal)[2] = s_redc[0] > 0 ? s_red[0] / ((double)s_redc[0] * (double)(lp.P * lp.P)) : 0.0;
+    gbl(a.scal)[3] = (double)s_redc[0];
   }
 }
 

@@ -43,6 +43,15 @@ struct Layout {
       dens[kMaxLevels]{};
   size_t ubar[kMaxLevels]{}, qmap[kMaxLevels]{};
   size_t part_sum[kMaxLevels]{}, part_cnt[kMaxLevels]{}, scal[kMaxLevels]{};
+  // training contexts: FP64 level images, saved state, adjoints (one region)
+  bool train = false;
+  int dpitch[kMaxLevels]{};
+  size_t ld[kMaxLevels]{}, rd[kMaxLevels]{}, uhist[kMaxLevels]{}, reset[kMaxLevels]{}, zmap[kMaxLevels]{},
+      smmap[kMaxLevels]{}, vmap = 0, ubar_keep = 0, qmap_keep = 0;
+  size_t adj_begin = 0, adj_end = 0;
+  size_t lbar[kMaxLevels]{}, rbar[kMaxLevels]{}, gbar[kMaxLevels]{}, ubar_adj[kMaxLevels]{},
+      qmap_adj[kMaxLevels]{}, vmap_adj = 0, pu_adj[kMaxLevels]{}, ppi_adj[kMaxLevels]{},
+      psig_adj[kMaxLevels]{}, pssd_adj[kMaxLevels]{};
   size_t total = 0;
 };
 
@@ -70,9 +79,10 @@ bool level_geometry(const bdis_params& p, int w, int h, int levels, LevelGeom* g
   return true;
 }
 
-bool make_layout(const bdis_params& p, int w, int h, int levels, Layout* lay) {
+bool make_layout(const bdis_params& p, int w, int h, int levels, Layout* lay, bool train = false) {
   Layout L;
   L.levels = levels;
+  L.train = train;
   if (!level_geometry(p, w, h, levels, L.g)) return false;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -108,6 +118,43 @@ bool make_layout(const bdis_params& p, int w, int h, int levels, Layout* lay) {
     L.part_cnt[n] = take((size_t)L.max_search_blocks[n] * 4);
     L.scal[n] = take(64);
   }
+  if (train) {
+    const int f = p.finest_level;
+    for (int n = 0; n < levels; ++n) {
+      const size_t np = (size_t)L.g[n].nx * L.g[n].ny, npx = (size_t)L.g[n].w * L.g[n].h;
+      L.dpitch[n] = (L.g[n].w + 7) / 8 * 8;
+      const size_t nd = (size_t)L.dpitch[n] * L.g[n].h;
+      L.ld[n] = take(nd * 8);
+      L.rd[n] = take(nd * 8);
+      if (n < f) continue;
+      L.uhist[n] = take(np * (size_t)(p.iters + 1) * 8);
+      L.reset[n] = take(np * 4);
+      L.zmap[n] = take(npx * 8);
+      L.smmap[n] = take(npx * 8);
+      if (n == f) {
+        L.vmap = take(npx * 8);
+        L.ubar_keep = take(npx * 8);
+        L.qmap_keep = take(npx * 8);
+      }
+    }
+    L.adj_begin = off;
+    for (int n = 0; n < levels; ++n) {
+      const size_t np = (size_t)L.g[n].nx * L.g[n].ny, npx = (size_t)L.g[n].w * L.g[n].h;
+      const size_t nd = (size_t)L.dpitch[n] * L.g[n].h;
+      L.lbar[n] = take(nd * 8);
+      L.rbar[n] = take(nd * 8);
+      L.gbar[n] = take(nd * 8);
+      if (n < f) continue;
+      L.ubar_adj[n] = take(npx * 8);
+      L.qmap_adj[n] = take(npx * 8);
+      if (n == f) L.vmap_adj = take(npx * 8);
+      L.pu_adj[n] = take(np * 8);
+      L.ppi_adj[n] = take(np * 8);
+      L.psig_adj[n] = take(np * 8);
+      L.pssd_adj[n] = take(np * kWin * 8);
+    }
+    L.adj_end = off;
+  }
   L.total = off;
   *lay = L;
   return true;
@@ -123,6 +170,14 @@ struct PairSpec {
   float* disp;
   float* var;
   float* conf;
+  // float path
+  const float* left32 = nullptr;
+  const float* right32 = nullptr;
+  // backward
+  const float* grad_disp = nullptr;
+  const float* grad_var = nullptr;
+  float* grad_left = nullptr;
+  float* grad_right = nullptr;
 };
 
 // Launch plan of one call: level-major job table and workgroup counts.
@@ -134,6 +189,7 @@ struct Plan {
   int pyr_blocks[kMaxLevels]{}, search_blocks[kMaxLevels]{}, prob_blocks[kMaxLevels]{},
       fuse_blocks[kMaxLevels]{};
   int threads[kMaxLevels]{};     // search workgroup size per level
+  bool f32 = false;              // float (FP64) path: per-pixel pyramid blocks, fixed search size
   std::vector<PairLevel> tab;
 };
 
@@ -171,6 +227,9 @@ struct bdis_ctx {
   std::map<std::string, GraphEntry> graphs;
   std::map<std::string, int> tuned;  // level shape key -> search workgroup threads
   int use_graph = 1;
+  bool train = false;                // created with BDIS_TRAIN
+  std::vector<PairSpec> last_f32;    // pairs of the last float-path call (backward state)
+  double* hyper_dev = nullptr;       // d loss / d hyperparameters accumulator (2 + 8)
   // geometry of the last single-pair compute (slot 0), for debug dumps
   int last_w = 0, last_h = 0;
   bool have_last = false;
@@ -201,7 +260,7 @@ bdis_status check_params_msg(const bdis_params* p, char* msg, size_t n) {
   if (p->stride < 1 || p->stride > p->patch)
     return snprintf(msg, n, "stride %d outside 1..patch", p->stride), BDIS_E_ARG;
   if (p->iters < 1 || p->iters > 256) return snprintf(msg, n, "iters %d outside 1..256", p->iters), BDIS_E_ARG;
-  if (p->float_pyramid != 0) return snprintf(msg, n, "float_pyramid must be 0 for uint8 input"), BDIS_E_ARG;
+  if (p->float_pyramid != 0 && p->float_pyramid != 1) return snprintf(msg, n, "float_pyramid must be 0 or 1"), BDIS_E_ARG;
   if (!finite_f(p->sigma_s) || !(p->sigma_s > 0.0f)) return snprintf(msg, n, "sigma_s must be > 0"), BDIS_E_ARG;
   if (!finite_f(p->sigma_r) || !(p->sigma_r > 0.0f)) return snprintf(msg, n, "sigma_r must be > 0"), BDIS_E_ARG;
   if (!finite_f(p->valid_ratio)) return snprintf(msg, n, "valid_ratio not finite"), BDIS_E_ARG;
@@ -304,11 +363,15 @@ void assign_offsets(const bdis_params& p, Plan& pl) {
   for (int n = 0; n < pl.max_levels; ++n) {
     int pyr = 0, se = 0, pr = 0, fu = 0;
     const bool patches = n >= p.finest_level;
+    const int threads = pl.f32 ? kSearchF64Threads : pl.threads[n];
     for (int e = 0; e < pl.tab_count[n]; ++e) {
       PairLevel& q = pl.tab[pl.tab_first[n] + e];
       q.pyr0 = pyr;
-      pyr += n >= 1 ? ((q.g.w + kPyrTx - 1) / kPyrTx) * ((q.g.h + kPyrTy - 1) / kPyrTy) : 0;
-      q.search_nbx = patches ? search_nbx(q.g, p.patch, pl.threads[n]) : 0;
+      if (pl.f32)  // one lane per pixel, every level (conversion at level 0; adjoint launches)
+        pyr += (q.g.w * q.g.h + kPixThreads - 1) / kPixThreads;
+      else
+        pyr += n >= 1 ? ((q.g.w + kPyrTx - 1) / kPyrTx) * ((q.g.h + kPyrTy - 1) / kPyrTy) : 0;
+      q.search_nbx = patches ? search_nbx(q.g, p.patch, threads) : 0;
       q.search0 = se;
       se += patches ? q.search_nbx * q.g.ny : 0;
       q.prob0 = pr;
@@ -323,14 +386,15 @@ void assign_offsets(const bdis_params& p, Plan& pl) {
   }
 }
 
-bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* out) {
+bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* out, bool f32 = false) {
   const bdis_params& p = c->p;
   Plan pl;
   pl.finest = p.finest_level;
+  pl.f32 = f32;
   std::vector<Layout> lays(pairs.size());
   for (size_t i = 0; i < pairs.size(); ++i) {
     const PairSpec& q = pairs[i];
-    if (!make_layout(p, q.w, q.h, q.levels, &lays[i]))
+    if (!make_layout(p, q.w, q.h, q.levels, &lays[i], c->train))
       return fail(c, BDIS_E_SIZE, "pair %zu: a level of %dx%d with %d levels is smaller than patch %d", i, q.w,
                   q.h, q.levels, p.patch);
     if (lays[i].total > c->slot_bytes)
@@ -390,13 +454,61 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
           e.confidence = q.conf;
         }
       }
+      if (f32) {
+        const int f = p.finest_level;
+        if (n == 0) {
+          e.src32L = q.left32;
+          e.src32R = q.right32;
+          e.src32pitch = q.pitch;
+        } else {
+          e.srcdL = BD(lay.ld[n - 1]);
+          e.srcdR = BD(lay.rd[n - 1]);
+          e.srcdpitch = lay.dpitch[n - 1];
+          e.srcLbar = BD(lay.lbar[n - 1]);
+          e.srcRbar = BD(lay.rbar[n - 1]);
+        }
+        e.Ld = BD(lay.ld[n]);
+        e.Rd = BD(lay.rd[n]);
+        e.dpitch = lay.dpitch[n];
+        e.Lbar = BD(lay.lbar[n]);
+        e.Rbar = BD(lay.rbar[n]);
+        e.Gbar = BD(lay.gbar[n]);
+        if (n >= f) {
+          const bool has_par = n + 1 < q.levels;
+          e.uhist = BD(lay.uhist[n]);
+          e.reset = reinterpret_cast<int*>(base + lay.reset[n]);
+          e.zmap = BD(lay.zmap[n]);
+          e.smmap = BD(lay.smmap[n]);
+          e.ubar_adj = BD(lay.ubar_adj[n]);
+          e.qmap_adj = BD(lay.qmap_adj[n]);
+          e.par_ubar_adj = has_par ? BD(lay.ubar_adj[n + 1]) : nullptr;
+          e.par_qmap_adj = has_par ? BD(lay.qmap_adj[n + 1]) : nullptr;
+          e.pu_adj = BD(lay.pu_adj[n]);
+          e.ppi_adj = BD(lay.ppi_adj[n]);
+          e.psig_adj = BD(lay.psig_adj[n]);
+          e.pssd_adj = BD(lay.pssd_adj[n]);
+          if (n == f) {
+            e.vmap = BD(lay.vmap);
+            e.ubar_keep = BD(lay.ubar_keep);
+            e.qmap_keep = BD(lay.qmap_keep);
+            e.vmap_adj = BD(lay.vmap_adj);
+            e.grad_disp = q.grad_disp;
+            e.grad_var = q.grad_var;
+          }
+        }
+        if (n == 0) {
+          e.grad_left = q.grad_left;
+          e.grad_right = q.grad_right;
+        }
+        e.hyper_adj = c->hyper_dev;
+      }
       pl.tab.push_back(e);
     }
     pl.tab_count[n] = (int)pl.tab.size() - pl.tab_first[n];
   }
   for (int n = 0; n < pl.max_levels; ++n) {
-    if (n < p.finest_level || pl.tab_count[n] == 0) {
-      pl.threads[n] = 256;
+    if (f32 || n < p.finest_level || pl.tab_count[n] == 0) {
+      pl.threads[n] = f32 ? kSearchF64Threads : 256;
       continue;
     }
     auto it = c->tuned.find(level_key(p, pl, n));
@@ -600,6 +712,84 @@ bdis_status run_pairs(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipStream
   return run_graph(c, pl, st);
 }
 
+// Float path forward: FP64 pyramid (level 0 converted from float), then the
+// usual per-level phases; training state is written as it goes.
+bdis_status run_pairs_f32(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipStream_t st) {
+  Plan pl;
+  bdis_status s = build_plan(c, pairs, &pl, true);
+  if (s != BDIS_OK) return s;
+  if ((s = upload_table(c, pl, st)) != BDIS_OK) return s;
+  const bdis_params& p = c->p;
+  hipError_t e;
+  for (int n = 0; n < pl.max_levels; ++n) {
+    const long tmk = timing_start(c, BDIS_K_PYRAMID, st);
+    e = launch_pyramid_f64(c->tab_dev + pl.tab_first[n], pl.tab_count[n], pl.pyr_blocks[n], n, st);
+    timing_stop(c, tmk, st);
+    if (e != hipSuccess) return hip_fail(c, e, "pyramid launch");
+  }
+  for (int n = pl.max_levels - 1; n >= p.finest_level; --n) {
+    const PairLevel* tab = c->tab_dev + pl.tab_first[n];
+    const int cnt = pl.tab_count[n];
+    const LevelParams lp = level_params(p, n);
+    long tmk = timing_start(c, BDIS_K_SEARCH, st);
+    e = launch_search_f64(tab, cnt, pl.search_blocks[n], lp, st);
+    timing_stop(c, tmk, st);
+    if (e != hipSuccess) return hip_fail(c, e, "search launch");
+    tmk = timing_start(c, BDIS_K_REDUCE, st);
+    e = launch_reduce(tab, cnt, lp, st);
+    timing_stop(c, tmk, st);
+    if (e != hipSuccess) return hip_fail(c, e, "reduction launch");
+    tmk = timing_start(c, BDIS_K_PROB, st);
+    e = launch_prob(tab, cnt, pl.prob_blocks[n], lp, st);
+    timing_stop(c, tmk, st);
+    if (e != hipSuccess) return hip_fail(c, e, "probability launch");
+    tmk = timing_start(c, BDIS_K_FUSE, st);
+    e = launch_fuse(tab, cnt, pl.fuse_blocks[n], lp, st);
+    timing_stop(c, tmk, st);
+    if (e != hipSuccess) return hip_fail(c, e, "fusion launch");
+  }
+  return BDIS_OK;
+}
+
+// Backward pass of the last float-path call: adjoints level by level from the
+// finest to the coarsest, then the transposed pyramid down to the images.
+bdis_status run_backward(bdis_ctx* c, std::vector<PairSpec> pairs, double* grad_hyper, hipStream_t st) {
+  Plan pl;
+  bdis_status s = build_plan(c, pairs, &pl, true);
+  if (s != BDIS_OK) return s;
+  if ((s = upload_table(c, pl, st)) != BDIS_OK) return s;
+  const bdis_params& p = c->p;
+  hipError_t e;
+  for (size_t i = 0; i < pairs.size(); ++i) {
+    Layout lay;
+    make_layout(p, pairs[i].w, pairs[i].h, pairs[i].levels, &lay, true);
+    e = hipMemsetAsync(c->ws + i * c->slot_bytes + lay.adj_begin, 0, lay.adj_end - lay.adj_begin, st);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint clear");
+  }
+  if ((e = hipMemsetAsync(c->hyper_dev, 0, sizeof(double) * (2 + kMaxLevels), st)) != hipSuccess)
+    return hip_fail(c, e, "adjoint clear");
+  for (int n = p.finest_level; n < pl.max_levels; ++n) {
+    const int blocks[3] = {pl.pyr_blocks[n], pl.search_blocks[n], pl.prob_blocks[n]};
+    const long tmk = timing_start(c, BDIS_K_BACKWARD, st);
+    e = launch_backward_level(c->tab_dev + pl.tab_first[n], pl.tab_count[n], blocks, level_params(p, n), st);
+    timing_stop(c, tmk, st);
+    if (e != hipSuccess) return hip_fail(c, e, "backward launch");
+  }
+  for (int n = pl.max_levels - 1; n >= 1; --n) {
+    const long tmk = timing_start(c, BDIS_K_BACKWARD, st);
+    e = launch_pyramid_adj(c->tab_dev + pl.tab_first[n], pl.tab_count[n], pl.pyr_blocks[n], st);
+    timing_stop(c, tmk, st);
+    if (e != hipSuccess) return hip_fail(c, e, "pyramid adjoint launch");
+  }
+  if ((e = launch_grad_out(c->tab_dev + pl.tab_first[0], pl.tab_count[0], pl.pyr_blocks[0], st)) != hipSuccess)
+    return hip_fail(c, e, "gradient output launch");
+  if (grad_hyper) {
+    e = hipMemcpyAsync(grad_hyper, c->hyper_dev, sizeof(double) * (2 + pl.max_levels), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(c, e, "hyper-gradient copy");
+  }
+  return BDIS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -637,10 +827,11 @@ bdis_status bdis_create(bdis_ctx** out, const bdis_params* p, int max_w, int max
   char msg[256];
   bdis_status st = check_params_msg(p, msg, sizeof msg);
   if (st != BDIS_OK) return fail(nullptr, st, "%s", msg);
-  if (max_w < 1 || max_h < 1 || max_batch < 1 || flags != 0)
-    return fail(nullptr, BDIS_E_ARG, "max_w/max_h/max_batch must be >= 1 and flags 0");
+  if (max_w < 1 || max_h < 1 || max_batch < 1 || (flags & ~BDIS_TRAIN) != 0)
+    return fail(nullptr, BDIS_E_ARG, "max_w/max_h/max_batch must be >= 1 and flags 0 or BDIS_TRAIN");
+  const bool train = (flags & BDIS_TRAIN) != 0;
   Layout lay;
-  if (!make_layout(*p, max_w, max_h, p->levels, &lay))
+  if (!make_layout(*p, max_w, max_h, p->levels, &lay, train))
     return fail(nullptr, BDIS_E_SIZE, "%dx%d with %d levels is smaller than patch %d", max_w, max_h,
                 p->levels, p->patch);
   const char* fault = std::getenv("BDIS_FAULT");
@@ -653,6 +844,7 @@ bdis_status bdis_create(bdis_ctx** out, const bdis_params* p, int max_w, int max
   c->max_h = max_h;
   c->max_batch = max_batch;
   c->slot_bytes = lay.total;
+  c->train = train;
   const char* g = std::getenv("BDIS_GRAPH");
   c->use_graph = !(g && std::strcmp(g, "0") == 0);
   hipError_t e = hipGetDevice(&c->device);
@@ -670,11 +862,13 @@ bdis_status bdis_create(bdis_ctx** out, const bdis_params* p, int max_w, int max
   // zero the workspace once (every array is rewritten before it is read)
   e = hipMemset(c->ws, 0, c->slot_bytes * (size_t)max_batch);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->tab_evt, hipEventDisableTiming);
+  if (e == hipSuccess && train) e = hipMalloc(reinterpret_cast<void**>(&c->hyper_dev), sizeof(double) * (2 + kMaxLevels));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->tab_evt) (void)hipEventDestroy(c->tab_evt);
+    if (c->hyper_dev) (void)hipFree(c->hyper_dev);
     (void)hipFree(c->ws);
     delete c;
     return fail(nullptr, BDIS_E_HIP, "workspace init: %s", hipGetErrorString(e));
@@ -689,10 +883,11 @@ bdis_status bdis_set_params(bdis_ctx* c, const bdis_params* p) {
   bdis_status st = check_params_msg(p, msg, sizeof msg);
   if (st != BDIS_OK) return fail(c, st, "%s", msg);
   Layout lay;
-  if (!make_layout(*p, c->max_w, c->max_h, p->levels, &lay) || lay.total > c->slot_bytes)
+  if (!make_layout(*p, c->max_w, c->max_h, p->levels, &lay, c->train) || lay.total > c->slot_bytes)
     return fail(c, BDIS_E_CAPACITY, "parameters need more workspace than the context holds");
   c->p = *p;
   c->have_last = false;
+  c->last_f32.clear();
   return BDIS_OK;
 }
 
@@ -702,6 +897,7 @@ bdis_status bdis_compute(bdis_ctx* c, const uint8_t* left, const uint8_t* right,
   if (!left || !right || !disp) return fail(c, BDIS_E_ARG, "left, right and disparity are required");
   if (w < 1 || h < 1 || pitch < w) return fail(c, BDIS_E_ARG, "bad image size %dx%d pitch %d", w, h, pitch);
   if (var && !c->p.variance) return fail(c, BDIS_E_ARG, "variance output given but params.variance is 0");
+  if (c->p.float_pyramid) return fail(c, BDIS_E_ARG, "uint8 input needs params.float_pyramid = 0");
   if (w > c->max_w || h > c->max_h)
     return fail(c, BDIS_E_CAPACITY, "image %dx%d exceeds the context's %dx%d", w, h, c->max_w, c->max_h);
   c->have_last = false;
@@ -733,9 +929,71 @@ bdis_status bdis_compute_batch(bdis_ctx* c, int n, const bdis_pair* pairs, void*
     if (q.w > c->max_w || q.h > c->max_h) return fail(c, BDIS_E_CAPACITY, "pair %d: %dx%d too large", i, q.w, q.h);
     v.push_back(PairSpec{q.left, q.right, q.w, q.h, q.pitch, lv, q.disparity, q.variance, q.confidence});
   }
+  if (c->p.float_pyramid) return fail(c, BDIS_E_ARG, "uint8 input needs params.float_pyramid = 0");
   c->have_last = false;
   if (n == 0) return BDIS_OK;
   return run_pairs(c, v, reinterpret_cast<hipStream_t>(stream));
+}
+
+bdis_status bdis_compute_f32_batch(bdis_ctx* c, int n, const bdis_pair_f32* pairs, void* stream) {
+  if (!c) return BDIS_E_ARG;
+  if (!c->train) return fail(c, BDIS_E_STATE, "the float path needs a context created with BDIS_TRAIN");
+  if (!c->p.float_pyramid) return fail(c, BDIS_E_ARG, "float input needs params.float_pyramid = 1");
+  if (n < 1 || !pairs) return fail(c, BDIS_E_ARG, "bad batch");
+  if (n > c->max_batch) return fail(c, BDIS_E_CAPACITY, "batch of %d exceeds max_batch %d", n, c->max_batch);
+  std::vector<PairSpec> v;
+  for (int i = 0; i < n; ++i) {
+    const bdis_pair_f32& q = pairs[i];
+    if (!q.left || !q.right || !q.disparity) return fail(c, BDIS_E_ARG, "pair %d: null pointer", i);
+    if (q.w < 1 || q.h < 1 || q.pitch < q.w || q.levels < 0) return fail(c, BDIS_E_ARG, "pair %d: bad size", i);
+    if (q.variance && !c->p.variance)
+      return fail(c, BDIS_E_ARG, "pair %d: variance output without params.variance", i);
+    const int lv = q.levels > 0 ? q.levels : c->p.levels;
+    if (lv > c->p.levels) return fail(c, BDIS_E_CAPACITY, "pair %d: %d levels > %d", i, lv, c->p.levels);
+    if (q.w > c->max_w || q.h > c->max_h) return fail(c, BDIS_E_CAPACITY, "pair %d: %dx%d too large", i, q.w, q.h);
+    PairSpec ps{nullptr, nullptr, q.w, q.h, q.pitch, lv, q.disparity, q.variance, q.confidence};
+    ps.left32 = q.left;
+    ps.right32 = q.right;
+    v.push_back(ps);
+  }
+  c->have_last = false;
+  c->last_f32.clear();
+  bdis_status st = run_pairs_f32(c, v, reinterpret_cast<hipStream_t>(stream));
+  if (st == BDIS_OK) c->last_f32 = v;
+  return st;
+}
+
+bdis_status bdis_compute_f32(bdis_ctx* c, const float* left, const float* right, int w, int h, int pitch,
+                             float* disp, float* var, float* conf, void* stream) {
+  if (!c) return BDIS_E_ARG;
+  bdis_pair_f32 q{left, right, w, h, pitch, 0, disp, var, conf};
+  return bdis_compute_f32_batch(c, 1, &q, stream);
+}
+
+bdis_status bdis_backward_batch(bdis_ctx* c, int n, const bdis_pair_grad* grads, double* grad_hyper,
+                                void* stream) {
+  if (!c) return BDIS_E_ARG;
+  if (c->last_f32.empty()) return fail(c, BDIS_E_STATE, "backward needs a preceding float-path compute");
+  if (n != (int)c->last_f32.size() || !grads)
+    return fail(c, BDIS_E_ARG, "backward batch of %d after a compute of %zu pairs", n, c->last_f32.size());
+  std::vector<PairSpec> v = c->last_f32;
+  for (int i = 0; i < n; ++i) {
+    if (!grads[i].grad_disparity && !grads[i].grad_variance)
+      return fail(c, BDIS_E_ARG, "pair %d: no output gradient", i);
+    if (grads[i].grad_variance && !c->p.variance)
+      return fail(c, BDIS_E_ARG, "pair %d: variance gradient without params.variance", i);
+    v[i].grad_disp = grads[i].grad_disparity;
+    v[i].grad_var = grads[i].grad_variance;
+    v[i].grad_left = grads[i].grad_left;
+    v[i].grad_right = grads[i].grad_right;
+  }
+  return run_backward(c, v, grad_hyper, reinterpret_cast<hipStream_t>(stream));
+}
+
+bdis_status bdis_backward(bdis_ctx* c, const float* grad_disparity, const float* grad_variance, float* grad_left,
+                          float* grad_right, double* grad_hyper, void* stream) {
+  bdis_pair_grad g{grad_disparity, grad_variance, grad_left, grad_right};
+  return bdis_backward_batch(c, 1, &g, grad_hyper, stream);
 }
 
 bdis_status bdis_debug_dump(bdis_ctx* c, int level, int what, void* host_dst, size_t bytes, void* stream) {
@@ -743,7 +1001,7 @@ bdis_status bdis_debug_dump(bdis_ctx* c, int level, int what, void* host_dst, si
   if (!c->have_last) return fail(c, BDIS_E_STATE, "no single-pair compute to dump");
   if (!host_dst || level < 0 || level >= c->p.levels) return fail(c, BDIS_E_ARG, "bad dump request");
   Layout lay;
-  make_layout(c->p, c->last_w, c->last_h, c->p.levels, &lay);
+  make_layout(c->p, c->last_w, c->last_h, c->p.levels, &lay, c->train);
   const LevelGeom& g = lay.g[level];
   const size_t npx = (size_t)g.w * g.h, np = (size_t)g.nx * g.ny;
   size_t off = 0, n = 0;
@@ -834,12 +1092,13 @@ void bdis_destroy(bdis_ctx* c) {
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   if (c->tab_dev) (void)hipFree(c->tab_dev);
   if (c->tab_host) (void)hipHostFree(c->tab_host);
+  if (c->hyper_dev) (void)hipFree(c->hyper_dev);
   if (c->ws) (void)hipFree(c->ws);
   delete c;
 }
 
 const char* bdis_last_error(const bdis_ctx* c) { return c ? c->err : g_create_err; }
 
-const char* bdis_version(void) { return "bdis-gfx950 0.2"; }
+const char* bdis_version(void) { return "bdis-gfx950 0.3"; }
 
 }  // extern "C"

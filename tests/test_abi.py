@@ -34,7 +34,7 @@ def test_defaults_follow_paper(B):
 
 @pytest.mark.parametrize("kw", [dict(patch=2), dict(patch=17), dict(stride=0), dict(stride=11),
                                 dict(iters=0), dict(levels=0), dict(levels=9), dict(sigma_s=0.0),
-                                dict(sigma_r=-1.0), dict(finest_level=1), dict(float_pyramid=1),
+                                dict(sigma_r=-1.0), dict(finest_level=1), dict(float_pyramid=2),
                                 dict(level_weight=[0.0] * 8), dict(sigma_s=float("nan"))])
 def test_bad_params_rejected(B, kw):
     assert B.check(B.params(**kw)) == B.E_ARG
@@ -67,6 +67,10 @@ def test_create_validation_before_any_device_call(B, monkeypatch):
 def test_null_context_calls(B):
     assert B.lib().bdis_compute(None, None, None, 1, 1, 1, None, None, None, None) == B.E_ARG
     assert B.lib().bdis_compute_batch(None, 0, None, None) == B.E_ARG
+    assert B.lib().bdis_compute_f32(None, None, None, 1, 1, 1, None, None, None, None) == B.E_ARG
+    assert B.lib().bdis_backward(None, None, None, None, None, None, None) == B.E_ARG
+    h = ctypes.c_void_p()
+    assert B.lib().bdis_create(ctypes.byref(h), ctypes.byref(B.params()), 64, 64, 1, 6) == B.E_ARG
     B.lib().bdis_destroy(None)
     assert B.lib().bdis_version().startswith(b"bdis")
 
