@@ -397,7 +397,8 @@ def _autograd_function():
             _set_hyper(bctx, sigma_s.item(), sigma_r.item(), omega.detach().cpu().tolist())
             out = bctx.compute_f32(left.detach().contiguous(), right.detach().contiguous())
             fctx.bctx = bctx
-            fctx.shapes = (left.shape, omega.shape, sigma_s.dtype, omega.dtype)
+            fctx.shapes = (left.shape, omega.shape, sigma_s.dtype, omega.dtype, sigma_s.device, sigma_r.device,
+                           omega.device)
             var = out["var"] if out["var"] is not None else torch.zeros_like(out["disp"])
             fctx.has_var = out["var"] is not None
             return out["disp"], var
@@ -410,10 +411,10 @@ def _autograd_function():
             if g_disp is None:
                 g_disp = torch.zeros(fctx.shapes[0], dtype=torch.float32, device=g_var.device)
             gl, gr, gh = fctx.bctx.backward(g_disp, g_var)
-            shape, oshape, sdt, odt = fctx.shapes
+            shape, oshape, sdt, odt, sdev, rdev, odev = fctx.shapes
             L = oshape[0]
-            return (gl.reshape(shape), gr.reshape(shape), gh[0].to(sdt), gh[1].to(sdt), gh[2:2 + L].to(odt),
-                    None)
+            return (gl.reshape(shape), gr.reshape(shape), gh[0].to(device=sdev, dtype=sdt),
+                    gh[1].to(device=rdev, dtype=sdt), gh[2:2 + L].to(device=odev, dtype=odt), None)
 
     return BDISFunction
 
