@@ -162,6 +162,69 @@ def bench_batch(bdis, torch, args):
                 epe_median_px=round(epe, 4))
 
 
+def bench_diff(bdis, torch, args):
+    """Differentiable form: a batch of 16 float 640x480 pairs, forward and backward
+    (K = 8 unrolled, 4 levels, P 8, S 4), and the plain uint8 form on the same pairs."""
+    import numpy as np
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    dev = torch.device("cuda:0")
+    n, uniq = args.diff_pairs, min(args.diff_pairs, 4)
+    log(f"differentiable form: {n} pairs 640x480 ({uniq} unique)")
+    base = [make_pair(4, i, quantize=False) for i in range(uniq)]
+    L = torch.stack([torch.from_numpy(base[i % uniq][0].astype(np.float32)) for i in range(n)]).to(dev)
+    R = torch.stack([torch.from_numpy(base[i % uniq][1].astype(np.float32)) for i in range(n)]).to(dev)
+    mp = method_params(4)
+    p = bdis.params(**mp)
+    ctx = bdis.Context(p, 640, 480, max_batch=n, train=True)
+    g = torch.randn((n, 480, 640), generator=torch.Generator().manual_seed(0)).to(dev)
+    for _ in range(2):
+        ctx.compute_f32(L, R)
+        ctx.backward(g)
+    torch.cuda.synchronize()
+    reps = args.diff_steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_f = t_b = 0.0
+    for _ in range(reps):
+        ev[0].record()
+        out = ctx.compute_f32(L, R)
+        ev[1].record()
+        ctx.backward(g)
+        ev[2].record()
+        torch.cuda.synchronize()
+        t_f += ev[0].elapsed_time(ev[1])
+        t_b += ev[1].elapsed_time(ev[2])
+    d = out["disp"].cpu().numpy()
+    epe_f = [np.abs(d[i][np.isfinite(d[i]) & base[i][3]] - base[i][2][np.isfinite(d[i]) & base[i][3]])
+             for i in range(uniq)]
+    ctx.close()
+    # the plain form on the same pairs, quantised to uint8
+    pu = bdis.params(**{k: v for k, v in mp.items() if k != "float_pyramid"})
+    ctxu = bdis.Context(pu, 640, 480, max_batch=n)
+    Lu = [torch.from_numpy(np.clip(np.rint(base[i % uniq][0]), 0, 255).astype(np.uint8)).to(dev) for i in range(n)]
+    Ru = [torch.from_numpy(np.clip(np.rint(base[i % uniq][1]), 0, 255).astype(np.uint8)).to(dev) for i in range(n)]
+    for _ in range(2):
+        outs = ctxu.compute_batch(Lu, Ru)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        outs = ctxu.compute_batch(Lu, Ru)
+    ev[1].record()
+    torch.cuda.synchronize()
+    t_u = ev[0].elapsed_time(ev[1]) / reps
+    du = [outs[i]["disp"].cpu().numpy() for i in range(uniq)]
+    epe_u = [np.abs(du[i][np.isfinite(du[i]) & base[i][3]] - base[i][2][np.isfinite(du[i]) & base[i][3]])
+             for i in range(uniq)]
+    ctxu.close()
+    fwd, bwd = t_f / reps, t_b / reps
+    return dict(pairs=n, unique_pairs=uniq, fwd_ms=round(fwd, 3), bwd_ms=round(bwd, 3),
+                bwd_fwd_ratio=round(bwd / fwd, 3), fwd_mpx_s=round(640 * 480 * n / fwd / 1e3, 2),
+                plain_u8_ms=round(t_u, 3), plain_u8_mpx_s=round(640 * 480 * n / t_u / 1e3, 2),
+                epe_median_px_float=round(float(np.median(np.concatenate(epe_f))), 4),
+                epe_median_px_plain=round(float(np.median(np.concatenate(epe_u))), 4),
+                config="16 x 640x480 float pairs (bumps 0-32 px), L=4 P=8 S=4 K=8, FP64 state; "
+                       "loss gradient = random field")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +234,9 @@ def main():
     ap.add_argument("--batch-unique", type=int, default=4)
     ap.add_argument("--batch-steps", type=int, default=6)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--diff-pairs", type=int, default=16)
+    ap.add_argument("--diff-steps", type=int, default=5)
+    ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -200,6 +266,8 @@ def main():
                 epe_median_px=round(s["epe"], 4))
     if not args.no_batch:
         line["batch_1080p"] = bench_batch(bdis, torch, args)
+    if not args.no_diff:
+        line["differentiable_c4"] = bench_diff(bdis, torch, args)
     if not args.no_cpu_baseline:
         from oracle import ref
         log("cpu baseline (FP64 oracle)")

@@ -77,47 +77,85 @@ BDIS_DEV void cover_range(int x, int n, int P, int S, int cnt, int& lo, int& hi,
   extra = (x >= n - P && cnt - 1 > hi) ? cnt - 1 : -1;
 }
 
+// Records staged per workgroup: the patches covering a 64 x 4 pixel tile
+// (about 26 x 6 for stride 3; tiles that cover more use direct loads).
+constexpr int kMaxRec = 512;
+
 __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab, int npairs, LevelParams lp) {
   __shared__ double s_m[kMaxPatch];
+  __shared__ double s_u[kMaxRec], s_w[kMaxRec], s_v[kMaxRec];
   const PairLevel& a = tab[find_pair<3>(tab, npairs, (int)blockIdx.x)];
   const int tid = threadIdx.x;
-  if (tid < lp.P) {
+  const int P = lp.P, S = lp.S;
+  if (tid < P) {
     const double sg = (double)lp.sigma_s;
     double acc = 0.0;
-    for (int c = 0; c < lp.P; ++c) {
+    for (int c = 0; c < P; ++c) {
       const double dd = (double)(tid - c);
       acc += exp(-dd * dd / (2.0 * sg * sg));
     }
     s_m[tid] = acc;
   }
-  __syncthreads();
   const int tiles_x = (a.g.w + kFuseTx - 1) / kFuseTx;
   const int t = (int)blockIdx.x - a.fuse0;
-  const int x = (t % tiles_x) * kFuseTx + tid % kFuseTx;
-  const int y = (t / tiles_x) * kFuseTy + tid / kFuseTx;
+  const int x0 = (t % tiles_x) * kFuseTx, y0 = (t / tiles_x) * kFuseTy;
+  const int x1 = min(x0 + kFuseTx, a.g.w) - 1, y1 = min(y0 + kFuseTy, a.g.h) - 1;
+  // patch index ranges covering the tile: [lo, hi] plus the border patch `ex`
+  int ilo, ihi, iex, jlo, jhi, jex, dummy0, dummy1, dummy2;
+  cover_range(x0, a.g.w, P, S, a.g.nx, ilo, dummy0, dummy1);
+  cover_range(x1, a.g.w, P, S, a.g.nx, dummy2, ihi, iex);
+  cover_range(y0, a.g.h, P, S, a.g.ny, jlo, dummy0, dummy1);
+  cover_range(y1, a.g.h, P, S, a.g.ny, dummy2, jhi, jex);
+  const int ni = ihi - ilo + 1 + (iex >= 0 ? 1 : 0);
+  const int nj = jhi - jlo + 1 + (jex >= 0 ? 1 : 0);
+  const bool staged = ni * nj <= kMaxRec;
+  if (staged) {
+    for (int r = tid; r < ni * nj; r += kFuseTx * kFuseTy) {
+      const int rj = r / ni, ri = r - rj * ni;
+      const int i = ilo + ri <= ihi ? ilo + ri : iex;
+      const int j = jlo + rj <= jhi ? jlo + rj : jex;
+      const D4 d = ld4(a.pa.dens + (size_t)j * a.g.nx + i);
+      s_u[r] = d.x;
+      s_w[r] = d.y;
+      s_v[r] = d.z;
+    }
+  }
+  __syncthreads();
+  const int x = x0 + tid % kFuseTx;
+  const int y = y0 + tid / kFuseTx;
   if (x >= a.g.w || y >= a.g.h) return;
-  const int P = lp.P, S = lp.S;
   const bool finest = lp.level == lp.finest;
-  int ilo, ihi, iex, jlo, jhi, jex;
-  cover_range(x, a.g.w, P, S, a.g.nx, ilo, ihi, iex);
-  cover_range(y, a.g.h, P, S, a.g.ny, jlo, jhi, jex);
+  int pilo, pihi, piex, pjlo, pjhi, pjex;
+  cover_range(x, a.g.w, P, S, a.g.nx, pilo, pihi, piex);
+  cover_range(y, a.g.h, P, S, a.g.ny, pjlo, pjhi, pjex);
   double z = 0.0, zu = 0.0, zm = 0.0, zv = 0.0;
-  const int jend = jex >= 0 ? jhi + 1 : jhi;
-  const int iend = iex >= 0 ? ihi + 1 : ihi;
-  for (int jj = jlo; jj <= jend; ++jj) {
-    const int j = jj <= jhi ? jj : jex;
+  const int jend = pjex >= 0 ? pjhi + 1 : pjhi;
+  const int iend = piex >= 0 ? pihi + 1 : pihi;
+  for (int jj = pjlo; jj <= jend; ++jj) {
+    const int j = jj <= pjhi ? jj : pjex;
     const double mb = s_m[y - grid_origin(j, a.g.h, P, S)];
-    const D4* row = a.pa.dens + (size_t)j * a.g.nx;
-    for (int ii = ilo; ii <= iend; ++ii) {
-      const int i = ii <= ihi ? ii : iex;
-      const D4 d = ld4(row + i);
-      if (d.y < 0.0) continue;  // rejected patch
+    const int rj = j <= jhi ? j - jlo : nj - 1;  // row of j in the staged block
+    for (int ii = pilo; ii <= iend; ++ii) {
+      const int i = ii <= pihi ? ii : piex;
+      double du, dw, dv;
+      if (staged) {
+        const int r = rj * ni + (i <= ihi ? i - ilo : ni - 1);
+        du = s_u[r];
+        dw = s_w[r];
+        dv = s_v[r];
+      } else {
+        const D4 d = ld4(a.pa.dens + (size_t)j * a.g.nx + i);
+        du = d.x;
+        dw = d.y;
+        dv = d.z;
+      }
+      if (dw < 0.0) continue;  // rejected patch
       const double m = s_m[x - grid_origin(i, a.g.w, P, S)] * mb;
-      const double wk = m * d.y;
+      const double wk = m * dw;
       z += wk;
-      zu += wk * d.x;
+      zu += wk * du;
       zm += m;
-      zv += wk * wk * d.z;
+      zv += wk * wk * dv;
     }
   }
   const size_t idx = (size_t)y * a.g.w + x;
