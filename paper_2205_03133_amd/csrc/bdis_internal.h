@@ -112,8 +112,9 @@ struct PairLevel {
   // adjoints (training contexts)
   double* Lbar;          // d loss / d level image
   double* Rbar;
-  double* srcLbar;       // d loss / d level n-1 images (n >= 1)
-  double* srcRbar;
+  const double* upLbar;  // d loss / d level n+1 images (nullptr at the coarsest level)
+  const double* upRbar;
+  int upw, uph, updpitch;
   double* Gbar;          // d loss / d template gradient (Sobel / 8) image
   double* ubar_adj;      // d loss / d fused maps of this level
   double* qmap_adj;

@@ -320,6 +320,32 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLeve
   const auto Rrow = Rg + (size_t)(oy + rr) * dp;
   double* Rbar_row = a.Rbar + (size_t)(oy + rr) * dp;
 
+  // Every warp of this patch row reads R at ox + m + c' (c' = 0..P) for its unit
+  // cell m.  Scatters into R are summed in registers while m stays the same (the
+  // cell is uniform over the patch, so the flush is too) and written with one
+  // atomic per touched pixel when it changes.
+  double acc[P + 1];
+#pragma unroll
+  for (int c = 0; c <= P; ++c) acc[c] = 0.0;
+  int mcur = 0;
+  bool have = false;
+  auto flush = [&]() {
+    if (have && row_live) {
+#pragma unroll
+      for (int c = 0; c <= P; ++c)
+        if (acc[c] != 0.0) atomic_add_d(Rbar_row + clampi(ox + mcur + c, 0, W - 1), acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c <= P; ++c) acc[c] = 0.0;
+  };
+  auto to_cell = [&](int m) {
+    if (!have || m != mcur) {
+      flush();
+      mcur = m;
+      have = true;
+    }
+  };
+
   // ---- window: SSD_d = sum (e - mean e)^2 at u + d
   const double u = gbl(a.pa.u)[k];
   double ub = gbl(a.pu_adj)[k];
@@ -341,16 +367,15 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLeve
     }
     const double emean = group_sum_d<G>(row_live ? se : 0.0) / (double)N;
     double urow = 0.0;
+    to_cell(m);
 #pragma unroll
     for (int c = 0; c < P; ++c) {
       const int xa = clampi(ox + c + m, 0, W - 1), xb = clampi(ox + c + m + 1, 0, W - 1);
       const double g2 = 2.0 * (ev[c] - emean) * sbar;
       urow += g2 * (Rrow[xb] - Rrow[xa]);
       Tb[c] -= g2;
-      if (row_live) {
-        atomic_add_d(Rbar_row + xa, g2 * (1.0 - f));
-        atomic_add_d(Rbar_row + xb, g2 * f);
-      }
+      acc[c] += g2 * (1.0 - f);
+      acc[c + 1] += g2 * f;
     }
     ub += group_sum_d<G>(row_live ? urow : 0.0);
   }
@@ -375,19 +400,19 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLeve
       }
       const double b = group_sum_d<G>(row_live ? br : 0.0);
       const double bp = group_sum_d<G>(row_live ? bpr : 0.0);
+      to_cell(m);
 #pragma unroll
       for (int c = 0; c < P; ++c) {
         Jb[c] += ub * (-(iw[c] - T[c]) / H + 2.0 * b * J[c] / (H * H));
         Tb[c] += ub * J[c] / H;
-        if (row_live) {
-          atomic_add_d(Rbar_row + clampi(ox + c + m, 0, W - 1), -ub * J[c] * (1.0 - f) / H);
-          atomic_add_d(Rbar_row + clampi(ox + c + m + 1, 0, W - 1), -ub * J[c] * f / H);
-        }
+        acc[c] -= ub * J[c] * (1.0 - f) / H;
+        acc[c + 1] -= ub * J[c] * f / H;
       }
       ub = ub * (1.0 - bp / H);
     }
     u0_adj = ub;
   }
+  flush();
 
   // ---- J = g - mean g, T and g live on the left level image
   double jb = 0.0;
@@ -412,45 +437,71 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLeve
   }
 }
 
-// Per pixel: template gradient g = Sobel_x(L) / 8 (reflect-101) -> level image.
+// Per pixel: the transposed template gradient g = Sobel_x(L) / 8 (reflect-101),
+// gathered: pixel (x, y) sums the gradient adjoints of the neighbours whose
+// stencil (after reflection) reads it.  One owner per pixel, no atomics.
 __global__ __launch_bounds__(kPixThreads) void k_sobel_adj(const PairLevel* tab, int npairs) {
   const PairLevel& a = tab[find_pair<0>(tab, npairs, (int)blockIdx.x)];
   const int idx = ((int)blockIdx.x - a.pyr0) * kPixThreads + (int)threadIdx.x;
   const int w = a.g.w, h = a.g.h;
   if (idx >= w * h) return;
   const int y = idx / w, x = idx - y * w;
-  const double v = gbl(a.Gbar)[(size_t)y * a.dpitch + x] / 8.0;
-  if (v == 0.0) return;
-  const int xm = reflect101(x - 1, w), xp = reflect101(x + 1, w);
-  const int ys[3] = {reflect101(y - 1, h), y, reflect101(y + 1, h)};
-  const double wy[3] = {1.0, 2.0, 1.0};
-  for (int t = 0; t < 3; ++t) {
-    double* row = a.Lbar + (size_t)ys[t] * a.dpitch;
-    atomic_add_d(row + xp, wy[t] * v);
-    atomic_add_d(row + xm, -wy[t] * v);
+  const auto Gb = gbl(a.Gbar);
+  double acc = 0.0;
+  for (int yy = max(y - 1, 0); yy <= min(y + 1, h - 1); ++yy) {
+    // rows yy-1, yy, yy+1 of the stencil weigh 1, 2, 1
+    const double wy = (reflect101(yy - 1, h) == y ? 1.0 : 0.0) + (yy == y ? 2.0 : 0.0) +
+                      (reflect101(yy + 1, h) == y ? 1.0 : 0.0);
+    if (wy == 0.0) continue;
+    for (int xx = max(x - 1, 0); xx <= min(x + 1, w - 1); ++xx) {
+      const double wx = (reflect101(xx + 1, w) == x ? 1.0 : 0.0) - (reflect101(xx - 1, w) == x ? 1.0 : 0.0);
+      if (wx != 0.0) acc += wy * wx * Gb[(size_t)yy * a.dpitch + xx];
+    }
   }
+  if (acc != 0.0) gbl(a.Lbar)[(size_t)y * a.dpitch + x] += acc / 8.0;
 }
 
-// Per pixel of level n >= 1: the transposed binomial pyramid step into level n-1.
+// Binomial tap weight with which level-(n+1) sample k (at 2k + t - 2, t = 0..4,
+// reflect-101 in a source of length n) reads source index i.
+BDIS_DEV double pyr_tap_weight(int k, int i, int n) {
+  const double kb[5] = {1.0, 4.0, 6.0, 4.0, 1.0};
+  double wgt = 0.0;
+#pragma unroll
+  for (int t = 0; t < 5; ++t)
+    if (reflect101(2 * k + t - 2, n) == i) wgt += kb[t];
+  return wgt;
+}
+
+// Per pixel of level n (n < coarsest): the transposed binomial pyramid step
+// from level n+1, gathered.  Parent samples k read source rows 2k-2 .. 2k+2
+// (reflected at most once), so only k in [i/2 - 2, i/2 + 2] can reach i.
 __global__ __launch_bounds__(kPixThreads) void k_pyr_adj(const PairLevel* tab, int npairs) {
   const PairLevel& a = tab[find_pair<0>(tab, npairs, (int)blockIdx.x)];
+  if (a.upLbar == nullptr) return;
   const int idx = ((int)blockIdx.x - a.pyr0) * kPixThreads + (int)threadIdx.x;
   const int w = a.g.w, h = a.g.h;
   if (idx >= w * h) return;
   const int y = idx / w, x = idx - y * w;
-  const double vl = gbl(a.Lbar)[(size_t)y * a.dpitch + x] / 256.0;
-  const double vr = gbl(a.Rbar)[(size_t)y * a.dpitch + x] / 256.0;
-  if (vl == 0.0 && vr == 0.0) return;
-  const int kb[5] = {1, 4, 6, 4, 1};
-  for (int b = 0; b < 5; ++b) {
-    const size_t row = (size_t)reflect101(2 * y + b - 2, a.sh) * a.srcdpitch;
-    for (int c = 0; c < 5; ++c) {
-      const int xx = reflect101(2 * x + c - 2, a.sw);
-      const double wgt = (double)(kb[c] * kb[b]);
-      if (vl != 0.0) atomic_add_d(a.srcLbar + row + xx, wgt * vl);
-      if (vr != 0.0) atomic_add_d(a.srcRbar + row + xx, wgt * vr);
+  const int ky0 = max(y / 2 - 2, 0), ky1 = min(y / 2 + 2, a.uph - 1);
+  const int kx0 = max(x / 2 - 2, 0), kx1 = min(x / 2 + 2, a.upw - 1);
+  double wxs[5];
+  for (int kx = kx0; kx <= kx1; ++kx) wxs[kx - kx0] = pyr_tap_weight(kx, x, w);
+  const auto uL = gbl(a.upLbar), uR = gbl(a.upRbar);
+  double sl = 0.0, sr = 0.0;
+  for (int ky = ky0; ky <= ky1; ++ky) {
+    const double wy = pyr_tap_weight(ky, y, h);
+    if (wy == 0.0) continue;
+    const size_t row = (size_t)ky * a.updpitch;
+    for (int kx = kx0; kx <= kx1; ++kx) {
+      const double wgt = wy * wxs[kx - kx0];
+      if (wgt == 0.0) continue;
+      sl += wgt * uL[row + kx];
+      sr += wgt * uR[row + kx];
     }
   }
+  const size_t o = (size_t)y * a.dpitch + x;
+  if (sl != 0.0) gbl(a.Lbar)[o] += sl / 256.0;
+  if (sr != 0.0) gbl(a.Rbar)[o] += sr / 256.0;
 }
 
 // Level 0, per pixel: image gradients out (float32, dense W x H).

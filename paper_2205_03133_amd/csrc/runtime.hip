@@ -464,8 +464,13 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
           e.srcdL = BD(lay.ld[n - 1]);
           e.srcdR = BD(lay.rd[n - 1]);
           e.srcdpitch = lay.dpitch[n - 1];
-          e.srcLbar = BD(lay.lbar[n - 1]);
-          e.srcRbar = BD(lay.rbar[n - 1]);
+        }
+        if (n + 1 < q.levels) {
+          e.upLbar = BD(lay.lbar[n + 1]);
+          e.upRbar = BD(lay.rbar[n + 1]);
+          e.upw = lay.g[n + 1].w;
+          e.uph = lay.g[n + 1].h;
+          e.updpitch = lay.dpitch[n + 1];
         }
         e.Ld = BD(lay.ld[n]);
         e.Rd = BD(lay.rd[n]);
@@ -775,7 +780,7 @@ bdis_status run_backward(bdis_ctx* c, std::vector<PairSpec> pairs, double* grad_
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "backward launch");
   }
-  for (int n = pl.max_levels - 1; n >= 1; --n) {
+  for (int n = pl.max_levels - 2; n >= 0; --n) {  // level n+1 -> level n
     const long tmk = timing_start(c, BDIS_K_BACKWARD, st);
     e = launch_pyramid_adj(c->tab_dev + pl.tab_first[n], pl.tab_count[n], pl.pyr_blocks[n], st);
     timing_stop(c, tmk, st);
