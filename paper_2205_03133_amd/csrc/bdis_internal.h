@@ -155,6 +155,7 @@ constexpr int kFuseTx = 64, kFuseTy = 4;    // fusion: 64 x 4 pixels per workgro
 
 // Workgroups of the float-path search (fixed size) and of per-pixel adjoint launches.
 constexpr int kSearchF64Threads = 256;
+constexpr size_t kAdjTileBytes = 64 * 1024;  // LDS accumulation tiles of the search adjoint
 constexpr int kPixThreads = 256;
 
 // Search workgroup sizes the tuner may pick (threads; patches = threads / G).
@@ -262,7 +263,8 @@ BDIS_DEV double group_sum_d(double v) {
 }
 
 // Hardware FP64 atomic add on global memory (accumulation of adjoints).
-BDIS_DEV void atomic_add_d(double* p, double v) { unsafeAtomicAdd(p, v); }
+// Global-memory FP64 add (every adjoint scatter targets HBM arrays).
+BDIS_DEV void atomic_add_d(double* p, double v) { (void)__builtin_amdgcn_global_atomic_fadd_f64(gbl(p), v); }
 
 // Reflect-101 index for |overshoot| < n (the only case the kernels produce).
 BDIS_DEV int reflect101(int i, int n) {

@@ -267,27 +267,12 @@ __global__ void k_tau_adj(const PairLevel* tab, int npairs, LevelParams lp) {
   sc[6] = 0.0;
 }
 
-// Per patch (lane per patch row): window and search adjoints, recomputing the
-// warps from the saved iterates; scatters into the level images, the template
-// gradient image and the parent displacement map.
 template <int P>
-__global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLevel* tab, int npairs, LevelParams lp) {
+BDIS_DEV void patch_adj(const PairLevel& a, const LevelParams& lp, int k, int r, int ox, int oy, int oxa, int xr0,
+                        int twl, int twr, double* sL, double* sG, double* sR) {
   constexpr int G = group_lanes(P);
-  constexpr int NPB = kSearchF64Threads / G;
   constexpr int N = P * P;
-  const PairLevel& a = tab[find_pair<1>(tab, npairs, (int)blockIdx.x)];
-  const int blk = (int)blockIdx.x - a.search0;
-  const int tid = threadIdx.x;
-  const int q = tid / G, r = tid % G;
-  const int W = a.g.w, Hh = a.g.h, S = lp.S;
-  const int j = blk / a.search_nbx;
-  const int i0 = (blk % a.search_nbx) * NPB;
-  const bool live = (i0 + q) < a.g.nx;
-  const int i = live ? i0 + q : a.g.nx - 1;
-  const int k = j * a.g.nx + i;
-  // whole groups skip rejected or idle patches (uniform within the group)
-  if (!live || !gbl(a.pa.acc)[k]) return;
-  const int ox = grid_origin(i, W, P, S), oy = grid_origin(j, Hh, P, S);
+  const int W = a.g.w, Hh = a.g.h;
   const bool row_live = r < P;
   const int rr = row_live ? r : P - 1;
   const auto Lg = gbl(a.Ld);
@@ -332,8 +317,14 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLeve
   auto flush = [&]() {
     if (have && row_live) {
 #pragma unroll
-      for (int c = 0; c <= P; ++c)
-        if (acc[c] != 0.0) atomic_add_d(Rbar_row + clampi(ox + mcur + c, 0, W - 1), acc[c]);
+      for (int c = 0; c <= P; ++c) {
+        if (acc[c] == 0.0) continue;
+        const int x = clampi(ox + mcur + c, 0, W - 1);
+        if (x - xr0 < twr)
+          unsafeAtomicAdd(sR + rr * twr + (x - xr0), acc[c]);
+        else
+          atomic_add_d(Rbar_row + x, acc[c]);
+      }
     }
 #pragma unroll
     for (int c = 0; c <= P; ++c) acc[c] = 0.0;
@@ -419,7 +410,16 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLeve
 #pragma unroll
   for (int c = 0; c < P; ++c) jb += Jb[c];
   const double jmean = group_sum_d<G>(row_live ? jb : 0.0) / (double)N;
-  if (row_live) {
+  if (row_live && twl > 0) {
+    double* Lrow = sL + rr * twl + (ox - oxa);
+    double* Grow = sG + rr * twl + (ox - oxa);
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      if (Tb[c] != 0.0) unsafeAtomicAdd(Lrow + c, Tb[c]);
+      const double gb = Jb[c] - jmean;
+      if (gb != 0.0) unsafeAtomicAdd(Grow + c, gb);
+    }
+  } else if (row_live) {
     double* Lrow = a.Lbar + (size_t)(oy + rr) * dp + ox;
     double* Grow = a.Gbar + (size_t)(oy + rr) * dp + ox;
 #pragma unroll
@@ -434,6 +434,72 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLeve
     const double cx = 0.5 * ((double)ox + 0.5 * (double)(P - 1));
     const double cy = 0.5 * ((double)oy + 0.5 * (double)(P - 1));
     bilinear_adj(a.par_ubar_adj, a.pw, a.ph, cx, cy, 2.0 * u0_adj);
+  }
+}
+
+// Per patch (lane per patch row): window and search adjoints, recomputing the
+// warps from the saved iterates; scatters into the level images, the template
+// gradient image and the parent displacement map.
+//
+// The patches of one workgroup are consecutive in one patch row, so they share
+// their P image rows: their scatters into the left image, the gradient image
+// and the right image are summed in LDS tiles (rows oy .. oy+P-1; the left
+// tiles start at the first patch's origin, the right tile at the lowest warp
+// cell any patch of the workgroup visits) and written to HBM once per tile
+// element.  Right-image samples beyond the tile go straight to HBM.  twl = 0
+// (tiles too large for LDS) sends everything straight to HBM.
+template <int P>
+__global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLevel* tab, int npairs, LevelParams lp,
+                                                                  int twl, int twr) {
+  constexpr int G = group_lanes(P);
+  constexpr int NPB = kSearchF64Threads / G;
+  constexpr int N = P * P;
+  extern __shared__ double s_tile[];  // [P][twl] left, [P][twl] gradient, [P][twr] right
+  __shared__ int s_lo;
+  const PairLevel& a = tab[find_pair<1>(tab, npairs, (int)blockIdx.x)];
+  const int blk = (int)blockIdx.x - a.search0;
+  const int tid = threadIdx.x;
+  const int q = tid / G, r = tid % G;
+  const int W = a.g.w, Hh = a.g.h, S = lp.S;
+  const int j = blk / a.search_nbx;
+  const int i0 = (blk % a.search_nbx) * NPB;
+  const bool live = (i0 + q) < a.g.nx;
+  const int i = live ? i0 + q : a.g.nx - 1;
+  const int k = j * a.g.nx + i;
+  // whole groups skip rejected or idle patches (uniform within the group)
+  const bool active = live && gbl(a.pa.acc)[k] != 0;
+  const int ox = grid_origin(i, W, P, S), oy = grid_origin(j, Hh, P, S);
+  const int oxa = grid_origin(i0, W, P, S);
+  double* sL = s_tile;
+  double* sG = s_tile + P * twl;
+  double* sR = s_tile + 2 * P * twl;
+  if (twl > 0) {
+    for (int e = tid; e < P * (2 * twl + twr); e += kSearchF64Threads) s_tile[e] = 0.0;
+    if (tid == 0) s_lo = INT_MAX;
+    __syncthreads();
+    if (active && r == 0) {  // lowest warp cell of this patch: window and iterations
+      int mlo = (int)floor(gbl(a.pa.u)[k] - 1.0);
+      const auto uh = gbl(a.uhist) + (size_t)k * (lp.K + 1);
+      for (int t = 0; t < lp.K; ++t) mlo = min(mlo, (int)floor(uh[t]));
+      atomicMin(&s_lo, ox + mlo);
+    }
+    __syncthreads();
+    if (s_lo == INT_MAX) return;  // no accepted patch here (uniform)
+  }
+  const int xr0 = twl > 0 ? s_lo : 0;
+  if (active) patch_adj<P>(a, lp, k, r, ox, oy, oxa, xr0, twl, twr, sL, sG, sR);
+  if (twl == 0) return;
+  __syncthreads();
+  const int dp = a.dpitch;
+  for (int e = tid; e < P * twl; e += kSearchF64Threads) {
+    const int rr = e / twl, x = oxa + e % twl;
+    const size_t o = (size_t)(oy + rr) * dp + x;
+    if (sL[e] != 0.0) atomic_add_d(a.Lbar + o, sL[e]);
+    if (sG[e] != 0.0) atomic_add_d(a.Gbar + o, sG[e]);
+  }
+  for (int e = tid; e < P * twr; e += kSearchF64Threads) {
+    const int rr = e / twr, x = xr0 + e % twr;
+    if (sR[e] != 0.0) atomic_add_d(a.Rbar + (size_t)(oy + rr) * dp + x, sR[e]);
   }
 }
 
@@ -517,7 +583,14 @@ __global__ __launch_bounds__(kPixThreads) void k_grad_out(const PairLevel* tab, 
 
 template <int P>
 hipError_t launch_sadj(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
-  hipLaunchKernelGGL(k_search_adj<P>, dim3(nblocks), dim3(kSearchF64Threads), 0, s, tab, npairs, lp);
+  constexpr int NPB = kSearchF64Threads / group_lanes(P);
+  int twl = (NPB - 1) * lp.S + P, twr = twl + 64;
+  size_t bytes = sizeof(double) * (size_t)P * (2 * twl + twr);
+  if (bytes > kAdjTileBytes) {
+    twl = twr = 0;
+    bytes = 0;
+  }
+  hipLaunchKernelGGL(k_search_adj<P>, dim3(nblocks), dim3(kSearchF64Threads), bytes, s, tab, npairs, lp, twl, twr);
   return hipGetLastError();
 }
 
