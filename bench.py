@@ -238,6 +238,8 @@ def main():
     ap.add_argument("--diff-steps", type=int, default=5)
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run one plain float32 copy kernel over MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU form "
@@ -268,6 +270,14 @@ def main():
         line["batch_1080p"] = bench_batch(bdis, torch, args)
     if not args.no_diff:
         line["differentiable_c4"] = bench_diff(bdis, torch, args)
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)  # reads and writes exactly 4n bytes
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = 4 * n
     if not args.no_cpu_baseline:
         from oracle import ref
         log("cpu baseline (FP64 oracle)")

@@ -17,6 +17,8 @@
 //            J = g - mean g, H = sum J^2, g = Sobel_x(L) / 8, T = L on the patch
 //   window   SSD_d = sum (e - mean e)^2, e = I_w(u + d) - T
 //   pyramid  L_n = B5 * L_{n-1} (even samples, reflect-101)
+#include <type_traits>
+
 #include "bdis_internal.h"
 
 namespace bdis {
@@ -74,19 +76,36 @@ __global__ __launch_bounds__(kPixThreads) void k_seed(const PairLevel* tab, int 
   if (a.vmap_adj) gbl(a.vmap_adj)[idx] = (ok && a.grad_var && lp.variance) ? (double)gbl(a.grad_var)[idx] : 0.0;
 }
 
-// Per patch (one lane): gather the fusion adjoint over the patch's pixels.
-__global__ __launch_bounds__(kPixThreads) void k_fuse_adj(const PairLevel* tab, int npairs, LevelParams lp) {
-  __shared__ double s_m1[kMaxPatch], s_dm1[kMaxPatch];
-  __shared__ double s_buf[kPixThreads];
-  const PairLevel& a = tab[find_pair<2>(tab, npairs, (int)blockIdx.x)];
+// Per patch: gather the fusion adjoint over the patch's pixels.  A workgroup
+// holds NPB consecutive patches of one patch row (laid out like the search);
+// each patch has a group of lanes, one per patch column.  The P image rows are
+// streamed through LDS: per row, one lane per pixel reads the fused maps and
+// their adjoints (coalesced, once per workgroup) and forms the per-pixel terms
+//   A1 = gU/Z, A2 = gU U/Z, B1 = gQ/SM, B2 = gQ Q/SM, C1 = gV/Z^2, C2 = gV V/Z
+// (zero on holes); each patch lane then adds its column's mask-weighted terms.
+// With m the mask weight and d m its sigma_s derivative, per patch:
+//   du = pi sum m A1,   dpi = sum m (u A1 - A2 + B1) + sum (2 pi s2 m^2 C1 - 2 m C2),
+//   dsig2 = pi^2 sum m^2 C1,
+//   dsigma_s += sum dm (pi u A1 - pi A2 + pi B1 - B2 + 2 pi^2 s2 m C1 - 2 pi C2).
+template <int P>
+__global__ __launch_bounds__(kSearchF64Threads) void k_fuse_adj(const PairLevel* tab, int npairs, LevelParams lp) {
+  constexpr int G = group_lanes(P);
+  constexpr int NPB = kSearchF64Threads / G;
+  constexpr int NT = 6;  // per-pixel terms
+  __shared__ double s_m1[P], s_dm1[P];
+  __shared__ double s_buf[kSearchF64Threads];
+  __shared__ double s_t[NT][kSearchF64Threads];
+  const PairLevel& a = tab[find_pair<1>(tab, npairs, (int)blockIdx.x)];
+  const int blk = (int)blockIdx.x - a.search0;
   const int tid = threadIdx.x;
-  const int P = lp.P, S = lp.S;
+  const int q = tid / G, c = tid % G;
+  const int S = lp.S, W = a.g.w;
   if (tid < P) {
     // m1(t) = sum_c exp(-(t - c)^2 / (2 s^2)) and its derivative in s
     const double sg = (double)lp.sigma_s;
     double m = 0.0, dm = 0.0;
-    for (int c = 0; c < P; ++c) {
-      const double d2 = (double)((tid - c) * (tid - c));
+    for (int cc = 0; cc < P; ++cc) {
+      const double d2 = (double)((tid - cc) * (tid - cc));
       const double e = exp(-d2 / (2.0 * sg * sg));
       m += e;
       dm += e * d2 / (sg * sg * sg);
@@ -94,53 +113,73 @@ __global__ __launch_bounds__(kPixThreads) void k_fuse_adj(const PairLevel* tab, 
     s_m1[tid] = m;
     s_dm1[tid] = dm;
   }
-  __syncthreads();
-  const int k = ((int)blockIdx.x - a.prob0) * kPixThreads + tid;
-  double ss_adj = 0.0;
+  const int j = blk / a.search_nbx;
+  const int i0 = (blk % a.search_nbx) * NPB;
+  const int i = i0 + q;
+  const int oy = grid_origin(j, a.g.h, P, S);
+  const int oxa = grid_origin(i0, W, P, S);
+  const int tw = min((NPB - 1) * S + P, W - oxa);  // tile columns (<= 256)
   const bool finest = lp.level == lp.finest;
-  if (k < a.g.nx * a.g.ny) {
-    const D4 d = ld4(a.pa.dens + k);
-    if (d.y >= 0.0) {
-      const int i = k % a.g.nx, j = k / a.g.nx;
-      const int ox = grid_origin(i, a.g.w, P, S), oy = grid_origin(j, a.g.h, P, S);
-      const auto ub = gbl(finest ? a.ubar_keep : a.ubar);
-      const auto qm = gbl(finest ? a.qmap_keep : a.qmap);
-      const auto zm = gbl(a.zmap);
-      const auto sm = gbl(a.smmap);
-      const auto gu = gbl(a.ubar_adj);
-      const auto gq = gbl(a.qmap_adj);
-      const bool vt = finest && lp.variance && a.vmap_adj != nullptr;
-      const double u = d.x, pi = d.y, s2 = vt ? d.z : 0.0;
-      double u_adj = 0.0, pi_adj = 0.0, sig_adj = 0.0;
-      for (int b = 0; b < P; ++b) {
-        const size_t row = (size_t)(oy + b) * a.g.w + ox;
-        for (int c = 0; c < P; ++c) {
-          const size_t idx = row + c;
-          const double Z = zm[idx];
-          if (!(Z > 0.0)) continue;
-          const double m = s_m1[b] * s_m1[c];
-          const double W = m * pi;
-          const double SM = sm[idx], U = ub[idx], Qx = qm[idx];
-          const double gU = gu[idx], gQ = gq[idx];
-          double mbar = gU * pi * (u - U) / Z + gQ * (pi - Qx) / SM;
-          u_adj += gU * W / Z;
-          pi_adj += gU * m * (u - U) / Z + gQ * m / SM;
-          if (vt) {
-            const double gV = gbl(a.vmap_adj)[idx], V = gbl(a.vmap)[idx];
-            const double t = 2.0 * W * s2 / (Z * Z) - 2.0 * V / Z;
-            pi_adj += gV * m * t;
-            sig_adj += gV * W * W / (Z * Z);
-            mbar += gV * pi * t;
-          }
-          ss_adj += mbar * (s_dm1[b] * s_m1[c] + s_m1[b] * s_dm1[c]);
+  const bool vt = finest && lp.variance && a.vmap_adj != nullptr;
+  const auto ub = gbl(finest ? a.ubar_keep : a.ubar);
+  const auto qm = gbl(finest ? a.qmap_keep : a.qmap);
+
+  bool active = false;
+  int k = 0, col = 0;
+  D4 d{};
+  if (i < a.g.nx) {
+    k = j * a.g.nx + i;
+    d = ld4(a.pa.dens + k);
+    active = d.y >= 0.0 && c < P;  // accepted patch, live column
+    col = grid_origin(i, W, P, S) - oxa + c;
+  }
+  const double u = d.x, pi = d.y, s2 = vt ? d.z : 0.0;
+  double su = 0.0, spi = 0.0, ssg = 0.0, sss = 0.0;
+  for (int b = 0; b < P; ++b) {
+    __syncthreads();  // previous row consumed (and the mask sums written)
+    if (tid < tw) {
+      const size_t idx = (size_t)(oy + b) * W + oxa + tid;
+      const double Z = gbl(a.zmap)[idx];
+      double t[NT] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      if (Z > 0.0) {
+        const double gU = gbl(a.ubar_adj)[idx], gQ = gbl(a.qmap_adj)[idx];
+        const double SM = gbl(a.smmap)[idx];
+        t[0] = gU / Z;
+        t[1] = t[0] * ub[idx];
+        t[2] = gQ / SM;
+        t[3] = t[2] * qm[idx];
+        if (vt) {
+          const double gV = gbl(a.vmap_adj)[idx];
+          t[4] = gV / (Z * Z);
+          t[5] = gV * gbl(a.vmap)[idx] / Z;
         }
       }
-      gbl(a.pu_adj)[k] = u_adj;
-      gbl(a.ppi_adj)[k] = pi_adj;
-      gbl(a.psig_adj)[k] = sig_adj;
+#pragma unroll
+      for (int e = 0; e < NT; ++e) s_t[e][tid] = t[e];
+    }
+    __syncthreads();
+    if (active) {
+      const double mb = s_m1[b], dmb = s_dm1[b];
+      const double m = mb * s_m1[c], dm = dmb * s_m1[c] + mb * s_dm1[c];
+      const double A1 = s_t[0][col], A2 = s_t[1][col], B1 = s_t[2][col], B2 = s_t[3][col];
+      const double C1 = s_t[4][col], C2 = s_t[5][col];
+      su += m * A1;
+      spi += m * (u * A1 - A2 + B1) + 2.0 * pi * s2 * m * m * C1 - 2.0 * m * C2;
+      ssg += m * m * C1;
+      sss += dm * (pi * u * A1 - pi * A2 + pi * B1 - B2 + 2.0 * pi * pi * s2 * m * C1 - 2.0 * pi * C2);
     }
   }
-  block_atomic_sum(ss_adj, a.hyper_adj + 0, s_buf);
+  if (i < a.g.nx && d.y >= 0.0) {  // uniform over the group
+    su = group_sum_d<G>(su);
+    spi = group_sum_d<G>(spi);
+    ssg = group_sum_d<G>(ssg);
+    if (c == 0) {
+      gbl(a.pu_adj)[k] = pi * su;
+      gbl(a.ppi_adj)[k] = spi;
+      gbl(a.psig_adj)[k] = pi * pi * ssg;
+    }
+  }
+  block_atomic_sum(sss, a.hyper_adj + 0, s_buf);
 }
 
 // Per pixel above the finest level: holes took the parent estimate.
@@ -371,36 +410,62 @@ BDIS_DEV void patch_adj(const PairLevel& a, const LevelParams& lp, int k, int r,
     ub += group_sum_d<G>(row_live ? urow : 0.0);
   }
 
-  // ---- reset, then the K iterations in reverse
+  // ---- reset, then the K iterations in reverse.  Within one unit cell m the
+  // warp is I_w(u) = (1 - f) Ra + f Rb with fixed samples Ra, Rb, so the
+  // per-column adjoints of consecutive iterations in that cell only differ by
+  // scalar factors: those are summed (al, be, de) and applied once per cell.
   double u0_adj = ub;
   const bool reset = gbl(a.reset)[k] != 0;
   if (!reset && H >= kEpsH) {
+    double crow = 0.0;
+#pragma unroll
+    for (int c = 0; c < P; ++c) crow += J[c] * T[c];
+    const double cT = group_sum_d<G>(row_live ? crow : 0.0);
     const auto uh = gbl(a.uhist) + (size_t)k * (lp.K + 1);
+    double Rv[P + 1];
+    double C0 = 0.0, C1 = 0.0, al = 0.0, be = 0.0, de = 0.0;
+    int mc = 0;
+    bool cell = false;
+    auto apply = [&]() {
+      if (!cell) return;
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        Jb[c] += -al * Rv[c] - be * Rv[c + 1] + (al + be) * T[c] + de * J[c];
+        Tb[c] += (al + be) * J[c];
+        acc[c] -= al * J[c];
+        acc[c + 1] -= be * J[c];
+      }
+      al = be = de = 0.0;
+    };
     for (int t = lp.K - 1; t >= 0; --t) {
       const double ut = uh[t];
       const double fm = floor(ut);
       const int m = (int)fm;
       const double f = ut - fm;
-      double iw[P], br = 0.0, bpr = 0.0;
+      if (!cell || m != mc) {
+        apply();
+        to_cell(m);
+        double c0 = 0.0, c1 = 0.0;
 #pragma unroll
-      for (int c = 0; c < P; ++c) {
-        const double ra = Rrow[clampi(ox + c + m, 0, W - 1)], rb = Rrow[clampi(ox + c + m + 1, 0, W - 1)];
-        iw[c] = (1.0 - f) * ra + f * rb;
-        br += J[c] * (iw[c] - T[c]);
-        bpr += J[c] * (rb - ra);
-      }
-      const double b = group_sum_d<G>(row_live ? br : 0.0);
-      const double bp = group_sum_d<G>(row_live ? bpr : 0.0);
-      to_cell(m);
+        for (int c = 0; c <= P; ++c) Rv[c] = Rrow[clampi(ox + c + m, 0, W - 1)];
 #pragma unroll
-      for (int c = 0; c < P; ++c) {
-        Jb[c] += ub * (-(iw[c] - T[c]) / H + 2.0 * b * J[c] / (H * H));
-        Tb[c] += ub * J[c] / H;
-        acc[c] -= ub * J[c] * (1.0 - f) / H;
-        acc[c + 1] -= ub * J[c] * f / H;
+        for (int c = 0; c < P; ++c) {
+          c0 += J[c] * Rv[c];
+          c1 += J[c] * Rv[c + 1];
+        }
+        C0 = group_sum_d<G>(row_live ? c0 : 0.0) - cT;
+        C1 = group_sum_d<G>(row_live ? c1 : 0.0) - cT;
+        mc = m;
+        cell = true;
       }
-      ub = ub * (1.0 - bp / H);
+      const double b = (1.0 - f) * C0 + f * C1;  // sum J (I_w - T)
+      const double s1 = ub / H;
+      al += s1 * (1.0 - f);
+      be += s1 * f;
+      de += 2.0 * s1 * b / H;
+      ub = ub * (1.0 - (C1 - C0) / H);
     }
+    apply();
     u0_adj = ub;
   }
   flush();
@@ -581,37 +646,49 @@ __global__ __launch_bounds__(kPixThreads) void k_grad_out(const PairLevel* tab, 
   if (a.grad_right) gbl(a.grad_right)[idx] = (float)gbl(a.Rbar)[(size_t)y * a.dpitch + x];
 }
 
-template <int P>
-hipError_t launch_sadj(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
-  constexpr int NPB = kSearchF64Threads / group_lanes(P);
-  int twl = (NPB - 1) * lp.S + P, twr = twl + 64;
-  size_t bytes = sizeof(double) * (size_t)P * (2 * twl + twr);
-  if (bytes > kAdjTileBytes) {
-    twl = twr = 0;
-    bytes = 0;
+// Calls f(std::integral_constant<int, P>) for the runtime patch size.
+template <typename F>
+hipError_t by_patch(int P, F&& f) {
+  switch (P) {
+    case 3: return f(std::integral_constant<int, 3>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 5: return f(std::integral_constant<int, 5>{});
+    case 6: return f(std::integral_constant<int, 6>{});
+    case 7: return f(std::integral_constant<int, 7>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    case 9: return f(std::integral_constant<int, 9>{});
+    case 10: return f(std::integral_constant<int, 10>{});
+    case 11: return f(std::integral_constant<int, 11>{});
+    case 12: return f(std::integral_constant<int, 12>{});
+    case 13: return f(std::integral_constant<int, 13>{});
+    case 14: return f(std::integral_constant<int, 14>{});
+    case 15: return f(std::integral_constant<int, 15>{});
+    case 16: return f(std::integral_constant<int, 16>{});
+    default: return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(k_search_adj<P>, dim3(nblocks), dim3(kSearchF64Threads), bytes, s, tab, npairs, lp, twl, twr);
-  return hipGetLastError();
 }
 
 hipError_t launch_search_adj(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
-  switch (lp.P) {
-    case 3: return launch_sadj<3>(tab, npairs, nblocks, lp, s);
-    case 4: return launch_sadj<4>(tab, npairs, nblocks, lp, s);
-    case 5: return launch_sadj<5>(tab, npairs, nblocks, lp, s);
-    case 6: return launch_sadj<6>(tab, npairs, nblocks, lp, s);
-    case 7: return launch_sadj<7>(tab, npairs, nblocks, lp, s);
-    case 8: return launch_sadj<8>(tab, npairs, nblocks, lp, s);
-    case 9: return launch_sadj<9>(tab, npairs, nblocks, lp, s);
-    case 10: return launch_sadj<10>(tab, npairs, nblocks, lp, s);
-    case 11: return launch_sadj<11>(tab, npairs, nblocks, lp, s);
-    case 12: return launch_sadj<12>(tab, npairs, nblocks, lp, s);
-    case 13: return launch_sadj<13>(tab, npairs, nblocks, lp, s);
-    case 14: return launch_sadj<14>(tab, npairs, nblocks, lp, s);
-    case 15: return launch_sadj<15>(tab, npairs, nblocks, lp, s);
-    case 16: return launch_sadj<16>(tab, npairs, nblocks, lp, s);
-    default: return hipErrorInvalidValue;
-  }
+  return by_patch(lp.P, [&](auto pc) {
+    constexpr int P = decltype(pc)::value;
+    constexpr int NPB = kSearchF64Threads / group_lanes(P);
+    int twl = (NPB - 1) * lp.S + P, twr = twl + 64;
+    size_t bytes = sizeof(double) * (size_t)P * (2 * twl + twr);
+    if (bytes > kAdjTileBytes) {
+      twl = twr = 0;
+      bytes = 0;
+    }
+    hipLaunchKernelGGL(k_search_adj<P>, dim3(nblocks), dim3(kSearchF64Threads), bytes, s, tab, npairs, lp, twl, twr);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_fuse_adj(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
+  return by_patch(lp.P, [&](auto pc) {
+    constexpr int P = decltype(pc)::value;
+    hipLaunchKernelGGL(k_fuse_adj<P>, dim3(nblocks), dim3(kSearchF64Threads), 0, s, tab, npairs, lp);
+    return hipGetLastError();
+  });
 }
 
 }  // namespace
@@ -622,11 +699,12 @@ hipError_t launch_backward_level(const PairLevel* tab, int npairs, const int* bl
   const dim3 pix(kPixThreads);
   hipLaunchKernelGGL(k_adj_init, dim3((npairs + 63) / 64), dim3(64), 0, s, tab, npairs);
   if (lp.level == lp.finest) hipLaunchKernelGGL(k_seed, dim3(blocks[0]), pix, 0, s, tab, npairs, lp);
-  hipLaunchKernelGGL(k_fuse_adj, dim3(blocks[2]), pix, 0, s, tab, npairs, lp);
+  hipError_t e = launch_fuse_adj(tab, npairs, blocks[1], lp, s);
+  if (e != hipSuccess) return e;
   if (lp.level > lp.finest) hipLaunchKernelGGL(k_hole_adj, dim3(blocks[0]), pix, 0, s, tab, npairs);
   hipLaunchKernelGGL(k_prob_adj, dim3(blocks[2]), pix, 0, s, tab, npairs, lp);
   hipLaunchKernelGGL(k_tau_adj, dim3((npairs + 63) / 64), dim3(64), 0, s, tab, npairs, lp);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = launch_search_adj(tab, npairs, blocks[1], lp, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_sobel_adj, dim3(blocks[0]), pix, 0, s, tab, npairs);
