@@ -40,11 +40,36 @@ def search_flops(bdis, p, w, h, levels=None):
     return tot
 
 
-def roofline(flops_per_step, steps, timing, kernel_name):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_hbm_traffic_c2_640x480_and_c5_1080p_batch64.md")
+SEARCH_SRC = os.path.join(ROOT, "paper_2205_03133_amd", "csrc", "k_search.hip")
+
+
+def measured_traffic(workload):
+    """HBM bytes per search launch from the committed FETCH_SIZE/WRITE_SIZE counter
+    runs (scaled by the copy-kernel calibration), or None once the kernel source
+    differs from the one the counters were taken on."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+        src = hashlib.sha256(open(SEARCH_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    sha, val = None, None
+    for ln in text.splitlines():
+        f = ln.split()
+        if len(f) == 3 and f[0] == "source_sha256":
+            sha = f[2]
+        if len(f) == 3 and f[0] == "traffic_bytes_per_launch" and f[1] == workload:
+            val = int(f[2])
+    return val if sha == src else None
+
+
+def roofline(flops_per_step, steps, timing, kernel_name, workload):
     s_ms, s_n = timing["search"]
     achieved = flops_per_step * steps / (s_ms * 1e-3) / 1e12
     return dict(bound="alu", achieved=round(achieved, 3), peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5), traffic=None, kernel=kernel_name,
+                frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5), traffic=measured_traffic(workload),
+                traffic_unit="bytes per launch", kernel=kernel_name,
                 avg_launch_us=round(s_ms * 1e3 / max(s_n, 1), 3), launches=s_n)
 
 
@@ -158,7 +183,7 @@ def bench_batch(bdis, torch, args):
                 config=dict(workload="1920x1080 synthetic pairs (planes+bumps 0-192 px, 30% textureless, "
                                      "dark gain U(0.2,0.5), noise 3), L=6 P=12 S=4 K=16 variance on",
                             share="64 of the 512-pair stream"),
-                roofline=roofline(flops, steps_ev, tk, "k_search_u8<12>"), kernels=kernel_table(tk),
+                roofline=roofline(flops, steps_ev, tk, "k_search_u8<12>", "1080p_batch64"), kernels=kernel_table(tk),
                 epe_median_px=round(epe, 4))
 
 
@@ -262,7 +287,7 @@ def main():
                 config=dict(workload="640x480 synthetic stereo pair (planes+bumps 0-64 px, 20% textureless, "
                                      "highlights, gain U(0.8,1.2), noise 2), L=5 P=8 S=3 K=16 variance on",
                             global_batch=1, pairs_per_step=1),
-                roofline=roofline(search_flops(bdis, p, w, h), args.steps, s["tk"], "k_search_u8<8>"),
+                roofline=roofline(search_flops(bdis, p, w, h), args.steps, s["tk"], "k_search_u8<8>", "640x480"),
                 kernels=kernel_table(s["tk"]),
                 ms_per_step_with_kernel_events=round(s["dt_ev"] * 1e3 / args.steps, 4),
                 epe_median_px=round(s["epe"], 4))
