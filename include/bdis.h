@@ -55,7 +55,9 @@ typedef enum {
  * list of Sec. IV-A where the paper gives a value. */
 typedef struct {
   int32_t levels;          /* L, 1..8: pyramid levels n = L-1 (coarsest) .. finest_level     */
-  int32_t finest_level;    /* f: finest processed level; 0 (full resolution) is supported   */
+  int32_t finest_level;    /* f, 0..L-1: finest searched level (paper: scale 2^1 -> f = 1);  */
+                           /* f > 0 upsamples its maps to W x H (bilinear at x / 2^f; the    */
+                           /* disparity scaled by 2^f, the variance by 4^f)                  */
   int32_t patch;           /* P, 3..16: square patch side (paper: 10)                        */
   int32_t stride;          /* S, 1..P: patch-grid stride (paper: overlap 0.55 -> S = 4)      */
   int32_t iters;           /* K, 1..256: fixed inverse-compositional iterations (paper: 12)  */
@@ -164,6 +166,16 @@ bdis_status bdis_backward(bdis_ctx* ctx, const float* grad_disparity, const floa
                           float* grad_left, float* grad_right, double* grad_hyper, void* stream);
 bdis_status bdis_backward_batch(bdis_ctx* ctx, int n, const bdis_pair_grad* grads, double* grad_hyper,
                                 void* stream);
+
+/* Depth form (Eq. 14 and Eq. 18): for each pixel of a W x H disparity map (and
+ * its variance), depth = fb / d and depth variance = (fb)^2 / d^4 * var, where
+ * fb is focal length x baseline (depth comes out in the units of the
+ * baseline when d and f are in pixels).  Pixels with d <= 0 or NaN get NaN.
+ * All pointers are device pointers with row pitch `pitch` (elements) on the
+ * inputs and dense W x H outputs; `variance` and `depth_variance` may be NULL
+ * (together).  Asynchronous on `stream`.  Errors: BDIS_E_ARG. */
+bdis_status bdis_depth(bdis_ctx* ctx, const float* disparity, const float* variance, int w, int h, int pitch,
+                       float fb, float* depth, float* depth_variance, void* stream);
 
 /* Debug access to the intermediates of the last single-pair compute (the
  * call synchronises `stream`).  `what` selects the array (BDIS_DBG_*), bytes

@@ -33,6 +33,7 @@ typedef struct {
   double *uinit, *pipar, *u, *ssd, *rho, *acc, *post, *pi, *sigk2, *hess;
   /* maps */
   double *ubar, *qmap, *valid;
+  double *odisp, *ovar, *oconf; /* finest level f > 0: outputs before upsampling */
   double sigma_r2, tau, nacc, gamma;
   uint64_t dhash; /* hash of every discrete decision taken on this level */
 } ref_level;
@@ -297,7 +298,8 @@ static double patch_variance(const double* s, double tau, double thresh, double 
 static void free_level(ref_level* lv) {
   double** ptrs[] = {&lv->left, &lv->right, &lv->grad, &lv->uinit, &lv->pipar, &lv->u,
                      &lv->ssd,  &lv->rho,   &lv->acc,  &lv->post,  &lv->pi,    &lv->sigk2,
-                     &lv->hess, &lv->ubar,  &lv->qmap, &lv->valid};
+                     &lv->hess, &lv->ubar,  &lv->qmap, &lv->valid, &lv->odisp, &lv->ovar,
+                     &lv->oconf};
   for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); ++i) {
     free(*ptrs[i]);
     *ptrs[i] = NULL;
@@ -344,7 +346,7 @@ static int alloc_level(ref_level* lv, int w, int h, int P, int S) {
 static int check_params(const bdis_ref_params* p, int w, int h, int pitch) {
   if (!p) return BDIS_REF_E_ARG;
   if (p->levels < 1 || p->levels > MAX_LEVELS) return BDIS_REF_E_ARG;
-  if (p->finest_level != 0) return BDIS_REF_E_ARG;
+  if (p->finest_level < 0 || p->finest_level >= p->levels) return BDIS_REF_E_ARG;
   if (p->patch < 3 || p->stride < 1 || p->stride > p->patch || p->iters < 1) return BDIS_REF_E_ARG;
   if (!(p->sigma_s > 0.0) || !(p->sigma_r > 0.0)) return BDIS_REF_E_ARG;
   if (w < 1 || h < 1 || pitch < w) return BDIS_REF_E_ARG;
@@ -359,6 +361,54 @@ static int check_params(const bdis_ref_params* p, int w, int h, int pitch) {
     if (n >= p->finest_level && (lw < p->patch || lh < p->patch)) return BDIS_REF_E_SIZE;
     lw = (lw + 1) >> 1;
     lh = (lh + 1) >> 1;
+  }
+  return BDIS_REF_OK;
+}
+
+/* Finest level f > 0 (Sec. IV-A runs levels 5..1): the full-resolution
+ * outputs sample the level-f maps bilinearly at (x / 2^f, y / 2^f) -- the
+ * pyramid keeps the even pixels, so level-0 pixel 2^f k lies on level-f pixel
+ * k -- clamped at the last row and column; disparity is scaled by 2^f (level-f
+ * pixels to full-resolution pixels) and variance by 4^f.  A pixel is invalid
+ * (NaN, NaN, confidence 0) when any sample it gives a nonzero weight is. */
+static void upsample(const ref_level* lf, int f, int w, int h, int variance, double* disp,
+                     double* var, double* conf) {
+  const double sc = (double)(1 << f);
+  for (int y = 0; y < h; ++y)
+    for (int x = 0; x < w; ++x) {
+      double sx = x / sc, sy = y / sc;
+      int x0 = (int)floor(sx), y0 = (int)floor(sy);
+      double ax = sx - x0, ay = sy - y0;
+      int xs[2] = {x0, x0 + 1 < lf->w ? x0 + 1 : lf->w - 1};
+      int ys[2] = {y0, y0 + 1 < lf->h ? y0 + 1 : lf->h - 1};
+      double wx[2] = {1.0 - ax, ax}, wy[2] = {1.0 - ay, ay};
+      double d = 0.0, v = 0.0, c = 0.0;
+      int ok = 1;
+      for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a) {
+          double wt = wx[a] * wy[b];
+          if (wt == 0.0) continue;
+          size_t k = (size_t)ys[b] * lf->w + xs[a];
+          if (isnan(lf->odisp[k])) ok = 0;
+          d += wt * lf->odisp[k];
+          v += wt * lf->ovar[k];
+          c += wt * lf->oconf[k];
+        }
+      size_t o = (size_t)y * w + x;
+      disp[o] = ok ? sc * d : NAN;
+      if (var) var[o] = (ok && variance) ? sc * sc * v : NAN;
+      if (conf) conf[o] = ok ? c : 0.0;
+    }
+}
+
+int bdis_ref_depth(const double* disp, const double* var, long n, double fb, double* depth,
+                   double* depth_var) {
+  if (!disp || !depth || n < 0 || !(fb > 0.0)) return BDIS_REF_E_ARG;
+  for (long i = 0; i < n; ++i) {
+    double d = disp[i];
+    int ok = d > 0.0; /* NaN compares false */
+    depth[i] = ok ? fb / d : NAN;
+    if (depth_var) depth_var[i] = (ok && var) ? fb * fb / (d * d * d * d) * var[i] : NAN;
   }
   return BDIS_REF_OK;
 }
@@ -400,6 +450,24 @@ static int run(const bdis_ref_params* p, const double* left0, const double* righ
     return BDIS_REF_E_NOMEM;
   }
   bdis_ref_mask(P, p->sigma_s, M);
+  /* Outputs of the finest level: the caller's arrays when f = 0, else level-f
+   * maps that are upsampled at the end. */
+  double *odisp = disp, *ovar = var, *oconf = conf;
+  if (f > 0) {
+    ref_level* lf = &t->lv[f];
+    size_t nf = (size_t)lf->w * lf->h;
+    lf->odisp = calloc(nf, sizeof(double));
+    lf->ovar = calloc(nf, sizeof(double));
+    lf->oconf = calloc(nf, sizeof(double));
+    if (!lf->odisp || !lf->ovar || !lf->oconf) {
+      free(M);
+      bdis_ref_trace_free(t);
+      return BDIS_REF_E_NOMEM;
+    }
+    odisp = lf->odisp;
+    ovar = lf->ovar;
+    oconf = lf->oconf;
+  }
   const double sfail = p->var_fail_sigma > 0.0 ? p->var_fail_sigma : (double)P;
   const double sfail2 = sfail * sfail;
 
@@ -536,13 +604,14 @@ static int run(const bdis_ref_params* p, const double* left0, const double* righ
           int ok = lv->valid[idx] != 0.0 &&
                    !(p->prob_thresh > 0.0 && lv->qmap[idx] < p->prob_thresh);
           /* Eq. 13 gives u on the right image; disparity d = x_l - x_r = -u */
-          disp[idx] = ok ? -lv->ubar[idx] : NAN;
-          if (conf) conf[idx] = ok ? lv->qmap[idx] : 0.0;
-          if (var) var[idx] = (ok && p->variance) ? zv : NAN;
+          odisp[idx] = ok ? -lv->ubar[idx] : NAN;
+          if (oconf) oconf[idx] = ok ? lv->qmap[idx] : 0.0;
+          if (ovar) ovar[idx] = (ok && p->variance) ? zv : NAN;
         }
       }
   }
   free(M);
+  if (f > 0) upsample(&t->lv[f], f, w, h, p->variance, disp, var, conf);
   if (trace_out)
     *trace_out = t;
   else
@@ -654,9 +723,12 @@ long bdis_ref_trace_get(const bdis_ref_trace* t, int level, int what, double* ds
     case BDIS_REF_UBAR: src = lv->ubar; cnt = npx; break;
     case BDIS_REF_QMAP: src = lv->qmap; cnt = npx; break;
     case BDIS_REF_VALID: src = lv->valid; cnt = npx; break;
+    case BDIS_REF_ODISP: src = lv->odisp; cnt = npx; break;
+    case BDIS_REF_OVAR: src = lv->ovar; cnt = npx; break;
+    case BDIS_REF_OCONF: src = lv->oconf; cnt = npx; break;
     default: return BDIS_REF_E_ARG;
   }
-  if (n < cnt) return BDIS_REF_E_ARG;
+  if (!src || n < cnt) return BDIS_REF_E_ARG;
   memcpy(dst, src, sizeof(double) * (size_t)cnt);
   return cnt;
 }

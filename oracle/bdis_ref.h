@@ -23,7 +23,7 @@ extern "C" {
 
 typedef struct {
   int32_t levels;          /* L: levels n = L-1 (coarsest) .. finest_level                 */
-  int32_t finest_level;    /* f: must be 0 in this oracle                                   */
+  int32_t finest_level;    /* f: finest processed level, 0 <= f < L; f > 0 upsamples its maps */
   int32_t patch;           /* P: square patch side, >= 3                                    */
   int32_t stride;          /* S: patch-grid stride, 1 <= S <= P                             */
   int32_t iters;           /* K: fixed number of inverse-compositional iterations, >= 1     */
@@ -60,7 +60,10 @@ enum {
   BDIS_REF_HESS = 12,    /* per patch: Gauss-Newton Hessian H                   */
   BDIS_REF_UBAR = 13,    /* level map: fused displacement                       */
   BDIS_REF_QMAP = 14,    /* level map: fused confidence                         */
-  BDIS_REF_VALID = 15    /* level map: 1 where at least one patch contributed   */
+  BDIS_REF_VALID = 15,   /* level map: 1 where at least one patch contributed   */
+  BDIS_REF_ODISP = 16,   /* finest level f > 0: disparity before upsampling     */
+  BDIS_REF_OVAR = 17,    /* finest level f > 0: variance before upsampling      */
+  BDIS_REF_OCONF = 18    /* finest level f > 0: confidence before upsampling    */
 };
 enum { BDIS_REF_SIGMA_R2 = 0, BDIS_REF_TAU = 1, BDIS_REF_NACC = 2, BDIS_REF_GAMMA = 3 };
 
@@ -88,6 +91,12 @@ int bdis_ref_grid(int n, int patch, int stride, int* origins, int cap);
 
 /* Spatial mixture mask M (P x P, row b, column a), as defined for the densification. */
 int bdis_ref_mask(int patch, double sigma_s, double* dst);
+
+/* Depth form (Eq. 14, 18): depth = fb / d and depth variance (fb)^2 / d^4 * var
+ * for d > 0 (fb = focal length x baseline, in the units wanted for depth);
+ * NaN elsewhere.  `var` and `depth_var` may be NULL. */
+int bdis_ref_depth(const double* disp, const double* var, long n, double fb, double* depth,
+                   double* depth_var);
 
 #ifdef __cplusplus
 }

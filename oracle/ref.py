@@ -18,7 +18,7 @@ SOURCES = [os.path.join(HERE, "bdis_ref.c")]
 
 NWIN = 5
 WHAT = dict(left=0, right=1, grad=2, uinit=3, pipar=4, u=5, ssd=6, rho=7, acc=8, post=9,
-            pi=10, sigk2=11, hess=12, ubar=13, qmap=14, valid=15)
+            pi=10, sigk2=11, hess=12, ubar=13, qmap=14, valid=15, odisp=16, ovar=17, oconf=18)
 SCALAR = dict(sigma_r2=0, tau=1, nacc=2, gamma=3)
 PER_PATCH = {"uinit", "pipar", "u", "ssd", "rho", "acc", "post", "pi", "sigk2", "hess"}
 
@@ -96,6 +96,7 @@ def lib():
         L.bdis_ref_grid.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_int), ctypes.c_int]
         L.bdis_ref_mask.argtypes = [ctypes.c_int, ctypes.c_double, dp]
+        L.bdis_ref_depth.argtypes = [dp, dp, ctypes.c_long, ctypes.c_double, dp, dp]
         _lib = L
     return _lib
 
@@ -198,3 +199,21 @@ def grid(n, patch, stride):
     out = (ctypes.c_int * cnt)()
     lib().bdis_ref_grid(n, patch, stride, out, cnt)
     return np.array(out[:], dtype=np.int64)
+
+
+def depth(disp, var, fb):
+    """Depth and depth variance from disparity and its variance (Eq. 14, 18)."""
+    disp = np.ascontiguousarray(disp, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    out = np.empty_like(disp)
+    ov = None
+    vp = None
+    if var is not None:
+        var = np.ascontiguousarray(var, dtype=np.float64)
+        ov = np.empty_like(disp)
+        vp = var.ctypes.data_as(dp)
+    st = lib().bdis_ref_depth(disp.ctypes.data_as(dp), vp, disp.size, fb, out.ctypes.data_as(dp),
+                              ov.ctypes.data_as(dp) if ov is not None else None)
+    if st:
+        raise OracleError(st)
+    return out, ov

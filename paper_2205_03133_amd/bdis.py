@@ -98,6 +98,7 @@ def lib():
         L.bdis_backward_batch.argtypes = [vp, i32, ctypes.POINTER(PairGrad), vp, vp]
         L.bdis_timing_enable.argtypes = [vp, i32]
         L.bdis_timing_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long)]
+        L.bdis_depth.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.c_float, vp, vp, vp]
         for name in ("bdis_params_default", "bdis_params_check", "bdis_create", "bdis_set_params",
                      "bdis_compute", "bdis_compute_batch", "bdis_debug_dump", "bdis_level_dims",
                      "bdis_timing_enable", "bdis_timing_read", "bdis_compute_f32", "bdis_compute_f32_batch",
@@ -148,10 +149,11 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _image_arg(t, name):
+def _image_arg(t, name, dtype=None):
     import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.uint8 or t.dim() != 2:
-        raise TypeError(f"{name} must be a 2-D uint8 CUDA tensor")
+    dtype = torch.uint8 if dtype is None else dtype
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or t.dim() != 2:
+        raise TypeError(f"{name} must be a 2-D {dtype} CUDA tensor")
     if t.stride(1) != 1:
         raise ValueError(f"{name} must have unit column stride")
     return t.data_ptr(), t.shape[1], t.shape[0], t.stride(0)
@@ -262,6 +264,24 @@ class Context:
         if st:
             raise self._err(st)
         return results
+
+    def depth(self, disp, fb, var=None, stream=None):
+        """Depth fb / d (and its variance (fb)^2 / d^4 var) of a disparity map
+        (float32 CUDA tensor, contiguous rows).  Returns (depth, depth_var or None)."""
+        import torch
+        dp, w, h, pitch = _image_arg(disp, "disparity", torch.float32)
+        vp = None
+        if var is not None:
+            vp, w2, h2, pitch2 = _image_arg(var, "variance", torch.float32)
+            if (w2, h2, pitch2) != (w, h, pitch):
+                raise ValueError("variance must match the disparity map")
+        depth = torch.empty((h, w), dtype=torch.float32, device=disp.device)
+        dvar = torch.empty((h, w), dtype=torch.float32, device=disp.device) if var is not None else None
+        st = lib().bdis_depth(self._h, dp, vp, w, h, pitch, float(fb), depth.data_ptr(),
+                              dvar.data_ptr() if dvar is not None else None, _stream_ptr(stream))
+        if st:
+            raise self._err(st)
+        return depth, dvar
 
     KERNELS = ("pyramid", "search", "prob", "fuse", "reduce", "backward")
 

@@ -87,8 +87,14 @@ struct PairLevel {
   float* disparity;
   float* variance;
   float* confidence;
+  // finest level f > 0, on the level-0 entry: the level-f output maps (dense
+  // fw x fh) that are upsampled into the outputs above
+  const float* fdisp;
+  const float* fvar;
+  const float* fconf;
+  int fw, fh, fshift;
   // workgroup offsets of this pair in each flattened launch
-  int pyr0, search0, prob0, fuse0;
+  int pyr0, search0, prob0, fuse0, up0;
   int search_nbx;  // search workgroups per patch row
 
   // ---- float (differentiable) path: FP64 level images, pitch in elements
@@ -175,6 +181,9 @@ hipError_t launch_prob(const PairLevel* tab, int npairs, int nblocks, const Leve
                        hipStream_t s);
 hipError_t launch_fuse(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,
                        hipStream_t s);
+hipError_t launch_upsample(const PairLevel* tab, int npairs, int nblocks, hipStream_t s);
+hipError_t launch_depth(const float* disp, const float* var, int w, int h, int pitch, float fb, float* depth,
+                        float* dvar, hipStream_t s);
 
 // Float (differentiable) path: FP64 pyramid and search, and the adjoint kernels.
 hipError_t launch_pyramid_f64(const PairLevel* tab, int npairs, int nblocks, int level, hipStream_t s);
@@ -197,6 +206,18 @@ hipError_t launch_grad_out(const PairLevel* tab, int npairs, int nblocks, hipStr
 // Index of the table entry whose [first, next first) workgroup range holds
 // workgroup `b` of a launch; Field selects the offset (0 pyramid, 1 search,
 // 2 probability, 3 fusion).  Entries are stored in increasing offset order.
+// Workgroups of a launch are handed to the 8 XCDs round-robin (workgroup b runs
+// on XCD b mod 8, each XCD with its own L2).  The kernels whose neighbouring
+// tiles share image rows index their work by this logical number instead, so
+// that each XCD takes one contiguous range of tiles and the shared rows stay
+// in its L2.  A bijection on [0, gridDim.x).
+constexpr int kXcds = 8;
+BDIS_DEV int xcd_block() {
+  const int b = (int)blockIdx.x, n = (int)gridDim.x;
+  const int x = b % kXcds, r = b / kXcds;
+  return x * (n / kXcds) + min(x, n % kXcds) + r;
+}
+
 template <int Field>
 BDIS_DEV int find_pair(const PairLevel* tab, int n, int b) {
   int lo = 0, hi = n - 1;
@@ -206,7 +227,8 @@ BDIS_DEV int find_pair(const PairLevel* tab, int n, int b) {
     if constexpr (Field == 0) off = tab[mid].pyr0;
     else if constexpr (Field == 1) off = tab[mid].search0;
     else if constexpr (Field == 2) off = tab[mid].prob0;
-    else off = tab[mid].fuse0;
+    else if constexpr (Field == 3) off = tab[mid].fuse0;
+    else off = tab[mid].up0;
     if (off <= b) lo = mid;
     else hi = mid - 1;
   }

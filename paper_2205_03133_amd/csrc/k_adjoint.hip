@@ -95,8 +95,9 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_fuse_adj(const PairLevel*
   __shared__ double s_m1[P], s_dm1[P];
   __shared__ double s_buf[kSearchF64Threads];
   __shared__ double s_t[NT][kSearchF64Threads];
-  const PairLevel& a = tab[find_pair<1>(tab, npairs, (int)blockIdx.x)];
-  const int blk = (int)blockIdx.x - a.search0;
+  const int lb = xcd_block();
+  const PairLevel& a = tab[find_pair<1>(tab, npairs, lb)];
+  const int blk = lb - a.search0;
   const int tid = threadIdx.x;
   const int q = tid / G, c = tid % G;
   const int S = lp.S, W = a.g.w;
@@ -521,8 +522,9 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLeve
   constexpr int N = P * P;
   extern __shared__ double s_tile[];  // [P][twl] left, [P][twl] gradient, [P][twr] right
   __shared__ int s_lo;
-  const PairLevel& a = tab[find_pair<1>(tab, npairs, (int)blockIdx.x)];
-  const int blk = (int)blockIdx.x - a.search0;
+  const int lb = xcd_block();
+  const PairLevel& a = tab[find_pair<1>(tab, npairs, lb)];
+  const int blk = lb - a.search0;
   const int tid = threadIdx.x;
   const int q = tid / G, r = tid % G;
   const int W = a.g.w, Hh = a.g.h, S = lp.S;

@@ -54,8 +54,9 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_f64(const PairLeve
   __shared__ double s_psum[NPB];
   __shared__ int s_pcnt[NPB];
 
-  const PairLevel& a = tab[find_pair<1>(tab, npairs, (int)blockIdx.x)];
-  const int blk = (int)blockIdx.x - a.search0;
+  const int lb = xcd_block();
+  const PairLevel& a = tab[find_pair<1>(tab, npairs, lb)];
+  const int blk = lb - a.search0;
   const int tid = threadIdx.x;
   const int q = tid / G, r = tid % G;
   const int W = a.g.w, Hh = a.g.h, S = lp.S;

@@ -84,7 +84,8 @@ constexpr int kMaxRec = 512;
 __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab, int npairs, LevelParams lp) {
   __shared__ double s_m[kMaxPatch];
   __shared__ double s_u[kMaxRec], s_w[kMaxRec], s_v[kMaxRec];
-  const PairLevel& a = tab[find_pair<3>(tab, npairs, (int)blockIdx.x)];
+  const int lb = xcd_block();
+  const PairLevel& a = tab[find_pair<3>(tab, npairs, lb)];
   const int tid = threadIdx.x;
   const int P = lp.P, S = lp.S;
   if (tid < P) {
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
     s_m[tid] = acc;
   }
   const int tiles_x = (a.g.w + kFuseTx - 1) / kFuseTx;
-  const int t = (int)blockIdx.x - a.fuse0;
+  const int t = lb - a.fuse0;
   const int x0 = (t % tiles_x) * kFuseTx, y0 = (t / tiles_x) * kFuseTy;
   const int x1 = min(x0 + kFuseTx, a.g.w) - 1, y1 = min(y0 + kFuseTy, a.g.h) - 1;
   // patch index ranges covering the tile: [lo, hi] plus the border patch `ex`
@@ -196,6 +197,61 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
   if (a.variance) gbl(a.variance)[idx] = (valid && lp.variance) ? (float)(zv / (z * z)) : nan;
 }
 
+// Finest level f > 0, per output pixel: bilinear sample of the level-f maps at
+// (x / 2^f, y / 2^f) (the pyramid keeps even pixels, so level-0 pixel 2^f k
+// lies on level-f pixel k), clamped at the last row and column; disparity
+// scaled by 2^f, variance by 4^f.  Invalid when a sample with nonzero weight is.
+__global__ __launch_bounds__(kPixThreads) void k_upsample(const PairLevel* tab, int npairs) {
+  const PairLevel& a = tab[find_pair<4>(tab, npairs, (int)blockIdx.x)];
+  const int idx = ((int)blockIdx.x - a.up0) * kPixThreads + (int)threadIdx.x;
+  const int w = a.g.w, h = a.g.h;
+  if (idx >= w * h) return;
+  const int y = idx / w, x = idx - y * w;
+  const double sc = (double)(1 << a.fshift);
+  const double sx = x / sc, sy = y / sc;
+  const int x0 = (int)floor(sx), y0 = (int)floor(sy);
+  const double ax = sx - x0, ay = sy - y0;
+  const int xs[2] = {x0, min(x0 + 1, a.fw - 1)};
+  const int ys[2] = {y0, min(y0 + 1, a.fh - 1)};
+  const double wx[2] = {1.0 - ax, ax}, wy[2] = {1.0 - ay, ay};
+  const auto fd = gbl(a.fdisp), fv = gbl(a.fvar), fc = gbl(a.fconf);
+  double d = 0.0, v = 0.0, c = 0.0;
+  bool ok = true;
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const double wt = wx[e] * wy[b];
+      if (wt == 0.0) continue;
+      const size_t k = (size_t)ys[b] * a.fw + xs[e];
+      const float dk = fd[k];
+      if (dk != dk) ok = false;
+      d += wt * (double)dk;
+      v += wt * (double)fv[k];
+      c += wt * (double)fc[k];
+    }
+  const float nan = __builtin_nanf("");
+  gbl(a.disparity)[idx] = ok ? (float)(sc * d) : nan;
+  if (a.variance) gbl(a.variance)[idx] = ok ? (float)(sc * sc * v) : nan;
+  if (a.confidence) gbl(a.confidence)[idx] = ok ? (float)c : 0.0f;
+}
+
+// Per pixel: depth fb / d and its variance (fb)^2 / d^4 var (Eq. 14, 18).
+__global__ __launch_bounds__(kPixThreads) void k_depth(const float* disp, const float* var, int w, int h,
+                                                       int pitch, float fb, float* depth, float* dvar) {
+  const int idx = (int)blockIdx.x * kPixThreads + (int)threadIdx.x;
+  if (idx >= w * h) return;
+  const int y = idx / w, x = idx - y * w;
+  const double d = (double)gbl(disp)[(size_t)y * pitch + x];
+  const bool ok = d > 0.0;
+  const double z = (double)fb / d;
+  gbl(depth)[idx] = ok ? (float)z : __builtin_nanf("");
+  if (dvar) {
+    const double v = (double)gbl(var)[(size_t)y * pitch + x];
+    gbl(dvar)[idx] = ok ? (float)(z * z / (d * d) * v) : __builtin_nanf("");
+  }
+}
+
 }  // namespace
 
 hipError_t launch_prob(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
@@ -207,6 +263,20 @@ hipError_t launch_prob(const PairLevel* tab, int npairs, int nblocks, const Leve
 hipError_t launch_fuse(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fuse, dim3(nblocks), dim3(kFuseTx * kFuseTy), 0, s, tab, npairs, lp);
+  return hipGetLastError();
+}
+
+hipError_t launch_upsample(const PairLevel* tab, int npairs, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_upsample, dim3(nblocks), dim3(kPixThreads), 0, s, tab, npairs);
+  return hipGetLastError();
+}
+
+hipError_t launch_depth(const float* disp, const float* var, int w, int h, int pitch, float fb, float* depth,
+                        float* dvar, hipStream_t s) {
+  const long n = (long)w * h;
+  hipLaunchKernelGGL(k_depth, dim3((unsigned)((n + kPixThreads - 1) / kPixThreads)), dim3(kPixThreads), 0, s, disp,
+                     var, w, h, pitch, fb, depth, dvar);
   return hipGetLastError();
 }
 

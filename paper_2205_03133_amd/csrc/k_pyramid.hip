@@ -18,7 +18,7 @@ constexpr int kSrcRows = 2 * kPyrTy + 3;  // source rows touched by kPyrTy outpu
 __global__ __launch_bounds__(kPyrTx* kPyrTy) void k_pyr_u8(const PairLevel* tab, int npairs) {
   __shared__ int hL[kSrcRows][kPyrTx];
   __shared__ int hR[kSrcRows][kPyrTx];
-  const int b = blockIdx.x;
+  const int b = xcd_block();
   const PairLevel& a = tab[find_pair<0>(tab, npairs, b)];
   const int tiles_x = (a.g.w + kPyrTx - 1) / kPyrTx;
   const int t = b - a.pyr0;

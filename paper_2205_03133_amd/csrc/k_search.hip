@@ -92,8 +92,9 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
   const uint8_t* s_left = reinterpret_cast<const uint8_t*>(s_left32);
   const uint8_t* s_right = reinterpret_cast<const uint8_t*>(s_right32);
 
-  const PairLevel& a = tab[find_pair<1>(tab, npairs, (int)blockIdx.x)];
-  const int blk = (int)blockIdx.x - a.search0;   // workgroup within the pair
+  const int lb = xcd_block();
+  const PairLevel& a = tab[find_pair<1>(tab, npairs, lb)];
+  const int blk = lb - a.search0;   // workgroup within the pair
   const int tid = threadIdx.x;
   const int q = tid / G;  // patch slot in the workgroup
   const int r = tid % G;  // patch row of this lane

@@ -42,6 +42,7 @@ struct Layout {
       dssd[kMaxLevels]{}, rho[kMaxLevels]{}, acc[kMaxLevels]{}, hess[kMaxLevels]{},
       dens[kMaxLevels]{};
   size_t ubar[kMaxLevels]{}, qmap[kMaxLevels]{};
+  size_t odisp = 0, ovar = 0, oconf = 0;  // finest level f > 0: outputs before upsampling
   size_t part_sum[kMaxLevels]{}, part_cnt[kMaxLevels]{}, scal[kMaxLevels]{};
   // training contexts: FP64 level images, saved state, adjoints (one region)
   bool train = false;
@@ -111,6 +112,11 @@ bool make_layout(const bdis_params& p, int w, int h, int levels, Layout* lay, bo
     if (n > p.finest_level) {
       L.ubar[n] = take(npx * 8);
       L.qmap[n] = take(npx * 8);
+    }
+    if (n == p.finest_level && n > 0) {
+      L.odisp = take(npx * 4);
+      L.ovar = take(npx * 4);
+      L.oconf = take(npx * 4);
     }
     // partials sized for the smallest workgroup the tuner may choose
     L.max_search_blocks[n] = search_nbx(L.g[n], p.patch, kSearchThreadOptions[0]) * L.g[n].ny;
@@ -189,6 +195,7 @@ struct Plan {
   int pyr_blocks[kMaxLevels]{}, search_blocks[kMaxLevels]{}, prob_blocks[kMaxLevels]{},
       fuse_blocks[kMaxLevels]{};
   int threads[kMaxLevels]{};     // search workgroup size per level
+  int up_blocks = 0;             // finest level f > 0: upsampling workgroups (level 0)
   bool f32 = false;              // float (FP64) path: per-pixel pyramid blocks, fixed search size
   std::vector<PairLevel> tab;
 };
@@ -253,8 +260,8 @@ bdis_status check_params_msg(const bdis_params* p, char* msg, size_t n) {
   if (!p) return snprintf(msg, n, "params is NULL"), BDIS_E_ARG;
   if (p->levels < 1 || p->levels > BDIS_MAX_LEVELS)
     return snprintf(msg, n, "levels %d outside 1..%d", p->levels, BDIS_MAX_LEVELS), BDIS_E_ARG;
-  if (p->finest_level != 0)
-    return snprintf(msg, n, "finest_level %d unsupported (only 0)", p->finest_level), BDIS_E_ARG;
+  if (p->finest_level < 0 || p->finest_level >= p->levels)
+    return snprintf(msg, n, "finest_level %d outside 0..levels-1", p->finest_level), BDIS_E_ARG;
   if (p->patch < 3 || p->patch > BDIS_MAX_PATCH)
     return snprintf(msg, n, "patch %d outside 3..%d", p->patch, BDIS_MAX_PATCH), BDIS_E_ARG;
   if (p->stride < 1 || p->stride > p->patch)
@@ -360,6 +367,13 @@ int default_threads(const Plan& pl, int n, int P) {
 
 // Assigns workgroup offsets for the given per-level search workgroup sizes.
 void assign_offsets(const bdis_params& p, Plan& pl) {
+  int up = 0;
+  for (int e = 0; p.finest_level > 0 && e < pl.tab_count[0]; ++e) {
+    PairLevel& q = pl.tab[pl.tab_first[0] + e];
+    q.up0 = up;
+    up += (q.g.w * q.g.h + kPixThreads - 1) / kPixThreads;
+  }
+  pl.up_blocks = up;
   for (int n = 0; n < pl.max_levels; ++n) {
     int pyr = 0, se = 0, pr = 0, fu = 0;
     const bool patches = n >= p.finest_level;
@@ -427,6 +441,17 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
       e.L = n == 0 ? q.left : B8(lay.lvl_l[n]);
       e.R = n == 0 ? q.right : B8(lay.lvl_r[n]);
       e.pitch = n == 0 ? q.pitch : lay.lpitch[n];
+      if (n == 0 && p.finest_level > 0) {
+        e.fdisp = reinterpret_cast<const float*>(base + lay.odisp);
+        e.fvar = reinterpret_cast<const float*>(base + lay.ovar);
+        e.fconf = reinterpret_cast<const float*>(base + lay.oconf);
+        e.fw = lay.g[p.finest_level].w;
+        e.fh = lay.g[p.finest_level].h;
+        e.fshift = p.finest_level;
+        e.disparity = q.disp;
+        e.variance = q.var;
+        e.confidence = q.conf;
+      }
       if (n >= p.finest_level) {
         const bool has_par = n + 1 < q.levels;
         e.par_ubar = has_par ? BD(lay.ubar[n + 1]) : nullptr;
@@ -448,6 +473,10 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
         if (n > p.finest_level) {
           e.ubar = BD(lay.ubar[n]);
           e.qmap = BD(lay.qmap[n]);
+        } else if (n > 0) {  // level-f maps, upsampled afterwards
+          e.disparity = reinterpret_cast<float*>(base + lay.odisp);
+          e.variance = reinterpret_cast<float*>(base + lay.ovar);
+          e.confidence = reinterpret_cast<float*>(base + lay.oconf);
         } else {
           e.disparity = q.disp;
           e.variance = q.var;
@@ -593,6 +622,12 @@ bdis_status launch_all(bdis_ctx* c, const Plan& pl, hipStream_t st) {
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "fusion launch");
   }
+  if (p.finest_level > 0) {
+    const long tmk = timing_start(c, BDIS_K_FUSE, st);
+    e = launch_upsample(c->tab_dev + pl.tab_first[0], pl.tab_count[0], pl.up_blocks, st);
+    timing_stop(c, tmk, st);
+    if (e != hipSuccess) return hip_fail(c, e, "upsampling launch");
+  }
   return BDIS_OK;
 }
 
@@ -607,6 +642,7 @@ std::string graph_key(const bdis_params& p, const Plan& pl) {
   add(pl.prob_blocks, sizeof pl.prob_blocks);
   add(pl.fuse_blocks, sizeof pl.fuse_blocks);
   add(pl.threads, sizeof pl.threads);
+  add(&pl.up_blocks, sizeof pl.up_blocks);
   add(&pl.max_levels, sizeof pl.max_levels);
   return k;
 }
@@ -753,12 +789,20 @@ bdis_status run_pairs_f32(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipSt
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "fusion launch");
   }
+  if (p.finest_level > 0) {
+    const long tmk = timing_start(c, BDIS_K_FUSE, st);
+    e = launch_upsample(c->tab_dev + pl.tab_first[0], pl.tab_count[0], pl.up_blocks, st);
+    timing_stop(c, tmk, st);
+    if (e != hipSuccess) return hip_fail(c, e, "upsampling launch");
+  }
   return BDIS_OK;
 }
 
 // Backward pass of the last float-path call: adjoints level by level from the
 // finest to the coarsest, then the transposed pyramid down to the images.
 bdis_status run_backward(bdis_ctx* c, std::vector<PairSpec> pairs, double* grad_hyper, hipStream_t st) {
+  if (c->p.finest_level != 0)
+    return fail(c, BDIS_E_ARG, "backward needs finest_level 0 (no adjoint of the upsampling)");
   Plan pl;
   bdis_status s = build_plan(c, pairs, &pl, true);
   if (s != BDIS_OK) return s;
@@ -1044,6 +1088,19 @@ bdis_status bdis_debug_dump(bdis_ctx* c, int level, int what, void* host_dst, si
   }
   if (e != hipSuccess) return hip_fail(c, e, "debug dump");
   return BDIS_OK;
+}
+
+bdis_status bdis_depth(bdis_ctx* c, const float* disp, const float* var, int w, int h, int pitch, float fb,
+                       float* depth, float* dvar, void* stream) {
+  if (!c) return BDIS_E_ARG;
+  if (!disp || !depth) return fail(c, BDIS_E_ARG, "disparity and depth are required");
+  if ((var == nullptr) != (dvar == nullptr))
+    return fail(c, BDIS_E_ARG, "variance and depth_variance go together");
+  if (w < 1 || h < 1 || pitch < w || (long)w * h > (long)INT32_MAX)
+    return fail(c, BDIS_E_ARG, "bad map size %dx%d pitch %d", w, h, pitch);
+  if (!finite_f(fb) || !(fb > 0.0f)) return fail(c, BDIS_E_ARG, "fb must be finite and > 0");
+  const hipError_t e = launch_depth(disp, var, w, h, pitch, fb, depth, dvar, reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BDIS_OK : hip_fail(c, e, "depth launch");
 }
 
 bdis_status bdis_level_dims(const bdis_params* p, int w, int h, int level, int* lw, int* lh, int* nx, int* ny) {

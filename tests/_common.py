@@ -60,18 +60,27 @@ def footprint(mask_patches, w, h, P, S):
     return out
 
 
-def variance_parity(gpu_var, ref_var, g_acc, g_sig, r_acc, r_sig, P, S):
+def variance_parity(gpu_var, ref_var, g_acc, g_sig, r_acc, r_sig, P, S, f=0, level_wh=None):
     """Variance agreement overall and away from patches whose decisions differ.
 
     A decision differs when acceptance differs, or when exactly one side
     failed the variance fit (sigma_k^2 == P^2 with the default failure sigma).
+    With a finest level f > 0 the patches live on the level-f grid (size
+    level_wh); their footprint grows by the one level-f pixel that bilinear
+    upsampling reaches and is mapped to full resolution.
     """
     h, w = ref_var.shape
     fail_g = g_acc & np.isclose(g_sig, P * P, rtol=0, atol=0)
     fail_r = r_acc & np.isclose(r_sig, P * P, rtol=0, atol=0)
     flip = (g_acc != r_acc) | (fail_g != fail_r)
     st = parity(gpu_var, ref_var, VAR_RTOL, rel=True)
-    fp = footprint(flip, w, h, P, S)
+    if f == 0:
+        fp = footprint(flip, w, h, P, S)
+    else:
+        from scipy import ndimage
+        lw, lh = level_wh
+        fp = ndimage.binary_dilation(footprint(flip, lw, lh, P, S), np.ones((3, 3), bool))
+        fp = np.kron(fp, np.ones((2 ** f, 2 ** f), bool))[:h, :w]
     st_away = parity(np.where(fp, 0.0, gpu_var), np.where(fp, 0.0, ref_var), VAR_RTOL, rel=True)
     # pixels excluded above are counted as agreeing; report the fraction over the rest
     n_rest = int((~fp).sum())

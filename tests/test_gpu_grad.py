@@ -31,7 +31,8 @@ def _fparams(B, **kw):
 
 
 @pytest.mark.parametrize("shape,kw", [((96, 160), {}), ((480, 640), dict(levels=4, variance=0)),
-                                      ((101, 133), dict(patch=7, stride=3, sigma_r_dynamic=0, sigma_r=6.0))])
+                                      ((101, 133), dict(patch=7, stride=3, sigma_r_dynamic=0, sigma_r=6.0)),
+                                      ((120, 200), dict(levels=4, finest_level=1))])
 def test_float_forward_parity(B, oracle, shape, kw):
     h, w = shape
     left, right, _, _ = _pair(h, w)
@@ -176,3 +177,15 @@ def test_hyperparameter_tuning_reduces_error(B):
     print("  losses", [round(x, 4) for x in losses], flush=True)
     assert min(losses[1:]) < losses[0]
     ctx.close()
+
+
+def test_backward_needs_finest_level_zero(B):
+    h, w = 64, 96
+    left, right, _, _ = _pair(h, w)
+    p = _fparams(B, levels=3, finest_level=1)
+    ctx = B.Context(p, w, h, train=True)
+    ctx.compute_f32(torch.from_numpy(left).cuda(), torch.from_numpy(right).cuda())
+    with pytest.raises(B.BdisError):
+        ctx.backward(torch.zeros((h, w), device="cuda"))
+    ctx.close()
+

@@ -35,8 +35,10 @@ def _run(B, left, right, p, case):
 
 
 def _check_variance(ctx, tr, g, r, p):
-    vp = variance_parity(g["var"], r["var"], ctx.debug(0, "acc") > 0, ctx.debug(0, "dens")[..., 2],
-                         tr.get(0, "acc") > 0, tr.get(0, "sigk2"), p.patch, p.stride)
+    f = p.finest_level
+    vp = variance_parity(g["var"], r["var"], ctx.debug(f, "acc") > 0, ctx.debug(f, "dens")[..., 2],
+                         tr.get(f, "acc") > 0, tr.get(f, "sigk2"), p.patch, p.stride, f=f,
+                         level_wh=tr.dims(f)[:2])
     _report("variance", vp["overall"])
     print(f"  variance away from {vp['flip_patches']} decision-flipped patches: {vp['away_frac']:.6f}",
           flush=True)
@@ -71,8 +73,8 @@ def test_level_dims_match_oracle(B, oracle):
         assert nx == len(oracle.grid(lw, 12, 4)) and ny == len(oracle.grid(lh, 12, 4))
 
 
-def _patch_parity(B, ctx, tr, levels):
-    for n in range(levels):
+def _patch_parity(B, ctx, tr, levels, finest=0):
+    for n in range(finest, levels):
         acc_g = ctx.debug(n, "acc") > 0
         acc_r = tr.get(n, "acc") > 0
         agree = (acc_g == acc_r).mean()
@@ -109,6 +111,55 @@ def test_end_to_end_workloads(B, oracle, cfg):
     ok = np.isfinite(g["disp"]) & valid
     print(f"  EPE vs ground truth: median={np.median(np.abs(g['disp'][ok] - gt[ok])):.4f} px "
           f"valid={np.isfinite(g['disp']).mean():.4f}", flush=True)
+    ctx.close()
+
+
+@pytest.mark.parametrize("f,prob", [(1, 0.15), (2, 0.0)])
+def test_paper_preset_finest_level(B, oracle, f, prob):
+    """Sec. IV-A: levels 5..f searched (coarsest scale 2^5), patch 10, overlap
+    0.55 (S = 4), 12 iterations, gamma 0.75, sigma_s 4, pixel threshold 0.15;
+    level-f maps upsampled to 640x480."""
+    from paper_2205_03133_amd.synth import make_pair
+    left, right, gt, valid = make_pair(2, 1)
+    p = B.params(levels=6, finest_level=f, patch=10, stride=4, iters=12, valid_ratio=0.75,
+                 sigma_s=4.0, prob_thresh=prob, variance=1)
+    ctx, g = _run(B, left, right, p, f"paper preset f={f} prob={prob}")
+    r = oracle.compute(left, right, oracle_params(oracle, p), trace=True)
+    _patch_parity(B, ctx, r["trace"], p.levels, finest=f)
+    st = parity(g["disp"], r["disp"], DISP_TOL)
+    _report("disparity", st)
+    assert st["frac"] >= PASS_FRAC
+    stc = parity(g["conf"], r["conf"], 1e-4)
+    _report("confidence", stc)
+    assert stc["frac"] >= PASS_FRAC
+    _check_variance(ctx, r["trace"], g, r, p)
+    ok = np.isfinite(g["disp"]) & valid
+    print(f"  EPE vs ground truth: median={np.median(np.abs(g['disp'][ok] - gt[ok])):.4f} px "
+          f"valid={np.isfinite(g['disp']).mean():.4f}", flush=True)
+    ctx.close()
+
+
+def test_depth_form(B, oracle):
+    import torch
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    left, right, _, _ = make_pair(1, 2)
+    p = B.params(**method_params(1))
+    p.variance = 1
+    ctx, g = _run(B, left, right, p, "depth form")
+    fb = 400.0
+    z, zv = ctx.depth(to_gpu(g["disp"]), fb, var=to_gpu(g["var"]))
+    torch.cuda.synchronize()
+    zr, zvr = oracle.depth(g["disp"].astype(np.float64), g["var"].astype(np.float64), fb)
+    st = parity(z.cpu().numpy(), zr, 1e-6, rel=True)
+    sv = parity(zv.cpu().numpy(), zvr, 1e-5, rel=True)
+    _report("depth", st)
+    _report("depth variance", sv)
+    assert st["frac"] == 1.0 and sv["frac"] == 1.0
+    zo, none = ctx.depth(to_gpu(g["disp"]), fb)
+    torch.cuda.synchronize()
+    assert none is None and torch.equal(torch.isnan(zo), torch.isnan(z))
+    with pytest.raises(B.BdisError):
+        ctx.depth(to_gpu(g["disp"]), -1.0)
     ctx.close()
 
 

@@ -550,3 +550,92 @@ def test_bad_arguments(oracle):
     assert e.value.code == -2
     with pytest.raises(oracle.OracleError):
         oracle.compute(img.astype(float) * np.nan, img.astype(float), oracle.default_params(levels=1, patch=4))
+
+
+# --------------------------------------------------------------------------
+# Finest level f > 0 (Sec. IV-A runs levels 5..1) and the depth form (Eq. 14, 18)
+# --------------------------------------------------------------------------
+
+def _preset_pair():
+    from paper_2205_03133_amd.synth import make_pair
+    left, right, _, _ = make_pair(1, 3)
+    return left, right
+
+
+@pytest.mark.parametrize("f,L", [(1, 4), (2, 4)])
+def test_finest_level_equals_run_on_level_image(oracle, f, L):
+    """Searching levels L-1..f of an image equals searching levels L-f-1..0 of its
+    level-f pyramid image (same weights shifted down by f): the level-f maps
+    before upsampling must be identical, bit for bit."""
+    left, right = _preset_pair()
+    w = [1.0, 3.0, 2.0, 5.0, 4.0, 1.0, 1.0, 1.0]
+    p = oracle.default_params(levels=L, finest_level=f, patch=8, stride=4, iters=8, variance=1,
+                              level_weight=w)
+    r = oracle.compute(left, right, p, trace=True)
+    t = r["trace"]
+    lf = t.get(f, "left").astype(np.uint8)
+    rf = t.get(f, "right").astype(np.uint8)
+    assert np.array_equal(lf, t.get(f, "left"))  # the integer pyramid keeps integers
+    q = oracle.default_params(levels=L - f, finest_level=0, patch=8, stride=4, iters=8, variance=1,
+                              level_weight=w[f:] + [1.0] * f)
+    s = oracle.compute(lf, rf, q)
+    for mine, theirs in (("odisp", "disp"), ("ovar", "var"), ("oconf", "conf")):
+        np.testing.assert_array_equal(t.get(f, mine), s[theirs])
+
+
+@pytest.mark.parametrize("f", [1, 2])
+def test_upsampling_is_bilinear(oracle, f):
+    """Full-resolution outputs against scipy's linear interpolation of the level-f
+    maps at (y / 2^f, x / 2^f) with edge clamping; validity: no invalid sample may
+    carry weight (interpolated invalid mask == 0)."""
+    left, right = _preset_pair()
+    p = oracle.default_params(levels=4, finest_level=f, patch=8, stride=4, iters=8, variance=1)
+    r = oracle.compute(left, right, p, trace=True)
+    t = r["trace"]
+    od, ov, oc = t.get(f, "odisp"), t.get(f, "ovar"), t.get(f, "oconf")
+    h, w = left.shape
+    yy, xx = np.mgrid[0:h, 0:w].astype(np.float64)
+    coords = np.stack([yy / 2 ** f, xx / 2 ** f])
+    bad = ~np.isfinite(od)
+    interp = lambda a: ndimage.map_coordinates(a, coords, order=1, mode="nearest")
+    badw = interp(bad.astype(np.float64))
+    valid = badw == 0.0
+    assert np.array_equal(np.isfinite(r["disp"]), valid)
+    np.testing.assert_allclose(r["disp"][valid], 2 ** f * interp(np.where(bad, 0.0, od))[valid],
+                               rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(r["var"][valid], 4 ** f * interp(np.where(bad, 0.0, ov))[valid],
+                               rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(r["conf"][valid], interp(np.where(bad, 0.0, oc))[valid], rtol=1e-12,
+                               atol=1e-12)
+    assert np.all(r["conf"][~valid] == 0.0)
+    # even pixels sit exactly on level-f pixels
+    s = 2 ** f
+    ev = r["disp"][::s, ::s]
+    m = np.isfinite(od)
+    np.testing.assert_array_equal(ev[m], s * od[m])
+
+
+def test_finest_level_rejected_outside_range(oracle):
+    img = np.zeros((64, 64), np.uint8)
+    for f in (-1, 3):
+        with pytest.raises(oracle.OracleError):
+            oracle.compute(img, img, oracle.default_params(levels=3, finest_level=f, patch=8))
+
+
+def test_depth_is_the_delta_method(oracle):
+    """Depth Z = fb / d; Eq. 18's factor (fb)^2 / d^4 is (dZ/dd)^2 of that map, checked
+    by central differences of the depth routine itself; d <= 0 and NaN are invalid."""
+    rng = np.random.default_rng(7)
+    d = rng.uniform(0.5, 60.0, 200)
+    var = rng.uniform(0.0, 2.0, 200)
+    fb = 523.7
+    z, zv = oracle.depth(d, var, fb)
+    np.testing.assert_allclose(z * d, fb, rtol=1e-14)
+    h = 1e-6 * d
+    zp, _ = oracle.depth(d + h, None, fb)
+    zm, _ = oracle.depth(d - h, None, fb)
+    slope = (zp - zm) / (2 * h)
+    np.testing.assert_allclose(zv, slope ** 2 * var, rtol=1e-6)
+    bad = np.array([0.0, -1.0, np.nan])
+    zb, zvb = oracle.depth(bad, np.ones(3), fb)
+    assert np.all(np.isnan(zb)) and np.all(np.isnan(zvb))
