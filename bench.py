@@ -64,13 +64,35 @@ def measured_traffic(workload):
     return val if sha == src else None
 
 
-def roofline(flops_per_step, steps, timing, kernel_name, workload):
+HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
+
+
+def search_bytes(bdis, p, w, h, levels=None):
+    """Algorithmic HBM bytes of the patch search of one pass: both level images
+    (1 B per pixel each), per patch its record (76 B written) and the 4-tap
+    reads of the parent maps (64 B, every level but the coarsest)."""
+    L = levels or p.levels
+    tot = 0
+    for n in range(p.finest_level, L):
+        lw, lh, nx, ny = bdis.level_dims(p, w, h, n)
+        tot += 2 * lw * lh + nx * ny * (76 + (64 if n + 1 < L else 0))
+    return tot
+
+
+def roofline(flops_per_step, steps, timing, kernel_name, workload, bytes_per_step=None):
     s_ms, s_n = timing["search"]
     achieved = flops_per_step * steps / (s_ms * 1e-3) / 1e12
-    return dict(bound="alu", achieved=round(achieved, 3), peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5), traffic=measured_traffic(workload),
-                traffic_unit="bytes per launch", kernel=kernel_name,
-                avg_launch_us=round(s_ms * 1e3 / max(s_n, 1), 3), launches=s_n)
+    out = dict(bound="alu", achieved=round(achieved, 3), peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+               frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5), traffic=measured_traffic(workload),
+               traffic_unit="bytes per launch", kernel=kernel_name,
+               avg_launch_us=round(s_ms * 1e3 / max(s_n, 1), 3), launches=s_n)
+    launch_s = s_ms * 1e-3 / max(s_n, 1)
+    if bytes_per_step is not None:
+        per_launch = bytes_per_step * steps / max(s_n, 1)
+        out["hbm_frac_algorithmic"] = round(per_launch / launch_s / 1e9 / HBM_PEAK_GBS, 5)
+    if out["traffic"] is not None:
+        out["hbm_frac_counters"] = round(out["traffic"] / launch_s / 1e9 / HBM_PEAK_GBS, 5)
+    return out
 
 
 def kernel_table(tk):
@@ -183,8 +205,135 @@ def bench_batch(bdis, torch, args):
                 config=dict(workload="1920x1080 synthetic pairs (planes+bumps 0-192 px, 30% textureless, "
                                      "dark gain U(0.2,0.5), noise 3), L=6 P=12 S=4 K=16 variance on",
                             share="64 of the 512-pair stream"),
-                roofline=roofline(flops, steps_ev, tk, "k_search_u8<12>", "1080p_batch64"), kernels=kernel_table(tk),
+                roofline=roofline(flops, steps_ev, tk, "k_search_u8<12>", "1080p_batch64",
+                                  search_bytes(bdis, p, 1920, 1080) * n), kernels=kernel_table(tk),
                 epe_median_px=round(epe, 4))
+
+
+def bench_mixed(bdis, torch, args):
+    """Mixed-resolution batch: 64 pairs from 320x240 to 1920x1080 (8 per size,
+    4-6 levels by size, P 8, S 3, K 16, variance on) in one call per step."""
+    import numpy as np
+    from paper_2205_03133_amd.synth import c3_sizes, make_pair, method_params
+    dev = torch.device("cuda:0")
+    sizes = c3_sizes()
+    log("mixed batch: generating one pair per size")
+    base = {}
+    for i, wh in enumerate(sizes):
+        if wh not in base:
+            base[wh] = (i, make_pair(3, i))
+    mp = [method_params(3, i) for i in range(len(sizes))]
+    p = bdis.params(**{k: v for k, v in mp[0].items() if k != "levels"}, levels=6)
+    lefts = [torch.from_numpy(base[wh][1][0]).to(dev) for wh in sizes]
+    rights = [torch.from_numpy(base[wh][1][1]).to(dev) for wh in sizes]
+    levels = [m["levels"] for m in mp]
+    outs = [{k: torch.empty((h, w), dtype=torch.float32, device=dev) for k in ("disp", "var", "conf")}
+            for (w, h) in sizes]
+    ctx = bdis.Context(p, 1920, 1080, max_batch=len(sizes))
+    for _ in range(2):
+        ctx.compute_batch(lefts, rights, levels=levels, outs=outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        ctx.compute_batch(lefts, rights, levels=levels, outs=outs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.timing(True)
+    steps_ev = max(1, args.batch_steps // 2)
+    for _ in range(steps_ev):
+        ctx.compute_batch(lefts, rights, levels=levels, outs=outs)
+    torch.cuda.synchronize()
+    tk = ctx.timing_read()
+    ctx.timing(False)
+    errs = []
+    for wh, (i, pr) in base.items():
+        k = sizes.index(wh)
+        d = outs[k]["disp"].cpu().numpy()
+        ok = np.isfinite(d) & pr[3]
+        errs.append(np.abs(d[ok] - pr[2][ok]))
+    ctx.close()
+    px = sum(w * h for (w, h) in sizes)
+    flops = sum(search_flops(bdis, p, w, h, levels[i]) for i, (w, h) in enumerate(sizes))
+    nbytes = sum(search_bytes(bdis, p, w, h, levels[i]) for i, (w, h) in enumerate(sizes))
+    return dict(metric="disparity Mpixel/s (mixed batch)", value=round(px * args.batch_steps / dt / 1e6, 2),
+                unit="Mpixel/s", pairs_per_step=len(sizes), megapixels_per_step=round(px / 1e6, 3),
+                unique_pairs=len(base), steps=args.batch_steps, ms_per_step=round(dt * 1e3 / args.batch_steps, 3),
+                config=dict(workload="64 synthetic pairs, 8 each of 320x240 .. 1920x1080, disparity up to 10% of "
+                                     "the width, L=4..6 by size, P=8 S=3 K=16 variance on"),
+                roofline=roofline(flops, steps_ev, tk, "k_search_u8<8>", "mixed64", nbytes),
+                kernels=kernel_table(tk), epe_median_px=round(float(np.median(np.concatenate(errs))), 4))
+
+
+def bench_preset(bdis, torch, args):
+    """The paper's preset on the 640x480 pair: levels 5..1 searched, P 10,
+    overlap 0.55 (S 4), 12 iterations, gamma 0.75, pixel threshold 0.15; the
+    level-1 maps upsampled to full resolution.  Without and with variance."""
+    import numpy as np
+    from paper_2205_03133_amd.synth import make_pair
+    dev = torch.device("cuda:0")
+    left, right, gt, valid = make_pair(2, 0)
+    lt, rt = torch.from_numpy(left).to(dev), torch.from_numpy(right).to(dev)
+    out = {}
+    for var in (0, 1):
+        p = bdis.params(levels=6, finest_level=1, patch=10, stride=4, iters=12, valid_ratio=0.75,
+                        sigma_s=4.0, prob_thresh=0.15, variance=var)
+        ctx = bdis.Context(p, 640, 480)
+        res = None
+        for _ in range(args.warmup):
+            res = ctx.compute(lt, rt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = ctx.compute(lt, rt)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        d = res["disp"].cpu().numpy()
+        ok = np.isfinite(d) & valid
+        out["variance_on" if var else "variance_off"] = dict(
+            ms_per_pair=round(dt * 1e3, 4), mpx_s=round(640 * 480 / dt / 1e6, 2),
+            valid_frac=round(float(np.isfinite(d).mean()), 4),
+            epe_median_px=round(float(np.median(np.abs(d[ok] - gt[ok]))), 4))
+        ctx.close()
+    out["config"] = "640x480 pair (planes+bumps 0-64 px), levels 5..1, P=10 S=4 K=12, gamma 0.75, prob 0.15"
+    out["paper_cpu_s"] = dict(variance_off=0.064, variance_on=0.072,
+                              note="one i5-9400 core, synthetic colon data (context)")
+    return out
+
+
+ABLATIONS = [("bdis", {}), ("no_sgmm", dict(fusion=2)), ("no_coarse_to_fine", dict(propagate=0)),
+             ("no_dynamic_sigma", dict(sigma_r_dynamic=0, sigma_r=8.0)), ("dis_weights_eq2", dict(fusion=1))]
+
+
+def bench_ablation(bdis, torch, args):
+    """Accuracy of the ablations of Sec. V (and the DIS weighting of Eq. 2) on
+    synthetic 640x480 pairs with ground truth: median / mean absolute disparity
+    error over valid pixels, and each normalised by the full method's."""
+    import numpy as np
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    dev = torch.device("cuda:0")
+    pairs = [make_pair(2, 100 + i) for i in range(args.ablation_pairs)]
+    out = {}
+    for name, kw in ABLATIONS:
+        mp = dict(method_params(2))
+        mp.update(kw)
+        ctx = bdis.Context(bdis.params(**mp), 640, 480)
+        med, mean, cov = [], [], []
+        for left, right, gt, valid in pairs:
+            d = ctx.compute(torch.from_numpy(left).to(dev), torch.from_numpy(right).to(dev))["disp"].cpu().numpy()
+            ok = np.isfinite(d) & valid
+            e = np.abs(d[ok] - gt[ok])
+            med.append(float(np.median(e)))
+            mean.append(float(e.mean()))
+            cov.append(float(ok.sum() / valid.sum()))
+        ctx.close()
+        out[name] = dict(median_px=round(float(np.mean(med)), 4), mean_px=round(float(np.mean(mean)), 4),
+                         valid_frac=round(float(np.mean(cov)), 4))
+    for name in out:
+        out[name]["median_norm"] = round(out[name]["median_px"] / out["bdis"]["median_px"], 4)
+        out[name]["mean_norm"] = round(out[name]["mean_px"] / out["bdis"]["mean_px"], 4)
+    out["config"] = (f"{args.ablation_pairs} synthetic 640x480 pairs (planes+bumps 0-64 px), L=5 P=8 S=3 K=16; "
+                     "errors averaged over pairs")
+    return out
 
 
 def bench_diff(bdis, torch, args):
@@ -263,6 +412,7 @@ def main():
     ap.add_argument("--diff-steps", type=int, default=5)
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ablation-pairs", type=int, default=4, help="pairs of the accuracy ablation (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one plain float32 copy kernel over MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -287,12 +437,17 @@ def main():
                 config=dict(workload="640x480 synthetic stereo pair (planes+bumps 0-64 px, 20% textureless, "
                                      "highlights, gain U(0.8,1.2), noise 2), L=5 P=8 S=3 K=16 variance on",
                             global_batch=1, pairs_per_step=1),
-                roofline=roofline(search_flops(bdis, p, w, h), args.steps, s["tk"], "k_search_u8<8>", "640x480"),
+                roofline=roofline(search_flops(bdis, p, w, h), args.steps, s["tk"], "k_search_u8<8>", "640x480",
+                                  search_bytes(bdis, p, w, h)),
                 kernels=kernel_table(s["tk"]),
                 ms_per_step_with_kernel_events=round(s["dt_ev"] * 1e3 / args.steps, 4),
                 epe_median_px=round(s["epe"], 4))
     if not args.no_batch:
         line["batch_1080p"] = bench_batch(bdis, torch, args)
+        line["batch_mixed"] = bench_mixed(bdis, torch, args)
+    line["paper_preset"] = bench_preset(bdis, torch, args)
+    if args.ablation_pairs > 0:
+        line["ablation"] = bench_ablation(bdis, torch, args)
     if not args.no_diff:
         line["differentiable_c4"] = bench_diff(bdis, torch, args)
     if args.copy_calibration > 0:

@@ -71,6 +71,12 @@ typedef struct {
   float var_fit_thresh;    /* largest mean squared fit residual of Eq. 17 (paper: 0.1)       */
   float prob_thresh;       /* confidence below this is invalid; 0 disables (paper: 0.15)     */
   float level_weight[BDIS_MAX_LEVELS]; /* omega_n: level n weighs omega_n / sum (Eq. 12: 2^n) */
+  int32_t fusion;          /* fusion weight of a patch at a pixel: 0 mask x probability      */
+                           /* (Eq. 13, default); 1 inverse squared photometric residual of   */
+                           /* the pixel, floored at 1 (Eq. 2, the DIS baseline); 2 Eq. 13    */
+                           /* with a uniform mask (the "no sGMM" ablation of Sec. V)         */
+  int32_t propagate;       /* 1 (default): patch probability adds the parent confidence      */
+                           /* (Eq. 11); 0: level term only (the "no coarse-to-fine" ablation)*/
 } bdis_params;
 
 /* One stereo pair of a batch (all pointers device pointers). */

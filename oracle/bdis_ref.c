@@ -348,6 +348,7 @@ static int check_params(const bdis_ref_params* p, int w, int h, int pitch) {
   if (p->levels < 1 || p->levels > MAX_LEVELS) return BDIS_REF_E_ARG;
   if (p->finest_level < 0 || p->finest_level >= p->levels) return BDIS_REF_E_ARG;
   if (p->patch < 3 || p->stride < 1 || p->stride > p->patch || p->iters < 1) return BDIS_REF_E_ARG;
+  if (p->fusion < 0 || p->fusion > 2 || (p->propagate != 0 && p->propagate != 1)) return BDIS_REF_E_ARG;
   if (!(p->sigma_s > 0.0) || !(p->sigma_r > 0.0)) return BDIS_REF_E_ARG;
   if (w < 1 || h < 1 || pitch < w) return BDIS_REF_E_ARG;
   double wsum = 0.0;
@@ -363,6 +364,19 @@ static int check_params(const bdis_ref_params* p, int w, int h, int pitch) {
     lh = (lh + 1) >> 1;
   }
   return BDIS_REF_OK;
+}
+
+/* Weight of patch k at pixel (x, y) in the fusion.  Eq. 13: mask x patch
+ * probability (fusion 0; fusion 2 passes a uniform mask).  Eq. 2 (DIS, fusion
+ * 1): the inverse squared photometric residual of the pixel under the patch's
+ * displacement, r = I_r(x + u) - I_l(x), floored at 1 as in DIS so that an
+ * exact match does not divide by zero (reading). */
+static double fusion_weight(int fusion, double m, double pi, const ref_level* lv, int x, int y,
+                            double u) {
+  if (fusion != 1) return m * pi;
+  double r = warp_sample(lv->right + (size_t)y * lv->w, lv->w, x, u) - lv->left[(size_t)y * lv->w + x];
+  double r2 = r * r;
+  return 1.0 / (r2 > 1.0 ? r2 : 1.0);
 }
 
 /* Finest level f > 0 (Sec. IV-A runs levels 5..1): the full-resolution
@@ -536,7 +550,8 @@ static int run(const bdis_ref_params* p, const double* left0, const double* righ
       double den = 0.0;
       for (int d = 0; d < NWIN; ++d) den += exp(-(s[d] - s[2]) / tau);
       lv->post[k] = 1.0 / den;
-      lv->pi[k] = gamma * lv->post[k] + lv->pipar[k];
+      /* Eq. 11; with propagation off (ablation) only the level term remains */
+      lv->pi[k] = gamma * lv->post[k] + (p->propagate ? lv->pipar[k] : 0.0);
       lv->sigk2[k] = (n == f && p->variance) ? patch_variance(s, tau, p->var_fit_thresh, sfail2) : NAN;
       mix(&lv->dhash, lv->sigk2[k] == sfail2);
     }
@@ -555,8 +570,8 @@ static int run(const bdis_ref_params* p, const double* left0, const double* righ
             if (ox + P <= x) continue;
             int k = j * lv->nx + i;
             if (lv->acc[k] == 0.0) continue;
-            double m = M[(y - oy) * P + (x - ox)];
-            double wk = m * lv->pi[k];
+            double m = p->fusion == 2 ? 1.0 : M[(y - oy) * P + (x - ox)];
+            double wk = fusion_weight(p->fusion, m, lv->pi[k], lv, x, y, lv->u[k]);
             z += wk;
             zu += wk * lv->u[k];
             zm += m;
@@ -581,7 +596,8 @@ static int run(const bdis_ref_params* p, const double* left0, const double* righ
                 if (ox + P <= x) continue;
                 int k = j * lv->nx + i;
                 if (lv->acc[k] == 0.0) continue;
-                double wn = M[(y - oy) * P + (x - ox)] * lv->pi[k] / z;
+                double m = p->fusion == 2 ? 1.0 : M[(y - oy) * P + (x - ox)];
+                double wn = fusion_weight(p->fusion, m, lv->pi[k], lv, x, y, lv->u[k]) / z;
                 zv += wn * wn * lv->sigk2[k];
               }
             }

@@ -37,6 +37,9 @@ typedef struct {
   double var_fit_thresh;   /* largest accepted mean squared fit residual (ln-p units)       */
   double prob_thresh;      /* pixels with confidence below this are invalid; 0 = off        */
   double level_weight[8];  /* omega_n; level n contributes omega_n / sum(omega)             */
+  int32_t fusion;          /* fusion weight: 0 Eq. 13 (mask x probability), 1 Eq. 2 (inverse */
+                           /* squared photometric residual, DIS), 2 Eq. 13 with a uniform mask */
+  int32_t propagate;       /* 1: add the parent confidence Pi (Eq. 11); 0: level term only    */
 } bdis_ref_params;
 
 typedef struct bdis_ref_trace bdis_ref_trace;

@@ -31,6 +31,7 @@ class RefParams(ctypes.Structure):
         ("sigma_s", ctypes.c_double), ("sigma_r", ctypes.c_double), ("valid_ratio", ctypes.c_double),
         ("var_fail_sigma", ctypes.c_double), ("var_fit_thresh", ctypes.c_double),
         ("prob_thresh", ctypes.c_double), ("level_weight", ctypes.c_double * 8),
+        ("fusion", ctypes.c_int32), ("propagate", ctypes.c_int32),
     ]
 
 
@@ -39,7 +40,7 @@ def default_params(**overrides):
     p = dict(levels=5, finest_level=0, patch=8, stride=4, iters=12, sigma_r_dynamic=1,
              variance=0, float_pyramid=0, sigma_s=4.0, sigma_r=1.0, valid_ratio=0.75,
              var_fail_sigma=0.0, var_fit_thresh=0.1, prob_thresh=0.0,
-             level_weight=[float(2 ** n) for n in range(8)])
+             level_weight=[float(2 ** n) for n in range(8)], fusion=0, propagate=1)
     for k, v in overrides.items():
         if k not in p:
             raise KeyError(k)

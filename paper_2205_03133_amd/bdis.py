@@ -31,6 +31,7 @@ class Params(ctypes.Structure):
         ("sigma_s", ctypes.c_float), ("sigma_r", ctypes.c_float), ("valid_ratio", ctypes.c_float),
         ("var_fail_sigma", ctypes.c_float), ("var_fit_thresh", ctypes.c_float),
         ("prob_thresh", ctypes.c_float), ("level_weight", ctypes.c_float * 8),
+        ("fusion", ctypes.c_int32), ("propagate", ctypes.c_int32),
     ]
 
     def as_dict(self):

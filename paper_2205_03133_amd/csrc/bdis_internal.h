@@ -152,6 +152,8 @@ struct LevelParams {
   float var_fail_sigma;  // <= 0 means P
   float sigma_s;
   float prob_thresh;
+  int fusion;       // 0 Eq. 13, 1 Eq. 2 (DIS), 2 Eq. 13 with a uniform mask
+  int propagate;    // 1: add the parent confidence (Eq. 11)
 };
 
 // Tile shapes of the flattened launches.

@@ -38,7 +38,7 @@ __global__ __launch_bounds__(kProbThreads) void k_prob(const PairLevel* tab, int
   double wsum = 0.0;
   for (int n = lp.finest; n < a.levels; ++n) wsum += (double)lp.omega[n];
   const double gamma = (double)lp.omega[lp.level] / wsum;
-  const double pi = gamma * post + gbl(a.pa.pipar)[k];
+  const double pi = gamma * post + (lp.propagate ? gbl(a.pa.pipar)[k] : 0.0);
   double sig = nan;
   if (lp.variance && lp.level == lp.finest) {
     const double sfail = lp.var_fail_sigma > 0.0f ? (double)lp.var_fail_sigma : (double)lp.P;
@@ -129,12 +129,15 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
   int pilo, pihi, piex, pjlo, pjhi, pjex;
   cover_range(x, a.g.w, P, S, a.g.nx, pilo, pihi, piex);
   cover_range(y, a.g.h, P, S, a.g.ny, pjlo, pjhi, pjex);
-  double z = 0.0, zu = 0.0, zm = 0.0, zv = 0.0;
+  double z = 0.0, zu = 0.0, zm = 0.0, zq = 0.0, zv = 0.0;
   const int jend = pjex >= 0 ? pjhi + 1 : pjhi;
+  // Eq. 2 (DIS weights): this pixel's left value and its right-image row
+  double lx = 0.0;
+  if (lp.fusion == 1) lx = a.Ld ? gbl(a.Ld)[(size_t)y * a.dpitch + x] : (double)gbl(a.L)[(size_t)y * a.pitch + x];
   const int iend = piex >= 0 ? pihi + 1 : pihi;
   for (int jj = pjlo; jj <= jend; ++jj) {
     const int j = jj <= pjhi ? jj : pjex;
-    const double mb = s_m[y - grid_origin(j, a.g.h, P, S)];
+    const double mb = lp.fusion == 2 ? 1.0 : s_m[y - grid_origin(j, a.g.h, P, S)];
     const int rj = j <= jhi ? j - jlo : nj - 1;  // row of j in the staged block
     for (int ii = pilo; ii <= iend; ++ii) {
       const int i = ii <= pihi ? ii : piex;
@@ -151,11 +154,29 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
         dv = d.z;
       }
       if (dw < 0.0) continue;  // rejected patch
-      const double m = s_m[x - grid_origin(i, a.g.w, P, S)] * mb;
-      const double wk = m * dw;
+      const double m = lp.fusion == 2 ? 1.0 : s_m[x - grid_origin(i, a.g.w, P, S)] * mb;
+      double wk = m * dw;
+      if (lp.fusion == 1) {
+        // 1 / max(1, r^2), r = I_r(x + u) - I_l(x): linear warp, indices clamped to the row
+        const double fm = floor(du);
+        const int mm = (int)fm;
+        const double fr = du - fm;
+        const int xa = clampi(x + mm, 0, a.g.w - 1), xb = clampi(x + mm + 1, 0, a.g.w - 1);
+        double ra, rb;
+        if (a.Rd) {
+          ra = gbl(a.Rd)[(size_t)y * a.dpitch + xa];
+          rb = gbl(a.Rd)[(size_t)y * a.dpitch + xb];
+        } else {
+          ra = (double)gbl(a.R)[(size_t)y * a.pitch + xa];
+          rb = (double)gbl(a.R)[(size_t)y * a.pitch + xb];
+        }
+        const double r = (1.0 - fr) * ra + fr * rb - lx;
+        wk = 1.0 / fmax(1.0, r * r);
+      }
       z += wk;
       zu += wk * du;
       zm += m;
+      zq += m * dw;
       zv += wk * wk * dv;
     }
   }
@@ -164,7 +185,7 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
   bool valid = z > 0.0;
   if (valid) {
     ub = zu / z;
-    qv = z / zm;
+    qv = zq / zm;
   } else if (finest) {
     ub = __builtin_nan("");
     qv = 0.0;

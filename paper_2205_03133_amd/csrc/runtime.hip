@@ -268,6 +268,8 @@ bdis_status check_params_msg(const bdis_params* p, char* msg, size_t n) {
     return snprintf(msg, n, "stride %d outside 1..patch", p->stride), BDIS_E_ARG;
   if (p->iters < 1 || p->iters > 256) return snprintf(msg, n, "iters %d outside 1..256", p->iters), BDIS_E_ARG;
   if (p->float_pyramid != 0 && p->float_pyramid != 1) return snprintf(msg, n, "float_pyramid must be 0 or 1"), BDIS_E_ARG;
+  if (p->fusion < 0 || p->fusion > 2) return snprintf(msg, n, "fusion %d outside 0..2", p->fusion), BDIS_E_ARG;
+  if (p->propagate != 0 && p->propagate != 1) return snprintf(msg, n, "propagate must be 0 or 1"), BDIS_E_ARG;
   if (!finite_f(p->sigma_s) || !(p->sigma_s > 0.0f)) return snprintf(msg, n, "sigma_s must be > 0"), BDIS_E_ARG;
   if (!finite_f(p->sigma_r) || !(p->sigma_r > 0.0f)) return snprintf(msg, n, "sigma_r must be > 0"), BDIS_E_ARG;
   if (!finite_f(p->valid_ratio)) return snprintf(msg, n, "valid_ratio not finite"), BDIS_E_ARG;
@@ -332,6 +334,8 @@ LevelParams level_params(const bdis_params& p, int n) {
   lp.var_fail_sigma = p.var_fail_sigma;
   lp.sigma_s = p.sigma_s;
   lp.prob_thresh = p.prob_thresh;
+  lp.fusion = p.fusion;
+  lp.propagate = p.propagate;
   return lp;
 }
 
@@ -803,6 +807,8 @@ bdis_status run_pairs_f32(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipSt
 bdis_status run_backward(bdis_ctx* c, std::vector<PairSpec> pairs, double* grad_hyper, hipStream_t st) {
   if (c->p.finest_level != 0)
     return fail(c, BDIS_E_ARG, "backward needs finest_level 0 (no adjoint of the upsampling)");
+  if (c->p.fusion != 0 || c->p.propagate != 1)
+    return fail(c, BDIS_E_ARG, "backward needs fusion 0 and propagate 1 (the method's own weights)");
   Plan pl;
   bdis_status s = build_plan(c, pairs, &pl, true);
   if (s != BDIS_OK) return s;
@@ -860,6 +866,8 @@ bdis_status bdis_params_default(bdis_params* p) {
   p->var_fail_sigma = 0.0f;
   p->var_fit_thresh = 0.1f;
   p->prob_thresh = 0.0f;
+  p->fusion = 0;
+  p->propagate = 1;
   for (int n = 0; n < BDIS_MAX_LEVELS; ++n) p->level_weight[n] = (float)(1 << n);
   return BDIS_OK;
 }

@@ -46,7 +46,7 @@ def oracle_params(oracle, bp):
         float_pyramid=d["float_pyramid"], sigma_s=float(d["sigma_s"]), sigma_r=float(d["sigma_r"]),
         valid_ratio=float(d["valid_ratio"]), var_fail_sigma=float(d["var_fail_sigma"]),
         var_fit_thresh=float(d["var_fit_thresh"]), prob_thresh=float(d["prob_thresh"]),
-        level_weight=[float(x) for x in d["level_weight"]])
+        level_weight=[float(x) for x in d["level_weight"]], fusion=d["fusion"], propagate=d["propagate"])
 
 
 def footprint(mask_patches, w, h, P, S):

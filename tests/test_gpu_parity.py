@@ -139,6 +139,31 @@ def test_paper_preset_finest_level(B, oracle, f, prob):
     ctx.close()
 
 
+@pytest.mark.parametrize("variant", [dict(fusion=1), dict(fusion=2), dict(propagate=0),
+                                     dict(sigma_r_dynamic=0, sigma_r=8.0)])
+def test_ablation_variants(B, oracle, variant):
+    """The ablations of Sec. V (no sGMM, no coarse-to-fine probability, fixed
+    sigma_r = 8) and the DIS fusion weights of Eq. 2, against the oracle."""
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    left, right, gt, valid = make_pair(2, 2)
+    kw = dict(method_params(2))
+    kw.update(variant)
+    p = B.params(**kw)
+    ctx, g = _run(B, left, right, p, f"ablation {variant}")
+    r = oracle.compute(left, right, oracle_params(oracle, p), trace=True)
+    _patch_parity(B, ctx, r["trace"], p.levels)
+    st = parity(g["disp"], r["disp"], DISP_TOL)
+    _report("disparity", st)
+    assert st["frac"] >= PASS_FRAC
+    stc = parity(g["conf"], r["conf"], 1e-4)
+    _report("confidence", stc)
+    assert stc["frac"] >= PASS_FRAC
+    _check_variance(ctx, r["trace"], g, r, p)
+    ok = np.isfinite(g["disp"]) & valid
+    print(f"  EPE vs ground truth: median={np.median(np.abs(g['disp'][ok] - gt[ok])):.4f} px", flush=True)
+    ctx.close()
+
+
 def test_depth_form(B, oracle):
     import torch
     from paper_2205_03133_amd.synth import make_pair, method_params

@@ -639,3 +639,92 @@ def test_depth_is_the_delta_method(oracle):
     bad = np.array([0.0, -1.0, np.nan])
     zb, zvb = oracle.depth(bad, np.ones(3), fb)
     assert np.all(np.isnan(zb)) and np.all(np.isnan(zvb))
+
+
+# --------------------------------------------------------------------------
+# Ablation weightings (Sec. V ablation study; Eq. 2 of the DIS baseline)
+# --------------------------------------------------------------------------
+
+def _cells(n, P, S, grid):
+    """Label of each coordinate by the set of patches covering it (grid origins)."""
+    o = grid(n, P, S)
+    cover = [tuple(np.nonzero((o <= x) & (x < o + P))[0]) for x in range(n)]
+    labels, out = {}, np.empty(n, np.int64)
+    for x, c in enumerate(cover):
+        out[x] = labels.setdefault(c, len(labels))
+    return out
+
+
+def test_uniform_mask_is_piecewise_constant(oracle):
+    """fusion 2 (no sGMM: equal weight for every pixel of a patch): the fused map is
+    constant wherever the set of covering patches is; the mixture mask (fusion 0)
+    is not."""
+    from paper_2205_03133_amd.synth import make_pair
+    left, right, _, _ = make_pair(1, 4)
+    left, right = np.ascontiguousarray(left[:96, :160]), np.ascontiguousarray(right[:96, :160])
+    P, S = 8, 3
+    lx, ly = _cells(160, P, S, oracle.grid), _cells(96, P, S, oracle.grid)
+    cell = ly[:, None] * 1000 + lx[None, :]
+
+    def spread(fusion):
+        p = oracle.default_params(levels=2, patch=P, stride=S, iters=8, fusion=fusion)
+        u = oracle.compute(left, right, p, trace=True)["trace"].get(0, "ubar")
+        worst = 0.0
+        for c in np.unique(cell):
+            v = u[cell == c]
+            v = v[np.isfinite(v)]
+            if v.size > 1:
+                worst = max(worst, float(v.max() - v.min()))
+        return worst
+
+    assert spread(2) <= 1e-12
+    assert spread(0) > 1e-3
+
+
+def test_no_propagation_keeps_level_term_only(oracle):
+    """propagate 0 (no coarse-to-fine probability): every accepted patch has
+    pi = Gamma_n * post, however confident its parent was; with propagation the
+    parent's confidence is added on."""
+    from paper_2205_03133_amd.synth import make_pair
+    left, right, _, _ = make_pair(1, 5)
+    for prop in (0, 1):
+        p = oracle.default_params(levels=3, patch=8, stride=4, iters=8, propagate=prop)
+        t = oracle.compute(left, right, p, trace=True)["trace"]
+        for n in range(3):
+            acc = t.get(n, "acc") > 0
+            extra = t.get(n, "pi")[acc] - t.scalar(n, "gamma") * t.get(n, "post")[acc]
+            if prop == 0:
+                assert np.all(extra == 0.0)
+            elif n < 2:
+                np.testing.assert_allclose(extra, t.get(n, "pipar")[acc], rtol=1e-15, atol=1e-15)
+                assert extra.max() > 0.0
+
+
+def test_dis_weights_from_library_interpolation(oracle):
+    """fusion 1 (Eq. 2, DIS): each covering patch weighs 1 / max(1, r^2) with r the
+    photometric residual of the pixel under its displacement; r is computed here
+    with scipy's linear interpolation of the right image (edge-clamped)."""
+    from paper_2205_03133_amd.synth import make_pair
+    left, right, _, _ = make_pair(1, 6)
+    left, right = np.ascontiguousarray(left[:64, :96]), np.ascontiguousarray(right[:64, :96])
+    P, S = 8, 4
+    p = oracle.default_params(levels=1, patch=P, stride=S, iters=8, fusion=1)
+    t = oracle.compute(left, right, p, trace=True)["trace"]
+    u, acc, ub = t.get(0, "u"), t.get(0, "acc") > 0, t.get(0, "ubar")
+    ox, oy = oracle.grid(96, P, S), oracle.grid(64, P, S)
+    L, R = left.astype(np.float64), right.astype(np.float64)
+    num = np.zeros((64, 96))
+    den = np.zeros((64, 96))
+    yy, xx = np.mgrid[0:64, 0:96].astype(np.float64)
+    for j in range(len(oy)):
+        for i in range(len(ox)):
+            if not acc[j, i]:
+                continue
+            sl = (slice(oy[j], oy[j] + P), slice(ox[i], ox[i] + P))
+            warped = ndimage.map_coordinates(R, [yy[sl], xx[sl] + u[j, i]], order=1, mode="nearest")
+            wgt = 1.0 / np.maximum(1.0, (warped - L[sl]) ** 2)
+            num[sl] += wgt * u[j, i]
+            den[sl] += wgt
+    ok = den > 0
+    np.testing.assert_allclose(ub[ok], num[ok] / den[ok], rtol=1e-12, atol=1e-12)
+    assert np.all(np.isnan(ub[~ok]))
