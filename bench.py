@@ -336,6 +336,32 @@ def bench_ablation(bdis, torch, args):
     return out
 
 
+def bench_coverage(bdis, torch, args):
+    """Variance coverage per frame (the Table 6 check on synthetic ground truth):
+    fraction of valid pixels with |d - d_gt| <= 1.96 sqrt(Var), on the 640x480
+    workload and on the paper preset (levels 5..1, variance upsampled)."""
+    import numpy as np
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    dev = torch.device("cuda:0")
+    pairs = [make_pair(2, 200 + i) for i in range(args.ablation_pairs)]
+    presets = dict(workload_640x480=dict(method_params(2)),
+                   paper_preset=dict(levels=6, finest_level=1, patch=10, stride=4, iters=12, valid_ratio=0.75,
+                                     sigma_s=4.0, prob_thresh=0.15, variance=1))
+    out = {}
+    for name, mp in presets.items():
+        ctx = bdis.Context(bdis.params(**mp), 640, 480)
+        fr = []
+        for left, right, gt, valid in pairs:
+            o = ctx.compute(torch.from_numpy(left).to(dev), torch.from_numpy(right).to(dev))
+            c, t = ctx.coverage(o["disp"], o["var"], torch.from_numpy(gt.astype(np.float32)).to(dev), 1.96,
+                                valid=torch.from_numpy(valid.astype(np.uint8)).to(dev))
+            fr.append(c / max(t, 1))
+        ctx.close()
+        out[name] = dict(per_frame=[round(x, 4) for x in fr], mean=round(float(np.mean(fr)), 4),
+                         ideal=0.95)
+    return out
+
+
 def bench_diff(bdis, torch, args):
     """Differentiable form: a batch of 16 float 640x480 pairs, forward and backward
     (K = 8 unrolled, 4 levels, P 8, S 4), and the plain uint8 form on the same pairs."""
@@ -448,6 +474,7 @@ def main():
     line["paper_preset"] = bench_preset(bdis, torch, args)
     if args.ablation_pairs > 0:
         line["ablation"] = bench_ablation(bdis, torch, args)
+        line["variance_coverage"] = bench_coverage(bdis, torch, args)
     if not args.no_diff:
         line["differentiable_c4"] = bench_diff(bdis, torch, args)
     if args.copy_calibration > 0:

@@ -183,6 +183,16 @@ bdis_status bdis_backward_batch(bdis_ctx* ctx, int n, const bdis_pair_grad* grad
 bdis_status bdis_depth(bdis_ctx* ctx, const float* disparity, const float* variance, int w, int h, int pitch,
                        float fb, float* depth, float* depth_variance, void* stream);
 
+/* Variance coverage (the frame-wise check of Sec. V, Table 6): over the pixels of
+ * a W x H map with a finite disparity, a finite non-negative variance, a finite
+ * reference disparity and valid != 0 (`valid` may be NULL), counts those with
+ * |d - ref| <= k sqrt(var), the comparison taken in double precision.
+ * counts: DEVICE array of 2 int64 (covered, considered), overwritten.
+ * disparity/variance/reference are float maps with row pitch `pitch`, valid
+ * (uint8) shares it.  Asynchronous on `stream`.  Errors: BDIS_E_ARG. */
+bdis_status bdis_coverage(bdis_ctx* ctx, const float* disparity, const float* variance, const float* reference,
+                          const uint8_t* valid, int w, int h, int pitch, float k, long long* counts, void* stream);
+
 /* Debug access to the intermediates of the last single-pair compute (the
  * call synchronises `stream`).  `what` selects the array (BDIS_DBG_*), bytes
  * is the capacity of host_dst; returns BDIS_E_ARG if too small. */

@@ -415,6 +415,21 @@ static void upsample(const ref_level* lf, int f, int w, int h, int variance, dou
     }
 }
 
+int bdis_ref_coverage(const double* disp, const double* var, const double* ref, const uint8_t* valid,
+                      long n, double k, long* covered, long* total) {
+  if (!disp || !var || !ref || !covered || !total || n < 0 || !(k >= 0.0)) return BDIS_REF_E_ARG;
+  long c = 0, t = 0;
+  for (long i = 0; i < n; ++i) {
+    if (valid && !valid[i]) continue;
+    if (!isfinite(disp[i]) || !isfinite(var[i]) || !isfinite(ref[i]) || var[i] < 0.0) continue;
+    ++t;
+    if (fabs(disp[i] - ref[i]) <= k * sqrt(var[i])) ++c;
+  }
+  *covered = c;
+  *total = t;
+  return BDIS_REF_OK;
+}
+
 int bdis_ref_depth(const double* disp, const double* var, long n, double fb, double* depth,
                    double* depth_var) {
   if (!disp || !depth || n < 0 || !(fb > 0.0)) return BDIS_REF_E_ARG;

@@ -95,6 +95,13 @@ int bdis_ref_grid(int n, int patch, int stride, int* origins, int cap);
 /* Spatial mixture mask M (P x P, row b, column a), as defined for the densification. */
 int bdis_ref_mask(int patch, double sigma_s, double* dst);
 
+/* Variance coverage (the frame-wise check of Sec. V, Table 6): over pixels with a
+ * valid disparity, a finite variance, a finite reference and valid[i] != 0 (valid
+ * may be NULL), counts those with |d - ref| <= k sqrt(var).  Writes the count
+ * and the number of pixels considered. */
+int bdis_ref_coverage(const double* disp, const double* var, const double* ref, const uint8_t* valid,
+                      long n, double k, long* covered, long* total);
+
 /* Depth form (Eq. 14, 18): depth = fb / d and depth variance (fb)^2 / d^4 * var
  * for d > 0 (fb = focal length x baseline, in the units wanted for depth);
  * NaN elsewhere.  `var` and `depth_var` may be NULL. */

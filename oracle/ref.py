@@ -98,6 +98,8 @@ def lib():
                                     ctypes.POINTER(ctypes.c_int), ctypes.c_int]
         L.bdis_ref_mask.argtypes = [ctypes.c_int, ctypes.c_double, dp]
         L.bdis_ref_depth.argtypes = [dp, dp, ctypes.c_long, ctypes.c_double, dp, dp]
+        L.bdis_ref_coverage.argtypes = [dp, dp, dp, ctypes.c_void_p, ctypes.c_long, ctypes.c_double,
+                                        ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]
         _lib = L
     return _lib
 
@@ -218,3 +220,18 @@ def depth(disp, var, fb):
     if st:
         raise OracleError(st)
     return out, ov
+
+
+def coverage(disp, var, ref, k=1.96, valid=None):
+    """(covered, total): pixels with |d - ref| <= k sqrt(var) among the usable ones."""
+    dp = ctypes.POINTER(ctypes.c_double)
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (disp, var, ref)]
+    vm = None if valid is None else np.ascontiguousarray(valid, dtype=np.uint8)
+    c, t = ctypes.c_long(), ctypes.c_long()
+    st = lib().bdis_ref_coverage(*(a.ctypes.data_as(dp) for a in arrs),
+                                 vm.ctypes.data if vm is not None else None, arrs[0].size, k,
+                                 ctypes.byref(c), ctypes.byref(t))
+    if st:
+        raise OracleError(st)
+    return c.value, t.value
+

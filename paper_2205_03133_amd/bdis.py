@@ -100,6 +100,7 @@ def lib():
         L.bdis_timing_enable.argtypes = [vp, i32]
         L.bdis_timing_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long)]
         L.bdis_depth.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.c_float, vp, vp, vp]
+        L.bdis_coverage.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, vp, vp]
         for name in ("bdis_params_default", "bdis_params_check", "bdis_create", "bdis_set_params",
                      "bdis_compute", "bdis_compute_batch", "bdis_debug_dump", "bdis_level_dims",
                      "bdis_timing_enable", "bdis_timing_read", "bdis_compute_f32", "bdis_compute_f32_batch",
@@ -283,6 +284,29 @@ class Context:
         if st:
             raise self._err(st)
         return depth, dvar
+
+    def coverage(self, disp, var, ref, k=1.96, valid=None, stream=None):
+        """Variance coverage of one frame: (covered, considered) pixel counts of
+        |d - ref| <= k sqrt(var) (float32 CUDA maps, shared row stride; `valid`
+        an optional uint8 mask).  Synchronises the stream to return the counts."""
+        import torch
+        dp, w, h, pitch = _image_arg(disp, "disparity", torch.float32)
+        vp_, w2, h2, p2 = _image_arg(var, "variance", torch.float32)
+        rp, w3, h3, p3 = _image_arg(ref, "reference", torch.float32)
+        if not (w == w2 == w3 and h == h2 == h3 and pitch == p2 == p3):
+            raise ValueError("disparity, variance and reference must share shape and row stride")
+        mp = None
+        if valid is not None:
+            mp, w4, h4, p4 = _image_arg(valid, "valid", torch.uint8)
+            if (w4, h4, p4) != (w, h, pitch):
+                raise ValueError("valid must share shape and row stride")
+        counts = torch.empty(2, dtype=torch.int64, device=disp.device)
+        st = lib().bdis_coverage(self._h, dp, vp_, rp, mp, w, h, pitch, float(k), counts.data_ptr(),
+                                 _stream_ptr(stream))
+        if st:
+            raise self._err(st)
+        c = counts.cpu()
+        return int(c[0]), int(c[1])
 
     KERNELS = ("pyramid", "search", "prob", "fuse", "reduce", "backward")
 

@@ -184,6 +184,8 @@ hipError_t launch_prob(const PairLevel* tab, int npairs, int nblocks, const Leve
 hipError_t launch_fuse(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,
                        hipStream_t s);
 hipError_t launch_upsample(const PairLevel* tab, int npairs, int nblocks, hipStream_t s);
+hipError_t launch_coverage(const float* disp, const float* var, const float* ref, const uint8_t* valid, int w,
+                           int h, int pitch, double k, unsigned long long* counts, hipStream_t s);
 hipError_t launch_depth(const float* disp, const float* var, int w, int h, int pitch, float fb, float* depth,
                         float* dvar, hipStream_t s);
 

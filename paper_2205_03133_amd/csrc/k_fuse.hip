@@ -273,6 +273,46 @@ __global__ __launch_bounds__(kPixThreads) void k_depth(const float* disp, const 
   }
 }
 
+// Per pixel: does the reference disparity lie within k standard deviations?
+// Block sums in LDS, one integer atomic per block (order-independent).
+__global__ __launch_bounds__(kPixThreads) void k_coverage(const float* disp, const float* var, const float* ref,
+                                                          const uint8_t* valid, int w, int h, int pitch, double k,
+                                                          unsigned long long* counts) {
+  __shared__ unsigned s_c[kPixThreads], s_t[kPixThreads];
+  const int tid = threadIdx.x;
+  const int idx = (int)blockIdx.x * kPixThreads + tid;
+  unsigned c = 0, t = 0;
+  if (idx < w * h) {
+    const int y = idx / w, x = idx - y * w;
+    const size_t o = (size_t)y * pitch + x;
+    const double d = (double)gbl(disp)[o], v = (double)gbl(var)[o], r = (double)gbl(ref)[o];
+    const bool use = (!valid || gbl(valid)[o] != 0) && isfinite(d) && isfinite(v) && isfinite(r) && v >= 0.0;
+    if (use) {
+      t = 1;
+      c = fabs(d - r) <= k * sqrt(v) ? 1 : 0;
+    }
+  }
+  s_c[tid] = c;
+  s_t[tid] = t;
+  __syncthreads();
+  for (int off = kPixThreads / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      s_c[tid] += s_c[tid + off];
+      s_t[tid] += s_t[tid + off];
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && s_t[0] > 0) {
+    atomicAdd(counts, (unsigned long long)s_c[0]);
+    atomicAdd(counts + 1, (unsigned long long)s_t[0]);
+  }
+}
+
+// Zeroes the two counters (a kernel, so that the call stays capturable).
+__global__ void k_zero2(unsigned long long* counts) {
+  if (threadIdx.x < 2) counts[threadIdx.x] = 0ull;
+}
+
 }  // namespace
 
 hipError_t launch_prob(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
@@ -298,6 +338,15 @@ hipError_t launch_depth(const float* disp, const float* var, int w, int h, int p
   const long n = (long)w * h;
   hipLaunchKernelGGL(k_depth, dim3((unsigned)((n + kPixThreads - 1) / kPixThreads)), dim3(kPixThreads), 0, s, disp,
                      var, w, h, pitch, fb, depth, dvar);
+  return hipGetLastError();
+}
+
+hipError_t launch_coverage(const float* disp, const float* var, const float* ref, const uint8_t* valid, int w,
+                           int h, int pitch, double k, unsigned long long* counts, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, s, counts);
+  const long n = (long)w * h;
+  hipLaunchKernelGGL(k_coverage, dim3((unsigned)((n + kPixThreads - 1) / kPixThreads)), dim3(kPixThreads), 0, s,
+                     disp, var, ref, valid, w, h, pitch, k, counts);
   return hipGetLastError();
 }
 

@@ -1111,6 +1111,19 @@ bdis_status bdis_depth(bdis_ctx* c, const float* disp, const float* var, int w, 
   return e == hipSuccess ? BDIS_OK : hip_fail(c, e, "depth launch");
 }
 
+bdis_status bdis_coverage(bdis_ctx* c, const float* disp, const float* var, const float* ref, const uint8_t* valid,
+                          int w, int h, int pitch, float k, long long* counts, void* stream) {
+  if (!c) return BDIS_E_ARG;
+  if (!disp || !var || !ref || !counts) return fail(c, BDIS_E_ARG, "disparity, variance, reference and counts are required");
+  if (w < 1 || h < 1 || pitch < w || (long)w * h > (long)INT32_MAX)
+    return fail(c, BDIS_E_ARG, "bad map size %dx%d pitch %d", w, h, pitch);
+  if (!finite_f(k) || k < 0.0f) return fail(c, BDIS_E_ARG, "k must be finite and >= 0");
+  const hipError_t e = launch_coverage(disp, var, ref, valid, w, h, pitch, (double)k,
+                                       reinterpret_cast<unsigned long long*>(counts),
+                                       reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? BDIS_OK : hip_fail(c, e, "coverage launch");
+}
+
 bdis_status bdis_level_dims(const bdis_params* p, int w, int h, int level, int* lw, int* lh, int* nx, int* ny) {
   char msg[256];
   if (check_params_msg(p, msg, sizeof msg) != BDIS_OK) return BDIS_E_ARG;

@@ -164,6 +164,25 @@ def test_ablation_variants(B, oracle, variant):
     ctx.close()
 
 
+def test_variance_coverage_counts(B, oracle):
+    """Coverage of the 1.96-sigma interval on a 640x480 frame: GPU counts equal the
+    oracle's on the same maps (both compare in double precision)."""
+    import torch
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    left, right, gt, valid = make_pair(2, 3)
+    p = B.params(**method_params(2))
+    ctx, g = _run(B, left, right, p, "variance coverage")
+    k = float(np.float32(1.96))
+    c, t = ctx.coverage(to_gpu(g["disp"]), to_gpu(g["var"]), to_gpu(gt.astype(np.float32)), k,
+                        valid=to_gpu(valid.astype(np.uint8)))
+    cr, tr_ = oracle.coverage(g["disp"], g["var"], gt.astype(np.float32), k, valid.astype(np.uint8))
+    print(f"  coverage {c}/{t} = {c / max(t, 1):.4f} (oracle {cr}/{tr_})", flush=True)
+    assert (c, t) == (cr, tr_) and t > 0
+    c2, t2 = ctx.coverage(to_gpu(g["disp"]), to_gpu(g["var"]), to_gpu(gt.astype(np.float32)), k)
+    assert (c2, t2) == oracle.coverage(g["disp"], g["var"], gt.astype(np.float32), k)
+    ctx.close()
+
+
 def test_depth_form(B, oracle):
     import torch
     from paper_2205_03133_amd.synth import make_pair, method_params

@@ -728,3 +728,24 @@ def test_dis_weights_from_library_interpolation(oracle):
     ok = den > 0
     np.testing.assert_allclose(ub[ok], num[ok] / den[ok], rtol=1e-12, atol=1e-12)
     assert np.all(np.isnan(ub[~ok]))
+
+
+def test_coverage_of_gaussian_errors(oracle):
+    """Coverage of the 1.96-sigma interval: with errors drawn from N(0, var) the
+    expected fraction is erf(1.96 / sqrt 2) = 0.9500 (binomial spread ~0.0007 at
+    10^5 draws); k = 1 gives 0.6827.  Invalid and non-finite pixels are skipped."""
+    rng = np.random.default_rng(11)
+    n = 100_000
+    var = rng.uniform(0.01, 4.0, n)
+    ref = rng.uniform(0.0, 60.0, n)
+    d = ref + rng.standard_normal(n) * np.sqrt(var)
+    for k, expect in ((1.96, math.erf(1.96 / math.sqrt(2))), (1.0, math.erf(1.0 / math.sqrt(2)))):
+        c, t = oracle.coverage(d, var, ref, k)
+        assert t == n
+        assert abs(c / t - expect) < 4 * math.sqrt(expect * (1 - expect) / n)
+    valid = np.ones(n, np.uint8)
+    valid[:10] = 0
+    d2 = d.copy()
+    d2[10:20] = np.nan
+    c, t = oracle.coverage(d2, var, ref, 1.96, valid)
+    assert t == n - 20
