@@ -34,6 +34,7 @@ typedef struct {
   /* maps */
   double *ubar, *qmap, *valid;
   double *odisp, *ovar, *oconf; /* finest level f > 0: outputs before upsampling */
+  double *fv, *vbar, *gy;        /* optical flow: per patch v, level map of v, y-gradient */
   double sigma_r2, tau, nacc, gamma;
   uint64_t dhash; /* hash of every discrete decision taken on this level */
 } ref_level;
@@ -299,7 +300,7 @@ static void free_level(ref_level* lv) {
   double** ptrs[] = {&lv->left, &lv->right, &lv->grad, &lv->uinit, &lv->pipar, &lv->u,
                      &lv->ssd,  &lv->rho,   &lv->acc,  &lv->post,  &lv->pi,    &lv->sigk2,
                      &lv->hess, &lv->ubar,  &lv->qmap, &lv->valid, &lv->odisp, &lv->ovar,
-                     &lv->oconf};
+                     &lv->oconf, &lv->fv,   &lv->vbar, &lv->gy};
   for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); ++i) {
     free(*ptrs[i]);
     *ptrs[i] = NULL;
@@ -706,6 +707,169 @@ int bdis_ref_compute_f64(const bdis_ref_params* p, const double* left, const dou
   return st;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Optical flow (2-D dense inverse search).  Eq. 1 with u a 2-vector: the     */
+/* inverse-compositional update of DIS on a 2 x 2 Hessian, the template       */
+/* gradients Sobel-x / 8 and Sobel-y / 8 (reflect-101), the warp bilinear in  */
+/* both axes with indices clamped to the image, and the fusion of Eq. 2.      */
+/* ------------------------------------------------------------------------- */
+static void sobel_y(const double* img, int w, int h, double* g) {
+  for (int y = 0; y < h; ++y) {
+    int ym = reflect101(y - 1, h), yp = reflect101(y + 1, h);
+    for (int x = 0; x < w; ++x) {
+      int xm = reflect101(x - 1, w), xp = reflect101(x + 1, w);
+      double gs = (img[(size_t)yp * w + xm] - img[(size_t)ym * w + xm]) +
+                  2.0 * (img[(size_t)yp * w + x] - img[(size_t)ym * w + x]) +
+                  (img[(size_t)yp * w + xp] - img[(size_t)ym * w + xp]);
+      g[(size_t)y * w + x] = gs / 8.0;
+    }
+  }
+}
+
+/* One patch: J = (gx - mean gx, gy - mean gy) over the patch, H = sum J J^T;
+ * K iterations of (u, v) <- (u, v) - H^-1 sum J (I1(x + u, y + v) - T); no update
+ * when det H < EPS_H (reading: the 1-D floor applied to the determinant);
+ * reset to the start when the step from it exceeds P in Euclidean length. */
+static void flow_patch(ref_level* lv, const bdis_ref_params* p, int k, int ox, int oy, double u0, double v0) {
+  const int P = p->patch, w = lv->w, h = lv->h, n = P * P;
+  const double *I0 = lv->left, *I1 = lv->right, *GX = lv->grad, *GY = lv->gy;
+  double mx = 0.0, my = 0.0;
+  for (int r = 0; r < P; ++r)
+    for (int c = 0; c < P; ++c) {
+      mx += GX[(size_t)(oy + r) * w + ox + c];
+      my += GY[(size_t)(oy + r) * w + ox + c];
+    }
+  mx /= n;
+  my /= n;
+  double hxx = 0.0, hxy = 0.0, hyy = 0.0;
+  for (int r = 0; r < P; ++r)
+    for (int c = 0; c < P; ++c) {
+      double jx = GX[(size_t)(oy + r) * w + ox + c] - mx, jy = GY[(size_t)(oy + r) * w + ox + c] - my;
+      hxx += jx * jx;
+      hxy += jx * jy;
+      hyy += jy * jy;
+    }
+  const double det = hxx * hyy - hxy * hxy;
+  lv->hess[k] = det;
+  double u = u0, v = v0;
+  if (det >= EPS_H) {
+    for (int t = 0; t < p->iters; ++t) {
+      double bx = 0.0, by = 0.0;
+      for (int r = 0; r < P; ++r)
+        for (int c = 0; c < P; ++c) {
+          size_t idx = (size_t)(oy + r) * w + ox + c;
+          double e = bilinear(I1, w, h, ox + c + u, oy + r + v) - I0[idx];
+          bx += (GX[idx] - mx) * e;
+          by += (GY[idx] - my) * e;
+        }
+      mix(&lv->dhash, (long long)floor(u));
+      mix(&lv->dhash, (long long)floor(v));
+      /* H^-1 b by the 2 x 2 adjugate */
+      u -= (hyy * bx - hxy * by) / det;
+      v -= (hxx * by - hxy * bx) / det;
+    }
+  }
+  const int reset = (u - u0) * (u - u0) + (v - v0) * (v - v0) > (double)P * (double)P;
+  mix(&lv->dhash, reset);
+  if (reset) {
+    u = u0;
+    v = v0;
+  }
+  lv->uinit[k] = u0;
+  lv->u[k] = u;
+  lv->fv[k] = v;
+  lv->acc[k] = 1.0;
+}
+
+int bdis_ref_flow(const bdis_ref_params* p, const uint8_t* i0, const uint8_t* i1, int w, int h, int pitch,
+                  double* flow_u, double* flow_v, bdis_ref_trace** trace_out) {
+  if (trace_out) *trace_out = NULL;
+  if (!i0 || !i1 || !flow_u || !flow_v) return BDIS_REF_E_ARG;
+  int st = check_params(p, w, h, pitch);
+  if (st) return st;
+  if (p->finest_level != 0) return BDIS_REF_E_ARG;
+  const int L = p->levels, P = p->patch, S = p->stride;
+  bdis_ref_trace* t = calloc(1, sizeof(*t));
+  if (!t) return BDIS_REF_E_NOMEM;
+  t->levels = L;
+  int lw = w, lh = h;
+  for (int n = 0; n < L; ++n) {
+    ref_level* lv = &t->lv[n];
+    int bad = alloc_level(lv, lw, lh, P, S);
+    size_t np = (size_t)lv->nx * lv->ny, npx = (size_t)lw * lh;
+    lv->fv = calloc(np, sizeof(double));
+    lv->vbar = calloc(npx, sizeof(double));
+    lv->gy = calloc(npx, sizeof(double));
+    if (bad || !lv->fv || !lv->vbar || !lv->gy) {
+      bdis_ref_trace_free(t);
+      return BDIS_REF_E_NOMEM;
+    }
+    lw = (lw + 1) >> 1;
+    lh = (lh + 1) >> 1;
+  }
+  for (int y = 0; y < h; ++y)
+    for (int x = 0; x < w; ++x) {
+      t->lv[0].left[(size_t)y * w + x] = (double)i0[(size_t)y * pitch + x];
+      t->lv[0].right[(size_t)y * w + x] = (double)i1[(size_t)y * pitch + x];
+    }
+  for (int n = 1; n < L; ++n) {
+    ref_level *a = &t->lv[n - 1], *b = &t->lv[n];
+    pyramid_down(a->left, a->w, a->h, b->left, b->w, b->h, 1);
+    pyramid_down(a->right, a->w, a->h, b->right, b->w, b->h, 1);
+  }
+  for (int n = L - 1; n >= 0; --n) {
+    ref_level* lv = &t->lv[n];
+    const ref_level* par = n + 1 < L ? &t->lv[n + 1] : NULL;
+    sobel_x(lv->left, lv->w, lv->h, lv->grad);
+    sobel_y(lv->left, lv->w, lv->h, lv->gy);
+    for (int j = 0; j < lv->ny; ++j)
+      for (int i = 0; i < lv->nx; ++i) {
+        const int ox = grid_origin(i, lv->w, P, S), oy = grid_origin(j, lv->h, P, S);
+        double u0 = 0.0, v0 = 0.0;
+        if (par) { /* the parent's fused flow at the patch centre, in this level's pixels */
+          const double cx = ox + 0.5 * (P - 1), cy = oy + 0.5 * (P - 1);
+          u0 = 2.0 * bilinear(par->ubar, par->w, par->h, 0.5 * cx, 0.5 * cy);
+          v0 = 2.0 * bilinear(par->vbar, par->w, par->h, 0.5 * cx, 0.5 * cy);
+        }
+        flow_patch(lv, p, j * lv->nx + i, ox, oy, u0, v0);
+      }
+    /* Eq. 2 fusion: weight 1 / max(1, r^2), r = I1(x + u_k) - I0(x) */
+    for (int y = 0; y < lv->h; ++y)
+      for (int x = 0; x < lv->w; ++x) {
+        double z = 0.0, zu = 0.0, zv = 0.0;
+        for (int j = 0; j < lv->ny; ++j) {
+          int oy = grid_origin(j, lv->h, P, S);
+          if (oy > y) break;
+          if (oy + P <= y) continue;
+          for (int i = 0; i < lv->nx; ++i) {
+            int ox = grid_origin(i, lv->w, P, S);
+            if (ox > x) break;
+            if (ox + P <= x) continue;
+            int k = j * lv->nx + i;
+            double r = bilinear(lv->right, lv->w, lv->h, x + lv->u[k], y + lv->fv[k]) -
+                       lv->left[(size_t)y * lv->w + x];
+            double wk = 1.0 / (r * r > 1.0 ? r * r : 1.0);
+            z += wk;
+            zu += wk * lv->u[k];
+            zv += wk * lv->fv[k];
+          }
+        }
+        size_t idx = (size_t)y * lv->w + x;
+        lv->ubar[idx] = zu / z; /* every pixel is covered: z > 0 */
+        lv->vbar[idx] = zv / z;
+        if (n == 0) {
+          flow_u[idx] = lv->ubar[idx];
+          flow_v[idx] = lv->vbar[idx];
+        }
+      }
+  }
+  if (trace_out)
+    *trace_out = t;
+  else
+    bdis_ref_trace_free(t);
+  return BDIS_REF_OK;
+}
+
 /* Patch-grid origins along an axis of length n; returns the count (or < 0). */
 int bdis_ref_grid(int n, int P, int S, int* origins, int cap) {
   if (P < 1 || S < 1 || n < P) return BDIS_REF_E_ARG;
@@ -757,6 +921,9 @@ long bdis_ref_trace_get(const bdis_ref_trace* t, int level, int what, double* ds
     case BDIS_REF_ODISP: src = lv->odisp; cnt = npx; break;
     case BDIS_REF_OVAR: src = lv->ovar; cnt = npx; break;
     case BDIS_REF_OCONF: src = lv->oconf; cnt = npx; break;
+    case BDIS_REF_FV: src = lv->fv; cnt = np; break;
+    case BDIS_REF_VBAR: src = lv->vbar; cnt = npx; break;
+    case BDIS_REF_GY: src = lv->gy; cnt = npx; break;
     default: return BDIS_REF_E_ARG;
   }
   if (!src || n < cnt) return BDIS_REF_E_ARG;

@@ -66,7 +66,10 @@ enum {
   BDIS_REF_VALID = 15,   /* level map: 1 where at least one patch contributed   */
   BDIS_REF_ODISP = 16,   /* finest level f > 0: disparity before upsampling     */
   BDIS_REF_OVAR = 17,    /* finest level f > 0: variance before upsampling      */
-  BDIS_REF_OCONF = 18    /* finest level f > 0: confidence before upsampling    */
+  BDIS_REF_OCONF = 18,   /* finest level f > 0: confidence before upsampling    */
+  BDIS_REF_FV = 19,      /* optical flow: per patch vertical displacement v     */
+  BDIS_REF_VBAR = 20,    /* optical flow: level map of the fused v (UBAR: u)    */
+  BDIS_REF_GY = 21       /* optical flow: y-gradient of the first frame (GRAD: x) */
 };
 enum { BDIS_REF_SIGMA_R2 = 0, BDIS_REF_TAU = 1, BDIS_REF_NACC = 2, BDIS_REF_GAMMA = 3 };
 
@@ -78,6 +81,14 @@ int bdis_ref_compute_u8(const bdis_ref_params* p, const uint8_t* left, const uin
 int bdis_ref_compute_f64(const bdis_ref_params* p, const double* left, const double* right,
                          int w, int h, int pitch, double* disparity, double* variance,
                          double* confidence, bdis_ref_trace** trace);
+
+/* 2-D dense inverse search (DIS optical flow, the base method BDIS extends):
+ * frames I0, I1 (uint8, integer pyramid), flow (u, v) with I1(x + u, y + v) ~
+ * I0(x, y); levels, patch, stride and iters from p (finest_level must be 0);
+ * per-patch 2-D inverse-compositional LK, fusion with the DIS weights of Eq. 2.
+ * Outputs: dense W x H doubles.  The trace keeps u (U, UBAR) and v (FV, VBAR). */
+int bdis_ref_flow(const bdis_ref_params* p, const uint8_t* i0, const uint8_t* i1, int w, int h, int pitch,
+                  double* flow_u, double* flow_v, bdis_ref_trace** trace);
 
 /* Level geometry: image size and patch-grid size; returns 0 or BDIS_REF_E_ARG. */
 int bdis_ref_trace_dims(const bdis_ref_trace* t, int level, int* w, int* h, int* nx, int* ny);

@@ -18,9 +18,10 @@ SOURCES = [os.path.join(HERE, "bdis_ref.c")]
 
 NWIN = 5
 WHAT = dict(left=0, right=1, grad=2, uinit=3, pipar=4, u=5, ssd=6, rho=7, acc=8, post=9,
-            pi=10, sigk2=11, hess=12, ubar=13, qmap=14, valid=15, odisp=16, ovar=17, oconf=18)
+            pi=10, sigk2=11, hess=12, ubar=13, qmap=14, valid=15, odisp=16, ovar=17, oconf=18,
+            fv=19, vbar=20, gy=21)
 SCALAR = dict(sigma_r2=0, tau=1, nacc=2, gamma=3)
-PER_PATCH = {"uinit", "pipar", "u", "ssd", "rho", "acc", "post", "pi", "sigk2", "hess"}
+PER_PATCH = {"uinit", "pipar", "u", "ssd", "rho", "acc", "post", "pi", "sigk2", "hess", "fv"}
 
 
 class RefParams(ctypes.Structure):
@@ -98,6 +99,8 @@ def lib():
                                     ctypes.POINTER(ctypes.c_int), ctypes.c_int]
         L.bdis_ref_mask.argtypes = [ctypes.c_int, ctypes.c_double, dp]
         L.bdis_ref_depth.argtypes = [dp, dp, ctypes.c_long, ctypes.c_double, dp, dp]
+        L.bdis_ref_flow.argtypes = [ctypes.POINTER(RefParams), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_void_p)]
         L.bdis_ref_coverage.argtypes = [dp, dp, dp, ctypes.c_void_p, ctypes.c_long, ctypes.c_double,
                                         ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]
         _lib = L
@@ -234,4 +237,25 @@ def coverage(disp, var, ref, k=1.96, valid=None):
     if st:
         raise OracleError(st)
     return c.value, t.value
+
+
+def flow(i0, i1, params, trace=False):
+    """2-D dense inverse search between two uint8 frames: dict(u, v[, trace]), H x W float64."""
+    i0 = np.ascontiguousarray(i0, dtype=np.uint8)
+    i1 = np.ascontiguousarray(i1, dtype=np.uint8)
+    if i0.shape != i1.shape or i0.ndim != 2:
+        raise ValueError("frames must be equal 2-D arrays")
+    h, w = i0.shape
+    u = np.empty((h, w), np.float64)
+    v = np.empty((h, w), np.float64)
+    handle = ctypes.c_void_p()
+    dp = ctypes.POINTER(ctypes.c_double)
+    st = lib().bdis_ref_flow(ctypes.byref(_to_struct(params)), i0.ctypes.data, i1.ctypes.data, w, h, w,
+                             u.ctypes.data_as(dp), v.ctypes.data_as(dp), ctypes.byref(handle) if trace else None)
+    if st:
+        raise OracleError(st)
+    out = dict(u=u, v=v)
+    if trace:
+        out["trace"] = Trace(handle.value, params["levels"])
+    return out
 

@@ -256,3 +256,32 @@ def make_pair(cfg, pair_idx=0, *, quantize=True):
         left = np.clip(left, 0.0, 255.0)
         right = np.clip(right, 0.0, 255.0)
     return left, right, gt.astype(np.float32), valid
+
+
+def make_flow_pair(idx=0, w=640, h=480, max_flow=12.0, noise=2.0):
+    """Two frames with a known smooth 2-D flow (optical-flow form of the search).
+
+    Recipe (draws from ``SeedSequence([2205, 3133, 99, idx])``): a 1/f texture
+    ``I1`` on an ``H x W`` canvas; a flow field ``(u, v)`` on the first frame's
+    grid made of six Gaussian bumps per component scaled to ``[-max_flow,
+    max_flow]``; ``I0(x, y) = I1(x + u, y + v)`` by bilinear interpolation with
+    edge clamping (so ``I1(x + u) = I0(x)`` holds exactly before noise);
+    Gaussian noise ``noise`` on both frames, round-half-even, clip to uint8.
+    Returns ``(I0, I1, u, v, valid)`` with ``valid`` where ``x + u`` stays in
+    the frame.
+    """
+    rng = np.random.default_rng(np.random.SeedSequence([2205, 3133, 99, int(idx)]))
+    i1 = _texture(rng, h, w)
+
+    def comp():
+        f = _bumps(rng, h, w, 6, -1.0, 1.0)
+        return f / max(np.abs(f).max(), 1e-12) * max_flow
+
+    u, v = comp(), comp()
+    yy, xx = np.mgrid[0:h, 0:w].astype(np.float64)
+    i0 = ndimage.map_coordinates(i1, [yy + v, xx + u], order=1, mode="nearest")
+    i0 = i0 + rng.standard_normal((h, w)) * noise
+    i1 = i1 + rng.standard_normal((h, w)) * noise
+    q = lambda a: np.clip(np.rint(a), 0, 255).astype(np.uint8)
+    valid = (xx + u >= 0) & (xx + u <= w - 1) & (yy + v >= 0) & (yy + v <= h - 1)
+    return q(i0), q(i1), u.astype(np.float32), v.astype(np.float32), valid

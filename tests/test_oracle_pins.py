@@ -749,3 +749,107 @@ def test_coverage_of_gaussian_errors(oracle):
     d2[10:20] = np.nan
     c, t = oracle.coverage(d2, var, ref, 1.96, valid)
     assert t == n - 20
+
+
+# --------------------------------------------------------------------------
+# Optical-flow form (2-D dense inverse search, the base method BDIS extends)
+# --------------------------------------------------------------------------
+
+def _flow_params(oracle, **kw):
+    base = dict(levels=3, patch=8, stride=4, iters=12)
+    base.update(kw)
+    return oracle.default_params(**base)
+
+
+@pytest.mark.parametrize("D", [(3, -2), (-5, 4), (0, 7)])
+def test_flow_exact_shift_recovered(oracle, D):
+    """I1(x + D) = I0(x) exactly: every interior pixel gets flow D to 1e-6."""
+    dx, dy = D
+    h, w = 96, 128
+    m = 12
+    canvas = np.rint(texture(31 + dx * 7 + dy, h + 2 * m, w + 2 * m)).astype(np.uint8)
+    i0 = np.ascontiguousarray(canvas[m:m + h, m:m + w])
+    i1 = np.ascontiguousarray(canvas[m - dy:m - dy + h, m - dx:m - dx + w])
+    r = oracle.flow(i0, i1, _flow_params(oracle))
+    inner = (slice(16, h - 16), slice(16, w - 16))
+    np.testing.assert_allclose(r["u"][inner], dx, atol=1e-6)
+    np.testing.assert_allclose(r["v"][inner], dy, atol=1e-6)
+
+
+def test_flow_sobel_y_matches_library(oracle):
+    from paper_2205_03133_amd.synth import make_flow_pair
+    i0, i1, _, _, _ = make_flow_pair(1, 80, 60)
+    t = oracle.flow(i0, i1, _flow_params(oracle, levels=2), trace=True)["trace"]
+    for n in range(2):
+        img = t.get(n, "left")
+        np.testing.assert_allclose(t.get(n, "gy"), ndimage.sobel(img, axis=0, mode="mirror") / 8.0, atol=1e-12)
+        np.testing.assert_allclose(t.get(n, "grad"), ndimage.sobel(img, axis=1, mode="mirror") / 8.0, atol=1e-12)
+
+
+def test_flow_transpose_equivariance(oracle):
+    """Transposing both frames transposes the flow and swaps its components (a
+    swapped x/y index or operand anywhere breaks it)."""
+    from paper_2205_03133_amd.synth import make_flow_pair
+    i0, i1, _, _, _ = make_flow_pair(2, 112, 96, 5.0)
+    p = _flow_params(oracle)
+    a = oracle.flow(i0, i1, p)
+    b = oracle.flow(np.ascontiguousarray(i0.T), np.ascontiguousarray(i1.T), p)
+    du = np.abs(a["u"] - b["v"].T)
+    dv = np.abs(a["v"] - b["u"].T)
+    assert (np.maximum(du, dv) <= 1e-9).mean() >= 0.999
+
+
+def test_flow_fusion_weights_from_library_interpolation(oracle):
+    """Single level: the fused flow is the Eq. 2 weighted mean of the covering
+    patches' flows, residuals taken with scipy's 2-D linear interpolation."""
+    from paper_2205_03133_amd.synth import make_flow_pair
+    i0, i1, _, _, _ = make_flow_pair(3, 72, 56, 3.0)
+    P, S = 8, 4
+    t = oracle.flow(i0, i1, _flow_params(oracle, levels=1, patch=P, stride=S), trace=True)["trace"]
+    u, v, ub, vb = t.get(0, "u"), t.get(0, "fv"), t.get(0, "ubar"), t.get(0, "vbar")
+    ox, oy = oracle.grid(72, P, S), oracle.grid(56, P, S)
+    I0, I1 = i0.astype(np.float64), i1.astype(np.float64)
+    yy, xx = np.mgrid[0:56, 0:72].astype(np.float64)
+    nu, nv, den = np.zeros((56, 72)), np.zeros((56, 72)), np.zeros((56, 72))
+    for j in range(len(oy)):
+        for i in range(len(ox)):
+            sl = (slice(oy[j], oy[j] + P), slice(ox[i], ox[i] + P))
+            wp = ndimage.map_coordinates(I1, [yy[sl] + v[j, i], xx[sl] + u[j, i]], order=1, mode="nearest")
+            wgt = 1.0 / np.maximum(1.0, (wp - I0[sl]) ** 2)
+            nu[sl] += wgt * u[j, i]
+            nv[sl] += wgt * v[j, i]
+            den[sl] += wgt
+    np.testing.assert_allclose(ub, nu / den, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(vb, nv / den, rtol=1e-12, atol=1e-12)
+
+
+def test_flow_matches_bruteforce_minimum_tiny(oracle):
+    """One level, start at 0, small shifts: the 2-D search lands on the minimum of
+    the mean-normalised SSD found by a 1/8-px brute-force sweep (0.25 px) for
+    most patches."""
+    from paper_2205_03133_amd.synth import make_flow_pair
+    i0, i1, _, _, _ = make_flow_pair(4, 48, 40, 1.2, noise=0.0)
+    P, S = 8, 8
+    t = oracle.flow(i0, i1, _flow_params(oracle, levels=1, patch=P, stride=S, iters=60), trace=True)["trace"]
+    u, v = t.get(0, "u"), t.get(0, "fv")
+    I0, I1 = i0.astype(np.float64), i1.astype(np.float64)
+    grid = np.arange(-2.0, 2.0 + 1e-9, 0.125)
+    ox, oy = oracle.grid(48, P, S), oracle.grid(40, P, S)
+    hits, tot = 0, 0
+    for j in range(len(oy)):
+        for i in range(len(ox)):
+            if not (1 <= i < len(ox) - 1 and 1 <= j < len(oy) - 1):
+                continue
+            yy, xx = np.mgrid[oy[j]:oy[j] + P, ox[i]:ox[i] + P].astype(np.float64)
+            T = I0[oy[j]:oy[j] + P, ox[i]:ox[i] + P]
+            best, arg = np.inf, None
+            for cv in grid:
+                for cu in grid:
+                    wp = ndimage.map_coordinates(I1, [yy + cv, xx + cu], order=1, mode="nearest")
+                    e = (wp - wp.mean()) - (T - T.mean())
+                    s = float((e * e).sum())
+                    if s < best:
+                        best, arg = s, (cu, cv)
+            tot += 1
+            hits += abs(u[j, i] - arg[0]) <= 0.25 and abs(v[j, i] - arg[1]) <= 0.25
+    assert tot >= 6 and hits / tot >= 0.6
