@@ -173,6 +173,19 @@ bdis_status bdis_backward(bdis_ctx* ctx, const float* grad_disparity, const floa
 bdis_status bdis_backward_batch(bdis_ctx* ctx, int n, const bdis_pair_grad* grads, double* grad_hyper,
                                 void* stream);
 
+/* Optical-flow form (f4): the 2-D dense inverse search that BDIS builds on
+ * (Eq. 1 with u a 2-vector) between two uint8 frames i0, i1 (device, row
+ * pitch `pitch`), with the context's levels, patch, stride and iterations:
+ * per patch an inverse-compositional update on the 2 x 2 Hessian of the
+ * Sobel-x / Sobel-y template gradients (bilinear warp, indices clamped; no
+ * update when det H < 1e-3; reset to the start after a step longer than P),
+ * per pixel the DIS fusion of Eq. 2.  Writes the flow (u, v), I1(x + u, y + v)
+ * ~ I0(x, y), as dense float W x H maps.  Needs float_pyramid 0 and
+ * finest_level 0; the probability, variance and ablation parameters are not
+ * used.  Errors: BDIS_E_ARG, BDIS_E_CAPACITY, BDIS_E_SIZE, BDIS_E_HIP. */
+bdis_status bdis_flow(bdis_ctx* ctx, const uint8_t* i0, const uint8_t* i1, int w, int h, int pitch, float* flow_u,
+                      float* flow_v, void* stream);
+
 /* Depth form (Eq. 14 and Eq. 18): for each pixel of a W x H disparity map (and
  * its variance), depth = fb / d and depth variance = (fb)^2 / d^4 * var, where
  * fb is focal length x baseline (depth comes out in the units of the

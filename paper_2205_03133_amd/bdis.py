@@ -100,6 +100,7 @@ def lib():
         L.bdis_timing_enable.argtypes = [vp, i32]
         L.bdis_timing_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long)]
         L.bdis_depth.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.c_float, vp, vp, vp]
+        L.bdis_flow.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp]
         L.bdis_coverage.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, vp, vp]
         for name in ("bdis_params_default", "bdis_params_check", "bdis_create", "bdis_set_params",
                      "bdis_compute", "bdis_compute_batch", "bdis_debug_dump", "bdis_level_dims",
@@ -266,6 +267,20 @@ class Context:
         if st:
             raise self._err(st)
         return results
+
+    def flow(self, i0, i1, stream=None):
+        """Optical flow (u, v) between two uint8 frames (2-D CUDA tensors, same shape)."""
+        import torch
+        p0, w, h, pitch = _image_arg(i0, "i0")
+        p1, w2, h2, pitch2 = _image_arg(i1, "i1")
+        if (w, h, pitch) != (w2, h2, pitch2):
+            raise ValueError("frames must have the same shape and row stride")
+        u = torch.empty((h, w), dtype=torch.float32, device=i0.device)
+        v = torch.empty((h, w), dtype=torch.float32, device=i0.device)
+        st = lib().bdis_flow(self._h, p0, p1, w, h, pitch, u.data_ptr(), v.data_ptr(), _stream_ptr(stream))
+        if st:
+            raise self._err(st)
+        return u, v
 
     def depth(self, disp, fb, var=None, stream=None):
         """Depth fb / d (and its variance (fb)^2 / d^4 var) of a disparity map

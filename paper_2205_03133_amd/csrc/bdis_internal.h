@@ -10,7 +10,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace bdis {
 
@@ -93,6 +96,9 @@ struct PairLevel {
   const float* fvar;
   const float* fconf;
   int fw, fh, fshift;
+  // optical-flow form, finest level: the flow outputs (dense w x h)
+  float* flow_u;
+  float* flow_v;
   // workgroup offsets of this pair in each flattened launch
   int pyr0, search0, prob0, fuse0, up0;
   int search_nbx;  // search workgroups per patch row
@@ -186,6 +192,8 @@ hipError_t launch_fuse(const PairLevel* tab, int npairs, int nblocks, const Leve
 hipError_t launch_upsample(const PairLevel* tab, int npairs, int nblocks, hipStream_t s);
 hipError_t launch_coverage(const float* disp, const float* var, const float* ref, const uint8_t* valid, int w,
                            int h, int pitch, double k, unsigned long long* counts, hipStream_t s);
+hipError_t launch_flow_search(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s);
+hipError_t launch_flow_fuse(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s);
 hipError_t launch_depth(const float* disp, const float* var, int w, int h, int pitch, float fb, float* depth,
                         float* dvar, hipStream_t s);
 
@@ -311,6 +319,37 @@ BDIS_DEV double bilinear(const double* m, int w, int h, double x, double y) {
   const double top = (1.0 - ax) * g[(size_t)y0 * w + x0] + ax * g[(size_t)y0 * w + x1];
   const double bot = (1.0 - ax) * g[(size_t)y1 * w + x0] + ax * g[(size_t)y1 * w + x1];
   return (1.0 - ay) * top + ay * bot;
+}
+
+// Covering patches along one axis: indices lo..hi (origin i*S), plus the last
+// patch (origin n-P) when it covers x but lies past hi.
+BDIS_DEV void cover_range(int x, int n, int P, int S, int cnt, int& lo, int& hi, int& extra) {
+  const int t = x - P;  // origin must exceed x - P
+  lo = t >= 0 ? t / S + 1 : 0;
+  hi = min(x / S, cnt - 1);
+  extra = (x >= n - P && cnt - 1 > hi) ? cnt - 1 : -1;
+}
+
+// Calls f(std::integral_constant<int, P>) for the runtime patch size.
+template <typename F>
+hipError_t by_patch(int P, F&& f) {
+  switch (P) {
+    case 3: return f(std::integral_constant<int, 3>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 5: return f(std::integral_constant<int, 5>{});
+    case 6: return f(std::integral_constant<int, 6>{});
+    case 7: return f(std::integral_constant<int, 7>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    case 9: return f(std::integral_constant<int, 9>{});
+    case 10: return f(std::integral_constant<int, 10>{});
+    case 11: return f(std::integral_constant<int, 11>{});
+    case 12: return f(std::integral_constant<int, 12>{});
+    case 13: return f(std::integral_constant<int, 13>{});
+    case 14: return f(std::integral_constant<int, 14>{});
+    case 15: return f(std::integral_constant<int, 15>{});
+    case 16: return f(std::integral_constant<int, 16>{});
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace bdis

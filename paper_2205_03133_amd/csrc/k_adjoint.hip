@@ -17,8 +17,6 @@
 //            J = g - mean g, H = sum J^2, g = Sobel_x(L) / 8, T = L on the patch
 //   window   SSD_d = sum (e - mean e)^2, e = I_w(u + d) - T
 //   pyramid  L_n = B5 * L_{n-1} (even samples, reflect-101)
-#include <type_traits>
-
 #include "bdis_internal.h"
 
 namespace bdis {
@@ -646,28 +644,6 @@ __global__ __launch_bounds__(kPixThreads) void k_grad_out(const PairLevel* tab, 
   const int y = idx / w, x = idx - y * w;
   if (a.grad_left) gbl(a.grad_left)[idx] = (float)gbl(a.Lbar)[(size_t)y * a.dpitch + x];
   if (a.grad_right) gbl(a.grad_right)[idx] = (float)gbl(a.Rbar)[(size_t)y * a.dpitch + x];
-}
-
-// Calls f(std::integral_constant<int, P>) for the runtime patch size.
-template <typename F>
-hipError_t by_patch(int P, F&& f) {
-  switch (P) {
-    case 3: return f(std::integral_constant<int, 3>{});
-    case 4: return f(std::integral_constant<int, 4>{});
-    case 5: return f(std::integral_constant<int, 5>{});
-    case 6: return f(std::integral_constant<int, 6>{});
-    case 7: return f(std::integral_constant<int, 7>{});
-    case 8: return f(std::integral_constant<int, 8>{});
-    case 9: return f(std::integral_constant<int, 9>{});
-    case 10: return f(std::integral_constant<int, 10>{});
-    case 11: return f(std::integral_constant<int, 11>{});
-    case 12: return f(std::integral_constant<int, 12>{});
-    case 13: return f(std::integral_constant<int, 13>{});
-    case 14: return f(std::integral_constant<int, 14>{});
-    case 15: return f(std::integral_constant<int, 15>{});
-    case 16: return f(std::integral_constant<int, 16>{});
-    default: return hipErrorInvalidValue;
-  }
 }
 
 hipError_t launch_search_adj(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {

@@ -68,15 +68,6 @@ __global__ __launch_bounds__(kProbThreads) void k_prob(const PairLevel* tab, int
   st4(a.pa.dens + k, D4{u, pi, sig, post});
 }
 
-// Covering patches along one axis: indices lo..hi (origin i*S), plus the last
-// patch (origin n-P) when it covers x but lies past hi.
-BDIS_DEV void cover_range(int x, int n, int P, int S, int cnt, int& lo, int& hi, int& extra) {
-  const int t = x - P;  // origin must exceed x - P
-  lo = t >= 0 ? t / S + 1 : 0;
-  hi = min(x / S, cnt - 1);
-  extra = (x >= n - P && cnt - 1 > hi) ? cnt - 1 : -1;
-}
-
 // Records staged per workgroup: the patches covering a 64 x 4 pixel tile
 // (about 26 x 6 for stride 3; tiles that cover more use direct loads).
 constexpr int kMaxRec = 512;

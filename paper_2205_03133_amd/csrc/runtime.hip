@@ -184,6 +184,9 @@ struct PairSpec {
   const float* grad_var = nullptr;
   float* grad_left = nullptr;
   float* grad_right = nullptr;
+  // optical-flow form
+  float* flow_u = nullptr;
+  float* flow_v = nullptr;
 };
 
 // Launch plan of one call: level-major job table and workgroup counts.
@@ -404,7 +407,8 @@ void assign_offsets(const bdis_params& p, Plan& pl) {
   }
 }
 
-bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* out, bool f32 = false) {
+bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* out, bool f32 = false,
+                       bool flow = false) {
   const bdis_params& p = c->p;
   Plan pl;
   pl.finest = p.finest_level;
@@ -485,6 +489,8 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
           e.disparity = q.disp;
           e.variance = q.var;
           e.confidence = q.conf;
+          e.flow_u = q.flow_u;
+          e.flow_v = q.flow_v;
         }
       }
       if (f32) {
@@ -545,8 +551,8 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
     pl.tab_count[n] = (int)pl.tab.size() - pl.tab_first[n];
   }
   for (int n = 0; n < pl.max_levels; ++n) {
-    if (f32 || n < p.finest_level || pl.tab_count[n] == 0) {
-      pl.threads[n] = f32 ? kSearchF64Threads : 256;
+    if (f32 || flow || n < p.finest_level || pl.tab_count[n] == 0) {
+      pl.threads[n] = (f32 || flow) ? kSearchF64Threads : 256;
       continue;
     }
     auto it = c->tuned.find(level_key(p, pl, n));
@@ -798,6 +804,36 @@ bdis_status run_pairs_f32(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipSt
     e = launch_upsample(c->tab_dev + pl.tab_first[0], pl.tab_count[0], pl.up_blocks, st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "upsampling launch");
+  }
+  return BDIS_OK;
+}
+
+// Optical-flow form: the same pyramid, then per level the 2-D search and the
+// Eq. 2 fusion (no probability, no reduction).
+bdis_status run_flow(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipStream_t st) {
+  Plan pl;
+  bdis_status s = build_plan(c, pairs, &pl, false, true);
+  if (s != BDIS_OK) return s;
+  if ((s = upload_table(c, pl, st)) != BDIS_OK) return s;
+  const bdis_params& p = c->p;
+  hipError_t e;
+  for (int n = 1; n < pl.max_levels; ++n) {
+    const long tmk = timing_start(c, BDIS_K_PYRAMID, st);
+    e = launch_pyramid(c->tab_dev + pl.tab_first[n], pl.tab_count[n], pl.pyr_blocks[n], st);
+    timing_stop(c, tmk, st);
+    if (e != hipSuccess) return hip_fail(c, e, "pyramid launch");
+  }
+  for (int n = pl.max_levels - 1; n >= 0; --n) {
+    const PairLevel* tab = c->tab_dev + pl.tab_first[n];
+    const LevelParams lp = level_params(p, n);
+    long tmk = timing_start(c, BDIS_K_SEARCH, st);
+    e = launch_flow_search(tab, pl.tab_count[n], pl.search_blocks[n], lp, st);
+    timing_stop(c, tmk, st);
+    if (e != hipSuccess) return hip_fail(c, e, "flow search launch");
+    tmk = timing_start(c, BDIS_K_FUSE, st);
+    e = launch_flow_fuse(tab, pl.tab_count[n], pl.fuse_blocks[n], lp, st);
+    timing_stop(c, tmk, st);
+    if (e != hipSuccess) return hip_fail(c, e, "flow fusion launch");
   }
   return BDIS_OK;
 }
@@ -1122,6 +1158,23 @@ bdis_status bdis_coverage(bdis_ctx* c, const float* disp, const float* var, cons
                                        reinterpret_cast<unsigned long long*>(counts),
                                        reinterpret_cast<hipStream_t>(stream));
   return e == hipSuccess ? BDIS_OK : hip_fail(c, e, "coverage launch");
+}
+
+bdis_status bdis_flow(bdis_ctx* c, const uint8_t* i0, const uint8_t* i1, int w, int h, int pitch, float* flow_u,
+                      float* flow_v, void* stream) {
+  if (!c) return BDIS_E_ARG;
+  if (!i0 || !i1 || !flow_u || !flow_v) return fail(c, BDIS_E_ARG, "frames and both flow outputs are required");
+  if (w < 1 || h < 1 || pitch < w) return fail(c, BDIS_E_ARG, "bad image size %dx%d pitch %d", w, h, pitch);
+  if (c->p.float_pyramid) return fail(c, BDIS_E_ARG, "uint8 frames need params.float_pyramid = 0");
+  if (c->p.finest_level != 0) return fail(c, BDIS_E_ARG, "the flow form needs finest_level 0");
+  if (w > c->max_w || h > c->max_h)
+    return fail(c, BDIS_E_CAPACITY, "image %dx%d exceeds the context's %dx%d", w, h, c->max_w, c->max_h);
+  c->have_last = false;
+  PairSpec ps{i0, i1, w, h, pitch, c->p.levels, nullptr, nullptr, nullptr};
+  ps.flow_u = flow_u;
+  ps.flow_v = flow_v;
+  std::vector<PairSpec> v{ps};
+  return run_flow(c, v, reinterpret_cast<hipStream_t>(stream));
 }
 
 bdis_status bdis_level_dims(const bdis_params* p, int w, int h, int level, int* lw, int* lh, int* nx, int* ny) {
