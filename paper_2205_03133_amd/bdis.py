@@ -280,6 +280,7 @@ class Context:
         st = lib().bdis_flow(self._h, p0, p1, w, h, pitch, u.data_ptr(), v.data_ptr(), _stream_ptr(stream))
         if st:
             raise self._err(st)
+        self._last_wh = (w, h)
         return u, v
 
     def depth(self, disp, fb, var=None, stream=None):

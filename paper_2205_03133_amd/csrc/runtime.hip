@@ -1174,7 +1174,13 @@ bdis_status bdis_flow(bdis_ctx* c, const uint8_t* i0, const uint8_t* i1, int w, 
   ps.flow_u = flow_u;
   ps.flow_v = flow_v;
   std::vector<PairSpec> v{ps};
-  return run_flow(c, v, reinterpret_cast<hipStream_t>(stream));
+  const bdis_status st = run_flow(c, v, reinterpret_cast<hipStream_t>(stream));
+  if (st == BDIS_OK) {  // per-patch flow stays readable through bdis_debug_dump (u: BDIS_DBG_U, v: BDIS_DBG_UINIT)
+    c->last_w = w;
+    c->last_h = h;
+    c->have_last = true;
+  }
+  return st;
 }
 
 bdis_status bdis_level_dims(const bdis_params* p, int w, int h, int level, int* lw, int* lh, int* nx, int* ny) {
