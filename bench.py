@@ -362,6 +362,36 @@ def bench_coverage(bdis, torch, args):
     return out
 
 
+def bench_flow(bdis, torch, args):
+    """Optical-flow form: one 640x480 pair of frames with a smooth 2-D flow up to
+    12 px (L=4 P=8 S=4 K=12), one call per step."""
+    import numpy as np
+    from paper_2205_03133_amd.synth import make_flow_pair
+    dev = torch.device("cuda:0")
+    i0, i1, gu, gv, valid = make_flow_pair(0, 640, 480, 12.0)
+    a, b = torch.from_numpy(i0).to(dev), torch.from_numpy(i1).to(dev)
+    ctx = bdis.Context(bdis.params(levels=4, patch=8, stride=4, iters=12), 640, 480)
+    for _ in range(args.warmup):
+        u, v = ctx.flow(a, b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        u, v = ctx.flow(a, b)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ctx.timing(True)
+    for _ in range(max(1, args.steps // 4)):
+        ctx.flow(a, b)
+    tk = ctx.timing_read()
+    ctx.timing(False)
+    epe = np.hypot(u.cpu().numpy() - gu, v.cpu().numpy() - gv)[valid]
+    ctx.close()
+    return dict(ms_per_pair=round(dt * 1e3, 4), mpx_s=round(640 * 480 / dt / 1e6, 2),
+                epe_median_px=round(float(np.median(epe)), 4), epe_mean_px=round(float(epe.mean()), 4),
+                kernels=kernel_table({k: tk[k] for k in ("pyramid", "search", "fuse")}),
+                config="640x480 frames, smooth 2-D flow up to 12 px, noise 2; L=4 P=8 S=4 K=12, Eq. 2 fusion")
+
+
 def bench_diff(bdis, torch, args):
     """Differentiable form: a batch of 16 float 640x480 pairs, forward and backward
     (K = 8 unrolled, 4 levels, P 8, S 4), and the plain uint8 form on the same pairs."""
@@ -472,6 +502,7 @@ def main():
         line["batch_1080p"] = bench_batch(bdis, torch, args)
         line["batch_mixed"] = bench_mixed(bdis, torch, args)
     line["paper_preset"] = bench_preset(bdis, torch, args)
+    line["optical_flow"] = bench_flow(bdis, torch, args)
     if args.ablation_pairs > 0:
         line["ablation"] = bench_ablation(bdis, torch, args)
         line["variance_coverage"] = bench_coverage(bdis, torch, args)
