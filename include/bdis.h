@@ -230,7 +230,8 @@ bdis_status bdis_debug_dump(bdis_ctx* ctx, int level, int what, void* host_dst, 
 
 /* Per-kernel timing with HIP events recorded on the compute stream around
  * every launch (for measurement; adds two event records per launch).
- * kernel: 0 pyramid, 1 patch search, 2 patch probability, 3 fusion,
+ * kernel: 0 pyramid, 1 patch search, 2 patch probability (launched for large
+ * levels only; small levels compute it inside the fusion), 3 fusion,
  * 4 the per-pair sigma_r reduction, 5 the backward pass (all its launches).
  * bdis_timing_enable(ctx, 1) clears the totals and starts recording;
  * bdis_timing_read synchronises the recorded events and returns the summed

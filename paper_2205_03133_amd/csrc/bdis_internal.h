@@ -160,11 +160,16 @@ struct LevelParams {
   float prob_thresh;
   int fusion;       // 0 Eq. 13, 1 Eq. 2 (DIS), 2 Eq. 13 with a uniform mask
   int propagate;    // 1: add the parent confidence (Eq. 11)
+  int inline_prob;  // 1: the fusion computes the patch records itself (small levels)
 };
 
 // Tile shapes of the flattened launches.
 constexpr int kPyrTx = 64, kPyrTy = 4;      // pyramid: 64 x 4 output pixels per workgroup
 constexpr int kProbThreads = 256;           // probability: patches per workgroup
+// Levels with at most this many patches (over the batch) have their patch
+// records computed inside the fusion (no separate launch); larger levels
+// compute each record once in a launch of their own.
+constexpr long kInlineProbPatches = 1 << 16;
 constexpr int kFuseTx = 64, kFuseTy = 4;    // fusion: 64 x 4 pixels per workgroup
 
 // Workgroups of the float-path search (fixed size) and of per-pixel adjoint launches.
@@ -185,8 +190,7 @@ hipError_t launch_pyramid(const PairLevel* tab, int npairs, int nblocks, hipStre
 hipError_t launch_search(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,
                          int threads, hipStream_t s);
 hipError_t launch_reduce(const PairLevel* tab, int npairs, const LevelParams& lp, hipStream_t s);
-hipError_t launch_prob(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,
-                       hipStream_t s);
+hipError_t launch_prob(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s);
 hipError_t launch_fuse(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,
                        hipStream_t s);
 hipError_t launch_upsample(const PairLevel* tab, int npairs, int nblocks, hipStream_t s);

@@ -1,6 +1,8 @@
 // Patch probability and fusion of the overlapping patches into the level maps.
 //
-// k_prob (one lane per patch; one launch covers a level of every pair): window posterior post = p0 / sum_d p_d with
+// Patch record (computed by the fusion workgroups for the patches covering
+// their tile; the tile holding a patch's origin stores it): window posterior
+// post = p0 / sum_d p_d with
 //   p_d = exp(-SSD_d / tau), tau = 2 sigma_r^2 s^2 (Eq. 5-6), in the stable
 //   form 1 / sum_d exp(-(SSD_d - SSD_0) / tau); the level's contribution
 //   Gamma_n * post plus the probability propagated from the parent level
@@ -21,17 +23,11 @@ namespace bdis {
 
 namespace {
 
-__global__ __launch_bounds__(kProbThreads) void k_prob(const PairLevel* tab, int npairs, LevelParams lp) {
-  const PairLevel& a = tab[find_pair<2>(tab, npairs, (int)blockIdx.x)];
-  const int k = ((int)blockIdx.x - a.prob0) * kProbThreads + (int)threadIdx.x;
-  if (k >= a.g.nx * a.g.ny) return;
+// The fusion record of patch k: (u, pi or -1 when rejected, sigma_k^2, post).
+BDIS_DEV D4 patch_record(const PairLevel& a, const LevelParams& lp, size_t k, double tau) {
   const double u = gbl(a.pa.u)[k];
   const double nan = __builtin_nan("");
-  if (!gbl(a.pa.acc)[k]) {
-    st4(a.pa.dens + k, D4{u, -1.0, nan, 0.0});
-    return;
-  }
-  const double tau = gbl(a.scal)[1];
+  if (!gbl(a.pa.acc)[k]) return D4{u, -1.0, nan, 0.0};
   const D4 d = ld4(a.pa.dssd + k);
   const double den = 1.0 + exp(-d.x / tau) + exp(-d.y / tau) + exp(-d.z / tau) + exp(-d.w / tau);
   const double post = 1.0 / den;
@@ -65,13 +61,25 @@ __global__ __launch_bounds__(kProbThreads) void k_prob(const PairLevel* tab, int
     }
     sig = v;
   }
-  st4(a.pa.dens + k, D4{u, pi, sig, post});
+  return D4{u, pi, sig, post};
+}
+
+// One lane per patch: the patch records of a level (used when the level is
+// large enough that computing them once beats recomputing them per tile).
+__global__ __launch_bounds__(kProbThreads) void k_prob(const PairLevel* tab, int npairs, LevelParams lp) {
+  const PairLevel& a = tab[find_pair<2>(tab, npairs, xcd_block())];
+  const int k = (xcd_block() - a.prob0) * kProbThreads + (int)threadIdx.x;
+  if (k >= a.g.nx * a.g.ny) return;
+  st4(a.pa.dens + k, patch_record(a, lp, (size_t)k, gbl(a.scal)[1]));
 }
 
 // Records staged per workgroup: the patches covering a 64 x 4 pixel tile
 // (about 26 x 6 for stride 3; tiles that cover more use direct loads).
 constexpr int kMaxRec = 512;
 
+// INLINE: the patch records are computed here (small levels) instead of read
+// from a preceding k_prob launch.
+template <bool INLINE>
 __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab, int npairs, LevelParams lp) {
   __shared__ double s_m[kMaxPatch];
   __shared__ double s_u[kMaxRec], s_w[kMaxRec], s_v[kMaxRec];
@@ -101,12 +109,22 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
   const int ni = ihi - ilo + 1 + (iex >= 0 ? 1 : 0);
   const int nj = jhi - jlo + 1 + (jex >= 0 ? 1 : 0);
   const bool staged = ni * nj <= kMaxRec;
+  const double tau = INLINE ? gbl(a.scal)[1] : 0.0;
   if (staged) {
     for (int r = tid; r < ni * nj; r += kFuseTx * kFuseTy) {
       const int rj = r / ni, ri = r - rj * ni;
       const int i = ilo + ri <= ihi ? ilo + ri : iex;
       const int j = jlo + rj <= jhi ? jlo + rj : jex;
-      const D4 d = ld4(a.pa.dens + (size_t)j * a.g.nx + i);
+      const size_t k = (size_t)j * a.g.nx + i;
+      D4 d;
+      if (INLINE) {
+        d = patch_record(a, lp, k, tau);
+        // the tile holding the patch origin keeps its record (backward pass, debug)
+        const int ox = grid_origin(i, a.g.w, P, S), oy = grid_origin(j, a.g.h, P, S);
+        if (ox >= x0 && ox <= x1 && oy >= y0 && oy <= y1) st4(a.pa.dens + k, d);
+      } else {
+        d = ld4(a.pa.dens + k);
+      }
       s_u[r] = d.x;
       s_w[r] = d.y;
       s_v[r] = d.z;
@@ -139,7 +157,14 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
         dw = s_w[r];
         dv = s_v[r];
       } else {
-        const D4 d = ld4(a.pa.dens + (size_t)j * a.g.nx + i);
+        const size_t k = (size_t)j * a.g.nx + i;
+        D4 d;
+        if (INLINE) {
+          d = patch_record(a, lp, k, tau);
+          if (x == grid_origin(i, a.g.w, P, S) && y == grid_origin(j, a.g.h, P, S)) st4(a.pa.dens + k, d);
+        } else {
+          d = ld4(a.pa.dens + k);
+        }
         du = d.x;
         dw = d.y;
         dv = d.z;
@@ -307,14 +332,17 @@ __global__ void k_zero2(unsigned long long* counts) {
 }  // namespace
 
 hipError_t launch_prob(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
-  if (nblocks <= 0) return hipSuccess;
+  if (nblocks <= 0 || lp.inline_prob) return hipSuccess;
   hipLaunchKernelGGL(k_prob, dim3(nblocks), dim3(kProbThreads), 0, s, tab, npairs, lp);
   return hipGetLastError();
 }
 
 hipError_t launch_fuse(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fuse, dim3(nblocks), dim3(kFuseTx * kFuseTy), 0, s, tab, npairs, lp);
+  if (lp.inline_prob)
+    hipLaunchKernelGGL(k_fuse<true>, dim3(nblocks), dim3(kFuseTx * kFuseTy), 0, s, tab, npairs, lp);
+  else
+    hipLaunchKernelGGL(k_fuse<false>, dim3(nblocks), dim3(kFuseTx * kFuseTy), 0, s, tab, npairs, lp);
   return hipGetLastError();
 }
 

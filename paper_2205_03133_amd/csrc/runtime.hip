@@ -199,6 +199,7 @@ struct Plan {
       fuse_blocks[kMaxLevels]{};
   int threads[kMaxLevels]{};     // search workgroup size per level
   int up_blocks = 0;             // finest level f > 0: upsampling workgroups (level 0)
+  int inline_prob[kMaxLevels]{}; // 1: the fusion computes the patch records (small levels)
   bool f32 = false;              // float (FP64) path: per-pixel pyramid blocks, fixed search size
   std::vector<PairLevel> tab;
 };
@@ -558,6 +559,11 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
     auto it = c->tuned.find(level_key(p, pl, n));
     pl.threads[n] = it != c->tuned.end() ? it->second : default_threads(pl, n, p.patch);
   }
+  for (int n = 0; n < pl.max_levels; ++n) {
+    long np = 0;
+    for (int e = 0; e < pl.tab_count[n]; ++e) np += (long)pl.tab[pl.tab_first[n] + e].g.nx * pl.tab[pl.tab_first[n] + e].g.ny;
+    pl.inline_prob[n] = np <= kInlineProbPatches ? 1 : 0;
+  }
   assign_offsets(p, pl);
   *out = std::move(pl);
   return BDIS_OK;
@@ -614,7 +620,8 @@ bdis_status launch_all(bdis_ctx* c, const Plan& pl, hipStream_t st) {
   for (int n = pl.max_levels - 1; n >= p.finest_level; --n) {
     const PairLevel* tab = c->tab_dev + pl.tab_first[n];
     const int cnt = pl.tab_count[n];
-    const LevelParams lp = level_params(p, n);
+    LevelParams lp = level_params(p, n);
+    lp.inline_prob = pl.inline_prob[n];
     long tmk = timing_start(c, BDIS_K_SEARCH, st);
     e = launch_search(tab, cnt, pl.search_blocks[n], lp, pl.threads[n], st);
     timing_stop(c, tmk, st);
@@ -653,6 +660,7 @@ std::string graph_key(const bdis_params& p, const Plan& pl) {
   add(pl.fuse_blocks, sizeof pl.fuse_blocks);
   add(pl.threads, sizeof pl.threads);
   add(&pl.up_blocks, sizeof pl.up_blocks);
+  add(pl.inline_prob, sizeof pl.inline_prob);
   add(&pl.max_levels, sizeof pl.max_levels);
   return k;
 }
@@ -720,7 +728,8 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
           e = launch_pyramid(c->tab_dev + trial.tab_first[n], trial.tab_count[n], trial.pyr_blocks[n], st);
         for (int n = trial.max_levels - 1; n >= p.finest_level && e == hipSuccess; --n) {
           const PairLevel* tab = c->tab_dev + trial.tab_first[n];
-          const LevelParams lp = level_params(p, n);
+          LevelParams lp = level_params(p, n);
+          lp.inline_prob = trial.inline_prob[n];
           (void)hipEventRecord(ev[2 * n], st);
           e = launch_search(tab, trial.tab_count[n], trial.search_blocks[n], lp, trial.threads[n], st);
           (void)hipEventRecord(ev[2 * n + 1], st);
@@ -781,7 +790,8 @@ bdis_status run_pairs_f32(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipSt
   for (int n = pl.max_levels - 1; n >= p.finest_level; --n) {
     const PairLevel* tab = c->tab_dev + pl.tab_first[n];
     const int cnt = pl.tab_count[n];
-    const LevelParams lp = level_params(p, n);
+    LevelParams lp = level_params(p, n);
+    lp.inline_prob = pl.inline_prob[n];
     long tmk = timing_start(c, BDIS_K_SEARCH, st);
     e = launch_search_f64(tab, cnt, pl.search_blocks[n], lp, st);
     timing_stop(c, tmk, st);
