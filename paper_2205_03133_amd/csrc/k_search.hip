@@ -22,7 +22,9 @@
 // that stay in the same unit cell cost a few scalar flops.  The window SSD of a
 // unit cell is an exact quadratic in the fraction f:
 //   SSD = [X0 + 2 f X1 + f^2 X2] / N with integer X0, X1, X2 (see below).
-// Only the final combinations are rounded (in double).
+// Only the final combinations are rounded (in double).  Every product of two
+// image-derived integers has factors within 24 bits (samples 0..255, Sobel sums
+// within +-1020), so they use the full-rate 24-bit multiply.
 #include "bdis_internal.h"
 
 #include <climits>
@@ -30,6 +32,9 @@
 namespace bdis {
 
 namespace {
+
+// Exact product of two integers known to lie within +-2^23.
+BDIS_DEV int mul24(int a, int b) { return __mul24(a, b); }
 
 // Reads N consecutive right-image samples of one row starting at column x:
 // from the LDS window when it covers them, else from global memory with the
@@ -168,8 +173,8 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
   for (int c = 0; c < P; ++c) {
     sG += Gx[c];
     sT += T[c];
-    sGG += Gx[c] * Gx[c];
-    sGT += Gx[c] * T[c];
+    sGG += mul24(Gx[c], Gx[c]);
+    sGT += mul24(Gx[c], T[c]);
   }
   if (!row_live) sG = sT = sGG = sGT = 0;
   sG = group_sum<G>(sG);
@@ -196,14 +201,14 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
       if (m != mc) {
         int Rv[P + 1];
         fetch_row<P + 1>(Rv, win, xs, rw, grow, ox + m, W);
-        int cg0 = 0, cs0 = 0, cg1 = 0, cs1 = 0;
+        int cg0 = 0, cs0 = 0, cg1 = 0;
 #pragma unroll
         for (int c = 0; c < P; ++c) {
-          cg0 += Gx[c] * Rv[c];
+          cg0 += mul24(Gx[c], Rv[c]);
           cs0 += Rv[c];
-          cg1 += Gx[c] * Rv[c + 1];
-          cs1 += Rv[c + 1];
+          cg1 += mul24(Gx[c], Rv[c + 1]);
         }
+        int cs1 = cs0 + Rv[P] - Rv[0];
         if (!row_live) cg0 = cs0 = cg1 = cs1 = 0;
         cg0 = group_sum<G>(cg0);
         cs0 = group_sum<G>(cs0);
@@ -228,29 +233,33 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
   const double f = u - fm;
   double X0[3], X1[3], X2[3];
   {
-    int Rv[P + 3];
+    int Rv[P + 3], D[P + 2];
     fetch_row<P + 3>(Rv, win, xs, rw, grow, ox + m - 1, W);
 #pragma unroll
+    for (int c = 0; c < P + 2; ++c) D[c] = Rv[c + 1] - Rv[c];
+    int sa = 0;
+#pragma unroll
+    for (int c = 0; c < P; ++c) sa += Rv[c] - T[c];
+#pragma unroll
     for (int cq = 0; cq < 3; ++cq) {
-      int sa = 0, saa = 0, sd = 0, sdd = 0, sad = 0;
+      // sum of d telescopes; sum of a slides by one sample per cell
+      if (cq > 0) sa += Rv[cq + P - 1] - Rv[cq - 1];
+      int sd = Rv[cq + P] - Rv[cq];
+      int saa = 0, sdd = 0, sad = 0;
 #pragma unroll
       for (int c = 0; c < P; ++c) {
         const int av = Rv[c + cq] - T[c];
-        const int dv = Rv[c + cq + 1] - Rv[c + cq];
-        sa += av;
-        saa += av * av;
-        sd += dv;
-        sdd += dv * dv;
-        sad += av * dv;
+        saa += mul24(av, av);
+        sdd += mul24(D[c + cq], D[c + cq]);
+        sad += mul24(av, D[c + cq]);
       }
-      if (!row_live) sa = saa = sd = sdd = sad = 0;
-      sa = group_sum<G>(sa);
-      saa = group_sum<G>(saa);
-      sd = group_sum<G>(sd);
-      sdd = group_sum<G>(sdd);
-      sad = group_sum<G>(sad);
-      X0[cq] = (double)((long long)N * saa - (long long)sa * sa);
-      X1[cq] = (double)((long long)N * sad - (long long)sa * sd);
+      const int ga = group_sum<G>(row_live ? sa : 0);
+      saa = group_sum<G>(row_live ? saa : 0);
+      sd = group_sum<G>(row_live ? sd : 0);
+      sdd = group_sum<G>(row_live ? sdd : 0);
+      sad = group_sum<G>(row_live ? sad : 0);
+      X0[cq] = (double)((long long)N * saa - (long long)ga * ga);
+      X1[cq] = (double)((long long)N * sad - (long long)ga * sd);
       X2[cq] = (double)((long long)N * sdd - (long long)sd * sd);
     }
   }
@@ -266,12 +275,19 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
     smh = ssd(0, f + 0.5);
     sph = ssd(1, f + 0.5);
   }
-  int inb = 0;
-#pragma unroll
-  for (int c = 0; c < P; ++c) {
-    const double xr = (double)(ox + c) + u;
-    inb += (xr >= 0.0 && xr <= (double)(W - 1)) ? 1 : 0;
-  }
+  // in-bounds count of the columns c = 0..P-1 with (ox + c) + u in [0, W-1]:
+  // the rounded sample position is monotone in c, so the count is the length
+  // of an interval whose ends are found by testing the same rounded predicate
+  // around the real-valued boundaries.
+  auto inside_lo = [&](int c) { return (double)(ox + c) + u >= 0.0; };
+  auto inside_hi = [&](int c) { return (double)(ox + c) + u <= (double)(W - 1); };
+  int clo = (int)fmin(fmax(ceil(-(double)ox - u), 0.0), (double)P);
+  while (clo > 0 && inside_lo(clo - 1)) --clo;
+  while (clo < P && !inside_lo(clo)) ++clo;
+  int chi = (int)fmin(fmax(floor((double)(W - 1 - ox) - u), -1.0), (double)(P - 1));
+  while (chi < P - 1 && inside_hi(chi + 1)) ++chi;
+  while (chi >= 0 && !inside_hi(chi)) --chi;
+  const int inb = chi >= clo ? chi - clo + 1 : 0;
   const double rho = (double)(inb * P) / (double)N;
   const bool acc = s0 <= sm1 && s0 <= smh && s0 <= sph && s0 <= sp1 && rho >= (double)lp.valid_ratio;
 
