@@ -160,15 +160,16 @@ struct LevelParams {
   float prob_thresh;
   int fusion;       // 0 Eq. 13, 1 Eq. 2 (DIS), 2 Eq. 13 with a uniform mask
   int propagate;    // 1: add the parent confidence (Eq. 11)
-  int inline_prob;  // 1: the fusion computes the patch records itself (small levels)
+  int inline_prob;  // 1: the fusion computes the level scalars and patch records itself (small levels)
 };
 
 // Tile shapes of the flattened launches.
 constexpr int kPyrTx = 64, kPyrTy = 4;      // pyramid: 64 x 4 output pixels per workgroup
 constexpr int kProbThreads = 256;           // probability: patches per workgroup
-// Levels with at most this many patches (over the batch) have their patch
-// records computed inside the fusion (no separate launch); larger levels
-// compute each record once in a launch of their own.
+// Levels with at most this many patches (over the batch) have their level
+// scalars (sigma_r, tau) and patch records computed inside the fusion (no
+// reduction or probability launch); larger levels compute each once in
+// launches of their own.
 constexpr long kInlineProbPatches = 1 << 16;
 constexpr int kFuseTx = 64, kFuseTy = 4;    // fusion: 64 x 4 pixels per workgroup
 
@@ -323,6 +324,45 @@ BDIS_DEV double bilinear(const double* m, int w, int h, double x, double y) {
   const double top = (1.0 - ax) * g[(size_t)y0 * w + x0] + ax * g[(size_t)y0 * w + x1];
   const double bot = (1.0 - ax) * g[(size_t)y1 * w + x0] + ax * g[(size_t)y1 * w + x1];
   return (1.0 - ay) * top + ay * bot;
+}
+
+// sigma_r^(n) of one pair (a workgroup of 256 threads), read from Sec. III-B
+// as the pooled per-pixel variance of the mean-normalised residual over the
+// accepted patches of the level, scaled by alpha_r^2 and floored; or the fixed
+// sigma_r.  tau = 2 sigma_r^2 s^2 (Eq. 6).  The search partials are summed in
+// a fixed order (strided per thread, then a fixed tree), so every workgroup
+// that calls this for a pair gets the same bits.  out: sigma_r^2, tau, pooled
+// residual, accepted count.  Every thread returns the values.
+BDIS_DEV void pair_scalars(const PairLevel& a, const LevelParams& lp, double* s_red, long long* s_redc,
+                           double out[4]) {
+  const int tid = threadIdx.x;
+  const int nblocks = a.search_nbx * a.g.ny;
+  double ps = 0.0;
+  long long pc = 0;
+  for (int b = tid; b < nblocks; b += 256) {
+    ps += gbl(a.part_sum)[b];
+    pc += gbl(a.part_cnt)[b];
+  }
+  s_red[tid] = ps;
+  s_redc[tid] = pc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) {
+      s_red[tid] += s_red[tid + off];
+      s_redc[tid] += s_redc[tid + off];
+    }
+    __syncthreads();
+  }
+  const double sum = s_red[0];
+  const long long cnt = s_redc[0];
+  __syncthreads();  // the buffers may be reused by the caller
+  const double alpha2 = (double)lp.sigma_r * (double)lp.sigma_r;
+  const double pooled = cnt > 0 ? sum / ((double)cnt * (double)(lp.P * lp.P)) : 0.0;
+  const double sr2 = lp.sigma_r_dynamic ? alpha2 * (pooled > kEpsSigma ? pooled : kEpsSigma) : alpha2;
+  out[0] = sr2;
+  out[1] = 2.0 * sr2 * (double)(kWin * kWin);
+  out[2] = pooled;
+  out[3] = (double)cnt;
 }
 
 // Covering patches along one axis: indices lo..hi (origin i*S), plus the last

@@ -109,7 +109,15 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
   const int ni = ihi - ilo + 1 + (iex >= 0 ? 1 : 0);
   const int nj = jhi - jlo + 1 + (jex >= 0 ? 1 : 0);
   const bool staged = ni * nj <= kMaxRec;
-  const double tau = INLINE ? gbl(a.scal)[1] : 0.0;
+  double tau = 0.0;
+  if (INLINE) {
+    __shared__ double s_red[256];
+    __shared__ long long s_redc[256];
+    double sc[4];
+    pair_scalars(a, lp, s_red, s_redc, sc);
+    tau = sc[1];
+    if (t == 0 && tid < 4) gbl(a.scal)[tid] = sc[tid];  // kept for the backward pass and debug
+  }
   if (staged) {
     for (int r = tid; r < ni * nj; r += kFuseTx * kFuseTy) {
       const int rj = r / ni, ri = r - rj * ni;

@@ -322,46 +322,16 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
   }
 }
 
-// sigma_r^(n) of each pair (one workgroup per pair), read from Sec. III-B as
-// the pooled per-pixel variance of the mean-normalised residual over the
-// accepted patches of the level, scaled by alpha_r^2 and floored; or the fixed
-// sigma_r.  tau = 2 sigma_r^2 s^2 (Eq. 6).  Fixed-order FP64 sums.
+// One workgroup per pair: the level scalars (sigma_r^2, tau, pooled residual,
+// accepted count) from the search partials.
 __global__ __launch_bounds__(256) void k_reduce(const PairLevel* tab, LevelParams lp) {
   __shared__ double s_red[256];
   __shared__ long long s_redc[256];
   const PairLevel& a = tab[blockIdx.x];
-  const int tid = threadIdx.x;
-  const int nblocks = a.search_nbx * a.g.ny;
-  double ps = 0.0;
-  long long pc = 0;
-  for (int b = tid; b < nblocks; b += 256) {
-    ps += gbl(a.part_sum)[b];
-    pc += gbl(a.part_cnt)[b];
-  }
-  s_red[tid] = ps;
-  s_redc[tid] = pc;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (tid < off) {
-      s_red[tid] += s_red[tid + off];
-      s_redc[tid] += s_redc[tid + off];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    double sr2;
-    const double alpha2 = (double)lp.sigma_r * (double)lp.sigma_r;
-    if (lp.sigma_r_dynamic) {
-      const double pooled = s_redc[0] > 0 ? s_red[0] / ((double)s_redc[0] * (double)(lp.P * lp.P)) : 0.0;
-      sr2 = alpha2 * (pooled > kEpsSigma ? pooled : kEpsSigma);
-    } else {
-      sr2 = alpha2;
-    }
-    gbl(a.scal)[0] = sr2;
-    gbl(a.scal)[1] = 2.0 * sr2 * (double)(kWin * kWin);
-    gbl(a.scal)[2] = s_redc[0] > 0 ? s_red[0] / ((double)s_redc[0] * (double)(lp.P * lp.P)) : 0.0;
-    gbl(a.scal)[3] = (double)s_redc[0];
-  }
+  double sc[4];
+  pair_scalars(a, lp, s_red, s_redc, sc);
+  if (threadIdx.x == 0)
+    for (int t = 0; t < 4; ++t) gbl(a.scal)[t] = sc[t];
 }
 
 template <int P>
@@ -381,7 +351,7 @@ hipError_t launch_p(const PairLevel* tab, int npairs, int nblocks, const LevelPa
 }  // namespace
 
 hipError_t launch_reduce(const PairLevel* tab, int npairs, const LevelParams& lp, hipStream_t s) {
-  if (npairs <= 0) return hipSuccess;
+  if (npairs <= 0 || lp.inline_prob) return hipSuccess;
   hipLaunchKernelGGL(k_reduce, dim3(npairs), dim3(256), 0, s, tab, lp);
   return hipGetLastError();
 }
