@@ -17,6 +17,8 @@
 // (vertical); the fused level maps in ubar (horizontal) and qmap (vertical).
 #include "bdis_internal.h"
 
+#include <climits>
+
 namespace bdis {
 
 namespace {
@@ -93,11 +95,33 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_flow_search(const PairLev
   }
   double u = u0, v = v0;
   if (det >= kEpsH) {
+    // The warped row of this lane reads I1 rows y + n, y + n + 1 at columns
+    // ox + m + c (c = 0..P), (m, n) = floor(u, v), all with the same bilinear
+    // fractions; the 2 (P + 1) samples are kept while (m, n) stays the same.
+    const auto I1 = gbl(a.R);
+    double S0[P + 1], S1[P + 1];
+    int mc = INT_MIN, nc = INT_MIN;
     for (int t = 0; t < lp.K; ++t) {
+      const double fu = floor(u), fv = floor(v);
+      const int m = (int)fu, n = (int)fv;
+      const double ax = u - fu, ay = v - fv;
+      if (m != mc || n != nc) {
+        const size_t r0 = (size_t)clampi(y + n, 0, Hh - 1) * pitch, r1 = (size_t)clampi(y + n + 1, 0, Hh - 1) * pitch;
+#pragma unroll
+        for (int c = 0; c <= P; ++c) {
+          const int xc = clampi(ox + m + c, 0, W - 1);
+          S0[c] = (double)I1[r0 + xc];
+          S1[c] = (double)I1[r1 + xc];
+        }
+        mc = m;
+        nc = n;
+      }
       double bx = 0.0, by = 0.0;
 #pragma unroll
       for (int c = 0; c < P; ++c) {
-        const double e = bilinear_u8(a.R, pitch, W, Hh, (double)(ox + c) + u, (double)y + v) - T[c];
+        const double top = (1.0 - ax) * S0[c] + ax * S0[c + 1];
+        const double bot = (1.0 - ax) * S1[c] + ax * S1[c + 1];
+        const double e = (1.0 - ay) * top + ay * bot - T[c];
         bx += gx[c] * e;
         by += gy[c] * e;
       }
