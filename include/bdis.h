@@ -8,7 +8,13 @@
  * per patch (Eq. 5-6), and probability-weighted fusion of the overlapping
  * patches through a spatial Gaussian mixture (Eq. 9-13), with the fused map
  * initialising the next finer level.  An optional per-pixel variance follows
- * Eq. 15-18 (disparity form, without the depth Jacobian).
+ * Eq. 15-18 (disparity form, without the depth Jacobian).  Also exported: a
+ * float form with reverse-mode gradients (bdis_compute_f32, bdis_backward),
+ * batches of pairs of mixed sizes in one call, the paper's preset that stops
+ * at a coarser level and upsamples (finest_level), the depth form of Eq. 14
+ * and 18 (bdis_depth), the ablation weightings of Sec. V (fusion,
+ * propagate), the variance coverage check (bdis_coverage) and the 2-D
+ * optical-flow form of the underlying dense inverse search (bdis_flow).
  *
  * Conventions shared by every entry point:
  *  - Image and output pointers are DEVICE pointers (HBM of the current HIP

@@ -2,7 +2,8 @@
 // (Eq. 1 with the inverse roles of Sec. III-A; window of Eq. 5-6 with offsets
 // -1, -1/2, 0, +1/2, +1 of Sec. IV-A; saddle / in-bounds rejection of
 // Sec. III-B and III-F), plus the per-pair reduction that sets sigma_r^(n)
-// (Sec. III-B): workgroups write partial sums, k_reduce adds them in order.
+// (Sec. III-B): workgroups write partial sums, which k_reduce (large levels)
+// or every fusion workgroup of the level (small levels) adds in a fixed order.
 //
 // Mapping: one lane per patch row, an aligned group of G = 8 or 16 lanes per
 // patch (a DPP quad/half-row/row, so group reductions are 3-4 DPP adds),
