@@ -84,3 +84,12 @@ def test_product_path_has_no_fallback():
                             "paper_2205_03133_amd", "bdis.py")).read()
     assert "oracle" not in src
     assert "raise RuntimeError" in src
+
+
+def test_smoke_parameters_are_valid(B):
+    """The smoke pass's parameters build on both sides (library and oracle)."""
+    import __graft_entry__ as ge
+    from oracle import ref
+    kw = ge.smoke_params()
+    assert B.check(B.params(**kw)) == B.OK
+    assert ref.default_params(**kw)["variance"] == 1
