@@ -375,38 +375,51 @@ BDIS_DEV void patch_adj(const PairLevel& a, const LevelParams& lp, int k, int r,
     }
   };
 
-  // ---- window: SSD_d = sum (e - mean e)^2 at u + d
+  // ---- window: SSD_d = sum (e - mean e)^2 at u + d.  The five offsets fall in
+  // the cells m0 - 1, m0, m0 + 1 (m0 = floor u), whose samples are read once.
   const double u = gbl(a.pa.u)[k];
   double ub = gbl(a.pu_adj)[k];
   const auto sa = gbl(a.pssd_adj) + (size_t)k * kWin;
+  const int m0 = (int)floor(u);
+  double Rw[P + 3];
+#pragma unroll
+  for (int c = 0; c < P + 3; ++c) Rw[c] = Rrow[clampi(ox + m0 - 1 + c, 0, W - 1)];
+  // one window sample at cell m0 - 1 + O, fraction f
+  auto window_term = [&](auto oc, double f, double sbar) {
+    constexpr int O = decltype(oc)::value;
+    double ev[P], se = 0.0;
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      ev[c] = (1.0 - f) * Rw[O + c] + f * Rw[O + c + 1] - T[c];
+      se += ev[c];
+    }
+    const double emean = group_sum_d<G>(row_live ? se : 0.0) / (double)N;
+    double urow = 0.0;
+    to_cell(m0 - 1 + O);
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      const double g2 = 2.0 * (ev[c] - emean) * sbar;
+      urow += g2 * (Rw[O + c + 1] - Rw[O + c]);
+      Tb[c] -= g2;
+      acc[c] += g2 * (1.0 - f);
+      acc[c + 1] += g2 * f;
+    }
+    ub += group_sum_d<G>(row_live ? urow : 0.0);
+  };
   for (int t = 0; t < kWin; ++t) {
     double sbar = sa[t];
     if (t == 2) sbar += gbl(a.scal)[5];  // share of d loss / d tau through sigma_r
     if (sbar == 0.0) continue;
     const double v = u + 0.5 * (double)(t - 2);  // offsets -1, -1/2, 0, 1/2, 1
     const double fm = floor(v);
-    const int m = (int)fm;
+    const int o = (int)fm - (m0 - 1);  // 0, 1 or 2
     const double f = v - fm;
-    double ev[P], se = 0.0;
-#pragma unroll
-    for (int c = 0; c < P; ++c) {
-      const double ra = Rrow[clampi(ox + c + m, 0, W - 1)], rb = Rrow[clampi(ox + c + m + 1, 0, W - 1)];
-      ev[c] = (1.0 - f) * ra + f * rb - T[c];
-      se += ev[c];
-    }
-    const double emean = group_sum_d<G>(row_live ? se : 0.0) / (double)N;
-    double urow = 0.0;
-    to_cell(m);
-#pragma unroll
-    for (int c = 0; c < P; ++c) {
-      const int xa = clampi(ox + c + m, 0, W - 1), xb = clampi(ox + c + m + 1, 0, W - 1);
-      const double g2 = 2.0 * (ev[c] - emean) * sbar;
-      urow += g2 * (Rrow[xb] - Rrow[xa]);
-      Tb[c] -= g2;
-      acc[c] += g2 * (1.0 - f);
-      acc[c + 1] += g2 * f;
-    }
-    ub += group_sum_d<G>(row_live ? urow : 0.0);
+    if (o == 0)
+      window_term(std::integral_constant<int, 0>{}, f, sbar);
+    else if (o == 1)
+      window_term(std::integral_constant<int, 1>{}, f, sbar);
+    else
+      window_term(std::integral_constant<int, 2>{}, f, sbar);
   }
 
   // ---- reset, then the K iterations in reverse.  Within one unit cell m the
