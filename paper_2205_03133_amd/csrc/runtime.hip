@@ -234,6 +234,9 @@ struct bdis_ctx {
   std::vector<PairLevel> tab_last;
   hipEvent_t tab_evt = nullptr;   // completion of the last upload
   bool tab_evt_live = false;
+  hipEvent_t done_evt = nullptr;  // end of the last call's work (orders calls on other streams)
+  hipStream_t done_stream = nullptr;
+  bool done_live = false;
   hipStream_t capture_stream = nullptr;
   std::map<std::string, GraphEntry> graphs;
   std::map<std::string, int> tuned;  // level shape key -> search workgroup threads
@@ -762,6 +765,32 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
   return BDIS_OK;
 }
 
+// Every call reuses the context's workspace and job table, so the work of a
+// call must not start before the previous call's work ends.  On the same
+// stream that holds by stream order; on another stream the new stream waits
+// for the event recorded at the end of the previous call (no host wait).
+bdis_status order_after_last(bdis_ctx* c, hipStream_t st) {
+  if (!c->done_live || c->done_stream == st) return BDIS_OK;
+  const hipError_t e = hipStreamWaitEvent(st, c->done_evt, 0);
+  return e == hipSuccess ? BDIS_OK : hip_fail(c, e, "ordering after the previous call");
+}
+
+bdis_status mark_done(bdis_ctx* c, hipStream_t st, bdis_status s) {
+  if (s != BDIS_OK) return s;
+  const hipError_t e = hipEventRecord(c->done_evt, st);
+  if (e != hipSuccess) return hip_fail(c, e, "call completion event");
+  c->done_stream = st;
+  c->done_live = true;
+  return BDIS_OK;
+}
+
+template <typename F>
+bdis_status ordered(bdis_ctx* c, hipStream_t st, F&& run) {
+  const bdis_status s = order_after_last(c, st);
+  if (s != BDIS_OK) return s;
+  return mark_done(c, st, run(st));
+}
+
 bdis_status run_pairs(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipStream_t st) {
   Plan pl;
   bdis_status s = build_plan(c, pairs, &pl);
@@ -965,12 +994,14 @@ bdis_status bdis_create(bdis_ctx** out, const bdis_params* p, int max_w, int max
   // zero the workspace once (every array is rewritten before it is read)
   e = hipMemset(c->ws, 0, c->slot_bytes * (size_t)max_batch);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->tab_evt, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->done_evt, hipEventDisableTiming);
   if (e == hipSuccess && train) e = hipMalloc(reinterpret_cast<void**>(&c->hyper_dev), sizeof(double) * (2 + kMaxLevels));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->tab_evt) (void)hipEventDestroy(c->tab_evt);
+    if (c->done_evt) (void)hipEventDestroy(c->done_evt);
     if (c->hyper_dev) (void)hipFree(c->hyper_dev);
     (void)hipFree(c->ws);
     delete c;
@@ -1005,7 +1036,7 @@ bdis_status bdis_compute(bdis_ctx* c, const uint8_t* left, const uint8_t* right,
     return fail(c, BDIS_E_CAPACITY, "image %dx%d exceeds the context's %dx%d", w, h, c->max_w, c->max_h);
   c->have_last = false;
   std::vector<PairSpec> v{PairSpec{left, right, w, h, pitch, c->p.levels, disp, var, conf}};
-  bdis_status st = run_pairs(c, v, reinterpret_cast<hipStream_t>(stream));
+  bdis_status st = ordered(c, reinterpret_cast<hipStream_t>(stream), [&](hipStream_t ss) { return run_pairs(c, v, ss); });
   if (st == BDIS_OK) {
     c->last_w = w;
     c->last_h = h;
@@ -1035,7 +1066,7 @@ bdis_status bdis_compute_batch(bdis_ctx* c, int n, const bdis_pair* pairs, void*
   if (c->p.float_pyramid) return fail(c, BDIS_E_ARG, "uint8 input needs params.float_pyramid = 0");
   c->have_last = false;
   if (n == 0) return BDIS_OK;
-  return run_pairs(c, v, reinterpret_cast<hipStream_t>(stream));
+  return ordered(c, reinterpret_cast<hipStream_t>(stream), [&](hipStream_t ss) { return run_pairs(c, v, ss); });
 }
 
 bdis_status bdis_compute_f32_batch(bdis_ctx* c, int n, const bdis_pair_f32* pairs, void* stream) {
@@ -1061,7 +1092,8 @@ bdis_status bdis_compute_f32_batch(bdis_ctx* c, int n, const bdis_pair_f32* pair
   }
   c->have_last = false;
   c->last_f32.clear();
-  bdis_status st = run_pairs_f32(c, v, reinterpret_cast<hipStream_t>(stream));
+  bdis_status st =
+      ordered(c, reinterpret_cast<hipStream_t>(stream), [&](hipStream_t ss) { return run_pairs_f32(c, v, ss); });
   if (st == BDIS_OK) c->last_f32 = v;
   return st;
 }
@@ -1090,7 +1122,8 @@ bdis_status bdis_backward_batch(bdis_ctx* c, int n, const bdis_pair_grad* grads,
     v[i].grad_left = grads[i].grad_left;
     v[i].grad_right = grads[i].grad_right;
   }
-  return run_backward(c, v, grad_hyper, reinterpret_cast<hipStream_t>(stream));
+  return ordered(c, reinterpret_cast<hipStream_t>(stream),
+                 [&](hipStream_t ss) { return run_backward(c, v, grad_hyper, ss); });
 }
 
 bdis_status bdis_backward(bdis_ctx* c, const float* grad_disparity, const float* grad_variance, float* grad_left,
@@ -1133,6 +1166,8 @@ bdis_status bdis_debug_dump(bdis_ctx* c, int level, int what, void* host_dst, si
   if ((what == BDIS_DBG_UBAR || what == BDIS_DBG_QMAP) && level <= c->p.finest_level)
     return fail(c, BDIS_E_ARG, "the finest level writes the outputs, not level maps");
   if (bytes < n) return fail(c, BDIS_E_ARG, "buffer of %zu bytes < %zu", bytes, n);
+  const bdis_status so = order_after_last(c, reinterpret_cast<hipStream_t>(stream));
+  if (so != BDIS_OK) return so;
   hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
   if (e == hipSuccess) {
     if (what == BDIS_DBG_LEFT || what == BDIS_DBG_RIGHT)  // padded rows -> dense W x H
@@ -1184,7 +1219,8 @@ bdis_status bdis_flow(bdis_ctx* c, const uint8_t* i0, const uint8_t* i1, int w, 
   ps.flow_u = flow_u;
   ps.flow_v = flow_v;
   std::vector<PairSpec> v{ps};
-  const bdis_status st = run_flow(c, v, reinterpret_cast<hipStream_t>(stream));
+  const bdis_status st =
+      ordered(c, reinterpret_cast<hipStream_t>(stream), [&](hipStream_t ss) { return run_flow(c, v, ss); });
   if (st == BDIS_OK) {  // per-patch flow stays readable through bdis_debug_dump (u: BDIS_DBG_U, v: BDIS_DBG_UINIT)
     c->last_w = w;
     c->last_h = h;
@@ -1241,6 +1277,7 @@ void bdis_destroy(bdis_ctx* c) {
   }
   for (hipEvent_t e : c->tm.pool) (void)hipEventDestroy(e);
   if (c->tab_evt) (void)hipEventDestroy(c->tab_evt);
+  if (c->done_evt) (void)hipEventDestroy(c->done_evt);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   if (c->tab_dev) (void)hipFree(c->tab_dev);
   if (c->tab_host) (void)hipHostFree(c->tab_host);

@@ -214,6 +214,36 @@ def test_most_levels_full_hd(B, oracle):
     ctx.close()
 
 
+def test_calls_on_two_streams_are_ordered(B):
+    """Two calls on different streams with no host synchronisation between them
+    reuse one workspace: the library orders them, so both results equal the
+    results of separate synchronised calls."""
+    import torch
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    a = make_pair(2, 4)
+    b = make_pair(2, 5)
+    p = B.params(**method_params(2))
+    ref = []
+    ctx = B.Context(p, 640, 480)
+    for q in (a, b):
+        out = ctx.compute(to_gpu(q[0]), to_gpu(q[1]))
+        torch.cuda.synchronize()
+        ref.append(out["disp"].clone())
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    la, ra, lb, rb = to_gpu(a[0]), to_gpu(a[1]), to_gpu(b[0]), to_gpu(b[1])
+    torch.cuda.synchronize()
+    print("[gpu] two streams, no host sync between the calls", flush=True)
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            oa = ctx.compute(la, ra, stream=s1)
+        with torch.cuda.stream(s2):
+            ob = ctx.compute(lb, rb, stream=s2)
+        torch.cuda.synchronize()
+        assert torch.equal(oa["disp"].nan_to_num(-999.0), ref[0].nan_to_num(-999.0))
+        assert torch.equal(ob["disp"].nan_to_num(-999.0), ref[1].nan_to_num(-999.0))
+    ctx.close()
+
+
 def test_depth_form(B, oracle):
     import torch
     from paper_2205_03133_amd.synth import make_pair, method_params
