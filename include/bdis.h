@@ -37,8 +37,9 @@
  *    of the last error of a context is available from bdis_last_error.
  *  - A context is not thread-safe: calls on one context must come from one
  *    host thread at a time.  Calls on different streams are ordered by the
- *    library (the next call's stream waits for the previous call's work),
- *    because every call reuses the context's workspace.
+ *    library, because every call reuses the context's workspace: the first
+ *    change of stream drains the device once, later ones make the new stream
+ *    wait for the previous call's work.
  */
 #ifndef BDIS_H
 #define BDIS_H

@@ -237,6 +237,7 @@ struct bdis_ctx {
   hipEvent_t done_evt = nullptr;  // end of the last call's work (orders calls on other streams)
   hipStream_t done_stream = nullptr;
   bool done_live = false;
+  bool multi_stream = false;      // calls have come on more than one stream
   hipStream_t capture_stream = nullptr;
   std::map<std::string, GraphEntry> graphs;
   std::map<std::string, int> tuned;  // level shape key -> search workgroup threads
@@ -766,22 +767,30 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
 }
 
 // Every call reuses the context's workspace and job table, so the work of a
-// call must not start before the previous call's work ends.  On the same
-// stream that holds by stream order; on another stream the new stream waits
-// for the event recorded at the end of the previous call (no host wait).
+// call must not start before the previous call's work ends.  On one stream
+// that holds by stream order and costs nothing.  The first time a call comes
+// on another stream the device is drained once; from then on every call
+// records an event at its end and a call on a different stream waits for it
+// (no host wait).
 bdis_status order_after_last(bdis_ctx* c, hipStream_t st) {
   if (!c->done_live || c->done_stream == st) return BDIS_OK;
-  const hipError_t e = hipStreamWaitEvent(st, c->done_evt, 0);
+  hipError_t e;
+  if (!c->multi_stream) {
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(c, e, "ordering after the previous call");
+    c->multi_stream = true;
+    return BDIS_OK;
+  }
+  e = hipStreamWaitEvent(st, c->done_evt, 0);
   return e == hipSuccess ? BDIS_OK : hip_fail(c, e, "ordering after the previous call");
 }
 
 bdis_status mark_done(bdis_ctx* c, hipStream_t st, bdis_status s) {
   if (s != BDIS_OK) return s;
-  const hipError_t e = hipEventRecord(c->done_evt, st);
-  if (e != hipSuccess) return hip_fail(c, e, "call completion event");
   c->done_stream = st;
   c->done_live = true;
-  return BDIS_OK;
+  if (!c->multi_stream) return BDIS_OK;
+  const hipError_t e = hipEventRecord(c->done_evt, st);
+  return e == hipSuccess ? BDIS_OK : hip_fail(c, e, "call completion event");
 }
 
 template <typename F>
