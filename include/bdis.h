@@ -99,7 +99,7 @@ typedef struct {
   const uint8_t* left;
   const uint8_t* right;
   int32_t w, h, pitch;
-  int32_t levels;          /* pyramid depth for this pair; 0 means params.levels           */
+  int32_t levels;          /* pyramid depth for this pair (finest_level < levels <= params.levels); 0 means params.levels */
   float* disparity;        /* H x W, required                                             */
   float* variance;         /* H x W, or NULL                                              */
   float* confidence;       /* H x W, or NULL                                              */

@@ -1069,6 +1069,8 @@ bdis_status bdis_compute_batch(bdis_ctx* c, int n, const bdis_pair* pairs, void*
     if (q.levels < 0) return fail(c, BDIS_E_ARG, "pair %d: negative levels", i);
     const int lv = q.levels > 0 ? q.levels : c->p.levels;
     if (lv > c->p.levels) return fail(c, BDIS_E_CAPACITY, "pair %d: %d levels > %d", i, lv, c->p.levels);
+    if (lv <= c->p.finest_level)
+      return fail(c, BDIS_E_ARG, "pair %d: %d levels do not reach finest_level %d", i, lv, c->p.finest_level);
     if (q.w > c->max_w || q.h > c->max_h) return fail(c, BDIS_E_CAPACITY, "pair %d: %dx%d too large", i, q.w, q.h);
     v.push_back(PairSpec{q.left, q.right, q.w, q.h, q.pitch, lv, q.disparity, q.variance, q.confidence});
   }
@@ -1093,6 +1095,8 @@ bdis_status bdis_compute_f32_batch(bdis_ctx* c, int n, const bdis_pair_f32* pair
       return fail(c, BDIS_E_ARG, "pair %d: variance output without params.variance", i);
     const int lv = q.levels > 0 ? q.levels : c->p.levels;
     if (lv > c->p.levels) return fail(c, BDIS_E_CAPACITY, "pair %d: %d levels > %d", i, lv, c->p.levels);
+    if (lv <= c->p.finest_level)
+      return fail(c, BDIS_E_ARG, "pair %d: %d levels do not reach finest_level %d", i, lv, c->p.finest_level);
     if (q.w > c->max_w || q.h > c->max_h) return fail(c, BDIS_E_CAPACITY, "pair %d: %dx%d too large", i, q.w, q.h);
     PairSpec ps{nullptr, nullptr, q.w, q.h, q.pitch, lv, q.disparity, q.variance, q.confidence};
     ps.left32 = q.left;

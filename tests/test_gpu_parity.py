@@ -363,6 +363,12 @@ def test_errors_leave_context_usable(B):
     torch.cuda.synchronize()
     assert torch.isfinite(out["disp"]).float().mean().item() > 0.8
     ctx.close()
+    # a batch pair whose pyramid stops before the finest level
+    ctx = B.Context(B.params(levels=3, finest_level=1, patch=8, stride=4, iters=8), 320, 240, max_batch=2)
+    with pytest.raises(B.BdisError) as e:
+        ctx.compute_batch([lt, lt], [rt, rt], levels=[3, 1])
+    assert e.value.code == B.E_ARG
+    ctx.close()
 
 
 def test_repeat_calls_identical(B):
