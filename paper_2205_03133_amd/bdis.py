@@ -174,6 +174,13 @@ class Context:
         if st:
             raise BdisError(st, lib().bdis_last_error(None).decode())
         self.max_w, self.max_h, self.max_batch = max_w, max_h, max_batch
+        import torch
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def _on_device(self, *tensors):
+        for t in tensors:
+            if t is not None and t.device != self.device:
+                raise ValueError(f"tensor on {t.device}; this context lives on {self.device}")
 
     def _err(self, st):
         return BdisError(st, lib().bdis_last_error(self._h).decode())
@@ -208,6 +215,7 @@ class Context:
         None when not requested).  ``out`` may hold preallocated tensors.
         """
         import torch
+        self._on_device(left, right)
         lp, w, h, pitch = _image_arg(left, "left")
         rp, w2, h2, pitch2 = _image_arg(right, "right")
         if (w, h, pitch) != (w2, h2, pitch2):
@@ -243,6 +251,7 @@ class Context:
         arr = (Pair * max(n, 1))()
         results = []
         for i in range(n):
+            self._on_device(lefts[i], rights[i])
             lp, w, h, pitch = _image_arg(lefts[i], "left")
             rp, w2, h2, pitch2 = _image_arg(rights[i], "right")
             if (w, h, pitch) != (w2, h2, pitch2):
@@ -271,6 +280,7 @@ class Context:
     def flow(self, i0, i1, stream=None):
         """Optical flow (u, v) between two uint8 frames (2-D CUDA tensors, same shape)."""
         import torch
+        self._on_device(i0, i1)
         p0, w, h, pitch = _image_arg(i0, "i0")
         p1, w2, h2, pitch2 = _image_arg(i1, "i1")
         if (w, h, pitch) != (w2, h2, pitch2):
@@ -348,6 +358,7 @@ class Context:
         (contiguous rows).  Returns dict(disp, var, conf) shaped like the input."""
         import torch
         single = lefts.dim() == 2
+        self._on_device(lefts, rights)
         L = lefts[None] if single else lefts
         R = rights[None] if single else rights
         if L.dtype != torch.float32 or R.dtype != torch.float32 or not L.is_cuda or L.shape != R.shape:
@@ -379,8 +390,9 @@ class Context:
         with grad_hyper = [sigma_s, sigma_r (alpha_r when dynamic), omega_0 .. omega_{L-1}]."""
         import torch
         B, h, w, dev = self._last_f32
-        gd = grad_disp.reshape(B, h, w).to(torch.float32).contiguous()
-        gv = grad_var.reshape(B, h, w).to(torch.float32).contiguous() if grad_var is not None else None
+        gd = grad_disp.reshape(B, h, w).to(device=dev, dtype=torch.float32).contiguous()
+        gv = (grad_var.reshape(B, h, w).to(device=dev, dtype=torch.float32).contiguous()
+              if grad_var is not None else None)
         gl = torch.empty((B, h, w), dtype=torch.float32, device=dev)
         gr = torch.empty((B, h, w), dtype=torch.float32, device=dev)
         gh = torch.zeros(2 + self.params.levels, dtype=torch.float64, device=dev)

@@ -793,9 +793,21 @@ bdis_status mark_done(bdis_ctx* c, hipStream_t st, bdis_status s) {
   return e == hipSuccess ? BDIS_OK : hip_fail(c, e, "call completion event");
 }
 
+// The workspace lives on the device current at bdis_create: calls must keep it current.
+bdis_status check_device(bdis_ctx* c) {
+  int dev = -1;
+  const hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(c, e, "hipGetDevice");
+  if (dev != c->device)
+    return fail(c, BDIS_E_STATE, "current device %d is not the context's device %d", dev, c->device);
+  return BDIS_OK;
+}
+
 template <typename F>
 bdis_status ordered(bdis_ctx* c, hipStream_t st, F&& run) {
-  const bdis_status s = order_after_last(c, st);
+  bdis_status s = check_device(c);
+  if (s != BDIS_OK) return s;
+  s = order_after_last(c, st);
   if (s != BDIS_OK) return s;
   return mark_done(c, st, run(st));
 }
@@ -1179,7 +1191,8 @@ bdis_status bdis_debug_dump(bdis_ctx* c, int level, int what, void* host_dst, si
   if ((what == BDIS_DBG_UBAR || what == BDIS_DBG_QMAP) && level <= c->p.finest_level)
     return fail(c, BDIS_E_ARG, "the finest level writes the outputs, not level maps");
   if (bytes < n) return fail(c, BDIS_E_ARG, "buffer of %zu bytes < %zu", bytes, n);
-  const bdis_status so = order_after_last(c, reinterpret_cast<hipStream_t>(stream));
+  bdis_status so = check_device(c);
+  if (so == BDIS_OK) so = order_after_last(c, reinterpret_cast<hipStream_t>(stream));
   if (so != BDIS_OK) return so;
   hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
   if (e == hipSuccess) {
