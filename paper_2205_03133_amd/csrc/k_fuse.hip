@@ -17,6 +17,10 @@
 //   weights); fused displacement sum W u / sum W (Eq. 13, normalised),
 //   confidence sum M pi / sum M, variance sum (W / sum W)^2 sigma_k^2 (Eq. 18,
 //   disparity form).  A gather has no atomics, so results are deterministic.
+//   With the mask weights (fusion 0, 2) the sums are evaluated separably: the
+//   mask factors into m(a) m(b), so the column sums over the covering patch
+//   columns are formed once per staged patch row and tile column in LDS and
+//   the pixel rows of the tile combine them.
 #include "bdis_internal.h"
 
 namespace bdis {
@@ -76,6 +80,8 @@ __global__ __launch_bounds__(kProbThreads) void k_prob(const PairLevel* tab, int
 // Records staged per workgroup: the patches covering a 64 x 4 pixel tile
 // (about 26 x 6 for stride 3; tiles that cover more use direct loads).
 constexpr int kMaxRec = 512;
+// Patch rows of a tile that the separable form keeps column sums for.
+constexpr int kSepRows = 8;
 
 // INLINE: the patch records are computed here (small levels) instead of read
 // from a preceding k_prob launch.
@@ -139,20 +145,69 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
     }
   }
   __syncthreads();
+  // Separable form (mask weights, fusion 0 and 2): the mask is m(x - o_x) m(y - o_y),
+  // so per staged patch row j and tile column the sums over the covering patch
+  // columns i are formed once and shared by the tile's pixel rows:
+  //   A0 = sum_i m_x pi, A1 = sum_i m_x pi u, A2 = sum_i m_x, A3 = sum_i (m_x pi)^2 sigma^2,
+  // then z = sum_j m_y A0, ..., zv = sum_j m_y^2 A3 per pixel.
+  __shared__ double s_A[4][kSepRows][kFuseTx];
+  const bool separable = staged && lp.fusion != 1 && nj <= kSepRows;
+  if (separable) {
+    for (int e = tid; e < nj * kFuseTx; e += kFuseTx * kFuseTy) {
+      const int rj = e / kFuseTx, xl = e - rj * kFuseTx;
+      const int xc = x0 + xl;
+      double A0 = 0.0, A1 = 0.0, A2 = 0.0, A3 = 0.0;
+      if (xc < a.g.w) {
+        int clo, chi, cex;
+        cover_range(xc, a.g.w, P, S, a.g.nx, clo, chi, cex);
+        const int cend = cex >= 0 ? chi + 1 : chi;
+        for (int ii = clo; ii <= cend; ++ii) {
+          const int i = ii <= chi ? ii : cex;
+          const int r = rj * ni + (i <= ihi ? i - ilo : ni - 1);
+          const double dw = s_w[r];
+          if (dw < 0.0) continue;  // rejected patch
+          const double mx = lp.fusion == 2 ? 1.0 : s_m[xc - grid_origin(i, a.g.w, P, S)];
+          const double wx = mx * dw;
+          A0 += wx;
+          A1 += wx * s_u[r];
+          A2 += mx;
+          A3 += wx * wx * s_v[r];
+        }
+      }
+      s_A[0][rj][xl] = A0;
+      s_A[1][rj][xl] = A1;
+      s_A[2][rj][xl] = A2;
+      s_A[3][rj][xl] = A3;
+    }
+    __syncthreads();
+  }
   const int x = x0 + tid % kFuseTx;
   const int y = y0 + tid / kFuseTx;
   if (x >= a.g.w || y >= a.g.h) return;
   const bool finest = lp.level == lp.finest;
   int pilo, pihi, piex, pjlo, pjhi, pjex;
-  cover_range(x, a.g.w, P, S, a.g.nx, pilo, pihi, piex);
   cover_range(y, a.g.h, P, S, a.g.ny, pjlo, pjhi, pjex);
   double z = 0.0, zu = 0.0, zm = 0.0, zq = 0.0, zv = 0.0;
   const int jend = pjex >= 0 ? pjhi + 1 : pjhi;
+  if (separable) {
+    const int xl = tid % kFuseTx;
+    for (int jj = pjlo; jj <= jend; ++jj) {
+      const int j = jj <= pjhi ? jj : pjex;
+      const int rj = j <= jhi ? j - jlo : nj - 1;
+      const double my = lp.fusion == 2 ? 1.0 : s_m[y - grid_origin(j, a.g.h, P, S)];
+      z += my * s_A[0][rj][xl];
+      zu += my * s_A[1][rj][xl];
+      zm += my * s_A[2][rj][xl];
+      zv += my * my * s_A[3][rj][xl];
+    }
+    zq = z;
+  }
+  cover_range(x, a.g.w, P, S, a.g.nx, pilo, pihi, piex);
   // Eq. 2 (DIS weights): this pixel's left value and its right-image row
   double lx = 0.0;
   if (lp.fusion == 1) lx = a.Ld ? gbl(a.Ld)[(size_t)y * a.dpitch + x] : (double)gbl(a.L)[(size_t)y * a.pitch + x];
   const int iend = piex >= 0 ? pihi + 1 : pihi;
-  for (int jj = pjlo; jj <= jend; ++jj) {
+  for (int jj = pjlo; !separable && jj <= jend; ++jj) {
     const int j = jj <= pjhi ? jj : pjex;
     const double mb = lp.fusion == 2 ? 1.0 : s_m[y - grid_origin(j, a.g.h, P, S)];
     const int rj = j <= jhi ? j - jlo : nj - 1;  // row of j in the staged block
