@@ -365,12 +365,22 @@ BDIS_DEV void pair_scalars(const PairLevel& a, const LevelParams& lp, double* s_
   out[3] = (double)cnt;
 }
 
+// floor(a / d) for 0 <= a < 2^22 and 1 <= d <= 2^10: a float reciprocal
+// estimate (error well below 1) corrected by one step each way, so exact; a
+// few instructions instead of the generic integer division.
+BDIS_DEV int div_small(int a, int d) {
+  int q = (int)((float)a * __builtin_amdgcn_rcpf((float)d));
+  q += (q + 1) * d <= a ? 1 : 0;
+  q -= q * d > a ? 1 : 0;
+  return q;
+}
+
 // Covering patches along one axis: indices lo..hi (origin i*S), plus the last
 // patch (origin n-P) when it covers x but lies past hi.
 BDIS_DEV void cover_range(int x, int n, int P, int S, int cnt, int& lo, int& hi, int& extra) {
   const int t = x - P;  // origin must exceed x - P
-  lo = t >= 0 ? t / S + 1 : 0;
-  hi = min(x / S, cnt - 1);
+  lo = t >= 0 ? div_small(t, S) + 1 : 0;
+  hi = min(div_small(x, S), cnt - 1);
   extra = (x >= n - P && cnt - 1 > hi) ? cnt - 1 : -1;
 }
 

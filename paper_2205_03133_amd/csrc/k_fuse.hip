@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
   }
   if (staged) {
     for (int r = tid; r < ni * nj; r += kFuseTx * kFuseTy) {
-      const int rj = r / ni, ri = r - rj * ni;
+      const int rj = div_small(r, ni), ri = r - rj * ni;
       const int i = ilo + ri <= ihi ? ilo + ri : iex;
       const int j = jlo + rj <= jhi ? jlo + rj : jex;
       const size_t k = (size_t)j * a.g.nx + i;
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
   const int y = y0 + tid / kFuseTx;
   if (x >= a.g.w || y >= a.g.h) return;
   const bool finest = lp.level == lp.finest;
-  int pilo, pihi, piex, pjlo, pjhi, pjex;
+  int pilo = 0, pihi = -1, piex = -1, pjlo = 0, pjhi = -1, pjex = -1;
   cover_range(y, a.g.h, P, S, a.g.ny, pjlo, pjhi, pjex);
   double z = 0.0, zu = 0.0, zm = 0.0, zq = 0.0, zv = 0.0;
   const int jend = pjex >= 0 ? pjhi + 1 : pjhi;
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
     }
     zq = z;
   }
-  cover_range(x, a.g.w, P, S, a.g.nx, pilo, pihi, piex);
+  if (!separable) cover_range(x, a.g.w, P, S, a.g.nx, pilo, pihi, piex);
   // Eq. 2 (DIS weights): this pixel's left value and its right-image row
   double lx = 0.0;
   if (lp.fusion == 1) lx = a.Ld ? gbl(a.Ld)[(size_t)y * a.dpitch + x] : (double)gbl(a.L)[(size_t)y * a.pitch + x];
