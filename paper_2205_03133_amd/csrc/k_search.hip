@@ -37,6 +37,13 @@ namespace {
 // Exact product of two integers known to lie within +-2^23.
 BDIS_DEV int mul24(int a, int b) { return __mul24(a, b); }
 
+// a*b - c*d of int32 values whose products and difference stay below 2^53 in
+// magnitude (true for every combination below: at most about 2^36), so the
+// double result is exact; full-rate FP64 instead of quarter-rate 64-bit mads.
+BDIS_DEV double exact_ab_cd(int a, int b, int c, int d) {
+  return fma((double)a, (double)b, -((double)c * (double)d));
+}
+
 // Reads N consecutive right-image samples of one row starting at column x:
 // from the LDS window when it covers them, else from global memory with the
 // column clamped to the image (identical values either way).
@@ -182,10 +189,10 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
   sT = group_sum<G>(sT);
   sGG = group_sum<G>(sGG);
   sGT = group_sum<G>(sGT);
-  const long long Hs = (long long)N * sGG - (long long)sG * sG;  // = 64 N H, exact
-  const double H = (double)Hs / (64.0 * N);
+  const double Hs = exact_ab_cd(N, sGG, sG, sG);  // = 64 N H, exact
+  const double H = Hs / (64.0 * N);
   const bool invert = H >= kEpsH;
-  const double step = invert ? 8.0 / (double)Hs : 0.0;
+  const double step = invert ? 8.0 / Hs : 0.0;
 
   const uint8_t* win = s_right + rr * RWB;
   const uint8_t* grow = a.R + (size_t)(oy + rr) * a.pitch;
@@ -215,8 +222,8 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
         cs0 = group_sum<G>(cs0);
         cg1 = group_sum<G>(cg1);
         cs1 = group_sum<G>(cs1);
-        E0 = (double)((long long)N * (cg0 - sGT) - (long long)sG * (cs0 - sT));
-        E1 = (double)((long long)N * (cg1 - sGT) - (long long)sG * (cs1 - sT));
+        E0 = exact_ab_cd(N, cg0 - sGT, sG, cs0 - sT);
+        E1 = exact_ab_cd(N, cg1 - sGT, sG, cs1 - sT);
         mc = m;
       }
       u -= ((1.0 - f) * E0 + f * E1) * step;
@@ -259,12 +266,13 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
       sd = group_sum<G>(row_live ? sd : 0);
       sdd = group_sum<G>(row_live ? sdd : 0);
       sad = group_sum<G>(row_live ? sad : 0);
-      X0[cq] = (double)((long long)N * saa - (long long)ga * ga);
-      X1[cq] = (double)((long long)N * sad - (long long)ga * sd);
-      X2[cq] = (double)((long long)N * sdd - (long long)sd * sd);
+      X0[cq] = exact_ab_cd(N, saa, ga, ga);
+      X1[cq] = exact_ab_cd(N, sad, ga, sd);
+      X2[cq] = exact_ab_cd(N, sdd, sd, sd);
     }
   }
-  auto ssd = [&](int cq, double fr) { return (X0[cq] + fr * (2.0 * X1[cq] + fr * X2[cq])) / (double)N; };
+  constexpr double kInvN = 1.0 / (double)N;  // SSD = [X0 + 2 f X1 + f^2 X2] / N, by the rounded 1/N
+  auto ssd = [&](int cq, double fr) { return (X0[cq] + fr * (2.0 * X1[cq] + fr * X2[cq])) * kInvN; };
   const double s0 = ssd(1, f);
   const double sm1 = ssd(0, f);
   const double sp1 = ssd(2, f);
