@@ -29,10 +29,11 @@
  *  - Compute calls are asynchronous on `stream` (a hipStream_t; NULL is the
  *    null stream) once a batch shape has been seen.  The first call with a
  *    new batch shape (pair sizes, levels and parameters) times the search
- *    workgroup sizes on `stream` and synchronises it, then records the launch
+ *    configurations (lanes per patch, workgroup size) per level on `stream`
+ *    and synchronises it, then records the launch
  *    sequence as a graph; a job table larger than any before synchronises the
  *    device before it is reallocated.  Environment: BDIS_TUNE=0 skips the
- *    timing (default sizes), BDIS_GRAPH=0 launches eagerly without graphs.
+ *    timing (default configuration), BDIS_GRAPH=0 launches eagerly without graphs.
  *  - Errors are returned as bdis_status; the library never aborts.  The text
  *    of the last error of a context is available from bdis_last_error.
  *  - A context is not thread-safe: calls on one context must come from one

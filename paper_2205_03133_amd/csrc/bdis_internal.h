@@ -17,7 +17,6 @@
 
 namespace bdis {
 
-constexpr int kWinRow = 512;     // columns of the right-image row window staged in LDS
 constexpr double kEpsH = 1e-3;   // smallest Hessian that is inverted
 constexpr double kEpsSigma = 1e-6;
 constexpr int kMaxPatch = 16;    // largest patch side
@@ -178,18 +177,49 @@ constexpr int kSearchF64Threads = 256;
 constexpr size_t kAdjTileBytes = 64 * 1024;  // LDS accumulation tiles of the search adjoint
 constexpr int kPixThreads = 256;
 
-// Search workgroup sizes the tuner may pick (threads; patches = threads / G).
-constexpr int kNumSearchOptions = 5;
-constexpr int kSearchThreadOptions[kNumSearchOptions] = {64, 128, 256, 512, 1024};
+// Uint8 search configurations the tuner may pick per level: a lane mapping
+// (kind) and a workgroup size.  Kind k puts G = search_lanes(P, k) lanes on a
+// patch, each lane holding R = ceil(P / G) consecutive patch rows: kind 0 one
+// row per lane (short per-lane chains, for latency-bound small levels), kinds
+// 1 and 2 two and three-to-four rows per lane (the per-patch iteration logic
+// repeated on fewer lanes, for throughput-bound large levels).
+constexpr int kSearchKinds = 3;
+constexpr int kNumSearchThreads = 4;
+constexpr int kSearchThreadOptions[kNumSearchThreads] = {64, 128, 256, 512};
+constexpr int kNumSearchOptions = kSearchKinds * kNumSearchThreads;
 
-__host__ __device__ inline int search_patches_per_block(int P, int threads) {
-  return threads / (P <= 8 ? 8 : 16);
+__host__ __device__ constexpr int search_lanes(int P, int kind) {
+  return kind == 0 ? (P <= 8 ? 8 : 16) : kind == 1 ? (P <= 8 ? 4 : 8) : (P <= 8 ? 2 : (P <= 12 ? 4 : 8));
+}
+__host__ __device__ inline int search_option_threads(int opt) { return kSearchThreadOptions[opt % kNumSearchThreads]; }
+__host__ __device__ inline int search_option_kind(int opt) { return opt / kNumSearchThreads; }
+__host__ __device__ inline int search_patches_per_block(int P, int opt) {
+  return search_option_threads(opt) / search_lanes(P, search_option_kind(opt));
+}
+
+// Columns of disparity spread among a workgroup's patches that the staged
+// right-image window absorbs; samples beyond it are read from global memory.
+constexpr int kWinSpread = 384;
+constexpr int kSearchMaxLds = 64 * 1024;
+
+// LDS layout of a uint8 search workgroup of `npb` patches at stride S: the left
+// tile holds P + 2 rows of `ltw` bytes (patch columns plus the Sobel border,
+// from a 4-aligned start), the right window P rows of `rwb` bytes.
+__host__ __device__ inline void search_lds_layout(int P, int npb, int S, int& ltw, int& rwb) {
+  const int span = (npb - 1) * S + P;  // columns covered by the patch origins
+  ltw = (span + 8) / 4 * 4;
+  rwb = (span + 2 * (P + 4) + 8 + kWinSpread + 15) / 16 * 16;
+}
+__host__ __device__ inline int search_lds_bytes(int P, int opt, int S) {
+  int ltw, rwb;
+  search_lds_layout(P, search_patches_per_block(P, opt), S, ltw, rwb);
+  return (P + 2) * ltw + P * rwb;
 }
 
 // Launchers over a device table of `npairs` entries (each returns the launch status).
 hipError_t launch_pyramid(const PairLevel* tab, int npairs, int nblocks, hipStream_t s);
 hipError_t launch_search(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,
-                         int threads, hipStream_t s);
+                         int opt, hipStream_t s);
 hipError_t launch_reduce(const PairLevel* tab, int npairs, const LevelParams& lp, hipStream_t s);
 hipError_t launch_prob(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s);
 hipError_t launch_fuse(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,
@@ -252,14 +282,15 @@ BDIS_DEV int find_pair(const PairLevel* tab, int n, int b) {
   return lo;
 }
 
-// All-reduce (sum) of an int over an aligned group of G lanes (G = 8 or 16)
-// with DPP lane permutations: quad swaps, then half-row and row mirrors.
+// All-reduce (sum) of an int over an aligned group of G lanes (G = 1, 2, 4, 8
+// or 16) with DPP lane permutations: quad swaps, then half-row and row mirrors.
 template <int G>
 BDIS_DEV int group_sum(int v) {
-  v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
-  v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
-  v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true);  // row_half_mirror
-  if constexpr (G == 16) v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, true);  // row_mirror
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group of 1..16 lanes");
+  if constexpr (G >= 2) v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
+  if constexpr (G >= 4) v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
+  if constexpr (G >= 8) v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true);  // row_half_mirror
+  if constexpr (G >= 16) v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, true);  // row_mirror
   return v;
 }
 
@@ -302,7 +333,6 @@ BDIS_DEV double group_sum_d(double v) {
 }
 
 // Hardware FP64 atomic add on global memory (accumulation of adjoints).
-// Global-memory FP64 add (every adjoint scatter targets HBM arrays).
 BDIS_DEV void atomic_add_d(double* p, double v) { (void)__builtin_amdgcn_global_atomic_fadd_f64(gbl(p), v); }
 
 // Reflect-101 index for |overshoot| < n (the only case the kernels produce).

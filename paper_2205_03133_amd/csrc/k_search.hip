@@ -5,10 +5,13 @@
 // (Sec. III-B): workgroups write partial sums, which k_reduce (large levels)
 // or every fusion workgroup of the level (small levels) adds in a fixed order.
 //
-// Mapping: one lane per patch row, an aligned group of G = 8 or 16 lanes per
-// patch (a DPP quad/half-row/row, so group reductions are 3-4 DPP adds),
-// THREADS/G patches of one patch row of one pair per workgroup (THREADS is
-// picked per level by the tuner).  The left rows around those
+// Mapping: an aligned group of G = 2..16 lanes per patch (a DPP pair, quad,
+// half-row or row, so group reductions are 1-4 DPP adds), each lane holding
+// R = ceil(P / G) consecutive patch rows; THREADS/G patches of one patch row
+// of one pair per workgroup.  The tuner picks G and THREADS per level: one
+// row per lane keeps the per-lane chain of the K dependent iterations short
+// (small, latency-bound levels), several rows per lane repeat the per-patch
+// iteration logic on fewer lanes (large, throughput-bound levels).  The left rows around those
 // patches (for the template and its Sobel gradient) and a window of the right
 // rows around the patches' starting displacements are staged in LDS once;
 // right-image samples outside the window fall back to (clamped) global loads.
@@ -44,21 +47,54 @@ BDIS_DEV double exact_ab_cd(int a, int b, int c, int d) {
   return fma((double)a, (double)b, -((double)c * (double)d));
 }
 
-// Reads N consecutive right-image samples of one row starting at column x:
-// from the LDS window when it covers them, else from global memory with the
+// Packed samples: four uint8 samples per dword, little-endian (byte b of word
+// w is column 4w + b), so byte-vector sums and dot products are v_dot4_u32_u8
+// (four exact 8-bit products per instruction).
+BDIS_DEV uint32_t dot4(uint32_t a, uint32_t b, uint32_t acc) { return __builtin_amdgcn_udot4(a, b, acc, false); }
+
+// Word w of a P-sample vector: mask of its valid bytes, and 1 in each valid byte.
+__host__ __device__ constexpr uint32_t valid_bytes(int w, int P) {
+  return P - 4 * w >= 4 ? 0xffffffffu : ((1u << (8 * (P - 4 * w))) - 1u);
+}
+__host__ __device__ constexpr uint32_t ones_word(int w, int P) { return valid_bytes(w, P) & 0x01010101u; }
+
+// Right-image samples of one row at columns x .. x + 4 NW + 3 as NW + 1 packed
+// words: from the LDS window (aligned dword reads, realigned with
+// v_alignbyte) when it holds every word read, else from global memory with each
 // column clamped to the image (identical values either way).
-template <int N>
-BDIS_DEV void fetch_row(int (&v)[N], const uint8_t* win, int xs, int rw, const uint8_t* grow,
-                        int x, int W) {
+template <int NW>
+BDIS_DEV void fetch_words(uint32_t (&B)[NW + 1], const uint8_t* win, int xs, int rw, const uint8_t* grow, int x,
+                          int W) {
   const int off = x - xs;
-  if (off >= 0 && off + N <= rw) {
+  const int a4 = off & ~3;
+  if (off >= 0 && a4 + 4 * (NW + 2) <= rw) {
+    const uint32_t* wp = reinterpret_cast<const uint32_t*>(win + a4);
+    const uint32_t sh = (uint32_t)(off & 3);
+    uint32_t D[NW + 2];
 #pragma unroll
-    for (int n = 0; n < N; ++n) v[n] = win[off + n];
+    for (int i = 0; i < NW + 2; ++i) D[i] = wp[i];
+#pragma unroll
+    for (int w = 0; w <= NW; ++w) B[w] = __builtin_amdgcn_alignbyte(D[w + 1], D[w], sh);
   } else {
+    // rare (samples far from the staged window): one word at a time, so that
+    // few loads and addresses are live at once
     const auto g = gbl(grow);
 #pragma unroll
-    for (int n = 0; n < N; ++n) v[n] = g[clampi(x + n, 0, W - 1)];
+    for (int w = 0; w <= NW; ++w) {
+      uint32_t v = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) v |= (uint32_t)g[clampi(x + 4 * w + b, 0, W - 1)] << (8 * b);
+      B[w] = v;
+      __builtin_amdgcn_sched_barrier(0);  // keep one word's loads in flight at a time
+    }
   }
+}
+
+// Words of the P samples starting J columns after the first sample of B.
+template <int NW, int J>
+BDIS_DEV uint32_t shifted_word(const uint32_t (&B)[NW + 1], int w) {
+  if constexpr (J == 0) return B[w];
+  else return __builtin_amdgcn_alignbyte(B[w + 1], B[w], (uint32_t)J);
 }
 
 // Copies columns [x0, x0 + 4 nd) of image row `rp` (width W) into LDS as nd
@@ -87,31 +123,37 @@ BDIS_DEV void stage_row(uint32_t* dst, const uint8_t* rp, int W, int x0, int nd,
   }
 }
 
-template <int P, int THREADS>
+template <int P, int G, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int npairs, LevelParams lp) {
-  constexpr int G = group_lanes(P);
+  static_assert(G >= 2 && G <= 16 && THREADS % 64 == 0, "lanes per patch and workgroup size");
+  constexpr int R = (P + G - 1) / G;             // patch rows per lane: rows g*R .. g*R+R-1
+  constexpr bool kAllRows = R * G == P;          // no lane holds rows past the patch
   constexpr int NPB = THREADS / G;               // patches per workgroup
-  constexpr int LTW = ((NPB - 1) * P + P + 2 + 3 + 3) / 4 * 4;  // left tile row bytes (S <= P, 4-aligned start)
-  constexpr int RWB = kWinRow;                   // right window row bytes
   constexpr int MARG = P + 4;                    // window margin around the start range
   constexpr int N = P * P;
+  constexpr int NW = (P + 3) / 4;                // packed words per patch row
   constexpr int NWAVES = THREADS / 64;
 
-  __shared__ uint32_t s_left32[(P + 2) * LTW / 4];
-  __shared__ uint32_t s_right32[P * RWB / 4];
+  extern __shared__ uint32_t s_dyn[];
   __shared__ int s_umin, s_umax;
   __shared__ double s_psum[NPB];
   __shared__ int s_pcnt[NPB];
-  const uint8_t* s_left = reinterpret_cast<const uint8_t*>(s_left32);
-  const uint8_t* s_right = reinterpret_cast<const uint8_t*>(s_right32);
 
   const int lb = xcd_block();
   const PairLevel& a = tab[find_pair<1>(tab, npairs, lb)];
   const int blk = lb - a.search0;   // workgroup within the pair
   const int tid = threadIdx.x;
-  const int q = tid / G;  // patch slot in the workgroup
-  const int r = tid % G;  // patch row of this lane
+  const int q = tid / G;   // patch slot in the workgroup
+  const int g = tid % G;   // lane within the patch
+  const int r0 = g * R;    // first patch row of this lane
   const int W = a.g.w, Hh = a.g.h, S = lp.S;
+  int LTW, RWB;
+  search_lds_layout(P, NPB, S, LTW, RWB);
+  uint32_t* s_left32 = s_dyn;
+  uint32_t* s_right32 = s_dyn + (P + 2) * LTW / 4;
+  const uint8_t* s_left = reinterpret_cast<const uint8_t*>(s_left32);
+  const uint8_t* s_right = reinterpret_cast<const uint8_t*>(s_right32);
+
   const int j = blk / a.search_nbx;
   const int i0 = (blk % a.search_nbx) * NPB;
   const bool live = (i0 + q) < a.g.nx;
@@ -145,7 +187,7 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
     stage_row<true>(s_left32 + ty * (LTW / 4), rp, W, xa, ndl, lane, ((uintptr_t)rp & 3) == 0);
   }
   __syncthreads();
-  if (r == 0 && live) {
+  if (g == 0 && live) {
     const int mu = (int)floor(uinit);
     atomicMin(&s_umin, mu);
     atomicMax(&s_umax, mu);
@@ -162,29 +204,77 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
   }
   __syncthreads();
 
-  // ---- template row: T and Sobel-x G (integer), rows r >= P are idle lanes
-  const bool row_live = r < P;
-  const int rr = row_live ? r : P - 1;
-  int T[P], Gx[P];
-  {
-    const uint8_t* l0 = s_left + rr * LTW + (ox - 1 - xa);
-    const uint8_t* l1 = l0 + LTW;
-    const uint8_t* l2 = l1 + LTW;
+  // ---- template rows of this lane: T and Sobel-x G (integer); rows past the
+  // patch (only when G does not divide P) read valid LDS and are masked out
+  bool rlive[R];
+  int rrow[R];
 #pragma unroll
-    for (int c = 0; c < P; ++c) {
-      T[c] = l1[c + 1];
-      Gx[c] = (l0[c + 2] - l0[c]) + 2 * (l1[c + 2] - l1[c]) + (l2[c + 2] - l2[c]);
+  for (int k = 0; k < R; ++k) {
+    rlive[k] = kAllRows || r0 + k < P;
+    rrow[k] = kAllRows ? r0 + k : min(r0 + k, P - 1);
+  }
+  // packed rows: T, and Gx + 1024 (0..2044) split into its high (0..7) and low
+  // bytes, so sum Gx R = 256 (Gh . R) + (Gl . R) - 1024 sum R; padding bytes 0.
+  // The rows are built one at a time from a rolling window of three tile rows.
+  uint32_t Tw[R][NW], Ghw[R][NW], Glw[R][NW];
+  int sG = 0, sT = 0, sGG = 0, sGT = 0, sTT = 0;
+  {
+    const uint8_t* base = s_left + (ox - 1 - xa);
+    auto tile_row = [&](int k, int (&v)[P + 2]) {
+      const int ty = kAllRows ? r0 + k : min(r0 + k, P + 1);  // tile row = image row oy - 1 + ty
+#pragma unroll
+      for (int c = 0; c < P + 2; ++c) v[c] = base[ty * LTW + c];
+    };
+    int Lu[P + 2], Lc[P + 2], Ld[P + 2];
+    tile_row(0, Lu);
+    tile_row(1, Lc);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      tile_row(k + 2, Ld);
+      int T[P], Gx[P];
+      int a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        T[c] = Lc[c + 1];
+        Gx[c] = (Lu[c + 2] - Lu[c]) + 2 * (Lc[c + 2] - Lc[c]) + (Ld[c + 2] - Ld[c]);
+        a0 += Gx[c];
+        a1 += T[c];
+        a2 += mul24(Gx[c], Gx[c]);
+        a3 += mul24(Gx[c], T[c]);
+        a4 += mul24(T[c], T[c]);
+      }
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        uint32_t tw = 0, hw = 0, lw = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int c = 4 * w + b;
+          if (c < P) {
+            const uint32_t gp = (uint32_t)(Gx[c] + 1024);
+            tw |= (uint32_t)T[c] << (8 * b);
+            hw |= (gp >> 8) << (8 * b);
+            lw |= (gp & 255u) << (8 * b);
+          }
+        }
+        Tw[k][w] = tw;
+        Ghw[k][w] = hw;
+        Glw[k][w] = lw;
+      }
+      if (rlive[k]) {
+        sG += a0;
+        sT += a1;
+        sGG += a2;
+        sGT += a3;
+        sTT += a4;
+      }
+#pragma unroll
+      for (int c = 0; c < P + 2; ++c) {
+        Lu[c] = Lc[c];
+        Lc[c] = Ld[c];
+      }
     }
   }
-  int sG = 0, sT = 0, sGG = 0, sGT = 0;
-#pragma unroll
-  for (int c = 0; c < P; ++c) {
-    sG += Gx[c];
-    sT += T[c];
-    sGG += mul24(Gx[c], Gx[c]);
-    sGT += mul24(Gx[c], T[c]);
-  }
-  if (!row_live) sG = sT = sGG = sGT = 0;
+  const int sT_lane = sT, sTT_lane = sTT;  // this lane's rows (the window sums below are per lane)
   sG = group_sum<G>(sG);
   sT = group_sum<G>(sT);
   sGG = group_sum<G>(sGG);
@@ -194,8 +284,8 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
   const bool invert = H >= kEpsH;
   const double step = invert ? 8.0 / Hs : 0.0;
 
-  const uint8_t* win = s_right + rr * RWB;
-  const uint8_t* grow = a.R + (size_t)(oy + rr) * a.pitch;
+  const uint8_t* win = s_right;
+  const uint8_t* grow = a.R + (size_t)oy * a.pitch;
 
   // ---- K inverse-compositional iterations (Eq. 1), cached cell correlations
   double u = uinit;
@@ -207,17 +297,29 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
       const int m = (int)fm;
       const double f = u - fm;
       if (m != mc) {
-        int Rv[P + 1];
-        fetch_row<P + 1>(Rv, win, xs, rw, grow, ox + m, W);
-        int cg0 = 0, cs0 = 0, cg1 = 0;
+        int cg0 = 0, cs0 = 0, cg1 = 0, cs1 = 0;
 #pragma unroll
-        for (int c = 0; c < P; ++c) {
-          cg0 += mul24(Gx[c], Rv[c]);
-          cs0 += Rv[c];
-          cg1 += mul24(Gx[c], Rv[c + 1]);
+        for (int k = 0; k < R; ++k) {
+          uint32_t B[NW + 1];
+          fetch_words<NW>(B, win + rrow[k] * RWB, xs, rw, grow + (size_t)rrow[k] * a.pitch, ox + m, W);
+          uint32_t h0 = 0, l0 = 0, s0 = 0, h1 = 0, l1 = 0, s1 = 0;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) {
+            const uint32_t a0 = B[w], a1 = shifted_word<NW, 1>(B, w);
+            h0 = dot4(a0, Ghw[k][w], h0);
+            l0 = dot4(a0, Glw[k][w], l0);
+            s0 = dot4(a0, ones_word(w, P), s0);
+            h1 = dot4(a1, Ghw[k][w], h1);
+            l1 = dot4(a1, Glw[k][w], l1);
+            s1 = dot4(a1, ones_word(w, P), s1);
+          }
+          if (rlive[k]) {
+            cg0 += 256 * (int)h0 + (int)l0 - 1024 * (int)s0;
+            cs0 += (int)s0;
+            cg1 += 256 * (int)h1 + (int)l1 - 1024 * (int)s1;
+            cs1 += (int)s1;
+          }
         }
-        int cs1 = cs0 + Rv[P] - Rv[0];
-        if (!row_live) cg0 = cs0 = cg1 = cs1 = 0;
         cg0 = group_sum<G>(cg0);
         cs0 = group_sum<G>(cs0);
         cg1 = group_sum<G>(cg1);
@@ -241,33 +343,56 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
   const double f = u - fm;
   double X0[3], X1[3], X2[3];
   {
-    int Rv[P + 3], D[P + 2];
-    fetch_row<P + 3>(Rv, win, xs, rw, grow, ox + m - 1, W);
+    // With A_j the P samples from column m - 1 + j of a row (j = 0..3):
+    //   sum a = S_q - sum T,  sum d = S_{q+1} - S_q,
+    //   sum a^2 = AA_q - 2 TA_q + TT,  sum d^2 = AA_{q+1} - 2 AB_q + AA_q,
+    //   sum a d = AB_q - AA_q - TA_{q+1} + TA_q,
+    // S_j = sum A_j, AA_j = A_j . A_j, AB_j = A_j . A_{j+1}, TA_j = T . A_j.
+    int gS[4] = {0, 0, 0, 0}, gAA[4] = {0, 0, 0, 0}, gAB[3] = {0, 0, 0}, gTA[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int c = 0; c < P + 2; ++c) D[c] = Rv[c + 1] - Rv[c];
-    int sa = 0;
+    for (int k = 0; k < R; ++k) {
+      uint32_t B[NW + 1];
+      fetch_words<NW>(B, win + rrow[k] * RWB, xs, rw, grow + (size_t)rrow[k] * a.pitch, ox + m - 1, W);
+      uint32_t A[4][NW];
 #pragma unroll
-    for (int c = 0; c < P; ++c) sa += Rv[c] - T[c];
+      for (int w = 0; w < NW; ++w) {
+        A[0][w] = shifted_word<NW, 0>(B, w) & valid_bytes(w, P);
+        A[1][w] = shifted_word<NW, 1>(B, w) & valid_bytes(w, P);
+        A[2][w] = shifted_word<NW, 2>(B, w) & valid_bytes(w, P);
+        A[3][w] = shifted_word<NW, 3>(B, w) & valid_bytes(w, P);
+      }
+      uint32_t S4[4] = {0, 0, 0, 0}, AA[4] = {0, 0, 0, 0}, AB[3] = {0, 0, 0}, TA[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          S4[jj] = dot4(A[jj][w], ones_word(w, P), S4[jj]);
+          AA[jj] = dot4(A[jj][w], A[jj][w], AA[jj]);
+          TA[jj] = dot4(A[jj][w], Tw[k][w], TA[jj]);
+        }
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) AB[jj] = dot4(A[jj][w], A[jj + 1][w], AB[jj]);
+      }
+      if (rlive[k]) {
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          gS[jj] += (int)S4[jj];
+          gAA[jj] += (int)AA[jj];
+          gTA[jj] += (int)TA[jj];
+        }
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) gAB[jj] += (int)AB[jj];
+      }
+    }
 #pragma unroll
     for (int cq = 0; cq < 3; ++cq) {
-      // sum of d telescopes; sum of a slides by one sample per cell
-      if (cq > 0) sa += Rv[cq + P - 1] - Rv[cq - 1];
-      int sd = Rv[cq + P] - Rv[cq];
-      int saa = 0, sdd = 0, sad = 0;
-#pragma unroll
-      for (int c = 0; c < P; ++c) {
-        const int av = Rv[c + cq] - T[c];
-        saa += mul24(av, av);
-        sdd += mul24(D[c + cq], D[c + cq]);
-        sad += mul24(av, D[c + cq]);
-      }
-      const int ga = group_sum<G>(row_live ? sa : 0);
-      saa = group_sum<G>(row_live ? saa : 0);
-      sd = group_sum<G>(row_live ? sd : 0);
-      sdd = group_sum<G>(row_live ? sdd : 0);
-      sad = group_sum<G>(row_live ? sad : 0);
-      X0[cq] = exact_ab_cd(N, saa, ga, ga);
-      X1[cq] = exact_ab_cd(N, sad, ga, sd);
+      const int sa = group_sum<G>(gS[cq] - sT_lane);
+      const int sd = group_sum<G>(gS[cq + 1] - gS[cq]);
+      const int saa = group_sum<G>(gAA[cq] - 2 * gTA[cq] + sTT_lane);
+      const int sdd = group_sum<G>(gAA[cq + 1] - 2 * gAB[cq] + gAA[cq]);
+      const int sad = group_sum<G>(gAB[cq] - gAA[cq] - gTA[cq + 1] + gTA[cq]);
+      X0[cq] = exact_ab_cd(N, saa, sa, sa);
+      X1[cq] = exact_ab_cd(N, sad, sa, sd);
       X2[cq] = exact_ab_cd(N, sdd, sd, sd);
     }
   }
@@ -301,7 +426,7 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
   const bool acc = s0 <= sm1 && s0 <= smh && s0 <= sph && s0 <= sp1 && rho >= (double)lp.valid_ratio;
 
   const int k = j * a.g.nx + i;
-  if (r == 0 && live) {
+  if (g == 0 && live) {
     gbl(a.pa.uinit)[k] = uinit;
     gbl(a.pa.pipar)[k] = pipar;
     gbl(a.pa.u)[k] = u;
@@ -313,21 +438,28 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
   }
 
   // ---- per-workgroup partial of the level reduction: sum of SSD(0) and count
-  // over accepted patches (summed per pair, in workgroup order, by k_reduce)
-  if (r == 0) {
+  // over accepted patches, as a fixed-order tree over the workgroup's patches
+  if (g == 0) {
     s_psum[q] = (live && acc) ? s0 : 0.0;
     s_pcnt[q] = (live && acc) ? 1 : 0;
   }
   __syncthreads();
-  if (tid == 0) {
+  if (wave == 0) {
     double ps = 0.0;
     int pc = 0;
-    for (int t = 0; t < NPB; ++t) {
+    for (int t = lane; t < NPB; t += 64) {
       ps += s_psum[t];
       pc += s_pcnt[t];
     }
-    gbl(a.part_sum)[blk] = ps;
-    gbl(a.part_cnt)[blk] = pc;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      ps += __shfl_xor(ps, o, 64);
+      pc += __shfl_xor(pc, o, 64);
+    }
+    if (lane == 0) {
+      gbl(a.part_sum)[blk] = ps;
+      gbl(a.part_cnt)[blk] = pc;
+    }
   }
 }
 
@@ -343,18 +475,31 @@ __global__ __launch_bounds__(256) void k_reduce(const PairLevel* tab, LevelParam
     for (int t = 0; t < 4; ++t) gbl(a.scal)[t] = sc[t];
 }
 
-template <int P>
-hipError_t launch_p(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, int threads,
-                    hipStream_t s) {
+template <int P, int G>
+hipError_t launch_pg(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, int threads, int lds,
+                     hipStream_t s) {
   switch (threads) {
-    case 64: hipLaunchKernelGGL((k_search_u8<P, 64>), dim3(nblocks), dim3(64), 0, s, tab, npairs, lp); break;
-    case 128: hipLaunchKernelGGL((k_search_u8<P, 128>), dim3(nblocks), dim3(128), 0, s, tab, npairs, lp); break;
-    case 256: hipLaunchKernelGGL((k_search_u8<P, 256>), dim3(nblocks), dim3(256), 0, s, tab, npairs, lp); break;
-    case 512: hipLaunchKernelGGL((k_search_u8<P, 512>), dim3(nblocks), dim3(512), 0, s, tab, npairs, lp); break;
-    case 1024: hipLaunchKernelGGL((k_search_u8<P, 1024>), dim3(nblocks), dim3(1024), 0, s, tab, npairs, lp); break;
+    case 64: hipLaunchKernelGGL((k_search_u8<P, G, 64>), dim3(nblocks), dim3(64), lds, s, tab, npairs, lp); break;
+    case 128: hipLaunchKernelGGL((k_search_u8<P, G, 128>), dim3(nblocks), dim3(128), lds, s, tab, npairs, lp); break;
+    case 256: hipLaunchKernelGGL((k_search_u8<P, G, 256>), dim3(nblocks), dim3(256), lds, s, tab, npairs, lp); break;
+    case 512: hipLaunchKernelGGL((k_search_u8<P, G, 512>), dim3(nblocks), dim3(512), lds, s, tab, npairs, lp); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_p(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, int opt, hipStream_t s) {
+  if (opt < 0 || opt >= kNumSearchOptions) return hipErrorInvalidValue;
+  const int lds = search_lds_bytes(P, opt, lp.S);
+  if (lds > kSearchMaxLds) return hipErrorInvalidValue;
+  const int threads = search_option_threads(opt);
+  switch (search_option_kind(opt)) {
+    case 0: return launch_pg<P, search_lanes(P, 0)>(tab, npairs, nblocks, lp, threads, lds, s);
+    case 1: return launch_pg<P, search_lanes(P, 1)>(tab, npairs, nblocks, lp, threads, lds, s);
+    case 2: return launch_pg<P, search_lanes(P, 2)>(tab, npairs, nblocks, lp, threads, lds, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
@@ -365,24 +510,24 @@ hipError_t launch_reduce(const PairLevel* tab, int npairs, const LevelParams& lp
   return hipGetLastError();
 }
 
-hipError_t launch_search(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, int threads,
+hipError_t launch_search(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, int opt,
                          hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
   switch (lp.P) {
-    case 3: return launch_p<3>(tab, npairs, nblocks, lp, threads, s);
-    case 4: return launch_p<4>(tab, npairs, nblocks, lp, threads, s);
-    case 5: return launch_p<5>(tab, npairs, nblocks, lp, threads, s);
-    case 6: return launch_p<6>(tab, npairs, nblocks, lp, threads, s);
-    case 7: return launch_p<7>(tab, npairs, nblocks, lp, threads, s);
-    case 8: return launch_p<8>(tab, npairs, nblocks, lp, threads, s);
-    case 9: return launch_p<9>(tab, npairs, nblocks, lp, threads, s);
-    case 10: return launch_p<10>(tab, npairs, nblocks, lp, threads, s);
-    case 11: return launch_p<11>(tab, npairs, nblocks, lp, threads, s);
-    case 12: return launch_p<12>(tab, npairs, nblocks, lp, threads, s);
-    case 13: return launch_p<13>(tab, npairs, nblocks, lp, threads, s);
-    case 14: return launch_p<14>(tab, npairs, nblocks, lp, threads, s);
-    case 15: return launch_p<15>(tab, npairs, nblocks, lp, threads, s);
-    case 16: return launch_p<16>(tab, npairs, nblocks, lp, threads, s);
+    case 3: return launch_p<3>(tab, npairs, nblocks, lp, opt, s);
+    case 4: return launch_p<4>(tab, npairs, nblocks, lp, opt, s);
+    case 5: return launch_p<5>(tab, npairs, nblocks, lp, opt, s);
+    case 6: return launch_p<6>(tab, npairs, nblocks, lp, opt, s);
+    case 7: return launch_p<7>(tab, npairs, nblocks, lp, opt, s);
+    case 8: return launch_p<8>(tab, npairs, nblocks, lp, opt, s);
+    case 9: return launch_p<9>(tab, npairs, nblocks, lp, opt, s);
+    case 10: return launch_p<10>(tab, npairs, nblocks, lp, opt, s);
+    case 11: return launch_p<11>(tab, npairs, nblocks, lp, opt, s);
+    case 12: return launch_p<12>(tab, npairs, nblocks, lp, opt, s);
+    case 13: return launch_p<13>(tab, npairs, nblocks, lp, opt, s);
+    case 14: return launch_p<14>(tab, npairs, nblocks, lp, opt, s);
+    case 15: return launch_p<15>(tab, npairs, nblocks, lp, opt, s);
+    case 16: return launch_p<16>(tab, npairs, nblocks, lp, opt, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -56,9 +56,20 @@ struct Layout {
   size_t total = 0;
 };
 
-int search_nbx(const LevelGeom& g, int P, int threads) {
-  const int npb = search_patches_per_block(P, threads);
-  return (g.nx + npb - 1) / npb;
+int search_nbx(const LevelGeom& g, int npb) { return (g.nx + npb - 1) / npb; }
+
+// Patches per search workgroup: the uint8 search in a tuned configuration
+// (option index), or the fixed float-path / optical-flow search.
+int search_npb(int P, int opt, bool f64_search) {
+  return f64_search ? kSearchF64Threads / group_lanes(P) : search_patches_per_block(P, opt);
+}
+
+// Fewest patches per workgroup over every search configuration (sizes the
+// per-workgroup partials).
+int min_search_npb(int P) {
+  int m = search_npb(P, 0, true);
+  for (int o = 0; o < kNumSearchOptions; ++o) m = std::min(m, search_npb(P, o, false));
+  return m;
 }
 
 // Level sizes W_n = ceil(W_{n-1} / 2); the patch grid exists on processed levels.
@@ -119,7 +130,9 @@ bool make_layout(const bdis_params& p, int w, int h, int levels, Layout* lay, bo
       L.oconf = take(npx * 4);
     }
     // partials sized for the smallest workgroup the tuner may choose
-    L.max_search_blocks[n] = search_nbx(L.g[n], p.patch, kSearchThreadOptions[0]) * L.g[n].ny;
+    L.max_search_blocks[n] =
+        search_nbx(L.g[n], min_search_npb(p.patch)) *
+        L.g[n].ny;
     L.part_sum[n] = take((size_t)L.max_search_blocks[n] * 8);
     L.part_cnt[n] = take((size_t)L.max_search_blocks[n] * 4);
     L.scal[n] = take(64);
@@ -197,7 +210,8 @@ struct Plan {
   int tab_count[kMaxLevels]{};   // entries (pairs having level n)
   int pyr_blocks[kMaxLevels]{}, search_blocks[kMaxLevels]{}, prob_blocks[kMaxLevels]{},
       fuse_blocks[kMaxLevels]{};
-  int threads[kMaxLevels]{};     // search workgroup size per level
+  bool flow = false;             // optical-flow search (fixed workgroups like the float path)
+  int search_opt[kMaxLevels]{};  // uint8 search configuration per level (lane mapping, workgroup size)
   int up_blocks = 0;             // finest level f > 0: upsampling workgroups (level 0)
   int inline_prob[kMaxLevels]{}; // 1: the fusion computes the patch records (small levels)
   bool f32 = false;              // float (FP64) path: per-pixel pyramid blocks, fixed search size
@@ -240,7 +254,7 @@ struct bdis_ctx {
   bool multi_stream = false;      // calls have come on more than one stream
   hipStream_t capture_stream = nullptr;
   std::map<std::string, GraphEntry> graphs;
-  std::map<std::string, int> tuned;  // level shape key -> search workgroup threads
+  std::map<std::string, int> tuned;  // level shape key -> uint8 search configuration (option index)
   int use_graph = 1;
   bool train = false;                // created with BDIS_TRAIN
   std::vector<PairSpec> last_f32;    // pairs of the last float-path call (backward state)
@@ -362,19 +376,20 @@ std::string level_key(const bdis_params& p, const Plan& pl, int n) {
   return buf;
 }
 
-// Default search workgroup size: the largest option that still gives every
-// compute unit (256 on MI355X) two workgroups; else the smallest option.
-int default_threads(const Plan& pl, int n, int P) {
-  for (int o = 2; o >= 0; --o) {  // 256, 128, 64
-    const int t = kSearchThreadOptions[o];
+// Default search configuration (untuned): one patch row per lane, the largest
+// workgroup that still gives every compute unit (256 on MI355X) two
+// workgroups; else the smallest workgroup.
+int default_search_opt(const Plan& pl, int n, int P, int S) {
+  for (int o = 2; o >= 0; --o) {  // kind 0 at 256, 128, 64 threads
+    if (search_lds_bytes(P, o, S) > kSearchMaxLds) continue;
     long blocks = 0;
     for (int e = 0; e < pl.tab_count[n]; ++e) {
       const PairLevel& q = pl.tab[pl.tab_first[n] + e];
-      blocks += (long)search_nbx(q.g, P, t) * q.g.ny;
+      blocks += (long)search_nbx(q.g, search_npb(P, o, false)) * q.g.ny;
     }
-    if (blocks >= 512) return t;
+    if (blocks >= 512) return o;
   }
-  return kSearchThreadOptions[0];
+  return 0;
 }
 
 // Assigns workgroup offsets for the given per-level search workgroup sizes.
@@ -389,7 +404,7 @@ void assign_offsets(const bdis_params& p, Plan& pl) {
   for (int n = 0; n < pl.max_levels; ++n) {
     int pyr = 0, se = 0, pr = 0, fu = 0;
     const bool patches = n >= p.finest_level;
-    const int threads = pl.f32 ? kSearchF64Threads : pl.threads[n];
+    const int opt = pl.search_opt[n];
     for (int e = 0; e < pl.tab_count[n]; ++e) {
       PairLevel& q = pl.tab[pl.tab_first[n] + e];
       q.pyr0 = pyr;
@@ -397,7 +412,7 @@ void assign_offsets(const bdis_params& p, Plan& pl) {
         pyr += (q.g.w * q.g.h + kPixThreads - 1) / kPixThreads;
       else
         pyr += n >= 1 ? ((q.g.w + kPyrTx - 1) / kPyrTx) * ((q.g.h + kPyrTy - 1) / kPyrTy) : 0;
-      q.search_nbx = patches ? search_nbx(q.g, p.patch, threads) : 0;
+      q.search_nbx = patches ? search_nbx(q.g, search_npb(p.patch, opt, pl.f32 || pl.flow)) : 0;
       q.search0 = se;
       se += patches ? q.search_nbx * q.g.ny : 0;
       q.prob0 = pr;
@@ -418,6 +433,7 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
   Plan pl;
   pl.finest = p.finest_level;
   pl.f32 = f32;
+  pl.flow = flow;
   std::vector<Layout> lays(pairs.size());
   for (size_t i = 0; i < pairs.size(); ++i) {
     const PairSpec& q = pairs[i];
@@ -557,11 +573,11 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
   }
   for (int n = 0; n < pl.max_levels; ++n) {
     if (f32 || flow || n < p.finest_level || pl.tab_count[n] == 0) {
-      pl.threads[n] = (f32 || flow) ? kSearchF64Threads : 256;
+      pl.search_opt[n] = 0;
       continue;
     }
     auto it = c->tuned.find(level_key(p, pl, n));
-    pl.threads[n] = it != c->tuned.end() ? it->second : default_threads(pl, n, p.patch);
+    pl.search_opt[n] = it != c->tuned.end() ? it->second : default_search_opt(pl, n, p.patch, p.stride);
   }
   for (int n = 0; n < pl.max_levels; ++n) {
     long np = 0;
@@ -627,7 +643,7 @@ bdis_status launch_all(bdis_ctx* c, const Plan& pl, hipStream_t st) {
     LevelParams lp = level_params(p, n);
     lp.inline_prob = pl.inline_prob[n];
     long tmk = timing_start(c, BDIS_K_SEARCH, st);
-    e = launch_search(tab, cnt, pl.search_blocks[n], lp, pl.threads[n], st);
+    e = launch_search(tab, cnt, pl.search_blocks[n], lp, pl.search_opt[n], st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "search launch");
     tmk = timing_start(c, BDIS_K_REDUCE, st);
@@ -662,7 +678,7 @@ std::string graph_key(const bdis_params& p, const Plan& pl) {
   add(pl.search_blocks, sizeof pl.search_blocks);
   add(pl.prob_blocks, sizeof pl.prob_blocks);
   add(pl.fuse_blocks, sizeof pl.fuse_blocks);
-  add(pl.threads, sizeof pl.threads);
+  add(pl.search_opt, sizeof pl.search_opt);
   add(&pl.up_blocks, sizeof pl.up_blocks);
   add(pl.inline_prob, sizeof pl.inline_prob);
   add(&pl.max_levels, sizeof pl.max_levels);
@@ -694,9 +710,9 @@ bdis_status run_graph(bdis_ctx* c, const Plan& pl, hipStream_t st) {
   return BDIS_OK;
 }
 
-// Picks the search workgroup size of every level of a new batch shape by
-// timing each option over full passes (every phase rewrites its outputs, so
-// trial passes leave nothing behind).
+// Picks the search configuration (lane mapping and workgroup size) of every
+// level of a new batch shape by timing each option over full passes (every
+// phase rewrites its outputs, so trial passes leave nothing behind).
 bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
   const bdis_params& p = c->p;
   bool need = false;
@@ -709,7 +725,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
   int best_t[kMaxLevels];
   for (int n = 0; n < kMaxLevels; ++n) {
     best_ms[n] = 1e30f;
-    best_t[n] = pl.threads[n];
+    best_t[n] = pl.search_opt[n];
   }
   if (enabled) {
     std::vector<hipEvent_t> ev(2 * kMaxLevels, nullptr);
@@ -717,8 +733,11 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
     for (auto& x : ev)
       if (e == hipSuccess) e = hipEventCreate(&x);
     for (int o = 0; o < kNumSearchOptions && e == hipSuccess; ++o) {
+      if (search_lds_bytes(p.patch, o, p.stride) > kSearchMaxLds) continue;
+      const int kind = search_option_kind(o);
+      if (kind > 0 && search_lanes(p.patch, kind) == search_lanes(p.patch, kind - 1)) continue;  // same mapping
       Plan trial = pl;
-      for (int n = 0; n < trial.max_levels; ++n) trial.threads[n] = kSearchThreadOptions[o];
+      for (int n = 0; n < trial.max_levels; ++n) trial.search_opt[n] = o;
       assign_offsets(p, trial);
       bdis_status s2 = upload_table(c, trial, st);
       if (s2 != BDIS_OK) {
@@ -735,7 +754,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
           LevelParams lp = level_params(p, n);
           lp.inline_prob = trial.inline_prob[n];
           (void)hipEventRecord(ev[2 * n], st);
-          e = launch_search(tab, trial.tab_count[n], trial.search_blocks[n], lp, trial.threads[n], st);
+          e = launch_search(tab, trial.tab_count[n], trial.search_blocks[n], lp, trial.search_opt[n], st);
           (void)hipEventRecord(ev[2 * n + 1], st);
           if (e == hipSuccess) e = launch_reduce(tab, trial.tab_count[n], lp, st);
           if (e == hipSuccess) e = launch_prob(tab, trial.tab_count[n], trial.prob_blocks[n], lp, st);
@@ -748,7 +767,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
           float ms = 0.0f;
           if (hipEventElapsedTime(&ms, ev[2 * n], ev[2 * n + 1]) == hipSuccess && ms < best_ms[n]) {
             best_ms[n] = ms;
-            best_t[n] = trial.threads[n];
+            best_t[n] = trial.search_opt[n];
           }
         }
       }
@@ -760,7 +779,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
   for (int n = p.finest_level; n < pl.max_levels; ++n) {
     if (!pl.tab_count[n]) continue;
     c->tuned[level_key(p, pl, n)] = best_t[n];
-    pl.threads[n] = best_t[n];
+    pl.search_opt[n] = best_t[n];
   }
   assign_offsets(p, pl);
   return BDIS_OK;
