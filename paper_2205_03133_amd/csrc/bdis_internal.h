@@ -160,6 +160,7 @@ struct LevelParams {
   int fusion;       // 0 Eq. 13, 1 Eq. 2 (DIS), 2 Eq. 13 with a uniform mask
   int propagate;    // 1: add the parent confidence (Eq. 11)
   int inline_prob;  // 1: the fusion computes the level scalars and patch records itself (small levels)
+  int fuse_ty;      // fusion tile height (kFuseTyShort or kFuseTyTall)
 };
 
 // Tile shapes of the flattened launches.
@@ -170,7 +171,12 @@ constexpr int kProbThreads = 256;           // probability: patches per workgrou
 // reduction or probability launch); larger levels compute each once in
 // launches of their own.
 constexpr long kInlineProbPatches = 1 << 16;
-constexpr int kFuseTx = 64, kFuseTy = 4;    // fusion: 64 x 4 pixels per workgroup
+// Fusion tiles: 64 x 4 pixels, one per lane of 256 (small levels, many
+// workgroups), or 64 x 16, two per lane of 512 (levels of at least
+// kFuseTallPixels pixels over the batch: fewer re-staged patch records).
+constexpr int kFuseTx = 64, kFuseTyShort = 4, kFuseTyTall = 16;
+constexpr long kFuseTallPixels = 1 << 20;
+__host__ __device__ constexpr int fuse_threads(int ty) { return ty == kFuseTyTall ? 512 : 256; }
 
 // Workgroups of the float-path search (fixed size) and of per-pixel adjoint launches.
 constexpr int kSearchF64Threads = 256;
@@ -367,14 +373,16 @@ BDIS_DEV void pair_scalars(const PairLevel& a, const LevelParams& lp, double* s_
                            double out[4]) {
   const int tid = threadIdx.x;
   const int nblocks = a.search_nbx * a.g.ny;
-  double ps = 0.0;
-  long long pc = 0;
-  for (int b = tid; b < nblocks; b += 256) {
-    ps += gbl(a.part_sum)[b];
-    pc += gbl(a.part_cnt)[b];
+  if (tid < 256) {  // the first 256 threads of the workgroup (256 or more)
+    double ps = 0.0;
+    long long pc = 0;
+    for (int b = tid; b < nblocks; b += 256) {
+      ps += gbl(a.part_sum)[b];
+      pc += gbl(a.part_cnt)[b];
+    }
+    s_red[tid] = ps;
+    s_redc[tid] = pc;
   }
-  s_red[tid] = ps;
-  s_redc[tid] = pc;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (tid < off) {

@@ -142,8 +142,9 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_flow_search(const PairLev
   }
 }
 
-// Per pixel (64 x 4 tiles): Eq. 2 fusion of the covering patches' flows.
-__global__ __launch_bounds__(kFuseTx* kFuseTy) void k_flow_fuse(const PairLevel* tab, int npairs, LevelParams lp) {
+// Per pixel (fusion tiles of lp.fuse_ty rows): Eq. 2 fusion of the covering
+// patches' flows.
+__global__ __launch_bounds__(512) void k_flow_fuse(const PairLevel* tab, int npairs, LevelParams lp) {
   const int lb = xcd_block();
   const PairLevel& a = tab[find_pair<3>(tab, npairs, lb)];
   const int tid = threadIdx.x;
@@ -151,36 +152,40 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_flow_fuse(const PairLevel*
   const int tiles_x = (a.g.w + kFuseTx - 1) / kFuseTx;
   const int t = lb - a.fuse0;
   const int x = (t % tiles_x) * kFuseTx + tid % kFuseTx;
-  const int y = (t / tiles_x) * kFuseTy + tid / kFuseTx;
-  if (x >= a.g.w || y >= a.g.h) return;
-  int ilo, ihi, iex, jlo, jhi, jex;
+  if (x >= a.g.w) return;
+  int ilo, ihi, iex;
   cover_range(x, a.g.w, P, S, a.g.nx, ilo, ihi, iex);
-  cover_range(y, a.g.h, P, S, a.g.ny, jlo, jhi, jex);
-  const double l0 = (double)gbl(a.L)[(size_t)y * a.pitch + x];
-  double z = 0.0, zu = 0.0, zv = 0.0;
-  const int jend = jex >= 0 ? jhi + 1 : jhi;
   const int iend = iex >= 0 ? ihi + 1 : ihi;
-  for (int jj = jlo; jj <= jend; ++jj) {
-    const int j = jj <= jhi ? jj : jex;
-    for (int ii = ilo; ii <= iend; ++ii) {
-      const int i = ii <= ihi ? ii : iex;
-      const size_t k = (size_t)j * a.g.nx + i;
-      const double uk = gbl(a.pa.u)[k], vk = gbl(a.pa.uinit)[k];
-      const double rres = bilinear_u8(a.R, a.pitch, a.g.w, a.g.h, (double)x + uk, (double)y + vk) - l0;
-      const double wk = 1.0 / fmax(1.0, rres * rres);
-      z += wk;
-      zu += wk * uk;
-      zv += wk * vk;
+  const int ty = lp.fuse_ty, lanes_y = (int)blockDim.x / kFuseTx;
+  for (int y = (t / tiles_x) * ty + tid / kFuseTx, yn = 0; yn < ty / lanes_y; ++yn, y += lanes_y) {
+    if (y >= a.g.h) break;
+    int jlo, jhi, jex;
+    cover_range(y, a.g.h, P, S, a.g.ny, jlo, jhi, jex);
+    const double l0 = (double)gbl(a.L)[(size_t)y * a.pitch + x];
+    double z = 0.0, zu = 0.0, zv = 0.0;
+    const int jend = jex >= 0 ? jhi + 1 : jhi;
+    for (int jj = jlo; jj <= jend; ++jj) {
+      const int j = jj <= jhi ? jj : jex;
+      for (int ii = ilo; ii <= iend; ++ii) {
+        const int i = ii <= ihi ? ii : iex;
+        const size_t k = (size_t)j * a.g.nx + i;
+        const double uk = gbl(a.pa.u)[k], vk = gbl(a.pa.uinit)[k];
+        const double rres = bilinear_u8(a.R, a.pitch, a.g.w, a.g.h, (double)x + uk, (double)y + vk) - l0;
+        const double wk = 1.0 / fmax(1.0, rres * rres);
+        z += wk;
+        zu += wk * uk;
+        zv += wk * vk;
+      }
     }
-  }
-  const size_t idx = (size_t)y * a.g.w + x;
-  const double fu = zu / z, fv = zv / z;  // every pixel is covered
-  if (lp.level > lp.finest) {
-    gbl(a.ubar)[idx] = fu;
-    gbl(a.qmap)[idx] = fv;
-  } else {
-    gbl(a.flow_u)[idx] = (float)fu;
-    gbl(a.flow_v)[idx] = (float)fv;
+    const size_t idx = (size_t)y * a.g.w + x;
+    const double fu = zu / z, fv = zv / z;  // every pixel is covered
+    if (lp.level > lp.finest) {
+      gbl(a.ubar)[idx] = fu;
+      gbl(a.qmap)[idx] = fv;
+    } else {
+      gbl(a.flow_u)[idx] = (float)fu;
+      gbl(a.flow_v)[idx] = (float)fv;
+    }
   }
 }
 
@@ -197,7 +202,8 @@ hipError_t launch_flow_search(const PairLevel* tab, int npairs, int nblocks, con
 
 hipError_t launch_flow_fuse(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_flow_fuse, dim3(nblocks), dim3(kFuseTx * kFuseTy), 0, s, tab, npairs, lp);
+  if (lp.fuse_ty != kFuseTyShort && lp.fuse_ty != kFuseTyTall) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_flow_fuse, dim3(nblocks), dim3(fuse_threads(lp.fuse_ty)), 0, s, tab, npairs, lp);
   return hipGetLastError();
 }
 

@@ -10,7 +10,7 @@
 //   Gauss-Newton fixed point is the least-squares line of ln p on d^2:
 //   sigma_k^2 = tau / (2 kappa), kappa the slope of SSD_d on d^2.
 //
-// k_fuse (one lane per level pixel, gather): over the accepted patches
+// k_fuse (gather over 64 x 4 or 64 x 16 pixel tiles): over the accepted patches
 //   covering the pixel, in ascending patch index, weights W_k = M(x - o_k) pi_k
 //   with the spatial mixture mask M(a, b) = m(a) m(b),
 //   m(a) = sum_c exp(-(a - c)^2 / (2 sigma_s^2)) (Eq. 9-10, unit mixture
@@ -77,16 +77,18 @@ __global__ __launch_bounds__(kProbThreads) void k_prob(const PairLevel* tab, int
   st4(a.pa.dens + k, patch_record(a, lp, (size_t)k, gbl(a.scal)[1]));
 }
 
-// Records staged per workgroup: the patches covering a 64 x 4 pixel tile
-// (about 26 x 6 for stride 3; tiles that cover more use direct loads).
+// Records staged per workgroup: the patches covering a tile (about 26 x 6
+// for 64 x 4 and 26 x 9 for 64 x 16 at stride 3; tiles that cover more use
+// direct loads).
 constexpr int kMaxRec = 512;
-// Patch rows of a tile that the separable form keeps column sums for.
-constexpr int kSepRows = 8;
 
 // INLINE: the patch records are computed here (small levels) instead of read
 // from a preceding k_prob launch.
-template <bool INLINE>
-__global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab, int npairs, LevelParams lp) {
+template <bool INLINE, int TY>
+__global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab, int npairs, LevelParams lp) {
+  constexpr int kThreads = fuse_threads(TY);
+  constexpr int kRowsPerLane = TY / (kThreads / kFuseTx);
+  constexpr int kSepRows = TY == kFuseTyTall ? 12 : 8;  // patch rows the separable form keeps sums for
   __shared__ double s_m[kMaxPatch];
   __shared__ double s_u[kMaxRec], s_w[kMaxRec], s_v[kMaxRec];
   const int lb = xcd_block();
@@ -104,8 +106,8 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
   }
   const int tiles_x = (a.g.w + kFuseTx - 1) / kFuseTx;
   const int t = lb - a.fuse0;
-  const int x0 = (t % tiles_x) * kFuseTx, y0 = (t / tiles_x) * kFuseTy;
-  const int x1 = min(x0 + kFuseTx, a.g.w) - 1, y1 = min(y0 + kFuseTy, a.g.h) - 1;
+  const int x0 = (t % tiles_x) * kFuseTx, y0 = (t / tiles_x) * TY;
+  const int x1 = min(x0 + kFuseTx, a.g.w) - 1, y1 = min(y0 + TY, a.g.h) - 1;
   // patch index ranges covering the tile: [lo, hi] plus the border patch `ex`
   int ilo, ihi, iex, jlo, jhi, jex, dummy0, dummy1, dummy2;
   cover_range(x0, a.g.w, P, S, a.g.nx, ilo, dummy0, dummy1);
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
     if (t == 0 && tid < 4) gbl(a.scal)[tid] = sc[tid];  // kept for the backward pass and debug
   }
   if (staged) {
-    for (int r = tid; r < ni * nj; r += kFuseTx * kFuseTy) {
+    for (int r = tid; r < ni * nj; r += kThreads) {
       const int rj = div_small(r, ni), ri = r - rj * ni;
       const int i = ilo + ri <= ihi ? ilo + ri : iex;
       const int j = jlo + rj <= jhi ? jlo + rj : jex;
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
   __shared__ double s_A[4][kSepRows][kFuseTx];
   const bool separable = staged && lp.fusion != 1 && nj <= kSepRows;
   if (separable) {
-    for (int e = tid; e < nj * kFuseTx; e += kFuseTx * kFuseTy) {
+    for (int e = tid; e < nj * kFuseTx; e += kThreads) {
       const int rj = e / kFuseTx, xl = e - rj * kFuseTx;
       const int xc = x0 + xl;
       double A0 = 0.0, A1 = 0.0, A2 = 0.0, A3 = 0.0;
@@ -181,120 +183,126 @@ __global__ __launch_bounds__(kFuseTx* kFuseTy) void k_fuse(const PairLevel* tab,
     }
     __syncthreads();
   }
-  const int x = x0 + tid % kFuseTx;
-  const int y = y0 + tid / kFuseTx;
-  if (x >= a.g.w || y >= a.g.h) return;
+  // every lane fuses kRowsPerLane pixels of its tile column
+  const int xl = tid % kFuseTx;
+  const int x = x0 + xl;
   const bool finest = lp.level == lp.finest;
-  int pilo = 0, pihi = -1, piex = -1, pjlo = 0, pjhi = -1, pjex = -1;
-  cover_range(y, a.g.h, P, S, a.g.ny, pjlo, pjhi, pjex);
-  double z = 0.0, zu = 0.0, zm = 0.0, zq = 0.0, zv = 0.0;
-  const int jend = pjex >= 0 ? pjhi + 1 : pjhi;
-  if (separable) {
-    const int xl = tid % kFuseTx;
-    for (int jj = pjlo; jj <= jend; ++jj) {
+  auto fuse_pixel = [&](int y) {
+    int pilo = 0, pihi = -1, piex = -1, pjlo = 0, pjhi = -1, pjex = -1;
+    cover_range(y, a.g.h, P, S, a.g.ny, pjlo, pjhi, pjex);
+    double z = 0.0, zu = 0.0, zm = 0.0, zq = 0.0, zv = 0.0;
+    const int jend = pjex >= 0 ? pjhi + 1 : pjhi;
+    if (separable) {
+      for (int jj = pjlo; jj <= jend; ++jj) {
+        const int j = jj <= pjhi ? jj : pjex;
+        const int rj = j <= jhi ? j - jlo : nj - 1;
+        const double my = lp.fusion == 2 ? 1.0 : s_m[y - grid_origin(j, a.g.h, P, S)];
+        z += my * s_A[0][rj][xl];
+        zu += my * s_A[1][rj][xl];
+        zm += my * s_A[2][rj][xl];
+        zv += my * my * s_A[3][rj][xl];
+      }
+      zq = z;
+    }
+    if (!separable) cover_range(x, a.g.w, P, S, a.g.nx, pilo, pihi, piex);
+    // Eq. 2 (DIS weights): this pixel's left value and its right-image row
+    double lx = 0.0;
+    if (lp.fusion == 1) lx = a.Ld ? gbl(a.Ld)[(size_t)y * a.dpitch + x] : (double)gbl(a.L)[(size_t)y * a.pitch + x];
+    const int iend = piex >= 0 ? pihi + 1 : pihi;
+    for (int jj = pjlo; !separable && jj <= jend; ++jj) {
       const int j = jj <= pjhi ? jj : pjex;
-      const int rj = j <= jhi ? j - jlo : nj - 1;
-      const double my = lp.fusion == 2 ? 1.0 : s_m[y - grid_origin(j, a.g.h, P, S)];
-      z += my * s_A[0][rj][xl];
-      zu += my * s_A[1][rj][xl];
-      zm += my * s_A[2][rj][xl];
-      zv += my * my * s_A[3][rj][xl];
-    }
-    zq = z;
-  }
-  if (!separable) cover_range(x, a.g.w, P, S, a.g.nx, pilo, pihi, piex);
-  // Eq. 2 (DIS weights): this pixel's left value and its right-image row
-  double lx = 0.0;
-  if (lp.fusion == 1) lx = a.Ld ? gbl(a.Ld)[(size_t)y * a.dpitch + x] : (double)gbl(a.L)[(size_t)y * a.pitch + x];
-  const int iend = piex >= 0 ? pihi + 1 : pihi;
-  for (int jj = pjlo; !separable && jj <= jend; ++jj) {
-    const int j = jj <= pjhi ? jj : pjex;
-    const double mb = lp.fusion == 2 ? 1.0 : s_m[y - grid_origin(j, a.g.h, P, S)];
-    const int rj = j <= jhi ? j - jlo : nj - 1;  // row of j in the staged block
-    for (int ii = pilo; ii <= iend; ++ii) {
-      const int i = ii <= pihi ? ii : piex;
-      double du, dw, dv;
-      if (staged) {
-        const int r = rj * ni + (i <= ihi ? i - ilo : ni - 1);
-        du = s_u[r];
-        dw = s_w[r];
-        dv = s_v[r];
-      } else {
-        const size_t k = (size_t)j * a.g.nx + i;
-        D4 d;
-        if (INLINE) {
-          d = patch_record(a, lp, k, tau);
-          if (x == grid_origin(i, a.g.w, P, S) && y == grid_origin(j, a.g.h, P, S)) st4(a.pa.dens + k, d);
+      const double mb = lp.fusion == 2 ? 1.0 : s_m[y - grid_origin(j, a.g.h, P, S)];
+      const int rj = j <= jhi ? j - jlo : nj - 1;  // row of j in the staged block
+      for (int ii = pilo; ii <= iend; ++ii) {
+        const int i = ii <= pihi ? ii : piex;
+        double du, dw, dv;
+        if (staged) {
+          const int r = rj * ni + (i <= ihi ? i - ilo : ni - 1);
+          du = s_u[r];
+          dw = s_w[r];
+          dv = s_v[r];
         } else {
-          d = ld4(a.pa.dens + k);
+          const size_t k = (size_t)j * a.g.nx + i;
+          D4 d;
+          if (INLINE) {
+            d = patch_record(a, lp, k, tau);
+            if (x == grid_origin(i, a.g.w, P, S) && y == grid_origin(j, a.g.h, P, S)) st4(a.pa.dens + k, d);
+          } else {
+            d = ld4(a.pa.dens + k);
+          }
+          du = d.x;
+          dw = d.y;
+          dv = d.z;
         }
-        du = d.x;
-        dw = d.y;
-        dv = d.z;
-      }
-      if (dw < 0.0) continue;  // rejected patch
-      const double m = lp.fusion == 2 ? 1.0 : s_m[x - grid_origin(i, a.g.w, P, S)] * mb;
-      double wk = m * dw;
-      if (lp.fusion == 1) {
-        // 1 / max(1, r^2), r = I_r(x + u) - I_l(x): linear warp, indices clamped to the row
-        const double fm = floor(du);
-        const int mm = (int)fm;
-        const double fr = du - fm;
-        const int xa = clampi(x + mm, 0, a.g.w - 1), xb = clampi(x + mm + 1, 0, a.g.w - 1);
-        double ra, rb;
-        if (a.Rd) {
-          ra = gbl(a.Rd)[(size_t)y * a.dpitch + xa];
-          rb = gbl(a.Rd)[(size_t)y * a.dpitch + xb];
-        } else {
-          ra = (double)gbl(a.R)[(size_t)y * a.pitch + xa];
-          rb = (double)gbl(a.R)[(size_t)y * a.pitch + xb];
+        if (dw < 0.0) continue;  // rejected patch
+        const double m = lp.fusion == 2 ? 1.0 : s_m[x - grid_origin(i, a.g.w, P, S)] * mb;
+        double wk = m * dw;
+        if (lp.fusion == 1) {
+          // 1 / max(1, r^2), r = I_r(x + u) - I_l(x): linear warp, indices clamped to the row
+          const double fm = floor(du);
+          const int mm = (int)fm;
+          const double fr = du - fm;
+          const int xa = clampi(x + mm, 0, a.g.w - 1), xb = clampi(x + mm + 1, 0, a.g.w - 1);
+          double ra, rb;
+          if (a.Rd) {
+            ra = gbl(a.Rd)[(size_t)y * a.dpitch + xa];
+            rb = gbl(a.Rd)[(size_t)y * a.dpitch + xb];
+          } else {
+            ra = (double)gbl(a.R)[(size_t)y * a.pitch + xa];
+            rb = (double)gbl(a.R)[(size_t)y * a.pitch + xb];
+          }
+          const double r = (1.0 - fr) * ra + fr * rb - lx;
+          wk = 1.0 / fmax(1.0, r * r);
         }
-        const double r = (1.0 - fr) * ra + fr * rb - lx;
-        wk = 1.0 / fmax(1.0, r * r);
+        z += wk;
+        zu += wk * du;
+        zm += m;
+        zq += m * dw;
+        zv += wk * wk * dv;
       }
-      z += wk;
-      zu += wk * du;
-      zm += m;
-      zq += m * dw;
-      zv += wk * wk * dv;
     }
-  }
-  const size_t idx = (size_t)y * a.g.w + x;
-  double ub, qv;
-  bool valid = z > 0.0;
-  if (valid) {
-    ub = zu / z;
-    qv = zq / zm;
-  } else if (finest) {
-    ub = __builtin_nan("");
-    qv = 0.0;
-  } else if (a.par_ubar) {
-    // hole above the finest level: the parent estimate
-    ub = 2.0 * bilinear(a.par_ubar, a.pw, a.ph, 0.5 * x, 0.5 * y);
-    qv = bilinear(a.par_q, a.pw, a.ph, 0.5 * x, 0.5 * y);
-  } else {
-    ub = 0.0;
-    qv = 0.0;
-  }
-  if (a.zmap) {  // training contexts keep the fusion sums for the backward pass
-    gbl(a.zmap)[idx] = valid ? z : 0.0;
-    gbl(a.smmap)[idx] = zm;
-    if (finest) {
-      gbl(a.ubar_keep)[idx] = ub;
-      gbl(a.qmap_keep)[idx] = qv;
-      if (a.vmap) gbl(a.vmap)[idx] = (valid && lp.variance) ? zv / (z * z) : 0.0;
+    const size_t idx = (size_t)y * a.g.w + x;
+    double ub, qv;
+    bool valid = z > 0.0;
+    if (valid) {
+      ub = zu / z;
+      qv = zq / zm;
+    } else if (finest) {
+      ub = __builtin_nan("");
+      qv = 0.0;
+    } else if (a.par_ubar) {
+      // hole above the finest level: the parent estimate
+      ub = 2.0 * bilinear(a.par_ubar, a.pw, a.ph, 0.5 * x, 0.5 * y);
+      qv = bilinear(a.par_q, a.pw, a.ph, 0.5 * x, 0.5 * y);
+    } else {
+      ub = 0.0;
+      qv = 0.0;
     }
-  }
-  if (!finest) {
-    gbl(a.ubar)[idx] = ub;
-    gbl(a.qmap)[idx] = qv;
-    return;
-  }
-  if (lp.prob_thresh > 0.0f && qv < (double)lp.prob_thresh) valid = false;
-  const float nan = __builtin_nanf("");
-  gbl(a.disparity)[idx] = valid ? (float)(-ub) : nan;
-  if (a.confidence) gbl(a.confidence)[idx] = valid ? (float)qv : 0.0f;
-  if (a.variance) gbl(a.variance)[idx] = (valid && lp.variance) ? (float)(zv / (z * z)) : nan;
+    if (a.zmap) {  // training contexts keep the fusion sums for the backward pass
+      gbl(a.zmap)[idx] = valid ? z : 0.0;
+      gbl(a.smmap)[idx] = zm;
+      if (finest) {
+        gbl(a.ubar_keep)[idx] = ub;
+        gbl(a.qmap_keep)[idx] = qv;
+        if (a.vmap) gbl(a.vmap)[idx] = (valid && lp.variance) ? zv / (z * z) : 0.0;
+      }
+    }
+    if (!finest) {
+      gbl(a.ubar)[idx] = ub;
+      gbl(a.qmap)[idx] = qv;
+      return;
+    }
+    if (lp.prob_thresh > 0.0f && qv < (double)lp.prob_thresh) valid = false;
+    const float nan = __builtin_nanf("");
+    gbl(a.disparity)[idx] = valid ? (float)(-ub) : nan;
+    if (a.confidence) gbl(a.confidence)[idx] = valid ? (float)qv : 0.0f;
+    if (a.variance) gbl(a.variance)[idx] = (valid && lp.variance) ? (float)(zv / (z * z)) : nan;
+  };
+  if (x < a.g.w)
+    for (int rr = 0; rr < kRowsPerLane; ++rr) {
+      const int y = y0 + tid / kFuseTx + rr * (kThreads / kFuseTx);
+      if (y < a.g.h) fuse_pixel(y);
+    }
 }
 
 // Finest level f > 0, per output pixel: bilinear sample of the level-f maps at
@@ -402,10 +410,17 @@ hipError_t launch_prob(const PairLevel* tab, int npairs, int nblocks, const Leve
 
 hipError_t launch_fuse(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  if (lp.inline_prob)
-    hipLaunchKernelGGL(k_fuse<true>, dim3(nblocks), dim3(kFuseTx * kFuseTy), 0, s, tab, npairs, lp);
+  if (lp.fuse_ty != kFuseTyShort && lp.fuse_ty != kFuseTyTall) return hipErrorInvalidValue;
+  const bool tall = lp.fuse_ty == kFuseTyTall;
+  const dim3 threads(fuse_threads(tall ? kFuseTyTall : kFuseTyShort));
+  if (lp.inline_prob && tall)
+    hipLaunchKernelGGL((k_fuse<true, kFuseTyTall>), dim3(nblocks), threads, 0, s, tab, npairs, lp);
+  else if (lp.inline_prob)
+    hipLaunchKernelGGL((k_fuse<true, kFuseTyShort>), dim3(nblocks), threads, 0, s, tab, npairs, lp);
+  else if (tall)
+    hipLaunchKernelGGL((k_fuse<false, kFuseTyTall>), dim3(nblocks), threads, 0, s, tab, npairs, lp);
   else
-    hipLaunchKernelGGL(k_fuse<false>, dim3(nblocks), dim3(kFuseTx * kFuseTy), 0, s, tab, npairs, lp);
+    hipLaunchKernelGGL((k_fuse<false, kFuseTyShort>), dim3(nblocks), threads, 0, s, tab, npairs, lp);
   return hipGetLastError();
 }
 

@@ -61,7 +61,8 @@ __host__ __device__ constexpr uint32_t ones_word(int w, int P) { return valid_by
 // Right-image samples of one row at columns x .. x + 4 NW + 3 as NW + 1 packed
 // words: from the LDS window (aligned dword reads, realigned with
 // v_alignbyte) when it holds every word read, else from global memory with each
-// column clamped to the image (identical values either way).
+// column clamped to the image (identical values either way).  `grow` is the
+// image row, W its width.
 template <int NW>
 BDIS_DEV void fetch_words(uint32_t (&B)[NW + 1], const uint8_t* win, int xs, int rw, const uint8_t* grow, int x,
                           int W) {
@@ -76,16 +77,33 @@ BDIS_DEV void fetch_words(uint32_t (&B)[NW + 1], const uint8_t* win, int xs, int
 #pragma unroll
     for (int w = 0; w <= NW; ++w) B[w] = __builtin_amdgcn_alignbyte(D[w + 1], D[w], sh);
   } else {
-    // rare (samples far from the staged window): one word at a time, so that
-    // few loads and addresses are live at once
+    // samples outside the staged window (patches whose iterations wander off):
+    // aligned dwords of the image row when the row is 4-aligned and the words
+    // lie inside it
     const auto g = gbl(grow);
+    const int x4 = x & ~3;
+    if (x4 >= 0 && x4 + 4 * (NW + 2) <= W && ((uintptr_t)grow & 3) == 0) {
+      const auto gw = reinterpret_cast<const __attribute__((address_space(1))) uint32_t*>(g + x4);
+      const uint32_t sh = (uint32_t)(x & 3);
+      uint32_t D[NW + 2];
 #pragma unroll
-    for (int w = 0; w <= NW; ++w) {
-      uint32_t v = 0;
+      for (int i = 0; i < NW + 2; ++i) D[i] = gw[i];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) v |= (uint32_t)g[clampi(x + 4 * w + b, 0, W - 1)] << (8 * b);
-      B[w] = v;
-      __builtin_amdgcn_sched_barrier(0);  // keep one word's loads in flight at a time
+      for (int w = 0; w <= NW; ++w) B[w] = __builtin_amdgcn_alignbyte(D[w + 1], D[w], sh);
+    } else {
+      // near the image borders: clamped samples, one word (four loads) per
+      // step; the empty asm keeps the address arithmetic inside this branch
+      int xx = x;
+      asm volatile("" : "+v"(xx));
+#pragma unroll 1
+      for (int w = 0; w <= NW; ++w) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) v |= (uint32_t)g[clampi(xx + 4 * w + b, 0, W - 1)] << (8 * b);
+#pragma unroll
+        for (int t = 0; t < NW; ++t) B[t] = B[t + 1];
+        B[NW] = v;
+      }
     }
   }
 }

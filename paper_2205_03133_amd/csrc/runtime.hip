@@ -214,6 +214,7 @@ struct Plan {
   int search_opt[kMaxLevels]{};  // uint8 search configuration per level (lane mapping, workgroup size)
   int up_blocks = 0;             // finest level f > 0: upsampling workgroups (level 0)
   int inline_prob[kMaxLevels]{}; // 1: the fusion computes the patch records (small levels)
+  int fuse_ty[kMaxLevels]{};     // fusion tile height per level
   bool f32 = false;              // float (FP64) path: per-pixel pyramid blocks, fixed search size
   std::vector<PairLevel> tab;
 };
@@ -361,6 +362,14 @@ LevelParams level_params(const bdis_params& p, int n) {
   return lp;
 }
 
+// Level parameters of a launch of level n under plan pl.
+LevelParams plan_level_params(const bdis_params& p, const Plan& pl, int n) {
+  LevelParams lp = level_params(p, n);
+  lp.inline_prob = pl.inline_prob[n];
+  lp.fuse_ty = pl.fuse_ty[n];
+  return lp;
+}
+
 // Tuning key of a level: the search workload shape across the batch.
 std::string level_key(const bdis_params& p, const Plan& pl, int n) {
   long np = 0;
@@ -418,7 +427,7 @@ void assign_offsets(const bdis_params& p, Plan& pl) {
       q.prob0 = pr;
       pr += patches ? (q.g.nx * q.g.ny + kProbThreads - 1) / kProbThreads : 0;
       q.fuse0 = fu;
-      fu += patches ? ((q.g.w + kFuseTx - 1) / kFuseTx) * ((q.g.h + kFuseTy - 1) / kFuseTy) : 0;
+      fu += patches ? ((q.g.w + kFuseTx - 1) / kFuseTx) * ((q.g.h + pl.fuse_ty[n] - 1) / pl.fuse_ty[n]) : 0;
     }
     pl.pyr_blocks[n] = pyr;
     pl.search_blocks[n] = se;
@@ -580,9 +589,14 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
     pl.search_opt[n] = it != c->tuned.end() ? it->second : default_search_opt(pl, n, p.patch, p.stride);
   }
   for (int n = 0; n < pl.max_levels; ++n) {
-    long np = 0;
-    for (int e = 0; e < pl.tab_count[n]; ++e) np += (long)pl.tab[pl.tab_first[n] + e].g.nx * pl.tab[pl.tab_first[n] + e].g.ny;
+    long np = 0, npx = 0;
+    for (int e = 0; e < pl.tab_count[n]; ++e) {
+      const LevelGeom& g = pl.tab[pl.tab_first[n] + e].g;
+      np += (long)g.nx * g.ny;
+      npx += (long)g.w * g.h;
+    }
     pl.inline_prob[n] = np <= kInlineProbPatches ? 1 : 0;
+    pl.fuse_ty[n] = (!flow && npx >= kFuseTallPixels) ? kFuseTyTall : kFuseTyShort;
   }
   assign_offsets(p, pl);
   *out = std::move(pl);
@@ -640,8 +654,7 @@ bdis_status launch_all(bdis_ctx* c, const Plan& pl, hipStream_t st) {
   for (int n = pl.max_levels - 1; n >= p.finest_level; --n) {
     const PairLevel* tab = c->tab_dev + pl.tab_first[n];
     const int cnt = pl.tab_count[n];
-    LevelParams lp = level_params(p, n);
-    lp.inline_prob = pl.inline_prob[n];
+    const LevelParams lp = plan_level_params(p, pl, n);
     long tmk = timing_start(c, BDIS_K_SEARCH, st);
     e = launch_search(tab, cnt, pl.search_blocks[n], lp, pl.search_opt[n], st);
     timing_stop(c, tmk, st);
@@ -751,8 +764,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
           e = launch_pyramid(c->tab_dev + trial.tab_first[n], trial.tab_count[n], trial.pyr_blocks[n], st);
         for (int n = trial.max_levels - 1; n >= p.finest_level && e == hipSuccess; --n) {
           const PairLevel* tab = c->tab_dev + trial.tab_first[n];
-          LevelParams lp = level_params(p, n);
-          lp.inline_prob = trial.inline_prob[n];
+          const LevelParams lp = plan_level_params(p, trial, n);
           (void)hipEventRecord(ev[2 * n], st);
           e = launch_search(tab, trial.tab_count[n], trial.search_blocks[n], lp, trial.search_opt[n], st);
           (void)hipEventRecord(ev[2 * n + 1], st);
@@ -859,8 +871,7 @@ bdis_status run_pairs_f32(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipSt
   for (int n = pl.max_levels - 1; n >= p.finest_level; --n) {
     const PairLevel* tab = c->tab_dev + pl.tab_first[n];
     const int cnt = pl.tab_count[n];
-    LevelParams lp = level_params(p, n);
-    lp.inline_prob = pl.inline_prob[n];
+    const LevelParams lp = plan_level_params(p, pl, n);
     long tmk = timing_start(c, BDIS_K_SEARCH, st);
     e = launch_search_f64(tab, cnt, pl.search_blocks[n], lp, st);
     timing_stop(c, tmk, st);
@@ -904,7 +915,7 @@ bdis_status run_flow(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipStream_
   }
   for (int n = pl.max_levels - 1; n >= 0; --n) {
     const PairLevel* tab = c->tab_dev + pl.tab_first[n];
-    const LevelParams lp = level_params(p, n);
+    const LevelParams lp = plan_level_params(p, pl, n);
     long tmk = timing_start(c, BDIS_K_SEARCH, st);
     e = launch_flow_search(tab, pl.tab_count[n], pl.search_blocks[n], lp, st);
     timing_stop(c, tmk, st);
