@@ -164,7 +164,10 @@ struct LevelParams {
 };
 
 // Tile shapes of the flattened launches.
-constexpr int kPyrTx = 64, kPyrTy = 4;      // pyramid: 64 x 4 output pixels per workgroup
+// Pyramid tiles: 64 x 4 output pixels (small levels) or 120 x 16 (levels of at
+// least kPyrTallPixels pixels over the batch).
+constexpr int kPyrSmallTx = 64, kPyrSmallTy = 4, kPyrTallTx = 120, kPyrTallTy = 16;
+constexpr long kPyrTallPixels = 1 << 18;
 constexpr int kProbThreads = 256;           // probability: patches per workgroup
 // Levels with at most this many patches (over the batch) have their level
 // scalars (sigma_r, tau) and patch records computed inside the fusion (no
@@ -223,7 +226,7 @@ __host__ __device__ inline int search_lds_bytes(int P, int opt, int S) {
 }
 
 // Launchers over a device table of `npairs` entries (each returns the launch status).
-hipError_t launch_pyramid(const PairLevel* tab, int npairs, int nblocks, hipStream_t s);
+hipError_t launch_pyramid(const PairLevel* tab, int npairs, int nblocks, bool tall, hipStream_t s);
 hipError_t launch_search(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,
                          int opt, hipStream_t s);
 hipError_t launch_reduce(const PairLevel* tab, int npairs, const LevelParams& lp, hipStream_t s);

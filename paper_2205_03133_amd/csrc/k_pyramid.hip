@@ -3,34 +3,48 @@
 // borders, sampled at even pixels, integer rounding (sum + 128) >> 8: exact
 // uint8 arithmetic, bit-identical to any correct implementation.
 //
-// One workgroup computes a 64 x 4 tile of level n for both views of one pair:
-// the 11 source rows it needs are filtered horizontally into LDS (integer),
-// then the vertical pass reads them back.  The kernel moves ~1.33x the
-// level-(n-1) bytes: HBM/latency bound and small next to the patch search.
+// Two forms, chosen per level by its pixel count over the batch:
+// k_pyr_small (small levels, latency-bound): 64 x 4 output tiles, each lane
+//   gathers its five source columns of 11 source rows and filters them
+//   horizontally into LDS, then vertically: few dependent steps.
+// k_pyr_tall (large levels, bandwidth-bound): 120 x 16 output tiles, in three
+//   passes:
+//   1. the 2 x 16 + 3 source rows of the tile (62 words of 4 bytes each) are
+//      staged in LDS, one 4-byte load per word, all of a lane's loads in
+//      flight at once; out-of-image columns of border tiles are then filled
+//      from the staged in-image bytes (reflect-101);
+//   2. horizontal pass: each lane filters four output columns of a row from
+//      four LDS words, a 4-tap v_dot4_u32_u8 (taps 1 4 6 4) plus the fifth tap,
+//      and writes the four 16-bit sums as one 8-byte LDS word;
+//   3. vertical pass: each lane combines five such rows into four output
+//      bytes and writes them as one dword (bytes at a ragged right edge).
+//   Every source byte is read from HBM about once (rows shared by
+//   neighbouring tiles come from L2), every output byte written once.
 #include "bdis_internal.h"
 
 namespace bdis {
 
 namespace {
 
-constexpr int kSrcRows = 2 * kPyrTy + 3;  // source rows touched by kPyrTy output rows
+constexpr int kSmallRows = 2 * kPyrSmallTy + 3;  // source rows touched by kPyrSmallTy output rows
 
-__global__ __launch_bounds__(kPyrTx* kPyrTy) void k_pyr_u8(const PairLevel* tab, int npairs) {
-  __shared__ int hL[kSrcRows][kPyrTx];
-  __shared__ int hR[kSrcRows][kPyrTx];
+__global__ __launch_bounds__(kPyrSmallTx* kPyrSmallTy) void k_pyr_small(const PairLevel* tab, int npairs) {
+  __shared__ int hL[kSmallRows][kPyrSmallTx];
+  __shared__ int hR[kSmallRows][kPyrSmallTx];
   const int b = xcd_block();
   const PairLevel& a = tab[find_pair<0>(tab, npairs, b)];
-  const int tiles_x = (a.g.w + kPyrTx - 1) / kPyrTx;
+  const int tiles_x = (a.g.w + kPyrSmallTx - 1) / kPyrSmallTx;
   const int t = b - a.pyr0;
-  const int tx = threadIdx.x % kPyrTx;
-  const int ty = threadIdx.x / kPyrTx;
-  const int x = (t % tiles_x) * kPyrTx + tx;    // output column
-  const int y0 = (t / tiles_x) * kPyrTy;        // first output row of the tile
+  const int tx = threadIdx.x % kPyrSmallTx;
+  const int ty = threadIdx.x / kPyrSmallTx;
+  const int x = (t % tiles_x) * kPyrSmallTx + tx;  // output column
+  const int y0 = (t / tiles_x) * kPyrSmallTy;      // first output row of the tile
   const int dw = a.g.w, dh = a.g.h;
-  const int xs = x < dw ? x : dw - 1;           // idle lanes read valid columns
-  const int cx[5] = {reflect101(2 * xs - 2, a.sw), reflect101(2 * xs - 1, a.sw), reflect101(2 * xs, a.sw),
-                     reflect101(2 * xs + 1, a.sw), reflect101(2 * xs + 2, a.sw)};
-  for (int r = ty; r < kSrcRows; r += kPyrTy) {
+  const int xs = x < dw ? x : dw - 1;  // idle lanes read valid columns
+  int cx[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) cx[k] = reflect101(2 * xs - 2 + k, a.sw);
+  for (int r = ty; r < kSmallRows; r += kPyrSmallTy) {
     int sy = 2 * y0 - 2 + r;
     // rows beyond sh + 1 feed only idle output rows: keep them in range
     sy = sy > a.sh + 1 ? a.sh - 1 : reflect101(sy, a.sh);
@@ -42,18 +56,179 @@ __global__ __launch_bounds__(kPyrTx* kPyrTy) void k_pyr_u8(const PairLevel* tab,
   __syncthreads();
   const int y = y0 + ty;
   if (x >= dw || y >= dh) return;
-  const int q = 2 * ty;  // local row of source row 2*y-2
+  const int q = 2 * ty;  // local row of source row 2y - 2
   const int sl = hL[q][tx] + 4 * hL[q + 1][tx] + 6 * hL[q + 2][tx] + 4 * hL[q + 3][tx] + hL[q + 4][tx];
   const int sr = hR[q][tx] + 4 * hR[q + 1][tx] + 6 * hR[q + 2][tx] + 4 * hR[q + 3][tx] + hR[q + 4][tx];
   gbl(a.dstL)[(size_t)y * a.pitch + x] = (uint8_t)((sl + 128) >> 8);
   gbl(a.dstR)[(size_t)y * a.pitch + x] = (uint8_t)((sr + 128) >> 8);
 }
 
+constexpr int kPyrThreads = 256;
+constexpr int kSrcRows = 2 * kPyrTallTy + 3;         // source rows 2 y0 - 2 .. 2 y0 + 2 kPyrTallTy
+constexpr int kSrcWords = (2 * kPyrTallTx + 8) / 4;  // source columns 2 x0 - 4 .. 2 x0 + 2 kPyrTallTx + 3
+static_assert(kSrcWords <= 64, "one staged word per lane");
+constexpr int kQuads = kPyrTallTx / 4;               // output column quads per row
+static_assert(kPyrTallTx % 4 == 0, "four output columns per lane");
+
+__global__ __launch_bounds__(kPyrThreads) void k_pyr_tall(const PairLevel* tab, int npairs) {
+  __shared__ uint32_t s_src[2][kSrcRows][kSrcWords];
+  __shared__ uint2 s_h[2][kSrcRows][kQuads];  // four 16-bit horizontal sums per entry
+  const int b = xcd_block();
+  const PairLevel& a = tab[find_pair<0>(tab, npairs, b)];
+  const int tiles_x = (a.g.w + kPyrTallTx - 1) / kPyrTallTx;
+  const int t = b - a.pyr0;
+  const int x0 = (t % tiles_x) * kPyrTallTx;  // first output column of the tile
+  const int y0 = (t / tiles_x) * kPyrTallTy;  // first output row of the tile
+  const int dw = a.g.w, dh = a.g.h, sw = a.sw, sh = a.sh;
+  const int cs = 2 * x0 - 4;              // source column of staged byte 0 (a multiple of 4)
+  const int tid = threadIdx.x;
+
+  // valid outputs of the tile: columns x0 .. x1, rows y0 .. y1; they read
+  // staged words 0 .. kmax and source rows 0 .. rmax
+  const int x1 = min(x0 + kPyrTallTx, dw) - 1, y1 = min(y0 + kPyrTallTy, dh) - 1;
+  const int nq = (x1 - x0) / 4 + 1;                 // output column quads
+  const int kmax = min((2 * x1 + 2 - cs) / 4, kSrcWords - 1);
+  const int rmax = 2 * (y1 - y0) + 4;
+
+  // ---- 1. stage the source rows (both views).  Wave w stages rows w, w + 4,
+  // ...; lane l the word l of each.  Every lane first issues all its loads
+  // (4-byte loads, the column clamped into the row) and then stores them; the
+  // bytes of words that reach past an image border are then rewritten from the
+  // staged in-image bytes with reflect-101 columns.
+  constexpr int kWaves = kPyrThreads / 64;
+  constexpr int kRowSlots = (kSrcRows + kWaves - 1) / kWaves;
+  const int wave = tid / 64, lane = tid % 64;
+  const int kl = min(lane, kSrcWords - 1);
+  const int c = cs + 4 * kl;  // first source column of this lane's word
+  auto src_row = [&](int v, int r) {
+    int sy = 2 * y0 - 2 + r;
+    // rows beyond sh + 1 feed only output rows past the level: keep them in range
+    sy = sy > sh + 1 ? sh - 1 : reflect101(sy, sh);
+    return (v ? a.srcR : a.srcL) + (size_t)sy * a.spitch;
+  };
+  const bool stage = lane <= kmax;
+  if (sw >= 4) {
+    // 4-byte loads at any byte address (global memory allows unaligned access)
+    const int cc = clampi(c, 0, sw - 4);
+    uint32_t wv[2][kRowSlots];
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int i = 0; i < kRowSlots; ++i) {
+        const int r = min(wave + kWaves * i, kSrcRows - 1);
+        __builtin_memcpy(&wv[v][i], src_row(v, r) + cc, 4);
+      }
+    // a word that starts left of the row or ends past it keeps the loaded bytes
+    // of its in-image columns at their place (the rest is rewritten below)
+    const int shift = c >= 0 ? 8 * min(c - cc, 3) : 0;
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int i = 0; i < kRowSlots; ++i) {
+        const int r = wave + kWaves * i;
+        if (r < kSrcRows && r <= rmax && stage) s_src[v][r][lane] = wv[v][i] >> shift;
+      }
+  } else {
+    for (int v = 0; v < 2; ++v)
+      for (int r = wave; r < kSrcRows && r <= rmax; r += kWaves)
+        if (stage) {
+          const auto g = gbl(src_row(v, r));
+          uint32_t word = 0;
+          for (int bb = 0; bb < 4; ++bb) word |= (uint32_t)g[clampi(c + bb, 0, sw - 1)] << (8 * bb);
+          s_src[v][r][lane] = word;
+        }
+  }
+  __syncthreads();
+  // out-of-image columns of border tiles: reflect-101 into staged in-image bytes
+  // (every needed target column lies in [max(cs, 0), sw - 1]); the few border
+  // lanes read all their target bytes first, then rewrite their words
+  if (cs < 0 || cs + 4 * (kmax + 1) > sw) {
+    if (stage && (c < 0 || c + 3 >= sw)) {
+      const uint8_t* sb = reinterpret_cast<const uint8_t*>(&s_src[0][0][0]);
+      int tgt[4];
+      uint32_t keep = 0;  // byte mask of the in-image columns of the word
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        const int col = c + bb;
+        if (col >= 0 && col < sw) keep |= 0xffu << (8 * bb);
+        tgt[bb] = clampi(reflect101(col, sw), max(cs, 0), min(sw - 1, cs + 4 * kSrcWords - 1)) - cs;
+      }
+      uint32_t fixed[2][kRowSlots];
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int i = 0; i < kRowSlots; ++i) {
+          const int r = min(wave + kWaves * i, kSrcRows - 1);
+          const uint8_t* row = sb + ((size_t)v * kSrcRows + r) * (kSrcWords * 4);
+          uint32_t word = 0;
+#pragma unroll
+          for (int bb = 0; bb < 4; ++bb) word |= (uint32_t)row[tgt[bb]] << (8 * bb);
+          fixed[v][i] = (s_src[v][r][lane] & keep) | (word & ~keep);
+        }
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int i = 0; i < kRowSlots; ++i) {
+          const int r = wave + kWaves * i;
+          if (r < kSrcRows && r <= rmax) s_src[v][r][lane] = fixed[v][i];
+        }
+    }
+    __syncthreads();
+  }
+
+  // ---- 2. horizontal pass: output columns 4q .. 4q+3 of the tile need staged
+  // bytes 8q + 2 .. 8q + 12 (words 2q .. 2q+3)
+  constexpr uint32_t kTaps = 0x04060401u;  // bytes 1, 4, 6, 4
+  const int nr = rmax + 1;
+  for (int e = tid; e < 2 * nr * nq; e += kPyrThreads) {
+    const int vr = div_small(e, nq), q = e - vr * nq;
+    const int v = vr >= nr ? 1 : 0, r = vr - v * nr;
+    const uint32_t d0 = s_src[v][r][2 * q], d1 = s_src[v][r][2 * q + 1];
+    const uint32_t d2 = s_src[v][r][2 * q + 2], d3 = s_src[v][r][2 * q + 3];
+    const uint32_t h0 = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(d1, d0, 2u), kTaps, (d1 >> 16) & 255u, false);
+    const uint32_t h1 = __builtin_amdgcn_udot4(d1, kTaps, d2 & 255u, false);
+    const uint32_t h2 = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(d2, d1, 2u), kTaps, (d2 >> 16) & 255u, false);
+    const uint32_t h3 = __builtin_amdgcn_udot4(d2, kTaps, d3 & 255u, false);
+    s_h[v][r][q] = make_uint2(h0 | (h1 << 16), h2 | (h3 << 16));
+  }
+  __syncthreads();
+
+  // ---- 3. vertical pass: output row y0 + yl from local rows 2 yl .. 2 yl + 4
+  const int ny = y1 - y0 + 1;
+  for (int e = tid; e < 2 * ny * nq; e += kPyrThreads) {
+    const int vy = div_small(e, nq), q = e - vy * nq;
+    const int v = vy >= ny ? 1 : 0, yl = vy - v * ny;
+    const int y = y0 + yl, x = x0 + 4 * q;
+    uint32_t acc[4] = {0u, 0u, 0u, 0u};
+    constexpr uint32_t kW[5] = {1u, 4u, 6u, 4u, 1u};
+#pragma unroll
+    for (int tr = 0; tr < 5; ++tr) {
+      const uint2 hv = s_h[v][2 * yl + tr][q];
+      acc[0] += kW[tr] * (hv.x & 0xffffu);
+      acc[1] += kW[tr] * (hv.x >> 16);
+      acc[2] += kW[tr] * (hv.y & 0xffffu);
+      acc[3] += kW[tr] * (hv.y >> 16);
+    }
+    uint32_t out = 0;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) out |= ((acc[kk] + 128u) >> 8) << (8 * kk);
+    uint8_t* row = (v ? a.dstR : a.dstL) + (size_t)y * a.pitch;
+    if (x + 3 < dw && ((uintptr_t)row & 3) == 0) {
+      gbl(reinterpret_cast<uint32_t*>(row + x))[0] = out;
+    } else {
+      for (int kk = 0; kk < 4 && x + kk < dw; ++kk) gbl(row)[x + kk] = (uint8_t)(out >> (8 * kk));
+    }
+  }
+}
+
 }  // namespace
 
-hipError_t launch_pyramid(const PairLevel* tab, int npairs, int nblocks, hipStream_t s) {
+hipError_t launch_pyramid(const PairLevel* tab, int npairs, int nblocks, bool tall, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pyr_u8, dim3(nblocks), dim3(kPyrTx * kPyrTy), 0, s, tab, npairs);
+  if (tall)
+    hipLaunchKernelGGL(k_pyr_tall, dim3(nblocks), dim3(kPyrThreads), 0, s, tab, npairs);
+  else
+    hipLaunchKernelGGL(k_pyr_small, dim3(nblocks), dim3(kPyrSmallTx * kPyrSmallTy), 0, s, tab, npairs);
   return hipGetLastError();
 }
 

@@ -215,6 +215,7 @@ struct Plan {
   int up_blocks = 0;             // finest level f > 0: upsampling workgroups (level 0)
   int inline_prob[kMaxLevels]{}; // 1: the fusion computes the patch records (small levels)
   int fuse_ty[kMaxLevels]{};     // fusion tile height per level
+  bool pyr_tall[kMaxLevels]{};   // pyramid level built with the large-tile kernel
   bool f32 = false;              // float (FP64) path: per-pixel pyramid blocks, fixed search size
   std::vector<PairLevel> tab;
 };
@@ -420,7 +421,9 @@ void assign_offsets(const bdis_params& p, Plan& pl) {
       if (pl.f32)  // one lane per pixel, every level (conversion at level 0; adjoint launches)
         pyr += (q.g.w * q.g.h + kPixThreads - 1) / kPixThreads;
       else
-        pyr += n >= 1 ? ((q.g.w + kPyrTx - 1) / kPyrTx) * ((q.g.h + kPyrTy - 1) / kPyrTy) : 0;
+        pyr += n >= 1 ? (pl.pyr_tall[n] ? ((q.g.w + kPyrTallTx - 1) / kPyrTallTx) * ((q.g.h + kPyrTallTy - 1) / kPyrTallTy)
+                                         : ((q.g.w + kPyrSmallTx - 1) / kPyrSmallTx) * ((q.g.h + kPyrSmallTy - 1) / kPyrSmallTy))
+                      : 0;
       q.search_nbx = patches ? search_nbx(q.g, search_npb(p.patch, opt, pl.f32 || pl.flow)) : 0;
       q.search0 = se;
       se += patches ? q.search_nbx * q.g.ny : 0;
@@ -597,6 +600,7 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
     }
     pl.inline_prob[n] = np <= kInlineProbPatches ? 1 : 0;
     pl.fuse_ty[n] = (!flow && npx >= kFuseTallPixels) ? kFuseTyTall : kFuseTyShort;
+    pl.pyr_tall[n] = npx >= kPyrTallPixels;
   }
   assign_offsets(p, pl);
   *out = std::move(pl);
@@ -647,7 +651,7 @@ bdis_status launch_all(bdis_ctx* c, const Plan& pl, hipStream_t st) {
   hipError_t e;
   for (int n = 1; n < pl.max_levels; ++n) {
     const long tmk = timing_start(c, BDIS_K_PYRAMID, st);
-    e = launch_pyramid(c->tab_dev + pl.tab_first[n], pl.tab_count[n], pl.pyr_blocks[n], st);
+    e = launch_pyramid(c->tab_dev + pl.tab_first[n], pl.tab_count[n], pl.pyr_blocks[n], pl.pyr_tall[n], st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "pyramid launch");
   }
@@ -694,6 +698,8 @@ std::string graph_key(const bdis_params& p, const Plan& pl) {
   add(pl.search_opt, sizeof pl.search_opt);
   add(&pl.up_blocks, sizeof pl.up_blocks);
   add(pl.inline_prob, sizeof pl.inline_prob);
+  add(pl.fuse_ty, sizeof pl.fuse_ty);
+  add(pl.pyr_tall, sizeof pl.pyr_tall);
   add(&pl.max_levels, sizeof pl.max_levels);
   return k;
 }
@@ -761,7 +767,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
       for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
         // a full pass with each level's search launch bracketed by events
         for (int n = 1; n < trial.max_levels && e == hipSuccess; ++n)
-          e = launch_pyramid(c->tab_dev + trial.tab_first[n], trial.tab_count[n], trial.pyr_blocks[n], st);
+          e = launch_pyramid(c->tab_dev + trial.tab_first[n], trial.tab_count[n], trial.pyr_blocks[n], trial.pyr_tall[n], st);
         for (int n = trial.max_levels - 1; n >= p.finest_level && e == hipSuccess; --n) {
           const PairLevel* tab = c->tab_dev + trial.tab_first[n];
           const LevelParams lp = plan_level_params(p, trial, n);
@@ -909,7 +915,7 @@ bdis_status run_flow(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipStream_
   hipError_t e;
   for (int n = 1; n < pl.max_levels; ++n) {
     const long tmk = timing_start(c, BDIS_K_PYRAMID, st);
-    e = launch_pyramid(c->tab_dev + pl.tab_first[n], pl.tab_count[n], pl.pyr_blocks[n], st);
+    e = launch_pyramid(c->tab_dev + pl.tab_first[n], pl.tab_count[n], pl.pyr_blocks[n], pl.pyr_tall[n], st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "pyramid launch");
   }

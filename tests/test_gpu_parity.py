@@ -52,7 +52,8 @@ def _report(name, st):
           f"mask_mismatch={st['mask_mismatch']} n={st['n']}", flush=True)
 
 
-@pytest.mark.parametrize("shape,L", [((217, 333), 4), ((64, 64), 3), ((101, 37), 3)])
+@pytest.mark.parametrize("shape,L", [((217, 333), 4), ((64, 64), 3), ((101, 37), 3), ((480, 640), 5),
+                                     ((270, 481), 4), ((1201, 1803), 4), ((1080, 1920), 3)])
 def test_pyramid_bit_exact(B, oracle, shape, L):
     rng = np.random.default_rng(sum(shape))
     left = rng.integers(0, 256, shape, dtype=np.uint8)
