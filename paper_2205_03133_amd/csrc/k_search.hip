@@ -52,6 +52,11 @@ BDIS_DEV double exact_ab_cd(int a, int b, int c, int d) {
 // (four exact 8-bit products per instruction).
 BDIS_DEV uint32_t dot4(uint32_t a, uint32_t b, uint32_t acc) { return __builtin_amdgcn_udot4(a, b, acc, false); }
 
+// Two 16-bit lanes in one register (packed integer v_pk_* arithmetic).
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+BDIS_DEV u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+BDIS_DEV uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+
 // Word w of a P-sample vector: mask of its valid bytes, and 1 in each valid byte.
 __host__ __device__ constexpr uint32_t valid_bytes(int w, int P) {
   return P - 4 * w >= 4 ? 0xffffffffu : ((1u << (8 * (P - 4 * w))) - 1u);
@@ -231,65 +236,82 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
     rlive[k] = kAllRows || r0 + k < P;
     rrow[k] = kAllRows ? r0 + k : min(r0 + k, P - 1);
   }
-  // packed rows: T, and Gx + 1024 (0..2044) split into its high (0..7) and low
+  // packed rows: T, and Gx + 1024 (4..2044) split into its high (0..7) and low
   // bytes, so sum Gx R = 256 (Gh . R) + (Gl . R) - 1024 sum R; padding bytes 0.
-  // The rows are built one at a time from a rolling window of three tile rows.
+  // Built from realigned LDS words of three tile rows at a time: the vertical
+  // [1 2 1] sums S as 16-bit pairs (v_pk_add_u16), Gx + 1024 = S[c + 2] + 1024
+  // - S[c] per pixel pair, its bytes gathered with v_perm; the row sums by dot4.
   uint32_t Tw[R][NW], Ghw[R][NW], Glw[R][NW];
   int sG = 0, sT = 0, sGG = 0, sGT = 0, sTT = 0;
   {
-    const uint8_t* base = s_left + (ox - 1 - xa);
-    auto tile_row = [&](int k, int (&v)[P + 2]) {
+    constexpr int NPAIR = 2 * (NW + 1);  // 16-bit pairs of bytes 0 .. 4 NW + 3
+    const int o0 = ox - 1 - xa;          // byte of column ox - 1 within a tile row
+    auto tile_words = [&](int k, uint32_t (&Bw)[NW + 1], u16x2 (&Pr)[NPAIR]) {
       const int ty = kAllRows ? r0 + k : min(r0 + k, P + 1);  // tile row = image row oy - 1 + ty
+      const int o = ty * LTW + o0;
+      const uint32_t* wp = s_left32 + (o >> 2);
+      const uint32_t sh = (uint32_t)(o & 3);
+      uint32_t D[NW + 2];
 #pragma unroll
-      for (int c = 0; c < P + 2; ++c) v[c] = base[ty * LTW + c];
+      for (int q2 = 0; q2 < NW + 2; ++q2) D[q2] = wp[q2];
+#pragma unroll
+      for (int w = 0; w <= NW; ++w) {
+        Bw[w] = __builtin_amdgcn_alignbyte(D[w + 1], D[w], sh);
+        Pr[2 * w] = as_u16x2(__builtin_amdgcn_perm(0u, Bw[w], 0x0c010c00u));      // bytes 0, 1
+        Pr[2 * w + 1] = as_u16x2(__builtin_amdgcn_perm(0u, Bw[w], 0x0c030c02u));  // bytes 2, 3
+      }
     };
-    int Lu[P + 2], Lc[P + 2], Ld[P + 2];
-    tile_row(0, Lu);
-    tile_row(1, Lc);
+    uint32_t Bu[NW + 1], Bc[NW + 1], Bd[NW + 1];
+    u16x2 Pu[NPAIR], Pc[NPAIR], Pd[NPAIR];
+    tile_words(0, Bu, Pu);
+    tile_words(1, Bc, Pc);
+    const u16x2 k1024 = {1024, 1024};
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      tile_row(k + 2, Ld);
-      int T[P], Gx[P];
-      int a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
+      tile_words(k + 2, Bd, Pd);
+      u16x2 Sv[NPAIR];
 #pragma unroll
-      for (int c = 0; c < P; ++c) {
-        T[c] = Lc[c + 1];
-        Gx[c] = (Lu[c + 2] - Lu[c]) + 2 * (Lc[c + 2] - Lc[c]) + (Ld[c + 2] - Ld[c]);
-        a0 += Gx[c];
-        a1 += T[c];
-        a2 += mul24(Gx[c], Gx[c]);
-        a3 += mul24(Gx[c], T[c]);
-        a4 += mul24(T[c], T[c]);
-      }
+      for (int p = 0; p < NPAIR; ++p) Sv[p] = Pu[p] + Pd[p] + Pc[p] + Pc[p];
+      uint32_t t1 = 0, t4 = 0, gh = 0, gl = 0, hh = 0, hl = 0, ll = 0, ht = 0, lt = 0;
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
-        uint32_t tw = 0, hw = 0, lw = 0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int c = 4 * w + b;
-          if (c < P) {
-            const uint32_t gp = (uint32_t)(Gx[c] + 1024);
-            tw |= (uint32_t)T[c] << (8 * b);
-            hw |= (gp >> 8) << (8 * b);
-            lw |= (gp & 255u) << (8 * b);
-          }
-        }
+        // T: columns ox + 4w .. ox + 4w + 3 = bytes 4w + 1 .. 4w + 4 of the centre row
+        const uint32_t tw = __builtin_amdgcn_alignbyte(Bc[w + 1], Bc[w], 1u) & valid_bytes(w, P);
+        const uint32_t ga = as_u32((Sv[2 * w + 1] + k1024) - Sv[2 * w]);      // pixels 4w, 4w + 1
+        const uint32_t gb = as_u32((Sv[2 * w + 2] + k1024) - Sv[2 * w + 1]);  // pixels 4w + 2, 4w + 3
+        const uint32_t lw = __builtin_amdgcn_perm(gb, ga, 0x06040200u) & valid_bytes(w, P);
+        const uint32_t hw = __builtin_amdgcn_perm(gb, ga, 0x07050301u) & valid_bytes(w, P);
         Tw[k][w] = tw;
         Ghw[k][w] = hw;
         Glw[k][w] = lw;
+        t1 = dot4(tw, 0x01010101u, t1);
+        t4 = dot4(tw, tw, t4);
+        gh = dot4(hw, 0x01010101u, gh);
+        gl = dot4(lw, 0x01010101u, gl);
+        hh = dot4(hw, hw, hh);
+        hl = dot4(hw, lw, hl);
+        ll = dot4(lw, lw, ll);
+        ht = dot4(hw, tw, ht);
+        lt = dot4(lw, tw, lt);
       }
       if (rlive[k]) {
-        sG += a0;
-        sT += a1;
-        sGG += a2;
-        sGT += a3;
-        sTT += a4;
+        // with g = Gx + 1024 = 256 Gh + Gl: sum Gx = sum g - 1024 P,
+        // sum Gx^2 = sum g^2 - 2048 sum g + 1024^2 P, sum Gx T = sum g T - 1024 sum T
+        const int sg = 256 * (int)gh + (int)gl;
+        const int sgg = 65536 * (int)hh + 512 * (int)hl + (int)ll;
+        sG += sg - 1024 * P;
+        sT += (int)t1;
+        sGG += sgg - 2048 * sg + 1048576 * P;
+        sGT += 256 * (int)ht + (int)lt - 1024 * (int)t1;
+        sTT += (int)t4;
       }
 #pragma unroll
-      for (int c = 0; c < P + 2; ++c) {
-        Lu[c] = Lc[c];
-        Lc[c] = Ld[c];
+      for (int p = 0; p < NPAIR; ++p) {
+        Pu[p] = Pc[p];
+        Pc[p] = Pd[p];
       }
+#pragma unroll
+      for (int w = 0; w <= NW; ++w) Bc[w] = Bd[w];
     }
   }
   const int sT_lane = sT, sTT_lane = sTT;  // this lane's rows (the window sums below are per lane)
