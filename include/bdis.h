@@ -33,7 +33,11 @@
  *    and synchronises it, then records the launch
  *    sequence as a graph; a job table larger than any before synchronises the
  *    device before it is reallocated.  Environment: BDIS_TUNE=0 skips the
- *    timing (default configuration), BDIS_GRAPH=0 launches eagerly without graphs.
+ *    timing (default configuration), BDIS_GRAPH=0 launches eagerly without
+ *    graphs, BDIS_SEARCH_CONFIG=k (read by bdis_create; k = lane mapping * 4 +
+ *    workgroup-size index into 64, 128, 256, 512) uses search configuration k
+ *    on every level without timing (bdis_create fails with BDIS_E_ARG for an
+ *    invalid k).
  *  - Errors are returned as bdis_status; the library never aborts.  The text
  *    of the last error of a context is available from bdis_last_error.
  *  - A context is not thread-safe: calls on one context must come from one

@@ -257,6 +257,7 @@ struct bdis_ctx {
   hipStream_t capture_stream = nullptr;
   std::map<std::string, GraphEntry> graphs;
   std::map<std::string, int> tuned;  // level shape key -> uint8 search configuration (option index)
+  int forced_opt = -1;               // BDIS_SEARCH_CONFIG: one configuration for every level, no tuning
   int use_graph = 1;
   bool train = false;                // created with BDIS_TRAIN
   std::vector<PairSpec> last_f32;    // pairs of the last float-path call (backward state)
@@ -590,6 +591,7 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
     }
     auto it = c->tuned.find(level_key(p, pl, n));
     pl.search_opt[n] = it != c->tuned.end() ? it->second : default_search_opt(pl, n, p.patch, p.stride);
+    if (c->forced_opt >= 0) pl.search_opt[n] = c->forced_opt;
   }
   for (int n = 0; n < pl.max_levels; ++n) {
     long np = 0, npx = 0;
@@ -739,7 +741,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
     if (pl.tab_count[n] && !c->tuned.count(level_key(p, pl, n))) need = true;
   if (!need) return BDIS_OK;
   const char* env = std::getenv("BDIS_TUNE");
-  const bool enabled = !(env && std::strcmp(env, "0") == 0);
+  const bool enabled = !(env && std::strcmp(env, "0") == 0) && c->forced_opt < 0;
   float best_ms[kMaxLevels];
   int best_t[kMaxLevels];
   for (int n = 0; n < kMaxLevels; ++n) {
@@ -1036,6 +1038,17 @@ bdis_status bdis_create(bdis_ctx** out, const bdis_params* p, int max_w, int max
   c->train = train;
   const char* g = std::getenv("BDIS_GRAPH");
   c->use_graph = !(g && std::strcmp(g, "0") == 0);
+  if (const char* so = std::getenv("BDIS_SEARCH_CONFIG")) {
+    char* end = nullptr;
+    const long v = std::strtol(so, &end, 10);
+    if (end == so || *end != '\0' || v < 0 || v >= kNumSearchOptions ||
+        search_lds_bytes(p->patch, (int)v, p->stride) > kSearchMaxLds) {
+      delete c;
+      return fail(nullptr, BDIS_E_ARG, "BDIS_SEARCH_CONFIG=%s: not a search configuration 0..%d for this patch and stride",
+                  so, kNumSearchOptions - 1);
+    }
+    c->forced_opt = (int)v;
+  }
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) {
     delete c;

@@ -458,3 +458,27 @@ def test_graph_replays_match_eager(B, monkeypatch):
         torch.cuda.synchronize()
     eager.close()
     graph.close()
+
+
+@pytest.mark.parametrize("P", [8, 12])
+def test_every_search_configuration(B, oracle, monkeypatch, P):
+    """Each lane mapping and workgroup size of the search (forced with
+    BDIS_SEARCH_CONFIG instead of tuned) against the oracle."""
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    left, right, _, _ = make_pair(2, 0)
+    kw = dict(method_params(2))
+    if P == 12:
+        kw.update(patch=12, stride=4, levels=4)
+    p = B.params(**kw)
+    r = oracle.compute(left, right, oracle_params(oracle, p), trace=True)
+    for opt in range(12):
+        monkeypatch.setenv("BDIS_SEARCH_CONFIG", str(opt))
+        ctx, g = _run(B, left, right, p, f"search configuration {opt}")
+        _patch_parity(B, ctx, r["trace"], p.levels)
+        st = parity(g["disp"], r["disp"], DISP_TOL)
+        _report("disparity", st)
+        assert st["frac"] >= PASS_FRAC
+        ctx.close()
+    monkeypatch.setenv("BDIS_SEARCH_CONFIG", "12")
+    with pytest.raises(B.BdisError):
+        B.Context(p, 640, 480)
