@@ -201,6 +201,22 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
     s_umax = INT_MIN;
   }
   const int wave = tid / 64, lane = tid % 64;
+  // ---- right window: rows oy .. oy+P-1, columns xs .. xs+rw-1 (clamped to the
+  // image), xs a multiple of 4.  When one workgroup holds the whole patch row
+  // and the image row with a margin of MARG columns on each side fits, that row
+  // is staged at once together with the left tile; otherwise the columns
+  // around the patches' starting displacements, after a workgroup min/max of
+  // floor(u0).
+  const bool full_row = a.search_nbx == 1 && W + 2 * MARG + 8 <= RWB;
+  auto stage_right = [&](int x0r, int nd) {
+    for (int ty = wave; ty < P; ty += NWAVES) {
+      const uint8_t* rp = a.R + (size_t)(oy + ty) * a.pitch;
+      stage_row<false>(s_right32 + ty * (RWB / 4), rp, W, x0r, nd, lane, ((uintptr_t)rp & 3) == 0);
+    }
+  };
+  int xs = (-MARG) & ~3;
+  int ndr = (W + MARG - xs + 3) / 4;
+  if (full_row) stage_right(xs, ndr);
   // ---- left tile: image rows oy-1 .. oy+P, columns xa .. oxl+P (reflect-101),
   // xa = (ox0 - 1) rounded down to a multiple of 4
   const int xa = (ox0 - 1) & ~3;
@@ -209,22 +225,19 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
     const uint8_t* rp = a.L + (size_t)reflect101(oy - 1 + ty, Hh) * a.pitch;
     stage_row<true>(s_left32 + ty * (LTW / 4), rp, W, xa, ndl, lane, ((uintptr_t)rp & 3) == 0);
   }
-  __syncthreads();
-  if (g == 0 && live) {
-    const int mu = (int)floor(uinit);
-    atomicMin(&s_umin, mu);
-    atomicMax(&s_umax, mu);
+  if (!full_row) {
+    __syncthreads();
+    if (g == 0 && live) {
+      const int mu = (int)floor(uinit);
+      atomicMin(&s_umin, mu);
+      atomicMax(&s_umax, mu);
+    }
+    __syncthreads();
+    xs = (ox0 + s_umin - MARG) & ~3;
+    ndr = min((oxl + P + s_umax + MARG + 2 - xs + 3) / 4, RWB / 4);
+    stage_right(xs, ndr);
   }
-  __syncthreads();
-  // ---- right window: rows oy .. oy+P-1, columns xs .. xs+rw-1 (clamped to the
-  // image), xs a multiple of 4
-  const int xs = (ox0 + s_umin - MARG) & ~3;
-  const int ndr = min((oxl + P + s_umax + MARG + 2 - xs + 3) / 4, RWB / 4);
   const int rw = 4 * ndr;
-  for (int ty = wave; ty < P; ty += NWAVES) {
-    const uint8_t* rp = a.R + (size_t)(oy + ty) * a.pitch;
-    stage_row<false>(s_right32 + ty * (RWB / 4), rp, W, xs, ndr, lane, ((uintptr_t)rp & 3) == 0);
-  }
   __syncthreads();
 
   // ---- template rows of this lane: T and Sobel-x G (integer); rows past the
