@@ -27,18 +27,33 @@ namespace bdis {
 
 namespace {
 
-// The fusion record of patch k: (u, pi or -1 when rejected, sigma_k^2, post).
-BDIS_DEV D4 patch_record(const PairLevel& a, const LevelParams& lp, size_t k, double tau) {
-  const double u = gbl(a.pa.u)[k];
+// The search results of patch k that its fusion record needs.
+struct PatchRaw {
+  double u, pipar;
+  D4 d;  // window SSD differences
+  int acc;
+};
+BDIS_DEV PatchRaw patch_raw(const PairLevel& a, const LevelParams& lp, size_t k) {
+  PatchRaw p;
+  p.u = gbl(a.pa.u)[k];
+  p.acc = gbl(a.pa.acc)[k];
+  p.d = ld4(a.pa.dssd + k);
+  p.pipar = lp.propagate ? gbl(a.pa.pipar)[k] : 0.0;
+  return p;
+}
+
+// The fusion record of a patch: (u, pi or -1 when rejected, sigma_k^2, post).
+BDIS_DEV D4 patch_record(const PairLevel& a, const LevelParams& lp, const PatchRaw& p, double tau) {
+  const double u = p.u;
   const double nan = __builtin_nan("");
-  if (!gbl(a.pa.acc)[k]) return D4{u, -1.0, nan, 0.0};
-  const D4 d = ld4(a.pa.dssd + k);
+  if (!p.acc) return D4{u, -1.0, nan, 0.0};
+  const D4 d = p.d;
   const double den = 1.0 + exp(-d.x / tau) + exp(-d.y / tau) + exp(-d.z / tau) + exp(-d.w / tau);
   const double post = 1.0 / den;
   double wsum = 0.0;
   for (int n = lp.finest; n < a.levels; ++n) wsum += (double)lp.omega[n];
   const double gamma = (double)lp.omega[lp.level] / wsum;
-  const double pi = gamma * post + (lp.propagate ? gbl(a.pa.pipar)[k] : 0.0);
+  const double pi = gamma * post + p.pipar;
   double sig = nan;
   if (lp.variance && lp.level == lp.finest) {
     const double sfail = lp.var_fail_sigma > 0.0f ? (double)lp.var_fail_sigma : (double)lp.P;
@@ -74,7 +89,7 @@ __global__ __launch_bounds__(kProbThreads) void k_prob(const PairLevel* tab, int
   const PairLevel& a = tab[find_pair<2>(tab, npairs, xcd_block())];
   const int k = (xcd_block() - a.prob0) * kProbThreads + (int)threadIdx.x;
   if (k >= a.g.nx * a.g.ny) return;
-  st4(a.pa.dens + k, patch_record(a, lp, (size_t)k, gbl(a.scal)[1]));
+  st4(a.pa.dens + k, patch_record(a, lp, patch_raw(a, lp, (size_t)k), gbl(a.scal)[1]));
 }
 
 // Records staged per workgroup: the patches covering a tile (about 26 x 6
@@ -117,30 +132,53 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
   const int ni = ihi - ilo + 1 + (iex >= 0 ? 1 : 0);
   const int nj = jhi - jlo + 1 + (jex >= 0 ? 1 : 0);
   const bool staged = ni * nj <= kMaxRec;
+  // staged records: slot s of this lane is record tid + s * kThreads
+  constexpr int kSlots = (kMaxRec + kThreads - 1) / kThreads;
+  auto rec_index = [&](int r, int& i, int& j) {
+    const int rj = div_small(r, ni), ri = r - rj * ni;
+    i = ilo + ri <= ihi ? ilo + ri : iex;
+    j = jlo + rj <= jhi ? jlo + rj : jex;
+  };
   double tau = 0.0;
   if (INLINE) {
+    // the search results of the staged patches are loaded before the level
+    // reduction, so both global round trips overlap
+    PatchRaw raw[kSlots];
+#pragma unroll
+    for (int sl = 0; sl < kSlots; ++sl) {
+      const int r = tid + sl * kThreads;
+      if (staged && r < ni * nj) {
+        int i, j;
+        rec_index(r, i, j);
+        raw[sl] = patch_raw(a, lp, (size_t)j * a.g.nx + i);
+      }
+    }
     __shared__ double s_red[256];
     __shared__ long long s_redc[256];
     double sc[4];
     pair_scalars(a, lp, s_red, s_redc, sc);
     tau = sc[1];
     if (t == 0 && tid < 4) gbl(a.scal)[tid] = sc[tid];  // kept for the backward pass and debug
-  }
-  if (staged) {
-    for (int r = tid; r < ni * nj; r += kThreads) {
-      const int rj = div_small(r, ni), ri = r - rj * ni;
-      const int i = ilo + ri <= ihi ? ilo + ri : iex;
-      const int j = jlo + rj <= jhi ? jlo + rj : jex;
-      const size_t k = (size_t)j * a.g.nx + i;
-      D4 d;
-      if (INLINE) {
-        d = patch_record(a, lp, k, tau);
+#pragma unroll
+    for (int sl = 0; sl < kSlots; ++sl) {
+      const int r = tid + sl * kThreads;
+      if (staged && r < ni * nj) {
+        int i, j;
+        rec_index(r, i, j);
+        const D4 d = patch_record(a, lp, raw[sl], tau);
         // the tile holding the patch origin keeps its record (backward pass, debug)
         const int ox = grid_origin(i, a.g.w, P, S), oy = grid_origin(j, a.g.h, P, S);
-        if (ox >= x0 && ox <= x1 && oy >= y0 && oy <= y1) st4(a.pa.dens + k, d);
-      } else {
-        d = ld4(a.pa.dens + k);
+        if (ox >= x0 && ox <= x1 && oy >= y0 && oy <= y1) st4(a.pa.dens + (size_t)j * a.g.nx + i, d);
+        s_u[r] = d.x;
+        s_w[r] = d.y;
+        s_v[r] = d.z;
       }
+    }
+  } else if (staged) {
+    for (int r = tid; r < ni * nj; r += kThreads) {
+      int i, j;
+      rec_index(r, i, j);
+      const D4 d = ld4(a.pa.dens + (size_t)j * a.g.nx + i);
       s_u[r] = d.x;
       s_w[r] = d.y;
       s_v[r] = d.z;
@@ -225,7 +263,7 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
           const size_t k = (size_t)j * a.g.nx + i;
           D4 d;
           if (INLINE) {
-            d = patch_record(a, lp, k, tau);
+            d = patch_record(a, lp, patch_raw(a, lp, k), tau);
             if (x == grid_origin(i, a.g.w, P, S) && y == grid_origin(j, a.g.h, P, S)) st4(a.pa.dens + k, d);
           } else {
             d = ld4(a.pa.dens + k);
