@@ -161,6 +161,9 @@ struct LevelParams {
   int propagate;    // 1: add the parent confidence (Eq. 11)
   int inline_prob;  // 1: the fusion computes the level scalars and patch records itself (small levels)
   int fuse_ty;      // fusion tile height (kFuseTyShort or kFuseTyTall)
+  // 1-D mixture mask m(a) = sum_c exp(-(a - c)^2 / (2 sigma_s^2)), a = 0..P-1
+  // (Eq. 9-10), evaluated once on the host per call
+  double mask[kMaxPatch];
 };
 
 // Tile shapes of the flattened launches.

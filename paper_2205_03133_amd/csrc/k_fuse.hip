@@ -110,15 +110,9 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
   const PairLevel& a = tab[find_pair<3>(tab, npairs, lb)];
   const int tid = threadIdx.x;
   const int P = lp.P, S = lp.S;
-  if (tid < P) {
-    const double sg = (double)lp.sigma_s;
-    double acc = 0.0;
-    for (int c = 0; c < P; ++c) {
-      const double dd = (double)(tid - c);
-      acc += exp(-dd * dd / (2.0 * sg * sg));
-    }
-    s_m[tid] = acc;
-  }
+  if (tid == 0)
+#pragma unroll
+    for (int c = 0; c < kMaxPatch; ++c) s_m[c] = lp.mask[c];
   const int tiles_x = (a.g.w + kFuseTx - 1) / kFuseTx;
   const int t = lb - a.fuse0;
   const int x0 = (t % tiles_x) * kFuseTx, y0 = (t / tiles_x) * TY;

@@ -344,7 +344,7 @@ void timing_stop(bdis_ctx* c, long mark, hipStream_t st) {
 // ---- planning ---------------------------------------------------------------
 
 LevelParams level_params(const bdis_params& p, int n) {
-  LevelParams lp;
+  LevelParams lp{};
   lp.level = n;
   lp.finest = p.finest_level;
   lp.P = p.patch;
@@ -361,6 +361,15 @@ LevelParams level_params(const bdis_params& p, int n) {
   lp.prob_thresh = p.prob_thresh;
   lp.fusion = p.fusion;
   lp.propagate = p.propagate;
+  const double sg = (double)p.sigma_s;
+  for (int a = 0; a < kMaxPatch; ++a) {
+    double acc = 0.0;
+    for (int c = 0; c < p.patch && a < p.patch; ++c) {
+      const double dd = (double)(a - c);
+      acc += std::exp(-dd * dd / (2.0 * sg * sg));
+    }
+    lp.mask[a] = acc;
+  }
   return lp;
 }
 
