@@ -468,12 +468,18 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
   // around the real-valued boundaries.
   auto inside_lo = [&](int c) { return (double)(ox + c) + u >= 0.0; };
   auto inside_hi = [&](int c) { return (double)(ox + c) + u <= (double)(W - 1); };
+  // The candidates come from one rounded subtraction each, so they are at most
+  // one column off the rounded predicate's boundary (each moves only when the
+  // boundary lies within an ulp of an integer); two correcting steps each way.
   int clo = (int)fmin(fmax(ceil(-(double)ox - u), 0.0), (double)P);
-  while (clo > 0 && inside_lo(clo - 1)) --clo;
-  while (clo < P && !inside_lo(clo)) ++clo;
   int chi = (int)fmin(fmax(floor((double)(W - 1 - ox) - u), -1.0), (double)(P - 1));
-  while (chi < P - 1 && inside_hi(chi + 1)) ++chi;
-  while (chi >= 0 && !inside_hi(chi)) --chi;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    if (clo > 0 && inside_lo(clo - 1)) --clo;
+    else if (clo < P && !inside_lo(clo)) ++clo;
+    if (chi < P - 1 && inside_hi(chi + 1)) ++chi;
+    else if (chi >= 0 && !inside_hi(chi)) --chi;
+  }
   const int inb = chi >= clo ? chi - clo + 1 : 0;
   const double rho = (double)(inb * P) / (double)N;
   const bool acc = s0 <= sm1 && s0 <= smh && s0 <= sph && s0 <= sp1 && rho >= (double)lp.valid_ratio;
