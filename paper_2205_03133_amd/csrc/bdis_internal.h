@@ -181,7 +181,7 @@ constexpr long kInlineProbPatches = 1 << 16;
 // workgroups), or 64 x 16, two per lane of 512 (levels of at least
 // kFuseTallPixels pixels over the batch: fewer re-staged patch records).
 constexpr int kFuseTx = 64, kFuseTyShort = 4, kFuseTyTall = 16;
-constexpr long kFuseTallPixels = 1 << 20;
+constexpr long kFuseTallPixels = 1 << 18;
 __host__ __device__ constexpr int fuse_threads(int ty) { return ty == kFuseTyTall ? 512 : 256; }
 
 // Workgroups of the float-path search (fixed size) and of per-pixel adjoint launches.
