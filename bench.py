@@ -41,17 +41,26 @@ def search_flops(bdis, p, w, h, levels=None):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_hbm_traffic_c2_640x480_and_c5_1080p_batch64.md")
-SEARCH_SRC = os.path.join(ROOT, "paper_2205_03133_amd", "csrc", "k_search.hip")
+# the search kernel's source and the header that fixes its layouts and launch shapes
+SEARCH_SRC = [os.path.join(ROOT, "paper_2205_03133_amd", "csrc", "k_search.hip"),
+              os.path.join(ROOT, "paper_2205_03133_amd", "csrc", "bdis_internal.h")]
+
+
+def search_source_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for p in SEARCH_SRC:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(workload):
     """HBM bytes per search launch from the committed FETCH_SIZE/WRITE_SIZE counter
     runs (scaled by the copy-kernel calibration), or None once the kernel source
     differs from the one the counters were taken on."""
-    import hashlib
     try:
         text = open(TRAFFIC_FILE).read()
-        src = hashlib.sha256(open(SEARCH_SRC, "rb").read()).hexdigest()
+        src = search_source_sha256()
     except OSError:
         return None
     sha, val = None, None
