@@ -743,6 +743,10 @@ bdis_status run_graph(bdis_ctx* c, const Plan& pl, hipStream_t st) {
 // Picks the search configuration (lane mapping and workgroup size) of every
 // level of a new batch shape by timing each option over full passes (every
 // phase rewrites its outputs, so trial passes leave nothing behind).
+// Timed passes per configuration (the first one only warms caches and code;
+// the best of the others counts).
+constexpr int kTuneReps = 5;
+
 bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
   const bdis_params& p = c->p;
   bool need = false;
@@ -775,7 +779,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
           if (x) (void)hipEventDestroy(x);
         return s2;
       }
-      for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+      for (int rep = 0; rep < kTuneReps && e == hipSuccess; ++rep) {
         // a full pass with each level's search launch bracketed by events
         for (int n = 1; n < trial.max_levels && e == hipSuccess; ++n)
           e = launch_pyramid(c->tab_dev + trial.tab_first[n], trial.tab_count[n], trial.pyr_blocks[n], trial.pyr_tall[n], st);
