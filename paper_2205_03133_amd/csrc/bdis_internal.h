@@ -186,6 +186,15 @@ __host__ __device__ constexpr int fuse_threads(int ty) { return ty == kFuseTyTal
 
 // Workgroups of the float-path search (fixed size) and of per-pixel adjoint launches.
 constexpr int kSearchF64Threads = 256;
+// Columns of the float-path search's staged right-image window: the patch
+// origins' span, a margin of P + 4 each side and 128 columns of disparity
+// spread, capped at 40 KB of LDS for the P rows.
+__host__ __device__ inline int f64_window_cols(int P, int S) {
+  const int npb = kSearchF64Threads / group_lanes(P);
+  const int want = (npb - 1) * S + P + 2 * (P + 4) + 2 + 128;
+  const int cap = 40 * 1024 / (8 * P);
+  return want < cap ? want : cap;
+}
 constexpr size_t kAdjTileBytes = 64 * 1024;  // LDS accumulation tiles of the search adjoint
 constexpr int kPixThreads = 256;
 

@@ -46,6 +46,22 @@ __global__ __launch_bounds__(kPixThreads) void k_pyr_f64(const PairLevel* tab, i
   gbl(a.Rd)[(size_t)y * a.dpitch + x] = accr / 256.0;
 }
 
+// N consecutive samples of a right-image row from column x: from the staged
+// LDS window (columns xs .. xs+rw-1) when it holds them all, else from global
+// memory with the columns clamped to the row.
+template <int N>
+BDIS_DEV void fetch_f64(double (&v)[N], const double* win, int xs, int rw,
+                        const __attribute__((address_space(1))) double* grow, int x, int W) {
+  const int off = x - xs;
+  if (off >= 0 && off + N <= rw) {
+#pragma unroll
+    for (int n = 0; n < N; ++n) v[n] = win[off + n];
+  } else {
+#pragma unroll
+    for (int n = 0; n < N; ++n) v[n] = grow[clampi(x + n, 0, W - 1)];
+  }
+}
+
 template <int P>
 __global__ __launch_bounds__(kSearchF64Threads) void k_search_f64(const PairLevel* tab, int npairs, LevelParams lp) {
   constexpr int G = group_lanes(P);
@@ -75,6 +91,34 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_f64(const PairLeve
     uinit = 2.0 * bilinear(a.par_ubar, a.pw, a.ph, cx, cy);
     pipar = bilinear(a.par_q, a.pw, a.ph, cx, cy);
   }
+
+  // ---- right rows oy .. oy+P-1 around the patches' starting displacements,
+  // staged in LDS (columns xs .. xs+rw-1, clamped to the image); samples
+  // outside come from global memory (identical values)
+  extern __shared__ double s_rwin[];  // [P][rwd]
+  __shared__ int s_umin, s_umax;
+  constexpr int MARG = P + 4;
+  const int rwd = f64_window_cols(P, S);
+  if (tid == 0) {
+    s_umin = INT_MAX;
+    s_umax = INT_MIN;
+  }
+  __syncthreads();
+  if (r == 0 && live) {
+    const int mu = (int)floor(uinit);
+    atomicMin(&s_umin, mu);
+    atomicMax(&s_umax, mu);
+  }
+  __syncthreads();
+  const int ox0 = grid_origin(i0, W, P, S);
+  const int oxl = grid_origin(min(i0 + NPB - 1, a.g.nx - 1), W, P, S);
+  const int xs = ox0 + s_umin - MARG;
+  const int rw = min(oxl + P + s_umax + MARG + 2 - xs, rwd);
+  for (int e = tid; e < P * rw; e += kSearchF64Threads) {
+    const int ty = e / rw, cx = e - ty * rw;
+    s_rwin[ty * rwd + cx] = gbl(a.Rd)[(size_t)(oy + ty) * a.dpitch + clampi(xs + cx, 0, W - 1)];
+  }
+  __syncthreads();
 
   const bool row_live = r < P;
   const int rr = row_live ? r : P - 1;
@@ -120,13 +164,12 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_f64(const PairLeve
       const double f = u - fm;
       if (m != mc) {
         double c0 = 0.0, c1 = 0.0;
-        double rv = Rrow[clampi(ox + m, 0, W - 1)];
+        double Rv[P + 1];
+        fetch_f64<P + 1>(Rv, s_rwin + rr * rwd, xs, rw, Rrow, ox + m, W);
 #pragma unroll
         for (int c = 0; c < P; ++c) {
-          const double rn = Rrow[clampi(ox + c + m + 1, 0, W - 1)];
-          c0 += J[c] * rv;
-          c1 += J[c] * rn;
-          rv = rn;
+          c0 += J[c] * Rv[c];
+          c1 += J[c] * Rv[c + 1];
         }
         C0 = group_sum_d<G>(row_live ? c0 : 0.0) - cT;
         C1 = group_sum_d<G>(row_live ? c1 : 0.0) - cT;
@@ -148,8 +191,7 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_f64(const PairLeve
   double X0[3], X1[3], X2[3];
   {
     double Rv[P + 3];
-#pragma unroll
-    for (int c = 0; c < P + 3; ++c) Rv[c] = Rrow[clampi(ox + m - 1 + c, 0, W - 1)];
+    fetch_f64<P + 3>(Rv, s_rwin + rr * rwd, xs, rw, Rrow, ox + m - 1, W);
 #pragma unroll
     for (int cq = 0; cq < 3; ++cq) {
       double sa = 0.0, saa = 0.0, sd = 0.0, sdd = 0.0, sad = 0.0;
@@ -220,7 +262,8 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_f64(const PairLeve
 
 template <int P>
 hipError_t launch_f64(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
-  hipLaunchKernelGGL(k_search_f64<P>, dim3(nblocks), dim3(kSearchF64Threads), 0, s, tab, npairs, lp);
+  const size_t lds = sizeof(double) * (size_t)P * f64_window_cols(P, lp.S);
+  hipLaunchKernelGGL(k_search_f64<P>, dim3(nblocks), dim3(kSearchF64Threads), lds, s, tab, npairs, lp);
   return hipGetLastError();
 }
 

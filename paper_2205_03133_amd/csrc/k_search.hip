@@ -11,10 +11,11 @@
 // of one pair per workgroup.  The tuner picks G and THREADS per level: one
 // row per lane keeps the per-lane chain of the K dependent iterations short
 // (small, latency-bound levels), several rows per lane repeat the per-patch
-// iteration logic on fewer lanes (large, throughput-bound levels).  The left rows around those
-// patches (for the template and its Sobel gradient) and a window of the right
-// rows around the patches' starting displacements are staged in LDS once;
-// right-image samples outside the window fall back to (clamped) global loads.
+// iteration logic on fewer lanes (large, throughput-bound levels).  The left
+// rows around those patches (for the template and its Sobel gradient) and a
+// window of the right rows around the patches' starting displacements are
+// staged in LDS once; right-image samples outside the window fall back to
+// (clamped) global loads.
 //
 // Arithmetic.  The uint8 path keeps every image sum exact in int32:
 //   with e_i(u) = I_w,i(u) - T_i and J_i = (G_i - sum G / N) / 8 (N = P^2),
@@ -26,9 +27,9 @@
 // that stay in the same unit cell cost a few scalar flops.  The window SSD of a
 // unit cell is an exact quadratic in the fraction f:
 //   SSD = [X0 + 2 f X1 + f^2 X2] / N with integer X0, X1, X2 (see below).
-// Only the final combinations are rounded (in double).  Every product of two
-// image-derived integers has factors within 24 bits (samples 0..255, Sobel sums
-// within +-1020), so they use the full-rate 24-bit multiply.
+// Only the final combinations are rounded (in double).  Image samples, template
+// bytes and the two bytes of Gx + 1024 are packed four per dword, so the sums
+// of products are v_dot4_u32_u8 (exact 8-bit products, 32-bit accumulation).
 #include "bdis_internal.h"
 
 #include <climits>
@@ -36,9 +37,6 @@
 namespace bdis {
 
 namespace {
-
-// Exact product of two integers known to lie within +-2^23.
-BDIS_DEV int mul24(int a, int b) { return __mul24(a, b); }
 
 // a*b - c*d of int32 values whose products and difference stay below 2^53 in
 // magnitude (true for every combination below: at most about 2^36), so the
