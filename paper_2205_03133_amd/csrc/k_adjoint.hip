@@ -530,7 +530,6 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLeve
                                                                   int twl, int twr) {
   constexpr int G = group_lanes(P);
   constexpr int NPB = kSearchF64Threads / G;
-  constexpr int N = P * P;
   extern __shared__ double s_tile[];  // [P][twl] left, [P][twl] gradient, [P][twr] right
   __shared__ int s_lo;
   const int lb = xcd_block();
