@@ -172,7 +172,6 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
   search_lds_layout(P, NPB, S, LTW, RWB);
   uint32_t* s_left32 = s_dyn;
   uint32_t* s_right32 = s_dyn + (P + 2) * LTW / 4;
-  const uint8_t* s_left = reinterpret_cast<const uint8_t*>(s_left32);
   const uint8_t* s_right = reinterpret_cast<const uint8_t*>(s_right32);
 
   const int j = blk / a.search_nbx;
