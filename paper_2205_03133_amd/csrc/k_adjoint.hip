@@ -406,9 +406,13 @@ BDIS_DEV void patch_adj(const PairLevel& a, const LevelParams& lp, int k, int r,
     }
     ub += group_sum_d<G>(row_live ? urow : 0.0);
   };
+  double sbars[kWin];  // all loads issued before the first use
+#pragma unroll
+  for (int t = 0; t < kWin; ++t) sbars[t] = sa[t];
+  sbars[2] += gbl(a.scal)[5];  // share of d loss / d tau through sigma_r
+#pragma unroll
   for (int t = 0; t < kWin; ++t) {
-    double sbar = sa[t];
-    if (t == 2) sbar += gbl(a.scal)[5];  // share of d loss / d tau through sigma_r
+    const double sbar = sbars[t];
     if (sbar == 0.0) continue;
     const double v = u + 0.5 * (double)(t - 2);  // offsets -1, -1/2, 0, 1/2, 1
     const double fm = floor(v);
@@ -449,8 +453,10 @@ BDIS_DEV void patch_adj(const PairLevel& a, const LevelParams& lp, int k, int r,
       }
       al = be = de = 0.0;
     };
+    double u_next = uh[lp.K - 1];  // the next iterate is loaded one step ahead
     for (int t = lp.K - 1; t >= 0; --t) {
-      const double ut = uh[t];
+      const double ut = u_next;
+      if (t > 0) u_next = uh[t - 1];
       const double fm = floor(ut);
       const int m = (int)fm;
       const double f = ut - fm;
