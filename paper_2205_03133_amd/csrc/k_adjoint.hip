@@ -134,23 +134,41 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_fuse_adj(const PairLevel*
   }
   const double u = d.x, pi = d.y, s2 = vt ? d.z : 0.0;
   double su = 0.0, spi = 0.0, ssg = 0.0, sss = 0.0;
-  for (int b = 0; b < P; ++b) {
-    __syncthreads();  // previous row consumed (and the mask sums written)
+  // the fused maps and their adjoints of row b (one lane per tile column), all
+  // issued at once and one row ahead of their use
+  constexpr int NF = 8;  // Z, gU, gQ, SM, U, Q, gV, V
+  auto load_row = [&](int b, double (&v)[NF]) {
     if (tid < tw) {
       const size_t idx = (size_t)(oy + b) * W + oxa + tid;
-      const double Z = gbl(a.zmap)[idx];
+      v[0] = gbl(a.zmap)[idx];
+      v[1] = gbl(a.ubar_adj)[idx];
+      v[2] = gbl(a.qmap_adj)[idx];
+      v[3] = gbl(a.smmap)[idx];
+      v[4] = ub[idx];
+      v[5] = qm[idx];
+      v[6] = vt ? gbl(a.vmap_adj)[idx] : 0.0;
+      v[7] = vt ? gbl(a.vmap)[idx] : 0.0;
+    }
+  };
+  double cur[NF] = {}, nxt[NF] = {};
+  load_row(0, cur);
+  for (int b = 0; b < P; ++b) {
+    if (b + 1 < P) load_row(b + 1, nxt);
+    __syncthreads();  // previous row consumed (and the mask sums written)
+    if (tid < tw) {
+      const double Z = cur[0];
       double t[NT] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       if (Z > 0.0) {
-        const double gU = gbl(a.ubar_adj)[idx], gQ = gbl(a.qmap_adj)[idx];
-        const double SM = gbl(a.smmap)[idx];
+        const double gU = cur[1], gQ = cur[2];
+        const double SM = cur[3];
         t[0] = gU / Z;
-        t[1] = t[0] * ub[idx];
+        t[1] = t[0] * cur[4];
         t[2] = gQ / SM;
-        t[3] = t[2] * qm[idx];
+        t[3] = t[2] * cur[5];
         if (vt) {
-          const double gV = gbl(a.vmap_adj)[idx];
+          const double gV = cur[6];
           t[4] = gV / (Z * Z);
-          t[5] = gV * gbl(a.vmap)[idx] / Z;
+          t[5] = gV * cur[7] / Z;
         }
       }
 #pragma unroll
@@ -167,6 +185,8 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_fuse_adj(const PairLevel*
       ssg += m * m * C1;
       sss += dm * (pi * u * A1 - pi * A2 + pi * B1 - B2 + 2.0 * pi * pi * s2 * m * C1 - 2.0 * pi * C2);
     }
+#pragma unroll
+    for (int e = 0; e < NF; ++e) cur[e] = nxt[e];
   }
   if (i < a.g.nx && d.y >= 0.0) {  // uniform over the group
     su = group_sum_d<G>(su);
