@@ -583,7 +583,8 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLeve
     if (active && r == 0) {  // lowest warp cell of this patch: window and iterations
       int mlo = (int)floor(gbl(a.pa.u)[k] - 1.0);
       const auto uh = gbl(a.uhist) + (size_t)k * (lp.K + 1);
-      for (int t = 0; t < lp.K; ++t) mlo = min(mlo, (int)floor(uh[t]));
+#pragma unroll 8
+      for (int t = 0; t < lp.K; ++t) mlo = min(mlo, (int)floor(uh[t]));  // loads issued eight at a time
       atomicMin(&s_lo, ox + mlo);
     }
     __syncthreads();
