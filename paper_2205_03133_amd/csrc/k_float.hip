@@ -92,34 +92,8 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_f64(const PairLeve
     pipar = bilinear(a.par_q, a.pw, a.ph, cx, cy);
   }
 
-  // ---- right rows oy .. oy+P-1 around the patches' starting displacements,
-  // staged in LDS (columns xs .. xs+rw-1, clamped to the image); samples
-  // outside come from global memory (identical values)
-  extern __shared__ double s_rwin[];  // [P][rwd]
-  __shared__ int s_umin, s_umax;
-  constexpr int MARG = P + 4;
-  const int rwd = f64_window_cols(P, S);
-  if (tid == 0) {
-    s_umin = INT_MAX;
-    s_umax = INT_MIN;
-  }
-  __syncthreads();
-  if (r == 0 && live) {
-    const int mu = (int)floor(uinit);
-    atomicMin(&s_umin, mu);
-    atomicMax(&s_umax, mu);
-  }
-  __syncthreads();
-  const int ox0 = grid_origin(i0, W, P, S);
-  const int oxl = grid_origin(min(i0 + NPB - 1, a.g.nx - 1), W, P, S);
-  const int xs = ox0 + s_umin - MARG;
-  const int rw = min(oxl + P + s_umax + MARG + 2 - xs, rwd);
-  for (int e = tid; e < P * rw; e += kSearchF64Threads) {
-    const int ty = e / rw, cx = e - ty * rw;
-    s_rwin[ty * rwd + cx] = gbl(a.Rd)[(size_t)(oy + ty) * a.dpitch + clampi(xs + cx, 0, W - 1)];
-  }
-  __syncthreads();
-
+  // ---- template row and its gradient (loaded before the staging barriers so
+  // that their loads overlap the window's)
   const bool row_live = r < P;
   const int rr = row_live ? r : P - 1;
   const auto Lg = gbl(a.Ld);
@@ -149,6 +123,34 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_f64(const PairLeve
   const double H = group_sum_d<G>(row_live ? hrow : 0.0);
   const double cT = group_sum_d<G>(row_live ? crow : 0.0);
   const bool invert = H >= kEpsH;
+
+  // ---- right rows oy .. oy+P-1 around the patches' starting displacements,
+  // staged in LDS (columns xs .. xs+rw-1, clamped to the image); samples
+  // outside come from global memory (identical values)
+  extern __shared__ double s_rwin[];  // [P][rwd]
+  __shared__ int s_umin, s_umax;
+  constexpr int MARG = P + 4;
+  const int rwd = f64_window_cols(P, S);
+  if (tid == 0) {
+    s_umin = INT_MAX;
+    s_umax = INT_MIN;
+  }
+  __syncthreads();
+  if (r == 0 && live) {
+    const int mu = (int)floor(uinit);
+    atomicMin(&s_umin, mu);
+    atomicMax(&s_umax, mu);
+  }
+  __syncthreads();
+  const int ox0 = grid_origin(i0, W, P, S);
+  const int oxl = grid_origin(min(i0 + NPB - 1, a.g.nx - 1), W, P, S);
+  const int xs = ox0 + s_umin - MARG;
+  const int rw = min(oxl + P + s_umax + MARG + 2 - xs, rwd);
+  for (int e = tid; e < P * rw; e += kSearchF64Threads) {
+    const int ty = e / rw, cx = e - ty * rw;
+    s_rwin[ty * rwd + cx] = gbl(a.Rd)[(size_t)(oy + ty) * a.dpitch + clampi(xs + cx, 0, W - 1)];
+  }
+  __syncthreads();
 
   const auto Rrow = Rg + (size_t)(oy + rr) * dp;
   double u = uinit;
