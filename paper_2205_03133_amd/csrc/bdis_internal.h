@@ -162,8 +162,9 @@ struct LevelParams {
   int inline_prob;  // 1: the fusion computes the level scalars and patch records itself (small levels)
   int fuse_ty;      // fusion tile height (kFuseTyShort or kFuseTyTall)
   // 1-D mixture mask m(a) = sum_c exp(-(a - c)^2 / (2 sigma_s^2)), a = 0..P-1
-  // (Eq. 9-10), evaluated once on the host per call
+  // (Eq. 9-10), and its derivative in sigma_s, evaluated once on the host
   double mask[kMaxPatch];
+  double dmask[kMaxPatch];
 };
 
 // Tile shapes of the flattened launches.

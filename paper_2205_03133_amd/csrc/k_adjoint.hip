@@ -99,19 +99,12 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_fuse_adj(const PairLevel*
   const int tid = threadIdx.x;
   const int q = tid / G, c = tid % G;
   const int S = lp.S, W = a.g.w;
-  if (tid < P) {
-    // m1(t) = sum_c exp(-(t - c)^2 / (2 s^2)) and its derivative in s
-    const double sg = (double)lp.sigma_s;
-    double m = 0.0, dm = 0.0;
-    for (int cc = 0; cc < P; ++cc) {
-      const double d2 = (double)((tid - cc) * (tid - cc));
-      const double e = exp(-d2 / (2.0 * sg * sg));
-      m += e;
-      dm += e * d2 / (sg * sg * sg);
+  if (tid == 0)  // m1(t) = sum_c exp(-(t - c)^2 / (2 s^2)) and its derivative in s
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      s_m1[t] = lp.mask[t];
+      s_dm1[t] = lp.dmask[t];
     }
-    s_m1[tid] = m;
-    s_dm1[tid] = dm;
-  }
   const int j = blk / a.search_nbx;
   const int i0 = (blk % a.search_nbx) * NPB;
   const int i = i0 + q;

@@ -363,12 +363,15 @@ LevelParams level_params(const bdis_params& p, int n) {
   lp.propagate = p.propagate;
   const double sg = (double)p.sigma_s;
   for (int a = 0; a < kMaxPatch; ++a) {
-    double acc = 0.0;
+    double acc = 0.0, dacc = 0.0;
     for (int c = 0; c < p.patch && a < p.patch; ++c) {
-      const double dd = (double)(a - c);
-      acc += std::exp(-dd * dd / (2.0 * sg * sg));
+      const double d2 = (double)((a - c) * (a - c));
+      const double e = std::exp(-d2 / (2.0 * sg * sg));
+      acc += e;
+      dacc += e * d2 / (sg * sg * sg);
     }
     lp.mask[a] = acc;
+    lp.dmask[a] = dacc;
   }
   return lp;
 }
