@@ -460,15 +460,19 @@ def test_graph_replays_match_eager(B, monkeypatch):
     graph.close()
 
 
-@pytest.mark.parametrize("P", [8, 12])
-def test_every_search_configuration(B, oracle, monkeypatch, P):
+@pytest.mark.parametrize("P,S", [(8, 3), (12, 4), (16, 16), (3, 1)])
+def test_every_search_configuration(B, oracle, monkeypatch, P, S):
     """Each lane mapping and workgroup size of the search (forced with
-    BDIS_SEARCH_CONFIG instead of tuned) against the oracle."""
+    BDIS_SEARCH_CONFIG instead of tuned) against the oracle, including the
+    largest patch and stride (largest LDS layout) and the smallest (most
+    patches per workgroup)."""
     from paper_2205_03133_amd.synth import make_pair, method_params
-    left, right, _, _ = make_pair(2, 0)
+    if P in (8, 12):
+        left, right, _, _ = make_pair(2, 0)
+    else:
+        left, right, _, _ = make_pair(1, 0)
     kw = dict(method_params(2))
-    if P == 12:
-        kw.update(patch=12, stride=4, levels=4)
+    kw.update(patch=P, stride=S, levels=5 if P == 8 else (4 if P == 12 else 3))
     p = B.params(**kw)
     r = oracle.compute(left, right, oracle_params(oracle, p), trace=True)
     for opt in range(12):
@@ -481,4 +485,4 @@ def test_every_search_configuration(B, oracle, monkeypatch, P):
         ctx.close()
     monkeypatch.setenv("BDIS_SEARCH_CONFIG", "12")
     with pytest.raises(B.BdisError):
-        B.Context(p, 640, 480)
+        B.Context(p, left.shape[1], left.shape[0])
