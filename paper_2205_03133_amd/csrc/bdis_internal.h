@@ -160,7 +160,9 @@ struct LevelParams {
   int fusion;       // 0 Eq. 13, 1 Eq. 2 (DIS), 2 Eq. 13 with a uniform mask
   int propagate;    // 1: add the parent confidence (Eq. 11)
   int inline_prob;  // 1: the fusion computes the level scalars and patch records itself (small levels)
-  int fuse_ty;      // fusion tile height (kFuseTyShort or kFuseTyTall)
+  int fuse_ty;      // fusion tile height (kFuseTyShort, kFuseTyTall or kFuseTyHuge)
+  int fuse_rec;     // patch records a fusion workgroup stages (<= kFuseMaxRec), fuse_lds_bytes
+  int fuse_sep;     // staged patch rows with separable column sums (<= fuse_sep_rows(fuse_ty))
   // 1-D mixture mask m(a) = sum_c exp(-(a - c)^2 / (2 sigma_s^2)), a = 0..P-1
   // (Eq. 9-10), and its derivative in sigma_s, evaluated once on the host
   double mask[kMaxPatch];
@@ -179,11 +181,31 @@ constexpr int kProbThreads = 256;           // probability: patches per workgrou
 // launches of their own.
 constexpr long kInlineProbPatches = 1 << 16;
 // Fusion tiles: 64 x 4 pixels, one per lane of 256 (small levels, many
-// workgroups), or 64 x 16, two per lane of 512 (levels of at least
-// kFuseTallPixels pixels over the batch: fewer re-staged patch records).
-constexpr int kFuseTx = 64, kFuseTyShort = 4, kFuseTyTall = 16;
-constexpr long kFuseTallPixels = 1 << 18;
-__host__ __device__ constexpr int fuse_threads(int ty) { return ty == kFuseTyTall ? 512 : 256; }
+// workgroups), 64 x 16, two per lane of 512 (levels of at least
+// kFuseTallPixels pixels over the batch: fewer re-staged patch records), or
+// 64 x 32, four per lane of 512 (levels of at least kFuseHugePixels).
+constexpr int kFuseTx = 64, kFuseTyShort = 4, kFuseTyTall = 16, kFuseTyHuge = 32;
+constexpr long kFuseTallPixels = 1 << 18, kFuseHugePixels = 1 << 22;
+__host__ __device__ constexpr int fuse_threads(int ty) { return ty == kFuseTyShort ? 256 : 512; }
+__host__ __device__ constexpr bool fuse_ty_ok(int ty) {
+  return ty == kFuseTyShort || ty == kFuseTyTall || ty == kFuseTyHuge;
+}
+// Patch records a fusion workgroup stages, and the staged patch rows whose
+// column sums the separable form keeps, per tile height.
+constexpr int kFuseMaxRec = 512;
+__host__ __device__ constexpr int fuse_sep_rows(int ty) {
+  return ty == kFuseTyHuge ? 16 : (ty == kFuseTyTall ? 12 : 8);
+}
+// Dynamic LDS of a fusion workgroup: three record arrays, then the column sums.
+__host__ __device__ constexpr int fuse_lds_bytes(int rec, int sep) {
+  return 8 * (3 * rec + 4 * kFuseTx * sep);
+}
+// Whether the patches covering any tile of height ty (at most (ty + P - 1) / S
+// + 1 grid rows plus the border patch, likewise for the 64 columns) fit both.
+__host__ __device__ constexpr bool fuse_tile_fits(int ty, int P, int S) {
+  return (ty + P - 1) / S + 2 <= fuse_sep_rows(ty) &&
+         ((kFuseTx + P - 1) / S + 2) * ((ty + P - 1) / S + 2) <= kFuseMaxRec;
+}
 
 // Workgroups of the float-path search (fixed size) and of per-pixel adjoint launches.
 constexpr int kSearchF64Threads = 256;

@@ -202,7 +202,7 @@ hipError_t launch_flow_search(const PairLevel* tab, int npairs, int nblocks, con
 
 hipError_t launch_flow_fuse(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  if (lp.fuse_ty != kFuseTyShort && lp.fuse_ty != kFuseTyTall) return hipErrorInvalidValue;
+  if (!fuse_ty_ok(lp.fuse_ty)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_flow_fuse, dim3(nblocks), dim3(fuse_threads(lp.fuse_ty)), 0, s, tab, npairs, lp);
   return hipGetLastError();
 }

@@ -10,7 +10,7 @@
 //   Gauss-Newton fixed point is the least-squares line of ln p on d^2:
 //   sigma_k^2 = tau / (2 kappa), kappa the slope of SSD_d on d^2.
 //
-// k_fuse (gather over 64 x 4 or 64 x 16 pixel tiles): over the accepted patches
+// k_fuse (gather over 64 x 4, 64 x 16 or 64 x 32 pixel tiles): over the accepted patches
 //   covering the pixel, in ascending patch index, weights W_k = M(x - o_k) pi_k
 //   with the spatial mixture mask M(a, b) = m(a) m(b),
 //   m(a) = sum_c exp(-(a - c)^2 / (2 sigma_s^2)) (Eq. 9-10, unit mixture
@@ -92,10 +92,12 @@ __global__ __launch_bounds__(kProbThreads) void k_prob(const PairLevel* tab, int
   st4(a.pa.dens + k, patch_record(a, lp, patch_raw(a, lp, (size_t)k), gbl(a.scal)[1]));
 }
 
-// Records staged per workgroup: the patches covering a tile (about 26 x 6
-// for 64 x 4 and 26 x 9 for 64 x 16 at stride 3; tiles that cover more use
-// direct loads).
-constexpr int kMaxRec = 512;
+// Records staged per workgroup: the patches covering a tile (about 25 x 5
+// for 64 x 4, 25 x 9 for 64 x 16 and 25 x 15 for 64 x 32 at patch 8, stride 3;
+// tiles that cover more than the level's lp.fuse_rec use direct loads).  The
+// record arrays and the separable column sums live in dynamic LDS sized per
+// level (fuse_lds_bytes), so small strides do not cost every level occupancy.
+constexpr int kMaxRec = kFuseMaxRec;
 
 // INLINE: the patch records are computed here (small levels) instead of read
 // from a preceding k_prob launch.
@@ -103,9 +105,13 @@ template <bool INLINE, int TY>
 __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab, int npairs, LevelParams lp) {
   constexpr int kThreads = fuse_threads(TY);
   constexpr int kRowsPerLane = TY / (kThreads / kFuseTx);
-  constexpr int kSepRows = TY == kFuseTyTall ? 12 : 8;  // patch rows the separable form keeps sums for
   __shared__ double s_m[kMaxPatch];
-  __shared__ double s_u[kMaxRec], s_w[kMaxRec], s_v[kMaxRec];
+  extern __shared__ double s_fdyn[];
+  const int rec_cap = lp.fuse_rec;
+  double* const s_u = s_fdyn;
+  double* const s_w = s_u + rec_cap;
+  double* const s_v = s_w + rec_cap;
+  double* const s_A = s_v + rec_cap;  // [lp.fuse_sep][4][kFuseTx]
   const int lb = xcd_block();
   const PairLevel& a = tab[find_pair<3>(tab, npairs, lb)];
   const int tid = threadIdx.x;
@@ -125,7 +131,7 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
   cover_range(y1, a.g.h, P, S, a.g.ny, dummy2, jhi, jex);
   const int ni = ihi - ilo + 1 + (iex >= 0 ? 1 : 0);
   const int nj = jhi - jlo + 1 + (jex >= 0 ? 1 : 0);
-  const bool staged = ni * nj <= kMaxRec;
+  const bool staged = ni * nj <= rec_cap;
   // staged records: slot s of this lane is record tid + s * kThreads
   constexpr int kSlots = (kMaxRec + kThreads - 1) / kThreads;
   auto rec_index = [&](int r, int& i, int& j) {
@@ -184,8 +190,7 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
   // columns i are formed once and shared by the tile's pixel rows:
   //   A0 = sum_i m_x pi, A1 = sum_i m_x pi u, A2 = sum_i m_x, A3 = sum_i (m_x pi)^2 sigma^2,
   // then z = sum_j m_y A0, ..., zv = sum_j m_y^2 A3 per pixel.
-  __shared__ double s_A[4][kSepRows][kFuseTx];
-  const bool separable = staged && lp.fusion != 1 && nj <= kSepRows;
+  const bool separable = staged && lp.fusion != 1 && nj <= lp.fuse_sep;
   if (separable) {
     for (int e = tid; e < nj * kFuseTx; e += kThreads) {
       const int rj = e / kFuseTx, xl = e - rj * kFuseTx;
@@ -208,10 +213,11 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
           A3 += wx * wx * s_v[r];
         }
       }
-      s_A[0][rj][xl] = A0;
-      s_A[1][rj][xl] = A1;
-      s_A[2][rj][xl] = A2;
-      s_A[3][rj][xl] = A3;
+      double* const A = s_A + rj * (4 * kFuseTx) + xl;
+      A[0] = A0;
+      A[kFuseTx] = A1;
+      A[2 * kFuseTx] = A2;
+      A[3 * kFuseTx] = A3;
     }
     __syncthreads();
   }
@@ -229,10 +235,11 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
         const int j = jj <= pjhi ? jj : pjex;
         const int rj = j <= jhi ? j - jlo : nj - 1;
         const double my = lp.fusion == 2 ? 1.0 : s_m[y - grid_origin(j, a.g.h, P, S)];
-        z += my * s_A[0][rj][xl];
-        zu += my * s_A[1][rj][xl];
-        zm += my * s_A[2][rj][xl];
-        zv += my * my * s_A[3][rj][xl];
+        const double* const A = s_A + rj * (4 * kFuseTx) + xl;
+        z += my * A[0];
+        zu += my * A[kFuseTx];
+        zm += my * A[2 * kFuseTx];
+        zv += my * my * A[3 * kFuseTx];
       }
       zq = z;
     }
@@ -330,9 +337,12 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
     if (a.confidence) gbl(a.confidence)[idx] = valid ? (float)qv : 0.0f;
     if (a.variance) gbl(a.variance)[idx] = (valid && lp.variance) ? (float)(zv / (z * z)) : nan;
   };
+  // A wavefront holds one pixel row of the tile, so y and everything derived
+  // from it (covering patch rows, vertical mask weights) are wave-uniform.
+  static_assert(kFuseTx == 64, "one tile row per wavefront");
   if (x < a.g.w)
     for (int rr = 0; rr < kRowsPerLane; ++rr) {
-      const int y = y0 + tid / kFuseTx + rr * (kThreads / kFuseTx);
+      const int y = __builtin_amdgcn_readfirstlane(y0 + tid / kFuseTx + rr * (kThreads / kFuseTx));
       if (y < a.g.h) fuse_pixel(y);
     }
 }
@@ -442,17 +452,25 @@ hipError_t launch_prob(const PairLevel* tab, int npairs, int nblocks, const Leve
 
 hipError_t launch_fuse(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  if (lp.fuse_ty != kFuseTyShort && lp.fuse_ty != kFuseTyTall) return hipErrorInvalidValue;
-  const bool tall = lp.fuse_ty == kFuseTyTall;
-  const dim3 threads(fuse_threads(tall ? kFuseTyTall : kFuseTyShort));
-  if (lp.inline_prob && tall)
-    hipLaunchKernelGGL((k_fuse<true, kFuseTyTall>), dim3(nblocks), threads, 0, s, tab, npairs, lp);
-  else if (lp.inline_prob)
-    hipLaunchKernelGGL((k_fuse<true, kFuseTyShort>), dim3(nblocks), threads, 0, s, tab, npairs, lp);
-  else if (tall)
-    hipLaunchKernelGGL((k_fuse<false, kFuseTyTall>), dim3(nblocks), threads, 0, s, tab, npairs, lp);
-  else
-    hipLaunchKernelGGL((k_fuse<false, kFuseTyShort>), dim3(nblocks), threads, 0, s, tab, npairs, lp);
+  if (!fuse_ty_ok(lp.fuse_ty) || lp.fuse_rec < 0 || lp.fuse_rec > kFuseMaxRec || lp.fuse_sep < 0 ||
+      lp.fuse_sep > fuse_sep_rows(lp.fuse_ty))
+    return hipErrorInvalidValue;
+  const dim3 threads(fuse_threads(lp.fuse_ty));
+  const size_t lds = fuse_lds_bytes(lp.fuse_rec, lp.fuse_sep);
+  const bool inl = lp.inline_prob != 0;
+  switch (lp.fuse_ty) {
+    case kFuseTyHuge:
+      if (inl) hipLaunchKernelGGL((k_fuse<true, kFuseTyHuge>), dim3(nblocks), threads, lds, s, tab, npairs, lp);
+      else hipLaunchKernelGGL((k_fuse<false, kFuseTyHuge>), dim3(nblocks), threads, lds, s, tab, npairs, lp);
+      break;
+    case kFuseTyTall:
+      if (inl) hipLaunchKernelGGL((k_fuse<true, kFuseTyTall>), dim3(nblocks), threads, lds, s, tab, npairs, lp);
+      else hipLaunchKernelGGL((k_fuse<false, kFuseTyTall>), dim3(nblocks), threads, lds, s, tab, npairs, lp);
+      break;
+    default:
+      if (inl) hipLaunchKernelGGL((k_fuse<true, kFuseTyShort>), dim3(nblocks), threads, lds, s, tab, npairs, lp);
+      else hipLaunchKernelGGL((k_fuse<false, kFuseTyShort>), dim3(nblocks), threads, lds, s, tab, npairs, lp);
+  }
   return hipGetLastError();
 }
 

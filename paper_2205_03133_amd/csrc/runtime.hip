@@ -381,6 +381,10 @@ LevelParams plan_level_params(const bdis_params& p, const Plan& pl, int n) {
   LevelParams lp = level_params(p, n);
   lp.inline_prob = pl.inline_prob[n];
   lp.fuse_ty = pl.fuse_ty[n];
+  // largest covering-patch block of a tile (bound of cover_range's counts)
+  const int nj = (lp.fuse_ty + p.patch - 1) / p.stride + 2, ni = (kFuseTx + p.patch - 1) / p.stride + 2;
+  lp.fuse_rec = std::min(ni * nj, kFuseMaxRec);
+  lp.fuse_sep = std::min(nj, fuse_sep_rows(lp.fuse_ty));
   return lp;
 }
 
@@ -613,7 +617,11 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
       npx += (long)g.w * g.h;
     }
     pl.inline_prob[n] = np <= kInlineProbPatches ? 1 : 0;
-    pl.fuse_ty[n] = (!flow && npx >= kFuseTallPixels) ? kFuseTyTall : kFuseTyShort;
+    const bool huge = npx >= kFuseHugePixels && fuse_tile_fits(kFuseTyHuge, p.patch, p.stride);
+    pl.fuse_ty[n] = flow                      ? kFuseTyShort
+                    : huge                    ? kFuseTyHuge
+                    : npx >= kFuseTallPixels ? kFuseTyTall
+                                              : kFuseTyShort;
     pl.pyr_tall[n] = npx >= kPyrTallPixels;
   }
   assign_offsets(p, pl);

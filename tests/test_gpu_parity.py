@@ -433,6 +433,33 @@ def test_batch_matches_single(B):
     ctx.close()
 
 
+def test_batch_of_full_hd_pairs_matches_single(B):
+    """Three 1920x1080 pairs in one call (levels past 4 Mpx take the tallest
+    fusion tile, and the batch stages records from a separate probability
+    launch) equal each pair computed alone."""
+    import torch
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    p = B.params(**method_params(5))
+    lefts, rights = [], []
+    for idx in range(3):
+        l, r, _, _ = make_pair(5, idx)
+        lefts.append(to_gpu(l))
+        rights.append(to_gpu(r))
+    print("[gpu] batch of 3 full-HD pairs vs single", flush=True)
+    ctx = B.Context(p, 1920, 1080, max_batch=3)
+    outs = ctx.compute_batch(lefts, rights)
+    torch.cuda.synchronize()
+    outs = [{k: v.clone() for k, v in o.items()} for o in outs]
+    one_ctx = B.Context(p, 1920, 1080)
+    for i in range(3):
+        one = one_ctx.compute(lefts[i], rights[i])
+        torch.cuda.synchronize()
+        for k in ("disp", "var", "conf"):
+            assert torch.equal(torch.nan_to_num(outs[i][k], nan=-7.0), torch.nan_to_num(one[k], nan=-7.0)), (i, k)
+    one_ctx.close()
+    ctx.close()
+
+
 def test_graph_replays_match_eager(B, monkeypatch):
     """Replays of the captured launch sequence equal an eager context's result, call after call."""
     import torch
