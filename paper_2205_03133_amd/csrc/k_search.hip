@@ -347,35 +347,61 @@ __global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int
       const int m = (int)fm;
       const double f = u - fm;
       if (m != mc) {
+        // E(m) and E(m + 1).  With several rows per lane (throughput-bound
+        // mappings), a step into a neighbouring cell keeps the shared end's
+        // value and correlates one position; the whole wavefront skips the
+        // second position when none of its patches jumped further.  One row per
+        // lane (latency-bound mappings) always correlates both positions, which
+        // keeps the two dependent chains interleaved.
+        constexpr bool kReuse = R >= 2;
+        const bool up = kReuse && m == mc + 1, down = kReuse && mc == m + 1, both = !up && !down;
+        const int pos = up ? m + 1 : m;
         int cg0 = 0, cs0 = 0, cg1 = 0, cs1 = 0;
 #pragma unroll
         for (int k = 0; k < R; ++k) {
           uint32_t B[NW + 1];
-          fetch_words<NW>(B, win + rrow[k] * RWB, xs, rw, grow + (size_t)rrow[k] * a.pitch, ox + m, W);
-          uint32_t h0 = 0, l0 = 0, s0 = 0, h1 = 0, l1 = 0, s1 = 0;
+          fetch_words<NW>(B, win + rrow[k] * RWB, xs, rw, grow + (size_t)rrow[k] * a.pitch, ox + pos, W);
+          uint32_t h0 = 0, l0 = 0, s0 = 0;
 #pragma unroll
           for (int w = 0; w < NW; ++w) {
-            const uint32_t a0 = B[w], a1 = shifted_word<NW, 1>(B, w);
-            h0 = dot4(a0, Ghw[k][w], h0);
-            l0 = dot4(a0, Glw[k][w], l0);
-            s0 = dot4(a0, ones_word(w, P), s0);
-            h1 = dot4(a1, Ghw[k][w], h1);
-            l1 = dot4(a1, Glw[k][w], l1);
-            s1 = dot4(a1, ones_word(w, P), s1);
+            h0 = dot4(B[w], Ghw[k][w], h0);
+            l0 = dot4(B[w], Glw[k][w], l0);
+            s0 = dot4(B[w], ones_word(w, P), s0);
           }
           if (rlive[k]) {
             cg0 += 256 * (int)h0 + (int)l0 - 1024 * (int)s0;
             cs0 += (int)s0;
-            cg1 += 256 * (int)h1 + (int)l1 - 1024 * (int)s1;
-            cs1 += (int)s1;
+          }
+          if (both) {
+            uint32_t h1 = 0, l1 = 0, s1 = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+              const uint32_t a1 = shifted_word<NW, 1>(B, w);
+              h1 = dot4(a1, Ghw[k][w], h1);
+              l1 = dot4(a1, Glw[k][w], l1);
+              s1 = dot4(a1, ones_word(w, P), s1);
+            }
+            if (rlive[k]) {
+              cg1 += 256 * (int)h1 + (int)l1 - 1024 * (int)s1;
+              cs1 += (int)s1;
+            }
           }
         }
         cg0 = group_sum<G>(cg0);
         cs0 = group_sum<G>(cs0);
-        cg1 = group_sum<G>(cg1);
-        cs1 = group_sum<G>(cs1);
-        E0 = exact_ab_cd(N, cg0 - sGT, sG, cs0 - sT);
-        E1 = exact_ab_cd(N, cg1 - sGT, sG, cs1 - sT);
+        const double En = exact_ab_cd(N, cg0 - sGT, sG, cs0 - sT);
+        if (both) {
+          cg1 = group_sum<G>(cg1);
+          cs1 = group_sum<G>(cs1);
+          E0 = En;
+          E1 = exact_ab_cd(N, cg1 - sGT, sG, cs1 - sT);
+        } else if (up) {
+          E0 = E1;
+          E1 = En;
+        } else {
+          E1 = E0;
+          E0 = En;
+        }
         mc = m;
       }
       u -= ((1.0 - f) * E0 + f * E1) * step;
