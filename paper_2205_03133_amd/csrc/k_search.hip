@@ -144,8 +144,15 @@ BDIS_DEV void stage_row(uint32_t* dst, const uint8_t* rp, int W, int x0, int nd,
   }
 }
 
+// Waves per SIMD the register allocation must allow: five for the
+// several-rows-per-lane mappings (throughput-bound levels).
+template <int P, int G>
+constexpr int search_min_waves() {
+  return (P + G - 1) / G >= 2 ? 5 : 1;
+}
+
 template <int P, int G, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_search_u8(const PairLevel* tab, int npairs, LevelParams lp) {
+__global__ __launch_bounds__(THREADS, (search_min_waves<P, G>())) void k_search_u8(const PairLevel* tab, int npairs, LevelParams lp) {
   static_assert(G >= 2 && G <= 16 && THREADS % 64 == 0, "lanes per patch and workgroup size");
   constexpr int R = (P + G - 1) / G;             // patch rows per lane: rows g*R .. g*R+R-1
   constexpr bool kAllRows = R * G == P;          // no lane holds rows past the patch
