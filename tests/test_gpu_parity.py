@@ -433,19 +433,25 @@ def test_batch_matches_single(B):
     ctx.close()
 
 
-def test_batch_of_full_hd_pairs_matches_single(B):
-    """Three 1920x1080 pairs in one call (levels past 4 Mpx take the tallest
-    fusion tile, and the batch stages records from a separate probability
-    launch) equal each pair computed alone."""
+@pytest.mark.parametrize("over", [
+    dict(),                                     # 64 x 32 tiles, separable sums, records from k_prob
+    dict(levels=3, patch=16, stride=16),        # 64 x 32 tiles with inline records (few patches)
+    dict(levels=4, fusion=1),                   # 64 x 32 tiles, Eq. 2 weights (no separable form)
+    dict(levels=3, patch=8, stride=2, iters=4),  # stride too small for 64 x 32: 64 x 16 tiles
+], ids=["c5", "inline", "eq2", "stride2"])
+def test_batch_of_full_hd_pairs_matches_single(B, over):
+    """Three 1920x1080 pairs in one call (levels past 4 Mpx over the batch take
+    the tallest fusion tile where its covering patches fit the staged form)
+    equal each pair computed alone (64 x 16 tiles)."""
     import torch
     from paper_2205_03133_amd.synth import make_pair, method_params
-    p = B.params(**method_params(5))
+    p = B.params(**{**method_params(5), **over})
     lefts, rights = [], []
     for idx in range(3):
         l, r, _, _ = make_pair(5, idx)
         lefts.append(to_gpu(l))
         rights.append(to_gpu(r))
-    print("[gpu] batch of 3 full-HD pairs vs single", flush=True)
+    print(f"[gpu] batch of 3 full-HD pairs vs single {over}", flush=True)
     ctx = B.Context(p, 1920, 1080, max_batch=3)
     outs = ctx.compute_batch(lefts, rights)
     torch.cuda.synchronize()
