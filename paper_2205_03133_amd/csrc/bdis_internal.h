@@ -170,9 +170,9 @@ struct LevelParams {
 };
 
 // Tile shapes of the flattened launches.
-// Pyramid tiles: 64 x 4 output pixels (small levels) or 120 x 16 (levels of at
+// Pyramid tiles: 64 x 4 output pixels (small levels) or 120 x 12 (levels of at
 // least kPyrTallPixels pixels over the batch).
-constexpr int kPyrSmallTx = 64, kPyrSmallTy = 4, kPyrTallTx = 120, kPyrTallTy = 16;
+constexpr int kPyrSmallTx = 64, kPyrSmallTy = 4, kPyrTallTx = 120, kPyrTallTy = 12;
 constexpr long kPyrTallPixels = 1 << 18;
 constexpr int kProbThreads = 256;           // probability: patches per workgroup
 // Levels with at most this many patches (over the batch) have their level

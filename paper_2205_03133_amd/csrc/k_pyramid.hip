@@ -7,9 +7,9 @@
 // k_pyr_small (small levels, latency-bound): 64 x 4 output tiles, each lane
 //   gathers its five source columns of 11 source rows and filters them
 //   horizontally into LDS, then vertically: few dependent steps.
-// k_pyr_tall (large levels, bandwidth-bound): 120 x 16 output tiles, in three
+// k_pyr_tall (large levels, bandwidth-bound): 120 x 12 output tiles, in three
 //   passes:
-//   1. the 2 x 16 + 3 source rows of the tile (62 words of 4 bytes each) are
+//   1. the 2 x 12 + 3 source rows of the tile (62 words of 4 bytes each) are
 //      staged in LDS, one 4-byte load per word, all of a lane's loads in
 //      flight at once; out-of-image columns of border tiles are then filled
 //      from the staged in-image bytes (reflect-101);
@@ -70,7 +70,9 @@ static_assert(kSrcWords <= 64, "one staged word per lane");
 constexpr int kQuads = kPyrTallTx / 4;               // output column quads per row
 static_assert(kPyrTallTx % 4 == 0, "four output columns per lane");
 
-__global__ __launch_bounds__(kPyrThreads) void k_pyr_tall(const PairLevel* tab, int npairs) {
+// Five waves per SIMD (at most 96 VGPRs, no spills; 26 KB of LDS allows six
+// workgroups per CU).
+__global__ __launch_bounds__(kPyrThreads, 5) void k_pyr_tall(const PairLevel* tab, int npairs) {
   __shared__ uint32_t s_src[2][kSrcRows][kSrcWords];
   __shared__ uint2 s_h[2][kSrcRows][kQuads];  // four 16-bit horizontal sums per entry
   const int b = xcd_block();
