@@ -86,7 +86,7 @@ typedef struct {
   int32_t float_pyramid;   /* 0: uint8 entry points (integer pyramid); 1: float entry points */
   float sigma_s;           /* spatial sigma of the mixture kernel, level px (paper: 4)       */
   float sigma_r;           /* fixed sigma_r (dynamic == 0) or its scale alpha_r (dynamic)   */
-  float valid_ratio;       /* gamma: least in-bounds fraction of an accepted patch (0.75)    */
+  float valid_ratio;       /* gamma in (0, 1]: least in-bounds fraction of an accepted patch  */
   float var_fail_sigma;    /* sigma given to a failed variance fit; <= 0 means P             */
   float var_fit_thresh;    /* largest mean squared fit residual of Eq. 17 (paper: 0.1)       */
   float prob_thresh;       /* confidence below this is invalid; 0 disables (paper: 0.15)     */

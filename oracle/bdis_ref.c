@@ -293,6 +293,31 @@ static double patch_variance(const double* s, double tau, double thresh, double 
 }
 
 /* ------------------------------------------------------------------------- */
+/* O4: start of every patch of a level below the coarsest.  Each patch starts  */
+/* from the parent level's fused map at its centre (Fig. 1: initialised with  */
+/* the prediction of the last level), scaled by 2 because a parent pixel      */
+/* spans two pixels of this level (Sec. III-B); the probability propagated to */
+/* the patch is the parent confidence at the same point.  Centre             */
+/* c = origin + (P - 1) / 2 in this level's pixels, (c_x / 2, c_y / 2) in the  */
+/* parent's, bilinear with indices clamped to the parent map.                 */
+/* ------------------------------------------------------------------------- */
+int bdis_ref_parent_init(const double* ubar, const double* qmap, int pw, int ph, int w, int h, int P, int S,
+                         double* uinit, double* pipar) {
+  if (!ubar || !qmap || !uinit || !pipar || pw < 1 || ph < 1 || P < 1 || S < 1 || w < P || h < P)
+    return BDIS_REF_E_ARG;
+  const int nx = grid_count(w, P, S), ny = grid_count(h, P, S);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const int k = j * nx + i;
+      const double cx = grid_origin(i, w, P, S) + 0.5 * (P - 1);
+      const double cy = grid_origin(j, h, P, S) + 0.5 * (P - 1);
+      uinit[k] = 2.0 * bilinear(ubar, pw, ph, 0.5 * cx, 0.5 * cy);
+      pipar[k] = bilinear(qmap, pw, ph, 0.5 * cx, 0.5 * cy);
+    }
+  return BDIS_REF_OK;
+}
+
+/* ------------------------------------------------------------------------- */
 /* driver                                                                    */
 /* ------------------------------------------------------------------------- */
 
@@ -351,6 +376,7 @@ static int check_params(const bdis_ref_params* p, int w, int h, int pitch) {
   if (p->patch < 3 || p->stride < 1 || p->stride > p->patch || p->iters < 1) return BDIS_REF_E_ARG;
   if (p->fusion < 0 || p->fusion > 2 || (p->propagate != 0 && p->propagate != 1)) return BDIS_REF_E_ARG;
   if (!(p->sigma_s > 0.0) || !(p->sigma_r > 0.0)) return BDIS_REF_E_ARG;
+  if (!(p->valid_ratio > 0.0) || p->valid_ratio > 1.0) return BDIS_REF_E_ARG; /* gamma is a fraction of the patch */
   if (w < 1 || h < 1 || pitch < w) return BDIS_REF_E_ARG;
   double wsum = 0.0;
   for (int n = p->finest_level; n < p->levels; ++n) {
@@ -506,22 +532,11 @@ static int run(const bdis_ref_params* p, const double* left0, const double* righ
     const ref_level* par = (n + 1 < L) ? &t->lv[n + 1] : NULL;
     const int np = lv->nx * lv->ny;
 
-    /* O4: each patch starts from the parent level's fused map at its centre
-     * (Fig. 1: initialised with the prediction of the last level), scaled by
-     * 2; the propagated probability is the parent confidence there. */
-    for (int j = 0; j < lv->ny; ++j)
-      for (int i = 0; i < lv->nx; ++i) {
-        int k = j * lv->nx + i;
-        double cx = grid_origin(i, lv->w, P, S) + 0.5 * (P - 1);
-        double cy = grid_origin(j, lv->h, P, S) + 0.5 * (P - 1);
-        if (par) {
-          lv->uinit[k] = 2.0 * bilinear(par->ubar, par->w, par->h, 0.5 * cx, 0.5 * cy);
-          lv->pipar[k] = bilinear(par->qmap, par->w, par->h, 0.5 * cx, 0.5 * cy);
-        } else {
-          lv->uinit[k] = 0.0;
-          lv->pipar[k] = 0.0;
-        }
-      }
+    /* O4 */
+    if (par)
+      bdis_ref_parent_init(par->ubar, par->qmap, par->w, par->h, lv->w, lv->h, P, S, lv->uinit, lv->pipar);
+    else
+      for (int k = 0; k < np; ++k) lv->uinit[k] = lv->pipar[k] = 0.0;
 
     /* O5-O8 */
     for (int j = 0; j < lv->ny; ++j)

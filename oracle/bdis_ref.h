@@ -32,7 +32,7 @@ typedef struct {
   int32_t float_pyramid;   /* 1: pyramid without integer rounding (used by the f64 entry)   */
   double sigma_s;          /* spatial sigma of the patch mixture kernel (level px)          */
   double sigma_r;          /* fixed sigma_r, or the scale alpha_r when dynamic              */
-  double valid_ratio;      /* gamma: minimum in-bounds fraction of an accepted patch        */
+  double valid_ratio;      /* gamma in (0, 1]: minimum in-bounds fraction of an accepted patch */
   double var_fail_sigma;   /* sigma assigned to a failed variance fit; <= 0 means P         */
   double var_fit_thresh;   /* largest accepted mean squared fit residual (ln-p units)       */
   double prob_thresh;      /* pixels with confidence below this are invalid; 0 = off        */
@@ -99,6 +99,13 @@ double bdis_ref_trace_scalar(const bdis_ref_trace* t, int level, int what);
  * variance-fit outcomes, holes): equal hashes mean equal branches. */
 uint64_t bdis_ref_trace_hash(const bdis_ref_trace* t, int level);
 void bdis_ref_trace_free(bdis_ref_trace* t);
+
+/* Start of the patches of a w x h level from the parent level's fused maps
+ * (pw x ph): per patch k of the level's grid (row-major), uinit[k] = 2 ubar and
+ * pipar[k] = qmap, both sampled bilinearly (indices clamped) at half the patch
+ * centre.  The same routine the compute entry points use between levels. */
+int bdis_ref_parent_init(const double* ubar, const double* qmap, int pw, int ph, int w, int h, int P, int S,
+                         double* uinit, double* pipar);
 
 /* Patch-grid origins along an axis of length n; returns the count or < 0. */
 int bdis_ref_grid(int n, int patch, int stride, int* origins, int cap);

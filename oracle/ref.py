@@ -98,6 +98,7 @@ def lib():
         L.bdis_ref_grid.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_int), ctypes.c_int]
         L.bdis_ref_mask.argtypes = [ctypes.c_int, ctypes.c_double, dp]
+        L.bdis_ref_parent_init.argtypes = [dp, dp] + [ctypes.c_int] * 6 + [dp, dp]
         L.bdis_ref_depth.argtypes = [dp, dp, ctypes.c_long, ctypes.c_double, dp, dp]
         L.bdis_ref_flow.argtypes = [ctypes.POINTER(RefParams), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                     ctypes.c_int, ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_void_p)]
@@ -195,6 +196,25 @@ def mask(patch, sigma_s):
     if st:
         raise OracleError(st)
     return out
+
+
+def parent_init(ubar, qmap, w, h, patch, stride):
+    """Start displacement and propagated probability of every patch of a w x h
+    level from the parent level's fused maps (ny x nx arrays each)."""
+    ubar = np.ascontiguousarray(ubar, dtype=np.float64)
+    qmap = np.ascontiguousarray(qmap, dtype=np.float64)
+    if ubar.shape != qmap.shape or ubar.ndim != 2:
+        raise ValueError("parent maps must be equal 2-D arrays")
+    ph, pw = ubar.shape
+    ny, nx = len(grid(h, patch, stride)), len(grid(w, patch, stride))
+    dp = ctypes.POINTER(ctypes.c_double)
+    u0 = np.empty((ny, nx), np.float64)
+    pi = np.empty((ny, nx), np.float64)
+    st = lib().bdis_ref_parent_init(ubar.ctypes.data_as(dp), qmap.ctypes.data_as(dp), pw, ph, w, h, patch,
+                                    stride, u0.ctypes.data_as(dp), pi.ctypes.data_as(dp))
+    if st:
+        raise OracleError(st)
+    return u0, pi
 
 
 def grid(n, patch, stride):

@@ -380,6 +380,9 @@ class Context:
         if st:
             raise self._err(st)
         self._last_f32 = (B, h, w, L.device)
+        # backward differentiates the latest float call only: callers that keep
+        # several calls' graphs check this counter (see the autograd Function)
+        self.f32_generation = getattr(self, "f32_generation", 0) + 1
         if single:
             return dict(disp=disp[0], var=var[0] if var is not None else None,
                         conf=conf[0] if conf is not None else None)
@@ -470,6 +473,7 @@ def _autograd_function():
             _set_hyper(bctx, sigma_s.item(), sigma_r.item(), omega.detach().cpu().tolist())
             out = bctx.compute_f32(left.detach().contiguous(), right.detach().contiguous())
             fctx.bctx = bctx
+            fctx.generation = bctx.f32_generation
             fctx.shapes = (left.shape, omega.shape, sigma_s.dtype, omega.dtype, sigma_s.device, sigma_r.device,
                            omega.device)
             var = out["var"] if out["var"] is not None else torch.zeros_like(out["disp"])
@@ -479,6 +483,10 @@ def _autograd_function():
         @staticmethod
         def backward(fctx, g_disp, g_var):
             import torch
+            if fctx.bctx.f32_generation != fctx.generation:
+                # the library keeps the saved state of its latest float call only
+                raise RuntimeError("BDIS backward: the context has run another forward since this node's; "
+                                   "use one context per pending node (or call backward before the next forward)")
             g_disp = torch.nan_to_num(g_disp) if g_disp is not None else None
             g_var = torch.nan_to_num(g_var) if (g_var is not None and fctx.has_var) else None
             if g_disp is None:

@@ -1,6 +1,10 @@
-"""Build of the gfx950 HIP library ``libbdis.so`` (in-tree, next to this file)."""
+"""Build of the gfx950 HIP library ``libbdis.so`` (in-tree, next to this file).
+
+Each HIP source is compiled to an object of its own (in parallel), then the
+objects are linked into the shared library."""
 from __future__ import annotations
 
+import concurrent.futures as cf
 import glob
 import os
 import subprocess
@@ -10,6 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "libbdis.so")
+OBJ_DIR = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -17,6 +22,8 @@ ARCH = "gfx950"
 # Packed FP32 instructions are disabled for all device code; hipcc's host pass
 # warns that it does not know the feature, which is harmless.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+COMMON = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-command-line-argument",
+          f"-I{INCLUDE}", f"-I{CSRC}"]
 
 
 def sources():
@@ -27,24 +34,42 @@ def headers():
     return sorted(glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(INCLUDE, "*.h")))
 
 
+def compile_command(src, obj):
+    return [HIPCC] + COMMON + DEVICE_FLAGS + ["-c", "-o", obj, src]
+
+
+def link_command(objs, out):
+    return [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out] + objs
+
+
 def command(out):
-    return ([HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-             "-Wall", "-Wno-unused-command-line-argument", f"-I{INCLUDE}", f"-I{CSRC}"]
-            + DEVICE_FLAGS + ["-o", out] + sources())
+    """The single-step form of the build (every source in one hipcc call)."""
+    return [HIPCC] + COMMON + ["-shared"] + DEVICE_FLAGS + ["-o", out] + sources()
 
 
-def build(force=True, verbose=False):
+def _run(cmd):
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stdout + res.stderr)
+
+
+def build(force=True, verbose=False, jobs=None):
     """Compile every HIP source into ``libbdis.so`` (always recompiles unless force=False)."""
     if not force and os.path.exists(LIB_PATH) and all(
             os.path.getmtime(LIB_PATH) >= os.path.getmtime(s) for s in sources() + headers()):
         return LIB_PATH
-    tmp = LIB_PATH + ".tmp"
-    cmd = command(tmp)
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    srcs = sources()
+    objs = [os.path.join(OBJ_DIR, os.path.basename(s)[:-4] + ".o") for s in srcs]
+    cmds = [compile_command(s, o) for s, o in zip(srcs, objs)]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
+        for c in cmds:
+            print(" ".join(c), flush=True)
+    jobs = jobs or min(len(cmds), max(1, min(16, os.cpu_count() or 1)))
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(_run, cmds))
+    tmp = LIB_PATH + ".tmp"
+    _run(link_command(objs, tmp))
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 

@@ -371,7 +371,7 @@ BDIS_DEV void patch_adj(const PairLevel& a, const LevelParams& lp, int k, int r,
       for (int c = 0; c <= P; ++c) {
         if (acc[c] == 0.0) continue;
         const int x = clampi(ox + mcur + c, 0, W - 1);
-        if (x - xr0 < twr)
+        if (x - xr0 >= 0 && x - xr0 < twr)
           unsafeAtomicAdd(sR + rr * twr + (x - xr0), acc[c]);
         else
           atomic_add_d(Rbar_row + x, acc[c]);
@@ -583,7 +583,9 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLeve
     __syncthreads();
     if (s_lo == INT_MAX) return;  // no accepted patch here (uniform)
   }
-  const int xr0 = twl > 0 ? s_lo : 0;
+  // the right tile starts at the lowest cell, but never past the last column:
+  // scatters are clamped to the row, so every one of them lands at or after it
+  const int xr0 = twl > 0 ? min(s_lo, W - 1) : 0;
   if (active) patch_adj<P>(a, lp, k, r, ox, oy, oxa, xr0, twl, twr, sL, sG, sR);
   if (twl == 0) return;
   __syncthreads();

@@ -297,7 +297,8 @@ bdis_status check_params_msg(const bdis_params* p, char* msg, size_t n) {
   if (p->propagate != 0 && p->propagate != 1) return snprintf(msg, n, "propagate must be 0 or 1"), BDIS_E_ARG;
   if (!finite_f(p->sigma_s) || !(p->sigma_s > 0.0f)) return snprintf(msg, n, "sigma_s must be > 0"), BDIS_E_ARG;
   if (!finite_f(p->sigma_r) || !(p->sigma_r > 0.0f)) return snprintf(msg, n, "sigma_r must be > 0"), BDIS_E_ARG;
-  if (!finite_f(p->valid_ratio)) return snprintf(msg, n, "valid_ratio not finite"), BDIS_E_ARG;
+  if (!finite_f(p->valid_ratio) || !(p->valid_ratio > 0.0f) || p->valid_ratio > 1.0f)
+    return snprintf(msg, n, "valid_ratio %g outside (0, 1]", (double)p->valid_ratio), BDIS_E_ARG;
   if (!finite_f(p->var_fail_sigma) || !finite_f(p->var_fit_thresh) || !finite_f(p->prob_thresh))
     return snprintf(msg, n, "variance/threshold parameters not finite"), BDIS_E_ARG;
   float wsum = 0.0f;

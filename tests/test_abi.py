@@ -36,7 +36,8 @@ def test_defaults_follow_paper(B):
                                 dict(iters=0), dict(levels=0), dict(levels=9), dict(sigma_s=0.0),
                                 dict(sigma_r=-1.0), dict(finest_level=5), dict(finest_level=-1), dict(float_pyramid=2),
                                 dict(level_weight=[0.0] * 8), dict(sigma_s=float("nan")), dict(fusion=3),
-                                dict(fusion=-1), dict(propagate=2)])
+                                dict(fusion=-1), dict(propagate=2), dict(valid_ratio=0.0),
+                                dict(valid_ratio=-0.5), dict(valid_ratio=1.25), dict(valid_ratio=float("inf"))])
 def test_bad_params_rejected(B, kw):
     assert B.check(B.params(**kw)) == B.E_ARG
 

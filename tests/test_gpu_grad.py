@@ -86,6 +86,77 @@ def test_backward_matches_gradient_oracle(B, oracle, shape, kw):
     ctx.close()
 
 
+def _backward_vs_oracle(B, oracle, pairs, kw, seed=2):
+    """GPU backward of a batch of float pairs against the FP64 gradient oracle,
+    pair by pair (image gradients) and summed (hyper-gradients)."""
+    from oracle import grad_ref as GR
+    h, w = pairs[0][0].shape
+    p = _fparams(B, **kw)
+    n = len(pairs)
+    rng = np.random.default_rng(seed)
+    vd = [rng.standard_normal((h, w)).astype(np.float32) for _ in range(n)]
+    vv = [(0.01 * rng.standard_normal((h, w))).astype(np.float32) for _ in range(n)] if p.variance else None
+    ctx = B.Context(p, w, h, max_batch=n, train=True)
+    L = torch.stack([torch.from_numpy(q[0]) for q in pairs]).cuda()
+    R = torch.stack([torch.from_numpy(q[1]) for q in pairs]).cuda()
+    ctx.compute_f32(L, R)
+    gl, gr, gh = ctx.backward(torch.from_numpy(np.stack(vd)).cuda(),
+                              torch.from_numpy(np.stack(vv)).cuda() if vv is not None else None)
+    torch.cuda.synchronize()
+    gl, gr, gh = gl.cpu().numpy(), gr.cpu().numpy(), gh.cpu().numpy()
+    hyp = 0.0
+    for b in range(n):
+        ref = GR.loss_and_grads(pairs[b][0].astype(np.float64), pairs[b][1].astype(np.float64),
+                                oracle_params(oracle, p), vd[b].astype(np.float64),
+                                vv[b].astype(np.float64) if vv is not None else None)
+        e_l, e_r = _rel(gl[b], ref["left"]), _rel(gr[b], ref["right"])
+        print(f"  pair {b}: rel err left {e_l:.2e} right {e_r:.2e}", flush=True)
+        assert e_l <= 1e-3 and e_r <= 1e-3
+        hyp = hyp + np.array([ref["sigma_s"], ref["sigma_r"]] + list(ref["omega"]))
+    print(f"  hyper gpu {gh} oracle {hyp}", flush=True)
+    np.testing.assert_allclose(gh, hyp, rtol=1e-3, atol=1e-6 * np.abs(hyp).max())
+    ctx.close()
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_backward_full_size_differentiation_workload(B, oracle, n):
+    """The differentiation workload's shape: 640x480 float pairs, 4 levels, 8x8
+    patches, stride 4, K = 8 unrolled; one pair and a batch of two."""
+    pairs = [_pair(480, 640, seed=10 + b) for b in range(n)]
+    print(f"[gpu] backward 640x480 L4 P8 S4 K8, batch {n}", flush=True)
+    _backward_vs_oracle(B, oracle, pairs, dict(levels=4, iters=8, variance=0))
+
+
+def test_backward_untiled_search_adjoint(B, oracle):
+    """Patch 16 at stride 10: the search adjoint's LDS accumulation tiles do not
+    fit, so every scatter of that kernel goes straight to HBM."""
+    print("[gpu] backward 160x96 L2 P16 S10 K6 (untiled search adjoint)", flush=True)
+    _backward_vs_oracle(B, oracle, [_pair(96, 160, seed=4)], dict(levels=2, patch=16, stride=10, iters=6))
+
+
+def test_autograd_rejects_stale_node(B):
+    """Two forwards on one context, then backward of the first: the context keeps
+    only the latest call's saved state, so the stale node raises instead of
+    returning the second call's gradients."""
+    h, w = 64, 96
+    left, right, _, _ = _pair(h, w, seed=3)
+    ctx = B.Context(_fparams(B, levels=2, iters=6), w, h, train=True)
+    fn = B.bdis_function()
+    ss = torch.tensor(4.0, dtype=torch.float64, requires_grad=True)
+    sr = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    om = torch.tensor([1.0, 2.0], dtype=torch.float64, requires_grad=True)
+    print("[gpu] autograd stale node", flush=True)
+    lt = torch.from_numpy(left).cuda().requires_grad_(True)
+    d1, _ = fn.apply(lt, torch.from_numpy(right).cuda(), ss, sr, om, ctx)
+    d2, _ = fn.apply(lt, torch.from_numpy(left).cuda(), ss, sr, om, ctx)
+    with pytest.raises(RuntimeError, match="another forward"):
+        torch.nan_to_num(d1).sum().backward()
+    torch.nan_to_num(d2).sum().backward()  # the latest node still works
+    torch.cuda.synchronize()
+    assert torch.isfinite(lt.grad).all()
+    ctx.close()
+
+
 def test_backward_batch_equals_single(B):
     h, w = 64, 96
     p = _fparams(B, levels=2, iters=6)

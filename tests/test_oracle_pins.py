@@ -359,6 +359,135 @@ def test_rejected_saddle(oracle):
         assert (~acc).sum() > 0
 
 
+def _inbounds_columns(ox, u, w, P):
+    """Columns c = 0..P-1 of a patch at origin ox whose sample x = ox + c + u lies
+    on the image row [0, w-1] (Sec. III-F / IV-A: valid pixels of a patch)."""
+    xr = ox[None, :, None] + np.arange(P)[None, None, :] + u[..., None]
+    return ((xr >= 0.0) & (xr <= w - 1.0)).sum(axis=-1)
+
+
+def _edge_shift_pair(seed, h, w, D):
+    """Integer shift D whose clamped border samples still match: the left view is
+    constant over the columns whose match falls off the right image (x < D for
+    D > 0, x > W-1-|D| for D < 0), so u = -D has zero residual on every patch,
+    the straddling ones included."""
+    canvas = np.rint(texture(seed, h, w + 2 * abs(D) + 2)).astype(np.uint8)
+    off = abs(D) + 1
+    if D > 0:
+        canvas[:, off:off + D] = canvas[:, off + D:off + D + 1]
+    else:
+        e = off + w - 1 - abs(D)
+        canvas[:, e + 1:off + w] = canvas[:, e:e + 1]
+    left = canvas[:, off:off + w]
+    right = canvas[:, off + D:off + D + w]
+    return np.ascontiguousarray(left), np.ascontiguousarray(right)
+
+
+@pytest.mark.parametrize("D", [5, -5])
+def test_inbounds_ratio_geometry(oracle, D):
+    """The in-bounds ratio behind gamma (Sec. III-F, Sec. IV-A: a patch without
+    enough valid pixels is discarded): for an exact-shift pair whose border
+    patches hang over the image edge (the left edge for D > 0, the right edge
+    for D < 0), rho is the count of patch columns whose warped position lies on
+    [0, W-1] divided by P (every row shifts alike), and it matches the column
+    count the known shift gives, up to the one column the converged u can put
+    on either side of an edge.  Acceptance then flips exactly when gamma
+    passes rho."""
+    h, w, P, S = 40, 72, 8, 2
+    left, right = _edge_shift_pair(40 + D, h, w, D)
+    ox = oracle.grid(w, P, S)
+    runs = {}
+    for k in (5, 6):  # gamma = k / P and just above it
+        for gam in (k / P, (k + 0.5) / P):
+            p = oracle.default_params(levels=3, patch=P, stride=S, iters=32, valid_ratio=gam)
+            runs[gam] = oracle.compute(left, right, p, trace=True)["trace"]
+    tr = runs[5 / P]
+    u, rho, ssd = tr.get(0, "u"), tr.get(0, "rho"), tr.get(0, "ssd")
+    cols = _inbounds_columns(ox, u, w, P)
+    np.testing.assert_array_equal(rho * P, cols.astype(np.float64))
+    # border patches straddle the edge: some columns in, some out
+    part = (cols > 0) & (cols < P)
+    assert part.sum() >= 2 * tr.dims(0)[3]
+    # against the known shift: columns x = ox + c - D on [0, W-1], up to one
+    # column on the edge itself (u = -D only to ~1e-6 there)
+    near = np.abs(u + D) < 1e-3
+    assert near[part].sum() >= tr.dims(0)[3]
+    exact = _inbounds_columns(ox, np.full(u.shape, -float(D)), w, P)
+    d = (cols - exact)[near]
+    assert np.all((d >= -1) & (d <= 1))
+    # acceptance: centre minimum of the window and rho >= gamma, flipping at
+    # gamma = rho (gamma also steers the coarser levels, so each run is checked
+    # on its own displacements)
+    def decided(t):
+        sd, rh = t.get(0, "ssd"), t.get(0, "rho")
+        return np.all(sd[..., 2:3] <= sd, axis=-1), rh, t.get(0, "acc") > 0
+    flipped = 0
+    for gam, t in runs.items():
+        cm, rh, acc = decided(t)
+        assert np.array_equal(acc, cm & (rh >= gam))
+    for k in (5, 6):
+        cm_a, rh_a, at = decided(runs[k / P])
+        cm_b, rh_b, above = decided(runs[(k + 0.5) / P])
+        on_edge = (rh_a * P == k) & (rh_b * P == k) & cm_a & cm_b
+        assert np.all(at[on_edge]) and not np.any(above[on_edge])
+        flipped += int(on_edge.sum())
+    assert flipped >= 4
+
+
+def _parent_centres(oracle, w, h, P, S):
+    cx = oracle.grid(w, P, S) + 0.5 * (P - 1)
+    cy = oracle.grid(h, P, S) + 0.5 * (P - 1)
+    return np.meshgrid(cx, cy)
+
+
+def test_parent_init_constant_map(oracle):
+    """A constant parent map c starts every patch at u0 = 2c with Pi = c
+    (Fig. 1: each level is initialised with the prediction of the last; one
+    parent pixel spans two pixels of this level, Sec. III-B)."""
+    w, h, P, S = 61, 45, 8, 3
+    pw, ph = (w + 1) // 2, (h + 1) // 2
+    for c, q in ((-3.25, 0.625), (1.5, 0.0), (0.0, 1.0)):
+        u0, pi = oracle.parent_init(np.full((ph, pw), c), np.full((ph, pw), q), w, h, P, S)
+        assert u0.shape == (len(oracle.grid(h, P, S)), len(oracle.grid(w, P, S)))
+        assert np.all(u0 == 2.0 * c) and np.all(pi == q)
+
+
+@pytest.mark.parametrize("a,b,e", [(0.25, -0.125, 3.0), (-1.5, 0.75, -2.0)])
+def test_parent_init_affine_map(oracle, a, b, e):
+    """An affine parent map a x + b y + e is reproduced exactly by bilinear
+    sampling, so away from the clamped border u0 = 2 (a c_x / 2 + b c_y / 2 + e)
+    at the patch centre c = origin + (P - 1) / 2; Pi samples the confidence map
+    at the same point.  Past the parent's last row / column the indices clamp:
+    there the start is the border value's extension."""
+    w, h, P, S = 70, 52, 8, 3
+    pw, ph = (w + 1) // 2, (h + 1) // 2
+    X, Y = np.meshgrid(np.arange(pw, dtype=np.float64), np.arange(ph, dtype=np.float64))
+    ubar = a * X + b * Y + e
+    qmap = 0.5 + 0.01 * X - 0.02 * Y
+    u0, pi = oracle.parent_init(ubar, qmap, w, h, P, S)
+    CX, CY = _parent_centres(oracle, w, h, P, S)
+    inside = (CX / 2 <= pw - 1) & (CY / 2 <= ph - 1)
+    assert inside.sum() > 100
+    np.testing.assert_allclose(u0[inside], 2.0 * (a * CX / 2 + b * CY / 2 + e)[inside], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(pi[inside], (0.5 + 0.01 * CX / 2 - 0.02 * CY / 2)[inside], rtol=0, atol=1e-12)
+    # clamped: the sample position is pulled onto the last parent row / column
+    cxc, cyc = np.minimum(CX / 2, pw - 1), np.minimum(CY / 2, ph - 1)
+    np.testing.assert_allclose(u0, 2.0 * (a * cxc + b * cyc + e), rtol=0, atol=1e-12)
+
+
+def test_parent_init_used_between_levels(oracle):
+    """The start of every level-n patch in a full run is the parent-map sample of
+    the level above (the same map the fusion of level n + 1 produced)."""
+    left, right = shifted_pair_u8(7, 64, 96, 3)
+    p = oracle.default_params(levels=3, patch=8, stride=3, iters=8)
+    tr = oracle.compute(left, right, p, trace=True)["trace"]
+    for n in range(2):
+        w, h, _, _ = tr.dims(n)
+        u0, pi = oracle.parent_init(tr.get(n + 1, "ubar"), tr.get(n + 1, "qmap"), w, h, 8, 3)
+        assert np.array_equal(u0, tr.get(n, "uinit")) and np.array_equal(pi, tr.get(n, "pipar"))
+    assert np.all(tr.get(2, "uinit") == 0.0) and np.all(tr.get(2, "pipar") == 0.0)
+
+
 # --------------------------------------------------------------------------
 # O11-O12: mixture mask and densification
 # --------------------------------------------------------------------------
