@@ -145,6 +145,26 @@ bdis_status bdis_compute(bdis_ctx* ctx, const uint8_t* left, const uint8_t* righ
  * Errors: as bdis_compute, plus BDIS_E_CAPACITY if n > max_batch. */
 bdis_status bdis_compute_batch(bdis_ctx* ctx, int n, const bdis_pair* pairs, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): bdis_compute
+ * of one uint8 pair without a context.  Same arguments and outputs as
+ * bdis_compute, with the method parameters passed directly.  The workspace and
+ * job table live in a static device array of 48 MiB that the library holds on
+ * every device it runs on until the process ends; the call allocates nothing
+ * (no hipMalloc, no pinned staging, no graph) and does not tune (the default
+ * search configuration of each level).  Every call on a device shares that
+ * device's array and leaves its contents behind (each array is rewritten
+ * before it is read, so nothing needs clearing): calls that overlap on one
+ * device -- on different streams or from different host threads -- race, so
+ * order them on one stream.  The pass runs asynchronously on `stream`; the
+ * host is never synchronised.  Errors: BDIS_E_ARG, BDIS_E_SIZE,
+ * BDIS_E_CAPACITY (the pair's workspace does not fit the array: e.g. one
+ * 1920 x 1080 pair at patch 8, stride 3, 6 levels fits, a 4K pair does not;
+ * the message gives the bytes needed), BDIS_E_HIP.  The text of a failure is
+ * read with bdis_last_error(NULL). */
+bdis_status bdis_compute_static(const bdis_params* p, const uint8_t* left, const uint8_t* right, int w, int h,
+                                int pitch, float* disparity, float* variance, float* confidence, void* stream);
+
 /* ---- differentiable (float) path --------------------------------------- */
 
 /* bdis_create flag: size the workspace for the float path and keep the state
@@ -275,7 +295,8 @@ bdis_status bdis_level_dims(const bdis_params* p, int w, int h, int level, int* 
 /* Frees the context and its workspace (synchronises the device). NULL is a no-op. */
 void bdis_destroy(bdis_ctx* ctx);
 
-/* Text of the last error on ctx (or of the last failed bdis_create if ctx is NULL). */
+/* Text of the last error on ctx (or, with ctx NULL, of the last failed
+ * bdis_create or bdis_compute_static). */
 const char* bdis_last_error(const bdis_ctx* ctx);
 
 /* Library version string. */

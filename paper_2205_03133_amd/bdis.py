@@ -86,6 +86,7 @@ def lib():
         L.bdis_set_params.argtypes = [vp, pp]
         L.bdis_compute.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp, vp]
         L.bdis_compute_batch.argtypes = [vp, i32, ctypes.POINTER(Pair), vp]
+        L.bdis_compute_static.argtypes = [pp, vp, vp, i32, i32, i32, vp, vp, vp, vp]
         L.bdis_debug_dump.argtypes = [vp, i32, i32, vp, ctypes.c_size_t, vp]
         L.bdis_level_dims.argtypes = [pp, i32, i32, i32] + [ctypes.POINTER(i32)] * 4
         L.bdis_destroy.argtypes = [vp]
@@ -103,7 +104,7 @@ def lib():
         L.bdis_flow.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp]
         L.bdis_coverage.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, vp, vp]
         for name in ("bdis_params_default", "bdis_params_check", "bdis_create", "bdis_set_params",
-                     "bdis_compute", "bdis_compute_batch", "bdis_debug_dump", "bdis_level_dims",
+                     "bdis_compute", "bdis_compute_batch", "bdis_compute_static", "bdis_debug_dump", "bdis_level_dims",
                      "bdis_timing_enable", "bdis_timing_read", "bdis_compute_f32", "bdis_compute_f32_batch",
                      "bdis_backward", "bdis_backward_batch"):
             getattr(L, name).restype = ctypes.c_int
@@ -160,6 +161,38 @@ def _image_arg(t, name, dtype=None):
     if t.stride(1) != 1:
         raise ValueError(f"{name} must have unit column stride")
     return t.data_ptr(), t.shape[1], t.shape[0], t.stride(0)
+
+
+def compute_static(p, left, right, *, variance=None, confidence=True, out=None, stream=None):
+    """One uint8 pair through ``bdis_compute_static`` (no context, no allocation
+    inside the library: its workspace is a static device array).  Output
+    tensors are allocated here unless ``out`` holds them.  Returns
+    ``dict(disp, var, conf)`` as ``Context.compute``."""
+    import torch
+    lp, w, h, pitch = _image_arg(left, "left")
+    rp, w2, h2, pitch2 = _image_arg(right, "right")
+    if (w, h, pitch) != (w2, h2, pitch2) or left.device != right.device:
+        raise ValueError("left and right must have the same shape, row stride and device")
+    if variance is None:
+        variance = bool(p.variance)
+    out = dict(out or {})
+    dev = left.device
+    disp = out.get("disp")
+    if disp is None:
+        disp = torch.empty((h, w), dtype=torch.float32, device=dev)
+    var = out.get("var") if variance else None
+    if variance and var is None:
+        var = torch.empty((h, w), dtype=torch.float32, device=dev)
+    conf = out.get("conf") if confidence else None
+    if confidence and conf is None:
+        conf = torch.empty((h, w), dtype=torch.float32, device=dev)
+    with torch.cuda.device(dev):
+        st = lib().bdis_compute_static(ctypes.byref(p), lp, rp, w, h, pitch, disp.data_ptr(),
+                                       var.data_ptr() if var is not None else None,
+                                       conf.data_ptr() if conf is not None else None, _stream_ptr(stream))
+    if st:
+        raise BdisError(st, lib().bdis_last_error(None).decode())
+    return dict(disp=disp, var=var, conf=conf)
 
 
 class Context:

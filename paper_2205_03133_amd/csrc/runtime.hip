@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -202,6 +203,28 @@ struct PairSpec {
   float* flow_v = nullptr;
 };
 
+// Job-table entries of a plan: inline storage for the levels of one pair (a
+// single-pair plan touches no heap), a heap vector beyond that.
+struct PlanTab {
+  PairLevel fixed[kMaxLevels];
+  std::vector<PairLevel> heap;
+  size_t n = 0;
+  void push_back(const PairLevel& e) {
+    if (heap.empty() && n < (size_t)kMaxLevels) {
+      fixed[n++] = e;
+      return;
+    }
+    if (heap.empty()) heap.assign(fixed, fixed + n);
+    heap.push_back(e);
+    ++n;
+  }
+  size_t size() const { return n; }
+  PairLevel* data() { return heap.empty() ? fixed : heap.data(); }
+  const PairLevel* data() const { return heap.empty() ? fixed : heap.data(); }
+  PairLevel& operator[](size_t i) { return data()[i]; }
+  const PairLevel& operator[](size_t i) const { return data()[i]; }
+};
+
 // Launch plan of one call: level-major job table and workgroup counts.
 struct Plan {
   int max_levels = 0;
@@ -217,7 +240,7 @@ struct Plan {
   int fuse_ty[kMaxLevels]{};     // fusion tile height per level
   bool pyr_tall[kMaxLevels]{};   // pyramid level built with the large-tile kernel
   bool f32 = false;              // float (FP64) path: per-pixel pyramid blocks, fixed search size
-  std::vector<PairLevel> tab;
+  PlanTab tab;
 };
 
 // HIP events recorded around each launch while timing is enabled.
@@ -457,15 +480,20 @@ void assign_offsets(const bdis_params& p, Plan& pl) {
   }
 }
 
-bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* out, bool f32 = false,
+bdis_status build_plan(bdis_ctx* c, const PairSpec* pairs, size_t npairs, Plan* out, bool f32 = false,
                        bool flow = false) {
   const bdis_params& p = c->p;
-  Plan pl;
+  Plan& pl = *out;
+  pl = Plan();
   pl.finest = p.finest_level;
   pl.f32 = f32;
   pl.flow = flow;
-  std::vector<Layout> lays(pairs.size());
-  for (size_t i = 0; i < pairs.size(); ++i) {
+  // a single pair's layout lives on the stack (no heap use)
+  Layout lay_one;
+  std::vector<Layout> lay_many;
+  if (npairs > 1) lay_many.resize(npairs);
+  Layout* lays = npairs > 1 ? lay_many.data() : &lay_one;
+  for (size_t i = 0; i < npairs; ++i) {
     const PairSpec& q = pairs[i];
     if (!make_layout(p, q.w, q.h, q.levels, &lays[i], c->train))
       return fail(c, BDIS_E_SIZE, "pair %zu: a level of %dx%d with %d levels is smaller than patch %d", i, q.w,
@@ -477,7 +505,7 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
   }
   for (int n = 0; n < pl.max_levels; ++n) {
     pl.tab_first[n] = (int)pl.tab.size();
-    for (size_t i = 0; i < pairs.size(); ++i) {
+    for (size_t i = 0; i < npairs; ++i) {
       const PairSpec& q = pairs[i];
       if (q.levels <= n) continue;
       const Layout& lay = lays[i];
@@ -606,8 +634,11 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
       pl.search_opt[n] = 0;
       continue;
     }
-    auto it = c->tuned.find(level_key(p, pl, n));
-    pl.search_opt[n] = it != c->tuned.end() ? it->second : default_search_opt(pl, n, p.patch, p.stride);
+    pl.search_opt[n] = default_search_opt(pl, n, p.patch, p.stride);
+    if (!c->tuned.empty()) {  // (the key is a string: looked up only when something was tuned)
+      auto it = c->tuned.find(level_key(p, pl, n));
+      if (it != c->tuned.end()) pl.search_opt[n] = it->second;
+    }
     if (c->forced_opt >= 0) pl.search_opt[n] = c->forced_opt;
   }
   for (int n = 0; n < pl.max_levels; ++n) {
@@ -626,7 +657,6 @@ bdis_status build_plan(bdis_ctx* c, const std::vector<PairSpec>& pairs, Plan* ou
     pl.pyr_tall[n] = npx >= kPyrTallPixels;
   }
   assign_offsets(p, pl);
-  *out = std::move(pl);
   return BDIS_OK;
 }
 
@@ -664,7 +694,7 @@ bdis_status upload_table(bdis_ctx* c, const Plan& pl, hipStream_t st) {
     return hip_fail(c, e, "job table upload");
   if ((e = hipEventRecord(c->tab_evt, st)) != hipSuccess) return hip_fail(c, e, "table event");
   c->tab_evt_live = true;
-  c->tab_last = pl.tab;
+  c->tab_last.assign(pl.tab.data(), pl.tab.data() + n);
   return BDIS_OK;
 }
 
@@ -878,7 +908,7 @@ bdis_status ordered(bdis_ctx* c, hipStream_t st, F&& run) {
 
 bdis_status run_pairs(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipStream_t st) {
   Plan pl;
-  bdis_status s = build_plan(c, pairs, &pl);
+  bdis_status s = build_plan(c, pairs.data(), pairs.size(), &pl);
   if (s != BDIS_OK) return s;
   if ((s = tune(c, pl, st)) != BDIS_OK) return s;
   if ((s = upload_table(c, pl, st)) != BDIS_OK) return s;
@@ -890,7 +920,7 @@ bdis_status run_pairs(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipStream
 // usual per-level phases; training state is written as it goes.
 bdis_status run_pairs_f32(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipStream_t st) {
   Plan pl;
-  bdis_status s = build_plan(c, pairs, &pl, true);
+  bdis_status s = build_plan(c, pairs.data(), pairs.size(), &pl, true);
   if (s != BDIS_OK) return s;
   if ((s = upload_table(c, pl, st)) != BDIS_OK) return s;
   const bdis_params& p = c->p;
@@ -935,7 +965,7 @@ bdis_status run_pairs_f32(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipSt
 // Eq. 2 fusion (no probability, no reduction).
 bdis_status run_flow(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipStream_t st) {
   Plan pl;
-  bdis_status s = build_plan(c, pairs, &pl, false, true);
+  bdis_status s = build_plan(c, pairs.data(), pairs.size(), &pl, false, true);
   if (s != BDIS_OK) return s;
   if ((s = upload_table(c, pl, st)) != BDIS_OK) return s;
   const bdis_params& p = c->p;
@@ -969,7 +999,7 @@ bdis_status run_backward(bdis_ctx* c, std::vector<PairSpec> pairs, double* grad_
   if (c->p.fusion != 0 || c->p.propagate != 1)
     return fail(c, BDIS_E_ARG, "backward needs fusion 0 and propagate 1 (the method's own weights)");
   Plan pl;
-  bdis_status s = build_plan(c, pairs, &pl, true);
+  bdis_status s = build_plan(c, pairs.data(), pairs.size(), &pl, true);
   if (s != BDIS_OK) return s;
   if ((s = upload_table(c, pl, st)) != BDIS_OK) return s;
   const bdis_params& p = c->p;
@@ -1002,6 +1032,53 @@ bdis_status run_backward(bdis_ctx* c, std::vector<PairSpec> pairs, double* grad_
     if (e != hipSuccess) return hip_fail(c, e, "hyper-gradient copy");
   }
   return BDIS_OK;
+}
+
+// ---- allocation-free single-pair path ----------------------------------------
+// bdis_compute_static runs the same launch sequence as bdis_compute on a
+// workspace that lives in the static device array `scratch` (job table first,
+// then the pair's workspace slot): no allocation, no graph, no tuning (the
+// default search configuration per level).  The array's host-side name is not
+// a device address: its address on each device comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kStaticScratchBytes = (size_t)48 << 20;
+constexpr int kMaxStaticDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxStaticDevices] = {nullptr};
+
+// Address of `scratch` on device `dev` (the current device).
+hipError_t static_scratch(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxStaticDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// Job-table entries written by a kernel from its arguments (captured by value,
+// so the call can sit under graph capture), kTabChunk entries per launch.
+constexpr int kTabChunk = 4;
+struct TabChunk {
+  PairLevel e[kTabChunk];
+};
+__global__ __launch_bounds__(64) void k_put_table(PairLevel* dst, int count, TabChunk ch) {
+  if (threadIdx.x != 0) return;
+#pragma unroll
+  for (int i = 0; i < kTabChunk; ++i)
+    if (i < count) dst[i] = ch.e[i];
+}
+
+// Copies a transient context's error text to the context-free error buffer.
+bdis_status static_fail(const bdis_ctx& sc, bdis_status s) {
+  if (s != BDIS_OK) std::snprintf(g_create_err, sizeof g_create_err, "%s", sc.err);
+  return s;
 }
 
 }  // namespace
@@ -1138,6 +1215,55 @@ bdis_status bdis_compute(bdis_ctx* c, const uint8_t* left, const uint8_t* right,
     c->have_last = true;
   }
   return st;
+}
+
+bdis_status bdis_compute_static(const bdis_params* p, const uint8_t* left, const uint8_t* right, int w, int h,
+                                int pitch, float* disp, float* var, float* conf, void* stream) {
+  char msg[256];
+  bdis_status s = check_params_msg(p, msg, sizeof msg);
+  if (s != BDIS_OK) return fail(nullptr, s, "%s", msg);
+  if (!left || !right || !disp) return fail(nullptr, BDIS_E_ARG, "left, right and disparity are required");
+  if (w < 1 || h < 1 || pitch < w) return fail(nullptr, BDIS_E_ARG, "bad image size %dx%d pitch %d", w, h, pitch);
+  if (var && !p->variance) return fail(nullptr, BDIS_E_ARG, "variance output given but params.variance is 0");
+  if (p->float_pyramid) return fail(nullptr, BDIS_E_ARG, "uint8 input needs params.float_pyramid = 0");
+  Layout lay;
+  if (!make_layout(*p, w, h, p->levels, &lay))
+    return fail(nullptr, BDIS_E_SIZE, "a level of %dx%d with %d levels is smaller than patch %d", w, h, p->levels,
+                p->patch);
+  const size_t tab_bytes = align_up(sizeof(PairLevel) * kMaxLevels);
+  if (tab_bytes + lay.total > kStaticScratchBytes)
+    return fail(nullptr, BDIS_E_CAPACITY, "%dx%d with these parameters needs %zu bytes of the %zu-byte static scratch",
+                w, h, tab_bytes + lay.total, kStaticScratchBytes);
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(nullptr, BDIS_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  char* base = nullptr;
+  if ((e = static_scratch(dev, &base)) != hipSuccess)
+    return fail(nullptr, BDIS_E_HIP, "static scratch address on device %d: %s", dev, hipGetErrorString(e));
+  // a transient context on the stack whose workspace and job table are the scratch
+  bdis_ctx sc;
+  sc.p = *p;
+  sc.max_w = w;
+  sc.max_h = h;
+  sc.max_batch = 1;
+  sc.slot_bytes = lay.total;
+  sc.ws = base + tab_bytes;
+  sc.device = dev;
+  sc.use_graph = 0;
+  sc.tab_dev = reinterpret_cast<PairLevel*>(base);
+  const PairSpec q{left, right, w, h, pitch, p->levels, disp, var, conf};
+  Plan pl;
+  if ((s = build_plan(&sc, &q, 1, &pl)) != BDIS_OK) return static_fail(sc, s);
+  const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  for (size_t i0 = 0; i0 < pl.tab.size(); i0 += kTabChunk) {
+    TabChunk ch;
+    const int cnt = (int)std::min(pl.tab.size() - i0, (size_t)kTabChunk);
+    std::memset(&ch, 0, sizeof ch);
+    std::memcpy(ch.e, pl.tab.data() + i0, sizeof(PairLevel) * (size_t)cnt);
+    hipLaunchKernelGGL(k_put_table, dim3(1), dim3(64), 0, st, sc.tab_dev + i0, cnt, ch);
+    if ((e = hipGetLastError()) != hipSuccess) return fail(nullptr, BDIS_E_HIP, "job table: %s", hipGetErrorString(e));
+  }
+  return static_fail(sc, launch_all(&sc, pl, st));
 }
 
 bdis_status bdis_compute_batch(bdis_ctx* c, int n, const bdis_pair* pairs, void* stream) {

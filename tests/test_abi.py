@@ -66,6 +66,21 @@ def test_create_validation_before_any_device_call(B, monkeypatch):
     assert not h.value
 
 
+def test_static_entry_validation_before_any_device_call(B):
+    L = B.lib()
+    p = B.params(levels=6, patch=8, stride=3, iters=16, variance=1)
+    fake = 1  # never dereferenced: every case below is refused on the host
+    assert L.bdis_compute_static(None, fake, fake, 64, 64, 64, fake, None, None, None) == B.E_ARG
+    assert L.bdis_compute_static(ctypes.byref(p), None, fake, 64, 64, 64, fake, None, None, None) == B.E_ARG
+    assert L.bdis_compute_static(ctypes.byref(p), fake, fake, 64, 64, 63, fake, None, None, None) == B.E_ARG
+    assert L.bdis_compute_static(ctypes.byref(B.params(variance=0)), fake, fake, 640, 480, 640, fake, fake, None,
+                                 None) == B.E_ARG
+    assert L.bdis_compute_static(ctypes.byref(p), fake, fake, 40, 40, 40, fake, None, None, None) == B.E_SIZE
+    assert L.bdis_compute_static(ctypes.byref(p), fake, fake, 3840, 2160, 3840, fake, None, None, None) == \
+        B.E_CAPACITY
+    assert b"static scratch" in L.bdis_last_error(None)
+
+
 def test_null_context_calls(B):
     assert B.lib().bdis_compute(None, None, None, 1, 1, 1, None, None, None, None) == B.E_ARG
     assert B.lib().bdis_compute_batch(None, 0, None, None) == B.E_ARG
