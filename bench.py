@@ -4,8 +4,10 @@ Headline: one step = one full coarse-to-fine pass (pyramid, patch search,
 probability, fusion, variance) over one 640x480 synthetic pair (5 levels, 8x8
 patches, stride 3, 16 iterations, variance on), inputs resident in HBM, through
 the library's default path (the captured launch graph).  A second timed region
-of the same K steps runs with per-kernel HIP events on the compute stream and
-gives the roofline of the dominant kernel (the patch search).
+of the same K steps runs eagerly with per-kernel HIP events that each kernel
+dispatch records itself (the library's timing mode) and gives the roofline of
+the dominant kernel (the patch search), overall and per pyramid level.  The
+oracle's result on the same pair gives the parity figures of the line.
 
 Also reported: the 1920x1080 batch stream (6 levels, 12x12 patches, stride 4,
 16 iterations, variance on) on one GPU's share of 64 pairs, and the FP64 CPU
@@ -109,28 +111,116 @@ def kernel_table(tk):
             for k, v in tk.items()}
 
 
-def cpu_baseline(left, right, params, budget_s=16.0):
-    """The FP64 oracle, one pair per thread on the host cores, on a bounded sample."""
-    from oracle import ref
-    ref.build(force=False)
-    threads = max(1, min(16, os.cpu_count() or 1))
-    t0 = time.perf_counter()
-    ref.compute(left, right, params)
-    t1 = time.perf_counter() - t0
-    reps = max(1, int(round(budget_s / (t1 * threads))))
-    n = threads * reps
+# A GPU's share of the host: at most this many oracle threads (one GPU of a
+# node gets 16 cores, whatever the node's core count).
+HOST_CORE_SHARE = 16
 
-    def job(_):
-        ref.compute(left, right, params)
+
+def host_info():
+    """Cores the process may use, the node's count and the CPU model."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(nproc=os.cpu_count(), usable=usable, threads=max(1, min(HOST_CORE_SHARE, usable)), model=model)
+
+
+def oracle_throughput(jobs, threads, keep_first=False):
+    """Runs the oracle on every (left, right, params) job over `threads` threads
+    (ctypes releases the GIL); returns (wall seconds, output pixels, the first
+    job's result if keep_first)."""
+    from oracle import ref
+
+    def job(j):
+        return ref.compute(j[0], j[1], j[2])
 
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=threads) as ex:
-        list(ex.map(job, range(n)))
+        res = list(ex.map(job, jobs))
     dt = time.perf_counter() - t0
+    return dt, sum(j[0].shape[0] * j[0].shape[1] for j in jobs), (res[0] if keep_first else None)
+
+
+def cpu_baseline(left, right, params, budget_s=16.0):
+    """The FP64 oracle on the host cores on a bounded sample of the headline
+    workload: one pass on one core (also kept for the parity figures), then
+    copies of the pair one per thread.  Returns (baseline dict, oracle result)."""
+    from oracle import ref
+    ref.build(force=False)
+    hi = host_info()
+    threads = hi["threads"]
+    t0 = time.perf_counter()
+    res = ref.compute(left, right, params)
+    t1 = time.perf_counter() - t0
+    reps = max(1, int(round(budget_s / (t1 * threads))))
+    n = threads * reps
+    dt, px, _ = oracle_throughput([(left, right, params)] * n, threads)
     h, w = left.shape
-    return dict(value=round(w * h * n / dt / 1e6, 4), unit="Mpixel/s", cores=threads, kind="oracle",
+    return dict(value=round(px / dt / 1e6, 4), unit="Mpixel/s", cores=threads, kind="oracle",
                 sample=f"{n} oracle passes over the 640x480 pair ({threads} threads x {reps}), "
-                       f"{dt:.1f} s wall, {n * t1:.1f} s of CPU work")
+                       f"{dt:.1f} s wall, {n * t1:.1f} s of CPU work",
+                one_core=dict(value=round(w * h / t1 / 1e6, 4), unit="Mpixel/s", seconds_per_pair=round(t1, 4)),
+                host=hi, note=f"{threads} threads: the host-core share of one GPU (the node shows {hi['nproc']})"), res
+
+
+def accuracy(d, gt, valid):
+    """Median end-point error and bad-1px over ground-truth-valid pixels with an
+    estimate, and the fraction of ground-truth-valid pixels with an estimate."""
+    import numpy as np
+    ok = np.isfinite(d) & valid
+    e = np.abs(d[ok] - gt[ok])
+    return dict(epe_median_px=round(float(np.median(e)), 4), bad1px=round(float((e > 1.0).mean()), 5),
+                density=round(float(ok.sum() / max(valid.sum(), 1)), 4))
+
+
+def parity_block(disp, var, ref_res, tol=1e-3, rtol=1e-3):
+    """GPU outputs against the FP64 oracle on the same pair: fraction of pixels
+    within tol px (a validity-mask disagreement counts as a miss), p99.9 and max
+    error, mask mismatches; variance at relative rtol likewise."""
+    import numpy as np
+
+    def stats(g, r, rel):
+        g = np.asarray(g, np.float64)
+        r = np.asarray(r, np.float64)
+        gv, rv = np.isfinite(g), np.isfinite(r)
+        both = gv & rv
+        err = np.abs(g - r)
+        if rel:
+            err = err / np.maximum(np.abs(r), 1e-30)
+        lim = rtol if rel else tol
+        ok = (both & (err <= lim)) | (~gv & ~rv)
+        e = err[both]
+        return dict(frac=round(float(ok.mean()), 6), p999=float(f"{np.quantile(e, 0.999):.3g}") if e.size else 0.0,
+                    max=float(f"{e.max():.3g}") if e.size else 0.0, mask_mismatch=int((gv != rv).sum()))
+    out = dict(disparity=dict(tol_px=tol, **stats(disp, ref_res["disp"], False)))
+    if var is not None and ref_res.get("var") is not None:
+        out["variance"] = dict(rtol=rtol, **stats(var, ref_res["var"], True))
+    return out
+
+
+def search_per_level(bdis, ctx, p, w, h, steps, npairs=1, levels=None):
+    """Per-level search launches of the event region: patches, mean launch time
+    and the algorithmic rate against the FP32 vector peak."""
+    out = []
+    P2 = p.patch * p.patch
+    for n in range(p.finest_level, levels or p.levels):
+        ms, k = ctx.timing_read(n)["search"]
+        if k == 0:
+            continue
+        _, _, nx, ny = bdis.level_dims(p, w, h, n)
+        flops = nx * ny * npairs * (4 * P2 + 5 * p.iters * P2 + 8 * WIN * P2)
+        per = ms * 1e-3 / k
+        out.append(dict(level=n, patches=nx * ny * npairs, avg_us=round(per * 1e6, 3),
+                        tflops=round(flops / per / 1e12, 3), frac=round(flops / per / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 5)))
+    return out
 
 
 def bench_single(bdis, torch, args):
@@ -145,6 +235,11 @@ def bench_single(bdis, torch, args):
     rt = torch.from_numpy(right).to(dev)
     out = {k: torch.empty((h, w), dtype=torch.float32, device=dev) for k in ("disp", "var", "conf")}
     log(f"640x480 pair, L={p.levels} P={p.patch} S={p.stride} K={p.iters}: warmup {args.warmup}")
+    t0 = time.perf_counter()
+    ctx.compute(lt, rt, out=out)
+    torch.cuda.synchronize()
+    first_ms = (time.perf_counter() - t0) * 1e3
+    tune_ms, cap_ms = ctx.setup_time()
     for _ in range(args.warmup):
         ctx.compute(lt, rt, out=out)
     torch.cuda.synchronize()
@@ -162,13 +257,64 @@ def bench_single(bdis, torch, args):
     torch.cuda.synchronize()
     dt_ev = time.perf_counter() - t1
     tk = ctx.timing_read()
+    per_level = search_per_level(bdis, ctx, p, w, h, args.steps)
     ctx.timing(False)
     d = out["disp"].cpu().numpy()
-    ok = np.isfinite(d) & valid
-    epe = float(np.median(np.abs(d[ok] - gt[ok])))
+    var = out["var"].cpu().numpy()
+    acc = accuracy(d, gt, valid)
     ctx.close()
-    return dict(w=w, h=h, p=p, dt=dt, dt_ev=dt_ev, tk=tk, epe=epe, left=left, right=right,
-                mp=method_params(2))
+    # single-call latency: host call to finished outputs, one call at a time
+    ctx = bdis.Context(p, w, h)
+    ctx.compute(lt, rt, out=out)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(min(args.steps, 50)):
+        t0 = time.perf_counter()
+        ctx.compute(lt, rt, out=out)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    tune2, cap2 = ctx.setup_time()
+    ctx.close()
+    lat.sort()
+    setup = dict(first_call_ms=round(first_ms, 2), tune_ms=round(tune_ms, 2), capture_ms=round(cap_ms, 2),
+                 note="first call of a new shape tunes the launch shapes (cached per shape and in the tuning "
+                      "file) and captures the graph; both outside the timed regions")
+    return dict(w=w, h=h, p=p, dt=dt, dt_ev=dt_ev, tk=tk, acc=acc, left=left, right=right, disp=d, var=var,
+                mp=method_params(2), per_level=per_level, setup=setup,
+                latency_ms=dict(median=round(lat[len(lat) // 2], 4), p90=round(lat[int(len(lat) * 0.9)], 4),
+                                calls=len(lat)))
+
+
+def bench_c1(bdis, torch, args):
+    """The small workload: one 320x240 pair (3 levels, P 8, S 4, K 8), one call
+    per step; throughput over the steps and single-call latency."""
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    dev = torch.device("cuda:0")
+    left, right, gt, valid = make_pair(1, 0)
+    h, w = left.shape
+    p = bdis.params(**method_params(1))
+    lt, rt = torch.from_numpy(left).to(dev), torch.from_numpy(right).to(dev)
+    out = {k: torch.empty((h, w), dtype=torch.float32, device=dev) for k in ("disp", "conf")}
+    with bdis.Context(p, w, h) as ctx:
+        for _ in range(args.warmup):
+            ctx.compute(lt, rt, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.compute(lt, rt, out=out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        lat = []
+        for _ in range(min(args.steps, 50)):
+            t1 = time.perf_counter()
+            ctx.compute(lt, rt, out=out)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t1) * 1e3)
+    lat.sort()
+    return dict(ms_per_pair=round(dt * 1e3, 4), mpx_s=round(w * h / dt / 1e6, 2),
+                latency_ms=dict(median=round(lat[len(lat) // 2], 4), p90=round(lat[int(len(lat) * 0.9)], 4)),
+                **accuracy(out["disp"].cpu().numpy(), gt, valid),
+                config="320x240 pair (bumps 0-32 px, noise 1 on the right), L=3 P=8 S=4 K=8, variance off")
 
 
 def bench_batch(bdis, torch, args):
@@ -187,8 +333,12 @@ def bench_batch(bdis, torch, args):
     outs = [{k: torch.empty((1080, 1920), dtype=torch.float32, device=dev) for k in ("disp", "var", "conf")}
             for _ in range(n)]
     log(f"1080p batch of {n}: warmup (includes tuning and graph capture)")
-    for _ in range(2):
-        ctx.compute_batch(lefts, rights, outs=outs)
+    t0 = time.perf_counter()
+    ctx.compute_batch(lefts, rights, outs=outs)
+    torch.cuda.synchronize()
+    setup = dict(first_call_ms=round((time.perf_counter() - t0) * 1e3, 2))
+    setup["tune_ms"], setup["capture_ms"] = (round(x, 2) for x in ctx.setup_time())
+    ctx.compute_batch(lefts, rights, outs=outs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.batch_steps):
@@ -200,23 +350,47 @@ def bench_batch(bdis, torch, args):
         ctx.compute_batch(lefts, rights, outs=outs)
     torch.cuda.synchronize()
     tk = ctx.timing_read()
+    per_level = search_per_level(bdis, ctx, p, 1920, 1080, max(1, args.batch_steps // 2), npairs=n)
     ctx.timing(False)
-    ok = [np.isfinite(outs[i]["disp"].cpu().numpy()) & base[i][3] for i in range(min(n, uniq))]
-    epe = float(np.median(np.concatenate(
-        [np.abs(outs[i]["disp"].cpu().numpy()[ok[i]] - base[i][2][ok[i]]) for i in range(len(ok))])))
+    nu = min(n, uniq)
+    dd = [outs[i]["disp"].cpu().numpy() for i in range(nu)]
+    acc = accuracy(np.stack(dd), np.stack([base[i][2] for i in range(nu)]), np.stack([base[i][3] for i in range(nu)]))
+    d0 = dd[0]
+    v0 = outs[0]["var"].cpu().numpy()
     ctx.close()
+    # the plain form: the same pairs one call each (single-pair context)
+    log("1080p pairs one at a time (plain form)")
+    one = bdis.Context(p, 1920, 1080)
+    o1 = {k: torch.empty((1080, 1920), dtype=torch.float32, device=dev) for k in ("disp", "var", "conf")}
+    for i in range(2):
+        one.compute(lefts[i], rights[i], out=o1)
+    torch.cuda.synchronize()
+    reps = max(uniq, 8)
+    t0 = time.perf_counter()
+    for i in range(reps):
+        one.compute(lefts[i % n], rights[i % n], out=o1)
+    torch.cuda.synchronize()
+    dt1 = (time.perf_counter() - t0) / reps
+    one.compute(lefts[0], rights[0], out=o1)
+    torch.cuda.synchronize()
+    same0 = bool(torch.equal(torch.nan_to_num(o1["disp"], nan=-7.0), torch.nan_to_num(outs[0]["disp"], nan=-7.0)))
+    one.close()
     steps_ev = max(1, args.batch_steps // 2)
     mpx = 1920 * 1080 * n * args.batch_steps / dt / 1e6
     flops = search_flops(bdis, p, 1920, 1080) * n
-    return dict(metric="disparity Mpixel/s (1080p batch)", value=round(mpx, 2), unit="Mpixel/s",
-                pairs_per_step=n, unique_pairs=uniq, steps=args.batch_steps,
-                ms_per_step=round(dt * 1e3 / args.batch_steps, 3),
-                config=dict(workload="1920x1080 synthetic pairs (planes+bumps 0-192 px, 30% textureless, "
-                                     "dark gain U(0.2,0.5), noise 3), L=6 P=12 S=4 K=16 variance on",
-                            share="64 of the 512-pair stream"),
-                roofline=roofline(flops, steps_ev, tk, "k_search_u8<12>", "1080p_batch64",
-                                  search_bytes(bdis, p, 1920, 1080) * n), kernels=kernel_table(tk),
-                epe_median_px=round(epe, 4))
+    res = dict(metric="disparity Mpixel/s (1080p batch)", value=round(mpx, 2), unit="Mpixel/s",
+               pairs_per_step=n, unique_pairs=uniq, steps=args.batch_steps,
+               ms_per_step=round(dt * 1e3 / args.batch_steps, 3),
+               config=dict(workload="1920x1080 synthetic pairs (planes+bumps 0-192 px, 30% textureless, "
+                                    "dark gain U(0.2,0.5), noise 3), L=6 P=12 S=4 K=16 variance on",
+                           share="64 of the 512-pair stream"),
+               roofline=roofline(flops, steps_ev, tk, "k_search_u8<12>", "1080p_batch64",
+                                 search_bytes(bdis, p, 1920, 1080) * n),
+               search_per_level=per_level, kernels=kernel_table(tk), setup=setup, **acc,
+               plain_single=dict(ms_per_pair=round(dt1 * 1e3, 4), mpx_s=round(1920 * 1080 / dt1 / 1e6, 2),
+                                 same_bits_as_batch_pair0=same0,
+                                 note="one bdis_compute per pair on a single-pair context, same pairs and method"))
+    return res, dict(left=base[0][0], right=base[0][1], disp=d0, var=v0, base=base, p=p)
 
 
 def bench_mixed(bdis, torch, args):
@@ -254,13 +428,15 @@ def bench_mixed(bdis, torch, args):
     torch.cuda.synchronize()
     tk = ctx.timing_read()
     ctx.timing(False)
-    errs = []
+    errs, bad, dens = [], [], []
     for wh, (i, pr) in base.items():
         k = sizes.index(wh)
         d = outs[k]["disp"].cpu().numpy()
         ok = np.isfinite(d) & pr[3]
         errs.append(np.abs(d[ok] - pr[2][ok]))
+        dens.append(ok.sum() / max(pr[3].sum(), 1))
     ctx.close()
+    ae = np.concatenate(errs)
     px = sum(w * h for (w, h) in sizes)
     flops = sum(search_flops(bdis, p, w, h, levels[i]) for i, (w, h) in enumerate(sizes))
     nbytes = sum(search_bytes(bdis, p, w, h, levels[i]) for i, (w, h) in enumerate(sizes))
@@ -270,7 +446,9 @@ def bench_mixed(bdis, torch, args):
                 config=dict(workload="64 synthetic pairs, 8 each of 320x240 .. 1920x1080, disparity up to 10% of "
                                      "the width, L=4..6 by size, P=8 S=3 K=16 variance on"),
                 roofline=roofline(flops, steps_ev, tk, "k_search_u8<8>", "mixed64", nbytes),
-                kernels=kernel_table(tk), epe_median_px=round(float(np.median(np.concatenate(errs))), 4))
+                kernels=kernel_table(tk), epe_median_px=round(float(np.median(ae)), 4),
+                bad1px=round(float((ae > 1.0).mean()), 5), density=round(float(np.mean(dens)), 4),
+                _oracle_jobs=[(base[wh][1][0], base[wh][1][1], mp[sizes.index(wh)]) for wh in sizes])
 
 
 def bench_preset(bdis, torch, args):
@@ -300,8 +478,7 @@ def bench_preset(bdis, torch, args):
         ok = np.isfinite(d) & valid
         out["variance_on" if var else "variance_off"] = dict(
             ms_per_pair=round(dt * 1e3, 4), mpx_s=round(640 * 480 / dt / 1e6, 2),
-            valid_frac=round(float(np.isfinite(d).mean()), 4),
-            epe_median_px=round(float(np.median(np.abs(d[ok] - gt[ok]))), 4))
+            valid_frac=round(float(np.isfinite(d).mean()), 4), **accuracy(d, gt, valid))
         ctx.close()
     out["config"] = "640x480 pair (planes+bumps 0-64 px), levels 5..1, P=10 S=4 K=12, gamma 0.75, prob 0.15"
     out["paper_cpu_s"] = dict(variance_off=0.064, variance_on=0.072,
@@ -326,7 +503,7 @@ def bench_ablation(bdis, torch, args):
         mp = dict(method_params(2))
         mp.update(kw)
         ctx = bdis.Context(bdis.params(**mp), 640, 480)
-        med, mean, cov = [], [], []
+        med, mean, cov, bad = [], [], [], []
         for left, right, gt, valid in pairs:
             d = ctx.compute(torch.from_numpy(left).to(dev), torch.from_numpy(right).to(dev))["disp"].cpu().numpy()
             ok = np.isfinite(d) & valid
@@ -334,9 +511,10 @@ def bench_ablation(bdis, torch, args):
             med.append(float(np.median(e)))
             mean.append(float(e.mean()))
             cov.append(float(ok.sum() / valid.sum()))
+            bad.append(float((e > 1.0).mean()))
         ctx.close()
         out[name] = dict(median_px=round(float(np.mean(med)), 4), mean_px=round(float(np.mean(mean)), 4),
-                         valid_frac=round(float(np.mean(cov)), 4))
+                         bad1px=round(float(np.mean(bad)), 5), valid_frac=round(float(np.mean(cov)), 4))
     for name in out:
         out[name]["median_norm"] = round(out[name]["median_px"] / out["bdis"]["median_px"], 4)
         out[name]["mean_norm"] = round(out[name]["mean_px"] / out["bdis"]["mean_px"], 4)
@@ -397,6 +575,7 @@ def bench_flow(bdis, torch, args):
     ctx.close()
     return dict(ms_per_pair=round(dt * 1e3, 4), mpx_s=round(640 * 480 / dt / 1e6, 2),
                 epe_median_px=round(float(np.median(epe)), 4), epe_mean_px=round(float(epe.mean()), 4),
+                bad1px=round(float((epe > 1.0).mean()), 5),
                 kernels=kernel_table({k: tk[k] for k in ("pyramid", "search", "fuse")}),
                 config="640x480 frames, smooth 2-D flow up to 12 px, noise 2; L=4 P=8 S=4 K=12, Eq. 2 fusion")
 
@@ -460,6 +639,8 @@ def bench_diff(bdis, torch, args):
                 plain_u8_ms=round(t_u, 3), plain_u8_mpx_s=round(640 * 480 * n / t_u / 1e3, 2),
                 epe_median_px_float=round(float(np.median(np.concatenate(epe_f))), 4),
                 epe_median_px_plain=round(float(np.median(np.concatenate(epe_u))), 4),
+                bad1px_float=round(float((np.concatenate(epe_f) > 1.0).mean()), 5),
+                bad1px_plain=round(float((np.concatenate(epe_u) > 1.0).mean()), 5),
                 config="16 x 640x480 float pairs (bumps 0-32 px), L=4 P=8 S=4 K=8, FP64 state; "
                        "loss gradient = random field")
 
@@ -506,10 +687,14 @@ def main():
                                   search_bytes(bdis, p, w, h)),
                 kernels=kernel_table(s["tk"]),
                 ms_per_step_with_kernel_events=round(s["dt_ev"] * 1e3 / args.steps, 4),
-                epe_median_px=round(s["epe"], 4))
+                latency_ms=s["latency_ms"], setup=s["setup"], **s["acc"])
+    line["roofline"]["per_level"] = s["per_level"]
+    line["c1_320x240"] = bench_c1(bdis, torch, args)
+    batch_extra, mixed_jobs = None, None
     if not args.no_batch:
-        line["batch_1080p"] = bench_batch(bdis, torch, args)
+        line["batch_1080p"], batch_extra = bench_batch(bdis, torch, args)
         line["batch_mixed"] = bench_mixed(bdis, torch, args)
+        mixed_jobs = line["batch_mixed"].pop("_oracle_jobs")
     line["paper_preset"] = bench_preset(bdis, torch, args)
     line["optical_flow"] = bench_flow(bdis, torch, args)
     if args.ablation_pairs > 0:
@@ -527,8 +712,28 @@ def main():
         line["copy_calibration_bytes"] = 4 * n
     if not args.no_cpu_baseline:
         from oracle import ref
-        log("cpu baseline (FP64 oracle)")
-        line["cpu_baseline"] = cpu_baseline(s["left"], s["right"], ref.default_params(**s["mp"]))
+        from paper_2205_03133_amd.synth import method_params
+        log("cpu baseline (FP64 oracle) and parity of the 640x480 pair")
+        line["cpu_baseline"], ores = cpu_baseline(s["left"], s["right"], ref.default_params(**s["mp"]))
+        line["parity"] = parity_block(s["disp"], s["var"], ores)
+        threads = line["cpu_baseline"]["cores"]
+        if batch_extra is not None:
+            log("oracle on 16 of the 1080p pairs (parity of pair 0, throughput)")
+            base = batch_extra["base"]
+            op = ref.default_params(**method_params(5))
+            jobs = [(base[i % len(base)][0], base[i % len(base)][1], op) for i in range(16)]
+            dt, px, r0 = oracle_throughput(jobs, threads, keep_first=True)
+            line["batch_1080p"]["parity_pair0"] = parity_block(batch_extra["disp"], batch_extra["var"], r0)
+            line["batch_1080p"]["cpu_oracle"] = dict(
+                value=round(px / dt / 1e6, 4), unit="Mpixel/s", cores=threads, kind="oracle",
+                sample=f"16 oracle passes over the 1080p pairs ({len(base)} unique), {dt:.1f} s wall",
+                seconds_for_512_pairs_extrapolated=round(dt * 512 / 16, 1))
+            log("oracle on the 64 mixed pairs")
+            jobs = [(l, r, ref.default_params(**m)) for (l, r, m) in mixed_jobs]
+            dt, px, _ = oracle_throughput(jobs, threads)
+            line["batch_mixed"]["cpu_oracle"] = dict(
+                value=round(px / dt / 1e6, 4), unit="Mpixel/s", cores=threads, kind="oracle",
+                sample=f"all 64 pairs ({len(set(id(j[0]) for j in jobs))} unique), {dt:.1f} s wall")
     line["paper_context"] = "17 Hz (0.064 s) at 640x480 on one i5-9400 core, levels 5..1, P=10, K=12"
     print(json.dumps(line), flush=True)
 

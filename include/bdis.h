@@ -28,16 +28,20 @@
  *    allocated in bdis_create and released in bdis_destroy.
  *  - Compute calls are asynchronous on `stream` (a hipStream_t; NULL is the
  *    null stream) once a batch shape has been seen.  The first call with a
- *    new batch shape (pair sizes, levels and parameters) times the search
- *    configurations (lanes per patch, workgroup size) per level on `stream`
- *    and synchronises it, then records the launch
- *    sequence as a graph; a job table larger than any before synchronises the
- *    device before it is reallocated.  Environment: BDIS_TUNE=0 skips the
- *    timing (default configuration), BDIS_GRAPH=0 launches eagerly without
- *    graphs, BDIS_SEARCH_CONFIG=k (read by bdis_create; k = lane mapping * 4 +
- *    workgroup-size index into 64, 128, 256, 512) uses search configuration k
- *    on every level without timing (bdis_create fails with BDIS_E_ARG for an
- *    invalid k).
+ *    new batch shape (pair sizes, levels and parameters) times the
+ *    launch shapes of every level on `stream` (search lanes per patch and
+ *    workgroup size, fusion tile height, pyramid form) and synchronises it,
+ *    then records the launch sequence as a graph; a job table larger than any
+ *    before synchronises the device before it is reallocated.  The tuned
+ *    choices persist in a cache file keyed by the device architecture and the
+ *    level shapes (read by bdis_create, rewritten after tuning), so a later
+ *    process skips the timing.  Environment: BDIS_TUNE=0 skips the timing
+ *    (size-based defaults), BDIS_TUNE_CACHE=path names the cache file
+ *    (default $HOME/.cache/bdis/tune.json; empty: no file), BDIS_GRAPH=0
+ *    launches eagerly without graphs, BDIS_SEARCH_CONFIG=k (read by
+ *    bdis_create; k = lane mapping * 4 + workgroup-size index into 64, 128,
+ *    256, 512) uses search configuration k on every level without timing
+ *    (bdis_create fails with BDIS_E_ARG for an invalid k).
  *  - Errors are returned as bdis_status; the library never aborts.  The text
  *    of the last error of a context is available from bdis_last_error.
  *  - A context is not thread-safe: calls on one context must come from one
@@ -268,14 +272,19 @@ enum {
 bdis_status bdis_debug_dump(bdis_ctx* ctx, int level, int what, void* host_dst, size_t bytes,
                             void* stream);
 
-/* Per-kernel timing with HIP events recorded on the compute stream around
- * every launch (for measurement; adds two event records per launch).
- * kernel: 0 pyramid, 1 patch search, 2 patch probability (launched for large
- * levels only; small levels compute it inside the fusion), 3 fusion,
- * 4 the per-pair sigma_r reduction, 5 the backward pass (all its launches).
- * bdis_timing_enable(ctx, 1) clears the totals and starts recording;
- * bdis_timing_read synchronises the recorded events and returns the summed
- * GPU time (ms) and the launch count of one kernel since enabling. */
+/* Per-kernel timing (for measurement): while enabled, calls launch eagerly
+ * (no graph) and each timed launch carries a pair of HIP events that its
+ * kernel dispatches record themselves (hipExtLaunchKernelGGL: start of the
+ * first kernel, end of the last), so a span is the kernels' own execution, as
+ * a profiler's kernel trace reports it.  kernel: 0 pyramid, 1 patch search,
+ * 2 patch probability (launched for large levels only; small levels compute
+ * it inside the fusion), 3 fusion, 4 the per-pair sigma_r reduction (large
+ * levels only), 5 the backward pass (all launches of a level).  A phase that
+ * launches nothing on a level is not counted.  bdis_timing_enable(ctx, 1)
+ * clears the totals and starts recording; bdis_timing_read synchronises the
+ * recorded events and returns the summed GPU time (ms) and the launch count
+ * of one kernel since enabling; bdis_timing_read_level the same for one
+ * pyramid level (level -1: all levels). */
 enum {
   BDIS_K_PYRAMID = 0,
   BDIS_K_SEARCH = 1,
@@ -286,7 +295,13 @@ enum {
   BDIS_K_COUNT = 6
 };
 bdis_status bdis_timing_enable(bdis_ctx* ctx, int enable);
+/* Host time (ms) the last bdis_compute / bdis_compute_batch call spent tuning
+ * launch shapes (first call of a new batch shape without a cached choice) and
+ * capturing its graph (first call of a new launch sequence); 0 when it did
+ * neither.  Errors: BDIS_E_ARG. */
+bdis_status bdis_setup_time(bdis_ctx* ctx, double* tune_ms, double* capture_ms);
 bdis_status bdis_timing_read(bdis_ctx* ctx, int kernel, double* total_ms, long* launches);
+bdis_status bdis_timing_read_level(bdis_ctx* ctx, int kernel, int level, double* total_ms, long* launches);
 
 /* Geometry of level `level` for a w x h input: level size and patch grid. */
 bdis_status bdis_level_dims(const bdis_params* p, int w, int h, int level, int* lw, int* lh,

@@ -100,12 +100,15 @@ def lib():
         L.bdis_backward_batch.argtypes = [vp, i32, ctypes.POINTER(PairGrad), vp, vp]
         L.bdis_timing_enable.argtypes = [vp, i32]
         L.bdis_timing_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long)]
+        L.bdis_setup_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.bdis_timing_read_level.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_long)]
         L.bdis_depth.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.c_float, vp, vp, vp]
         L.bdis_flow.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp]
         L.bdis_coverage.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, vp, vp]
         for name in ("bdis_params_default", "bdis_params_check", "bdis_create", "bdis_set_params",
                      "bdis_compute", "bdis_compute_batch", "bdis_compute_static", "bdis_debug_dump", "bdis_level_dims",
-                     "bdis_timing_enable", "bdis_timing_read", "bdis_compute_f32", "bdis_compute_f32_batch",
+                     "bdis_timing_enable", "bdis_timing_read", "bdis_timing_read_level", "bdis_setup_time", "bdis_compute_f32", "bdis_compute_f32_batch",
                      "bdis_backward", "bdis_backward_batch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -375,12 +378,22 @@ class Context:
         if st:
             raise self._err(st)
 
-    def timing_read(self):
-        """{kernel: (total_ms, launches)} since timing was enabled (synchronises)."""
+    def setup_time(self):
+        """(tune_ms, capture_ms): host time the last compute call spent tuning and
+        capturing its graph (0 when it did neither)."""
+        t, c = ctypes.c_double(), ctypes.c_double()
+        st = lib().bdis_setup_time(self._h, ctypes.byref(t), ctypes.byref(c))
+        if st:
+            raise self._err(st)
+        return t.value, c.value
+
+    def timing_read(self, level=-1):
+        """{kernel: (total_ms, launches)} since timing was enabled (synchronises);
+        one pyramid level's launches when ``level`` >= 0."""
         out = {}
         for k, name in enumerate(self.KERNELS):
             ms, n = ctypes.c_double(), ctypes.c_long()
-            st = lib().bdis_timing_read(self._h, k, ctypes.byref(ms), ctypes.byref(n))
+            st = lib().bdis_timing_read_level(self._h, k, level, ctypes.byref(ms), ctypes.byref(n))
             if st:
                 raise self._err(st)
             out[name] = (ms.value, n.value)

@@ -9,6 +9,7 @@
 // offsets, so uneven sizes and pyramid depths share one launch.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -284,6 +285,29 @@ hipError_t launch_backward_level(const PairLevel* tab, int npairs, const int* bl
                                  hipStream_t s);
 hipError_t launch_pyramid_adj(const PairLevel* tab, int npairs, int nblocks, hipStream_t s);
 hipError_t launch_grad_out(const PairLevel* tab, int npairs, int nblocks, hipStream_t s);
+
+// Per-kernel timing (bdis_timing_enable): the runtime hands the events of a
+// timed launch to bdis_launch, which lets the kernel dispatch record them
+// itself (hipExtLaunchKernelGGL): the first kernel of the launch records the
+// start, every kernel the stop.  A timed span is then the kernels' own
+// execution, as a profiler's kernel trace reports it, without the cost of
+// separate event records.  Thread-local; set and cleared by the runtime.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool used = false;  // a kernel has recorded the start
+};
+LaunchEvents& launch_events();
+
+template <typename F, typename... Args>
+void bdis_launch(F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s, Args... args) {
+  LaunchEvents& ev = launch_events();
+  if (ev.stop) {
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, ev.used ? nullptr : ev.start, ev.stop, 0u, args...);
+    ev.used = true;
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+  }
+}
 
 // ---------------------------------------------------------------------------
 // device helpers

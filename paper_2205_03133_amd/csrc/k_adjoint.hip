@@ -690,7 +690,7 @@ hipError_t launch_search_adj(const PairLevel* tab, int npairs, int nblocks, cons
       twl = twr = 0;
       bytes = 0;
     }
-    hipLaunchKernelGGL(k_search_adj<P>, dim3(nblocks), dim3(kSearchF64Threads), bytes, s, tab, npairs, lp, twl, twr);
+    bdis_launch(k_search_adj<P>, dim3(nblocks), dim3(kSearchF64Threads), bytes, s, tab, npairs, lp, twl, twr);
     return hipGetLastError();
   });
 }
@@ -698,7 +698,7 @@ hipError_t launch_search_adj(const PairLevel* tab, int npairs, int nblocks, cons
 hipError_t launch_fuse_adj(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
   return by_patch(lp.P, [&](auto pc) {
     constexpr int P = decltype(pc)::value;
-    hipLaunchKernelGGL(k_fuse_adj<P>, dim3(nblocks), dim3(kSearchF64Threads), 0, s, tab, npairs, lp);
+    bdis_launch(k_fuse_adj<P>, dim3(nblocks), dim3(kSearchF64Threads), 0, s, tab, npairs, lp);
     return hipGetLastError();
   });
 }
@@ -709,29 +709,29 @@ hipError_t launch_fuse_adj(const PairLevel* tab, int npairs, int nblocks, const 
 hipError_t launch_backward_level(const PairLevel* tab, int npairs, const int* blocks, const LevelParams& lp,
                                  hipStream_t s) {
   const dim3 pix(kPixThreads);
-  hipLaunchKernelGGL(k_adj_init, dim3((npairs + 63) / 64), dim3(64), 0, s, tab, npairs);
-  if (lp.level == lp.finest) hipLaunchKernelGGL(k_seed, dim3(blocks[0]), pix, 0, s, tab, npairs, lp);
+  bdis_launch(k_adj_init, dim3((npairs + 63) / 64), dim3(64), 0, s, tab, npairs);
+  if (lp.level == lp.finest) bdis_launch(k_seed, dim3(blocks[0]), pix, 0, s, tab, npairs, lp);
   hipError_t e = launch_fuse_adj(tab, npairs, blocks[1], lp, s);
   if (e != hipSuccess) return e;
-  if (lp.level > lp.finest) hipLaunchKernelGGL(k_hole_adj, dim3(blocks[0]), pix, 0, s, tab, npairs);
-  hipLaunchKernelGGL(k_prob_adj, dim3(blocks[2]), pix, 0, s, tab, npairs, lp);
-  hipLaunchKernelGGL(k_tau_adj, dim3((npairs + 63) / 64), dim3(64), 0, s, tab, npairs, lp);
+  if (lp.level > lp.finest) bdis_launch(k_hole_adj, dim3(blocks[0]), pix, 0, s, tab, npairs);
+  bdis_launch(k_prob_adj, dim3(blocks[2]), pix, 0, s, tab, npairs, lp);
+  bdis_launch(k_tau_adj, dim3((npairs + 63) / 64), dim3(64), 0, s, tab, npairs, lp);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = launch_search_adj(tab, npairs, blocks[1], lp, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sobel_adj, dim3(blocks[0]), pix, 0, s, tab, npairs);
+  bdis_launch(k_sobel_adj, dim3(blocks[0]), pix, 0, s, tab, npairs);
   return hipGetLastError();
 }
 
 hipError_t launch_pyramid_adj(const PairLevel* tab, int npairs, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pyr_adj, dim3(nblocks), dim3(kPixThreads), 0, s, tab, npairs);
+  bdis_launch(k_pyr_adj, dim3(nblocks), dim3(kPixThreads), 0, s, tab, npairs);
   return hipGetLastError();
 }
 
 hipError_t launch_grad_out(const PairLevel* tab, int npairs, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_grad_out, dim3(nblocks), dim3(kPixThreads), 0, s, tab, npairs);
+  bdis_launch(k_grad_out, dim3(nblocks), dim3(kPixThreads), 0, s, tab, npairs);
   return hipGetLastError();
 }
 

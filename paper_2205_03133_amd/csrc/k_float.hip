@@ -265,7 +265,7 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_f64(const PairLeve
 template <int P>
 hipError_t launch_f64(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
   const size_t lds = sizeof(double) * (size_t)P * f64_window_cols(P, lp.S);
-  hipLaunchKernelGGL(k_search_f64<P>, dim3(nblocks), dim3(kSearchF64Threads), lds, s, tab, npairs, lp);
+  bdis_launch(k_search_f64<P>, dim3(nblocks), dim3(kSearchF64Threads), lds, s, tab, npairs, lp);
   return hipGetLastError();
 }
 
@@ -273,7 +273,7 @@ hipError_t launch_f64(const PairLevel* tab, int npairs, int nblocks, const Level
 
 hipError_t launch_pyramid_f64(const PairLevel* tab, int npairs, int nblocks, int level, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pyr_f64, dim3(nblocks), dim3(kPixThreads), 0, s, tab, npairs, level);
+  bdis_launch(k_pyr_f64, dim3(nblocks), dim3(kPixThreads), 0, s, tab, npairs, level);
   return hipGetLastError();
 }
 

@@ -195,7 +195,7 @@ hipError_t launch_flow_search(const PairLevel* tab, int npairs, int nblocks, con
   if (nblocks <= 0) return hipSuccess;
   return by_patch(lp.P, [&](auto pc) {
     constexpr int P = decltype(pc)::value;
-    hipLaunchKernelGGL(k_flow_search<P>, dim3(nblocks), dim3(kSearchF64Threads), 0, s, tab, npairs, lp);
+    bdis_launch(k_flow_search<P>, dim3(nblocks), dim3(kSearchF64Threads), 0, s, tab, npairs, lp);
     return hipGetLastError();
   });
 }
@@ -203,7 +203,7 @@ hipError_t launch_flow_search(const PairLevel* tab, int npairs, int nblocks, con
 hipError_t launch_flow_fuse(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
   if (!fuse_ty_ok(lp.fuse_ty)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_flow_fuse, dim3(nblocks), dim3(fuse_threads(lp.fuse_ty)), 0, s, tab, npairs, lp);
+  bdis_launch(k_flow_fuse, dim3(nblocks), dim3(fuse_threads(lp.fuse_ty)), 0, s, tab, npairs, lp);
   return hipGetLastError();
 }
 

@@ -83,6 +83,33 @@ BDIS_DEV D4 patch_record(const PairLevel& a, const LevelParams& lp, const PatchR
   return D4{u, pi, sig, post};
 }
 
+// Mask-weighted sums of one covering patch row at one pixel column, and their
+// combination over the patch rows (the mask factors into m(x - o_x) m(y - o_y)):
+//   A0 = sum_i m_x pi, A1 = sum_i m_x pi u, A2 = sum_i m_x, A3 = sum_i (m_x pi)^2 sigma^2,
+//   z = sum_j m_y A0, zu = sum_j m_y A1, zm = sum_j m_y A2, zv = sum_j m_y^2 A3.
+// The staged separable form and the direct per-pixel form both go through
+// these two helpers (explicit FMAs, patches in ascending index), so the fused
+// maps are the same bits whatever the tile shape.
+struct ColSums {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+};
+BDIS_DEV void col_add(ColSums& c, double mx, double pi, double u, double sig) {
+  const double wx = mx * pi;
+  c.a0 += wx;
+  c.a1 = fma(wx, u, c.a1);
+  c.a2 += mx;
+  c.a3 = fma(wx * wx, sig, c.a3);
+}
+struct PixSums {
+  double z = 0.0, zu = 0.0, zm = 0.0, zv = 0.0;
+};
+BDIS_DEV void row_add(PixSums& p, double my, double a0, double a1, double a2, double a3) {
+  p.z = fma(my, a0, p.z);
+  p.zu = fma(my, a1, p.zu);
+  p.zm = fma(my, a2, p.zm);
+  p.zv = fma(my * my, a3, p.zv);
+}
+
 // One lane per patch: the patch records of a level (used when the level is
 // large enough that computing them once beats recomputing them per tile).
 __global__ __launch_bounds__(kProbThreads) void k_prob(const PairLevel* tab, int npairs, LevelParams lp) {
@@ -195,7 +222,7 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
     for (int e = tid; e < nj * kFuseTx; e += kThreads) {
       const int rj = e / kFuseTx, xl = e - rj * kFuseTx;
       const int xc = x0 + xl;
-      double A0 = 0.0, A1 = 0.0, A2 = 0.0, A3 = 0.0;
+      ColSums cs;
       if (xc < a.g.w) {
         int clo, chi, cex;
         cover_range(xc, a.g.w, P, S, a.g.nx, clo, chi, cex);
@@ -205,19 +232,14 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
           const int r = rj * ni + (i <= ihi ? i - ilo : ni - 1);
           const double dw = s_w[r];
           if (dw < 0.0) continue;  // rejected patch
-          const double mx = lp.fusion == 2 ? 1.0 : s_m[xc - grid_origin(i, a.g.w, P, S)];
-          const double wx = mx * dw;
-          A0 += wx;
-          A1 += wx * s_u[r];
-          A2 += mx;
-          A3 += wx * wx * s_v[r];
+          col_add(cs, lp.fusion == 2 ? 1.0 : s_m[xc - grid_origin(i, a.g.w, P, S)], dw, s_u[r], s_v[r]);
         }
       }
       double* const A = s_A + rj * (4 * kFuseTx) + xl;
-      A[0] = A0;
-      A[kFuseTx] = A1;
-      A[2 * kFuseTx] = A2;
-      A[3 * kFuseTx] = A3;
+      A[0] = cs.a0;
+      A[kFuseTx] = cs.a1;
+      A[2 * kFuseTx] = cs.a2;
+      A[3 * kFuseTx] = cs.a3;
     }
     __syncthreads();
   }
@@ -228,7 +250,8 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
   auto fuse_pixel = [&](int y) {
     int pilo = 0, pihi = -1, piex = -1, pjlo = 0, pjhi = -1, pjex = -1;
     cover_range(y, a.g.h, P, S, a.g.ny, pjlo, pjhi, pjex);
-    double z = 0.0, zu = 0.0, zm = 0.0, zq = 0.0, zv = 0.0;
+    PixSums ps;
+    double zq = 0.0;  // Eq. 2 weights only: sum M pi (with mask weights it equals sum W)
     const int jend = pjex >= 0 ? pjhi + 1 : pjhi;
     if (separable) {
       for (int jj = pjlo; jj <= jend; ++jj) {
@@ -236,12 +259,8 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
         const int rj = j <= jhi ? j - jlo : nj - 1;
         const double my = lp.fusion == 2 ? 1.0 : s_m[y - grid_origin(j, a.g.h, P, S)];
         const double* const A = s_A + rj * (4 * kFuseTx) + xl;
-        z += my * A[0];
-        zu += my * A[kFuseTx];
-        zm += my * A[2 * kFuseTx];
-        zv += my * my * A[3 * kFuseTx];
+        row_add(ps, my, A[0], A[kFuseTx], A[2 * kFuseTx], A[3 * kFuseTx]);
       }
-      zq = z;
     }
     if (!separable) cover_range(x, a.g.w, P, S, a.g.nx, pilo, pihi, piex);
     // Eq. 2 (DIS weights): this pixel's left value and its right-image row
@@ -252,6 +271,7 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
       const int j = jj <= pjhi ? jj : pjex;
       const double mb = lp.fusion == 2 ? 1.0 : s_m[y - grid_origin(j, a.g.h, P, S)];
       const int rj = j <= jhi ? j - jlo : nj - 1;  // row of j in the staged block
+      ColSums cs;  // mask weights: this patch row's sums, as the separable form forms them
       for (int ii = pilo; ii <= iend; ++ii) {
         const int i = ii <= pihi ? ii : piex;
         double du, dw, dv;
@@ -274,9 +294,11 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
           dv = d.z;
         }
         if (dw < 0.0) continue;  // rejected patch
-        const double m = lp.fusion == 2 ? 1.0 : s_m[x - grid_origin(i, a.g.w, P, S)] * mb;
-        double wk = m * dw;
-        if (lp.fusion == 1) {
+        if (lp.fusion != 1) {
+          col_add(cs, lp.fusion == 2 ? 1.0 : s_m[x - grid_origin(i, a.g.w, P, S)], dw, du, dv);
+          continue;
+        }
+        {
           // 1 / max(1, r^2), r = I_r(x + u) - I_l(x): linear warp, indices clamped to the row
           const double fm = floor(du);
           const int mm = (int)fm;
@@ -291,15 +313,19 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
             rb = (double)gbl(a.R)[(size_t)y * a.pitch + xb];
           }
           const double r = (1.0 - fr) * ra + fr * rb - lx;
-          wk = 1.0 / fmax(1.0, r * r);
+          const double wk = 1.0 / fmax(1.0, r * r);
+          const double m = s_m[x - grid_origin(i, a.g.w, P, S)] * mb;
+          ps.z += wk;
+          ps.zu += wk * du;
+          ps.zm += m;
+          zq += m * dw;
+          ps.zv += wk * wk * dv;
         }
-        z += wk;
-        zu += wk * du;
-        zm += m;
-        zq += m * dw;
-        zv += wk * wk * dv;
       }
+      if (lp.fusion != 1) row_add(ps, mb, cs.a0, cs.a1, cs.a2, cs.a3);
     }
+    if (lp.fusion != 1) zq = ps.z;
+    const double z = ps.z, zu = ps.zu, zm = ps.zm, zv = ps.zv;
     const size_t idx = (size_t)y * a.g.w + x;
     double ub, qv;
     bool valid = z > 0.0;
@@ -446,7 +472,7 @@ __global__ void k_zero2(unsigned long long* counts) {
 
 hipError_t launch_prob(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s) {
   if (nblocks <= 0 || lp.inline_prob) return hipSuccess;
-  hipLaunchKernelGGL(k_prob, dim3(nblocks), dim3(kProbThreads), 0, s, tab, npairs, lp);
+  bdis_launch(k_prob, dim3(nblocks), dim3(kProbThreads), 0, s, tab, npairs, lp);
   return hipGetLastError();
 }
 
@@ -460,39 +486,39 @@ hipError_t launch_fuse(const PairLevel* tab, int npairs, int nblocks, const Leve
   const bool inl = lp.inline_prob != 0;
   switch (lp.fuse_ty) {
     case kFuseTyHuge:
-      if (inl) hipLaunchKernelGGL((k_fuse<true, kFuseTyHuge>), dim3(nblocks), threads, lds, s, tab, npairs, lp);
-      else hipLaunchKernelGGL((k_fuse<false, kFuseTyHuge>), dim3(nblocks), threads, lds, s, tab, npairs, lp);
+      if (inl) bdis_launch((k_fuse<true, kFuseTyHuge>), dim3(nblocks), threads, lds, s, tab, npairs, lp);
+      else bdis_launch((k_fuse<false, kFuseTyHuge>), dim3(nblocks), threads, lds, s, tab, npairs, lp);
       break;
     case kFuseTyTall:
-      if (inl) hipLaunchKernelGGL((k_fuse<true, kFuseTyTall>), dim3(nblocks), threads, lds, s, tab, npairs, lp);
-      else hipLaunchKernelGGL((k_fuse<false, kFuseTyTall>), dim3(nblocks), threads, lds, s, tab, npairs, lp);
+      if (inl) bdis_launch((k_fuse<true, kFuseTyTall>), dim3(nblocks), threads, lds, s, tab, npairs, lp);
+      else bdis_launch((k_fuse<false, kFuseTyTall>), dim3(nblocks), threads, lds, s, tab, npairs, lp);
       break;
     default:
-      if (inl) hipLaunchKernelGGL((k_fuse<true, kFuseTyShort>), dim3(nblocks), threads, lds, s, tab, npairs, lp);
-      else hipLaunchKernelGGL((k_fuse<false, kFuseTyShort>), dim3(nblocks), threads, lds, s, tab, npairs, lp);
+      if (inl) bdis_launch((k_fuse<true, kFuseTyShort>), dim3(nblocks), threads, lds, s, tab, npairs, lp);
+      else bdis_launch((k_fuse<false, kFuseTyShort>), dim3(nblocks), threads, lds, s, tab, npairs, lp);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_upsample(const PairLevel* tab, int npairs, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_upsample, dim3(nblocks), dim3(kPixThreads), 0, s, tab, npairs);
+  bdis_launch(k_upsample, dim3(nblocks), dim3(kPixThreads), 0, s, tab, npairs);
   return hipGetLastError();
 }
 
 hipError_t launch_depth(const float* disp, const float* var, int w, int h, int pitch, float fb, float* depth,
                         float* dvar, hipStream_t s) {
   const long n = (long)w * h;
-  hipLaunchKernelGGL(k_depth, dim3((unsigned)((n + kPixThreads - 1) / kPixThreads)), dim3(kPixThreads), 0, s, disp,
+  bdis_launch(k_depth, dim3((unsigned)((n + kPixThreads - 1) / kPixThreads)), dim3(kPixThreads), 0, s, disp,
                      var, w, h, pitch, fb, depth, dvar);
   return hipGetLastError();
 }
 
 hipError_t launch_coverage(const float* disp, const float* var, const float* ref, const uint8_t* valid, int w,
                            int h, int pitch, double k, unsigned long long* counts, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero2, dim3(1), dim3(64), 0, s, counts);
+  bdis_launch(k_zero2, dim3(1), dim3(64), 0, s, counts);
   const long n = (long)w * h;
-  hipLaunchKernelGGL(k_coverage, dim3((unsigned)((n + kPixThreads - 1) / kPixThreads)), dim3(kPixThreads), 0, s,
+  bdis_launch(k_coverage, dim3((unsigned)((n + kPixThreads - 1) / kPixThreads)), dim3(kPixThreads), 0, s,
                      disp, var, ref, valid, w, h, pitch, k, counts);
   return hipGetLastError();
 }

@@ -228,9 +228,9 @@ __global__ __launch_bounds__(kPyrThreads, 5) void k_pyr_tall(const PairLevel* ta
 hipError_t launch_pyramid(const PairLevel* tab, int npairs, int nblocks, bool tall, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
   if (tall)
-    hipLaunchKernelGGL(k_pyr_tall, dim3(nblocks), dim3(kPyrThreads), 0, s, tab, npairs);
+    bdis_launch(k_pyr_tall, dim3(nblocks), dim3(kPyrThreads), 0, s, tab, npairs);
   else
-    hipLaunchKernelGGL(k_pyr_small, dim3(nblocks), dim3(kPyrSmallTx * kPyrSmallTy), 0, s, tab, npairs);
+    bdis_launch(k_pyr_small, dim3(nblocks), dim3(kPyrSmallTx * kPyrSmallTy), 0, s, tab, npairs);
   return hipGetLastError();
 }
 

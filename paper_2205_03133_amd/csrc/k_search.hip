@@ -568,10 +568,10 @@ template <int P, int G>
 hipError_t launch_pg(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, int threads, int lds,
                      hipStream_t s) {
   switch (threads) {
-    case 64: hipLaunchKernelGGL((k_search_u8<P, G, 64>), dim3(nblocks), dim3(64), lds, s, tab, npairs, lp); break;
-    case 128: hipLaunchKernelGGL((k_search_u8<P, G, 128>), dim3(nblocks), dim3(128), lds, s, tab, npairs, lp); break;
-    case 256: hipLaunchKernelGGL((k_search_u8<P, G, 256>), dim3(nblocks), dim3(256), lds, s, tab, npairs, lp); break;
-    case 512: hipLaunchKernelGGL((k_search_u8<P, G, 512>), dim3(nblocks), dim3(512), lds, s, tab, npairs, lp); break;
+    case 64: bdis_launch((k_search_u8<P, G, 64>), dim3(nblocks), dim3(64), lds, s, tab, npairs, lp); break;
+    case 128: bdis_launch((k_search_u8<P, G, 128>), dim3(nblocks), dim3(128), lds, s, tab, npairs, lp); break;
+    case 256: bdis_launch((k_search_u8<P, G, 256>), dim3(nblocks), dim3(256), lds, s, tab, npairs, lp); break;
+    case 512: bdis_launch((k_search_u8<P, G, 512>), dim3(nblocks), dim3(512), lds, s, tab, npairs, lp); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -595,7 +595,7 @@ hipError_t launch_p(const PairLevel* tab, int npairs, int nblocks, const LevelPa
 
 hipError_t launch_reduce(const PairLevel* tab, int npairs, const LevelParams& lp, hipStream_t s) {
   if (npairs <= 0 || lp.inline_prob) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce, dim3(npairs), dim3(256), 0, s, tab, lp);
+  bdis_launch(k_reduce, dim3(npairs), dim3(256), 0, s, tab, lp);
   return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@
 #include <bdis.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -23,14 +24,29 @@
 #include <utility>
 #include <vector>
 
+#include <sys/stat.h>
+#include <unistd.h>
+
 #include "bdis_internal.h"
 
 using namespace bdis;
+
+namespace bdis {
+LaunchEvents& launch_events() {
+  static thread_local LaunchEvents ev;
+  return ev;
+}
+}  // namespace bdis
 
 namespace {
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Host wall-clock time in ms (tuning and capture times).
+double wall_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 // Byte offsets of every array of one pair within its workspace slot.
 struct Layout {
@@ -243,12 +259,24 @@ struct Plan {
   PlanTab tab;
 };
 
-// HIP events recorded around each launch while timing is enabled.
+// HIP events recorded by the timed launches while timing is enabled.
+struct TimingMark {
+  int kernel, level;
+  size_t idx;  // index of the start event (the stop event follows it)
+};
 struct Timing {
   bool on = false;
-  std::vector<hipEvent_t> pool;               // reused events
-  size_t used = 0;                            // events handed out since enable
-  std::vector<std::pair<int, size_t>> marks;  // (kernel, index of start event)
+  std::vector<hipEvent_t> pool;   // reused events
+  size_t used = 0;                // events handed out since enable
+  std::vector<TimingMark> marks;
+};
+
+// Launch shapes the tuner picked for one level shape (-1 / 0: not tuned, the
+// size thresholds decide).
+struct TuneChoice {
+  int search = -1;   // uint8 search configuration (option index)
+  int fuse_ty = 0;   // fusion tile height
+  int pyr_tall = -1; // pyramid form: 1 staged 120 x 12 tiles, 0 gather 64 x 4 tiles
 };
 
 // A captured launch sequence for one batch shape.
@@ -279,7 +307,10 @@ struct bdis_ctx {
   bool multi_stream = false;      // calls have come on more than one stream
   hipStream_t capture_stream = nullptr;
   std::map<std::string, GraphEntry> graphs;
-  std::map<std::string, int> tuned;  // level shape key -> uint8 search configuration (option index)
+  std::map<std::string, TuneChoice> tuned;  // level shape key -> tuned launch shapes of the level
+  std::string arch;                  // gcnArchName of the device (part of the tuning keys)
+  std::string tune_cache;            // file the tuned choices persist in ("" = none)
+  double last_tune_ms = 0.0, last_capture_ms = 0.0;  // host time of the last call's tuning / capture
   int forced_opt = -1;               // BDIS_SEARCH_CONFIG: one configuration for every level, no tuning
   int use_graph = 1;
   bool train = false;                // created with BDIS_TRAIN
@@ -349,20 +380,32 @@ hipEvent_t next_event(bdis_ctx* c) {
   return c->tm.pool[c->tm.used++];
 }
 
-long timing_start(bdis_ctx* c, int kernel, hipStream_t st) {
+// Hands a pair of events to the launches that follow (recorded by their
+// dispatches); timing_stop takes them back and drops the mark when nothing was
+// launched (a phase a level skips).
+long timing_start(bdis_ctx* c, int kernel, hipStream_t, int level = -1) {
   if (!c->tm.on) return -1;
   const size_t idx = c->tm.used;
   hipEvent_t a = next_event(c);
   hipEvent_t b = next_event(c);
   if (!a || !b) return -1;
-  (void)hipEventRecord(a, st);
-  c->tm.marks.emplace_back(kernel, idx);
+  c->tm.marks.push_back(TimingMark{kernel, level, idx});
+  LaunchEvents& ev = launch_events();
+  ev.start = a;
+  ev.stop = b;
+  ev.used = false;
   return (long)idx;
 }
 
-void timing_stop(bdis_ctx* c, long mark, hipStream_t st) {
+void timing_stop(bdis_ctx* c, long mark, hipStream_t) {
   if (mark < 0) return;
-  (void)hipEventRecord(c->tm.pool[(size_t)mark + 1], st);
+  LaunchEvents& ev = launch_events();
+  const bool used = ev.used;
+  ev = LaunchEvents{};
+  if (!used) {
+    c->tm.marks.pop_back();
+    c->tm.used -= 2;
+  }
 }
 
 // ---- planning ---------------------------------------------------------------
@@ -412,18 +455,23 @@ LevelParams plan_level_params(const bdis_params& p, const Plan& pl, int n) {
   return lp;
 }
 
-// Tuning key of a level: the search workload shape across the batch.
-std::string level_key(const bdis_params& p, const Plan& pl, int n) {
-  long np = 0;
+// Tuning key of a level: the device architecture and the level's workload
+// shape across the batch (patch, stride, iterations, pairs, patches, pixels,
+// widest level image, and what changes the fusion's work).
+std::string level_key(const bdis_ctx* c, const Plan& pl, int n) {
+  const bdis_params& p = c->p;
+  long np = 0, npx = 0;
   int maxw = 0;
   for (int e = 0; e < pl.tab_count[n]; ++e) {
     const PairLevel& q = pl.tab[pl.tab_first[n] + e];
     np += (long)q.g.nx * q.g.ny;
+    npx += (long)q.g.w * q.g.h;
     maxw = std::max(maxw, q.g.w);
   }
-  char buf[160];
-  snprintf(buf, sizeof buf, "P%d S%d K%d n%d pairs%d patches%ld w%d", p.patch, p.stride, p.iters, n,
-           pl.tab_count[n], np, maxw);
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s P%d S%d K%d n%d f%d pairs%d patches%ld pixels%ld w%d fusion%d var%d",
+           c->arch.c_str(), p.patch, p.stride, p.iters, n, p.finest_level, pl.tab_count[n], np, npx, maxw,
+           p.fusion, p.variance);
   return buf;
 }
 
@@ -635,11 +683,6 @@ bdis_status build_plan(bdis_ctx* c, const PairSpec* pairs, size_t npairs, Plan* 
       continue;
     }
     pl.search_opt[n] = default_search_opt(pl, n, p.patch, p.stride);
-    if (!c->tuned.empty()) {  // (the key is a string: looked up only when something was tuned)
-      auto it = c->tuned.find(level_key(p, pl, n));
-      if (it != c->tuned.end()) pl.search_opt[n] = it->second;
-    }
-    if (c->forced_opt >= 0) pl.search_opt[n] = c->forced_opt;
   }
   for (int n = 0; n < pl.max_levels; ++n) {
     long np = 0, npx = 0;
@@ -656,6 +699,25 @@ bdis_status build_plan(bdis_ctx* c, const PairSpec* pairs, size_t npairs, Plan* 
                                               : kFuseTyShort;
     pl.pyr_tall[n] = npx >= kPyrTallPixels;
   }
+  // tuned choices of this batch shape (uint8 stereo path; the key is a string,
+  // so it is built only when something was tuned or loaded)
+  if (!f32 && !flow && !c->tuned.empty()) {
+    for (int n = 0; n < pl.max_levels; ++n) {
+      if (pl.tab_count[n] == 0) continue;
+      auto it = c->tuned.find(level_key(c, pl, n));
+      if (it == c->tuned.end()) continue;
+      const TuneChoice& tc = it->second;
+      if (n >= p.finest_level && tc.search >= 0 && tc.search < kNumSearchOptions &&
+          search_lds_bytes(p.patch, tc.search, p.stride) <= kSearchMaxLds)
+        pl.search_opt[n] = tc.search;
+      if (n >= p.finest_level && fuse_ty_ok(tc.fuse_ty) &&
+          (tc.fuse_ty != kFuseTyHuge || fuse_tile_fits(kFuseTyHuge, p.patch, p.stride)))
+        pl.fuse_ty[n] = tc.fuse_ty;
+      if (n >= 1 && (tc.pyr_tall == 0 || tc.pyr_tall == 1)) pl.pyr_tall[n] = tc.pyr_tall == 1;
+    }
+  }
+  if (!f32 && !flow && c->forced_opt >= 0)
+    for (int n = p.finest_level; n < pl.max_levels; ++n) pl.search_opt[n] = c->forced_opt;
   assign_offsets(p, pl);
   return BDIS_OK;
 }
@@ -703,7 +765,7 @@ bdis_status launch_all(bdis_ctx* c, const Plan& pl, hipStream_t st) {
   const bdis_params& p = c->p;
   hipError_t e;
   for (int n = 1; n < pl.max_levels; ++n) {
-    const long tmk = timing_start(c, BDIS_K_PYRAMID, st);
+    const long tmk = timing_start(c, BDIS_K_PYRAMID, st, n);
     e = launch_pyramid(c->tab_dev + pl.tab_first[n], pl.tab_count[n], pl.pyr_blocks[n], pl.pyr_tall[n], st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "pyramid launch");
@@ -712,19 +774,19 @@ bdis_status launch_all(bdis_ctx* c, const Plan& pl, hipStream_t st) {
     const PairLevel* tab = c->tab_dev + pl.tab_first[n];
     const int cnt = pl.tab_count[n];
     const LevelParams lp = plan_level_params(p, pl, n);
-    long tmk = timing_start(c, BDIS_K_SEARCH, st);
+    long tmk = timing_start(c, BDIS_K_SEARCH, st, n);
     e = launch_search(tab, cnt, pl.search_blocks[n], lp, pl.search_opt[n], st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "search launch");
-    tmk = timing_start(c, BDIS_K_REDUCE, st);
+    tmk = timing_start(c, BDIS_K_REDUCE, st, n);
     e = launch_reduce(tab, cnt, lp, st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "reduction launch");
-    tmk = timing_start(c, BDIS_K_PROB, st);
+    tmk = timing_start(c, BDIS_K_PROB, st, n);
     e = launch_prob(tab, cnt, pl.prob_blocks[n], lp, st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "probability launch");
-    tmk = timing_start(c, BDIS_K_FUSE, st);
+    tmk = timing_start(c, BDIS_K_FUSE, st, n);
     e = launch_fuse(tab, cnt, pl.fuse_blocks[n], lp, st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "fusion launch");
@@ -762,6 +824,7 @@ bdis_status run_graph(bdis_ctx* c, const Plan& pl, hipStream_t st) {
   auto it = c->graphs.find(key);
   hipError_t e;
   if (it == c->graphs.end()) {
+    const double t0 = wall_ms();
     GraphEntry ge;
     if ((e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
       return hip_fail(c, e, "graph capture begin");
@@ -777,86 +840,217 @@ bdis_status run_graph(bdis_ctx* c, const Plan& pl, hipStream_t st) {
       return hip_fail(c, e, "graph instantiate");
     }
     it = c->graphs.emplace(key, ge).first;
+    c->last_capture_ms = wall_ms() - t0;
   }
   if ((e = hipGraphLaunch(it->second.exec, st)) != hipSuccess) return hip_fail(c, e, "graph launch");
   return BDIS_OK;
 }
 
-// Picks the search configuration (lane mapping and workgroup size) of every
-// level of a new batch shape by timing each option over full passes (every
-// phase rewrites its outputs, so trial passes leave nothing behind).
-// Timed passes per configuration (the first one only warms caches and code;
-// the best of the others counts).
+// ---- tuning cache file --------------------------------------------------------
+// One JSON object; each tuned level shape is one line
+//   "<key>": {"search": S, "fuse_ty": T, "pyr_tall": Y},
+// where the key starts with the device architecture.  Read at bdis_create
+// (entries of the context's architecture), rewritten after each tuning with
+// the entries of every architecture (written to a temporary file, then
+// renamed).  A missing or unreadable file only means tuning again.
+
+// Entries of the cache file (every architecture).
+std::map<std::string, TuneChoice> read_tune_cache(const std::string& path) {
+  std::map<std::string, TuneChoice> out;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return out;
+  char line[1024];
+  while (std::fgets(line, sizeof line, f)) {
+    const char* q0 = std::strchr(line, '"');
+    if (!q0) continue;
+    const char* q1 = std::strchr(q0 + 1, '"');
+    if (!q1) continue;
+    TuneChoice tc;
+    if (std::sscanf(q1 + 1, " : {\"search\": %d, \"fuse_ty\": %d, \"pyr_tall\": %d}", &tc.search, &tc.fuse_ty,
+                    &tc.pyr_tall) == 3)
+      out[std::string(q0 + 1, q1)] = tc;
+  }
+  std::fclose(f);
+  return out;
+}
+
+bdis_status save_tune_cache(bdis_ctx* c) {
+  if (c->tune_cache.empty()) return BDIS_OK;
+  std::map<std::string, TuneChoice> all = read_tune_cache(c->tune_cache);
+  for (const auto& kv : c->tuned) all[kv.first] = kv.second;
+  // the directory of the file (one level created if missing)
+  const size_t slash = c->tune_cache.rfind('/');
+  if (slash != std::string::npos && slash > 0) {
+    const std::string dir = c->tune_cache.substr(0, slash);
+    const size_t up = dir.rfind('/');
+    if (up != std::string::npos && up > 0) (void)mkdir(dir.substr(0, up).c_str(), 0755);
+    (void)mkdir(dir.c_str(), 0755);
+  }
+  char tmp_suffix[64];
+  std::snprintf(tmp_suffix, sizeof tmp_suffix, ".tmp%ld", (long)getpid());
+  const std::string tmp = c->tune_cache + tmp_suffix;
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return BDIS_OK;  // the cache is an optimisation: an unwritable file is not an error
+  std::fprintf(f, "{\n\"bdis_tune_cache\": 1,\n\"entries\": {\n");
+  size_t k = 0;
+  for (const auto& kv : all)
+    std::fprintf(f, "\"%s\": {\"search\": %d, \"fuse_ty\": %d, \"pyr_tall\": %d}%s\n", kv.first.c_str(),
+                 kv.second.search, kv.second.fuse_ty, kv.second.pyr_tall, ++k < all.size() ? "," : "");
+  std::fprintf(f, "}\n}\n");
+  const bool ok = std::fclose(f) == 0;
+  if (!ok || std::rename(tmp.c_str(), c->tune_cache.c_str()) != 0) (void)std::remove(tmp.c_str());
+  return BDIS_OK;
+}
+
+// The cache file: BDIS_TUNE_CACHE if set ("" disables it), else
+// $HOME/.cache/bdis/tune.json.
+std::string tune_cache_path() {
+  if (const char* e = std::getenv("BDIS_TUNE_CACHE")) return e;
+  const char* home = std::getenv("HOME");
+  if (!home || !*home) return "";
+  return std::string(home) + "/.cache/bdis/tune.json";
+}
+
+// Picks the launch shapes of every level of a new batch shape by timing the
+// options over full passes (every phase rewrites its outputs, so trial passes
+// leave nothing behind; every option gives identical results):
+//   1. the search configuration (lane mapping and workgroup size),
+//   2. the fusion tile height (64 x 4, 64 x 16, 64 x 32 where its covering
+//      patches fit the staged form), with the searches at their best,
+//   3. the pyramid form (gather 64 x 4 or staged 120 x 12 tiles).
+// Each timed launch records its events from its own dispatch.  Timed passes
+// per option: the first one only warms caches and code, the best of the
+// others counts.  The choices are kept per level shape and written to the
+// tuning cache file.
 constexpr int kTuneReps = 5;
+
+bdis_status save_tune_cache(bdis_ctx* c);
 
 bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
   const bdis_params& p = c->p;
   bool need = false;
-  for (int n = p.finest_level; n < pl.max_levels; ++n)
-    if (pl.tab_count[n] && !c->tuned.count(level_key(p, pl, n))) need = true;
+  for (int n = 0; n < pl.max_levels; ++n)
+    if (pl.tab_count[n] && !c->tuned.count(level_key(c, pl, n))) need = true;
   if (!need) return BDIS_OK;
   const char* env = std::getenv("BDIS_TUNE");
   const bool enabled = !(env && std::strcmp(env, "0") == 0) && c->forced_opt < 0;
-  float best_ms[kMaxLevels];
-  int best_t[kMaxLevels];
-  for (int n = 0; n < kMaxLevels; ++n) {
-    best_ms[n] = 1e30f;
-    best_t[n] = pl.search_opt[n];
+  const double t0 = wall_ms();
+  TuneChoice best[kMaxLevels];
+  for (int n = 0; n < pl.max_levels; ++n) {
+    best[n].search = pl.search_opt[n];
+    best[n].fuse_ty = pl.fuse_ty[n];
+    best[n].pyr_tall = pl.pyr_tall[n] ? 1 : 0;
   }
   if (enabled) {
     std::vector<hipEvent_t> ev(2 * kMaxLevels, nullptr);
     hipError_t e = hipSuccess;
     for (auto& x : ev)
       if (e == hipSuccess) e = hipEventCreate(&x);
-    for (int o = 0; o < kNumSearchOptions && e == hipSuccess; ++o) {
+    bdis_status s2 = BDIS_OK;
+    // Times `trial` over kTuneReps passes; phase 0 search, 1 fusion, 2 pyramid.
+    // best_ms[n] / pick(n) record a level whose timed launch beat its best.
+    auto run_trial = [&](Plan& trial, int phase, float* best_ms, auto&& pick) {
+      assign_offsets(p, trial);
+      if ((s2 = upload_table(c, trial, st)) != BDIS_OK) return;
+      auto timed = [&](int n, int ph, auto&& launch) {
+        if (ph != phase) return launch();
+        LaunchEvents& le = launch_events();
+        le.start = ev[2 * n];
+        le.stop = ev[2 * n + 1];
+        le.used = false;
+        const hipError_t r = launch();
+        le = LaunchEvents{};
+        return r;
+      };
+      for (int rep = 0; rep < kTuneReps && e == hipSuccess; ++rep) {
+        for (int n = 1; n < trial.max_levels && e == hipSuccess; ++n)
+          e = timed(n, 2, [&] {
+            return launch_pyramid(c->tab_dev + trial.tab_first[n], trial.tab_count[n], trial.pyr_blocks[n],
+                                  trial.pyr_tall[n], st);
+          });
+        for (int n = trial.max_levels - 1; n >= p.finest_level && e == hipSuccess; --n) {
+          const PairLevel* tab = c->tab_dev + trial.tab_first[n];
+          const int cnt = trial.tab_count[n];
+          const LevelParams lp = plan_level_params(p, trial, n);
+          e = timed(n, 0, [&] { return launch_search(tab, cnt, trial.search_blocks[n], lp, trial.search_opt[n], st); });
+          if (e == hipSuccess) e = launch_reduce(tab, cnt, lp, st);
+          if (e == hipSuccess) e = launch_prob(tab, cnt, trial.prob_blocks[n], lp, st);
+          if (e == hipSuccess) e = timed(n, 1, [&] { return launch_fuse(tab, cnt, trial.fuse_blocks[n], lp, st); });
+        }
+        if (p.finest_level > 0 && e == hipSuccess)
+          e = launch_upsample(c->tab_dev + trial.tab_first[0], trial.tab_count[0], trial.up_blocks, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess || rep == 0) continue;  // the first pass warms caches and code
+        const int lo = phase == 2 ? 1 : p.finest_level;
+        for (int n = lo; n < trial.max_levels; ++n) {
+          if (!trial.tab_count[n]) continue;
+          float ms = 0.0f;
+          if (hipEventElapsedTime(&ms, ev[2 * n], ev[2 * n + 1]) == hipSuccess && ms < best_ms[n]) {
+            best_ms[n] = ms;
+            pick(n);
+          }
+        }
+      }
+    };
+    // 1. search configurations
+    float bs[kMaxLevels];
+    std::fill(bs, bs + kMaxLevels, 1e30f);
+    for (int o = 0; o < kNumSearchOptions && e == hipSuccess && s2 == BDIS_OK; ++o) {
       if (search_lds_bytes(p.patch, o, p.stride) > kSearchMaxLds) continue;
       const int kind = search_option_kind(o);
       if (kind > 0 && search_lanes(p.patch, kind) == search_lanes(p.patch, kind - 1)) continue;  // same mapping
       Plan trial = pl;
       for (int n = 0; n < trial.max_levels; ++n) trial.search_opt[n] = o;
-      assign_offsets(p, trial);
-      bdis_status s2 = upload_table(c, trial, st);
-      if (s2 != BDIS_OK) {
-        for (auto& x : ev)
-          if (x) (void)hipEventDestroy(x);
-        return s2;
+      run_trial(trial, 0, bs, [&](int n) { best[n].search = o; });
+    }
+    // 2. fusion tile heights (searches at their best)
+    float bf[kMaxLevels];
+    std::fill(bf, bf + kMaxLevels, 1e30f);
+    const int tys[3] = {kFuseTyShort, kFuseTyTall, kFuseTyHuge};
+    for (int ty : tys) {
+      if (e != hipSuccess || s2 != BDIS_OK) break;
+      if (ty == kFuseTyHuge && !fuse_tile_fits(kFuseTyHuge, p.patch, p.stride)) continue;
+      Plan trial = pl;
+      for (int n = 0; n < trial.max_levels; ++n) {
+        if (n >= p.finest_level) trial.search_opt[n] = best[n].search;
+        trial.fuse_ty[n] = ty;
       }
-      for (int rep = 0; rep < kTuneReps && e == hipSuccess; ++rep) {
-        // a full pass with each level's search launch bracketed by events
-        for (int n = 1; n < trial.max_levels && e == hipSuccess; ++n)
-          e = launch_pyramid(c->tab_dev + trial.tab_first[n], trial.tab_count[n], trial.pyr_blocks[n], trial.pyr_tall[n], st);
-        for (int n = trial.max_levels - 1; n >= p.finest_level && e == hipSuccess; --n) {
-          const PairLevel* tab = c->tab_dev + trial.tab_first[n];
-          const LevelParams lp = plan_level_params(p, trial, n);
-          (void)hipEventRecord(ev[2 * n], st);
-          e = launch_search(tab, trial.tab_count[n], trial.search_blocks[n], lp, trial.search_opt[n], st);
-          (void)hipEventRecord(ev[2 * n + 1], st);
-          if (e == hipSuccess) e = launch_reduce(tab, trial.tab_count[n], lp, st);
-          if (e == hipSuccess) e = launch_prob(tab, trial.tab_count[n], trial.prob_blocks[n], lp, st);
-          if (e == hipSuccess) e = launch_fuse(tab, trial.tab_count[n], trial.fuse_blocks[n], lp, st);
+      run_trial(trial, 1, bf, [&](int n) { best[n].fuse_ty = ty; });
+    }
+    // 3. pyramid forms
+    float bp[kMaxLevels];
+    std::fill(bp, bp + kMaxLevels, 1e30f);
+    for (int tall = 0; tall <= 1 && e == hipSuccess && s2 == BDIS_OK; ++tall) {
+      Plan trial = pl;
+      for (int n = 0; n < trial.max_levels; ++n) {
+        if (n >= p.finest_level) {
+          trial.search_opt[n] = best[n].search;
+          trial.fuse_ty[n] = best[n].fuse_ty;
         }
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess || rep == 0) continue;  // the first pass warms caches and code
-        for (int n = p.finest_level; n < trial.max_levels; ++n) {
-          if (!trial.tab_count[n]) continue;
-          float ms = 0.0f;
-          if (hipEventElapsedTime(&ms, ev[2 * n], ev[2 * n + 1]) == hipSuccess && ms < best_ms[n]) {
-            best_ms[n] = ms;
-            best_t[n] = trial.search_opt[n];
-          }
-        }
+        trial.pyr_tall[n] = tall == 1;
       }
+      run_trial(trial, 2, bp, [&](int n) { best[n].pyr_tall = tall; });
     }
     for (auto& x : ev)
       if (x) (void)hipEventDestroy(x);
+    if (s2 != BDIS_OK) return s2;
     if (e != hipSuccess) return hip_fail(c, e, "tuning");
   }
-  for (int n = p.finest_level; n < pl.max_levels; ++n) {
+  for (int n = 0; n < pl.max_levels; ++n) {
     if (!pl.tab_count[n]) continue;
-    c->tuned[level_key(p, pl, n)] = best_t[n];
-    pl.search_opt[n] = best_t[n];
+    TuneChoice tc = best[n];
+    if (n < p.finest_level) tc.search = -1, tc.fuse_ty = 0;
+    if (n == 0) tc.pyr_tall = -1;
+    c->tuned[level_key(c, pl, n)] = tc;
+    if (n >= p.finest_level) {
+      pl.search_opt[n] = best[n].search;
+      pl.fuse_ty[n] = best[n].fuse_ty;
+    }
+    if (n >= 1) pl.pyr_tall[n] = best[n].pyr_tall == 1;
   }
   assign_offsets(p, pl);
+  c->last_tune_ms = wall_ms() - t0;
+  if (enabled) return save_tune_cache(c);
   return BDIS_OK;
 }
 
@@ -907,6 +1101,7 @@ bdis_status ordered(bdis_ctx* c, hipStream_t st, F&& run) {
 }
 
 bdis_status run_pairs(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipStream_t st) {
+  c->last_tune_ms = c->last_capture_ms = 0.0;
   Plan pl;
   bdis_status s = build_plan(c, pairs.data(), pairs.size(), &pl);
   if (s != BDIS_OK) return s;
@@ -926,7 +1121,7 @@ bdis_status run_pairs_f32(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipSt
   const bdis_params& p = c->p;
   hipError_t e;
   for (int n = 0; n < pl.max_levels; ++n) {
-    const long tmk = timing_start(c, BDIS_K_PYRAMID, st);
+    const long tmk = timing_start(c, BDIS_K_PYRAMID, st, n);
     e = launch_pyramid_f64(c->tab_dev + pl.tab_first[n], pl.tab_count[n], pl.pyr_blocks[n], n, st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "pyramid launch");
@@ -935,19 +1130,19 @@ bdis_status run_pairs_f32(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipSt
     const PairLevel* tab = c->tab_dev + pl.tab_first[n];
     const int cnt = pl.tab_count[n];
     const LevelParams lp = plan_level_params(p, pl, n);
-    long tmk = timing_start(c, BDIS_K_SEARCH, st);
+    long tmk = timing_start(c, BDIS_K_SEARCH, st, n);
     e = launch_search_f64(tab, cnt, pl.search_blocks[n], lp, st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "search launch");
-    tmk = timing_start(c, BDIS_K_REDUCE, st);
+    tmk = timing_start(c, BDIS_K_REDUCE, st, n);
     e = launch_reduce(tab, cnt, lp, st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "reduction launch");
-    tmk = timing_start(c, BDIS_K_PROB, st);
+    tmk = timing_start(c, BDIS_K_PROB, st, n);
     e = launch_prob(tab, cnt, pl.prob_blocks[n], lp, st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "probability launch");
-    tmk = timing_start(c, BDIS_K_FUSE, st);
+    tmk = timing_start(c, BDIS_K_FUSE, st, n);
     e = launch_fuse(tab, cnt, pl.fuse_blocks[n], lp, st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "fusion launch");
@@ -971,7 +1166,7 @@ bdis_status run_flow(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipStream_
   const bdis_params& p = c->p;
   hipError_t e;
   for (int n = 1; n < pl.max_levels; ++n) {
-    const long tmk = timing_start(c, BDIS_K_PYRAMID, st);
+    const long tmk = timing_start(c, BDIS_K_PYRAMID, st, n);
     e = launch_pyramid(c->tab_dev + pl.tab_first[n], pl.tab_count[n], pl.pyr_blocks[n], pl.pyr_tall[n], st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "pyramid launch");
@@ -979,11 +1174,11 @@ bdis_status run_flow(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipStream_
   for (int n = pl.max_levels - 1; n >= 0; --n) {
     const PairLevel* tab = c->tab_dev + pl.tab_first[n];
     const LevelParams lp = plan_level_params(p, pl, n);
-    long tmk = timing_start(c, BDIS_K_SEARCH, st);
+    long tmk = timing_start(c, BDIS_K_SEARCH, st, n);
     e = launch_flow_search(tab, pl.tab_count[n], pl.search_blocks[n], lp, st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "flow search launch");
-    tmk = timing_start(c, BDIS_K_FUSE, st);
+    tmk = timing_start(c, BDIS_K_FUSE, st, n);
     e = launch_flow_fuse(tab, pl.tab_count[n], pl.fuse_blocks[n], lp, st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "flow fusion launch");
@@ -1014,13 +1209,13 @@ bdis_status run_backward(bdis_ctx* c, std::vector<PairSpec> pairs, double* grad_
     return hip_fail(c, e, "adjoint clear");
   for (int n = p.finest_level; n < pl.max_levels; ++n) {
     const int blocks[3] = {pl.pyr_blocks[n], pl.search_blocks[n], pl.prob_blocks[n]};
-    const long tmk = timing_start(c, BDIS_K_BACKWARD, st);
+    const long tmk = timing_start(c, BDIS_K_BACKWARD, st, n);
     e = launch_backward_level(c->tab_dev + pl.tab_first[n], pl.tab_count[n], blocks, level_params(p, n), st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "backward launch");
   }
   for (int n = pl.max_levels - 2; n >= 0; --n) {  // level n+1 -> level n
-    const long tmk = timing_start(c, BDIS_K_BACKWARD, st);
+    const long tmk = timing_start(c, BDIS_K_BACKWARD, st, n);
     e = launch_pyramid_adj(c->tab_dev + pl.tab_first[n], pl.tab_count[n], pl.pyr_blocks[n], st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "pyramid adjoint launch");
@@ -1156,6 +1351,19 @@ bdis_status bdis_create(bdis_ctx** out, const bdis_params* p, int max_w, int max
     delete c;
     return fail(nullptr, BDIS_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
   }
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, c->device);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(nullptr, BDIS_E_HIP, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+  }
+  c->arch = prop.gcnArchName;
+  for (char& ch : c->arch)
+    if (ch == '"' || ch == ' ') ch = '_';
+  c->tune_cache = tune_cache_path();
+  if (!c->tune_cache.empty() && c->forced_opt < 0)
+    for (const auto& kv : read_tune_cache(c->tune_cache))
+      if (kv.first.compare(0, c->arch.size() + 1, c->arch + " ") == 0) c->tuned.insert(kv);
   e = hipMalloc(reinterpret_cast<void**>(&c->ws), c->slot_bytes * (size_t)max_batch);
   if (e != hipSuccess) {
     delete c;
@@ -1476,15 +1684,27 @@ bdis_status bdis_timing_enable(bdis_ctx* c, int enable) {
   return BDIS_OK;
 }
 
+bdis_status bdis_setup_time(bdis_ctx* c, double* tune_ms, double* capture_ms) {
+  if (!c || !tune_ms || !capture_ms) return BDIS_E_ARG;
+  *tune_ms = c->last_tune_ms;
+  *capture_ms = c->last_capture_ms;
+  return BDIS_OK;
+}
+
 bdis_status bdis_timing_read(bdis_ctx* c, int kernel, double* total_ms, long* launches) {
-  if (!c || kernel < 0 || kernel >= BDIS_K_COUNT || !total_ms || !launches) return BDIS_E_ARG;
+  return bdis_timing_read_level(c, kernel, -1, total_ms, launches);
+}
+
+bdis_status bdis_timing_read_level(bdis_ctx* c, int kernel, int level, double* total_ms, long* launches) {
+  if (!c || kernel < 0 || kernel >= BDIS_K_COUNT || level < -1 || level >= kMaxLevels || !total_ms || !launches)
+    return BDIS_E_ARG;
   double tot = 0.0;
   long n = 0;
   for (const auto& m : c->tm.marks) {
-    if (m.first != kernel) continue;
-    hipError_t e = hipEventSynchronize(c->tm.pool[m.second + 1]);
+    if (m.kernel != kernel || (level >= 0 && m.level != level)) continue;
+    hipError_t e = hipEventSynchronize(c->tm.pool[m.idx + 1]);
     float ms = 0.0f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->tm.pool[m.second], c->tm.pool[m.second + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->tm.pool[m.idx], c->tm.pool[m.idx + 1]);
     if (e != hipSuccess) return hip_fail(c, e, "timing read");
     tot += ms;
     ++n;

@@ -18,3 +18,11 @@ def oracle():
     from oracle import ref
     ref.build()
     return ref
+
+
+@pytest.fixture(autouse=True)
+def _no_tune_cache_file(monkeypatch):
+    """Tests tune afresh: no tuning cache file is read or written unless a test
+    names one itself."""
+    if "BDIS_TUNE_CACHE" not in os.environ:
+        monkeypatch.setenv("BDIS_TUNE_CACHE", "")
