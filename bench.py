@@ -23,7 +23,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published fp32 vector peak
+# MI355X vector peaks: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6
+# TFLOP/s for non-packed 32-bit and for FP64 operations (the rate the search's
+# int32 / dot4 / FP64 code issues at: packed FP32 is disabled for all device
+# code of this build), 157.3 TFLOP/s with packed FP32 (reported beside it).
+VALU_PEAK_TFLOPS = 78.6
+FP32_PACKED_PEAK_TFLOPS = 157.3
 WIN = 5
 
 
@@ -80,21 +85,24 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 
 def search_bytes(bdis, p, w, h, levels=None):
     """Algorithmic HBM bytes of the patch search of one pass: both level images
-    (1 B per pixel each), per patch its record (76 B written) and the 4-tap
-    reads of the parent maps (64 B, every level but the coarsest)."""
+    (1 B per pixel each), per patch what the later phases read (displacement,
+    propagated probability, four window SSD differences as FP64, acceptance:
+    52 B written) and the 4-tap reads of the parent maps (64 B, every level but
+    the coarsest)."""
     L = levels or p.levels
     tot = 0
     for n in range(p.finest_level, L):
         lw, lh, nx, ny = bdis.level_dims(p, w, h, n)
-        tot += 2 * lw * lh + nx * ny * (76 + (64 if n + 1 < L else 0))
+        tot += 2 * lw * lh + nx * ny * (52 + (64 if n + 1 < L else 0))
     return tot
 
 
 def roofline(flops_per_step, steps, timing, kernel_name, workload, bytes_per_step=None):
     s_ms, s_n = timing["search"]
     achieved = flops_per_step * steps / (s_ms * 1e-3) / 1e12
-    out = dict(bound="alu", achieved=round(achieved, 3), peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-               frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 5), traffic=measured_traffic(workload),
+    out = dict(bound="alu", achieved=round(achieved, 3), peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
+               frac=round(achieved / VALU_PEAK_TFLOPS, 5), traffic=measured_traffic(workload),
+               frac_of_packed_fp32_peak=round(achieved / FP32_PACKED_PEAK_TFLOPS, 5),
                traffic_unit="bytes per launch", kernel=kernel_name,
                avg_launch_us=round(s_ms * 1e3 / max(s_n, 1), 3), launches=s_n)
     launch_s = s_ms * 1e-3 / max(s_n, 1)
@@ -219,7 +227,7 @@ def search_per_level(bdis, ctx, p, w, h, steps, npairs=1, levels=None):
         flops = nx * ny * npairs * (4 * P2 + 5 * p.iters * P2 + 8 * WIN * P2)
         per = ms * 1e-3 / k
         out.append(dict(level=n, patches=nx * ny * npairs, avg_us=round(per * 1e6, 3),
-                        tflops=round(flops / per / 1e12, 3), frac=round(flops / per / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 5)))
+                        tflops=round(flops / per / 1e12, 3), frac=round(flops / per / 1e12 / VALU_PEAK_TFLOPS, 5)))
     return out
 
 
@@ -661,6 +669,9 @@ def main():
     ap.add_argument("--ablation-pairs", type=int, default=4, help="pairs of the accuracy ablation (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one plain float32 copy kernel over MIB MiB (reference for HBM counters)")
+    ap.add_argument("--only", default="", metavar="LEGS",
+                    help="comma-separated legs to run besides the headline pair (c1, batch, mixed, preset, flow, "
+                         "ablation, diff); default all.  For profiling one workload at a time.")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU form "
@@ -689,18 +700,24 @@ def main():
                 ms_per_step_with_kernel_events=round(s["dt_ev"] * 1e3 / args.steps, 4),
                 latency_ms=s["latency_ms"], setup=s["setup"], **s["acc"])
     line["roofline"]["per_level"] = s["per_level"]
-    line["c1_320x240"] = bench_c1(bdis, torch, args)
+    legs = set(x.strip() for x in args.only.split(",") if x.strip())
+    run = lambda name: not legs or name in legs  # noqa: E731
+    if run("c1"):
+        line["c1_320x240"] = bench_c1(bdis, torch, args)
     batch_extra, mixed_jobs = None, None
-    if not args.no_batch:
+    if not args.no_batch and run("batch"):
         line["batch_1080p"], batch_extra = bench_batch(bdis, torch, args)
+    if not args.no_batch and run("mixed"):
         line["batch_mixed"] = bench_mixed(bdis, torch, args)
         mixed_jobs = line["batch_mixed"].pop("_oracle_jobs")
-    line["paper_preset"] = bench_preset(bdis, torch, args)
-    line["optical_flow"] = bench_flow(bdis, torch, args)
-    if args.ablation_pairs > 0:
+    if run("preset"):
+        line["paper_preset"] = bench_preset(bdis, torch, args)
+    if run("flow"):
+        line["optical_flow"] = bench_flow(bdis, torch, args)
+    if args.ablation_pairs > 0 and run("ablation"):
         line["ablation"] = bench_ablation(bdis, torch, args)
         line["variance_coverage"] = bench_coverage(bdis, torch, args)
-    if not args.no_diff:
+    if not args.no_diff and run("diff"):
         line["differentiable_c4"] = bench_diff(bdis, torch, args)
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 4
@@ -728,6 +745,7 @@ def main():
                 value=round(px / dt / 1e6, 4), unit="Mpixel/s", cores=threads, kind="oracle",
                 sample=f"16 oracle passes over the 1080p pairs ({len(base)} unique), {dt:.1f} s wall",
                 seconds_for_512_pairs_extrapolated=round(dt * 512 / 16, 1))
+        if mixed_jobs is not None:
             log("oracle on the 64 mixed pairs")
             jobs = [(l, r, ref.default_params(**m)) for (l, r, m) in mixed_jobs]
             dt, px, _ = oracle_throughput(jobs, threads)

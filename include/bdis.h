@@ -122,8 +122,14 @@ bdis_status bdis_params_check(const bdis_params* p);
 
 /* Creates a context for images up to max_w x max_h and batches of up to
  * max_batch pairs, allocating its device workspace on the current device.
- * flags: 0, or BDIS_TRAIN for the differentiable float path (below).  On
- * failure *out is NULL.
+ * The workspace holds what the coarse-to-fine pass of Sec. III / Fig. 1 keeps
+ * between its steps: the pyramid of both views (one pixel of level n covers
+ * 2^n x 2^n input pixels, Sec. III-B), the per-patch search results of each
+ * level (Eq. 1, 5-6) and the fused maps that start the next finer level
+ * (Eq. 13, Fig. 1).
+ * flags: 0, or a combination of BDIS_TRAIN (the differentiable float path,
+ * below) and BDIS_KEEP (intermediates for bdis_debug_dump).  On failure *out
+ * is NULL.
  * Errors: BDIS_E_ARG (null out/params, bad params, max_* < 1),
  *         BDIS_E_SIZE (max_w x max_h too small for the levels and patch),
  *         BDIS_E_NOMEM, BDIS_E_HIP. */
@@ -136,7 +142,12 @@ bdis_status bdis_create(bdis_ctx** out, const bdis_params* p, int max_w, int max
 bdis_status bdis_set_params(bdis_ctx* ctx, const bdis_params* p);
 
 /* One rectified uint8 pair -> disparity (required), variance and confidence
- * (nullable).  variance must be NULL unless params.variance is 1.
+ * (nullable): the problem the paper states in Sec. III (a rectified pair in,
+ * per-pixel disparity out; coarse to fine as in Fig. 1), each level searched
+ * patch by patch (Eq. 1, inverse-compositional 1-D search; Eq. 5-6 window
+ * posterior) and fused (Eq. 9-13); confidence is the fused probability of
+ * Eq. 13, variance the disparity form of Eq. 15-18.  variance must be NULL
+ * unless params.variance is 1.
  * Errors: BDIS_E_ARG, BDIS_E_SIZE (image too small for levels/patch),
  *         BDIS_E_CAPACITY (w > max_w or h > max_h), BDIS_E_HIP. */
 bdis_status bdis_compute(bdis_ctx* ctx, const uint8_t* left, const uint8_t* right, int w, int h,
@@ -144,7 +155,9 @@ bdis_status bdis_compute(bdis_ctx* ctx, const uint8_t* left, const uint8_t* righ
                          void* stream);
 
 /* A batch of n pairs of possibly different sizes and pyramid depths, all in
- * one call (every level of every pair in a fixed sequence of launches).
+ * one call (every level of every pair in a fixed sequence of launches): per
+ * pair the same computation as bdis_compute (Sec. III, Eq. 1, 5-6, 9-13,
+ * 15-18), with the same results bit for bit.
  * pairs is a HOST array of n descriptors.  Outputs as bdis_compute.
  * Errors: as bdis_compute, plus BDIS_E_CAPACITY if n > max_batch. */
 bdis_status bdis_compute_batch(bdis_ctx* ctx, int n, const bdis_pair* pairs, void* stream);
@@ -174,6 +187,12 @@ bdis_status bdis_compute_static(const bdis_params* p, const uint8_t* left, const
 /* bdis_create flag: size the workspace for the float path and keep the state
  * its backward pass needs (iterates of every patch, fusion sums, adjoints). */
 #define BDIS_TRAIN 1u
+/* bdis_create flag: store every per-patch intermediate of the uint8 path for
+ * bdis_debug_dump (start values, SSD(0), in-bounds ratios, Hessians and the
+ * patch records of every level).  Without it the search stores only what the
+ * later phases read (displacement, propagated probability, window SSD
+ * differences, acceptance). */
+#define BDIS_KEEP 2u
 
 /* One float pair of a batch (device pointers, pitch in elements). */
 typedef struct {
@@ -252,7 +271,9 @@ bdis_status bdis_coverage(bdis_ctx* ctx, const float* disparity, const float* va
 
 /* Debug access to the intermediates of the last single-pair compute (the
  * call synchronises `stream`).  `what` selects the array (BDIS_DBG_*), bytes
- * is the capacity of host_dst; returns BDIS_E_ARG if too small. */
+ * is the capacity of host_dst; returns BDIS_E_ARG if too small.  UINIT, SSD0,
+ * RHO, HESS and DENS are stored only by contexts created with BDIS_KEEP
+ * (BDIS_E_STATE otherwise). */
 enum {
   BDIS_DBG_LEFT = 0,    /* uint8 level image, W_n x H_n                              */
   BDIS_DBG_RIGHT = 1,   /* uint8 level image                                         */

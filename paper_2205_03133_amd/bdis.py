@@ -60,6 +60,7 @@ class PairGrad(ctypes.Structure):
 
 
 TRAIN = 1
+KEEP = 2
 
 
 class BdisError(RuntimeError):
@@ -199,14 +200,15 @@ def compute_static(p, left, right, *, variance=None, confidence=True, out=None, 
 
 
 class Context:
-    """Owns a ``bdis_ctx`` (device workspace sized for max_w x max_h x max_batch)."""
+    """Owns a ``bdis_ctx`` (device workspace sized for max_w x max_h x max_batch).
+    ``keep`` stores every per-patch intermediate for ``debug`` (BDIS_KEEP)."""
 
-    def __init__(self, p, max_w, max_h, max_batch=1, train=False):
+    def __init__(self, p, max_w, max_h, max_batch=1, train=False, keep=False):
         self._h = ctypes.c_void_p()
         self.params = p
         self.train = train
         st = lib().bdis_create(ctypes.byref(self._h), ctypes.byref(p), max_w, max_h, max_batch,
-                               TRAIN if train else 0)
+                               (TRAIN if train else 0) | (KEEP if keep else 0))
         if st:
             raise BdisError(st, lib().bdis_last_error(None).decode())
         self.max_w, self.max_h, self.max_batch = max_w, max_h, max_batch

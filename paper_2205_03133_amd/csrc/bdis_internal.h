@@ -50,16 +50,18 @@ struct alignas(16) D4 {
 // iteration does not contract, and rounding this state to FP32 alone moves
 // ~0.3% of output pixels by more than 1e-3 px.
 struct PatchArrays {
-  double* uinit;  // initial displacement (from the parent level)
+  double* uinit;  // initial displacement (from the parent level)           [kept]
   double* pipar;  // probability propagated from the parent level
   double* u;      // final displacement
-  double* ssd0;   // window SSD at the centre
+  double* ssd0;   // window SSD at the centre                               [kept]
   D4* dssd;       // SSD(d) - SSD(0), d = -1, -1/2, +1/2, +1
-  float* rho;     // in-bounds ratio (exact in FP32: a multiple of 1/P)
+  float* rho;     // in-bounds ratio (exact in FP32: a multiple of 1/P)     [kept]
   int* acc;       // 1 accepted
-  float* hess;    // Gauss-Newton Hessian of the patch
-  D4* dens;       // (u, weight: pi if accepted else -1, sigma_k^2, post)
+  float* hess;    // Gauss-Newton Hessian of the patch                      [kept]
+  D4* dens;       // (u, weight: pi if accepted else -1, sigma_k^2, post)  [kept on
+                  // levels whose records the fusion computes itself]
 };
+// [kept]: written only when the launch stores every intermediate (LevelParams::keep).
 
 // One pair at one pyramid level: everything a workgroup of any phase needs.
 struct PairLevel {
@@ -80,7 +82,10 @@ struct PairLevel {
   const double* par_q;
   int pw, ph;
   PatchArrays pa;
-  // sigma_r reduction of this pair and level: per-workgroup partials
+  // sigma_r reduction of this pair and level, one partial per search
+  // workgroup: the sum of SSD(0) over its accepted patches (uint8 path: the
+  // exact fixed-point sums of the low and high 32-bit halves as two uint64 at
+  // 2 b and 2 b + 1; float path: a double at b) and their count
   double* part_sum;
   int* part_cnt;
   double* scal;    // [sigma_r^2, tau, pooled residual, accepted count, d loss / d tau, SSD(0) adjoint share]
@@ -164,6 +169,9 @@ struct LevelParams {
   int fuse_ty;      // fusion tile height (kFuseTyShort, kFuseTyTall or kFuseTyHuge)
   int fuse_rec;     // patch records a fusion workgroup stages (<= kFuseMaxRec), fuse_lds_bytes
   int fuse_sep;     // staged patch rows with separable column sums (<= fuse_sep_rows(fuse_ty))
+  int keep;         // 1: store every per-patch intermediate (debug dumps, training), else
+                    // only what the later phases read
+  int f64_sums;     // 1: the float path's search partials (doubles), else the exact sums
   // 1-D mixture mask m(a) = sum_c exp(-(a - c)^2 / (2 sigma_s^2)), a = 0..P-1
   // (Eq. 9-10), and its derivative in sigma_s, evaluated once on the host
   double mask[kMaxPatch];
@@ -260,6 +268,31 @@ __host__ __device__ inline int search_lds_bytes(int P, int opt, int S) {
   search_lds_layout(P, search_patches_per_block(P, opt), S, ltw, rwb);
   return (P + 2) * ltw + P * rwb;
 }
+
+// The level sum behind sigma_r (Sec. III-B) on the uint8 path is exact: each
+// accepted patch's SSD(0) is rounded once to a multiple of 2^-36 (an integer
+// below 2^63: SSD(0) <= (2 * 255)^2 P^2 < 2^27), split into its high and low
+// 32-bit halves, and the halves are summed separately in 64 bits (below 2^55
+// for any level of up to 2^23 patches, so no carries), so the sum does not
+// depend on how patches are grouped into workgroups or in which order partials
+// are added (search configuration, batch composition, reduction shape).  The
+// rounding is far below the FP64 rounding of a sequential sum of the values.
+constexpr double kSumScale = 68719476736.0;          // 2^36
+constexpr double kSumInvScale = 1.0 / 68719476736.0;  // exact
+// An SSD(0) value as the fixed-point integer of the level sum (negative
+// rounding residue of the closed form clamped to 0).
+__host__ __device__ inline unsigned long long ssd_fixed(double ssd) {
+  const double v = ssd > 0.0 ? ssd * kSumScale : 0.0;
+  return v < 9.2e18 ? (unsigned long long)llrint(v) : 9200000000000000000ull;
+}
+// The sum from its half sums: (sum of high halves) 2^32 + (sum of low halves),
+// scaled back (two roundings of an exact integer: the same bits every time).
+__host__ __device__ inline double fixed_sum_value(unsigned long long hi_sum, unsigned long long lo_sum) {
+  return ((double)hi_sum * 4294967296.0 + (double)lo_sum) * kSumInvScale;
+}
+// Upper bound of the search workgroups of a level (every configuration puts at
+// least four patches of one row in a workgroup): sizes the partial arrays.
+__host__ __device__ inline int max_partials(const LevelGeom& g) { return (g.nx + 3) / 4 * g.ny; }
 
 // Launchers over a device table of `npairs` entries (each returns the launch status).
 hipError_t launch_pyramid(const PairLevel* tab, int npairs, int nblocks, bool tall, hipStream_t s);
@@ -400,6 +433,35 @@ BDIS_DEV double group_sum_d(double v) {
   return v;
 }
 
+// Sum over the 64 lanes of a wavefront of a 64-bit integer: DPP butterflies
+// within each row of 16 lanes (no LDS round trips), then the four row sums
+// read from lanes 0, 16, 32, 48.  Every lane returns the total.
+template <int Ctrl>
+BDIS_DEV unsigned long long dpp_move_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffull), Ctrl, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), Ctrl, 0xF, 0xF, true);
+  return ((unsigned long long)(unsigned int)hi << 32) | (unsigned int)lo;
+}
+BDIS_DEV unsigned long long wave_sum_u64(unsigned long long v) {
+  v += dpp_move_u64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move_u64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move_u64<0x141>(v);  // row_half_mirror
+  v += dpp_move_u64<0x140>(v);  // row_mirror
+  unsigned long long t = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const unsigned int lo = (unsigned int)__builtin_amdgcn_readlane((int)(v & 0xffffffffull), 16 * r);
+    const unsigned int hi = (unsigned int)__builtin_amdgcn_readlane((int)(v >> 32), 16 * r);
+    t += ((unsigned long long)hi << 32) | lo;
+  }
+  return t;
+}
+BDIS_DEV int wave_sum_i32(int v) {
+  v = group_sum<16>(v);
+  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) + __builtin_amdgcn_readlane(v, 32) +
+         __builtin_amdgcn_readlane(v, 48);
+}
+
 // Hardware FP64 atomic add on global memory (accumulation of adjoints).
 BDIS_DEV void atomic_add_d(double* p, double v) { (void)__builtin_amdgcn_global_atomic_fadd_f64(gbl(p), v); }
 
@@ -424,7 +486,7 @@ BDIS_DEV double bilinear(const double* m, int w, int h, double x, double y) {
   return (1.0 - ay) * top + ay * bot;
 }
 
-// sigma_r^(n) of one pair (a workgroup of 256 threads), read from Sec. III-B
+// sigma_r^(n) of one pair (called by a whole workgroup), read from Sec. III-B
 // as the pooled per-pixel variance of the mean-normalised residual over the
 // accepted patches of the level, scaled by alpha_r^2 and floored; or the fixed
 // sigma_r.  tau = 2 sigma_r^2 s^2 (Eq. 6).  The search partials are summed in
@@ -433,28 +495,65 @@ BDIS_DEV double bilinear(const double* m, int w, int h, double x, double y) {
 // residual, accepted count.  Every thread returns the values.
 BDIS_DEV void pair_scalars(const PairLevel& a, const LevelParams& lp, double* s_red, long long* s_redc,
                            double out[4]) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, nt = (int)blockDim.x;
   const int nblocks = a.search_nbx * a.g.ny;
-  if (tid < 256) {  // the first 256 threads of the workgroup (256 or more)
-    double ps = 0.0;
-    long long pc = 0;
-    for (int b = tid; b < nblocks; b += 256) {
-      ps += gbl(a.part_sum)[b];
-      pc += gbl(a.part_cnt)[b];
+  double sum;
+  long long cnt;
+  if (!lp.f64_sums) {
+    // exact integer sums: any split and order give the same value, so every
+    // thread strides over the partials, waves reduce by DPP and one barrier
+    // combines the waves
+    unsigned long long lo = 0, hi = 0;
+    int c = 0;
+    const auto ps = gbl(reinterpret_cast<const unsigned long long*>(a.part_sum));
+    for (int b = tid; b < nblocks; b += nt) {
+      lo += ps[2 * b];
+      hi += ps[2 * b + 1];
+      c += gbl(a.part_cnt)[b];
     }
-    s_red[tid] = ps;
-    s_redc[tid] = pc;
-  }
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (tid < off) {
-      s_red[tid] += s_red[tid + off];
-      s_redc[tid] += s_redc[tid + off];
+    lo = wave_sum_u64(lo);
+    hi = wave_sum_u64(hi);
+    c = wave_sum_i32(c);
+    unsigned long long* s_w = reinterpret_cast<unsigned long long*>(s_red);
+    const int wave = tid / 64, nw = (nt + 63) / 64;
+    if (tid % 64 == 0) {
+      s_w[2 * wave] = lo;
+      s_w[2 * wave + 1] = hi;
+      s_redc[wave] = c;
     }
     __syncthreads();
+    unsigned long long tlo = 0, thi = 0;
+    cnt = 0;
+    for (int w = 0; w < nw; ++w) {
+      tlo += s_w[2 * w];
+      thi += s_w[2 * w + 1];
+      cnt += s_redc[w];
+    }
+    sum = fixed_sum_value(thi, tlo);
+  } else {
+    // float path: 256 virtual lanes (each thread takes every nt-th one when the
+    // workgroup is smaller), the same sums in the same order at any size
+    for (int vt = tid; vt < 256; vt += nt) {
+      double ps = 0.0;
+      long long pc = 0;
+      for (int b = vt; b < nblocks; b += 256) {
+        ps += gbl(a.part_sum)[b];
+        pc += gbl(a.part_cnt)[b];
+      }
+      s_red[vt] = ps;
+      s_redc[vt] = pc;
+    }
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      for (int vt = tid; vt < off; vt += nt) {
+        s_red[vt] += s_red[vt + off];
+        s_redc[vt] += s_redc[vt + off];
+      }
+      __syncthreads();
+    }
+    sum = s_red[0];
+    cnt = s_redc[0];
   }
-  const double sum = s_red[0];
-  const long long cnt = s_redc[0];
   __syncthreads();  // the buffers may be reused by the caller
   const double alpha2 = (double)lp.sigma_r * (double)lp.sigma_r;
   const double pooled = cnt > 0 ? sum / ((double)cnt * (double)(lp.P * lp.P)) : 0.0;

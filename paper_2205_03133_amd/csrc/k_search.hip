@@ -164,7 +164,7 @@ __global__ __launch_bounds__(THREADS, (search_min_waves<P, G>())) void k_search_
 
   extern __shared__ uint32_t s_dyn[];
   __shared__ int s_umin, s_umax;
-  __shared__ double s_psum[NPB];
+  __shared__ unsigned long long s_psum[NPB];
   __shared__ int s_pcnt[NPB];
 
   const int lb = xcd_block();
@@ -514,39 +514,44 @@ __global__ __launch_bounds__(THREADS, (search_min_waves<P, G>())) void k_search_
   const double rho = (double)(inb * P) / (double)N;
   const bool acc = s0 <= sm1 && s0 <= smh && s0 <= sph && s0 <= sp1 && rho >= (double)lp.valid_ratio;
 
+  // the search results the probability and fusion read (52 B per patch), and
+  // with lp.keep the rest of the patch state (debug dumps)
   const int k = j * a.g.nx + i;
   if (g == 0 && live) {
-    gbl(a.pa.uinit)[k] = uinit;
     gbl(a.pa.pipar)[k] = pipar;
     gbl(a.pa.u)[k] = u;
-    gbl(a.pa.ssd0)[k] = s0;
     st4(a.pa.dssd + k, D4{sm1 - s0, smh - s0, sph - s0, sp1 - s0});
-    gbl(a.pa.rho)[k] = (float)rho;
     gbl(a.pa.acc)[k] = acc ? 1 : 0;
-    gbl(a.pa.hess)[k] = (float)H;
+    if (lp.keep) {
+      gbl(a.pa.uinit)[k] = uinit;
+      gbl(a.pa.ssd0)[k] = s0;
+      gbl(a.pa.rho)[k] = (float)rho;
+      gbl(a.pa.hess)[k] = (float)H;
+    }
   }
 
-  // ---- per-workgroup partial of the level reduction: sum of SSD(0) and count
-  // over accepted patches, as a fixed-order tree over the workgroup's patches
+  // ---- this workgroup's partial of the level reduction: the exact
+  // fixed-point sum of SSD(0) over its accepted patches and their count
   if (g == 0) {
-    s_psum[q] = (live && acc) ? s0 : 0.0;
+    s_psum[q] = (live && acc) ? ssd_fixed(s0) : 0ull;
     s_pcnt[q] = (live && acc) ? 1 : 0;
   }
   __syncthreads();
   if (wave == 0) {
-    double ps = 0.0;
+    unsigned long long lo = 0, hi = 0;
     int pc = 0;
     for (int t = lane; t < NPB; t += 64) {
-      ps += s_psum[t];
+      lo += s_psum[t] & 0xffffffffull;
+      hi += s_psum[t] >> 32;
       pc += s_pcnt[t];
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      ps += __shfl_xor(ps, o, 64);
-      pc += __shfl_xor(pc, o, 64);
-    }
+    lo = wave_sum_u64(lo);
+    hi = wave_sum_u64(hi);
+    pc = wave_sum_i32(pc);
     if (lane == 0) {
-      gbl(a.part_sum)[blk] = ps;
+      const auto pw = gbl(reinterpret_cast<unsigned long long*>(a.part_sum));
+      pw[2 * blk] = lo;
+      pw[2 * blk + 1] = hi;
       gbl(a.part_cnt)[blk] = pc;
     }
   }

@@ -53,7 +53,7 @@ struct Layout {
   int levels = 0;
   LevelGeom g[kMaxLevels]{};
   int lpitch[kMaxLevels]{};      // row pitch of the level images (64-byte rows)
-  int max_search_blocks[kMaxLevels]{};
+  int sum_parts[kMaxLevels]{};
   size_t lvl_l[kMaxLevels]{}, lvl_r[kMaxLevels]{};
   size_t uinit[kMaxLevels]{}, pipar[kMaxLevels]{}, u[kMaxLevels]{}, ssd0[kMaxLevels]{},
       dssd[kMaxLevels]{}, rho[kMaxLevels]{}, acc[kMaxLevels]{}, hess[kMaxLevels]{},
@@ -79,14 +79,6 @@ int search_nbx(const LevelGeom& g, int npb) { return (g.nx + npb - 1) / npb; }
 // (option index), or the fixed float-path / optical-flow search.
 int search_npb(int P, int opt, bool f64_search) {
   return f64_search ? kSearchF64Threads / group_lanes(P) : search_patches_per_block(P, opt);
-}
-
-// Fewest patches per workgroup over every search configuration (sizes the
-// per-workgroup partials).
-int min_search_npb(int P) {
-  int m = search_npb(P, 0, true);
-  for (int o = 0; o < kNumSearchOptions; ++o) m = std::min(m, search_npb(P, o, false));
-  return m;
 }
 
 // Level sizes W_n = ceil(W_{n-1} / 2); the patch grid exists on processed levels.
@@ -146,12 +138,10 @@ bool make_layout(const bdis_params& p, int w, int h, int levels, Layout* lay, bo
       L.ovar = take(npx * 4);
       L.oconf = take(npx * 4);
     }
-    // partials sized for the smallest workgroup the tuner may choose
-    L.max_search_blocks[n] =
-        search_nbx(L.g[n], min_search_npb(p.patch)) *
-        L.g[n].ny;
-    L.part_sum[n] = take((size_t)L.max_search_blocks[n] * 8);
-    L.part_cnt[n] = take((size_t)L.max_search_blocks[n] * 4);
+    // partials of the sigma_r reduction: one per search workgroup (16 bytes)
+    L.sum_parts[n] = max_partials(L.g[n]);
+    L.part_sum[n] = take((size_t)L.sum_parts[n] * 16);
+    L.part_cnt[n] = take((size_t)L.sum_parts[n] * 4);
     L.scal[n] = take(64);
   }
   if (train) {
@@ -254,6 +244,7 @@ struct Plan {
   int up_blocks = 0;             // finest level f > 0: upsampling workgroups (level 0)
   int inline_prob[kMaxLevels]{}; // 1: the fusion computes the patch records (small levels)
   int fuse_ty[kMaxLevels]{};     // fusion tile height per level
+  bool keep = false;             // store every per-patch intermediate (LevelParams::keep)
   bool pyr_tall[kMaxLevels]{};   // pyramid level built with the large-tile kernel
   bool f32 = false;              // float (FP64) path: per-pixel pyramid blocks, fixed search size
   PlanTab tab;
@@ -314,6 +305,7 @@ struct bdis_ctx {
   int forced_opt = -1;               // BDIS_SEARCH_CONFIG: one configuration for every level, no tuning
   int use_graph = 1;
   bool train = false;                // created with BDIS_TRAIN
+  bool keep = false;                 // created with BDIS_KEEP
   std::vector<PairSpec> last_f32;    // pairs of the last float-path call (backward state)
   double* hyper_dev = nullptr;       // d loss / d hyperparameters accumulator (2 + 8)
   // geometry of the last single-pair compute (slot 0), for debug dumps
@@ -452,6 +444,8 @@ LevelParams plan_level_params(const bdis_params& p, const Plan& pl, int n) {
   const int nj = (lp.fuse_ty + p.patch - 1) / p.stride + 2, ni = (kFuseTx + p.patch - 1) / p.stride + 2;
   lp.fuse_rec = std::min(ni * nj, kFuseMaxRec);
   lp.fuse_sep = std::min(nj, fuse_sep_rows(lp.fuse_ty));
+  lp.keep = pl.keep ? 1 : 0;
+  lp.f64_sums = pl.f32 ? 1 : 0;
   return lp;
 }
 
@@ -536,6 +530,7 @@ bdis_status build_plan(bdis_ctx* c, const PairSpec* pairs, size_t npairs, Plan* 
   pl.finest = p.finest_level;
   pl.f32 = f32;
   pl.flow = flow;
+  pl.keep = c->keep || f32;  // the backward pass reads the records
   // a single pair's layout lives on the stack (no heap use)
   Layout lay_one;
   std::vector<Layout> lay_many;
@@ -760,13 +755,18 @@ bdis_status upload_table(bdis_ctx* c, const Plan& pl, hipStream_t st) {
   return BDIS_OK;
 }
 
+// The pyramid launch of level n under plan pl.
+hipError_t launch_pyramid_level(const PairLevel* tab_dev, const Plan& pl, int n, hipStream_t st) {
+  return launch_pyramid(tab_dev + pl.tab_first[n], pl.tab_count[n], pl.pyr_blocks[n], pl.pyr_tall[n], st);
+}
+
 // The launch sequence of a plan (eager; optionally timed per kernel).
 bdis_status launch_all(bdis_ctx* c, const Plan& pl, hipStream_t st) {
   const bdis_params& p = c->p;
   hipError_t e;
   for (int n = 1; n < pl.max_levels; ++n) {
     const long tmk = timing_start(c, BDIS_K_PYRAMID, st, n);
-    e = launch_pyramid(c->tab_dev + pl.tab_first[n], pl.tab_count[n], pl.pyr_blocks[n], pl.pyr_tall[n], st);
+    e = launch_pyramid_level(c->tab_dev, pl, n, st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "pyramid launch");
   }
@@ -952,6 +952,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
     auto run_trial = [&](Plan& trial, int phase, float* best_ms, auto&& pick) {
       assign_offsets(p, trial);
       if ((s2 = upload_table(c, trial, st)) != BDIS_OK) return;
+      bool rec[kMaxLevels] = {};  // levels whose timed phase launched a kernel (recorded its events)
       auto timed = [&](int n, int ph, auto&& launch) {
         if (ph != phase) return launch();
         LaunchEvents& le = launch_events();
@@ -959,15 +960,13 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
         le.stop = ev[2 * n + 1];
         le.used = false;
         const hipError_t r = launch();
+        rec[n] = le.used;
         le = LaunchEvents{};
         return r;
       };
       for (int rep = 0; rep < kTuneReps && e == hipSuccess; ++rep) {
         for (int n = 1; n < trial.max_levels && e == hipSuccess; ++n)
-          e = timed(n, 2, [&] {
-            return launch_pyramid(c->tab_dev + trial.tab_first[n], trial.tab_count[n], trial.pyr_blocks[n],
-                                  trial.pyr_tall[n], st);
-          });
+          e = timed(n, 2, [&] { return launch_pyramid_level(c->tab_dev, trial, n, st); });
         for (int n = trial.max_levels - 1; n >= p.finest_level && e == hipSuccess; --n) {
           const PairLevel* tab = c->tab_dev + trial.tab_first[n];
           const int cnt = trial.tab_count[n];
@@ -983,7 +982,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
         if (e != hipSuccess || rep == 0) continue;  // the first pass warms caches and code
         const int lo = phase == 2 ? 1 : p.finest_level;
         for (int n = lo; n < trial.max_levels; ++n) {
-          if (!trial.tab_count[n]) continue;
+          if (!trial.tab_count[n] || !rec[n]) continue;  // nothing launched at this level
           float ms = 0.0f;
           if (hipEventElapsedTime(&ms, ev[2 * n], ev[2 * n + 1]) == hipSuccess && ms < best_ms[n]) {
             best_ms[n] = ms;
@@ -1167,7 +1166,7 @@ bdis_status run_flow(bdis_ctx* c, const std::vector<PairSpec>& pairs, hipStream_
   hipError_t e;
   for (int n = 1; n < pl.max_levels; ++n) {
     const long tmk = timing_start(c, BDIS_K_PYRAMID, st, n);
-    e = launch_pyramid(c->tab_dev + pl.tab_first[n], pl.tab_count[n], pl.pyr_blocks[n], pl.pyr_tall[n], st);
+    e = launch_pyramid_level(c->tab_dev, pl, n, st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "pyramid launch");
   }
@@ -1315,8 +1314,8 @@ bdis_status bdis_create(bdis_ctx** out, const bdis_params* p, int max_w, int max
   char msg[256];
   bdis_status st = check_params_msg(p, msg, sizeof msg);
   if (st != BDIS_OK) return fail(nullptr, st, "%s", msg);
-  if (max_w < 1 || max_h < 1 || max_batch < 1 || (flags & ~BDIS_TRAIN) != 0)
-    return fail(nullptr, BDIS_E_ARG, "max_w/max_h/max_batch must be >= 1 and flags 0 or BDIS_TRAIN");
+  if (max_w < 1 || max_h < 1 || max_batch < 1 || (flags & ~(BDIS_TRAIN | BDIS_KEEP)) != 0)
+    return fail(nullptr, BDIS_E_ARG, "max_w/max_h/max_batch must be >= 1 and flags a combination of BDIS_TRAIN, BDIS_KEEP");
   const bool train = (flags & BDIS_TRAIN) != 0;
   Layout lay;
   if (!make_layout(*p, max_w, max_h, p->levels, &lay, train))
@@ -1333,6 +1332,7 @@ bdis_status bdis_create(bdis_ctx** out, const bdis_params* p, int max_w, int max
   c->max_batch = max_batch;
   c->slot_bytes = lay.total;
   c->train = train;
+  c->keep = (flags & BDIS_KEEP) != 0;
   const char* g = std::getenv("BDIS_GRAPH");
   c->use_graph = !(g && std::strcmp(g, "0") == 0);
   if (const char* so = std::getenv("BDIS_SEARCH_CONFIG")) {
@@ -1594,6 +1594,9 @@ bdis_status bdis_debug_dump(bdis_ctx* c, int level, int what, void* host_dst, si
   }
   if ((what == BDIS_DBG_LEFT || what == BDIS_DBG_RIGHT) && level == 0)
     return fail(c, BDIS_E_ARG, "level 0 images are the caller's inputs");
+  if (!c->keep && (what == BDIS_DBG_UINIT || what == BDIS_DBG_SSD0 || what == BDIS_DBG_RHO ||
+                   what == BDIS_DBG_HESS || what == BDIS_DBG_DENS))
+    return fail(c, BDIS_E_STATE, "dump %d is stored only by contexts created with BDIS_KEEP", what);
   if ((what >= BDIS_DBG_UINIT && what <= BDIS_DBG_DENS) && !patch_level)
     return fail(c, BDIS_E_ARG, "level %d has no patches", level);
   if ((what == BDIS_DBG_UBAR || what == BDIS_DBG_QMAP) && level <= c->p.finest_level)

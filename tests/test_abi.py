@@ -87,7 +87,7 @@ def test_null_context_calls(B):
     assert B.lib().bdis_compute_f32(None, None, None, 1, 1, 1, None, None, None, None) == B.E_ARG
     assert B.lib().bdis_backward(None, None, None, None, None, None, None) == B.E_ARG
     h = ctypes.c_void_p()
-    assert B.lib().bdis_create(ctypes.byref(h), ctypes.byref(B.params()), 64, 64, 1, 6) == B.E_ARG
+    assert B.lib().bdis_create(ctypes.byref(h), ctypes.byref(B.params()), 64, 64, 1, 4) == B.E_ARG
     B.lib().bdis_destroy(None)
     assert B.lib().bdis_version().startswith(b"bdis")
 
