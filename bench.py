@@ -47,7 +47,7 @@ def search_flops(bdis, p, w, h, levels=None):
     return tot
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_hbm_traffic_c2_640x480_and_c5_1080p_batch64.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_hbm_traffic_640x480_1080p_batch64_mixed64.md")
 # the search kernel's source and the header that fixes its layouts and launch shapes
 SEARCH_SRC = [os.path.join(ROOT, "paper_2205_03133_amd", "csrc", "k_search.hip"),
               os.path.join(ROOT, "paper_2205_03133_amd", "csrc", "bdis_internal.h")]
