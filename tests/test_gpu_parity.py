@@ -7,8 +7,8 @@ disagreements counted as misses, max error printed.
 import numpy as np
 import pytest
 
-from _common import (DISP_TOL, MAX_FLIP_FRAC, PASS_FRAC, VAR_FLOOR, VAR_RTOL, oracle_params, parity,
-                     to_gpu, variance_parity)
+from _common import (DISP_TOL, MAX_FLIP_FRAC, MAX_ILL_FRAC, PASS_FRAC, VAR_FLOOR, VAR_RTOL, divergence_analysis,
+                     oracle_params, parity, to_gpu, variance_parity)
 
 pytestmark = pytest.mark.gpu
 
@@ -431,6 +431,86 @@ def test_batch_matches_single(B):
             assert torch.equal(torch.nan_to_num(outs[i][k], nan=-7.0), torch.nan_to_num(one[k], nan=-7.0)), (i, k)
         ctx1.close()
     ctx.close()
+
+
+def _explain_pair(B, oracle, left, right, p, g, r):
+    """Disagreements of a pair (computed in a batch: g) with the oracle (r),
+    explained patch by patch on a single-pair run that keeps its
+    intermediates (the same bits as the batch)."""
+    import torch
+    h, w = left.shape
+    ctx = B.Context(p, w, h, keep=True)
+    one = ctx.compute(to_gpu(left), to_gpu(right))
+    torch.cuda.synchronize()
+    for k in ("disp", "var", "conf"):
+        assert np.array_equal(np.nan_to_num(one[k].cpu().numpy(), nan=-7.0), np.nan_to_num(g[k], nan=-7.0)), k
+    tr = oracle.compute(left, right, oracle_params(oracle, p), trace=True)["trace"]
+    counts, fp0, how = divergence_analysis(ctx, tr, p)
+    for n in sorted(counts, reverse=True):
+        nx, ny = tr.dims(n)[2:]
+        print(f"  level {n}: {counts[n]} patches disagree of {nx * ny}: {how[n]}", flush=True)
+    for n in counts:
+        nx, ny = tr.dims(n)[2:]
+        assert how[n]["window_tie"] <= MAX_FLIP_FRAC * nx * ny
+        assert how[n]["searched"] <= MAX_ILL_FRAC * nx * ny
+    assert p.finest_level == 0
+    n_rest = int((~fp0).sum())
+    for name, tol in (("disp", DISP_TOL), ("conf", 1e-4)):
+        away = parity(np.where(fp0, 0.0, g[name]), np.where(fp0, 0.0, r[name]), tol)
+        frac_rest = 1.0 - (1.0 - away["frac"]) * away["n"] / max(n_rest, 1)
+        print(f"  {name} away from the {int(fp0.sum())} pixels those patches reach: {frac_rest:.6f}", flush=True)
+        assert frac_rest >= PASS_FRAC
+    # the variance also moves with the level's tau, which the differing
+    # acceptances change: fit decisions (Eq. 17 threshold) near the margin flip
+    vp = variance_parity(g["var"], r["var"], ctx.debug(0, "acc") > 0, ctx.debug(0, "dens")[..., 2],
+                         tr.get(0, "acc") > 0, tr.get(0, "sigk2"), p.patch, p.stride, exclude=fp0)
+    print(f"  variance away from those pixels and from {vp['flip_patches']} decision-flipped patches: "
+          f"{vp['away_frac']:.6f}", flush=True)
+    assert vp["flip_frac"] <= MAX_FLIP_FRAC
+    assert vp["away_frac"] >= PASS_FRAC
+    ctx.close()
+
+
+def test_mixed_batch_against_oracle(B, oracle):
+    """Pairs of the mixed-resolution batch (640x480 up to 1920x1080, P 8 S 3
+    K 16, depth 5 or 6 by size, variance) computed in one batched call and each
+    compared with the FP64 oracle directly (not only through the single-pair
+    path)."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    idx = [16, 24, 32, 40, 48, 56]   # 640x480, 720x576, 1024x768, 1280x720, 1600x900, 1920x1080
+    pairs = [make_pair(3, i) for i in idx]
+    mps = [method_params(3, i) for i in idx]
+    assert {m["levels"] for m in mps} == {5, 6}
+    p = B.params(**mps[-1])
+    print(f"[gpu] mixed batch of {len(idx)} pairs vs oracle: "
+          + ", ".join(f"{pr[0].shape[1]}x{pr[0].shape[0]} L{m['levels']}" for pr, m in zip(pairs, mps)), flush=True)
+    ctx = B.Context(p, 1920, 1080, max_batch=len(idx))
+    outs = ctx.compute_batch([to_gpu(pr[0]) for pr in pairs], [to_gpu(pr[1]) for pr in pairs],
+                             levels=[m["levels"] for m in mps])
+    torch.cuda.synchronize()
+    got = [{k: v.cpu().numpy() for k, v in o.items()} for o in outs]
+    ctx.close()
+
+    def ref(i):
+        return oracle.compute(pairs[i][0], pairs[i][1], oracle_params(oracle, B.params(**mps[i])))
+    with ThreadPoolExecutor(max_workers=len(idx)) as ex:
+        refs = list(ex.map(ref, range(len(idx))))
+    for i, (g, r) in enumerate(zip(got, refs)):
+        print(f"  pair {idx[i]} ({pairs[i][0].shape[1]}x{pairs[i][0].shape[0]}, L{mps[i]['levels']})", flush=True)
+        st = parity(g["disp"], r["disp"], DISP_TOL)
+        _report("disparity", st)
+        stc = parity(g["conf"], r["conf"], 1e-4)
+        _report("confidence", stc)
+        stv = parity(g["var"], r["var"], VAR_RTOL, rel=True)
+        _report("variance", stv)
+        if min(st["frac"], stc["frac"]) >= PASS_FRAC and stv["frac"] >= VAR_FLOOR:
+            continue
+        # Below the bar: every disagreeing patch must be explained (inherited
+        # from a disagreement at the parent level, or ill-conditioned in exact
+        # arithmetic), and the pixels away from their footprint must agree.
+        _explain_pair(B, oracle, pairs[i][0], pairs[i][1], B.params(**mps[i]), g, r)
 
 
 @pytest.mark.parametrize("over", [

@@ -217,6 +217,45 @@ def test_search_stays_within_patch_threshold(oracle):
         assert np.any(du == 0.0) and np.any(du > 0.0)
 
 
+def test_search_against_exact_rational_trajectory(oracle):
+    """Eq. 1 in exact rational arithmetic (the test helper `exact_lk`) against
+    the oracle's FP64 search.  Well-conditioned patches agree to rounding.  A
+    near-textureless patch of the mixed-resolution workload (1600x900 pair,
+    level 1) is chaotic: its huge steps amplify one rounding into pixels, so
+    the oracle's FP64 result is off the exact one by more than 1 px and starts
+    1e-9 px apart end more than 1e-3 px apart -- no FP64 evaluation order
+    determines such a patch to the 1e-3 px parity tolerance."""
+    from _common import exact_lk
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    left, right = shifted_pair_u8(21, 40, 56, 3)
+    P, K = 8, 8
+    p = oracle.default_params(levels=1, patch=P, stride=4, iters=K)
+    tr = oracle.compute(left, right, p, trace=True)["trace"]
+    H, u, u0 = tr.get(0, "hess"), tr.get(0, "u"), tr.get(0, "uinit")
+    L0, R0 = tr.get(0, "left"), tr.get(0, "right")
+    ny, nx = H.shape
+    ox = np.minimum(np.arange(nx) * 4, L0.shape[1] - P)
+    oy = np.minimum(np.arange(ny) * 4, L0.shape[0] - P)
+    checked = 0
+    for j, i in np.argwhere(H > np.median(H))[:10]:
+        e = exact_lk(L0, R0, int(ox[i]), int(oy[j]), P, K, u0[j, i])
+        assert abs(float(e) - u[j, i]) < 1e-9, (j, i, float(e), u[j, i])
+        checked += 1
+    assert checked == 10
+
+    l3, r3, _, _ = make_pair(3, 48)
+    mp = method_params(3, 48)
+    tr = oracle.compute(l3, r3, oracle.default_params(**mp), trace=True)["trace"]
+    L1, R1 = tr.get(1, "left"), tr.get(1, "right")
+    j, i = 124, 3
+    ox1, oy1 = 3 * i, 3 * j
+    assert tr.get(1, "uinit")[j, i] == 0.0 and tr.get(1, "hess")[j, i] < 10.0
+    e = exact_lk(L1, R1, ox1, oy1, mp["patch"], mp["iters"], 0.0)
+    assert abs(float(e) - tr.get(1, "u")[j, i]) > 1.0
+    e2 = exact_lk(L1, R1, ox1, oy1, mp["patch"], mp["iters"], 1e-9)
+    assert abs(float(e2 - e)) > 1e-3
+
+
 def test_zero_hessian_keeps_start(oracle):
     flat = np.full((20, 30), 100, np.uint8)
     other = np.random.default_rng(0).integers(0, 256, (20, 30), dtype=np.uint8)
