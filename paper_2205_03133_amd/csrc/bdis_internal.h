@@ -303,6 +303,20 @@ hipError_t launch_prob(const PairLevel* tab, int npairs, int nblocks, const Leve
 hipError_t launch_fuse(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,
                        hipStream_t s);
 hipError_t launch_upsample(const PairLevel* tab, int npairs, int nblocks, hipStream_t s);
+// The coarsest level of each pair in one workgroup (pyramid step, search, level
+// scalars, records and fusion of that level): lanes per patch (0: the level
+// takes the per-phase launches) and the dynamic LDS layout in bytes.
+struct TopShape {
+  int g;                  // lanes per patch
+  int sw4, src_rows;      // row stride and rows of one staged view of the level below
+  int img_px;             // bytes of one plain level image
+  int ltw, rwb;           // row strides of the search's left (rows -1 .. h) and right views
+  int np_max;             // patches of the largest pair of the launch
+  int off_img, off_left, off_right, off_pat;
+  int lds;
+};
+TopShape top_shape(int P, int S, int maxw, int maxh, int maxsw, int maxsh, int maxnp);
+hipError_t launch_top(const PairLevel* tab, int npairs, const LevelParams& lp, const TopShape& ts, hipStream_t s);
 hipError_t launch_coverage(const float* disp, const float* var, const float* ref, const uint8_t* valid, int w,
                            int h, int pitch, double k, unsigned long long* counts, hipStream_t s);
 hipError_t launch_flow_search(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp, hipStream_t s);
@@ -486,6 +500,20 @@ BDIS_DEV double bilinear(const double* m, int w, int h, double x, double y) {
   return (1.0 - ay) * top + ay * bot;
 }
 
+// The level scalars from the level sum of SSD(0) over the accepted patches
+// and their count (Sec. III-B, Eq. 6): sigma_r^2 (the pooled per-pixel variance
+// of the mean-normalised residual scaled by alpha_r^2 and floored, or the
+// fixed alpha_r^2), tau = 2 sigma_r^2 s^2, the pooled residual, the count.
+BDIS_DEV void level_scalars(const LevelParams& lp, double sum, long long cnt, double out[4]) {
+  const double alpha2 = (double)lp.sigma_r * (double)lp.sigma_r;
+  const double pooled = cnt > 0 ? sum / ((double)cnt * (double)(lp.P * lp.P)) : 0.0;
+  const double sr2 = lp.sigma_r_dynamic ? alpha2 * (pooled > kEpsSigma ? pooled : kEpsSigma) : alpha2;
+  out[0] = sr2;
+  out[1] = 2.0 * sr2 * (double)(kWin * kWin);
+  out[2] = pooled;
+  out[3] = (double)cnt;
+}
+
 // sigma_r^(n) of one pair (called by a whole workgroup), read from Sec. III-B
 // as the pooled per-pixel variance of the mean-normalised residual over the
 // accepted patches of the level, scaled by alpha_r^2 and floored; or the fixed
@@ -555,13 +583,7 @@ BDIS_DEV void pair_scalars(const PairLevel& a, const LevelParams& lp, double* s_
     cnt = s_redc[0];
   }
   __syncthreads();  // the buffers may be reused by the caller
-  const double alpha2 = (double)lp.sigma_r * (double)lp.sigma_r;
-  const double pooled = cnt > 0 ? sum / ((double)cnt * (double)(lp.P * lp.P)) : 0.0;
-  const double sr2 = lp.sigma_r_dynamic ? alpha2 * (pooled > kEpsSigma ? pooled : kEpsSigma) : alpha2;
-  out[0] = sr2;
-  out[1] = 2.0 * sr2 * (double)(kWin * kWin);
-  out[2] = pooled;
-  out[3] = (double)cnt;
+  level_scalars(lp, sum, cnt, out);
 }
 
 // floor(a / d) for 0 <= a < 2^22 and 1 <= d <= 2^10: a float reciprocal

@@ -24,7 +24,10 @@ BDIS_DEV PatchRaw patch_raw(const PairLevel& a, const LevelParams& lp, size_t k)
 
 // The fusion record of patch p of pyramid level `level`: (u, pi or -1 when
 // rejected, sigma_k^2 at the finest level with variance on, else NaN, post).
+// No floating-point contraction, so every kernel that inlines it gets the
+// same bits.
 BDIS_DEV D4 patch_record(const PairLevel& a, const LevelParams& lp, int level, const PatchRaw& p, double tau) {
+#pragma clang fp contract(off)
   const double u = p.u;
   const double nan = __builtin_nan("");
   if (!p.acc) return D4{u, -1.0, nan, 0.0};
@@ -69,12 +72,14 @@ BDIS_DEV D4 patch_record(const PairLevel& a, const LevelParams& lp, int level, c
 //   A0 = sum_i m_x pi, A1 = sum_i m_x pi u, A2 = sum_i m_x, A3 = sum_i (m_x pi)^2 sigma^2,
 //   z = sum_j m_y A0, zu = sum_j m_y A1, zm = sum_j m_y A2, zv = sum_j m_y^2 A3.
 // The staged separable form and the direct per-pixel form both go through
-// these two helpers (explicit FMAs, patches in ascending index), so the fused
-// maps are the same bits whatever the tile shape.
+// these two helpers (explicit FMAs, no other contraction, patches in ascending
+// index), so the fused maps are the same bits whatever the tile shape and
+// whichever kernel inlines them.
 struct ColSums {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 };
 BDIS_DEV void col_add(ColSums& c, double mx, double pi, double u, double sig) {
+#pragma clang fp contract(off)
   const double wx = mx * pi;
   c.a0 += wx;
   c.a1 = fma(wx, u, c.a1);
@@ -85,6 +90,7 @@ struct PixSums {
   double z = 0.0, zu = 0.0, zm = 0.0, zv = 0.0;
 };
 BDIS_DEV void row_add(PixSums& p, double my, double a0, double a1, double a2, double a3) {
+#pragma clang fp contract(off)
   p.z = fma(my, a0, p.z);
   p.zu = fma(my, a1, p.zu);
   p.zm = fma(my, a2, p.zm);

@@ -247,6 +247,8 @@ struct Plan {
   bool keep = false;             // store every per-patch intermediate (LevelParams::keep)
   bool pyr_tall[kMaxLevels]{};   // pyramid level built with the large-tile kernel
   bool f32 = false;              // float (FP64) path: per-pixel pyramid blocks, fixed search size
+  int top_level = -1;            // level whose pyramid step, search and fusion run in k_top (-1: none)
+  TopShape top{};                // its launch shape
   PlanTab tab;
 };
 
@@ -268,6 +270,7 @@ struct TuneChoice {
   int search = -1;   // uint8 search configuration (option index)
   int fuse_ty = 0;   // fusion tile height
   int pyr_tall = -1; // pyramid form: 1 staged 120 x 12 tiles, 0 gather 64 x 4 tiles
+  int top = -1;      // coarsest level: 1 one workgroup per pair (k_top), 0 the per-phase launches
 };
 
 // A captured launch sequence for one batch shape.
@@ -303,6 +306,7 @@ struct bdis_ctx {
   std::string tune_cache;            // file the tuned choices persist in ("" = none)
   double last_tune_ms = 0.0, last_capture_ms = 0.0;  // host time of the last call's tuning / capture
   int forced_opt = -1;               // BDIS_SEARCH_CONFIG: one configuration for every level, no tuning
+  bool top_off = false;              // BDIS_TOP=0: the coarsest level takes the per-phase launches
   int use_graph = 1;
   bool train = false;                // created with BDIS_TRAIN
   bool keep = false;                 // created with BDIS_KEEP
@@ -696,6 +700,7 @@ bdis_status build_plan(bdis_ctx* c, const PairSpec* pairs, size_t npairs, Plan* 
   }
   // tuned choices of this batch shape (uint8 stereo path; the key is a string,
   // so it is built only when something was tuned or loaded)
+  bool top_tuned_off = false;
   if (!f32 && !flow && !c->tuned.empty()) {
     for (int n = 0; n < pl.max_levels; ++n) {
       if (pl.tab_count[n] == 0) continue;
@@ -709,10 +714,28 @@ bdis_status build_plan(bdis_ctx* c, const PairSpec* pairs, size_t npairs, Plan* 
           (tc.fuse_ty != kFuseTyHuge || fuse_tile_fits(kFuseTyHuge, p.patch, p.stride)))
         pl.fuse_ty[n] = tc.fuse_ty;
       if (n >= 1 && (tc.pyr_tall == 0 || tc.pyr_tall == 1)) pl.pyr_tall[n] = tc.pyr_tall == 1;
+      if (tc.top == 0) top_tuned_off = true;
     }
   }
   if (!f32 && !flow && c->forced_opt >= 0)
     for (int n = p.finest_level; n < pl.max_levels; ++n) pl.search_opt[n] = c->forced_opt;
+  // the coarsest level of the deepest pairs (every entry there is a pair's
+  // coarsest level) in one workgroup per pair, when it is above the finest
+  // level, uses the mask weights and fits
+  const int top = pl.max_levels - 1;
+  if (!f32 && !flow && !c->top_off && !top_tuned_off && top >= 1 && top > p.finest_level && p.fusion != 1 && pl.tab_count[top] > 0) {
+    int mw = 0, mh = 0, msw = 0, msh = 0, mnp = 0;
+    for (int e = 0; e < pl.tab_count[top]; ++e) {
+      const PairLevel& q = pl.tab[pl.tab_first[top] + e];
+      mw = std::max(mw, q.g.w);
+      mh = std::max(mh, q.g.h);
+      msw = std::max(msw, q.sw);
+      msh = std::max(msh, q.sh);
+      mnp = std::max(mnp, q.g.nx * q.g.ny);
+    }
+    pl.top = top_shape(p.patch, p.stride, mw, mh, msw, msh, mnp);
+    if (pl.top.g > 0) pl.top_level = top;
+  }
   assign_offsets(p, pl);
   return BDIS_OK;
 }
@@ -765,6 +788,7 @@ bdis_status launch_all(bdis_ctx* c, const Plan& pl, hipStream_t st) {
   const bdis_params& p = c->p;
   hipError_t e;
   for (int n = 1; n < pl.max_levels; ++n) {
+    if (n == pl.top_level) continue;  // built inside k_top
     const long tmk = timing_start(c, BDIS_K_PYRAMID, st, n);
     e = launch_pyramid_level(c->tab_dev, pl, n, st);
     timing_stop(c, tmk, st);
@@ -774,6 +798,13 @@ bdis_status launch_all(bdis_ctx* c, const Plan& pl, hipStream_t st) {
     const PairLevel* tab = c->tab_dev + pl.tab_first[n];
     const int cnt = pl.tab_count[n];
     const LevelParams lp = plan_level_params(p, pl, n);
+    if (n == pl.top_level) {  // pyramid step, search, scalars, records and fusion in one launch
+      const long tmk = timing_start(c, BDIS_K_SEARCH, st, n);
+      e = launch_top(tab, cnt, lp, pl.top, st);
+      timing_stop(c, tmk, st);
+      if (e != hipSuccess) return hip_fail(c, e, "top-level launch");
+      continue;
+    }
     long tmk = timing_start(c, BDIS_K_SEARCH, st, n);
     e = launch_search(tab, cnt, pl.search_blocks[n], lp, pl.search_opt[n], st);
     timing_stop(c, tmk, st);
@@ -866,8 +897,8 @@ std::map<std::string, TuneChoice> read_tune_cache(const std::string& path) {
     const char* q1 = std::strchr(q0 + 1, '"');
     if (!q1) continue;
     TuneChoice tc;
-    if (std::sscanf(q1 + 1, " : {\"search\": %d, \"fuse_ty\": %d, \"pyr_tall\": %d}", &tc.search, &tc.fuse_ty,
-                    &tc.pyr_tall) == 3)
+    if (std::sscanf(q1 + 1, " : {\"search\": %d, \"fuse_ty\": %d, \"pyr_tall\": %d, \"top\": %d}", &tc.search,
+                    &tc.fuse_ty, &tc.pyr_tall, &tc.top) == 4)
       out[std::string(q0 + 1, q1)] = tc;
   }
   std::fclose(f);
@@ -894,8 +925,9 @@ bdis_status save_tune_cache(bdis_ctx* c) {
   std::fprintf(f, "{\n\"bdis_tune_cache\": 1,\n\"entries\": {\n");
   size_t k = 0;
   for (const auto& kv : all)
-    std::fprintf(f, "\"%s\": {\"search\": %d, \"fuse_ty\": %d, \"pyr_tall\": %d}%s\n", kv.first.c_str(),
-                 kv.second.search, kv.second.fuse_ty, kv.second.pyr_tall, ++k < all.size() ? "," : "");
+    std::fprintf(f, "\"%s\": {\"search\": %d, \"fuse_ty\": %d, \"pyr_tall\": %d, \"top\": %d}%s\n",
+                 kv.first.c_str(), kv.second.search, kv.second.fuse_ty, kv.second.pyr_tall, kv.second.top,
+                 ++k < all.size() ? "," : "");
   std::fprintf(f, "}\n}\n");
   const bool ok = std::fclose(f) == 0;
   if (!ok || std::rename(tmp.c_str(), c->tune_cache.c_str()) != 0) (void)std::remove(tmp.c_str());
@@ -940,15 +972,19 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
     best[n].search = pl.search_opt[n];
     best[n].fuse_ty = pl.fuse_ty[n];
     best[n].pyr_tall = pl.pyr_tall[n] ? 1 : 0;
+    best[n].top = n == pl.top_level ? 1 : -1;
   }
+  const int top_cand = pl.top_level;  // the level k_top could take (-1: none)
   if (enabled) {
     std::vector<hipEvent_t> ev(2 * kMaxLevels, nullptr);
     hipError_t e = hipSuccess;
     for (auto& x : ev)
       if (e == hipSuccess) e = hipEventCreate(&x);
     bdis_status s2 = BDIS_OK;
-    // Times `trial` over kTuneReps passes; phase 0 search, 1 fusion, 2 pyramid.
-    // best_ms[n] / pick(n) record a level whose timed launch beat its best.
+    // Times `trial` over kTuneReps passes; phase 0 search, 1 fusion, 2 pyramid,
+    // 3 the coarsest level's span (its pyramid step through its fusion, or the
+    // k_top launch).  best_ms[n] / pick(n) record a level whose timed launch
+    // (or span) beat its best.
     auto run_trial = [&](Plan& trial, int phase, float* best_ms, auto&& pick) {
       assign_offsets(p, trial);
       if ((s2 = upload_table(c, trial, st)) != BDIS_OK) return;
@@ -964,23 +1000,42 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
         le = LaunchEvents{};
         return r;
       };
+      const int top = trial.max_levels - 1;
+      auto span_begin = [&](int n) {
+        LaunchEvents& le = launch_events();
+        le.start = ev[2 * n];
+        le.stop = ev[2 * n + 1];
+        le.used = false;
+      };
+      auto span_end = [&](int n) {
+        rec[n] = launch_events().used;
+        launch_events() = LaunchEvents{};
+      };
       for (int rep = 0; rep < kTuneReps && e == hipSuccess; ++rep) {
-        for (int n = 1; n < trial.max_levels && e == hipSuccess; ++n)
+        for (int n = 1; n < trial.max_levels && e == hipSuccess; ++n) {
+          if (phase == 3 && n == top) span_begin(n);
+          if (n == trial.top_level) continue;
           e = timed(n, 2, [&] { return launch_pyramid_level(c->tab_dev, trial, n, st); });
+        }
         for (int n = trial.max_levels - 1; n >= p.finest_level && e == hipSuccess; --n) {
           const PairLevel* tab = c->tab_dev + trial.tab_first[n];
           const int cnt = trial.tab_count[n];
           const LevelParams lp = plan_level_params(p, trial, n);
-          e = timed(n, 0, [&] { return launch_search(tab, cnt, trial.search_blocks[n], lp, trial.search_opt[n], st); });
-          if (e == hipSuccess) e = launch_reduce(tab, cnt, lp, st);
-          if (e == hipSuccess) e = launch_prob(tab, cnt, trial.prob_blocks[n], lp, st);
-          if (e == hipSuccess) e = timed(n, 1, [&] { return launch_fuse(tab, cnt, trial.fuse_blocks[n], lp, st); });
+          if (n == trial.top_level) {
+            e = launch_top(tab, cnt, lp, trial.top, st);
+          } else {
+            e = timed(n, 0, [&] { return launch_search(tab, cnt, trial.search_blocks[n], lp, trial.search_opt[n], st); });
+            if (e == hipSuccess) e = launch_reduce(tab, cnt, lp, st);
+            if (e == hipSuccess) e = launch_prob(tab, cnt, trial.prob_blocks[n], lp, st);
+            if (e == hipSuccess) e = timed(n, 1, [&] { return launch_fuse(tab, cnt, trial.fuse_blocks[n], lp, st); });
+          }
+          if (phase == 3 && n == top) span_end(n);
         }
         if (p.finest_level > 0 && e == hipSuccess)
           e = launch_upsample(c->tab_dev + trial.tab_first[0], trial.tab_count[0], trial.up_blocks, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess || rep == 0) continue;  // the first pass warms caches and code
-        const int lo = phase == 2 ? 1 : p.finest_level;
+        const int lo = phase == 2 ? 1 : phase == 3 ? top : p.finest_level;
         for (int n = lo; n < trial.max_levels; ++n) {
           if (!trial.tab_count[n] || !rec[n]) continue;  // nothing launched at this level
           float ms = 0.0f;
@@ -999,6 +1054,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
       const int kind = search_option_kind(o);
       if (kind > 0 && search_lanes(p.patch, kind) == search_lanes(p.patch, kind - 1)) continue;  // same mapping
       Plan trial = pl;
+      trial.top_level = -1;
       for (int n = 0; n < trial.max_levels; ++n) trial.search_opt[n] = o;
       run_trial(trial, 0, bs, [&](int n) { best[n].search = o; });
     }
@@ -1010,6 +1066,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
       if (e != hipSuccess || s2 != BDIS_OK) break;
       if (ty == kFuseTyHuge && !fuse_tile_fits(kFuseTyHuge, p.patch, p.stride)) continue;
       Plan trial = pl;
+      trial.top_level = -1;
       for (int n = 0; n < trial.max_levels; ++n) {
         if (n >= p.finest_level) trial.search_opt[n] = best[n].search;
         trial.fuse_ty[n] = ty;
@@ -1021,6 +1078,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
     std::fill(bp, bp + kMaxLevels, 1e30f);
     for (int tall = 0; tall <= 1 && e == hipSuccess && s2 == BDIS_OK; ++tall) {
       Plan trial = pl;
+      trial.top_level = -1;
       for (int n = 0; n < trial.max_levels; ++n) {
         if (n >= p.finest_level) {
           trial.search_opt[n] = best[n].search;
@@ -1029,6 +1087,24 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
         trial.pyr_tall[n] = tall == 1;
       }
       run_trial(trial, 2, bp, [&](int n) { best[n].pyr_tall = tall; });
+    }
+    // 4. the coarsest level in one workgroup per pair against its per-phase
+    // launches (the others at their best)
+    if (top_cand >= 0) {
+      float bt[kMaxLevels];
+      std::fill(bt, bt + kMaxLevels, 1e30f);
+      for (int use = 0; use <= 1 && e == hipSuccess && s2 == BDIS_OK; ++use) {
+        Plan trial = pl;
+        trial.top_level = use ? top_cand : -1;
+        for (int n = 0; n < trial.max_levels; ++n) {
+          if (n >= p.finest_level) {
+            trial.search_opt[n] = best[n].search;
+            trial.fuse_ty[n] = best[n].fuse_ty;
+          }
+          trial.pyr_tall[n] = best[n].pyr_tall == 1;
+        }
+        run_trial(trial, 3, bt, [&](int n) { best[n].top = use; });
+      }
     }
     for (auto& x : ev)
       if (x) (void)hipEventDestroy(x);
@@ -1046,6 +1122,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
       pl.fuse_ty[n] = best[n].fuse_ty;
     }
     if (n >= 1) pl.pyr_tall[n] = best[n].pyr_tall == 1;
+    if (n == top_cand && best[n].top == 0) pl.top_level = -1;
   }
   assign_offsets(p, pl);
   c->last_tune_ms = wall_ms() - t0;
@@ -1335,6 +1412,8 @@ bdis_status bdis_create(bdis_ctx** out, const bdis_params* p, int max_w, int max
   c->keep = (flags & BDIS_KEEP) != 0;
   const char* g = std::getenv("BDIS_GRAPH");
   c->use_graph = !(g && std::strcmp(g, "0") == 0);
+  const char* tp = std::getenv("BDIS_TOP");
+  c->top_off = tp && std::strcmp(tp, "0") == 0;
   if (const char* so = std::getenv("BDIS_SEARCH_CONFIG")) {
     char* end = nullptr;
     const long v = std::strtol(so, &end, 10);

@@ -634,3 +634,64 @@ def test_lean_context_matches_keep_context(B):
                 assert ctx.debug(1, "ubar").shape == (240, 320)
     for k in ("disp", "var", "conf"):
         assert torch.equal(torch.nan_to_num(outs[0][k], nan=-7.0), torch.nan_to_num(outs[1][k], nan=-7.0)), k
+
+
+@pytest.mark.parametrize("case", ["c2", "c5", "mixed_top", "c1", "preset", "batch"])
+def test_top_level_kernel_matches_per_phase_launches(B, monkeypatch, case):
+    """The coarsest level in one workgroup per pair (pyramid step, search,
+    level scalars, records, fusion) gives the same bits as the per-phase
+    launches (BDIS_TOP=0), for every lane mapping it picks: outputs, the
+    level's images, patch results, records, scalars and fused maps."""
+    import torch
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    sizes = None
+    if case == "c2":
+        pr, p = [make_pair(2, 0)], B.params(**method_params(2))                      # P8, 8 lanes per patch
+    elif case == "c5":
+        pr, p = [make_pair(5, 0)], B.params(**method_params(5))                      # P12, 8 lanes
+    elif case == "mixed_top":
+        pr, p = [make_pair(3, 56)], B.params(**method_params(3, 56))                 # 1920x1080 P8 S3: 4 lanes
+    elif case == "c1":
+        pr, p = [make_pair(1, 0)], B.params(**method_params(1))                      # 80x60 top: 2 lanes
+    elif case == "preset":
+        pr = [make_pair(2, 1)]
+        p = B.params(levels=6, finest_level=1, patch=10, stride=4, iters=12, valid_ratio=0.75, sigma_s=4.0,
+                     prob_thresh=0.15, variance=1)
+    else:
+        pr = [make_pair(2, i) for i in range(3)]
+        p = B.params(**method_params(2))
+        sizes = [(640, 480), (600, 440), (560, 480)]                                 # top entries of different sizes
+    lefts, rights = [], []
+    for i, (l, r, _, _) in enumerate(pr):
+        if sizes:
+            w, h = sizes[i]
+            l, r = l[:h, :w], r[:h, :w]
+        lefts.append(to_gpu(l))
+        rights.append(to_gpu(r))
+    h, w = max(t.shape[0] for t in lefts), max(t.shape[1] for t in lefts)
+    res = []
+    for top in ("1", "0"):
+        monkeypatch.setenv("BDIS_TOP", top)
+        print(f"[gpu] {case}: BDIS_TOP={top} {[tuple(t.shape) for t in lefts]} L={p.levels} P={p.patch} S={p.stride}",
+              flush=True)
+        ctx = B.Context(p, w, h, max_batch=len(lefts), keep=True)
+        if len(lefts) == 1:
+            o = [ctx.compute(lefts[0], rights[0])]
+        else:
+            o = ctx.compute_batch(lefts, rights)
+        torch.cuda.synchronize()
+        got = {"out": [{k: v.clone() for k, v in oo.items() if v is not None} for oo in o]}
+        if len(lefts) == 1:
+            n = p.levels - 1
+            for what in ("left", "right", "u", "pipar", "dssd", "acc", "uinit", "ssd0", "rho", "hess", "dens",
+                         "ubar", "qmap", "scal"):
+                got[what] = ctx.debug(n, what)
+        ctx.close()
+        res.append(got)
+    for i in range(len(lefts)):
+        for k in res[1]["out"][i]:
+            assert torch.equal(torch.nan_to_num(res[0]["out"][i][k], nan=-7.0),
+                               torch.nan_to_num(res[1]["out"][i][k], nan=-7.0)), (i, k)
+    for k in res[0]:
+        if k != "out":
+            assert np.array_equal(np.nan_to_num(res[0][k], nan=-7.0), np.nan_to_num(res[1][k], nan=-7.0)), k
