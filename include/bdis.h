@@ -32,7 +32,8 @@
  *    launch shapes of every level on `stream` (search lanes per patch and
  *    workgroup size, fusion tile height, pyramid form, and whether the
  *    coarsest level's pyramid step, search and fusion run as one workgroup
- *    per pair) and synchronises it,
+ *    per pair, and whether runs of small pyramid levels are built by one
+ *    launch) and synchronises it,
  *    then records the launch sequence as a graph; a job table larger than any
  *    before synchronises the device before it is reallocated.  The tuned
  *    choices persist in a cache file keyed by the device architecture and the
@@ -43,8 +44,11 @@
  *    launches eagerly without graphs, BDIS_SEARCH_CONFIG=k (read by
  *    bdis_create; k = lane mapping * 4 + workgroup-size index into 64, 128,
  *    256, 512) uses search configuration k on every level without timing
- *    (bdis_create fails with BDIS_E_ARG for an invalid k), BDIS_TOP=0 (read
- *    by bdis_create) keeps the coarsest level in its per-phase launches.
+ *    (bdis_create fails with BDIS_E_ARG for an invalid k); read by
+ *    bdis_create, BDIS_TOP=0 / 1 keeps the coarsest level in its per-phase
+ *    launches / runs it as one workgroup per pair where that fits, and
+ *    BDIS_CHAIN=0 / 1 builds the pyramid one launch per level / builds runs of
+ *    small levels in one launch where possible (unset: the tuner times both).
  *  - Errors are returned as bdis_status; the library never aborts.  The text
  *    of the last error of a context is available from bdis_last_error.
  *  - A context is not thread-safe: calls on one context must come from one

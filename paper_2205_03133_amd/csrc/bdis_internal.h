@@ -296,6 +296,16 @@ __host__ __device__ inline int max_partials(const LevelGeom& g) { return (g.nx +
 
 // Launchers over a device table of `npairs` entries (each returns the launch status).
 hipError_t launch_pyramid(const PairLevel* tab, int npairs, int nblocks, bool tall, hipStream_t s);
+// Small pyramid levels n0 + 1 .. n0 + m in one launch (tiles of the top one;
+// each workgroup stages the level-n0 region its tile depends on).
+struct PyrChain {
+  int first[kMaxLevels];  // first table entry of each level
+  int n0, m;              // built from level n0: levels n0 + 1 .. n0 + m
+  int tile;               // top-level tile edge
+  int lds_half, lds;      // dynamic LDS: two halves (0: does not fit)
+};
+PyrChain pyr_chain_shape(int n0, int m, int tile_top);
+hipError_t launch_pyr_chain(const PairLevel* tab, int npairs, int nblocks, const PyrChain& ca, hipStream_t s);
 hipError_t launch_search(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,
                          int opt, hipStream_t s);
 hipError_t launch_reduce(const PairLevel* tab, int npairs, const LevelParams& lp, hipStream_t s);

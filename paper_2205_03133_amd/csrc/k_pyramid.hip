@@ -223,7 +223,168 @@ __global__ __launch_bounds__(kPyrThreads, 5) void k_pyr_tall(const PairLevel* ta
   }
 }
 
+// Several small levels in one launch.  Workgroup b owns a tile x tile block of
+// the top level n0 + m of one pair and, scaled by 2^(top - k), the matching
+// block of every level k in between; it stages the region of level n0 those
+// pixels depend on (the block grown by two source pixels per side per level,
+// clipped to the level) with every load in flight at once, then builds each
+// level's region in LDS from the one below (a pixel reads its 5 x 5 taps at
+// reflect-101 positions, which stay inside the region below) and writes the
+// pixels it owns.  Halo pixels are computed by every neighbouring workgroup
+// that needs them; there is no communication between workgroups.
+constexpr int kChainThreads = 512;
+constexpr int kChainWordsPerThread = 16;  // staged source words per thread
+constexpr int kChainMaxLevels = 4;        // levels one chain launch builds
+
+__global__ __launch_bounds__(kChainThreads) void k_pyr_chain(const PairLevel* tab, int npairs, PyrChain ca) {
+  extern __shared__ __align__(16) uint8_t s_ch[];
+  const int b = xcd_block();
+  const int top = ca.n0 + ca.m;
+  const PairLevel* ttab = tab + ca.first[top];
+  const int e = find_pair<0>(ttab, npairs, b);
+  const PairLevel& at = ttab[e];
+  const int tiles_x = (at.g.w + ca.tile - 1) / ca.tile;
+  const int t = b - at.pyr0;
+  const int tid = threadIdx.x;
+  const int tx = (t % tiles_x) * ca.tile, ty = (t / tiles_x) * ca.tile;
+  // level sizes relative to n0 (j = 0 .. m), in registers (the loops below are unrolled)
+  int lw[kChainMaxLevels + 1], lh[kChainMaxLevels + 1];
+  lw[0] = tab[ca.first[ca.n0 + 1] + e].sw;
+  lh[0] = tab[ca.first[ca.n0 + 1] + e].sh;
+#pragma unroll
+  for (int j = 1; j <= kChainMaxLevels; ++j) {
+    const PairLevel& q = tab[ca.first[min(ca.n0 + j, top)] + e];
+    lw[j] = q.g.w;
+    lh[j] = q.g.h;
+  }
+  const int wtop = at.g.w, htop = at.g.h;
+  const int tx1 = min(tx + ca.tile, wtop), ty1 = min(ty + ca.tile, htop);
+  // region of level n0 + j needed by the tile, d = m - j levels below the top:
+  // [2^d (tx - 2) + 2, 2^d (tx1 + 1) - 1) (the tile grown by two source pixels
+  // per side per level), clipped to the level
+  auto region = [&](int j, int& x0, int& x1, int& y0, int& y1) {
+    const int d = ca.m - j;
+    x0 = max((tx - 2) * (1 << d) + 2, 0);
+    x1 = min((tx1 + 1) * (1 << d) - 1, lw[j]);
+    y0 = max((ty - 2) * (1 << d) + 2, 0);
+    y1 = min((ty1 + 1) * (1 << d) - 1, lh[j]);
+  };
+  int rx0, rx1, ry0, ry1;
+  region(0, rx0, rx1, ry0, ry1);
+  // the source region starts at a 4-aligned column (dword loads)
+  const int ax0 = rx0 & ~3;
+  const int sw_words = (rx1 - ax0 + 3) / 4;
+  const int srows = ry1 - ry0;
+
+  // ---- 1. stage the level-n0 region of both views
+  {
+    const PairLevel& a1 = tab[ca.first[ca.n0 + 1] + e];
+    const int words = 2 * srows * sw_words;
+    uint32_t v[kChainWordsPerThread];
+#pragma unroll
+    for (int i = 0; i < kChainWordsPerThread; ++i) {
+      const int idx = tid + i * kChainThreads;
+      v[i] = 0;
+      if (idx < words) {
+        const int row = idx / sw_words, c = ax0 + 4 * (idx - row * sw_words);
+        const bool right = row >= srows;
+        const int y = ry0 + (right ? row - srows : row);
+        const uint8_t* rp = (right ? a1.srcR : a1.srcL) + (size_t)y * a1.spitch;
+        const auto gp = gbl(rp);
+        if (((uintptr_t)rp & 3) == 0 && c + 3 < lw[0]) {
+          v[i] = *reinterpret_cast<const __attribute__((address_space(1))) uint32_t*>(gp + c);
+        } else {
+#pragma unroll
+          for (int bb = 0; bb < 4; ++bb) v[i] |= (uint32_t)gp[min(c + bb, lw[0] - 1)] << (8 * bb);
+        }
+      }
+    }
+    uint32_t* const dst = reinterpret_cast<uint32_t*>(s_ch);
+#pragma unroll
+    for (int i = 0; i < kChainWordsPerThread; ++i) {
+      const int idx = tid + i * kChainThreads;
+      if (idx < words) dst[idx] = v[i];
+    }
+  }
+  __syncthreads();
+
+  // ---- 2. each level from the one below (the LDS halves alternate)
+  const uint8_t* src = s_ch;
+  int src_x0 = ax0, src_y0 = ry0, src_stride = 4 * sw_words, src_rows = srows;
+  uint8_t* buf = s_ch + ca.lds_half;
+#pragma unroll
+  for (int j = 1; j <= kChainMaxLevels; ++j) {
+    if (j > ca.m) break;
+    const int k = ca.n0 + j;
+    const PairLevel& q = tab[ca.first[k] + e];
+    int x0, x1, y0, y1;
+    region(j, x0, x1, y0, y1);
+    const int cw = x1 - x0, chh = y1 - y0;
+    const int stride = (cw + 3) & ~3;
+    // owned block of this level: the top tile scaled by 2^(m - j); the last
+    // tile of a row or column reaches the level's edge
+    const int d = ca.m - j;
+    const int ox0 = tx << d, oy0 = ty << d;
+    const int ox1 = tx + ca.tile >= wtop ? lw[j] : min((tx + ca.tile) << d, lw[j]);
+    const int oy1 = ty + ca.tile >= htop ? lh[j] : min((ty + ca.tile) << d, lh[j]);
+    const int sw = lw[j - 1], shh = lh[j - 1];
+    const bool last = j == ca.m;
+    for (int idx = tid; idx < 2 * cw * chh; idx += kChainThreads) {
+      const int v = idx >= cw * chh, p = v ? idx - cw * chh : idx;
+      const int yl = div_small(p, cw), xl = p - yl * cw;
+      const int x = x0 + xl, y = y0 + yl;
+      const uint8_t* sv = src + v * src_rows * src_stride;
+      int cx[5];
+#pragma unroll
+      for (int kk = 0; kk < 5; ++kk) cx[kk] = reflect101(2 * x - 2 + kk, sw) - src_x0;
+      int acc = 0;
+#pragma unroll
+      for (int kk = 0; kk < 5; ++kk) {
+        const uint8_t* row = sv + (reflect101(2 * y - 2 + kk, shh) - src_y0) * src_stride;
+        const int hsum = row[cx[0]] + 4 * row[cx[1]] + 6 * row[cx[2]] + 4 * row[cx[3]] + row[cx[4]];
+        acc += (kk == 2 ? 6 : (kk == 1 || kk == 3) ? 4 : 1) * hsum;
+      }
+      const uint8_t o = (uint8_t)((acc + 128) >> 8);
+      if (!last) buf[v * chh * stride + yl * stride + xl] = o;
+      if (x >= ox0 && x < ox1 && y >= oy0 && y < oy1) gbl(v ? q.dstR : q.dstL)[(size_t)y * q.pitch + x] = o;
+    }
+    if (last) break;
+    __syncthreads();
+    uint8_t* const old = const_cast<uint8_t*>(src);
+    src = buf;
+    buf = old;
+    src_x0 = x0;
+    src_y0 = y0;
+    src_stride = stride;
+    src_rows = chh;
+  }
+}
+
 }  // namespace
+
+PyrChain pyr_chain_shape(int n0, int m, int tile_top) {
+  PyrChain ca{};
+  ca.n0 = n0;
+  ca.m = m;
+  ca.tile = tile_top;
+  // the largest region of any level of the chain (the source level's), both
+  // views, twice (ping-pong between levels)
+  int wmax = tile_top;
+  for (int k = 0; k < m; ++k) wmax = 2 * wmax + 3;
+  const int src_bytes = 2 * wmax * ((wmax + 3 + 3) & ~3);
+  ca.lds_half = (src_bytes + 15) & ~15;
+  ca.lds = 2 * ca.lds_half;
+  if (m > kChainMaxLevels || 2L * wmax * (((wmax + 3 + 3) & ~3) / 4) > (long)kChainWordsPerThread * kChainThreads)
+    ca.lds = 0;
+  return ca;
+}
+
+hipError_t launch_pyr_chain(const PairLevel* tab, int npairs, int nblocks, const PyrChain& ca, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  if (ca.lds <= 0 || ca.m < 1) return hipErrorInvalidValue;
+  bdis_launch(k_pyr_chain, dim3(nblocks), dim3(kChainThreads), ca.lds, s, tab, npairs, ca);
+  return hipGetLastError();
+}
 
 hipError_t launch_pyramid(const PairLevel* tab, int npairs, int nblocks, bool tall, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;

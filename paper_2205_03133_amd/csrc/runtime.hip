@@ -249,6 +249,8 @@ struct Plan {
   bool f32 = false;              // float (FP64) path: per-pixel pyramid blocks, fixed search size
   int top_level = -1;            // level whose pyramid step, search and fusion run in k_top (-1: none)
   TopShape top{};                // its launch shape
+  PyrChain chain{};              // small pyramid levels built by one launch (chain.m == 0: none)
+  int chain_blocks = 0;
   PlanTab tab;
 };
 
@@ -271,6 +273,7 @@ struct TuneChoice {
   int fuse_ty = 0;   // fusion tile height
   int pyr_tall = -1; // pyramid form: 1 staged 120 x 12 tiles, 0 gather 64 x 4 tiles
   int top = -1;      // coarsest level: 1 one workgroup per pair (k_top), 0 the per-phase launches
+  int chain = -1;    // highest level of a pyramid chain: 1 one launch for the chained levels, 0 one each
 };
 
 // A captured launch sequence for one batch shape.
@@ -306,7 +309,10 @@ struct bdis_ctx {
   std::string tune_cache;            // file the tuned choices persist in ("" = none)
   double last_tune_ms = 0.0, last_capture_ms = 0.0;  // host time of the last call's tuning / capture
   int forced_opt = -1;               // BDIS_SEARCH_CONFIG: one configuration for every level, no tuning
-  bool top_off = false;              // BDIS_TOP=0: the coarsest level takes the per-phase launches
+  int top_mode = -1;                 // BDIS_TOP: 0 the coarsest level in per-phase launches, 1 in k_top
+                                     // where it fits, unset: timed by the tuner
+  int chain_mode = -1;               // BDIS_CHAIN: 0 one pyramid launch per level, 1 chained small
+                                     // levels where possible, unset: timed by the tuner
   int use_graph = 1;
   bool train = false;                // created with BDIS_TRAIN
   bool keep = false;                 // created with BDIS_KEEP
@@ -524,6 +530,39 @@ void assign_offsets(const bdis_params& p, Plan& pl) {
     pl.prob_blocks[n] = pr;
     pl.fuse_blocks[n] = fu;
   }
+  // the pyramid chain's workgroups: tiles of its top level (through that level's pyr0)
+  pl.chain_blocks = 0;
+  if (pl.chain.m > 0) {
+    const int top = pl.chain.n0 + pl.chain.m, tile = pl.chain.tile;
+    for (int e = 0; e < pl.tab_count[top]; ++e) {
+      PairLevel& q = pl.tab[pl.tab_first[top] + e];
+      q.pyr0 = pl.chain_blocks;
+      pl.chain_blocks += ((q.g.w + tile - 1) / tile) * ((q.g.h + tile - 1) / tile);
+    }
+  }
+}
+
+// The pyramid chain of a plan: the longest run of small (gather-form) levels
+// below the coarsest level the pyramid launches build (the k_top level builds
+// its own), present for every pair of the run, above level 1 (built from the
+// caller's images by its own launch), of two to four levels.
+void plan_chain(Plan& pl) {
+  pl.chain = PyrChain{};
+  const int last = pl.top_level >= 0 ? pl.top_level - 1 : pl.max_levels - 1;
+  if (last < 3) return;
+  int first = last;
+  while (first - 1 >= 2 && !pl.pyr_tall[first - 1] && pl.tab_count[first - 1] == pl.tab_count[last]) --first;
+  if (pl.pyr_tall[last] || pl.tab_count[last] == 0) return;
+  for (int k = first; k <= last; ++k)
+    if (pl.pyr_tall[k] || pl.tab_count[k] != pl.tab_count[last]) return;
+  const int m = std::min(last - first + 1, 4);
+  if (m < 2) return;
+  const int n0 = last - m;
+  const int tile = 16 >> m;  // small tiles: many workgroups, each a short chain
+  PyrChain ca = pyr_chain_shape(n0, m, tile);
+  if (ca.lds <= 0 || ca.lds > 64 * 1024) return;
+  for (int k = 0; k < kMaxLevels; ++k) ca.first[k] = pl.tab_first[k];
+  pl.chain = ca;
 }
 
 bdis_status build_plan(bdis_ctx* c, const PairSpec* pairs, size_t npairs, Plan* out, bool f32 = false,
@@ -700,7 +739,7 @@ bdis_status build_plan(bdis_ctx* c, const PairSpec* pairs, size_t npairs, Plan* 
   }
   // tuned choices of this batch shape (uint8 stereo path; the key is a string,
   // so it is built only when something was tuned or loaded)
-  bool top_tuned_off = false;
+  bool top_tuned_off = false, chain_tuned_off = false;
   if (!f32 && !flow && !c->tuned.empty()) {
     for (int n = 0; n < pl.max_levels; ++n) {
       if (pl.tab_count[n] == 0) continue;
@@ -715,6 +754,7 @@ bdis_status build_plan(bdis_ctx* c, const PairSpec* pairs, size_t npairs, Plan* 
         pl.fuse_ty[n] = tc.fuse_ty;
       if (n >= 1 && (tc.pyr_tall == 0 || tc.pyr_tall == 1)) pl.pyr_tall[n] = tc.pyr_tall == 1;
       if (tc.top == 0) top_tuned_off = true;
+      if (tc.chain == 0) chain_tuned_off = true;
     }
   }
   if (!f32 && !flow && c->forced_opt >= 0)
@@ -723,7 +763,7 @@ bdis_status build_plan(bdis_ctx* c, const PairSpec* pairs, size_t npairs, Plan* 
   // coarsest level) in one workgroup per pair, when it is above the finest
   // level, uses the mask weights and fits
   const int top = pl.max_levels - 1;
-  if (!f32 && !flow && !c->top_off && !top_tuned_off && top >= 1 && top > p.finest_level && p.fusion != 1 && pl.tab_count[top] > 0) {
+  if (!f32 && !flow && c->top_mode != 0 && (c->top_mode == 1 || !top_tuned_off) && top >= 1 && top > p.finest_level && p.fusion != 1 && pl.tab_count[top] > 0) {
     int mw = 0, mh = 0, msw = 0, msh = 0, mnp = 0;
     for (int e = 0; e < pl.tab_count[top]; ++e) {
       const PairLevel& q = pl.tab[pl.tab_first[top] + e];
@@ -736,6 +776,7 @@ bdis_status build_plan(bdis_ctx* c, const PairSpec* pairs, size_t npairs, Plan* 
     pl.top = top_shape(p.patch, p.stride, mw, mh, msw, msh, mnp);
     if (pl.top.g > 0) pl.top_level = top;
   }
+  if (!f32 && !flow && c->chain_mode != 0 && (c->chain_mode == 1 || !chain_tuned_off)) plan_chain(pl);
   assign_offsets(p, pl);
   return BDIS_OK;
 }
@@ -789,8 +830,11 @@ bdis_status launch_all(bdis_ctx* c, const Plan& pl, hipStream_t st) {
   hipError_t e;
   for (int n = 1; n < pl.max_levels; ++n) {
     if (n == pl.top_level) continue;  // built inside k_top
+    const bool chained = pl.chain.m > 0 && n > pl.chain.n0 && n <= pl.chain.n0 + pl.chain.m;
+    if (chained && n > pl.chain.n0 + 1) continue;  // built by the chain launch
     const long tmk = timing_start(c, BDIS_K_PYRAMID, st, n);
-    e = launch_pyramid_level(c->tab_dev, pl, n, st);
+    e = chained ? launch_pyr_chain(c->tab_dev, pl.tab_count[n], pl.chain_blocks, pl.chain, st)
+                : launch_pyramid_level(c->tab_dev, pl, n, st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "pyramid launch");
   }
@@ -897,8 +941,8 @@ std::map<std::string, TuneChoice> read_tune_cache(const std::string& path) {
     const char* q1 = std::strchr(q0 + 1, '"');
     if (!q1) continue;
     TuneChoice tc;
-    if (std::sscanf(q1 + 1, " : {\"search\": %d, \"fuse_ty\": %d, \"pyr_tall\": %d, \"top\": %d}", &tc.search,
-                    &tc.fuse_ty, &tc.pyr_tall, &tc.top) == 4)
+    if (std::sscanf(q1 + 1, " : {\"search\": %d, \"fuse_ty\": %d, \"pyr_tall\": %d, \"top\": %d, \"chain\": %d}",
+                    &tc.search, &tc.fuse_ty, &tc.pyr_tall, &tc.top, &tc.chain) == 5)
       out[std::string(q0 + 1, q1)] = tc;
   }
   std::fclose(f);
@@ -925,9 +969,9 @@ bdis_status save_tune_cache(bdis_ctx* c) {
   std::fprintf(f, "{\n\"bdis_tune_cache\": 1,\n\"entries\": {\n");
   size_t k = 0;
   for (const auto& kv : all)
-    std::fprintf(f, "\"%s\": {\"search\": %d, \"fuse_ty\": %d, \"pyr_tall\": %d, \"top\": %d}%s\n",
+    std::fprintf(f, "\"%s\": {\"search\": %d, \"fuse_ty\": %d, \"pyr_tall\": %d, \"top\": %d, \"chain\": %d}%s\n",
                  kv.first.c_str(), kv.second.search, kv.second.fuse_ty, kv.second.pyr_tall, kv.second.top,
-                 ++k < all.size() ? "," : "");
+                 kv.second.chain, ++k < all.size() ? "," : "");
   std::fprintf(f, "}\n}\n");
   const bool ok = std::fclose(f) == 0;
   if (!ok || std::rename(tmp.c_str(), c->tune_cache.c_str()) != 0) (void)std::remove(tmp.c_str());
@@ -975,6 +1019,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
     best[n].top = n == pl.top_level ? 1 : -1;
   }
   const int top_cand = pl.top_level;  // the level k_top could take (-1: none)
+  int chain_lo = -1, chain_hi = -1;   // levels spanned by the chain timing (phase 4)
   if (enabled) {
     std::vector<hipEvent_t> ev(2 * kMaxLevels, nullptr);
     hipError_t e = hipSuccess;
@@ -983,8 +1028,9 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
     bdis_status s2 = BDIS_OK;
     // Times `trial` over kTuneReps passes; phase 0 search, 1 fusion, 2 pyramid,
     // 3 the coarsest level's span (its pyramid step through its fusion, or the
-    // k_top launch).  best_ms[n] / pick(n) record a level whose timed launch
-    // (or span) beat its best.
+    // k_top launch), 4 the span of the chained pyramid levels (the chain
+    // launch, or one launch each).  best_ms[n] / pick(n) record a level whose
+    // timed launch (or span) beat its best.
     auto run_trial = [&](Plan& trial, int phase, float* best_ms, auto&& pick) {
       assign_offsets(p, trial);
       if ((s2 = upload_table(c, trial, st)) != BDIS_OK) return;
@@ -1014,8 +1060,16 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
       for (int rep = 0; rep < kTuneReps && e == hipSuccess; ++rep) {
         for (int n = 1; n < trial.max_levels && e == hipSuccess; ++n) {
           if (phase == 3 && n == top) span_begin(n);
+          if (phase == 4 && n == chain_lo) span_begin(chain_hi);
           if (n == trial.top_level) continue;
-          e = timed(n, 2, [&] { return launch_pyramid_level(c->tab_dev, trial, n, st); });
+          const bool chained = trial.chain.m > 0 && n > trial.chain.n0 && n <= trial.chain.n0 + trial.chain.m;
+          if (chained) {
+            if (n == trial.chain.n0 + 1)
+              e = launch_pyr_chain(c->tab_dev, trial.tab_count[n], trial.chain_blocks, trial.chain, st);
+          } else {
+            e = timed(n, 2, [&] { return launch_pyramid_level(c->tab_dev, trial, n, st); });
+          }
+          if (phase == 4 && n == chain_hi) span_end(chain_hi);
         }
         for (int n = trial.max_levels - 1; n >= p.finest_level && e == hipSuccess; --n) {
           const PairLevel* tab = c->tab_dev + trial.tab_first[n];
@@ -1035,7 +1089,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
           e = launch_upsample(c->tab_dev + trial.tab_first[0], trial.tab_count[0], trial.up_blocks, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess || rep == 0) continue;  // the first pass warms caches and code
-        const int lo = phase == 2 ? 1 : phase == 3 ? top : p.finest_level;
+        const int lo = phase == 2 ? 1 : phase == 3 ? top : phase == 4 ? chain_hi : p.finest_level;
         for (int n = lo; n < trial.max_levels; ++n) {
           if (!trial.tab_count[n] || !rec[n]) continue;  // nothing launched at this level
           float ms = 0.0f;
@@ -1055,6 +1109,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
       if (kind > 0 && search_lanes(p.patch, kind) == search_lanes(p.patch, kind - 1)) continue;  // same mapping
       Plan trial = pl;
       trial.top_level = -1;
+      trial.chain.m = 0;
       for (int n = 0; n < trial.max_levels; ++n) trial.search_opt[n] = o;
       run_trial(trial, 0, bs, [&](int n) { best[n].search = o; });
     }
@@ -1067,6 +1122,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
       if (ty == kFuseTyHuge && !fuse_tile_fits(kFuseTyHuge, p.patch, p.stride)) continue;
       Plan trial = pl;
       trial.top_level = -1;
+      trial.chain.m = 0;
       for (int n = 0; n < trial.max_levels; ++n) {
         if (n >= p.finest_level) trial.search_opt[n] = best[n].search;
         trial.fuse_ty[n] = ty;
@@ -1079,6 +1135,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
     for (int tall = 0; tall <= 1 && e == hipSuccess && s2 == BDIS_OK; ++tall) {
       Plan trial = pl;
       trial.top_level = -1;
+      trial.chain.m = 0;
       for (int n = 0; n < trial.max_levels; ++n) {
         if (n >= p.finest_level) {
           trial.search_opt[n] = best[n].search;
@@ -1090,12 +1147,13 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
     }
     // 4. the coarsest level in one workgroup per pair against its per-phase
     // launches (the others at their best)
-    if (top_cand >= 0) {
+    if (top_cand >= 0 && c->top_mode < 0) {
       float bt[kMaxLevels];
       std::fill(bt, bt + kMaxLevels, 1e30f);
       for (int use = 0; use <= 1 && e == hipSuccess && s2 == BDIS_OK; ++use) {
         Plan trial = pl;
         trial.top_level = use ? top_cand : -1;
+        trial.chain.m = 0;
         for (int n = 0; n < trial.max_levels; ++n) {
           if (n >= p.finest_level) {
             trial.search_opt[n] = best[n].search;
@@ -1104,6 +1162,31 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
           trial.pyr_tall[n] = best[n].pyr_tall == 1;
         }
         run_trial(trial, 3, bt, [&](int n) { best[n].top = use; });
+      }
+    }
+    // 5. one launch for the chained small pyramid levels against one each
+    // (everything else at its best)
+    if (c->chain_mode < 0 && e == hipSuccess && s2 == BDIS_OK) {
+      Plan cand = pl;
+      for (int n = 0; n < cand.max_levels; ++n) {
+        if (n >= p.finest_level) {
+          cand.search_opt[n] = best[n].search;
+          cand.fuse_ty[n] = best[n].fuse_ty;
+        }
+        if (n >= 1) cand.pyr_tall[n] = best[n].pyr_tall == 1;
+      }
+      if (top_cand >= 0 && best[top_cand].top == 0) cand.top_level = -1;
+      plan_chain(cand);
+      if (cand.chain.m > 0) {
+        chain_lo = cand.chain.n0 + 1;
+        chain_hi = cand.chain.n0 + cand.chain.m;
+        float bc[kMaxLevels];
+        std::fill(bc, bc + kMaxLevels, 1e30f);
+        for (int use = 0; use <= 1 && e == hipSuccess && s2 == BDIS_OK; ++use) {
+          Plan trial = cand;
+          if (!use) trial.chain.m = 0;
+          run_trial(trial, 4, bc, [&](int n) { best[n].chain = use; });
+        }
       }
     }
     for (auto& x : ev)
@@ -1124,6 +1207,8 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
     if (n >= 1) pl.pyr_tall[n] = best[n].pyr_tall == 1;
     if (n == top_cand && best[n].top == 0) pl.top_level = -1;
   }
+  pl.chain.m = 0;
+  if (c->chain_mode == 1 || (c->chain_mode < 0 && !(chain_hi >= 0 && best[chain_hi].chain == 0))) plan_chain(pl);
   assign_offsets(p, pl);
   c->last_tune_ms = wall_ms() - t0;
   if (enabled) return save_tune_cache(c);
@@ -1412,8 +1497,9 @@ bdis_status bdis_create(bdis_ctx** out, const bdis_params* p, int max_w, int max
   c->keep = (flags & BDIS_KEEP) != 0;
   const char* g = std::getenv("BDIS_GRAPH");
   c->use_graph = !(g && std::strcmp(g, "0") == 0);
-  const char* tp = std::getenv("BDIS_TOP");
-  c->top_off = tp && std::strcmp(tp, "0") == 0;
+  auto mode = [](const char* v) { return !v ? -1 : std::strcmp(v, "0") == 0 ? 0 : std::strcmp(v, "1") == 0 ? 1 : -1; };
+  c->top_mode = mode(std::getenv("BDIS_TOP"));
+  c->chain_mode = mode(std::getenv("BDIS_CHAIN"));
   if (const char* so = std::getenv("BDIS_SEARCH_CONFIG")) {
     char* end = nullptr;
     const long v = std::strtol(so, &end, 10);

@@ -695,3 +695,56 @@ def test_top_level_kernel_matches_per_phase_launches(B, monkeypatch, case):
     for k in res[0]:
         if k != "out":
             assert np.array_equal(np.nan_to_num(res[0][k], nan=-7.0), np.nan_to_num(res[1][k], nan=-7.0)), k
+
+
+@pytest.mark.parametrize("case", ["c2", "c5", "preset", "batch"])
+@pytest.mark.parametrize("top", ["0", "1"])
+def test_pyramid_chain_matches_level_launches(B, monkeypatch, case, top):
+    """Runs of small pyramid levels built by one launch (each workgroup
+    stages the region of the level below its tile needs) give the same level
+    images and the same outputs as one launch per level (BDIS_CHAIN=0)."""
+    import torch
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    monkeypatch.setenv("BDIS_TOP", top)
+    sizes = None
+    if case == "c2":
+        pr, p = [make_pair(2, 0)], B.params(**method_params(2))           # levels 2-4 (or 2-3) chained
+    elif case == "c5":
+        pr, p = [make_pair(5, 0)], B.params(**method_params(5))           # levels 2-5 (or 2-4), 4-pixel tiles
+    elif case == "preset":
+        pr = [make_pair(2, 1)]
+        p = B.params(levels=6, finest_level=1, patch=10, stride=4, iters=12, valid_ratio=0.75, sigma_s=4.0,
+                     prob_thresh=0.15, variance=1)
+    else:
+        pr = [make_pair(2, i) for i in range(3)]
+        p = B.params(**method_params(2))
+        sizes = [(640, 480), (600, 440), (560, 480)]
+    lefts, rights = [], []
+    for i, (l, r, _, _) in enumerate(pr):
+        if sizes:
+            w, h = sizes[i]
+            l, r = l[:h, :w], r[:h, :w]
+        lefts.append(to_gpu(l))
+        rights.append(to_gpu(r))
+    h, w = max(t.shape[0] for t in lefts), max(t.shape[1] for t in lefts)
+    res = []
+    for chain in ("1", "0"):
+        monkeypatch.setenv("BDIS_CHAIN", chain)
+        print(f"[gpu] {case}: BDIS_CHAIN={chain} BDIS_TOP={top} L={p.levels} P={p.patch}", flush=True)
+        ctx = B.Context(p, w, h, max_batch=len(lefts), keep=len(lefts) == 1)
+        o = [ctx.compute(lefts[0], rights[0])] if len(lefts) == 1 else ctx.compute_batch(lefts, rights)
+        torch.cuda.synchronize()
+        got = {"out": [{k: v.clone() for k, v in oo.items() if v is not None} for oo in o]}
+        if len(lefts) == 1:
+            for n in range(1, p.levels):
+                got[f"left{n}"] = ctx.debug(n, "left")
+                got[f"right{n}"] = ctx.debug(n, "right")
+        ctx.close()
+        res.append(got)
+    for i in range(len(lefts)):
+        for k in res[1]["out"][i]:
+            assert torch.equal(torch.nan_to_num(res[0]["out"][i][k], nan=-7.0),
+                               torch.nan_to_num(res[1]["out"][i][k], nan=-7.0)), (i, k)
+    for k in res[0]:
+        if k != "out":
+            assert np.array_equal(res[0][k], res[1][k]), k

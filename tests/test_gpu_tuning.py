@@ -1,8 +1,9 @@
 """The launch-shape tuner and its cache file: the choices persist across
 contexts, a context that finds its shapes in the file does not tune, and every
 choice the file can force (fusion tile height, pyramid form, search
-configuration, the coarsest level in one workgroup or in per-phase launches)
-gives the same bits."""
+configuration, the coarsest level in one workgroup or in per-phase launches,
+one launch for the chained small pyramid levels or one each) gives the same
+bits."""
 import json
 import os
 
@@ -54,7 +55,7 @@ def test_tune_cache_and_forced_choices(B, tmp_path, monkeypatch, cfg):
     entries = doc["entries"]
     assert len(entries) == p.levels
     for key, v in entries.items():
-        assert key.startswith("gfx950") and set(v) == {"search", "fuse_ty", "pyr_tall", "top"}
+        assert key.startswith("gfx950") and set(v) == {"search", "fuse_ty", "pyr_tall", "top", "chain"}
     top_entries = [v for v in entries.values() if v["top"] >= 0]
     assert len(top_entries) == 1  # the coarsest level, timed both ways
     print(f"  tuned in {tune_ms:.1f} ms, captured in {cap_ms:.1f} ms", flush=True)
@@ -63,20 +64,21 @@ def test_tune_cache_and_forced_choices(B, tmp_path, monkeypatch, cfg):
     assert _equal(out, ref)
     # every choice forced through the file gives the same bits
     variants = [("fuse_ty", 4), ("fuse_ty", 16), ("fuse_ty", 32), ("pyr_tall", 0), ("pyr_tall", 1),
-                ("search", 0), ("search", 5), ("search", 10), ("top", 0), ("top", 1)]
+                ("search", 0), ("search", 5), ("search", 10), ("top", 0), ("top", 1), ("chain", 0), ("chain", 1)]
     for field, val in variants:
         forced = {k: dict(v) for k, v in entries.items()}
         for k, v in forced.items():
             if field == "pyr_tall" and v["pyr_tall"] < 0:
                 continue  # level 0 has no pyramid step
-            if field == "top" and v["top"] < 0:
-                continue  # only the coarsest level has the choice
+            if field in ("top", "chain") and v[field] < 0:
+                continue  # only the coarsest level / the chain's top level has the choice
             v[field] = val
         # one entry per line, as the library writes it
         with open(path, "w") as f:
             f.write('{\n"bdis_tune_cache": 1,\n"entries": {\n')
             f.write(",\n".join(f'"{k}": {{"search": {v["search"]}, "fuse_ty": {v["fuse_ty"]}, '
-                               f'"pyr_tall": {v["pyr_tall"]}, "top": {v["top"]}}}' for k, v in forced.items()))
+                               f'"pyr_tall": {v["pyr_tall"]}, "top": {v["top"]}, "chain": {v["chain"]}}}'
+                               for k, v in forced.items()))
             f.write("\n}\n}\n")
         print(f"  forced {field} = {val}", flush=True)
         out, t3, _ = _run(B, p, l, r)
