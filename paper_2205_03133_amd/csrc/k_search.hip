@@ -31,6 +31,10 @@ constexpr int search_min_waves() {
   return (P + G - 1) / G >= 2 ? 5 : 1;
 }
 
+// Workgroups of one patch row that each stage the whole right row (beyond
+// this, the repeated row loads cost more than the window's placement step).
+constexpr int kFullRowWorkgroups = 4;
+
 template <int P, int G, int THREADS>
 __global__ __launch_bounds__(THREADS, (search_min_waves<P, G>())) void k_search_u8(const PairLevel* tab, int npairs, LevelParams lp) {
   static_assert(G >= 2 && G <= 16 && THREADS % 64 == 0, "lanes per patch and workgroup size");
@@ -66,6 +70,49 @@ __global__ __launch_bounds__(THREADS, (search_min_waves<P, G>())) void k_search_
   const int ox0 = grid_origin(i0, W, P, S);
   const int oxl = grid_origin(ilast, W, P, S);
 
+  if (tid == 0) {
+    s_umin = INT_MAX;
+    s_umax = INT_MIN;
+  }
+  const int wave = tid / 64, lane = tid % 64;
+  // ---- right window: rows oy .. oy+P-1, columns xs .. xs+rw-1 (clamped to the
+  // image), xs a multiple of 4.  When at most four workgroups share the patch
+  // row and the image row with a margin of MARG columns on each side fits, that
+  // row is staged at once together with the left tile (no barrier and no
+  // second round trip for the window's placement); otherwise the columns
+  // around the patches' starting displacements, after a workgroup min/max of
+  // floor(u0).
+  // ---- left tile: image rows oy-1 .. oy+P, columns xa .. oxl+P (reflect-101),
+  // xa = (ox0 - 1) rounded down to a multiple of 4.
+  // The first word of every row a lane stages (the left tile's, and the full
+  // right rows') is loaded before the parent maps are read, so those loads and
+  // the parent's are one round trip; the words are stored afterwards.
+  const bool full_row = a.search_nbx <= kFullRowWorkgroups && W + 2 * MARG + 8 <= RWB;
+  int xs = (-MARG) & ~3;
+  int ndr = (W + MARG - xs + 3) / 4;
+  const int xa = (ox0 - 1) & ~3;
+  const int ndl = (oxl + P + 1 - xa + 3) / 4;
+  constexpr int LR = (P + 2 + NWAVES - 1) / NWAVES, RR = (P + NWAVES - 1) / NWAVES;
+  uint32_t lw0[LR], rw0[RR];
+#pragma unroll
+  for (int r = 0; r < LR; ++r) {
+    const int ty = wave + r * NWAVES;
+    lw0[r] = 0;
+    if (ty < P + 2 && lane < ndl) {
+      const uint8_t* rp = a.L + (size_t)reflect101(oy - 1 + ty, Hh) * a.pitch;
+      lw0[r] = row_word<true>(rp, W, xa + 4 * lane, ((uintptr_t)rp & 3) == 0);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RR; ++r) {
+    const int ty = wave + r * NWAVES;
+    rw0[r] = 0;
+    if (full_row && ty < P && lane < ndr) {
+      const uint8_t* rp = a.R + (size_t)(oy + ty) * a.pitch;
+      rw0[r] = row_word<false>(rp, W, xs + 4 * lane, ((uintptr_t)rp & 3) == 0);
+    }
+  }
+
   // ---- start from the parent level (Fig. 1): 2 * fused map at the centre
   double uinit = 0.0, pipar = 0.0;
   if (a.par_ubar) {
@@ -75,34 +122,31 @@ __global__ __launch_bounds__(THREADS, (search_min_waves<P, G>())) void k_search_
     pipar = bilinear(a.par_q, a.pw, a.ph, cx, cy);
   }
 
-  if (tid == 0) {
-    s_umin = INT_MAX;
-    s_umax = INT_MIN;
-  }
-  const int wave = tid / 64, lane = tid % 64;
-  // ---- right window: rows oy .. oy+P-1, columns xs .. xs+rw-1 (clamped to the
-  // image), xs a multiple of 4.  When one workgroup holds the whole patch row
-  // and the image row with a margin of MARG columns on each side fits, that row
-  // is staged at once together with the left tile; otherwise the columns
-  // around the patches' starting displacements, after a workgroup min/max of
-  // floor(u0).
-  const bool full_row = a.search_nbx == 1 && W + 2 * MARG + 8 <= RWB;
   auto stage_right = [&](int x0r, int nd) {
     for (int ty = wave; ty < P; ty += NWAVES) {
       const uint8_t* rp = a.R + (size_t)(oy + ty) * a.pitch;
       stage_row<false>(s_right32 + ty * (RWB / 4), rp, W, x0r, nd, lane, ((uintptr_t)rp & 3) == 0);
     }
   };
-  int xs = (-MARG) & ~3;
-  int ndr = (W + MARG - xs + 3) / 4;
-  if (full_row) stage_right(xs, ndr);
-  // ---- left tile: image rows oy-1 .. oy+P, columns xa .. oxl+P (reflect-101),
-  // xa = (ox0 - 1) rounded down to a multiple of 4
-  const int xa = (ox0 - 1) & ~3;
-  const int ndl = (oxl + P + 1 - xa + 3) / 4;
-  for (int ty = wave; ty < P + 2; ty += NWAVES) {
-    const uint8_t* rp = a.L + (size_t)reflect101(oy - 1 + ty, Hh) * a.pitch;
-    stage_row<true>(s_left32 + ty * (LTW / 4), rp, W, xa, ndl, lane, ((uintptr_t)rp & 3) == 0);
+#pragma unroll
+  for (int r = 0; r < LR; ++r) {
+    const int ty = wave + r * NWAVES;
+    if (ty < P + 2) {
+      if (lane < ndl) s_left32[ty * (LTW / 4) + lane] = lw0[r];
+      const uint8_t* rp = a.L + (size_t)reflect101(oy - 1 + ty, Hh) * a.pitch;
+      stage_row<true>(s_left32 + ty * (LTW / 4), rp, W, xa, ndl, lane, ((uintptr_t)rp & 3) == 0, 64);
+    }
+  }
+  if (full_row) {
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+      const int ty = wave + r * NWAVES;
+      if (ty < P) {
+        if (lane < ndr) s_right32[ty * (RWB / 4) + lane] = rw0[r];
+        const uint8_t* rp = a.R + (size_t)(oy + ty) * a.pitch;
+        stage_row<false>(s_right32 + ty * (RWB / 4), rp, W, xs, ndr, lane, ((uintptr_t)rp & 3) == 0, 64);
+      }
+    }
   }
   if (!full_row) {
     __syncthreads();

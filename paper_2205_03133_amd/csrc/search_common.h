@@ -109,26 +109,25 @@ BDIS_DEV uint32_t shifted_word(const uint32_t (&B)[NW + 1], int w) {
 // dwords; x0 is a multiple of 4.  Columns outside the row are mapped by
 // reflect-101 (REFLECT) or clamping, and then clamped, so every access stays
 // in the row.  Interior dwords of a 4-aligned row are single global loads.
+// The dword of columns c .. c + 3 of row `rp` as stage_row stores it.
 template <bool REFLECT>
-BDIS_DEV void stage_row(uint32_t* dst, const uint8_t* rp, int W, int x0, int nd, int lane, bool aligned) {
+BDIS_DEV uint32_t row_word(const uint8_t* rp, int W, int c, bool aligned) {
   const auto g = gbl(rp);
-  for (int k = lane; k < nd; k += 64) {
-    const int c = x0 + 4 * k;
-    uint32_t v;
-    if (aligned && c >= 0 && c + 3 < W) {
-      v = *reinterpret_cast<const __attribute__((address_space(1))) uint32_t*>(g + c);
-    } else {
-      v = 0;
+  if (aligned && c >= 0 && c + 3 < W) return *reinterpret_cast<const __attribute__((address_space(1))) uint32_t*>(g + c);
+  uint32_t v = 0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        int x = c + b;
-        x = REFLECT ? reflect101(x, W) : x;
-        x = clampi(x, 0, W - 1);
-        v |= (uint32_t)g[x] << (8 * b);
-      }
-    }
-    dst[k] = v;
+  for (int b = 0; b < 4; ++b) {
+    int x = c + b;
+    x = REFLECT ? reflect101(x, W) : x;
+    x = clampi(x, 0, W - 1);
+    v |= (uint32_t)g[x] << (8 * b);
   }
+  return v;
+}
+
+template <bool REFLECT>
+BDIS_DEV void stage_row(uint32_t* dst, const uint8_t* rp, int W, int x0, int nd, int lane, bool aligned, int k0 = 0) {
+  for (int k = k0 + lane; k < nd; k += 64) dst[k] = row_word<REFLECT>(rp, W, x0 + 4 * k, aligned);
 }
 
 
