@@ -48,8 +48,10 @@ def search_flops(bdis, p, w, h, levels=None):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "search_hbm_traffic_640x480_1080p_batch64_mixed64.md")
-# the search kernel's source and the header that fixes its layouts and launch shapes
+# the search kernel's sources: the kernel, its per-patch body and the header
+# that fixes its layouts and launch shapes
 SEARCH_SRC = [os.path.join(ROOT, "paper_2205_03133_amd", "csrc", "k_search.hip"),
+              os.path.join(ROOT, "paper_2205_03133_amd", "csrc", "search_common.h"),
               os.path.join(ROOT, "paper_2205_03133_amd", "csrc", "bdis_internal.h")]
 
 

@@ -247,8 +247,10 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
     const size_t idx = (size_t)y * a.g.w + x;
     double ub, qv;
     bool valid = z > 0.0;
+    // one division for the normalisation by sum W (displacement and variance)
+    const double rz = valid ? 1.0 / z : 0.0;
     if (valid) {
-      ub = zu / z;
+      ub = zu * rz;
       qv = zq / zm;
     } else if (finest) {
       ub = __builtin_nan("");
@@ -267,7 +269,7 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
       if (finest) {
         gbl(a.ubar_keep)[idx] = ub;
         gbl(a.qmap_keep)[idx] = qv;
-        if (a.vmap) gbl(a.vmap)[idx] = (valid && lp.variance) ? zv / (z * z) : 0.0;
+        if (a.vmap) gbl(a.vmap)[idx] = (valid && lp.variance) ? zv * (rz * rz) : 0.0;
       }
     }
     if (!finest) {
@@ -279,7 +281,7 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
     const float nan = __builtin_nanf("");
     gbl(a.disparity)[idx] = valid ? (float)(-ub) : nan;
     if (a.confidence) gbl(a.confidence)[idx] = valid ? (float)qv : 0.0f;
-    if (a.variance) gbl(a.variance)[idx] = (valid && lp.variance) ? (float)(zv / (z * z)) : nan;
+    if (a.variance) gbl(a.variance)[idx] = (valid && lp.variance) ? (float)(zv * (rz * rz)) : nan;
   };
   // A wavefront holds one pixel row of the tile, so y and everything derived
   // from it (covering patch rows, vertical mask weights) are wave-uniform.
