@@ -36,12 +36,15 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def search_flops(bdis, p, w, h, levels=None):
+def search_flops(bdis, p, w, h, levels=None, skip=()):
     """Algorithmic flops of the patch search of one pass: per patch 4P^2 (template
-    setup) + 5KP^2 (K warped-patch iterations) + 8sP^2 (s-sample window), FMA = 2."""
+    setup) + 5KP^2 (K warped-patch iterations) + 8sP^2 (s-sample window), FMA = 2.
+    Levels in `skip` (searched inside the fused coarsest-level kernel) are left out."""
     tot = 0
     P2 = p.patch * p.patch
     for n in range(levels or p.levels):
+        if n in skip:
+            continue
         _, _, nx, ny = bdis.level_dims(p, w, h, n)
         tot += nx * ny * (4 * P2 + 5 * p.iters * P2 + 8 * WIN * P2)
     return tot
@@ -85,7 +88,7 @@ def measured_traffic(workload):
 HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 
 
-def search_bytes(bdis, p, w, h, levels=None):
+def search_bytes(bdis, p, w, h, levels=None, skip=()):
     """Algorithmic HBM bytes of the patch search of one pass: both level images
     (1 B per pixel each), per patch what the later phases read (displacement,
     propagated probability, four window SSD differences as FP64, acceptance:
@@ -94,6 +97,8 @@ def search_bytes(bdis, p, w, h, levels=None):
     L = levels or p.levels
     tot = 0
     for n in range(p.finest_level, L):
+        if n in skip:
+            continue
         lw, lh, nx, ny = bdis.level_dims(p, w, h, n)
         tot += 2 * lw * lh + nx * ny * (52 + (64 if n + 1 < L else 0))
     return tot
@@ -216,6 +221,11 @@ def parity_block(disp, var, ref_res, tol=1e-3, rtol=1e-3):
     return out
 
 
+def top_levels(ctx, levels):
+    """Levels of the timed region that ran in the fused coarsest-level kernel."""
+    return {n for n in range(levels) if ctx.timing_read(n)["top"][1] > 0}
+
+
 def search_per_level(bdis, ctx, p, w, h, steps, npairs=1, levels=None):
     """Per-level search launches of the event region: patches, mean launch time
     and the algorithmic rate against the FP32 vector peak."""
@@ -268,6 +278,7 @@ def bench_single(bdis, torch, args):
     dt_ev = time.perf_counter() - t1
     tk = ctx.timing_read()
     per_level = search_per_level(bdis, ctx, p, w, h, args.steps)
+    top = top_levels(ctx, p.levels)
     ctx.timing(False)
     d = out["disp"].cpu().numpy()
     var = out["var"].cpu().numpy()
@@ -289,7 +300,7 @@ def bench_single(bdis, torch, args):
     setup = dict(first_call_ms=round(first_ms, 2), tune_ms=round(tune_ms, 2), capture_ms=round(cap_ms, 2),
                  note="first call of a new shape tunes the launch shapes (cached per shape and in the tuning "
                       "file) and captures the graph; both outside the timed regions")
-    return dict(w=w, h=h, p=p, dt=dt, dt_ev=dt_ev, tk=tk, acc=acc, left=left, right=right, disp=d, var=var,
+    return dict(w=w, h=h, p=p, dt=dt, dt_ev=dt_ev, tk=tk, top=top, acc=acc, left=left, right=right, disp=d, var=var,
                 mp=method_params(2), per_level=per_level, setup=setup,
                 latency_ms=dict(median=round(lat[len(lat) // 2], 4), p90=round(lat[int(len(lat) * 0.9)], 4),
                                 calls=len(lat)))
@@ -361,6 +372,7 @@ def bench_batch(bdis, torch, args):
     torch.cuda.synchronize()
     tk = ctx.timing_read()
     per_level = search_per_level(bdis, ctx, p, 1920, 1080, max(1, args.batch_steps // 2), npairs=n)
+    top = top_levels(ctx, p.levels)
     ctx.timing(False)
     nu = min(n, uniq)
     dd = [outs[i]["disp"].cpu().numpy() for i in range(nu)]
@@ -387,7 +399,7 @@ def bench_batch(bdis, torch, args):
     one.close()
     steps_ev = max(1, args.batch_steps // 2)
     mpx = 1920 * 1080 * n * args.batch_steps / dt / 1e6
-    flops = search_flops(bdis, p, 1920, 1080) * n
+    flops = search_flops(bdis, p, 1920, 1080, skip=top) * n
     res = dict(metric="disparity Mpixel/s (1080p batch)", value=round(mpx, 2), unit="Mpixel/s",
                pairs_per_step=n, unique_pairs=uniq, steps=args.batch_steps,
                ms_per_step=round(dt * 1e3 / args.batch_steps, 3),
@@ -395,7 +407,7 @@ def bench_batch(bdis, torch, args):
                                     "dark gain U(0.2,0.5), noise 3), L=6 P=12 S=4 K=16 variance on",
                            share="64 of the 512-pair stream"),
                roofline=roofline(flops, steps_ev, tk, "k_search_u8<12>", "1080p_batch64",
-                                 search_bytes(bdis, p, 1920, 1080) * n),
+                                 search_bytes(bdis, p, 1920, 1080, skip=top) * n),
                search_per_level=per_level, kernels=kernel_table(tk), setup=setup, **acc,
                plain_single=dict(ms_per_pair=round(dt1 * 1e3, 4), mpx_s=round(1920 * 1080 / dt1 / 1e6, 2),
                                  same_bits_as_batch_pair0=same0,
@@ -437,6 +449,7 @@ def bench_mixed(bdis, torch, args):
         ctx.compute_batch(lefts, rights, levels=levels, outs=outs)
     torch.cuda.synchronize()
     tk = ctx.timing_read()
+    top = top_levels(ctx, max(levels))
     ctx.timing(False)
     errs, bad, dens = [], [], []
     for wh, (i, pr) in base.items():
@@ -448,8 +461,8 @@ def bench_mixed(bdis, torch, args):
     ctx.close()
     ae = np.concatenate(errs)
     px = sum(w * h for (w, h) in sizes)
-    flops = sum(search_flops(bdis, p, w, h, levels[i]) for i, (w, h) in enumerate(sizes))
-    nbytes = sum(search_bytes(bdis, p, w, h, levels[i]) for i, (w, h) in enumerate(sizes))
+    flops = sum(search_flops(bdis, p, w, h, levels[i], skip=top) for i, (w, h) in enumerate(sizes))
+    nbytes = sum(search_bytes(bdis, p, w, h, levels[i], skip=top) for i, (w, h) in enumerate(sizes))
     return dict(metric="disparity Mpixel/s (mixed batch)", value=round(px * args.batch_steps / dt / 1e6, 2),
                 unit="Mpixel/s", pairs_per_step=len(sizes), megapixels_per_step=round(px / 1e6, 3),
                 unique_pairs=len(base), steps=args.batch_steps, ms_per_step=round(dt * 1e3 / args.batch_steps, 3),
@@ -696,8 +709,8 @@ def main():
                 config=dict(workload="640x480 synthetic stereo pair (planes+bumps 0-64 px, 20% textureless, "
                                      "highlights, gain U(0.8,1.2), noise 2), L=5 P=8 S=3 K=16 variance on",
                             global_batch=1, pairs_per_step=1),
-                roofline=roofline(search_flops(bdis, p, w, h), args.steps, s["tk"], "k_search_u8<8>", "640x480",
-                                  search_bytes(bdis, p, w, h)),
+                roofline=roofline(search_flops(bdis, p, w, h, skip=s["top"]), args.steps, s["tk"], "k_search_u8<8>",
+                                  "640x480", search_bytes(bdis, p, w, h, skip=s["top"])),
                 kernels=kernel_table(s["tk"]),
                 ms_per_step_with_kernel_events=round(s["dt_ev"] * 1e3 / args.steps, 4),
                 latency_ms=s["latency_ms"], setup=s["setup"], **s["acc"])

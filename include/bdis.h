@@ -307,7 +307,9 @@ bdis_status bdis_debug_dump(bdis_ctx* ctx, int level, int what, void* host_dst, 
  * a profiler's kernel trace reports it.  kernel: 0 pyramid, 1 patch search,
  * 2 patch probability (launched for large levels only; small levels compute
  * it inside the fusion), 3 fusion, 4 the per-pair sigma_r reduction (large
- * levels only), 5 the backward pass (all launches of a level).  A phase that
+ * levels only), 5 the backward pass (all launches of a level), 6 the coarsest
+ * level run as one workgroup per pair (its pyramid step, search, level
+ * scalars, records and fusion in one launch).  A phase that
  * launches nothing on a level is not counted.  bdis_timing_enable(ctx, 1)
  * clears the totals and starts recording; bdis_timing_read synchronises the
  * recorded events and returns the summed GPU time (ms) and the launch count
@@ -320,7 +322,8 @@ enum {
   BDIS_K_FUSE = 3,
   BDIS_K_REDUCE = 4,
   BDIS_K_BACKWARD = 5,
-  BDIS_K_COUNT = 6
+  BDIS_K_TOP = 6,
+  BDIS_K_COUNT = 7
 };
 bdis_status bdis_timing_enable(bdis_ctx* ctx, int enable);
 /* Host time (ms) the last bdis_compute / bdis_compute_batch call spent tuning

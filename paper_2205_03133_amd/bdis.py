@@ -372,7 +372,7 @@ class Context:
         c = counts.cpu()
         return int(c[0]), int(c[1])
 
-    KERNELS = ("pyramid", "search", "prob", "fuse", "reduce", "backward")
+    KERNELS = ("pyramid", "search", "prob", "fuse", "reduce", "backward", "top")
 
     def timing(self, enable):
         """Start (clearing totals) or stop per-kernel HIP-event timing."""

@@ -231,6 +231,10 @@ struct PlanTab {
   const PairLevel& operator[](size_t i) const { return data()[i]; }
 };
 
+// Untuned plans run the coarsest level in k_top from this many pairs on (one
+// workgroup per pair at once beats the level's launches there).
+constexpr int kTopMinPairs = 8;
+
 // Launch plan of one call: level-major job table and workgroup counts.
 struct Plan {
   int max_levels = 0;
@@ -248,6 +252,7 @@ struct Plan {
   bool pyr_tall[kMaxLevels]{};   // pyramid level built with the large-tile kernel
   bool f32 = false;              // float (FP64) path: per-pixel pyramid blocks, fixed search size
   int top_level = -1;            // level whose pyramid step, search and fusion run in k_top (-1: none)
+  int top_fits = -1;             // the level k_top could take (-1: none)
   TopShape top{};                // its launch shape
   PyrChain chain{};              // small pyramid levels built by one launch (chain.m == 0: none)
   int chain_blocks = 0;
@@ -739,7 +744,7 @@ bdis_status build_plan(bdis_ctx* c, const PairSpec* pairs, size_t npairs, Plan* 
   }
   // tuned choices of this batch shape (uint8 stereo path; the key is a string,
   // so it is built only when something was tuned or loaded)
-  bool top_tuned_off = false, chain_tuned_off = false;
+  bool top_tuned_off = false, top_tuned_on = false, chain_tuned_off = false;
   if (!f32 && !flow && !c->tuned.empty()) {
     for (int n = 0; n < pl.max_levels; ++n) {
       if (pl.tab_count[n] == 0) continue;
@@ -754,6 +759,7 @@ bdis_status build_plan(bdis_ctx* c, const PairSpec* pairs, size_t npairs, Plan* 
         pl.fuse_ty[n] = tc.fuse_ty;
       if (n >= 1 && (tc.pyr_tall == 0 || tc.pyr_tall == 1)) pl.pyr_tall[n] = tc.pyr_tall == 1;
       if (tc.top == 0) top_tuned_off = true;
+      if (tc.top == 1) top_tuned_on = true;
       if (tc.chain == 0) chain_tuned_off = true;
     }
   }
@@ -763,7 +769,7 @@ bdis_status build_plan(bdis_ctx* c, const PairSpec* pairs, size_t npairs, Plan* 
   // coarsest level) in one workgroup per pair, when it is above the finest
   // level, uses the mask weights and fits
   const int top = pl.max_levels - 1;
-  if (!f32 && !flow && c->top_mode != 0 && (c->top_mode == 1 || !top_tuned_off) && top >= 1 && top > p.finest_level && p.fusion != 1 && pl.tab_count[top] > 0) {
+  if (!f32 && !flow && c->top_mode != 0 && top >= 1 && top > p.finest_level && p.fusion != 1 && pl.tab_count[top] > 0) {
     int mw = 0, mh = 0, msw = 0, msh = 0, mnp = 0;
     for (int e = 0; e < pl.tab_count[top]; ++e) {
       const PairLevel& q = pl.tab[pl.tab_first[top] + e];
@@ -774,7 +780,13 @@ bdis_status build_plan(bdis_ctx* c, const PairSpec* pairs, size_t npairs, Plan* 
       mnp = std::max(mnp, q.g.nx * q.g.ny);
     }
     pl.top = top_shape(p.patch, p.stride, mw, mh, msw, msh, mnp);
-    if (pl.top.g > 0) pl.top_level = top;
+    if (pl.top.g > 0) {
+      pl.top_fits = top;
+      // forced, tuned, or (untuned) for batches of many pairs, where one
+      // workgroup per pair at once beats the level's launches
+      const bool use = c->top_mode == 1 || top_tuned_on || (!top_tuned_off && pl.tab_count[top] >= kTopMinPairs);
+      if (use) pl.top_level = top;
+    }
   }
   if (!f32 && !flow && c->chain_mode != 0 && (c->chain_mode == 1 || !chain_tuned_off)) plan_chain(pl);
   assign_offsets(p, pl);
@@ -843,7 +855,7 @@ bdis_status launch_all(bdis_ctx* c, const Plan& pl, hipStream_t st) {
     const int cnt = pl.tab_count[n];
     const LevelParams lp = plan_level_params(p, pl, n);
     if (n == pl.top_level) {  // pyramid step, search, scalars, records and fusion in one launch
-      const long tmk = timing_start(c, BDIS_K_SEARCH, st, n);
+      const long tmk = timing_start(c, BDIS_K_TOP, st, n);
       e = launch_top(tab, cnt, lp, pl.top, st);
       timing_stop(c, tmk, st);
       if (e != hipSuccess) return hip_fail(c, e, "top-level launch");
@@ -891,6 +903,10 @@ std::string graph_key(const bdis_params& p, const Plan& pl) {
   add(pl.fuse_ty, sizeof pl.fuse_ty);
   add(pl.pyr_tall, sizeof pl.pyr_tall);
   add(&pl.max_levels, sizeof pl.max_levels);
+  add(&pl.top_level, sizeof pl.top_level);
+  add(&pl.top, sizeof pl.top);
+  add(&pl.chain, sizeof pl.chain);
+  add(&pl.chain_blocks, sizeof pl.chain_blocks);
   return k;
 }
 
@@ -999,6 +1015,7 @@ std::string tune_cache_path() {
 // others counts.  The choices are kept per level shape and written to the
 // tuning cache file.
 constexpr int kTuneReps = 5;
+constexpr int kTuneGraphReps = 10;  // replays per captured combination of the structural choices
 
 bdis_status save_tune_cache(bdis_ctx* c);
 
@@ -1016,21 +1033,18 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
     best[n].search = pl.search_opt[n];
     best[n].fuse_ty = pl.fuse_ty[n];
     best[n].pyr_tall = pl.pyr_tall[n] ? 1 : 0;
-    best[n].top = n == pl.top_level ? 1 : -1;
+    best[n].top = n == pl.top_fits ? (pl.top_level == n ? 1 : 0) : -1;
   }
-  const int top_cand = pl.top_level;  // the level k_top could take (-1: none)
-  int chain_lo = -1, chain_hi = -1;   // levels spanned by the chain timing (phase 4)
+  const int top_cand = pl.top_fits;   // the level k_top could take (-1: none)
+  int chain_hi = -1;                  // top level of the pyramid chain, where its choice is kept
   if (enabled) {
     std::vector<hipEvent_t> ev(2 * kMaxLevels, nullptr);
     hipError_t e = hipSuccess;
     for (auto& x : ev)
       if (e == hipSuccess) e = hipEventCreate(&x);
     bdis_status s2 = BDIS_OK;
-    // Times `trial` over kTuneReps passes; phase 0 search, 1 fusion, 2 pyramid,
-    // 3 the coarsest level's span (its pyramid step through its fusion, or the
-    // k_top launch), 4 the span of the chained pyramid levels (the chain
-    // launch, or one launch each).  best_ms[n] / pick(n) record a level whose
-    // timed launch (or span) beat its best.
+    // Times `trial` over kTuneReps passes; phase 0 search, 1 fusion, 2 pyramid.
+    // best_ms[n] / pick(n) record a level whose timed launch beat its best.
     auto run_trial = [&](Plan& trial, int phase, float* best_ms, auto&& pick) {
       assign_offsets(p, trial);
       if ((s2 = upload_table(c, trial, st)) != BDIS_OK) return;
@@ -1046,21 +1060,8 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
         le = LaunchEvents{};
         return r;
       };
-      const int top = trial.max_levels - 1;
-      auto span_begin = [&](int n) {
-        LaunchEvents& le = launch_events();
-        le.start = ev[2 * n];
-        le.stop = ev[2 * n + 1];
-        le.used = false;
-      };
-      auto span_end = [&](int n) {
-        rec[n] = launch_events().used;
-        launch_events() = LaunchEvents{};
-      };
       for (int rep = 0; rep < kTuneReps && e == hipSuccess; ++rep) {
         for (int n = 1; n < trial.max_levels && e == hipSuccess; ++n) {
-          if (phase == 3 && n == top) span_begin(n);
-          if (phase == 4 && n == chain_lo) span_begin(chain_hi);
           if (n == trial.top_level) continue;
           const bool chained = trial.chain.m > 0 && n > trial.chain.n0 && n <= trial.chain.n0 + trial.chain.m;
           if (chained) {
@@ -1069,7 +1070,6 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
           } else {
             e = timed(n, 2, [&] { return launch_pyramid_level(c->tab_dev, trial, n, st); });
           }
-          if (phase == 4 && n == chain_hi) span_end(chain_hi);
         }
         for (int n = trial.max_levels - 1; n >= p.finest_level && e == hipSuccess; --n) {
           const PairLevel* tab = c->tab_dev + trial.tab_first[n];
@@ -1083,13 +1083,12 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
             if (e == hipSuccess) e = launch_prob(tab, cnt, trial.prob_blocks[n], lp, st);
             if (e == hipSuccess) e = timed(n, 1, [&] { return launch_fuse(tab, cnt, trial.fuse_blocks[n], lp, st); });
           }
-          if (phase == 3 && n == top) span_end(n);
         }
         if (p.finest_level > 0 && e == hipSuccess)
           e = launch_upsample(c->tab_dev + trial.tab_first[0], trial.tab_count[0], trial.up_blocks, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess || rep == 0) continue;  // the first pass warms caches and code
-        const int lo = phase == 2 ? 1 : phase == 3 ? top : phase == 4 ? chain_hi : p.finest_level;
+        const int lo = phase == 2 ? 1 : p.finest_level;
         for (int n = lo; n < trial.max_levels; ++n) {
           if (!trial.tab_count[n] || !rec[n]) continue;  // nothing launched at this level
           float ms = 0.0f;
@@ -1145,49 +1144,77 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
       }
       run_trial(trial, 2, bp, [&](int n) { best[n].pyr_tall = tall; });
     }
-    // 4. the coarsest level in one workgroup per pair against its per-phase
-    // launches (the others at their best)
-    if (top_cand >= 0 && c->top_mode < 0) {
-      float bt[kMaxLevels];
-      std::fill(bt, bt + kMaxLevels, 1e30f);
-      for (int use = 0; use <= 1 && e == hipSuccess && s2 == BDIS_OK; ++use) {
-        Plan trial = pl;
-        trial.top_level = use ? top_cand : -1;
-        trial.chain.m = 0;
-        for (int n = 0; n < trial.max_levels; ++n) {
-          if (n >= p.finest_level) {
-            trial.search_opt[n] = best[n].search;
-            trial.fuse_ty[n] = best[n].fuse_ty;
-          }
-          trial.pyr_tall[n] = best[n].pyr_tall == 1;
-        }
-        run_trial(trial, 3, bt, [&](int n) { best[n].top = use; });
-      }
-    }
-    // 5. one launch for the chained small pyramid levels against one each
-    // (everything else at its best)
-    if (c->chain_mode < 0 && e == hipSuccess && s2 == BDIS_OK) {
-      Plan cand = pl;
-      for (int n = 0; n < cand.max_levels; ++n) {
+    // 4. the structural choices: the coarsest level in one workgroup per pair
+    // or in its per-phase launches, and one launch for a run of small pyramid
+    // levels or one each.  They change the number of launches, whose cost is
+    // the graph's node overhead, so each combination (the rest at its best)
+    // is captured as a graph and its replays are timed.
+    if ((top_cand >= 0 && c->top_mode < 0) || c->chain_mode < 0) {
+      Plan base = pl;
+      for (int n = 0; n < base.max_levels; ++n) {
         if (n >= p.finest_level) {
-          cand.search_opt[n] = best[n].search;
-          cand.fuse_ty[n] = best[n].fuse_ty;
+          base.search_opt[n] = best[n].search;
+          base.fuse_ty[n] = best[n].fuse_ty;
         }
-        if (n >= 1) cand.pyr_tall[n] = best[n].pyr_tall == 1;
+        if (n >= 1) base.pyr_tall[n] = best[n].pyr_tall == 1;
       }
-      if (top_cand >= 0 && best[top_cand].top == 0) cand.top_level = -1;
-      plan_chain(cand);
-      if (cand.chain.m > 0) {
-        chain_lo = cand.chain.n0 + 1;
-        chain_hi = cand.chain.n0 + cand.chain.m;
-        float bc[kMaxLevels];
-        std::fill(bc, bc + kMaxLevels, 1e30f);
-        for (int use = 0; use <= 1 && e == hipSuccess && s2 == BDIS_OK; ++use) {
-          Plan trial = cand;
-          if (!use) trial.chain.m = 0;
-          run_trial(trial, 4, bc, [&](int n) { best[n].chain = use; });
+      const bool was_timing = c->tm.on;
+      c->tm.on = false;  // captured launches record no timing events
+      float best_ms = 1e30f;
+      int best_top = top_cand >= 0 ? 1 : -1, best_chain = -1;
+      for (int top = 1; top >= 0 && e == hipSuccess && s2 == BDIS_OK; --top) {
+        if (top == 1 && top_cand < 0) continue;
+        if (c->top_mode >= 0 && top != c->top_mode && top_cand >= 0) continue;
+        for (int ch = 1; ch >= 0 && e == hipSuccess && s2 == BDIS_OK; --ch) {
+          Plan trial = base;
+          trial.top_level = top ? top_cand : -1;
+          trial.chain.m = 0;
+          if (ch) {
+            if (c->chain_mode == 0) continue;
+            plan_chain(trial);
+            if (trial.chain.m == 0) continue;
+          } else if (c->chain_mode == 1) {
+            Plan probe = trial;
+            plan_chain(probe);
+            if (probe.chain.m > 0) continue;
+          }
+          assign_offsets(p, trial);
+          if ((s2 = upload_table(c, trial, st)) != BDIS_OK) break;
+          hipGraph_t g = nullptr;
+          hipGraphExec_t ge = nullptr;
+          if ((e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) break;
+          const bdis_status s3 = launch_all(c, trial, c->capture_stream);
+          e = hipStreamEndCapture(c->capture_stream, &g);
+          if (s3 != BDIS_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            s2 = s3;
+            break;
+          }
+          if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+          for (int r = 0; r < 2 && e == hipSuccess; ++r) e = hipGraphLaunch(ge, st);  // warm-up
+          if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+          for (int r = 0; r < kTuneGraphReps && e == hipSuccess; ++r) e = hipGraphLaunch(ge, st);
+          if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+          if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+          float ms = 0.0f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+          if (ge) (void)hipGraphExecDestroy(ge);
+          if (g) (void)hipGraphDestroy(g);
+          if (e == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best_top = top_cand >= 0 ? top : -1;
+            best_chain = ch;
+            // the level that keeps the chain choice: the top of the chain this
+            // top-level choice allows
+            Plan probe = trial;
+            plan_chain(probe);
+            chain_hi = probe.chain.m > 0 ? probe.chain.n0 + probe.chain.m : -1;
+          }
         }
       }
+      c->tm.on = was_timing;
+      if (top_cand >= 0) best[top_cand].top = best_top;
+      if (chain_hi >= 0 && best_chain >= 0) best[chain_hi].chain = best_chain;
     }
     for (auto& x : ev)
       if (x) (void)hipEventDestroy(x);
@@ -1205,7 +1232,7 @@ bdis_status tune(bdis_ctx* c, Plan& pl, hipStream_t st) {
       pl.fuse_ty[n] = best[n].fuse_ty;
     }
     if (n >= 1) pl.pyr_tall[n] = best[n].pyr_tall == 1;
-    if (n == top_cand && best[n].top == 0) pl.top_level = -1;
+    if (n == top_cand) pl.top_level = best[n].top == 1 ? n : -1;
   }
   pl.chain.m = 0;
   if (c->chain_mode == 1 || (c->chain_mode < 0 && !(chain_hi >= 0 && best[chain_hi].chain == 0))) plan_chain(pl);
