@@ -22,18 +22,34 @@ BDIS_DEV PatchRaw patch_raw(const PairLevel& a, const LevelParams& lp, size_t k)
   return p;
 }
 
+// 1 / x to within about one unit in the last place: the hardware estimate
+// refined by two Newton steps, e <- 1 - x r, r <- r + r e (each step squares
+// the relative error), for x in [2^-1000, 2^1000]; the correctly rounded
+// division elsewhere (zero, huge, subnormal, NaN).  About half the FP64
+// instructions of the division; used wherever a result is normalised, by
+// every kernel that computes that result, so the kernels agree bit for bit.
+BDIS_DEV double recip(double x) {
+  if (__builtin_expect(!(fabs(x) >= 0x1p-1000 && fabs(x) <= 0x1p1000), 0)) return 1.0 / x;
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
 // The fusion record of patch p of pyramid level `level`: (u, pi or -1 when
 // rejected, sigma_k^2 at the finest level with variance on, else NaN, post).
 // No floating-point contraction, so every kernel that inlines it gets the
-// same bits.
+// same bits.  Divisions by tau and by the constants of the fit are taken as
+// products with their reciprocals.
 BDIS_DEV D4 patch_record(const PairLevel& a, const LevelParams& lp, int level, const PatchRaw& p, double tau) {
 #pragma clang fp contract(off)
   const double u = p.u;
   const double nan = __builtin_nan("");
   if (!p.acc) return D4{u, -1.0, nan, 0.0};
   const D4 d = p.d;
-  const double den = 1.0 + exp(-d.x / tau) + exp(-d.y / tau) + exp(-d.z / tau) + exp(-d.w / tau);
-  const double post = 1.0 / den;
+  const double rt = 1.0 / tau;
+  const double den = 1.0 + exp(-d.x * rt) + exp(-d.y * rt) + exp(-d.z * rt) + exp(-d.w * rt);
+  const double post = recip(den);
   double wsum = 0.0;
   for (int n = lp.finest; n < a.levels; ++n) wsum += (double)lp.omega[n];
   const double gamma = (double)lp.omega[level] / wsum;
@@ -45,18 +61,18 @@ BDIS_DEV D4 patch_record(const PairLevel& a, const LevelParams& lp, int level, c
     // sum (x - mean x)^2 = 7/8.
     const double y[5] = {d.x, d.y, 0.0, d.z, d.w};
     const double x[5] = {1.0, 0.25, 0.0, 0.25, 1.0};
-    const double ym = (y[0] + y[1] + y[2] + y[3] + y[4]) / 5.0;
+    const double ym = (y[0] + y[1] + y[2] + y[3] + y[4]) * 0.2;
     double sxy = 0.0;
     for (int t = 0; t < 5; ++t) sxy += (x[t] - 0.5) * y[t];
-    const double kappa = sxy / 0.875;
+    const double kappa = sxy * (8.0 / 7.0);
     double v = sfail * sfail;
     if (kappa > 0.0) {
       double mse = 0.0;
       for (int t = 0; t < 5; ++t) {
-        const double res = (y[t] - (ym + kappa * (x[t] - 0.5))) / tau;
+        const double res = (y[t] - (ym + kappa * (x[t] - 0.5))) * rt;
         mse += res * res;
       }
-      mse /= 5.0;
+      mse *= 0.2;
       if (mse <= (double)lp.var_fit_thresh) {
         const double s2 = tau / (2.0 * kappa);
         v = s2 < v ? s2 : v;

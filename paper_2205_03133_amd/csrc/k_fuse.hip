@@ -47,7 +47,7 @@ constexpr int kMaxRec = kFuseMaxRec;
 // INLINE: the patch records are computed here (small levels) instead of read
 // from a preceding k_prob launch.
 template <bool INLINE, int TY>
-__global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab, int npairs, LevelParams lp) {
+__global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* __restrict__ tab, int npairs, LevelParams lp) {
   constexpr int kThreads = fuse_threads(TY);
   constexpr int kRowsPerLane = TY / (kThreads / kFuseTx);
   __shared__ double s_m[kMaxPatch];
@@ -165,6 +165,14 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
   const int xl = tid % kFuseTx;
   const int x = x0 + xl;
   const bool finest = lp.level == lp.finest;
+  // the table fields the pixel loop uses, read once: a scalar load of each
+  // would otherwise sit inside the loop, after the stores of every pixel
+  double* const o_ubar = a.ubar;
+  double* const o_qmap = a.qmap;
+  float* const o_disp = a.disparity;
+  float* const o_conf = a.confidence;
+  float* const o_var = a.variance;
+  double* const o_zmap = a.zmap;
   auto fuse_pixel = [&](int y) {
     int pilo = 0, pihi = -1, piex = -1, pjlo = 0, pjhi = -1, pjex = -1;
     cover_range(y, a.g.h, P, S, a.g.ny, pjlo, pjhi, pjex);
@@ -247,11 +255,12 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
     const size_t idx = (size_t)y * a.g.w + x;
     double ub, qv;
     bool valid = z > 0.0;
-    // one division for the normalisation by sum W (displacement and variance)
-    const double rz = valid ? 1.0 / z : 0.0;
+    // the normalisations by sum W (displacement and variance) and by sum M
+    // (confidence) through refined reciprocals
+    const double rz = valid ? recip(z) : 0.0;
     if (valid) {
       ub = zu * rz;
-      qv = zq / zm;
+      qv = zq * recip(zm);
     } else if (finest) {
       ub = __builtin_nan("");
       qv = 0.0;
@@ -263,8 +272,8 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
       ub = 0.0;
       qv = 0.0;
     }
-    if (a.zmap) {  // training contexts keep the fusion sums for the backward pass
-      gbl(a.zmap)[idx] = valid ? z : 0.0;
+    if (o_zmap) {  // training contexts keep the fusion sums for the backward pass
+      gbl(o_zmap)[idx] = valid ? z : 0.0;
       gbl(a.smmap)[idx] = zm;
       if (finest) {
         gbl(a.ubar_keep)[idx] = ub;
@@ -273,15 +282,15 @@ __global__ __launch_bounds__(fuse_threads(TY)) void k_fuse(const PairLevel* tab,
       }
     }
     if (!finest) {
-      gbl(a.ubar)[idx] = ub;
-      gbl(a.qmap)[idx] = qv;
+      gbl(o_ubar)[idx] = ub;
+      gbl(o_qmap)[idx] = qv;
       return;
     }
     if (lp.prob_thresh > 0.0f && qv < (double)lp.prob_thresh) valid = false;
     const float nan = __builtin_nanf("");
-    gbl(a.disparity)[idx] = valid ? (float)(-ub) : nan;
-    if (a.confidence) gbl(a.confidence)[idx] = valid ? (float)qv : 0.0f;
-    if (a.variance) gbl(a.variance)[idx] = (valid && lp.variance) ? (float)(zv * (rz * rz)) : nan;
+    gbl(o_disp)[idx] = valid ? (float)(-ub) : nan;
+    if (o_conf) gbl(o_conf)[idx] = valid ? (float)qv : 0.0f;
+    if (o_var) gbl(o_var)[idx] = (valid && lp.variance) ? (float)(zv * (rz * rz)) : nan;
   };
   // A wavefront holds one pixel row of the tile, so y and everything derived
   // from it (covering patch rows, vertical mask weights) are wave-uniform.

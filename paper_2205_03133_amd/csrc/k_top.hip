@@ -220,8 +220,8 @@ __global__ __launch_bounds__(kTopThreads) void k_top(const PairLevel* tab, Level
       row_add(ps, mb, cs.a0, cs.a1, cs.a2, cs.a3);
     }
     const bool valid = ps.z > 0.0;
-    gbl(a.ubar)[idx] = valid ? ps.zu * (1.0 / ps.z) : 0.0;  // as the fusion launch normalises
-    gbl(a.qmap)[idx] = valid ? ps.z / ps.zm : 0.0;
+    gbl(a.ubar)[idx] = valid ? ps.zu * recip(ps.z) : 0.0;  // as the fusion launch normalises
+    gbl(a.qmap)[idx] = valid ? ps.z * recip(ps.zm) : 0.0;
   }
 }
 
