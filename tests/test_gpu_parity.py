@@ -286,6 +286,53 @@ def test_ragged_shapes(B, oracle, shape, P, S, L, K):
     ctx.close()
 
 
+@pytest.mark.parametrize("case,L,K", [("one level", 1, 16), ("one iteration", 3, 1), ("two levels, one iteration", 2, 1)])
+def test_degenerate_depths(B, oracle, case, L, K):
+    """A single pyramid level (no parent maps: u_0 = 0, Pi = 0) and a single
+    Lucas-Kanade step per patch, against the oracle."""
+    from paper_2205_03133_amd.synth import make_pair
+    left, right, _, _ = make_pair(1, 5)
+    h, w = 120, 176
+    left, right = np.ascontiguousarray(left[:h, :w]), np.ascontiguousarray(right[:h, :w])
+    p = B.params(levels=L, patch=8, stride=4, iters=K, variance=1)
+    ctx, g = _run(B, left, right, p, case)
+    r = oracle.compute(left, right, oracle_params(oracle, p), trace=True)
+    st = parity(g["disp"], r["disp"], DISP_TOL)
+    _report("disparity", st)
+    assert st["frac"] >= PASS_FRAC
+    _check_variance(ctx, r["trace"], g, r, p)
+    ctx.close()
+
+
+def test_empty_batch_and_one_level_pair_in_a_batch(B):
+    """An empty batch is a no-op; a batch mixing a one-level pair with deeper
+    pairs equals the per-pair calls."""
+    import torch
+    from paper_2205_03133_amd.synth import make_pair
+    p = B.params(levels=3, patch=8, stride=4, iters=8, variance=1)
+    ctx = B.Context(p, 256, 192, max_batch=3)
+    print("[gpu] empty batch", flush=True)
+    assert ctx.compute_batch([], []) == []
+    sizes = [(256, 192, 1), (200, 150, 3), (160, 120, 2)]
+    lefts, rights = [], []
+    for idx, (w, h, _) in enumerate(sizes):
+        l, r, _, _ = make_pair(1, 10 + idx)
+        lefts.append(to_gpu(l[:h, :w]))
+        rights.append(to_gpu(r[:h, :w]))
+    print("[gpu] batch with a one-level pair", flush=True)
+    outs = ctx.compute_batch(lefts, rights, levels=[s[2] for s in sizes])
+    torch.cuda.synchronize()
+    outs = [{k: v.clone() for k, v in o.items()} for o in outs]
+    for i, (w, h, L) in enumerate(sizes):
+        ctx1 = B.Context(B.params(levels=L, patch=8, stride=4, iters=8, variance=1), w, h)
+        one = ctx1.compute(lefts[i], rights[i])
+        torch.cuda.synchronize()
+        for k in ("disp", "var", "conf"):
+            assert torch.equal(torch.nan_to_num(outs[i][k], nan=-7.0), torch.nan_to_num(one[k], nan=-7.0)), (i, k)
+        ctx1.close()
+    ctx.close()
+
+
 def test_exact_shift_recovered_on_gpu(B):
     """A textured pair shifted by an integer D comes back as D to 1e-6 px (interior)."""
     from scipy import ndimage
