@@ -226,19 +226,25 @@ def top_levels(ctx, levels):
     return {n for n in range(levels) if ctx.timing_read(n)["top"][1] > 0}
 
 
-def search_per_level(bdis, ctx, p, w, h, steps, npairs=1, levels=None):
+def search_per_level(bdis, ctx, p, w, h, steps, npairs=1, levels=None, shapes=None):
     """Per-level search launches of the event region: patches, mean launch time
-    and the algorithmic rate against the FP32 vector peak."""
+    and the algorithmic rate against the vector peak.  `shapes` (a list of
+    (w, h, levels) per pair) replaces npairs copies of w x h for mixed batches."""
     out = []
     P2 = p.patch * p.patch
-    for n in range(p.finest_level, levels or p.levels):
+    shapes = shapes or [(w, h, levels or p.levels)] * npairs
+    for n in range(p.finest_level, max(s[2] for s in shapes)):
         ms, k = ctx.timing_read(n)["search"]
         if k == 0:
             continue
-        _, _, nx, ny = bdis.level_dims(p, w, h, n)
-        flops = nx * ny * npairs * (4 * P2 + 5 * p.iters * P2 + 8 * WIN * P2)
+        patches = 0
+        for (sw, sh, sl) in shapes:
+            if n < sl:
+                _, _, nx, ny = bdis.level_dims(p, sw, sh, n)
+                patches += nx * ny
+        flops = patches * (4 * P2 + 5 * p.iters * P2 + 8 * WIN * P2)
         per = ms * 1e-3 / k
-        out.append(dict(level=n, patches=nx * ny * npairs, avg_us=round(per * 1e6, 3),
+        out.append(dict(level=n, patches=patches, avg_us=round(per * 1e6, 3),
                         tflops=round(flops / per / 1e12, 3), frac=round(flops / per / 1e12 / VALU_PEAK_TFLOPS, 5)))
     return out
 
@@ -450,6 +456,8 @@ def bench_mixed(bdis, torch, args):
     torch.cuda.synchronize()
     tk = ctx.timing_read()
     top = top_levels(ctx, max(levels))
+    per_level = search_per_level(bdis, ctx, p, 0, 0, steps_ev,
+                                 shapes=[(w, h, levels[i]) for i, (w, h) in enumerate(sizes)])
     ctx.timing(False)
     errs, bad, dens = [], [], []
     for wh, (i, pr) in base.items():
@@ -469,7 +477,7 @@ def bench_mixed(bdis, torch, args):
                 config=dict(workload="64 synthetic pairs, 8 each of 320x240 .. 1920x1080, disparity up to 10% of "
                                      "the width, L=4..6 by size, P=8 S=3 K=16 variance on"),
                 roofline=roofline(flops, steps_ev, tk, "k_search_u8<8>", "mixed64", nbytes),
-                kernels=kernel_table(tk), epe_median_px=round(float(np.median(ae)), 4),
+                search_per_level=per_level, kernels=kernel_table(tk), epe_median_px=round(float(np.median(ae)), 4),
                 bad1px=round(float((ae > 1.0).mean()), 5), density=round(float(np.mean(dens)), 4),
                 _oracle_jobs=[(base[wh][1][0], base[wh][1][1], mp[sizes.index(wh)]) for wh in sizes])
 
