@@ -466,6 +466,7 @@ BDIS_DEV void patch_adj(const PairLevel& a, const LevelParams& lp, int k, int r,
       }
       al = be = de = 0.0;
     };
+    const double rH = 1.0 / H;    // one division for the K reverse steps
     double u_next = uh[lp.K - 1];  // the next iterate is loaded one step ahead
     for (int t = lp.K - 1; t >= 0; --t) {
       const double ut = u_next;
@@ -490,11 +491,11 @@ BDIS_DEV void patch_adj(const PairLevel& a, const LevelParams& lp, int k, int r,
         cell = true;
       }
       const double b = (1.0 - f) * C0 + f * C1;  // sum J (I_w - T)
-      const double s1 = ub / H;
+      const double s1 = ub * rH;
       al += s1 * (1.0 - f);
       be += s1 * f;
-      de += 2.0 * s1 * b / H;
-      ub = ub * (1.0 - (C1 - C0) / H);
+      de += 2.0 * s1 * b * rH;
+      ub = ub * (1.0 - (C1 - C0) * rH);
     }
     apply();
     u0_adj = ub;
