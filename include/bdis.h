@@ -35,7 +35,9 @@
  *    per pair, and whether runs of small pyramid levels are built by one
  *    launch) and synchronises it,
  *    then records the launch sequence as a graph; a job table larger than any
- *    before synchronises the device before it is reallocated.  The tuned
+ *    before synchronises the device before it is reallocated.  A context
+ *    keeps at most 32 recorded sequences: recording one more destroys the
+ *    least recently launched one, after synchronising the device.  The tuned
  *    choices persist in a cache file keyed by the device architecture and the
  *    level shapes (read by bdis_create, rewritten after tuning), so a later
  *    process skips the timing.  Environment: BDIS_TUNE=0 skips the timing

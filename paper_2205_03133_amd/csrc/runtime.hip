@@ -285,7 +285,11 @@ struct TuneChoice {
 struct GraphEntry {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  unsigned long long used = 0;  // the context's launch count at its last launch
 };
+// Captured launch sequences a context keeps (one per batch shape and set of
+// launch choices); beyond this the least recently launched one is destroyed.
+constexpr size_t kMaxGraphs = 32;
 
 }  // namespace
 
@@ -309,6 +313,7 @@ struct bdis_ctx {
   bool multi_stream = false;      // calls have come on more than one stream
   hipStream_t capture_stream = nullptr;
   std::map<std::string, GraphEntry> graphs;
+  unsigned long long graph_launches = 0;
   std::map<std::string, TuneChoice> tuned;  // level shape key -> tuned launch shapes of the level
   std::string arch;                  // gcnArchName of the device (part of the tuning keys)
   std::string tune_cache;            // file the tuned choices persist in ("" = none)
@@ -916,6 +921,17 @@ bdis_status run_graph(bdis_ctx* c, const Plan& pl, hipStream_t st) {
   hipError_t e;
   if (it == c->graphs.end()) {
     const double t0 = wall_ms();
+    if (c->graphs.size() >= kMaxGraphs) {
+      // the least recently launched graph goes; the device is synchronised
+      // first, so that no launch of it is still in flight when it is destroyed
+      auto lru = c->graphs.begin();
+      for (auto g = c->graphs.begin(); g != c->graphs.end(); ++g)
+        if (g->second.used < lru->second.used) lru = g;
+      if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(c, e, "graph eviction");
+      if (lru->second.exec) (void)hipGraphExecDestroy(lru->second.exec);
+      if (lru->second.graph) (void)hipGraphDestroy(lru->second.graph);
+      c->graphs.erase(lru);
+    }
     GraphEntry ge;
     if ((e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
       return hip_fail(c, e, "graph capture begin");
@@ -934,6 +950,7 @@ bdis_status run_graph(bdis_ctx* c, const Plan& pl, hipStream_t st) {
     c->last_capture_ms = wall_ms() - t0;
   }
   if ((e = hipGraphLaunch(it->second.exec, st)) != hipSuccess) return hip_fail(c, e, "graph launch");
+  it->second.used = ++c->graph_launches;
   return BDIS_OK;
 }
 

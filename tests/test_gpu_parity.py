@@ -593,6 +593,44 @@ def test_batch_of_full_hd_pairs_matches_single(B, over):
     ctx.close()
 
 
+def test_graph_cache_evicts_and_recaptures(B, monkeypatch):
+    """More batch shapes than a context keeps graphs for: the least recently
+    launched graph is dropped and captured again on its next use, with the
+    same results; the shapes seen in between still replay."""
+    import torch
+    from paper_2205_03133_amd.synth import make_pair
+    monkeypatch.setenv("BDIS_TUNE", "0")
+    monkeypatch.setenv("BDIS_TUNE_CACHE", "")
+    p = B.params(levels=2, patch=8, stride=4, iters=4, variance=1)
+    l, r, _, _ = make_pair(1, 7)
+    ctx = B.Context(p, 160, 120)
+    shapes = [(64 + 2 * i, 48 + (i % 3)) for i in range(36)]
+    print(f"[gpu] graph cache: {len(shapes)} shapes", flush=True)
+    first = {}
+    for (w, h) in shapes:
+        out = ctx.compute(to_gpu(l[:h, :w]), to_gpu(r[:h, :w]))
+        torch.cuda.synchronize()
+        assert ctx.setup_time()[1] > 0.0, (w, h)  # a new shape is captured
+        if (w, h) in shapes[:2] + shapes[-2:]:
+            first[(w, h)] = {k: v.clone() for k, v in out.items()}
+    # the last shape is still cached: replayed without a capture
+    w, h = shapes[-1]
+    again = ctx.compute(to_gpu(l[:h, :w]), to_gpu(r[:h, :w]))
+    torch.cuda.synchronize()
+    assert ctx.setup_time()[1] == 0.0
+    for k in ("disp", "var", "conf"):
+        assert torch.equal(torch.nan_to_num(again[k], nan=-7.0), torch.nan_to_num(first[(w, h)][k], nan=-7.0)), k
+    # the first shapes were evicted: captured again, same bits
+    for (w, h) in shapes[:2]:
+        again = ctx.compute(to_gpu(l[:h, :w]), to_gpu(r[:h, :w]))
+        torch.cuda.synchronize()
+        assert ctx.setup_time()[1] > 0.0, (w, h)
+        for k in ("disp", "var", "conf"):
+            assert torch.equal(torch.nan_to_num(again[k], nan=-7.0),
+                               torch.nan_to_num(first[(w, h)][k], nan=-7.0)), (w, h, k)
+    ctx.close()
+
+
 def test_graph_replays_match_eager(B, monkeypatch):
     """Replays of the captured launch sequence equal an eager context's result, call after call."""
     import torch
