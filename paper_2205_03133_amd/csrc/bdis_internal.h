@@ -172,6 +172,8 @@ struct LevelParams {
   int keep;         // 1: store every per-patch intermediate (debug dumps, training), else
                     // only what the later phases read
   int f64_sums;     // 1: the float path's search partials (doubles), else the exact sums
+  int wide_win;     // 1: the search stages its whole right window (small launches), else
+                    // only the columns around its patches' starting range
   // 1-D mixture mask m(a) = sum_c exp(-(a - c)^2 / (2 sigma_s^2)), a = 0..P-1
   // (Eq. 9-10), and its derivative in sigma_s, evaluated once on the host
   double mask[kMaxPatch];

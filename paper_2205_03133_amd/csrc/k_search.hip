@@ -156,8 +156,12 @@ __global__ __launch_bounds__(THREADS, (search_min_waves<P, G>())) void k_search_
       atomicMax(&s_umax, mu);
     }
     __syncthreads();
-    xs = (ox0 + s_umin - MARG) & ~3;
-    ndr = min((oxl + P + s_umax + MARG + 2 - xs + 3) / 4, RWB / 4);
+    // on small launches the window's spare columns widen both margins, so that
+    // iterations that wander off still read LDS
+    const int need = oxl + P + s_umax + MARG + 2 - (ox0 + s_umin - MARG);
+    const int extra = lp.wide_win ? max(0, (RWB - 8 - need) / 2) : 0;
+    xs = (ox0 + s_umin - MARG - extra) & ~3;
+    ndr = min((oxl + P + s_umax + MARG + 2 + extra - xs + 3) / 4, RWB / 4);
     stage_right(xs, ndr);
   }
   const int rw = 4 * ndr;

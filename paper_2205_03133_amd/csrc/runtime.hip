@@ -456,6 +456,12 @@ LevelParams level_params(const bdis_params& p, int n) {
 }
 
 // Level parameters of a launch of level n under plan pl.
+// Search launches of at most this many workgroups stage the whole right
+// window (latency-bound levels: patches that wander past the start range still
+// read LDS); larger ones stage only the start range and its margins (the extra
+// columns would cost more traffic than they save).
+constexpr int kWideWindowBlocks = 4096;
+
 LevelParams plan_level_params(const bdis_params& p, const Plan& pl, int n) {
   LevelParams lp = level_params(p, n);
   lp.inline_prob = pl.inline_prob[n];
@@ -466,6 +472,7 @@ LevelParams plan_level_params(const bdis_params& p, const Plan& pl, int n) {
   lp.fuse_sep = std::min(nj, fuse_sep_rows(lp.fuse_ty));
   lp.keep = pl.keep ? 1 : 0;
   lp.f64_sums = pl.f32 ? 1 : 0;
+  lp.wide_win = pl.search_blocks[n] <= kWideWindowBlocks ? 1 : 0;
   return lp;
 }
 
