@@ -38,9 +38,9 @@
  *    before synchronises the device before it is reallocated.  A context
  *    keeps at most 32 recorded sequences: recording one more destroys the
  *    least recently launched one, after synchronising the device.  The tuned
- *    choices persist in a cache file keyed by the device architecture and the
- *    level shapes (read by bdis_create, rewritten after tuning), so a later
- *    process skips the timing.  Environment: BDIS_TUNE=0 skips the timing
+ *    choices persist in a cache file keyed by the device architecture, the
+ *    library version and the level shapes (read by bdis_create, rewritten
+ *    after tuning), so a later process skips the timing.  Environment: BDIS_TUNE=0 skips the timing
  *    (size-based defaults), BDIS_TUNE_CACHE=path names the cache file
  *    (default $HOME/.cache/bdis/tune.json; empty: no file), BDIS_GRAPH=0
  *    launches eagerly without graphs, BDIS_SEARCH_CONFIG=k (read by

@@ -476,8 +476,8 @@ LevelParams plan_level_params(const bdis_params& p, const Plan& pl, int n) {
   return lp;
 }
 
-// Tuning key of a level: the device architecture and the level's workload
-// shape across the batch (patch, stride, iterations, pairs, patches, pixels,
+// Tuning key of a level: the device architecture, the library version and the
+// level's workload shape across the batch (patch, stride, iterations, pairs, patches, pixels,
 // widest level image, and what changes the fusion's work).
 std::string level_key(const bdis_ctx* c, const Plan& pl, int n) {
   const bdis_params& p = c->p;
@@ -489,10 +489,12 @@ std::string level_key(const bdis_ctx* c, const Plan& pl, int n) {
     npx += (long)q.g.w * q.g.h;
     maxw = std::max(maxw, q.g.w);
   }
-  char buf[256];
-  snprintf(buf, sizeof buf, "%s P%d S%d K%d n%d f%d pairs%d patches%ld pixels%ld w%d fusion%d var%d",
-           c->arch.c_str(), p.patch, p.stride, p.iters, n, p.finest_level, pl.tab_count[n], np, npx, maxw,
-           p.fusion, p.variance);
+  // the library version is part of the key: a build whose kernels changed
+  // times its choices again instead of reusing another build's
+  char buf[320];
+  snprintf(buf, sizeof buf, "%s %s P%d S%d K%d n%d f%d pairs%d patches%ld pixels%ld w%d fusion%d var%d",
+           c->arch.c_str(), bdis_version(), p.patch, p.stride, p.iters, n, p.finest_level, pl.tab_count[n], np,
+           npx, maxw, p.fusion, p.variance);
   return buf;
 }
 
@@ -1953,6 +1955,6 @@ void bdis_destroy(bdis_ctx* c) {
 
 const char* bdis_last_error(const bdis_ctx* c) { return c ? c->err : g_create_err; }
 
-const char* bdis_version(void) { return "bdis-gfx950 0.3"; }
+const char* bdis_version(void) { return "bdis-gfx950 0.4"; }
 
 }  // extern "C"
