@@ -593,6 +593,36 @@ def test_batch_of_full_hd_pairs_matches_single(B, over):
     ctx.close()
 
 
+def test_full_stream_of_512_pairs_in_one_call(B, tmp_path, monkeypatch):
+    """The whole 512-pair 1920x1080 stream in one call, tuned as the bench runs
+    it: sampled pairs across the batch equal their pair computed alone (pair
+    0 alone is compared with the oracle by test_full_size_1080p)."""
+    import torch
+    from paper_2205_03133_amd.synth import make_pair, method_params
+    monkeypatch.setenv("BDIS_TUNE_CACHE", str(tmp_path / "tune.json"))
+    p = B.params(**method_params(5))
+    uniq = [make_pair(5, i) for i in range(4)]
+    ul = [to_gpu(q[0]) for q in uniq]
+    ur = [to_gpu(q[1]) for q in uniq]
+    n = 512
+    print(f"[gpu] {n} full-HD pairs in one call", flush=True)
+    ctx = B.Context(p, 1920, 1080, max_batch=n)
+    outs = ctx.compute_batch([ul[i % 4] for i in range(n)], [ur[i % 4] for i in range(n)])
+    torch.cuda.synchronize()
+    one_ctx = B.Context(p, 1920, 1080)
+    single = []
+    for i in range(4):
+        one = one_ctx.compute(ul[i], ur[i])
+        torch.cuda.synchronize()
+        single.append({k: v.clone() for k, v in one.items()})
+    for i in (0, 1, 2, 3, 129, 256, 383, 510, 511):
+        for k in ("disp", "var", "conf"):
+            assert torch.equal(torch.nan_to_num(outs[i][k], nan=-7.0),
+                               torch.nan_to_num(single[i % 4][k], nan=-7.0)), (i, k)
+    one_ctx.close()
+    ctx.close()
+
+
 def test_graph_cache_evicts_and_recaptures(B, monkeypatch):
     """More batch shapes than a context keeps graphs for: the least recently
     launched graph is dropped and captured again on its next use, with the
