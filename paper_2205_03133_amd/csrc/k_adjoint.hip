@@ -648,11 +648,35 @@ __global__ __launch_bounds__(kPixThreads) void k_pyr_adj(const PairLevel* tab, i
   const int w = a.g.w, h = a.g.h;
   if (idx >= w * h) return;
   const int y = idx / w, x = idx - y * w;
+  const auto uL = gbl(a.upLbar), uR = gbl(a.upRbar);
+  const size_t o = (size_t)y * a.dpitch + x;
+  if (x >= 3 && x <= w - 4 && y >= 3 && y <= h - 4) {
+    // interior: no reflected index reaches the pixel, so its parent taps are
+    // those with 2k + t - 2 = i: k = i/2 - 1, i/2, i/2 + 1 with weights 1, 6, 1
+    // (i even) or k = (i-1)/2, (i+1)/2 with weights 4, 4 (i odd).  The same
+    // nonzero terms in the same order as the general form below, so the same
+    // bits.
+    const int nx = (x & 1) ? 2 : 3, ny = (y & 1) ? 2 : 3;
+    const int kx0 = (x & 1) ? x / 2 : x / 2 - 1, ky0 = (y & 1) ? y / 2 : y / 2 - 1;
+    const double w3[3] = {1.0, 6.0, 1.0}, w2[2] = {4.0, 4.0};
+    double sl = 0.0, sr = 0.0;
+    for (int jy = 0; jy < ny; ++jy) {
+      const double wy = (y & 1) ? w2[jy] : w3[jy];
+      const size_t row = (size_t)(ky0 + jy) * a.updpitch + kx0;
+      for (int jx = 0; jx < nx; ++jx) {
+        const double wgt = wy * ((x & 1) ? w2[jx] : w3[jx]);
+        sl += wgt * uL[row + jx];
+        sr += wgt * uR[row + jx];
+      }
+    }
+    if (sl != 0.0) gbl(a.Lbar)[o] += sl / 256.0;
+    if (sr != 0.0) gbl(a.Rbar)[o] += sr / 256.0;
+    return;
+  }
   const int ky0 = max(y / 2 - 2, 0), ky1 = min(y / 2 + 2, a.uph - 1);
   const int kx0 = max(x / 2 - 2, 0), kx1 = min(x / 2 + 2, a.upw - 1);
   double wxs[5];
   for (int kx = kx0; kx <= kx1; ++kx) wxs[kx - kx0] = pyr_tap_weight(kx, x, w);
-  const auto uL = gbl(a.upLbar), uR = gbl(a.upRbar);
   double sl = 0.0, sr = 0.0;
   for (int ky = ky0; ky <= ky1; ++ky) {
     const double wy = pyr_tap_weight(ky, y, h);
@@ -665,7 +689,6 @@ __global__ __launch_bounds__(kPixThreads) void k_pyr_adj(const PairLevel* tab, i
       sr += wgt * uR[row + kx];
     }
   }
-  const size_t o = (size_t)y * a.dpitch + x;
   if (sl != 0.0) gbl(a.Lbar)[o] += sl / 256.0;
   if (sr != 0.0) gbl(a.Rbar)[o] += sr / 256.0;
 }
