@@ -338,6 +338,28 @@ namespace {
 
 char g_create_err[512] = {0};
 
+// Zeroes `n` bytes at `p` (16-byte stores for the aligned body, bytes at the
+// ends): a kernel rather than a memset node, so that a call a caller captures
+// into a graph replays correctly.
+__global__ __launch_bounds__(256) void k_zero_bytes(unsigned char* p, size_t n) {
+  const size_t head = std::min(n, (size_t)((16 - ((uintptr_t)p & 15)) & 15));
+  const size_t n16 = (n - head) / 16;
+  const size_t tail = head + 16 * n16;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint4* body = reinterpret_cast<uint4*>(p + head);
+  for (size_t i = t; i < n16; i += stride) body[i] = make_uint4(0u, 0u, 0u, 0u);
+  if (t < head) p[t] = 0;
+  if (t < n - tail) p[tail + t] = 0;
+}
+hipError_t zero_bytes(void* p, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const size_t n16 = n / 16 + 1;
+  const unsigned blocks = (unsigned)std::min<size_t>((n16 + 255) / 256, 4096);
+  bdis_launch(k_zero_bytes, dim3(blocks), dim3(256), 0, st, static_cast<unsigned char*>(p), n);
+  return hipGetLastError();
+}
+
 bdis_status fail(bdis_ctx* c, bdis_status st, const char* fmt, ...) {
   char* dst = c ? c->err : g_create_err;
   va_list ap;
@@ -1416,10 +1438,10 @@ bdis_status run_backward(bdis_ctx* c, std::vector<PairSpec> pairs, double* grad_
   for (size_t i = 0; i < pairs.size(); ++i) {
     Layout lay;
     make_layout(p, pairs[i].w, pairs[i].h, pairs[i].levels, &lay, true);
-    e = hipMemsetAsync(c->ws + i * c->slot_bytes + lay.adj_begin, 0, lay.adj_end - lay.adj_begin, st);
+    e = zero_bytes(c->ws + i * c->slot_bytes + lay.adj_begin, lay.adj_end - lay.adj_begin, st);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint clear");
   }
-  if ((e = hipMemsetAsync(c->hyper_dev, 0, sizeof(double) * (2 + kMaxLevels), st)) != hipSuccess)
+  if ((e = zero_bytes(c->hyper_dev, sizeof(double) * (2 + kMaxLevels), st)) != hipSuccess)
     return hip_fail(c, e, "adjoint clear");
   for (int n = p.finest_level; n < pl.max_levels; ++n) {
     const int blocks[3] = {pl.pyr_blocks[n], pl.search_blocks[n], pl.prob_blocks[n]};

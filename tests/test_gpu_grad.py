@@ -157,6 +157,31 @@ def test_autograd_rejects_stale_node(B):
     ctx.close()
 
 
+def test_repeated_backward_starts_from_cleared_adjoints(B):
+    """Backward twice after one forward, and again after a second forward on
+    another pair: each call clears its adjoint state first, so repeated calls
+    agree (to the rounding of their FP64 atomics) and follow the new pair."""
+    h, w = 80, 128
+    p = _fparams(B, levels=3, iters=6)
+    ctx = B.Context(p, w, h, train=True)
+    g = torch.randn((h, w), generator=torch.Generator().manual_seed(1)).cuda()
+    res = []
+    for seed in (5, 5, 6):
+        left, right, _, _ = _pair(h, w, seed=seed)
+        print(f"[gpu] backward after forward of pair {seed}", flush=True)
+        ctx.compute_f32(torch.from_numpy(left).cuda(), torch.from_numpy(right).cuda())
+        gl, gr, gh = ctx.backward(g)
+        gl2, gr2, gh2 = ctx.backward(g)
+        torch.cuda.synchronize()
+        for x, y in ((gl, gl2), (gr, gr2), (gh, gh2)):
+            assert torch.allclose(x, y, rtol=1e-9, atol=1e-12)
+        res.append((gl.clone(), gr.clone(), gh.clone()))
+    for x, y in zip(res[0], res[1]):
+        assert torch.allclose(x, y, rtol=1e-9, atol=1e-12)
+    assert not torch.allclose(res[0][0], res[2][0])
+    ctx.close()
+
+
 def test_backward_batch_equals_single(B):
     h, w = 64, 96
     p = _fparams(B, levels=2, iters=6)
