@@ -318,37 +318,72 @@ __global__ void k_tau_adj(const PairLevel* tab, int npairs, LevelParams lp) {
   sc[6] = 0.0;
 }
 
+// What a patch row's adjoint reads before its first scatter: the template row
+// and its zero-mean gradient, H, the patch's final displacement and its
+// adjoint, the window's right-image samples and the window SSD adjoints.  The
+// search adjoint issues these loads before its workgroup prologue, so that
+// their round trips overlap the prologue's.
 template <int P>
-BDIS_DEV void patch_adj(const PairLevel& a, const LevelParams& lp, int k, int r, int ox, int oy, int oxa, int xr0,
-                        int twl, int twr, double* sL, double* sG, double* sR) {
+struct AdjStart {
+  double T[P], J[P], H;
+  double u, ub;
+  double Rw[P + 3];  // right samples at columns ox + m0 - 1 .. ox + m0 + P + 1, m0 = floor(u)
+  double sbars[kWin];
+};
+
+template <int P>
+BDIS_DEV void patch_adj_start(const PairLevel& a, int k, int r, int ox, int oy, AdjStart<P>& st) {
   constexpr int G = group_lanes(P);
   constexpr int N = P * P;
   const int W = a.g.w, Hh = a.g.h;
   const bool row_live = r < P;
   const int rr = row_live ? r : P - 1;
   const auto Lg = gbl(a.Ld);
-  const auto Rg = gbl(a.Rd);
   const int dp = a.dpitch;
   const int yr = oy + rr;
   const size_t r0 = (size_t)reflect101(yr - 1, Hh) * dp, r1 = (size_t)yr * dp,
                r2 = (size_t)reflect101(yr + 1, Hh) * dp;
-  double T[P], J[P];
+  st.u = gbl(a.pa.u)[k];
+  st.ub = gbl(a.pu_adj)[k];
+  const auto sa = gbl(a.pssd_adj) + (size_t)k * kWin;
+#pragma unroll
+  for (int t = 0; t < kWin; ++t) st.sbars[t] = sa[t];
+  st.sbars[2] += gbl(a.scal)[5];  // share of d loss / d tau through sigma_r
   double sg = 0.0;
 #pragma unroll
   for (int c = 0; c < P; ++c) {
     const int x = ox + c, xm = reflect101(x - 1, W), xp = reflect101(x + 1, W);
-    T[c] = Lg[r1 + x];
-    J[c] = ((Lg[r0 + xp] - Lg[r0 + xm]) + 2.0 * (Lg[r1 + xp] - Lg[r1 + xm]) + (Lg[r2 + xp] - Lg[r2 + xm])) / 8.0;
-    sg += J[c];
+    st.T[c] = Lg[r1 + x];
+    st.J[c] = ((Lg[r0 + xp] - Lg[r0 + xm]) + 2.0 * (Lg[r1 + xp] - Lg[r1 + xm]) + (Lg[r2 + xp] - Lg[r2 + xm])) / 8.0;
+    sg += st.J[c];
   }
+  const auto Rrow = gbl(a.Rd) + (size_t)(oy + rr) * dp;
+  const int m0 = (int)floor(st.u);
+#pragma unroll
+  for (int c = 0; c < P + 3; ++c) st.Rw[c] = Rrow[clampi(ox + m0 - 1 + c, 0, W - 1)];
   const double gbar = group_sum_d<G>(row_live ? sg : 0.0) / (double)N;
   double hrow = 0.0;
 #pragma unroll
   for (int c = 0; c < P; ++c) {
-    J[c] -= gbar;
-    hrow += J[c] * J[c];
+    st.J[c] -= gbar;
+    hrow += st.J[c] * st.J[c];
   }
-  const double H = group_sum_d<G>(row_live ? hrow : 0.0);
+  st.H = group_sum_d<G>(row_live ? hrow : 0.0);
+}
+
+template <int P>
+BDIS_DEV void patch_adj(const PairLevel& a, const LevelParams& lp, int k, int r, int ox, int oy, int oxa, int xr0,
+                        int twl, int twr, double* sL, double* sG, double* sR, const AdjStart<P>& st) {
+  constexpr int G = group_lanes(P);
+  constexpr int N = P * P;
+  const int W = a.g.w;
+  const bool row_live = r < P;
+  const int rr = row_live ? r : P - 1;
+  const auto Rg = gbl(a.Rd);
+  const int dp = a.dpitch;
+  const double* const T = st.T;
+  const double* const J = st.J;
+  const double H = st.H;
 
   double Tb[P], Jb[P];
 #pragma unroll
@@ -390,13 +425,10 @@ BDIS_DEV void patch_adj(const PairLevel& a, const LevelParams& lp, int k, int r,
 
   // ---- window: SSD_d = sum (e - mean e)^2 at u + d.  The five offsets fall in
   // the cells m0 - 1, m0, m0 + 1 (m0 = floor u), whose samples are read once.
-  const double u = gbl(a.pa.u)[k];
-  double ub = gbl(a.pu_adj)[k];
-  const auto sa = gbl(a.pssd_adj) + (size_t)k * kWin;
+  const double u = st.u;
+  double ub = st.ub;
   const int m0 = (int)floor(u);
-  double Rw[P + 3];
-#pragma unroll
-  for (int c = 0; c < P + 3; ++c) Rw[c] = Rrow[clampi(ox + m0 - 1 + c, 0, W - 1)];
+  const double* const Rw = st.Rw;
   // one window sample at cell m0 - 1 + O, fraction f
   auto window_term = [&](auto oc, double f, double sbar) {
     constexpr int O = decltype(oc)::value;
@@ -419,13 +451,9 @@ BDIS_DEV void patch_adj(const PairLevel& a, const LevelParams& lp, int k, int r,
     }
     ub += group_sum_d<G>(row_live ? urow : 0.0);
   };
-  double sbars[kWin];  // all loads issued before the first use
-#pragma unroll
-  for (int t = 0; t < kWin; ++t) sbars[t] = sa[t];
-  sbars[2] += gbl(a.scal)[5];  // share of d loss / d tau through sigma_r
 #pragma unroll
   for (int t = 0; t < kWin; ++t) {
-    const double sbar = sbars[t];
+    const double sbar = st.sbars[t];
     if (sbar == 0.0) continue;
     const double v = u + 0.5 * (double)(t - 2);  // offsets -1, -1/2, 0, 1/2, 1
     const double fm = floor(v);
@@ -570,6 +598,8 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLeve
   double* sL = s_tile;
   double* sG = s_tile + P * twl;
   double* sR = s_tile + 2 * P * twl;
+  AdjStart<P> st;
+  if (active) patch_adj_start<P>(a, k, r, ox, oy, st);
   if (twl > 0) {
     for (int e = tid; e < P * (2 * twl + twr); e += kSearchF64Threads) s_tile[e] = 0.0;
     if (tid == 0) s_lo = INT_MAX;
@@ -587,7 +617,7 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLeve
   // the right tile starts at the lowest cell, but never past the last column:
   // scatters are clamped to the row, so every one of them lands at or after it
   const int xr0 = twl > 0 ? min(s_lo, W - 1) : 0;
-  if (active) patch_adj<P>(a, lp, k, r, ox, oy, oxa, xr0, twl, twr, sL, sG, sR);
+  if (active) patch_adj<P>(a, lp, k, r, ox, oy, oxa, xr0, twl, twr, sL, sG, sR, st);
   if (twl == 0) return;
   __syncthreads();
   const int dp = a.dpitch;
