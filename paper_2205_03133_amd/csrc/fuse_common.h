@@ -36,6 +36,37 @@ BDIS_DEV double recip(double x) {
   return r;
 }
 
+// The variance fit of a patch record (Eq. 15-17): kappa, the least-squares
+// slope of SSD_d - SSD_0 on x_d = d^2 (x = 1, 1/4, 0, 1/4, 1; mean x = 1/2,
+// sum (x - mean x)^2 = 7/8), and whether it passes: kappa > 0 and the mean
+// squared residual of the line, in units of tau (rt = 1 / tau), within the
+// threshold.  No contraction; the record and its adjoint both decide here, so
+// they take the same decision.
+struct VarFit {
+  double kappa;
+  bool pass;
+};
+BDIS_DEV VarFit var_fit(const D4& d, double rt, float thresh) {
+#pragma clang fp contract(off)
+  const double y[5] = {d.x, d.y, 0.0, d.z, d.w};
+  const double x[5] = {1.0, 0.25, 0.0, 0.25, 1.0};
+  const double ym = (y[0] + y[1] + y[2] + y[3] + y[4]) * 0.2;
+  double sxy = 0.0;
+  for (int t = 0; t < 5; ++t) sxy += (x[t] - 0.5) * y[t];
+  const double kappa = sxy * (8.0 / 7.0);
+  bool pass = false;
+  if (kappa > 0.0) {
+    double mse = 0.0;
+    for (int t = 0; t < 5; ++t) {
+      const double res = (y[t] - (ym + kappa * (x[t] - 0.5))) * rt;
+      mse += res * res;
+    }
+    mse *= 0.2;
+    pass = mse <= (double)thresh;
+  }
+  return VarFit{kappa, pass};
+}
+
 // The fusion record of patch p of pyramid level `level`: (u, pi or -1 when
 // rejected, sigma_k^2 at the finest level with variance on, else NaN, post).
 // No floating-point contraction, so every kernel that inlines it gets the
@@ -57,26 +88,11 @@ BDIS_DEV D4 patch_record(const PairLevel& a, const LevelParams& lp, int level, c
   double sig = nan;
   if (lp.variance && level == lp.finest) {
     const double sfail = lp.var_fail_sigma > 0.0f ? (double)lp.var_fail_sigma : (double)lp.P;
-    // OLS of y_d = SSD_d - SSD_0 on x_d = d^2, x = (1, 1/4, 0, 1/4, 1), mean x = 1/2,
-    // sum (x - mean x)^2 = 7/8.
-    const double y[5] = {d.x, d.y, 0.0, d.z, d.w};
-    const double x[5] = {1.0, 0.25, 0.0, 0.25, 1.0};
-    const double ym = (y[0] + y[1] + y[2] + y[3] + y[4]) * 0.2;
-    double sxy = 0.0;
-    for (int t = 0; t < 5; ++t) sxy += (x[t] - 0.5) * y[t];
-    const double kappa = sxy * (8.0 / 7.0);
     double v = sfail * sfail;
-    if (kappa > 0.0) {
-      double mse = 0.0;
-      for (int t = 0; t < 5; ++t) {
-        const double res = (y[t] - (ym + kappa * (x[t] - 0.5))) * rt;
-        mse += res * res;
-      }
-      mse *= 0.2;
-      if (mse <= (double)lp.var_fit_thresh) {
-        const double s2 = tau / (2.0 * kappa);
-        v = s2 < v ? s2 : v;
-      }
+    const VarFit vf = var_fit(d, rt, lp.var_fit_thresh);
+    if (vf.pass) {
+      const double s2 = tau / (2.0 * vf.kappa);
+      v = s2 < v ? s2 : v;
     }
     sig = v;
   }

@@ -18,6 +18,7 @@
 //   window   SSD_d = sum (e - mean e)^2, e = I_w(u + d) - T
 //   pyramid  L_n = B5 * L_{n-1} (even samples, reflect-101)
 #include "bdis_internal.h"
+#include "fuse_common.h"
 
 namespace bdis {
 
@@ -241,23 +242,12 @@ __global__ __launch_bounds__(kPixThreads) void k_prob_adj(const PairLevel* tab, 
     }
     tau_adj = -post_adj * post * post * sedl / (tau * tau);
     if (vt && sig_adj != 0.0) {
-      // the fit passed and was not capped iff sigma_k^2 = tau / (2 kappa) < sigma_fail^2
+      // the fit passed and was not capped iff sigma_k^2 = tau / (2 kappa) < sigma_fail^2,
+      // decided by the record's own arithmetic
       const double sfail = lp.var_fail_sigma > 0.0f ? (double)lp.var_fail_sigma : (double)P;
-      const double y[5] = {dl[0], dl[1], 0.0, dl[2], dl[3]};
-      const double x[5] = {1.0, 0.25, 0.0, 0.25, 1.0};
-      const double ym = (y[0] + y[1] + y[2] + y[3] + y[4]) / 5.0;
-      double sxy = 0.0;
-      for (int t = 0; t < 5; ++t) sxy += (x[t] - 0.5) * y[t];
-      const double kappa = sxy / 0.875;
-      bool pass = kappa > 0.0;
-      if (pass) {
-        double mse = 0.0;
-        for (int t = 0; t < 5; ++t) {
-          const double res = (y[t] - (ym + kappa * (x[t] - 0.5))) / tau;
-          mse += res * res;
-        }
-        pass = mse / 5.0 <= (double)lp.var_fit_thresh && tau / (2.0 * kappa) < sfail * sfail;
-      }
+      const VarFit vf = var_fit(dd, 1.0 / tau, lp.var_fit_thresh);
+      const double kappa = vf.kappa;
+      const bool pass = vf.pass && tau / (2.0 * kappa) < sfail * sfail;
       if (pass) {
         tau_adj += sig_adj / (2.0 * kappa);
         const double kappa_adj = -sig_adj * tau / (2.0 * kappa * kappa);
