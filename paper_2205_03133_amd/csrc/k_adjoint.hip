@@ -52,15 +52,6 @@ BDIS_DEV void block_atomic_sum(double v, double* dst, double* s_buf) {
   __syncthreads();
 }
 
-// Per pair: clear this level's d loss / d tau accumulator.
-__global__ void k_adj_init(const PairLevel* tab, int npairs) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= npairs) return;
-  gbl(tab[e].scal)[4] = 0.0;
-  gbl(tab[e].scal)[5] = 0.0;
-  gbl(tab[e].scal)[6] = 0.0;
-}
-
 // Finest level, per pixel: d loss / d Ubar = -d loss / d disparity on output
 // pixels (d = -Ubar), d loss / d variance likewise; 0 elsewhere.
 __global__ __launch_bounds__(kPixThreads) void k_seed(const PairLevel* tab, int npairs, LevelParams lp) {
@@ -767,7 +758,6 @@ hipError_t launch_fuse_adj(const PairLevel* tab, int npairs, int nblocks, const 
 hipError_t launch_backward_level(const PairLevel* tab, int npairs, const int* blocks, const LevelParams& lp,
                                  hipStream_t s) {
   const dim3 pix(kPixThreads);
-  bdis_launch(k_adj_init, dim3((npairs + 63) / 64), dim3(64), 0, s, tab, npairs);
   if (lp.level == lp.finest) bdis_launch(k_seed, dim3(blocks[0]), pix, 0, s, tab, npairs, lp);
   hipError_t e = launch_fuse_adj(tab, npairs, blocks[1], lp, s);
   if (e != hipSuccess) return e;

@@ -352,6 +352,16 @@ __global__ __launch_bounds__(256) void k_zero_bytes(unsigned char* p, size_t n) 
   if (t < head) p[t] = 0;
   if (t < n - tail) p[tail + t] = 0;
 }
+// The adjoint scalars of every entry of a job table (d loss / d tau, its share
+// per accepted SSD(0), d loss / d Gamma): zeroed once per backward pass.
+__global__ __launch_bounds__(64) void k_adj_scal_zero(const PairLevel* tab, int n) {
+  const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (e >= n) return;
+  double* sc = tab[e].scal;
+  sc[4] = 0.0;
+  sc[5] = 0.0;
+  sc[6] = 0.0;
+}
 hipError_t zero_bytes(void* p, size_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const size_t n16 = n / 16 + 1;
@@ -1443,6 +1453,9 @@ bdis_status run_backward(bdis_ctx* c, std::vector<PairSpec> pairs, double* grad_
   }
   if ((e = zero_bytes(c->hyper_dev, sizeof(double) * (2 + kMaxLevels), st)) != hipSuccess)
     return hip_fail(c, e, "adjoint clear");
+  const int ntab = (int)pl.tab.size();
+  bdis_launch(k_adj_scal_zero, dim3((ntab + 63) / 64), dim3(64), 0, st, c->tab_dev, ntab);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "adjoint clear");
   for (int n = p.finest_level; n < pl.max_levels; ++n) {
     const int blocks[3] = {pl.pyr_blocks[n], pl.search_blocks[n], pl.prob_blocks[n]};
     const long tmk = timing_start(c, BDIS_K_BACKWARD, st, n);
