@@ -266,37 +266,39 @@ __global__ __launch_bounds__(kPixThreads) void k_prob_adj(const PairLevel* tab, 
   block_atomic_sum(gam_adj, a.scal + 6, s_buf);
 }
 
-// Per pair: tau -> sigma_r (or alpha_r) and, in the dynamic mode, the share of
-// d loss / d tau that every accepted SSD(0) of the level receives; level weights.
-__global__ void k_tau_adj(const PairLevel* tab, int npairs, LevelParams lp) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= npairs) return;
-  const PairLevel& a = tab[e];
-  auto sc = gbl(a.scal);
+// The level's d loss / d tau (summed by the probability adjoint) through tau =
+// 2 sigma_r^2 s^2: returns the share every accepted SSD(0) of the level receives
+// in the dynamic mode (0 otherwise); with `commit` (once per pair) adds the
+// hyper-gradients of sigma_r (alpha_r) and of the level weights,
+// Gamma_n = omega_n / sum omega.
+BDIS_DEV double tau_adjoint(const PairLevel& a, const LevelParams& lp, bool commit) {
+  const auto sc = gbl(a.scal);
   const double tau_adj = sc[4];
   const double al = (double)lp.sigma_r;
   const double w2 = 2.0 * kWin * kWin;  // tau = w2 * sigma_r^2
-  double shr = 0.0;
+  double shr = 0.0, sr_adj;
   if (lp.sigma_r_dynamic) {
     const double pooled = sc[2], nacc = sc[3];
     if (pooled > kEpsSigma) {
-      atomic_add_d(a.hyper_adj + 1, tau_adj * w2 * 2.0 * al * pooled);
+      sr_adj = tau_adj * w2 * 2.0 * al * pooled;
       shr = tau_adj * w2 * al * al / (nacc * (double)(lp.P * lp.P));
     } else {
-      atomic_add_d(a.hyper_adj + 1, tau_adj * w2 * 2.0 * al * kEpsSigma);
+      sr_adj = tau_adj * w2 * 2.0 * al * kEpsSigma;
     }
   } else {
-    atomic_add_d(a.hyper_adj + 1, tau_adj * w2 * 2.0 * al);
+    sr_adj = tau_adj * w2 * 2.0 * al;
   }
-  sc[5] = shr;
-  // level weights: Gamma_n = omega_n / sum_{m=f}^{L-1} omega_m
-  const double gam_adj = sc[6];
-  double wsum = 0.0;
-  for (int n = lp.finest; n < a.levels; ++n) wsum += (double)lp.omega[n];
-  const double gamma = (double)lp.omega[lp.level] / wsum;
-  for (int m = lp.finest; m < a.levels; ++m)
-    atomic_add_d(a.hyper_adj + 2 + m, gam_adj * ((m == lp.level ? 1.0 : 0.0) - gamma) / wsum);
-  sc[6] = 0.0;
+  if (commit) {
+    atomic_add_d(a.hyper_adj + 1, sr_adj);
+    // level weights: Gamma_n = omega_n / sum_{m=f}^{L-1} omega_m
+    const double gam_adj = sc[6];
+    double wsum = 0.0;
+    for (int n = lp.finest; n < a.levels; ++n) wsum += (double)lp.omega[n];
+    const double gamma = (double)lp.omega[lp.level] / wsum;
+    for (int m = lp.finest; m < a.levels; ++m)
+      atomic_add_d(a.hyper_adj + 2 + m, gam_adj * ((m == lp.level ? 1.0 : 0.0) - gamma) / wsum);
+  }
+  return shr;
 }
 
 // What a patch row's adjoint reads before its first scatter: the template row
@@ -313,7 +315,7 @@ struct AdjStart {
 };
 
 template <int P>
-BDIS_DEV void patch_adj_start(const PairLevel& a, int k, int r, int ox, int oy, AdjStart<P>& st) {
+BDIS_DEV void patch_adj_start(const PairLevel& a, int k, int r, int ox, int oy, double shr, AdjStart<P>& st) {
   constexpr int G = group_lanes(P);
   constexpr int N = P * P;
   const int W = a.g.w, Hh = a.g.h;
@@ -329,7 +331,7 @@ BDIS_DEV void patch_adj_start(const PairLevel& a, int k, int r, int ox, int oy, 
   const auto sa = gbl(a.pssd_adj) + (size_t)k * kWin;
 #pragma unroll
   for (int t = 0; t < kWin; ++t) st.sbars[t] = sa[t];
-  st.sbars[2] += gbl(a.scal)[5];  // share of d loss / d tau through sigma_r
+  st.sbars[2] += shr;  // share of d loss / d tau through sigma_r
   double sg = 0.0;
 #pragma unroll
   for (int c = 0; c < P; ++c) {
@@ -579,8 +581,12 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLeve
   double* sL = s_tile;
   double* sG = s_tile + P * twl;
   double* sR = s_tile + 2 * P * twl;
+  // the level's tau adjoint (summed by the probability adjoint): its share per
+  // accepted SSD(0), and, once per pair (thread 0 of the pair's first
+  // workgroup), the hyper-gradients of sigma_r and of the level weights
+  const double shr = tau_adjoint(a, lp, blk == 0 && tid == 0);
   AdjStart<P> st;
-  if (active) patch_adj_start<P>(a, k, r, ox, oy, st);
+  if (active) patch_adj_start<P>(a, k, r, ox, oy, shr, st);
   if (twl > 0) {
     for (int e = tid; e < P * (2 * twl + twr); e += kSearchF64Threads) s_tile[e] = 0.0;
     if (tid == 0) s_lo = INT_MAX;
@@ -763,7 +769,6 @@ hipError_t launch_backward_level(const PairLevel* tab, int npairs, const int* bl
   if (e != hipSuccess) return e;
   if (lp.level > lp.finest) bdis_launch(k_hole_adj, dim3(blocks[0]), pix, 0, s, tab, npairs);
   bdis_launch(k_prob_adj, dim3(blocks[2]), pix, 0, s, tab, npairs, lp);
-  bdis_launch(k_tau_adj, dim3((npairs + 63) / 64), dim3(64), 0, s, tab, npairs, lp);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = launch_search_adj(tab, npairs, blocks[1], lp, s)) != hipSuccess) return e;
