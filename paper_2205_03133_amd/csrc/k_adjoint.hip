@@ -186,18 +186,6 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_fuse_adj(const PairLevel*
   block_atomic_sum(sss, a.hyper_adj + 0, s_buf);
 }
 
-// Per pixel above the finest level: holes took the parent estimate.
-__global__ __launch_bounds__(kPixThreads) void k_hole_adj(const PairLevel* tab, int npairs) {
-  const PairLevel& a = tab[find_pair<0>(tab, npairs, (int)blockIdx.x)];
-  const int idx = ((int)blockIdx.x - a.pyr0) * kPixThreads + (int)threadIdx.x;
-  if (idx >= a.g.w * a.g.h || !a.par_ubar_adj) return;
-  if (gbl(a.zmap)[idx] > 0.0) return;
-  const int y = idx / a.g.w, x = idx - y * a.g.w;
-  const double gU = gbl(a.ubar_adj)[idx], gQ = gbl(a.qmap_adj)[idx];
-  if (gU != 0.0) bilinear_adj(a.par_ubar_adj, a.pw, a.ph, 0.5 * x, 0.5 * y, 2.0 * gU);
-  if (gQ != 0.0) bilinear_adj(a.par_qmap_adj, a.pw, a.ph, 0.5 * x, 0.5 * y, gQ);
-}
-
 // Per patch: posterior, propagation and patch-variance adjoints -> window SSDs,
 // tau, level weights and the parent confidence.
 __global__ __launch_bounds__(kPixThreads) void k_prob_adj(const PairLevel* tab, int npairs, LevelParams lp) {
@@ -623,12 +611,20 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLeve
 // Per pixel: the transposed template gradient g = Sobel_x(L) / 8 (reflect-101),
 // gathered: pixel (x, y) sums the gradient adjoints of the neighbours whose
 // stencil (after reflection) reads it.  One owner per pixel, no atomics.
-__global__ __launch_bounds__(kPixThreads) void k_sobel_adj(const PairLevel* tab, int npairs) {
+__global__ __launch_bounds__(kPixThreads) void k_sobel_adj(const PairLevel* tab, int npairs, int holes) {
   const PairLevel& a = tab[find_pair<0>(tab, npairs, (int)blockIdx.x)];
   const int idx = ((int)blockIdx.x - a.pyr0) * kPixThreads + (int)threadIdx.x;
   const int w = a.g.w, h = a.g.h;
   if (idx >= w * h) return;
   const int y = idx / w, x = idx - y * w;
+  // above the finest level, holes (no accepted covering patch) took the parent
+  // estimate: their adjoints go to the parent maps (read by the parent level's
+  // pass, which runs after this one)
+  if (holes && a.par_ubar_adj && !(gbl(a.zmap)[idx] > 0.0)) {
+    const double gU = gbl(a.ubar_adj)[idx], gQ = gbl(a.qmap_adj)[idx];
+    if (gU != 0.0) bilinear_adj(a.par_ubar_adj, a.pw, a.ph, 0.5 * x, 0.5 * y, 2.0 * gU);
+    if (gQ != 0.0) bilinear_adj(a.par_qmap_adj, a.pw, a.ph, 0.5 * x, 0.5 * y, gQ);
+  }
   const auto Gb = gbl(a.Gbar);
   double acc = 0.0;
   if (x >= 2 && x <= w - 3 && y >= 2 && y <= h - 3) {
@@ -767,12 +763,11 @@ hipError_t launch_backward_level(const PairLevel* tab, int npairs, const int* bl
   if (lp.level == lp.finest) bdis_launch(k_seed, dim3(blocks[0]), pix, 0, s, tab, npairs, lp);
   hipError_t e = launch_fuse_adj(tab, npairs, blocks[1], lp, s);
   if (e != hipSuccess) return e;
-  if (lp.level > lp.finest) bdis_launch(k_hole_adj, dim3(blocks[0]), pix, 0, s, tab, npairs);
   bdis_launch(k_prob_adj, dim3(blocks[2]), pix, 0, s, tab, npairs, lp);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = launch_search_adj(tab, npairs, blocks[1], lp, s)) != hipSuccess) return e;
-  bdis_launch(k_sobel_adj, dim3(blocks[0]), pix, 0, s, tab, npairs);
+  bdis_launch(k_sobel_adj, dim3(blocks[0]), pix, 0, s, tab, npairs, lp.level > lp.finest ? 1 : 0);
   return hipGetLastError();
 }
 
