@@ -341,7 +341,15 @@ char g_create_err[512] = {0};
 // Zeroes `n` bytes at `p` (16-byte stores for the aligned body, bytes at the
 // ends): a kernel rather than a memset node, so that a call a caller captures
 // into a graph replays correctly.
-__global__ __launch_bounds__(256) void k_zero_bytes(unsigned char* p, size_t n) {
+// Up to kZeroJobs byte ranges zeroed by one launch (blockIdx.y picks the range).
+constexpr int kZeroJobs = 32;
+struct ZeroJobs {
+  unsigned char* p[kZeroJobs];
+  size_t n[kZeroJobs];
+};
+__global__ __launch_bounds__(256) void k_zero_bytes(ZeroJobs jobs) {
+  unsigned char* const p = jobs.p[blockIdx.y];
+  const size_t n = jobs.n[blockIdx.y];
   const size_t head = std::min(n, (size_t)((16 - ((uintptr_t)p & 15)) & 15));
   const size_t n16 = (n - head) / 16;
   const size_t tail = head + 16 * n16;
@@ -362,12 +370,25 @@ __global__ __launch_bounds__(64) void k_adj_scal_zero(const PairLevel* tab, int 
   sc[5] = 0.0;
   sc[6] = 0.0;
 }
-hipError_t zero_bytes(void* p, size_t n, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  const size_t n16 = n / 16 + 1;
-  const unsigned blocks = (unsigned)std::min<size_t>((n16 + 255) / 256, 4096);
-  bdis_launch(k_zero_bytes, dim3(blocks), dim3(256), 0, st, static_cast<unsigned char*>(p), n);
-  return hipGetLastError();
+// Zeroes the byte ranges (p[i], n[i]), i < count, kZeroJobs ranges per launch.
+hipError_t zero_ranges(unsigned char* const* p, const size_t* n, int count, hipStream_t st) {
+  for (int b = 0; b < count; b += kZeroJobs) {
+    ZeroJobs jobs{};
+    const int m = std::min(kZeroJobs, count - b);
+    size_t most = 0;
+    for (int i = 0; i < m; ++i) {
+      jobs.p[i] = p[b + i];
+      jobs.n[i] = n[b + i];
+      most = std::max(most, n[b + i]);
+    }
+    if (most == 0) continue;
+    const size_t n16 = most / 16 + 1;
+    const unsigned blocks = (unsigned)std::min<size_t>((n16 + 255) / 256, 4096);
+    bdis_launch(k_zero_bytes, dim3(blocks, (unsigned)m), dim3(256), 0, st, jobs);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 bdis_status fail(bdis_ctx* c, bdis_status st, const char* fmt, ...) {
@@ -1445,13 +1466,18 @@ bdis_status run_backward(bdis_ctx* c, std::vector<PairSpec> pairs, double* grad_
   if ((s = upload_table(c, pl, st)) != BDIS_OK) return s;
   const bdis_params& p = c->p;
   hipError_t e;
+  // every pair's adjoint buffers and the hyper-gradient sums start from zero
+  std::vector<unsigned char*> zp;
+  std::vector<size_t> zn;
   for (size_t i = 0; i < pairs.size(); ++i) {
     Layout lay;
     make_layout(p, pairs[i].w, pairs[i].h, pairs[i].levels, &lay, true);
-    e = zero_bytes(c->ws + i * c->slot_bytes + lay.adj_begin, lay.adj_end - lay.adj_begin, st);
-    if (e != hipSuccess) return hip_fail(c, e, "adjoint clear");
+    zp.push_back(reinterpret_cast<unsigned char*>(c->ws + i * c->slot_bytes + lay.adj_begin));
+    zn.push_back(lay.adj_end - lay.adj_begin);
   }
-  if ((e = zero_bytes(c->hyper_dev, sizeof(double) * (2 + kMaxLevels), st)) != hipSuccess)
+  zp.push_back(reinterpret_cast<unsigned char*>(c->hyper_dev));
+  zn.push_back(sizeof(double) * (2 + kMaxLevels));
+  if ((e = zero_ranges(zp.data(), zn.data(), (int)zp.size(), st)) != hipSuccess)
     return hip_fail(c, e, "adjoint clear");
   const int ntab = (int)pl.tab.size();
   bdis_launch(k_adj_scal_zero, dim3((ntab + 63) / 64), dim3(64), 0, st, c->tab_dev, ntab);
