@@ -205,9 +205,10 @@ __global__ __launch_bounds__(kPixThreads) void k_prob_adj(const PairLevel* tab, 
     const D4 dd = ld4(a.pa.dssd + k);
     const double dl[4] = {dd.x, dd.y, dd.z, dd.w};
     const double tau = gbl(a.scal)[1];
+    const double rt = 1.0 / tau;  // the record's own form: exponents as products with 1 / tau
     double e[4], se = 1.0;
     for (int t = 0; t < 4; ++t) {
-      e[t] = exp(-dl[t] / tau);
+      e[t] = exp(-dl[t] * rt);
       se += e[t];
     }
     const double post = 1.0 / se;
@@ -216,15 +217,15 @@ __global__ __launch_bounds__(kPixThreads) void k_prob_adj(const PairLevel* tab, 
     double dl_adj[4];
     double sedl = 0.0;
     for (int t = 0; t < 4; ++t) {
-      dl_adj[t] = post_adj * post * post * e[t] / tau;
+      dl_adj[t] = post_adj * post * post * e[t] * rt;
       sedl += e[t] * dl[t];
     }
-    tau_adj = -post_adj * post * post * sedl / (tau * tau);
+    tau_adj = -post_adj * post * post * sedl * (rt * rt);
     if (vt && sig_adj != 0.0) {
       // the fit passed and was not capped iff sigma_k^2 = tau / (2 kappa) < sigma_fail^2,
       // decided by the record's own arithmetic
       const double sfail = lp.var_fail_sigma > 0.0f ? (double)lp.var_fail_sigma : (double)P;
-      const VarFit vf = var_fit(dd, 1.0 / tau, lp.var_fit_thresh);
+      const VarFit vf = var_fit(dd, rt, lp.var_fit_thresh);
       const double kappa = vf.kappa;
       const bool pass = vf.pass && tau / (2.0 * kappa) < sfail * sfail;
       if (pass) {
