@@ -671,13 +671,27 @@ BDIS_DEV double pyr_tap_weight(int k, int i, int n) {
 // (reflected at most once), so only k in [i/2 - 2, i/2 + 2] can reach i.
 __global__ __launch_bounds__(kPixThreads) void k_pyr_adj(const PairLevel* tab, int npairs) {
   const PairLevel& a = tab[find_pair<0>(tab, npairs, (int)blockIdx.x)];
-  if (a.upLbar == nullptr) return;
   const int idx = ((int)blockIdx.x - a.pyr0) * kPixThreads + (int)threadIdx.x;
   const int w = a.g.w, h = a.g.h;
   if (idx >= w * h) return;
   const int y = idx / w, x = idx - y * w;
-  const auto uL = gbl(a.upLbar), uR = gbl(a.upRbar);
   const size_t o = (size_t)y * a.dpitch + x;
+  // adds the parent's share to this pixel's image adjoints; at level 0 (the
+  // entries that carry the caller's gradient outputs) also writes those
+  auto finish = [&](double sl, double sr) {
+    double vl = 0.0, vr = 0.0;
+    if (sl != 0.0 || a.grad_left) vl = gbl(a.Lbar)[o];
+    if (sr != 0.0 || a.grad_right) vr = gbl(a.Rbar)[o];
+    if (sl != 0.0) gbl(a.Lbar)[o] = vl = vl + sl / 256.0;
+    if (sr != 0.0) gbl(a.Rbar)[o] = vr = vr + sr / 256.0;
+    if (a.grad_left) gbl(a.grad_left)[idx] = (float)vl;
+    if (a.grad_right) gbl(a.grad_right)[idx] = (float)vr;
+  };
+  if (a.upLbar == nullptr) {  // a pair's coarsest level: no parent share
+    finish(0.0, 0.0);
+    return;
+  }
+  const auto uL = gbl(a.upLbar), uR = gbl(a.upRbar);
   if (x >= 3 && x <= w - 4 && y >= 3 && y <= h - 4) {
     // interior: no reflected index reaches the pixel, so its parent taps are
     // those with 2k + t - 2 = i: k = i/2 - 1, i/2, i/2 + 1 with weights 1, 6, 1
@@ -697,8 +711,7 @@ __global__ __launch_bounds__(kPixThreads) void k_pyr_adj(const PairLevel* tab, i
         sr += wgt * uR[row + jx];
       }
     }
-    if (sl != 0.0) gbl(a.Lbar)[o] += sl / 256.0;
-    if (sr != 0.0) gbl(a.Rbar)[o] += sr / 256.0;
+    finish(sl, sr);
     return;
   }
   const int ky0 = max(y / 2 - 2, 0), ky1 = min(y / 2 + 2, a.uph - 1);
@@ -717,8 +730,7 @@ __global__ __launch_bounds__(kPixThreads) void k_pyr_adj(const PairLevel* tab, i
       sr += wgt * uR[row + kx];
     }
   }
-  if (sl != 0.0) gbl(a.Lbar)[o] += sl / 256.0;
-  if (sr != 0.0) gbl(a.Rbar)[o] += sr / 256.0;
+  finish(sl, sr);
 }
 
 // Level 0, per pixel: image gradients out (float32, dense W x H).

@@ -1495,7 +1495,10 @@ bdis_status run_backward(bdis_ctx* c, std::vector<PairSpec> pairs, double* grad_
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "pyramid adjoint launch");
   }
-  if ((e = launch_grad_out(c->tab_dev + pl.tab_first[0], pl.tab_count[0], pl.pyr_blocks[0], st)) != hipSuccess)
+  // the level-0 pyramid adjoint writes the image gradients; with one level, a
+  // launch of its own does
+  if (pl.max_levels < 2 &&
+      (e = launch_grad_out(c->tab_dev + pl.tab_first[0], pl.tab_count[0], pl.pyr_blocks[0], st)) != hipSuccess)
     return hip_fail(c, e, "gradient output launch");
   if (grad_hyper) {
     e = hipMemcpyAsync(grad_hyper, c->hyper_dev, sizeof(double) * (2 + pl.max_levels), hipMemcpyDeviceToDevice, st);
