@@ -52,20 +52,6 @@ BDIS_DEV void block_atomic_sum(double v, double* dst, double* s_buf) {
   __syncthreads();
 }
 
-// Finest level, per pixel: d loss / d Ubar = -d loss / d disparity on output
-// pixels (d = -Ubar), d loss / d variance likewise; 0 elsewhere.
-__global__ __launch_bounds__(kPixThreads) void k_seed(const PairLevel* tab, int npairs, LevelParams lp) {
-  const PairLevel& a = tab[find_pair<0>(tab, npairs, (int)blockIdx.x)];
-  const int idx = ((int)blockIdx.x - a.pyr0) * kPixThreads + (int)threadIdx.x;
-  if (idx >= a.g.w * a.g.h) return;
-  const double z = gbl(a.zmap)[idx];
-  bool ok = z > 0.0;
-  if (ok && lp.prob_thresh > 0.0f && gbl(a.qmap_keep)[idx] < (double)lp.prob_thresh) ok = false;
-  gbl(a.ubar_adj)[idx] = (ok && a.grad_disp) ? -(double)gbl(a.grad_disp)[idx] : 0.0;
-  gbl(a.qmap_adj)[idx] = 0.0;
-  if (a.vmap_adj) gbl(a.vmap_adj)[idx] = (ok && a.grad_var && lp.variance) ? (double)gbl(a.grad_var)[idx] : 0.0;
-}
-
 // Per patch: gather the fusion adjoint over the patch's pixels.  A workgroup
 // holds NPB consecutive patches of one patch row (laid out like the search);
 // each patch has a group of lanes, one per patch column.  The P image rows are
@@ -104,7 +90,7 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_fuse_adj(const PairLevel*
   const int oxa = grid_origin(i0, W, P, S);
   const int tw = min((NPB - 1) * S + P, W - oxa);  // tile columns (<= 256)
   const bool finest = lp.level == lp.finest;
-  const bool vt = finest && lp.variance && a.vmap_adj != nullptr;
+  const bool vt = finest && lp.variance && a.vmap != nullptr;
   const auto ub = gbl(finest ? a.ubar_keep : a.ubar);
   const auto qm = gbl(finest ? a.qmap_keep : a.qmap);
 
@@ -122,17 +108,31 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_fuse_adj(const PairLevel*
   // the fused maps and their adjoints of row b (one lane per tile column), all
   // issued at once and one row ahead of their use
   constexpr int NF = 8;  // Z, gU, gQ, SM, U, Q, gV, V
+  // At the finest level the map adjoints come straight from the caller's
+  // output gradients: d loss / d Ubar = -d loss / d disparity and d loss / d
+  // variance on output pixels (a fused value, and confidence at or above the
+  // pixel threshold), 0 elsewhere; the confidence adjoint is 0.
+  const float pthr = lp.prob_thresh;
   auto load_row = [&](int b, double (&v)[NF]) {
     if (tid < tw) {
       const size_t idx = (size_t)(oy + b) * W + oxa + tid;
       v[0] = gbl(a.zmap)[idx];
-      v[1] = gbl(a.ubar_adj)[idx];
-      v[2] = gbl(a.qmap_adj)[idx];
       v[3] = gbl(a.smmap)[idx];
       v[4] = ub[idx];
       v[5] = qm[idx];
-      v[6] = vt ? gbl(a.vmap_adj)[idx] : 0.0;
       v[7] = vt ? gbl(a.vmap)[idx] : 0.0;
+      if (finest) {
+        const double gd = a.grad_disp ? (double)gbl(a.grad_disp)[idx] : 0.0;
+        const double gv = (vt && a.grad_var) ? (double)gbl(a.grad_var)[idx] : 0.0;
+        const bool ok = v[0] > 0.0 && !(pthr > 0.0f && v[5] < (double)pthr);
+        v[1] = ok ? -gd : 0.0;
+        v[2] = 0.0;
+        v[6] = ok ? gv : 0.0;
+      } else {
+        v[1] = gbl(a.ubar_adj)[idx];
+        v[2] = gbl(a.qmap_adj)[idx];
+        v[6] = 0.0;
+      }
     }
   };
   double cur[NF] = {}, nxt[NF] = {};
@@ -773,7 +773,6 @@ hipError_t launch_fuse_adj(const PairLevel* tab, int npairs, int nblocks, const 
 hipError_t launch_backward_level(const PairLevel* tab, int npairs, const int* blocks, const LevelParams& lp,
                                  hipStream_t s) {
   const dim3 pix(kPixThreads);
-  if (lp.level == lp.finest) bdis_launch(k_seed, dim3(blocks[0]), pix, 0, s, tab, npairs, lp);
   hipError_t e = launch_fuse_adj(tab, npairs, blocks[1], lp, s);
   if (e != hipSuccess) return e;
   bdis_launch(k_prob_adj, dim3(blocks[2]), pix, 0, s, tab, npairs, lp);

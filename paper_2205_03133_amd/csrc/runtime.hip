@@ -68,7 +68,7 @@ struct Layout {
       smmap[kMaxLevels]{}, vmap = 0, ubar_keep = 0, qmap_keep = 0;
   size_t adj_begin = 0, adj_end = 0;
   size_t lbar[kMaxLevels]{}, rbar[kMaxLevels]{}, gbar[kMaxLevels]{}, ubar_adj[kMaxLevels]{},
-      qmap_adj[kMaxLevels]{}, vmap_adj = 0, pu_adj[kMaxLevels]{}, ppi_adj[kMaxLevels]{},
+      qmap_adj[kMaxLevels]{}, pu_adj[kMaxLevels]{}, ppi_adj[kMaxLevels]{},
       psig_adj[kMaxLevels]{}, pssd_adj[kMaxLevels]{};
   size_t total = 0;
 };
@@ -171,9 +171,12 @@ bool make_layout(const bdis_params& p, int w, int h, int levels, Layout* lay, bo
       L.rbar[n] = take(nd * 8);
       L.gbar[n] = take(nd * 8);
       if (n < f) continue;
-      L.ubar_adj[n] = take(npx * 8);
-      L.qmap_adj[n] = take(npx * 8);
-      if (n == f) L.vmap_adj = take(npx * 8);
+      // the finest level's map adjoints are formed from the caller's output
+      // gradients where they are read (the fusion adjoint): no buffers
+      if (n > f) {
+        L.ubar_adj[n] = take(npx * 8);
+        L.qmap_adj[n] = take(npx * 8);
+      }
       L.pu_adj[n] = take(np * 8);
       L.ppi_adj[n] = take(np * 8);
       L.psig_adj[n] = take(np * 8);
@@ -760,8 +763,8 @@ bdis_status build_plan(bdis_ctx* c, const PairSpec* pairs, size_t npairs, Plan* 
           e.reset = reinterpret_cast<int*>(base + lay.reset[n]);
           e.zmap = BD(lay.zmap[n]);
           e.smmap = BD(lay.smmap[n]);
-          e.ubar_adj = BD(lay.ubar_adj[n]);
-          e.qmap_adj = BD(lay.qmap_adj[n]);
+          e.ubar_adj = n > f ? BD(lay.ubar_adj[n]) : nullptr;
+          e.qmap_adj = n > f ? BD(lay.qmap_adj[n]) : nullptr;
           e.par_ubar_adj = has_par ? BD(lay.ubar_adj[n + 1]) : nullptr;
           e.par_qmap_adj = has_par ? BD(lay.qmap_adj[n + 1]) : nullptr;
           e.pu_adj = BD(lay.pu_adj[n]);
@@ -772,7 +775,6 @@ bdis_status build_plan(bdis_ctx* c, const PairSpec* pairs, size_t npairs, Plan* 
             e.vmap = BD(lay.vmap);
             e.ubar_keep = BD(lay.ubar_keep);
             e.qmap_keep = BD(lay.qmap_keep);
-            e.vmap_adj = BD(lay.vmap_adj);
             e.grad_disp = q.grad_disp;
             e.grad_var = q.grad_var;
           }
