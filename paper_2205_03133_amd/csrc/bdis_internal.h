@@ -137,7 +137,6 @@ struct PairLevel {
   double* qmap_adj;
   double* par_ubar_adj;  // d loss / d parent maps (nullptr at the coarsest level)
   double* par_qmap_adj;
-  double* vmap_adj;      // finest level: d loss / d variance
   double* pu_adj;        // per patch: d loss / d u, d pi, d sigma_k^2
   double* ppi_adj;
   double* psig_adj;
