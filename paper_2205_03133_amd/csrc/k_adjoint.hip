@@ -468,27 +468,54 @@ BDIS_DEV void patch_adj(const PairLevel& a, const LevelParams& lp, int k, int r,
     };
     const double rH = 1.0 / H;    // one division for the K reverse steps
     double u_next = uh[lp.K - 1];  // the next iterate is loaded one step ahead
+    // the cell's correlations with the gradient, from its samples in Rv
+    auto enter_cell = [&](int m) {
+      double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        c0 += J[c] * Rv[c];
+        c1 += J[c] * Rv[c + 1];
+      }
+      C0 = group_sum_d<G>(row_live ? c0 : 0.0) - cT;
+      C1 = group_sum_d<G>(row_live ? c1 : 0.0) - cT;
+      mc = m;
+      cell = true;
+    };
+    {
+      // The first cell of the reverse pass (that of u_(K-1)) is nearly always
+      // one of the window's three cells, whose samples are already held: the
+      // same pixels as a reload, without its round trip.
+      const int m = (int)floor(u_next);
+      const int o = m - (m0 - 1);
+      to_cell(m);
+      // (constant indices in each branch keep Rw and Rv in registers)
+      if (o == 0) {
+#pragma unroll
+        for (int c = 0; c <= P; ++c) Rv[c] = Rw[c];
+      } else if (o == 1) {
+#pragma unroll
+        for (int c = 0; c <= P; ++c) Rv[c] = Rw[c + 1];
+      } else if (o == 2) {
+#pragma unroll
+        for (int c = 0; c <= P; ++c) Rv[c] = Rw[c + 2];
+      } else {
+#pragma unroll
+        for (int c = 0; c <= P; ++c) Rv[c] = Rrow[clampi(ox + c + m, 0, W - 1)];
+      }
+      enter_cell(m);
+    }
     for (int t = lp.K - 1; t >= 0; --t) {
       const double ut = u_next;
       if (t > 0) u_next = uh[t - 1];
       const double fm = floor(ut);
       const int m = (int)fm;
       const double f = ut - fm;
-      if (!cell || m != mc) {
+      if (m != mc) {
         apply();
         to_cell(m);
-        double c0 = 0.0, c1 = 0.0;
 #pragma unroll
         for (int c = 0; c <= P; ++c) Rv[c] = Rrow[clampi(ox + c + m, 0, W - 1)];
-#pragma unroll
-        for (int c = 0; c < P; ++c) {
-          c0 += J[c] * Rv[c];
-          c1 += J[c] * Rv[c + 1];
-        }
-        C0 = group_sum_d<G>(row_live ? c0 : 0.0) - cT;
-        C1 = group_sum_d<G>(row_live ? c1 : 0.0) - cT;
-        mc = m;
-        cell = true;
+        enter_cell(m);
       }
       const double b = (1.0 - f) * C0 + f * C1;  // sum J (I_w - T)
       const double s1 = ub * rH;
