@@ -704,15 +704,22 @@ __global__ __launch_bounds__(kPixThreads) void k_pyr_adj(const PairLevel* tab, i
   const int y = idx / w, x = idx - y * w;
   const size_t o = (size_t)y * a.dpitch + x;
   // adds the parent's share to this pixel's image adjoints; at level 0 (the
-  // entries that carry the caller's gradient outputs) also writes those
+  // entries that carry the caller's gradient outputs) writes those instead:
+  // nothing reads a level-0 adjoint after this pass
   auto finish = [&](double sl, double sr) {
     double vl = 0.0, vr = 0.0;
     if (sl != 0.0 || a.grad_left) vl = gbl(a.Lbar)[o];
     if (sr != 0.0 || a.grad_right) vr = gbl(a.Rbar)[o];
-    if (sl != 0.0) gbl(a.Lbar)[o] = vl = vl + sl / 256.0;
-    if (sr != 0.0) gbl(a.Rbar)[o] = vr = vr + sr / 256.0;
-    if (a.grad_left) gbl(a.grad_left)[idx] = (float)vl;
-    if (a.grad_right) gbl(a.grad_right)[idx] = (float)vr;
+    if (sl != 0.0) vl += sl / 256.0;
+    if (sr != 0.0) vr += sr / 256.0;
+    if (a.grad_left)
+      gbl(a.grad_left)[idx] = (float)vl;
+    else if (sl != 0.0)
+      gbl(a.Lbar)[o] = vl;
+    if (a.grad_right)
+      gbl(a.grad_right)[idx] = (float)vr;
+    else if (sr != 0.0)
+      gbl(a.Rbar)[o] = vr;
   };
   if (a.upLbar == nullptr) {  // a pair's coarsest level: no parent share
     finish(0.0, 0.0);
