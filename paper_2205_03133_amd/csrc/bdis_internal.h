@@ -339,9 +339,11 @@ hipError_t launch_depth(const float* disp, const float* var, int w, int h, int p
 hipError_t launch_pyramid_f64(const PairLevel* tab, int npairs, int nblocks, int level, hipStream_t s);
 hipError_t launch_search_f64(const PairLevel* tab, int npairs, int nblocks, const LevelParams& lp,
                              hipStream_t s);
+// sobel_in_pyramid: the level's transposed template gradient is left to the
+// pyramid adjoint launch of the same level (launch_pyramid_adj with sobel).
 hipError_t launch_backward_level(const PairLevel* tab, int npairs, const int* blocks, const LevelParams& lp,
-                                 hipStream_t s);
-hipError_t launch_pyramid_adj(const PairLevel* tab, int npairs, int nblocks, hipStream_t s);
+                                 bool sobel_in_pyramid, hipStream_t s);
+hipError_t launch_pyramid_adj(const PairLevel* tab, int npairs, int nblocks, bool sobel, hipStream_t s);
 hipError_t launch_grad_out(const PairLevel* tab, int npairs, int nblocks, hipStream_t s);
 
 // Per-kernel timing (bdis_timing_enable): the runtime hands the events of a

@@ -636,9 +636,42 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_adj(const PairLeve
   }
 }
 
-// Per pixel: the transposed template gradient g = Sobel_x(L) / 8 (reflect-101),
-// gathered: pixel (x, y) sums the gradient adjoints of the neighbours whose
-// stencil (after reflection) reads it.  One owner per pixel, no atomics.
+// The transposed template gradient g = Sobel_x(L) / 8 (reflect-101) at pixel
+// (x, y), gathered: the sum of the gradient adjoints of the neighbours whose
+// stencil (after reflection) reads the pixel, with their stencil weights (the
+// caller divides by 8).
+BDIS_DEV double sobel_gather(const PairLevel& a, int x, int y) {
+  const int w = a.g.w, h = a.g.h;
+  const auto Gb = gbl(a.Gbar);
+  double acc = 0.0;
+  if (x >= 2 && x <= w - 3 && y >= 2 && y <= h - 3) {
+    // interior: no reflection reaches the pixel; rows y-1, y, y+1 weigh 1, 2, 1,
+    // columns x-1 and x+1 weigh +1 and -1: the nonzero terms of the general
+    // form below, in its order, so the same bits
+    const double wys[3] = {1.0, 2.0, 1.0};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const size_t row = (size_t)(y - 1 + j) * a.dpitch;
+      acc += wys[j] * 1.0 * Gb[row + x - 1];
+      acc += wys[j] * -1.0 * Gb[row + x + 1];
+    }
+    return acc;
+  }
+  for (int yy = max(y - 1, 0); yy <= min(y + 1, h - 1); ++yy) {
+    // rows yy-1, yy, yy+1 of the stencil weigh 1, 2, 1
+    const double wy = (reflect101(yy - 1, h) == y ? 1.0 : 0.0) + (yy == y ? 2.0 : 0.0) +
+                      (reflect101(yy + 1, h) == y ? 1.0 : 0.0);
+    if (wy == 0.0) continue;
+    for (int xx = max(x - 1, 0); xx <= min(x + 1, w - 1); ++xx) {
+      const double wx = (reflect101(xx + 1, w) == x ? 1.0 : 0.0) - (reflect101(xx - 1, w) == x ? 1.0 : 0.0);
+      if (wx != 0.0) acc += wy * wx * Gb[(size_t)yy * a.dpitch + xx];
+    }
+  }
+  return acc;
+}
+
+// Per pixel: the transposed template gradient, added to the level image's
+// adjoint.  One owner per pixel, no atomics.
 __global__ __launch_bounds__(kPixThreads) void k_sobel_adj(const PairLevel* tab, int npairs, int holes) {
   const PairLevel& a = tab[find_pair<0>(tab, npairs, (int)blockIdx.x)];
   const int idx = ((int)blockIdx.x - a.pyr0) * kPixThreads + (int)threadIdx.x;
@@ -653,32 +686,7 @@ __global__ __launch_bounds__(kPixThreads) void k_sobel_adj(const PairLevel* tab,
     if (gU != 0.0) bilinear_adj(a.par_ubar_adj, a.pw, a.ph, 0.5 * x, 0.5 * y, 2.0 * gU);
     if (gQ != 0.0) bilinear_adj(a.par_qmap_adj, a.pw, a.ph, 0.5 * x, 0.5 * y, gQ);
   }
-  const auto Gb = gbl(a.Gbar);
-  double acc = 0.0;
-  if (x >= 2 && x <= w - 3 && y >= 2 && y <= h - 3) {
-    // interior: no reflection reaches the pixel; rows y-1, y, y+1 weigh 1, 2, 1,
-    // columns x-1 and x+1 weigh +1 and -1: the nonzero terms of the general
-    // form below, in its order, so the same bits
-    const double wys[3] = {1.0, 2.0, 1.0};
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const size_t row = (size_t)(y - 1 + j) * a.dpitch;
-      acc += wys[j] * 1.0 * Gb[row + x - 1];
-      acc += wys[j] * -1.0 * Gb[row + x + 1];
-    }
-    if (acc != 0.0) gbl(a.Lbar)[(size_t)y * a.dpitch + x] += acc / 8.0;
-    return;
-  }
-  for (int yy = max(y - 1, 0); yy <= min(y + 1, h - 1); ++yy) {
-    // rows yy-1, yy, yy+1 of the stencil weigh 1, 2, 1
-    const double wy = (reflect101(yy - 1, h) == y ? 1.0 : 0.0) + (yy == y ? 2.0 : 0.0) +
-                      (reflect101(yy + 1, h) == y ? 1.0 : 0.0);
-    if (wy == 0.0) continue;
-    for (int xx = max(x - 1, 0); xx <= min(x + 1, w - 1); ++xx) {
-      const double wx = (reflect101(xx + 1, w) == x ? 1.0 : 0.0) - (reflect101(xx - 1, w) == x ? 1.0 : 0.0);
-      if (wx != 0.0) acc += wy * wx * Gb[(size_t)yy * a.dpitch + xx];
-    }
-  }
+  const double acc = sobel_gather(a, x, y);
   if (acc != 0.0) gbl(a.Lbar)[(size_t)y * a.dpitch + x] += acc / 8.0;
 }
 
@@ -696,7 +704,9 @@ BDIS_DEV double pyr_tap_weight(int k, int i, int n) {
 // Per pixel of level n (n < coarsest): the transposed binomial pyramid step
 // from level n+1, gathered.  Parent samples k read source rows 2k-2 .. 2k+2
 // (reflected at most once), so only k in [i/2 - 2, i/2 + 2] can reach i.
-__global__ __launch_bounds__(kPixThreads) void k_pyr_adj(const PairLevel* tab, int npairs) {
+// sobel: the level's transposed template gradient is added here first (in
+// place of a k_sobel_adj launch at this level; the same terms in the same order).
+__global__ __launch_bounds__(kPixThreads) void k_pyr_adj(const PairLevel* tab, int npairs, int sobel) {
   const PairLevel& a = tab[find_pair<0>(tab, npairs, (int)blockIdx.x)];
   const int idx = ((int)blockIdx.x - a.pyr0) * kPixThreads + (int)threadIdx.x;
   const int w = a.g.w, h = a.g.h;
@@ -707,14 +717,16 @@ __global__ __launch_bounds__(kPixThreads) void k_pyr_adj(const PairLevel* tab, i
   // entries that carry the caller's gradient outputs) writes those instead:
   // nothing reads a level-0 adjoint after this pass
   auto finish = [&](double sl, double sr) {
+    const double sg = sobel ? sobel_gather(a, x, y) : 0.0;
     double vl = 0.0, vr = 0.0;
-    if (sl != 0.0 || a.grad_left) vl = gbl(a.Lbar)[o];
+    if (sl != 0.0 || sg != 0.0 || a.grad_left) vl = gbl(a.Lbar)[o];
     if (sr != 0.0 || a.grad_right) vr = gbl(a.Rbar)[o];
+    if (sg != 0.0) vl += sg / 8.0;
     if (sl != 0.0) vl += sl / 256.0;
     if (sr != 0.0) vr += sr / 256.0;
     if (a.grad_left)
       gbl(a.grad_left)[idx] = (float)vl;
-    else if (sl != 0.0)
+    else if (sl != 0.0 || sg != 0.0)
       gbl(a.Lbar)[o] = vl;
     if (a.grad_right)
       gbl(a.grad_right)[idx] = (float)vr;
@@ -805,7 +817,7 @@ hipError_t launch_fuse_adj(const PairLevel* tab, int npairs, int nblocks, const 
 
 // blocks: [per-pixel workgroups, search workgroups, per-patch workgroups]
 hipError_t launch_backward_level(const PairLevel* tab, int npairs, const int* blocks, const LevelParams& lp,
-                                 hipStream_t s) {
+                                 bool sobel_in_pyramid, hipStream_t s) {
   const dim3 pix(kPixThreads);
   hipError_t e = launch_fuse_adj(tab, npairs, blocks[1], lp, s);
   if (e != hipSuccess) return e;
@@ -813,13 +825,14 @@ hipError_t launch_backward_level(const PairLevel* tab, int npairs, const int* bl
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = launch_search_adj(tab, npairs, blocks[1], lp, s)) != hipSuccess) return e;
+  if (sobel_in_pyramid) return hipSuccess;
   bdis_launch(k_sobel_adj, dim3(blocks[0]), pix, 0, s, tab, npairs, lp.level > lp.finest ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_pyramid_adj(const PairLevel* tab, int npairs, int nblocks, hipStream_t s) {
+hipError_t launch_pyramid_adj(const PairLevel* tab, int npairs, int nblocks, bool sobel, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  bdis_launch(k_pyr_adj, dim3(nblocks), dim3(kPixThreads), 0, s, tab, npairs);
+  bdis_launch(k_pyr_adj, dim3(nblocks), dim3(kPixThreads), 0, s, tab, npairs, sobel ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -1484,16 +1484,21 @@ bdis_status run_backward(bdis_ctx* c, std::vector<PairSpec> pairs, double* grad_
   const int ntab = (int)pl.tab.size();
   bdis_launch(k_adj_scal_zero, dim3((ntab + 63) / 64), dim3(64), 0, st, c->tab_dev, ntab);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "adjoint clear");
+  // with more than one level, level 0's transposed template gradient is taken
+  // by its pyramid adjoint launch (one per-pixel pass over level 0 fewer)
+  const bool sobel0_in_pyramid = pl.max_levels >= 2;
   for (int n = p.finest_level; n < pl.max_levels; ++n) {
     const int blocks[3] = {pl.pyr_blocks[n], pl.search_blocks[n], pl.prob_blocks[n]};
     const long tmk = timing_start(c, BDIS_K_BACKWARD, st, n);
-    e = launch_backward_level(c->tab_dev + pl.tab_first[n], pl.tab_count[n], blocks, level_params(p, n), st);
+    e = launch_backward_level(c->tab_dev + pl.tab_first[n], pl.tab_count[n], blocks, level_params(p, n),
+                              n == 0 && sobel0_in_pyramid, st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "backward launch");
   }
   for (int n = pl.max_levels - 2; n >= 0; --n) {  // level n+1 -> level n
     const long tmk = timing_start(c, BDIS_K_BACKWARD, st, n);
-    e = launch_pyramid_adj(c->tab_dev + pl.tab_first[n], pl.tab_count[n], pl.pyr_blocks[n], st);
+    e = launch_pyramid_adj(c->tab_dev + pl.tab_first[n], pl.tab_count[n], pl.pyr_blocks[n],
+                           n == 0 && sobel0_in_pyramid, st);
     timing_stop(c, tmk, st);
     if (e != hipSuccess) return hip_fail(c, e, "pyramid adjoint launch");
   }
