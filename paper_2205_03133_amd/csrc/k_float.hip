@@ -158,6 +158,9 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_f64(const PairLeve
   {
     int mc = INT_MIN;
     double C0 = 0.0, C1 = 0.0;
+    // one division by the Hessian per patch, off the iterations' dependent
+    // chain; the adjoint's reverse steps use the same reciprocal
+    const double rH = invert ? 1.0 / H : 0.0;
     for (int t = 0; t < lp.K; ++t) {
       if (keep) gbl(a.uhist)[(size_t)k * (lp.K + 1) + t] = u;
       if (!invert) continue;
@@ -177,7 +180,7 @@ __global__ __launch_bounds__(kSearchF64Threads) void k_search_f64(const PairLeve
         C1 = group_sum_d<G>(row_live ? c1 : 0.0) - cT;
         mc = m;
       }
-      u -= ((1.0 - f) * C0 + f * C1) / H;
+      u -= ((1.0 - f) * C0 + f * C1) * rH;
     }
   }
   if (keep) gbl(a.uhist)[(size_t)k * (lp.K + 1) + lp.K] = u;
