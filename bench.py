@@ -66,23 +66,29 @@ def search_source_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, levels):
     """HBM bytes per search launch from the committed FETCH_SIZE/WRITE_SIZE counter
-    runs (scaled by the copy-kernel calibration), or None once the kernel source
-    differs from the one the counters were taken on."""
+    runs (per level, scaled by the copy-kernel calibration): the mean over the
+    levels this run's pass searched, so that it matches the timed launches
+    whichever structure the tuner picked for the coarsest level.  None when a
+    level was not counted or the kernel source differs from the one the
+    counters were taken on."""
     try:
         text = open(TRAFFIC_FILE).read()
         src = search_source_sha256()
     except OSError:
         return None
-    sha, val = None, None
+    sha, per_level = None, {}
     for ln in text.splitlines():
         f = ln.split()
         if len(f) == 3 and f[0] == "source_sha256":
             sha = f[2]
-        if len(f) == 3 and f[0] == "traffic_bytes_per_launch" and f[1] == workload:
-            val = int(f[2])
-    return val if sha == src else None
+        if len(f) == 4 and f[0] == "traffic_bytes_level" and f[1] == workload:
+            per_level[int(f[2])] = int(f[3])
+    levels = list(levels)
+    if sha != src or not levels or any(n not in per_level for n in levels):
+        return None
+    return sum(per_level[n] for n in levels) // len(levels)
 
 
 HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
@@ -104,11 +110,11 @@ def search_bytes(bdis, p, w, h, levels=None, skip=()):
     return tot
 
 
-def roofline(flops_per_step, steps, timing, kernel_name, workload, bytes_per_step=None):
+def roofline(flops_per_step, steps, timing, kernel_name, workload, levels, bytes_per_step=None):
     s_ms, s_n = timing["search"]
     achieved = flops_per_step * steps / (s_ms * 1e-3) / 1e12
     out = dict(bound="alu", achieved=round(achieved, 3), peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
-               frac=round(achieved / VALU_PEAK_TFLOPS, 5), traffic=measured_traffic(workload),
+               frac=round(achieved / VALU_PEAK_TFLOPS, 5), traffic=measured_traffic(workload, levels),
                frac_of_packed_fp32_peak=round(achieved / FP32_PACKED_PEAK_TFLOPS, 5),
                traffic_unit="bytes per launch", kernel=kernel_name,
                avg_launch_us=round(s_ms * 1e3 / max(s_n, 1), 3), launches=s_n)
@@ -413,6 +419,7 @@ def bench_batch(bdis, torch, args):
                                     "dark gain U(0.2,0.5), noise 3), L=6 P=12 S=4 K=16 variance on",
                            share="64 of the 512-pair stream"),
                roofline=roofline(flops, steps_ev, tk, "k_search_u8<12>", "1080p_batch64",
+                                 [m for m in range(p.finest_level, p.levels) if m not in top],
                                  search_bytes(bdis, p, 1920, 1080, skip=top) * n),
                search_per_level=per_level, kernels=kernel_table(tk), setup=setup, **acc,
                plain_single=dict(ms_per_pair=round(dt1 * 1e3, 4), mpx_s=round(1920 * 1080 / dt1 / 1e6, 2),
@@ -476,7 +483,8 @@ def bench_mixed(bdis, torch, args):
                 unique_pairs=len(base), steps=args.batch_steps, ms_per_step=round(dt * 1e3 / args.batch_steps, 3),
                 config=dict(workload="64 synthetic pairs, 8 each of 320x240 .. 1920x1080, disparity up to 10% of "
                                      "the width, L=4..6 by size, P=8 S=3 K=16 variance on"),
-                roofline=roofline(flops, steps_ev, tk, "k_search_u8<8>", "mixed64", nbytes),
+                roofline=roofline(flops, steps_ev, tk, "k_search_u8<8>", "mixed64",
+                                  [m for m in range(p.finest_level, max(levels)) if m not in top], nbytes),
                 search_per_level=per_level, kernels=kernel_table(tk), epe_median_px=round(float(np.median(ae)), 4),
                 bad1px=round(float((ae > 1.0).mean()), 5), density=round(float(np.mean(dens)), 4),
                 _oracle_jobs=[(base[wh][1][0], base[wh][1][1], mp[sizes.index(wh)]) for wh in sizes])
@@ -718,7 +726,8 @@ def main():
                                      "highlights, gain U(0.8,1.2), noise 2), L=5 P=8 S=3 K=16 variance on",
                             global_batch=1, pairs_per_step=1),
                 roofline=roofline(search_flops(bdis, p, w, h, skip=s["top"]), args.steps, s["tk"], "k_search_u8<8>",
-                                  "640x480", search_bytes(bdis, p, w, h, skip=s["top"])),
+                                  "640x480", [m for m in range(p.finest_level, p.levels) if m not in s["top"]],
+                                  search_bytes(bdis, p, w, h, skip=s["top"])),
                 kernels=kernel_table(s["tk"]),
                 ms_per_step_with_kernel_events=round(s["dt_ev"] * 1e3 / args.steps, 4),
                 latency_ms=s["latency_ms"], setup=s["setup"], **s["acc"])
